@@ -1,0 +1,531 @@
+"""Plain, slow, FP64 reference implementation of multilevel NMF.
+
+TEST INFRASTRUCTURE ONLY.  This module is the correctness oracle for the HIP
+library.  Only ``tests/``, ``__graft_entry__.smoke()`` and the CPU-baseline leg
+of ``bench.py`` may import it.  It shares no code, tables or helpers with the
+GPU path.
+
+Paper: N. Gillis and F. Glineur, "A Multilevel Approach for Nonnegative Matrix
+Factorization" (arXiv:1009.0881).  Every function cites the passage it follows.
+Everything is numpy float64; inputs are the generator's FP32 arrays widened
+exactly.  Library primitives (matmul, solve, svd, norm) serve as single steps;
+there is no blocking, fusion or reordering beyond what the paper states.
+
+Readings of passages where the paper is silent (each one also listed in the
+design notes):
+  R1  levels: h_{l+1} = ceil(h_l / 2); coarse node c sits on fine node 2c.
+      Reduces to the paper's (2^a+1) -> (2^(a-1)+1) grid (Section 4.2, Fig. 2).
+  R2  full weighting at a boundary: keep the 1-D weights (1,2,1) of the fine
+      neighbours that exist and renormalise each row to sum 1 ("weights adapted
+      correspondingly", eq. restr).  Reproduces the printed 3x3 -> 2x2 R.
+  R3  prolongation at an even-side edge: the mean over the coarse neighbours
+      rd(i/2) that exist (eq. prol).  Reproduces the printed P^T.
+  R4  BLOCK2 (2x2 pixel-block restriction, not in the paper): restriction is
+      the block mean, prolongation replicates.
+  R5  schedule: the time budget T of Alg. 4-6 is counted in fine-iteration
+      equivalents with the paper's cost model m' ~ m/4 (Section 4.3, Table 1);
+      Run(d, t) performs floor(t * 4^d) iterations at depth d.
+  R6  HALS with B_kk = 0 (resp. D_kk = 0): that column of V (row of W) is left
+      unchanged (every value minimises its one-column problem).
+  R7  MU with a zero denominator: that entry is left unchanged (it is then 0).
+  R8  ANLS: NNLS by the Lawson-Hanson active-set method on the Gram form
+      (Appendix A.2); variables whose Gram diagonal is 0 keep their value.
+  R9  error: e = ||M_l - V W||_F (not squared) and rel_err = e / ||M_l||_F,
+      evaluated after every full iteration at the current level.
+  R10 stopping: with tol > 0 the solve ends after the first finest-level
+      iteration whose rel_err <= tol; after the schedule, finest-level
+      iterations continue until then or until max_fine_iters more iterations.
+"""
+from __future__ import annotations
+
+import math
+from fractions import Fraction
+from typing import Dict, List, Optional, Sequence, Tuple
+
+import numpy as np
+
+HALS, MU, ANLS = 0, 1, 2
+NI, VC, FMG = 0, 1, 2
+XFER_FW, XFER_BLOCK2 = 0, 1
+
+ALGO_NAMES = {HALS: "hals", MU: "mu", ANLS: "anls"}
+CYCLE_NAMES = {NI: "ni", VC: "vc", FMG: "fmg"}
+
+__all__ = [
+    "HALS", "MU", "ANLS", "NI", "VC", "FMG", "XFER_FW", "XFER_BLOCK2",
+    "level_sides", "transfer_1d", "restrict_matrix", "prolong_matrix",
+    "restrict_images", "prolong_images", "smoothness",
+    "schedule", "level_iteration_totals",
+    "hals_update_V", "hals_update_W", "hals_iteration",
+    "mu_update_V", "mu_update_W", "mu_iteration",
+    "nnls_gram", "anls_update_V", "anls_update_W", "anls_iteration",
+    "iteration", "rel_err", "objective", "gram_form_residual2",
+    "eckart_young_floor", "prolongation_bound", "solve", "SolveResult",
+]
+
+
+# ---------------------------------------------------------------------------
+# Levels and transfer operators (Section 4.2: Fig. 2, eq. restr, eq. prol)
+# ---------------------------------------------------------------------------
+
+def level_sides(h: int, w: int, levels: int) -> List[Tuple[int, int]]:
+    """Image sides per level, finest first (reading R1).
+
+    Section 4.2 keeps one grid point out of two in each direction.  A side
+    smaller than 2 cannot be restricted further and is rejected.
+    """
+    if levels < 1:
+        raise ValueError("levels must be >= 1")
+    sides = [(h, w)]
+    for _ in range(levels - 1):
+        ph, pw = sides[-1]
+        if ph < 2 or pw < 2:
+            raise ValueError("cannot restrict a side smaller than 2")
+        sides.append(((ph + 1) // 2, (pw + 1) // 2))
+    return sides
+
+
+def transfer_1d(N: int, xfer: int) -> Tuple[np.ndarray, np.ndarray]:
+    """1-D restriction R1 (N' x N) and prolongation P1 (N x N'), N' = ceil(N/2).
+
+    FW (eq. restr read per axis): coarse node c averages fine nodes 2c-1, 2c,
+    2c+1 with weights 1, 2, 1; missing nodes are dropped and the row is
+    renormalised (reading R2).  Prolongation (eq. prol): fine node f takes the
+    mean of the coarse nodes rd(f/2) = {f/2} (f even) or {(f-1)/2, (f+1)/2}
+    (f odd) that exist (reading R3).
+
+    BLOCK2 (reading R4): coarse c is the mean of fine {2c, 2c+1} that exist;
+    fine f copies coarse floor(f/2).
+    """
+    Nc = (N + 1) // 2
+    R = np.zeros((Nc, N))
+    P = np.zeros((N, Nc))
+    if xfer == XFER_FW:
+        for c in range(Nc):
+            for delta, wgt in ((-1, 1.0), (0, 2.0), (1, 1.0)):
+                f = 2 * c + delta
+                if 0 <= f < N:
+                    R[c, f] = wgt
+            R[c, :] /= R[c, :].sum()
+        for f in range(N):
+            if f % 2 == 0:
+                nb = [f // 2]
+            else:
+                nb = [(f - 1) // 2, (f + 1) // 2]
+            nb = [c for c in nb if 0 <= c < Nc]
+            for c in nb:
+                P[f, c] = 1.0 / len(nb)
+    elif xfer == XFER_BLOCK2:
+        for c in range(Nc):
+            fs = [f for f in (2 * c, 2 * c + 1) if f < N]
+            for f in fs:
+                R[c, f] = 1.0 / len(fs)
+        for f in range(N):
+            P[f, f // 2] = 1.0
+    else:
+        raise ValueError("unknown transfer operator")
+    return R, P
+
+
+def restrict_matrix(h: int, w: int, xfer: int) -> np.ndarray:
+    """Dense 2-D restriction R = R_h (x) R_w for row-major vectorised h x w
+    images (pixel (y, x) -> y*w + x); Section 4.2 allows either vectorisation
+    order.  Dense: only for small images (tests)."""
+    Rh, _ = transfer_1d(h, xfer)
+    Rw, _ = transfer_1d(w, xfer)
+    return np.kron(Rh, Rw)
+
+
+def prolong_matrix(h: int, w: int, xfer: int) -> np.ndarray:
+    """Dense 2-D prolongation P = P_h (x) P_w from the ceil(h/2) x ceil(w/2)
+    grid to the h x w grid (Section 4.2, eq. prol)."""
+    _, Ph = transfer_1d(h, xfer)
+    _, Pw = transfer_1d(w, xfer)
+    return np.kron(Ph, Pw)
+
+
+def restrict_images(X: np.ndarray, h: int, w: int, xfer: int) -> np.ndarray:
+    """R(X) applied columnwise (Section 4.1): each column of X is a row-major
+    h x w image.  Uses the separable form R_h X_img R_w^T, which equals the
+    Kronecker operator applied to the vectorised image."""
+    Rh, _ = transfer_1d(h, xfer)
+    Rw, _ = transfer_1d(w, xfer)
+    ncol = X.shape[1]
+    imgs = np.asarray(X, dtype=np.float64).T.reshape(ncol, h, w)
+    out = np.einsum("ay,nyx,bx->nab", Rh, imgs, Rw, optimize=True)
+    return out.reshape(ncol, -1).T.copy()
+
+
+def prolong_images(Y: np.ndarray, h: int, w: int, xfer: int) -> np.ndarray:
+    """P(Y) applied columnwise from the coarse grid of an h x w image."""
+    _, Ph = transfer_1d(h, xfer)
+    _, Pw = transfer_1d(w, xfer)
+    hc, wc = Ph.shape[1], Pw.shape[1]
+    ncol = Y.shape[1]
+    imgs = np.asarray(Y, dtype=np.float64).T.reshape(ncol, hc, wc)
+    out = np.einsum("ya,nab,xb->nyx", Ph, imgs, Pw, optimize=True)
+    return out.reshape(ncol, -1).T.copy()
+
+
+def smoothness(M: np.ndarray, h: int, w: int, xfer: int) -> float:
+    """s_M = ||M - P(R(M))||_F / ||M||_F (Section 4.1)."""
+    M = np.asarray(M, dtype=np.float64)
+    back = prolong_images(restrict_images(M, h, w, xfer), h, w, xfer)
+    return float(np.linalg.norm(M - back) / np.linalg.norm(M))
+
+
+# ---------------------------------------------------------------------------
+# Multigrid cycles (Alg. 4 NI, Alg. 5 VC, Alg. 6 FMG; Table 1 budget)
+# ---------------------------------------------------------------------------
+
+def schedule(cycle: int, levels: int, T) -> List[Tuple[str, int, int]]:
+    """Flat list of steps ("restrict", d, 0), ("prolong", d, 0) or
+    ("run", d, count) for a budget of T fine-iteration equivalents.
+
+    restrict d   : V at depth d -> depth d+1
+    prolong d    : V at depth d+1 -> depth d
+    run d count  : ``count`` iterations of the NMF algorithm at depth d
+
+    Depth 0 is the finest level.  Budgets are exact rationals; Run(d, t)
+    performs floor(t * 4^d) iterations (reading R5), and zero-iteration runs
+    are dropped.
+    """
+    steps: List[Tuple[str, int, int]] = []
+    T = Fraction(T)
+
+    def run(d: int, t: Fraction) -> None:
+        count = math.floor(t * 4 ** d)
+        if count > 0:
+            steps.append(("run", d, int(count)))
+
+    def ni(L: int, t: Fraction, d: int) -> None:          # Alg. 4
+        if L == 1:
+            run(d, t)
+            return
+        steps.append(("restrict", d, 0))
+        ni(L - 1, t / 4, d + 1)
+        steps.append(("prolong", d, 0))
+        run(d, 3 * t / 4)
+
+    def vc(L: int, t: Fraction, d: int) -> None:          # Alg. 5
+        if L == 1:
+            run(d, t)
+            return
+        run(d, t / 4)
+        steps.append(("restrict", d, 0))
+        vc(L - 1, t / 4, d + 1)
+        steps.append(("prolong", d, 0))
+        run(d, t / 2)
+
+    def fmg(L: int, t: Fraction, d: int) -> None:         # Alg. 6
+        if L == 1:
+            run(d, t)
+            return
+        steps.append(("restrict", d, 0))
+        fmg(L - 1, t / 4, d + 1)
+        steps.append(("prolong", d, 0))
+        vc(L, 3 * t / 4, d)
+
+    {NI: ni, VC: vc, FMG: fmg}[cycle](levels, T, 0)
+    return steps
+
+
+def level_iteration_totals(steps: Sequence[Tuple[str, int, int]], levels: int) -> List[int]:
+    tot = [0] * levels
+    for kind, d, c in steps:
+        if kind == "run":
+            tot[d] += c
+    return tot
+
+
+# ---------------------------------------------------------------------------
+# Inner NMF algorithms (Section 2: Alg. 1 ANLS, Alg. 2 MU, Alg. 3 HALS)
+# ---------------------------------------------------------------------------
+
+def hals_update_V(M: np.ndarray, V: np.ndarray, W: np.ndarray, hook=None) -> np.ndarray:
+    """First half of Alg. 3: A = M W^T, B = W W^T, then for k = 1..r in order
+    V[:,k] <- max(0, (A[:,k] - sum_{l != k} V[:,l] B[l,k]) / B[k,k]),
+    using already-updated columns (Gauss-Seidel).  B[k,k] = 0: unchanged (R6)."""
+    V = np.array(V, dtype=np.float64, copy=True)
+    A = M @ W.T
+    B = W @ W.T
+    r = V.shape[1]
+    for k in range(r):
+        if B[k, k] > 0:
+            others = [l for l in range(r) if l != k]
+            s = V[:, others] @ B[others, k]
+            V[:, k] = np.maximum(0.0, (A[:, k] - s) / B[k, k])
+        if hook is not None:
+            hook("V", k, V)
+    return V
+
+
+def hals_update_W(M: np.ndarray, V: np.ndarray, W: np.ndarray, hook=None) -> np.ndarray:
+    """Second half of Alg. 3: C = V^T M, D = V^T V, then for k = 1..r
+    W[k,:] <- max(0, (C[k,:] - sum_{l != k} D[k,l] W[l,:]) / D[k,k])."""
+    W = np.array(W, dtype=np.float64, copy=True)
+    C = V.T @ M
+    D = V.T @ V
+    r = W.shape[0]
+    for k in range(r):
+        if D[k, k] > 0:
+            others = [l for l in range(r) if l != k]
+            s = D[k, others] @ W[others, :]
+            W[k, :] = np.maximum(0.0, (C[k, :] - s) / D[k, k])
+        if hook is not None:
+            hook("W", k, W)
+    return W
+
+
+def hals_iteration(M, V, W):
+    V = hals_update_V(M, V, W)
+    W = hals_update_W(M, V, W)
+    return V, W
+
+
+def mu_update_V(M: np.ndarray, V: np.ndarray, W: np.ndarray) -> np.ndarray:
+    """Alg. 2, first line: V <- V o [M W^T] / [V (W W^T)] (Hadamard ops).
+    Zero denominator: entry unchanged (R7)."""
+    num = M @ W.T
+    den = V @ (W @ W.T)
+    out = np.array(V, dtype=np.float64, copy=True)
+    ok = den > 0
+    out[ok] = V[ok] * num[ok] / den[ok]
+    return out
+
+
+def mu_update_W(M: np.ndarray, V: np.ndarray, W: np.ndarray) -> np.ndarray:
+    """Alg. 2, second line: W <- W o [V^T M] / [(V^T V) W]."""
+    num = V.T @ M
+    den = (V.T @ V) @ W
+    out = np.array(W, dtype=np.float64, copy=True)
+    ok = den > 0
+    out[ok] = W[ok] * num[ok] / den[ok]
+    return out
+
+
+def mu_iteration(M, V, W):
+    V = mu_update_V(M, V, W)
+    W = mu_update_W(M, V, W)
+    return V, W
+
+
+def nnls_gram(G: np.ndarray, b: np.ndarray, x_keep: Optional[np.ndarray] = None,
+              tol_scale: float = 1e-12) -> np.ndarray:
+    """min_{x >= 0} 0.5 x^T G x - b^T x by the Lawson-Hanson active-set method
+    (Appendix A.2, steps 0-3).
+
+    Start with every variable active (at zero).  Repeatedly move into the
+    passive set the active variable with the largest positive negative-gradient
+    b - G x (lowest index on ties), solve the unconstrained problem on the
+    passive set from the normal equations, and whenever a passive variable of
+    that solution is nonpositive, step from x towards it only as far as
+    feasibility allows and return the variables that reached zero to the active
+    set.  Stop when no active variable has a positive negative-gradient above
+    tol = tol_scale * max(1, max|b|).
+
+    Variables with G[k,k] == 0 take no part and keep ``x_keep[k]`` (R8): for a
+    Gram matrix G = X^T X this means column k of X is zero, so row/column k of
+    G and b[k] vanish and the variable does not affect the objective.
+    """
+    r = b.shape[0]
+    live = np.array([G[k, k] > 0 for k in range(r)], dtype=bool)
+    x = np.zeros(r)
+    if x_keep is not None:
+        x[~live] = np.asarray(x_keep, dtype=np.float64)[~live]
+    tol = tol_scale * max(1.0, float(np.max(np.abs(b))) if r else 1.0)
+    passive = np.zeros(r, dtype=bool)
+    blocked = np.zeros(r, dtype=bool)   # entered and was immediately rejected
+    for _outer in range(10 * r + 10):
+        grad_neg = b - G @ x
+        cand = live & ~passive & ~blocked & (grad_neg > tol)
+        if not cand.any():
+            break
+        j = int(np.argmax(np.where(cand, grad_neg, -np.inf)))
+        passive[j] = True
+        first = True
+        while True:
+            idx = np.flatnonzero(passive)
+            z = np.zeros(r)
+            z[~live] = x[~live]
+            z[idx] = np.linalg.solve(G[np.ix_(idx, idx)], b[idx])
+            if np.all(z[idx] > 0):
+                x = z
+                blocked[:] = False
+                break
+            if first and z[j] <= 0:
+                # rounding made the entering variable infeasible: reject it
+                passive[j] = False
+                blocked[j] = True
+                break
+            first = False
+            bad = idx[z[idx] <= 0]
+            ratios = x[bad] / (x[bad] - z[bad])
+            alpha = float(np.min(ratios))
+            x = x + alpha * (z - x)
+            leave = passive & (x <= 0)
+            leave[bad[int(np.argmin(ratios))]] = True
+            x[leave] = 0.0
+            passive &= ~leave
+            blocked[:] = False
+            if not passive.any():
+                break
+    return x
+
+
+def anls_update_V(M: np.ndarray, V: np.ndarray, W: np.ndarray) -> np.ndarray:
+    """Alg. 1, first line: V <- argmin_{V >= 0} ||M - V W||_F^2, i.e. m
+    independent NNLS problems V[i,:] (W W^T) = M[i,:] W^T (Appendix A.2)."""
+    B = W @ W.T
+    A = M @ W.T
+    out = np.empty_like(np.asarray(V, dtype=np.float64))
+    for i in range(M.shape[0]):
+        out[i, :] = nnls_gram(B, A[i, :], x_keep=np.asarray(V[i, :], dtype=np.float64))
+    return out
+
+
+def anls_update_W(M: np.ndarray, V: np.ndarray, W: np.ndarray) -> np.ndarray:
+    """Alg. 1, second line: W <- argmin_{W >= 0} ||M - V W||_F^2, column-wise
+    on the Gram form (V^T V, V^T M[:,j]) (eq. subNNLS)."""
+    D = V.T @ V
+    C = V.T @ M
+    out = np.empty_like(np.asarray(W, dtype=np.float64))
+    for j in range(M.shape[1]):
+        out[:, j] = nnls_gram(D, C[:, j], x_keep=np.asarray(W[:, j], dtype=np.float64))
+    return out
+
+
+def anls_iteration(M, V, W):
+    V = anls_update_V(M, V, W)
+    W = anls_update_W(M, V, W)
+    return V, W
+
+
+def iteration(algo: int, M, V, W):
+    return {HALS: hals_iteration, MU: mu_iteration, ANLS: anls_iteration}[algo](M, V, W)
+
+
+# ---------------------------------------------------------------------------
+# Objective and diagnostics (eq. NMF, eq. subNNLS, Section 4.1 bound)
+# ---------------------------------------------------------------------------
+
+def objective(M, V, W) -> float:
+    """||M - V W||_F^2 (eq. NMF)."""
+    return float(np.sum((np.asarray(M, dtype=np.float64) - V @ W) ** 2))
+
+
+def rel_err(M, V, W) -> float:
+    """||M - V W||_F / ||M||_F, evaluated directly (reading R9)."""
+    M = np.asarray(M, dtype=np.float64)
+    return float(np.linalg.norm(M - V @ W) / np.linalg.norm(M))
+
+
+def gram_form_residual2(normM2, C, W, D, B):
+    """||M - V W||_F^2 written through Gram products (eq. subNNLS summed over
+    columns): ||M||^2 - 2 <V^T M, W> + <V^T V, W W^T>.  Works for numpy floats,
+    and for object arrays of Fractions (exact pins)."""
+    return normM2 - 2 * np.sum(C * W) + np.sum(D * B)
+
+
+def eckart_young_floor(M, r: int) -> float:
+    """Lower bound on rel_err for any rank-r product: sqrt(sum_{i>r} s_i^2)/||M||."""
+    s = np.linalg.svd(np.asarray(M, dtype=np.float64), compute_uv=False)
+    return float(np.sqrt(np.sum(s[r:] ** 2)) / np.sqrt(np.sum(s ** 2)))
+
+
+def prolongation_bound(M, h, w, xfer, Vc, W) -> Tuple[float, float]:
+    """Section 4.1, step 4: ||M - P(V') W|| <= s_M ||M|| + ||P||_F ||R(M) - V' W||.
+    Returns (lhs, rhs)."""
+    M = np.asarray(M, dtype=np.float64)
+    Pm = prolong_matrix(h, w, xfer)
+    lhs = float(np.linalg.norm(M - prolong_images(Vc, h, w, xfer) @ W))
+    sM = smoothness(M, h, w, xfer)
+    Rm = restrict_images(M, h, w, xfer)
+    rhs = sM * float(np.linalg.norm(M)) + float(np.linalg.norm(Pm)) * float(np.linalg.norm(Rm - Vc @ W))
+    return lhs, rhs
+
+
+# ---------------------------------------------------------------------------
+# Whole multilevel solve
+# ---------------------------------------------------------------------------
+
+class SolveResult:
+    def __init__(self):
+        self.V: Optional[np.ndarray] = None
+        self.W: Optional[np.ndarray] = None
+        self.log: List[Tuple[int, float]] = []   # (depth, rel_err) per iteration
+        self.stopped = False
+        self.fine_iters = 0
+        self.total_iters = 0
+        self.fine_equiv = 0.0
+        self.bound_checks: List[Tuple[float, float]] = []
+
+    @property
+    def rel_errs(self) -> np.ndarray:
+        return np.array([e for _, e in self.log])
+
+
+def solve(M, h: int, w: int, r: int, levels: int, algo: int, cycle: int, xfer: int,
+          T, V0, W0, tol: float = 0.0, max_fine_iters: int = 0,
+          check_bound: bool = False, callback=None) -> SolveResult:
+    """Multilevel NMF (Section 4.1 steps 1-5 applied recursively by Alg. 4/5/6).
+
+    The restrictions of M are computed once per level and kept (Alg. 6 note).
+    W is passed between levels unchanged (only m is coarsened).  For ANLS the
+    V iterate is not an input of the algorithm (Alg. 1, Remark 1), so its
+    transfers do not influence the result.
+    """
+    M = np.asarray(M, dtype=np.float64)
+    sides = level_sides(h, w, levels)
+    Ms = [M]
+    for d in range(levels - 1):
+        hd, wd = sides[d]
+        Ms.append(restrict_images(Ms[-1], hd, wd, xfer))
+    V = np.asarray(V0, dtype=np.float64).copy()
+    W = np.asarray(W0, dtype=np.float64).copy()
+    res = SolveResult()
+    depth = 0
+
+    def one(d):
+        nonlocal V, W
+        V, W = iteration(algo, Ms[d], V, W)
+        e = rel_err(Ms[d], V, W)
+        res.log.append((d, e))
+        res.total_iters += 1
+        res.fine_equiv += 4.0 ** (-d)
+        if d == 0:
+            res.fine_iters += 1
+        if callback is not None:
+            callback(d, V, W, e)
+        return e
+
+    for kind, d, count in schedule(cycle, levels, T):
+        if kind == "restrict":
+            assert depth == d
+            hd, wd = sides[d]
+            V = restrict_images(V, hd, wd, xfer)
+            depth = d + 1
+        elif kind == "prolong":
+            assert depth == d + 1
+            hd, wd = sides[d]
+            if check_bound:
+                res.bound_checks.append(prolongation_bound(Ms[d], hd, wd, xfer, V, W))
+            V = prolong_images(V, hd, wd, xfer)
+            depth = d
+        else:
+            assert depth == d
+            for _ in range(count):
+                e = one(d)
+                if tol > 0 and d == 0 and e <= tol:
+                    res.stopped = True
+                    break
+        if res.stopped:
+            break
+    assert res.stopped or depth == 0
+    if tol > 0 and not res.stopped:
+        for _ in range(max_fine_iters):
+            if one(0) <= tol:
+                res.stopped = True
+                break
+    res.V, res.W = V, W
+    return res

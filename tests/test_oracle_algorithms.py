@@ -1,0 +1,218 @@
+"""Pins for the oracle's inner NMF algorithms (Alg. 1-3, Appendix A)."""
+import itertools
+from fractions import Fraction
+
+import numpy as np
+import pytest
+import scipy.optimize as so
+
+import oracle as O
+
+
+def rand_problem(m, n, r, seed):
+    rng = np.random.default_rng(seed)
+    M = rng.uniform(size=(m, n))
+    V = rng.uniform(size=(m, r))
+    W = rng.uniform(size=(r, n))
+    return M, V, W
+
+
+# --------------------------------------------------------------------- HALS
+
+@pytest.mark.parametrize("seed", range(6))
+def test_hals_each_column_step_is_the_bruteforce_minimiser(seed):
+    # Each V[:,k] (resp. W[k,:]) update is the exact minimiser of the objective
+    # over that column (row) with the others fixed (Section 2.3).  The brute
+    # force: a bounded least-squares solver on the one-column problem.
+    M, V, W = rand_problem(5, 6, 3, seed)
+    state = {"V": V.copy(), "W": W.copy()}
+
+    def hook_v(which, k, Vnew):
+        Vprev = state["V"]
+        assert W[k, :].any()
+        rest = M - np.delete(Vprev, k, axis=1) @ np.delete(W, k, axis=0)
+        A = np.kron(W[k, :][:, None], np.eye(M.shape[0]))      # vec(v w_k^T) = (w_k (x) I) v
+        sol = so.lsq_linear(A, rest.reshape(-1, order="F"), bounds=(0, np.inf),
+                            tol=1e-14, method="bvls").x
+        np.testing.assert_allclose(Vnew[:, k], sol, atol=1e-9)
+        # the other columns are untouched by this step
+        np.testing.assert_array_equal(np.delete(Vnew, k, 1), np.delete(Vprev, k, 1))
+        state["V"] = Vnew.copy()
+
+    Vn = O.hals_update_V(M, V, W, hook=hook_v)
+
+    def hook_w(which, k, Wnew):
+        Wprev = state["W"]
+        if not Vn[:, k].any():
+            # D_kk = 0: every row is a minimiser; the oracle keeps it (reading R6)
+            np.testing.assert_array_equal(Wnew[k, :], Wprev[k, :])
+            state["W"] = Wnew.copy()
+            return
+        rest = M - np.delete(Vn, k, axis=1) @ np.delete(Wprev, k, axis=0)
+        A = np.kron(np.eye(M.shape[1]), Vn[:, k][:, None])     # vec(v_k w^T) = (I (x) v_k) w
+        sol = so.lsq_linear(A, rest.reshape(-1, order="F"), bounds=(0, np.inf),
+                            tol=1e-14, method="bvls").x
+        np.testing.assert_allclose(Wnew[k, :], sol, atol=1e-9)
+        state["W"] = Wnew.copy()
+
+    O.hals_update_W(M, Vn, W, hook=hook_w)
+
+
+def test_hals_objective_nonincreasing_after_every_column_update():
+    M, V, W = rand_problem(12, 9, 4, 7)
+    vals = [O.objective(M, V, W)]
+    cur = {"W": W}
+    Vn = O.hals_update_V(M, V, W, hook=lambda _, k, Vk: vals.append(O.objective(M, Vk, W)))
+    O.hals_update_W(M, Vn, W, hook=lambda _, k, Wk: vals.append(O.objective(M, Vn, Wk)))
+    assert len(vals) == 1 + 2 * 4
+    assert all(b <= a * (1 + 1e-13) for a, b in zip(vals, vals[1:]))
+
+
+def test_hals_zero_row_of_W_leaves_V_column_unchanged():
+    M, V, W = rand_problem(6, 5, 3, 1)
+    W[1, :] = 0.0
+    Vn = O.hals_update_V(M, V, W)
+    np.testing.assert_array_equal(Vn[:, 1], V[:, 1])
+
+
+# ----------------------------------------------------------------------- MU
+
+@pytest.mark.parametrize("seed", range(4))
+def test_mu_each_half_step_is_nonincreasing(seed):
+    M, V, W = rand_problem(15, 11, 4, seed)
+    for _ in range(20):
+        f0 = O.objective(M, V, W)
+        V = O.mu_update_V(M, V, W)
+        f1 = O.objective(M, V, W)
+        W = O.mu_update_W(M, V, W)
+        f2 = O.objective(M, V, W)
+        assert f1 <= f0 * (1 + 1e-13) and f2 <= f1 * (1 + 1e-13)
+
+
+def test_mu_zero_entries_stay_zero_and_scalar_case():
+    M, V, W = rand_problem(8, 7, 3, 3)
+    V[2, 1] = 0.0
+    W[0, 4] = 0.0
+    V2, W2 = O.mu_iteration(M, V, W)
+    assert V2[2, 1] == 0.0 and W2[0, 4] == 0.0
+    # 1x1x1: V <- V * (M W) / (V W W) = M / W exactly
+    v = O.mu_update_V(np.array([[6.0]]), np.array([[5.0]]), np.array([[2.0]]))
+    assert v[0, 0] == 3.0
+
+
+# --------------------------------------------------------------------- ANLS
+
+def enumerate_nnls(G, b):
+    """Exhaustive search over all 2^r passive sets with a KKT check."""
+    r = len(b)
+    best = None
+    for mask in itertools.product([False, True], repeat=r):
+        idx = [i for i in range(r) if mask[i]]
+        x = np.zeros(r)
+        if idx:
+            x[idx] = np.linalg.solve(G[np.ix_(idx, idx)], b[idx])
+        g = G @ x - b
+        if (x >= -1e-12).all() and all(abs(g[i]) < 1e-9 for i in idx) and \
+                all(g[i] >= -1e-9 for i in range(r) if i not in idx):
+            assert best is None or np.allclose(best, x, atol=1e-9), "KKT point not unique"
+            best = x
+    return best
+
+
+@pytest.mark.parametrize("r", [1, 2, 3, 4])
+@pytest.mark.parametrize("seed", range(10))
+def test_nnls_equals_exhaustive_enumeration(r, seed):
+    rng = np.random.default_rng(100 * r + seed)
+    X = rng.normal(size=(r + 3, r))
+    y = rng.normal(size=r + 3)
+    G, b = X.T @ X, X.T @ y
+    np.testing.assert_allclose(O.nnls_gram(G, b), enumerate_nnls(G, b), atol=1e-9)
+
+
+@pytest.mark.parametrize("r", [5, 10, 20, 40])
+def test_nnls_equals_scipy_nnls(r):
+    rng = np.random.default_rng(r)
+    for _ in range(5):
+        X = np.abs(rng.normal(size=(3 * r, r)))
+        y = rng.normal(size=3 * r) + 0.3
+        ref, _ = so.nnls(X, y)
+        got = O.nnls_gram(X.T @ X, X.T @ y)
+        np.testing.assert_allclose(got, ref, atol=1e-8 * max(1, np.abs(ref).max()))
+
+
+def test_anls_half_steps_are_exact_minimisers():
+    M, V, W = rand_problem(20, 15, 5, 11)
+    Vn = O.anls_update_V(M, V, W)
+    for i in range(M.shape[0]):
+        ref, _ = so.nnls(W.T, M[i, :])
+        np.testing.assert_allclose(Vn[i], ref, atol=1e-9)
+    Wn = O.anls_update_W(M, Vn, W)
+    for j in range(M.shape[1]):
+        ref, _ = so.nnls(Vn, M[:, j])
+        np.testing.assert_allclose(Wn[:, j], ref, atol=1e-9)
+
+
+def test_anls_ignores_initial_V():
+    M, V, W = rand_problem(10, 8, 3, 5)
+    a = O.anls_iteration(M, V, W)
+    b = O.anls_iteration(M, np.zeros_like(V), W)
+    np.testing.assert_allclose(a[0], b[0], atol=1e-13)
+    np.testing.assert_allclose(a[1], b[1], atol=1e-13)
+
+
+def test_nnls_zero_diagonal_variable_keeps_value():
+    X = np.random.default_rng(0).uniform(size=(6, 3))
+    X[:, 1] = 0.0
+    y = np.random.default_rng(1).uniform(size=6)
+    x = O.nnls_gram(X.T @ X, X.T @ y, x_keep=np.array([9.0, 7.0, 9.0]))
+    assert x[1] == 7.0
+    ref, _ = so.nnls(X[:, [0, 2]], y)
+    np.testing.assert_allclose(x[[0, 2]], ref, atol=1e-10)
+
+
+# -------------------------------------------------------------- all three
+
+@pytest.mark.parametrize("algo", [O.HALS, O.MU, O.ANLS])
+def test_exact_positive_factorisation_is_a_fixed_point(algo):
+    rng = np.random.default_rng(42)
+    Vs = rng.uniform(0.5, 1.5, size=(9, 3))
+    Ws = rng.uniform(0.5, 1.5, size=(3, 7))
+    M = Vs @ Ws
+    V, W = O.iteration(algo, M, Vs, Ws)
+    np.testing.assert_allclose(V, Vs, rtol=1e-9)
+    np.testing.assert_allclose(W, Ws, rtol=1e-9)
+
+
+@pytest.mark.parametrize("algo", [O.HALS, O.MU, O.ANLS])
+def test_monotone_and_above_eckart_young(algo):
+    M, V, W = rand_problem(30, 20, 4, 9)
+    floor = O.eckart_young_floor(M, 4)
+    prev = O.rel_err(M, V, W)
+    for _ in range(15):
+        V, W = O.iteration(algo, M, V, W)
+        e = O.rel_err(M, V, W)
+        assert e <= prev * (1 + 1e-12)
+        assert e >= floor * (1 - 1e-12)
+        assert (V >= 0).all() and (W >= 0).all()
+        prev = e
+
+
+def test_gram_form_residual_equals_direct_residual_exactly():
+    # eq. subNNLS summed over columns, checked in exact rational arithmetic.
+    rng = np.random.default_rng(3)
+    M = rng.integers(0, 9, size=(5, 4)).astype(object)
+    V = rng.integers(0, 5, size=(5, 2)).astype(object)
+    W = rng.integers(0, 5, size=(2, 4)).astype(object)
+    F = np.vectorize(Fraction)
+    M, V, W = F(M), F(V), F(W)
+    direct = np.sum((M - V.dot(W)) ** 2)
+    normM2 = np.sum(M * M)
+    got = O.gram_form_residual2(normM2, V.T.dot(M), W, V.T.dot(V), W.dot(W.T))
+    assert got == direct
+
+
+def test_rel_err_definition():
+    M = np.array([[3.0, 0.0], [0.0, 4.0]])
+    V = np.array([[1.0], [0.0]])
+    W = np.array([[3.0, 0.0]])
+    assert O.rel_err(M, V, W) == pytest.approx(4.0 / 5.0, abs=1e-15)
