@@ -1,0 +1,182 @@
+/*
+ * nmf.h - C ABI of the MI355X multilevel NMF library (libnmf.so).
+ *
+ * Problem (Section 2, eq. NMF): given a nonnegative m x n matrix M whose
+ * columns are vectorised h x w images (m = h*w) and a rank r, find V >= 0
+ * (m x r) and W >= 0 (r x n) with M ~ V W, minimising ||M - V W||_F^2.
+ *
+ * Method (Section 4): the inner algorithm (HALS = Alg. 3, MU = Alg. 2,
+ * ANLS = Alg. 1) runs on a hierarchy of coarser pixel grids built by the
+ * nonnegative restriction of eq. restr; V is moved between levels by the
+ * prolongation of eq. prol; the order of levels is nested iteration (Alg. 4),
+ * V-cycle (Alg. 5) or full multigrid (Alg. 6) with the Table 1 budget split.
+ *
+ * Conventions shared by every entry point
+ *  - All device pointers are HIP device memory on the current device.  The
+ *    caller allocates and owns every buffer; nmf_solve never allocates and
+ *    never frees caller memory.  A "stream" is a hipStream_t passed as void*
+ *    (NULL = the null stream).
+ *  - Layouts: M is m x n column-major (image j = M + j*ldm, ldm >= m, each
+ *    image row-major: pixel (y, x) at y*w + x).  V is m x r column-major
+ *    (basis image k = V + k*m).  W is r x n row-major (W + k*n).
+ *  - Every call returns an nmf_status; no exception or abort crosses the ABI.
+ *    On error nmf_last_error(plan) (or nmf_last_error(NULL) for errors that
+ *    precede a plan) returns a human-readable message (thread-local storage,
+ *    valid until the next call on the same thread).
+ */
+#ifndef NMF_H
+#define NMF_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct nmf_plan_s *nmf_plan_t;
+typedef int32_t nmf_status;
+
+enum {
+    NMF_OK = 0,
+    NMF_E_ARG = -1,        /* null pointer, unknown enum, bad iteration count      */
+    NMF_E_SHAPE = -2,      /* m != h*w, r out of [1,64], a side < 2 to restrict,
+                              ANLS with a level that has fewer pixels than r       */
+    NMF_E_NOMEM = -3,      /* workspace too small / host allocation failed          */
+    NMF_E_DEVICE = -4,     /* a HIP call failed (message has the HIP error)         */
+    NMF_E_NONFINITE = -5,  /* NaN/Inf in M (input check) or in a residual           */
+    NMF_E_NEGATIVE = -6,   /* M has a negative entry (input check)                  */
+    NMF_E_BUSY = -7        /* server: request does not fit the admission budget     */
+};
+
+enum { NMF_HALS = 0, NMF_MU = 1, NMF_ANLS = 2 };          /* Alg. 3, Alg. 2, Alg. 1 */
+enum { NMF_NI = 0, NMF_VC = 1, NMF_FMG = 2 };             /* Alg. 4, Alg. 5, Alg. 6 */
+/* Transfer operators.  FW: full weighting (eq. restr, boundary weights of the
+ * fine neighbours that exist renormalised to sum 1) with the rd() mean
+ * prolongation (eq. prol).  BLOCK2: 2x2 pixel-block mean / replication. */
+enum { NMF_XFER_FW = 0, NMF_XFER_BLOCK2 = 1 };
+/* Number format of the two M-streaming products M W^T and V^T M.  BF16 keeps
+ * an extra bf16 copy of every level of M in the workspace and accumulates in
+ * FP32; Grams, updates and residuals stay FP32/FP64 as in FP32 mode. */
+enum { NMF_FP32 = 0, NMF_BF16 = 1 };
+
+typedef struct {
+    int64_t m, n;          /* M is m x n; m must equal h*w                          */
+    int64_t ldm;           /* column stride of M in elements (0 = m)                */
+    int32_t h, w;          /* finest image grid                                     */
+    int32_t r;             /* rank, 1..64                                           */
+    int32_t levels;        /* >= 1 (1 = plain single-level NMF)                     */
+    int32_t algo;          /* NMF_HALS / NMF_MU / NMF_ANLS                          */
+    int32_t cycle;         /* NMF_NI / NMF_VC / NMF_FMG                             */
+    int32_t xfer;          /* NMF_XFER_FW / NMF_XFER_BLOCK2                         */
+    int32_t prec;          /* NMF_FP32 / NMF_BF16                                   */
+    int32_t refine_iters;  /* BF16 only: finest-level FP32 iterations appended      */
+    int32_t max_fine_iters;/* tol > 0: cap on finest-level iterations after the
+                              schedule (0 = none)                                   */
+    int32_t check_every;   /* tol > 0: host polls the device stop flag every this
+                              many continuation iterations (0 = 8)                  */
+    int32_t log_cap;       /* capacity of the per-iteration rel_err log (0 = 4096)  */
+    int32_t check_input;   /* 1: scan M for negative / non-finite entries first    */
+    int32_t reserved;
+    double tol;            /* > 0: stop after the first finest-level iteration with
+                              rel_err <= tol (absolute threshold on rel_err)        */
+} nmf_desc;
+
+typedef struct {
+    int32_t log_len;         /* iterations logged (all levels, <= log_cap)          */
+    int32_t total_iters;     /* iterations executed over all levels                 */
+    int32_t fine_iters;      /* iterations executed on the finest level             */
+    int32_t stopped;         /* 1 if tol was reached                                */
+    double rel_err;          /* rel_err of the last iteration executed              */
+    double fine_equiv;       /* work in finest-iteration equivalents: sum 4^-depth  */
+} nmf_result;
+
+/* Validate a problem description and build a plan (host only, no device
+ * work).  *workspace_bytes receives the size of the device workspace every
+ * nmf_solve with this plan needs (256-byte aligned base required). */
+nmf_status nmf_plan(const nmf_desc *desc, nmf_plan_t *out, size_t *workspace_bytes);
+
+/* Run the multilevel solve with a budget of `iters` finest-iteration
+ * equivalents (Table 1; levels = 1 gives `iters` plain iterations).
+ * dV (m x r) and dW (r x n) hold V0, W0 on entry and the result on return
+ * (for ANLS V0 is not used, Alg. 1 / Remark 1).  dM is read only.
+ * The call enqueues work on `stream`; it returns after the stream finished
+ * (it synchronises once at the end, and every check_every continuation
+ * iterations when tol > 0).  The per-iteration rel_err log is read with
+ * nmf_query_log.  Concurrent solves with the same plan must use distinct
+ * workspaces. */
+nmf_status nmf_solve(nmf_plan_t plan, const float *dM, float *dV, float *dW, int32_t iters,
+                     void *dWorkspace, void *stream, nmf_result *hOut);
+
+nmf_status nmf_destroy(nmf_plan_t plan);
+
+const char *nmf_status_string(nmf_status s);
+const char *nmf_last_error(nmf_plan_t plan);
+
+/* ---- introspection (host only; used by the bit-exact tests) --------------- */
+
+/* Image sides of every level, finest first: hw[2*l] = h_l, hw[2*l+1] = w_l. */
+nmf_status nmf_query_levels(nmf_plan_t plan, int32_t *hw, int32_t cap_levels);
+
+/* The integer schedule for a budget of `iters`: triples (kind, depth, count)
+ * with kind 0 = run `count` iterations at `depth`, 1 = restrict V from depth
+ * to depth+1, 2 = prolong V from depth+1 to depth.  *nsteps receives the
+ * number of triples; at most cap triples are written. */
+nmf_status nmf_query_schedule(nmf_plan_t plan, int32_t iters, int32_t *steps, int32_t cap,
+                              int32_t *nsteps);
+
+/* Copy the rel_err log of the last nmf_solve (device workspace -> host):
+ * rel_err[i] and depth[i] for i < min(cap, log_len).  Synchronises `stream`. */
+nmf_status nmf_query_log(nmf_plan_t plan, const void *dWorkspace, void *stream,
+                         double *rel_err, int32_t *depth, int32_t cap);
+
+/* ---- single operators (device pointers; used by the kernel parity tests) -- */
+
+/* Y = R(X) columnwise for `ncols` images of X (h x w, column stride ldx) into
+ * Y (ceil(h/2) x ceil(w/2), column stride ceil(h/2)*ceil(w/2)); eq. restr. */
+nmf_status nmf_restrict(int32_t xfer, int32_t h, int32_t w, int64_t ncols, const float *dX,
+                        int64_t ldx, float *dY, void *stream);
+
+/* X = P(Y) columnwise: Y has ceil(h/2) x ceil(w/2) images, X has h x w; eq. prol. */
+nmf_status nmf_prolong(int32_t xfer, int32_t h, int32_t w, int64_t ncols, const float *dY,
+                       float *dX, void *stream);
+
+/* One iteration of `algo` on a single level (the update of V then W, as the
+ * sweep inside nmf_solve does), followed by the residual.  The workspace is
+ * the one of a plan with levels = 1 and the same m, n, r, algo, prec.  The
+ * rel_err of the iteration is written to *hRelErr (synchronises). */
+nmf_status nmf_iterate(nmf_plan_t plan, const float *dM, float *dV, float *dW, int32_t count,
+                       void *dWorkspace, void *stream, double *hRelErr);
+
+/* The two M-streaming products on their own: A = M W^T (m x r, column-major)
+ * and C = V^T M (r x n, row-major), FP32 operands on the matrix cores with
+ * FP32 accumulation (the products A and C of Alg. 3; 2mnr flops each,
+ * Appendix A.1).  Level-0 shapes of `plan`; its workspace is used as scratch.
+ * Synchronises nothing. */
+nmf_status nmf_products(nmf_plan_t plan, const float *dM, const float *dV, const float *dW,
+                        float *dA, float *dC, void *dWorkspace, void *stream);
+
+/* FP64 Gram G = X X^T of r vectors of length L (vector a at dX + a*ldx),
+ * accumulated in FP64 (used for W W^T and V^T V).  dG is r x r FP64. */
+nmf_status nmf_gram(int32_t r, int64_t L, const float *dX, int64_t ldx, double *dG,
+                    void *dWorkspace, size_t ws_bytes, void *stream);
+
+/* ---- kernel timing (HIP events on the solve's stream) ---------------------
+ * Kernel kinds: 0 A-pass (M W^T + V update), 1 Gram V^T V, 2 C-pass partials
+ * (V^T M), 3 C-pass reduction + W update, 4 Gram W W^T, 5 residual, 6 NNLS
+ * rows of V, 7 NNLS columns of W, 8 restriction, 9 prolongation, 10 ||M||^2.
+ * With bit k of `mask` set, every launch of kind k by later nmf_solve /
+ * nmf_iterate calls on this plan is bracketed by two hipEventRecord calls on
+ * the call's stream; the elapsed times are summed when the call synchronises
+ * at its end.  nmf_profile_read copies the per-kind launch counts and total
+ * milliseconds (cap entries) and, if reset != 0, clears them. */
+#define NMF_NUM_KERNEL_KINDS 11
+nmf_status nmf_profile(nmf_plan_t plan, uint32_t mask);
+nmf_status nmf_profile_read(nmf_plan_t plan, int64_t *counts, double *total_ms, int32_t cap,
+                            int32_t reset);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* NMF_H */

@@ -1,0 +1,504 @@
+// C ABI of libnmf and the host executor that runs a schedule on a stream.
+#include <cstdio>
+#include <cstring>
+#include <new>
+
+#include "nmf_internal.h"
+
+struct nmf_plan_s {
+    nmf::Plan p;
+};
+
+namespace nmf {
+
+namespace {
+
+thread_local std::string g_err;
+
+nmf_status fail(nmf_plan_t plan, nmf_status st, const std::string &msg) {
+    if (plan) plan->p.err = msg;
+    g_err = msg;
+    return st;
+}
+
+#define NMF_HIP(call)                                                                      \
+    do {                                                                                   \
+        hipError_t e_ = (call);                                                            \
+        if (e_ != hipSuccess)                                                              \
+            return fail(plan, NMF_E_DEVICE, std::string(#call) + ": " + hipGetErrorString(e_)); \
+    } while (0)
+
+// Pointers into one workspace, for one solve.
+struct Ctx {
+    nmf_plan_t plan;
+    const Plan *p;
+    hipStream_t s;
+    char *ws;
+    DevState *st;
+    const int32_t *stop;
+    double *log_rel;
+    int32_t *log_depth;
+    double *norm;
+    double *Bd, *Dd, *gparts, *rparts;
+    float *Bf, *Df, *A, *C;
+    double *Cp;
+    std::vector<const float *> M;
+    std::vector<int64_t> ldm;
+    std::vector<float *> V;
+    float *W;
+    int log_idx = 0;
+    std::vector<int8_t> depths;   // depth of every executed iteration (host mirror)
+};
+
+template <class T>
+T *at(char *base, size_t off) {
+    return reinterpret_cast<T *>(base + off);
+}
+
+// ---- optional HIP-event timing of selected kernel kinds -------------------
+int prof_begin(nmf_plan_t plan, hipStream_t s, int kind) {
+    Profiler &pf = plan->p.prof;
+    if (!(pf.mask & (1u << kind))) return -1;
+    const size_t i = pf.pending_kind.size();
+    while (pf.pool.size() < 2 * (i + 1)) {
+        hipEvent_t e;
+        if (hipEventCreate(&e) != hipSuccess) return -1;
+        pf.pool.push_back(e);
+    }
+    if (hipEventRecord(pf.pool[2 * i], s) != hipSuccess) return -1;
+    pf.pending_kind.push_back(kind);
+    return (int)i;
+}
+
+void prof_end(nmf_plan_t plan, hipStream_t s, int idx) {
+    if (idx >= 0) (void)hipEventRecord(plan->p.prof.pool[2 * idx + 1], s);
+}
+
+// Call only after the stream has been synchronised.
+void prof_collect(nmf_plan_t plan) {
+    Profiler &pf = plan->p.prof;
+    for (size_t i = 0; i < pf.pending_kind.size(); ++i) {
+        float ms = 0.0f;
+        if (hipEventElapsedTime(&ms, pf.pool[2 * i], pf.pool[2 * i + 1]) == hipSuccess) {
+            pf.counts[pf.pending_kind[i]]++;
+            pf.ms[pf.pending_kind[i]] += ms;
+        }
+    }
+    pf.pending_kind.clear();
+    (void)hipGetLastError();
+}
+
+#define NMF_LAUNCH(kind, call)                              \
+    do {                                                    \
+        const int pi_ = prof_begin(c.plan, c.s, (kind));    \
+        NMF_HIP(call);                                      \
+        prof_end(c.plan, c.s, pi_);                         \
+    } while (0)
+
+Ctx make_ctx(nmf_plan_t plan, const float *dM, float *dV, float *dW, void *dws, hipStream_t s) {
+    const Plan &p = plan->p;
+    plan->p.prof.pending_kind.clear();
+    Ctx c;
+    c.plan = plan;
+    c.p = &p;
+    c.s = s;
+    c.ws = static_cast<char *>(dws);
+    c.st = at<DevState>(c.ws, p.ws.off_state);
+    c.stop = &c.st->stop;
+    c.log_rel = at<double>(c.ws, p.ws.off_log);
+    c.log_depth = at<int32_t>(c.ws, p.ws.off_logdepth);
+    c.norm = at<double>(c.ws, p.ws.off_norm);
+    c.Bd = at<double>(c.ws, p.ws.off_Bd);
+    c.Dd = at<double>(c.ws, p.ws.off_Dd);
+    c.Bf = at<float>(c.ws, p.ws.off_Bf);
+    c.Df = at<float>(c.ws, p.ws.off_Df);
+    c.gparts = at<double>(c.ws, p.ws.off_gparts);
+    c.rparts = at<double>(c.ws, p.ws.off_rparts);
+    c.Cp = at<double>(c.ws, p.ws.off_cparts);
+    c.A = p.ws.off_A ? at<float>(c.ws, p.ws.off_A) : nullptr;
+    c.C = p.ws.off_C ? at<float>(c.ws, p.ws.off_C) : nullptr;
+    for (size_t l = 0; l < p.lv.size(); ++l) {
+        if (l == 0) {
+            c.M.push_back(dM);
+            c.ldm.push_back(p.d.ldm);
+            c.V.push_back(dV);
+        } else {
+            c.M.push_back(at<float>(c.ws, p.lv[l].off_M));
+            c.ldm.push_back(p.lv[l].m);
+            c.V.push_back(at<float>(c.ws, p.lv[l].off_V));
+        }
+    }
+    c.W = dW;
+    return c;
+}
+
+nmf_status gram_W(Ctx &c) {
+    nmf_plan_t plan = c.plan;
+    const Plan &p = *c.p;
+    NMF_LAUNCH(K_GRAM_W, launch_gram(p.rpad, p.d.r, p.d.n, c.W, p.d.n, p.gram_w_parts,
+                                     p.gram_w_chunk, c.gparts, c.Bd, c.Bf, c.stop, c.s));
+    return NMF_OK;
+}
+
+// One iteration of the inner algorithm at depth d, then the residual.
+nmf_status sweep(Ctx &c, int d) {
+    nmf_plan_t plan = c.plan;
+    const Plan &p = *c.p;
+    const LevelInfo &li = p.lv[d];
+    const int r = p.d.r;
+    const int64_t n = p.d.n, m = li.m;
+    const float *M = c.M[d];
+    const int64_t ld = c.ldm[d];
+    float *V = c.V[d];
+    int32_t *flags = &c.st->flags;
+    int nparts;
+    if (p.d.algo == NMF_ANLS) {
+        NMF_LAUNCH(K_APASS, launch_apass(p.rpad, 2, M, ld, m, n, c.W, c.Bd, V, c.A, r, c.stop, c.s));
+        NMF_LAUNCH(K_NNLS_ROWS, launch_nnls_rows(p.rpad, c.Bd, c.A, m, r, V, flags, c.stop, c.s));
+        NMF_LAUNCH(K_GRAM_V, launch_gram(p.rpad, r, m, V, m, li.gram_parts, li.gram_chunk, c.gparts, c.Dd,
+                            c.Df, c.stop, c.s));
+        NMF_LAUNCH(K_CPART, launch_cpass_partial(p.rpad, M, ld, m, n, V, r, li.cp_chunks, li.cp_chunk, c.Cp,
+                                     c.stop, c.s));
+        NMF_LAUNCH(K_CFINAL, launch_cpass_final(p.rpad, 2, c.Cp, li.cp_chunks, n, r, c.Dd, c.W, c.C, c.rparts,
+                                   c.stop, c.s));
+        NMF_LAUNCH(K_NNLS_COLS, launch_nnls_cols(p.rpad, c.Dd, c.C, n, r, c.W, c.rparts, flags, c.stop, c.s));
+        nparts = nnls_cols_blocks(n);
+    } else {
+        const int mode = p.d.algo == NMF_HALS ? 0 : 1;
+        NMF_LAUNCH(K_APASS, launch_apass(p.rpad, mode, M, ld, m, n, c.W, c.Bd, V, nullptr, r, c.stop, c.s));
+        NMF_LAUNCH(K_GRAM_V, launch_gram(p.rpad, r, m, V, m, li.gram_parts, li.gram_chunk, c.gparts, c.Dd,
+                            c.Df, c.stop, c.s));
+        NMF_LAUNCH(K_CPART, launch_cpass_partial(p.rpad, M, ld, m, n, V, r, li.cp_chunks, li.cp_chunk, c.Cp,
+                                     c.stop, c.s));
+        NMF_LAUNCH(K_CFINAL, launch_cpass_final(p.rpad, mode, c.Cp, li.cp_chunks, n, r, c.Dd, c.W, nullptr,
+                                   c.rparts, c.stop, c.s));
+        nparts = cpass_final_blocks(n);
+    }
+    nmf_status st = gram_W(c);
+    if (st != NMF_OK) return st;
+    NMF_LAUNCH(K_RESID, launch_residual(c.rparts, nparts, c.Dd, c.Bd, r, c.norm, d, c.log_rel,
+                                        c.log_depth, c.log_idx, p.d.log_cap, c.st, p.d.tol, c.s));
+    c.log_idx++;
+    c.depths.push_back((int8_t)d);
+    return NMF_OK;
+}
+
+// Restrict M to every level (cached for the whole solve, as in Alg. 6's note)
+// and compute ||M_l||_F^2 in FP64.
+nmf_status prepare_levels(Ctx &c) {
+    nmf_plan_t plan = c.plan;
+    const Plan &p = *c.p;
+    for (size_t l = 1; l < p.lv.size(); ++l) {
+        NMF_LAUNCH(K_RESTRICT, launch_restrict(p.d.xfer, p.lv[l - 1].h, p.lv[l - 1].w, p.d.n,
+                                               c.M[l - 1], c.ldm[l - 1],
+                                               const_cast<float *>(c.M[l]), nullptr, c.s));
+    }
+    for (size_t l = 0; l < p.lv.size(); ++l) {
+        NMF_LAUNCH(K_SUMSQ,
+                   launch_sumsq(c.M[l], c.ldm[l], p.lv[l].m, p.d.n, c.rparts, 1024, c.norm + l, c.s));
+    }
+    return NMF_OK;
+}
+
+nmf_status read_state(Ctx &c, DevState &hs) {
+    nmf_plan_t plan = c.plan;
+    NMF_HIP(hipMemcpyAsync(&hs, c.st, sizeof(DevState), hipMemcpyDeviceToHost, c.s));
+    NMF_HIP(hipStreamSynchronize(c.s));
+    return NMF_OK;
+}
+
+nmf_status check_input(Ctx &c) {
+    nmf_plan_t plan = c.plan;
+    const Plan &p = *c.p;
+    NMF_HIP(launch_check_input(c.M[0], p.d.ldm, p.d.m, p.d.n, &c.st->flags, c.s));
+    DevState hs;
+    nmf_status st = read_state(c, hs);
+    if (st != NMF_OK) return st;
+    if (hs.flags & 2) return fail(plan, NMF_E_NONFINITE, "M has a NaN or Inf entry");
+    if (hs.flags & 1) return fail(plan, NMF_E_NEGATIVE, "M has a negative entry");
+    return NMF_OK;
+}
+
+nmf_status finish(Ctx &c, nmf_result *out) {
+    nmf_plan_t plan = c.plan;
+    DevState hs;
+    nmf_status st = read_state(c, hs);
+    if (st != NMF_OK) return st;
+    prof_collect(plan);
+    if (out) {
+        memset(out, 0, sizeof *out);
+        const int n = hs.log_len;
+        out->log_len = n < c.p->d.log_cap ? n : c.p->d.log_cap;
+        out->total_iters = n;
+        out->stopped = hs.stopped;
+        out->rel_err = hs.last_rel;
+        for (int i = 0; i < n && i < (int)c.depths.size(); ++i) {
+            if (c.depths[i] == 0) out->fine_iters++;
+            double f = 1.0;
+            for (int k = 0; k < c.depths[i]; ++k) f *= 0.25;
+            out->fine_equiv += f;
+        }
+    }
+    if (hs.status != 0)
+        return fail(plan, hs.status, "non-finite residual during the solve");
+    if (hs.flags & 4)
+        return fail(plan, NMF_E_NONFINITE,
+                    "NNLS met a non-positive pivot (collinear or singular Gram)");
+    return NMF_OK;
+}
+
+}  // namespace
+}  // namespace nmf
+
+using namespace nmf;
+
+extern "C" {
+
+const char *nmf_status_string(nmf_status s) {
+    switch (s) {
+        case NMF_OK: return "ok";
+        case NMF_E_ARG: return "invalid argument";
+        case NMF_E_SHAPE: return "invalid shape";
+        case NMF_E_NOMEM: return "out of memory / workspace too small";
+        case NMF_E_DEVICE: return "device (HIP) error";
+        case NMF_E_NONFINITE: return "non-finite value";
+        case NMF_E_NEGATIVE: return "negative entry in M";
+        case NMF_E_BUSY: return "admission budget exceeded";
+        default: return "unknown status";
+    }
+}
+
+const char *nmf_last_error(nmf_plan_t plan) {
+    return plan ? plan->p.err.c_str() : g_err.c_str();
+}
+
+nmf_status nmf_plan(const nmf_desc *desc, nmf_plan_t *out, size_t *workspace_bytes) {
+    if (!desc || !out) return fail(nullptr, NMF_E_ARG, "null desc or out");
+    nmf_plan_t plan = new (std::nothrow) nmf_plan_s;
+    if (!plan) return fail(nullptr, NMF_E_NOMEM, "host allocation failed");
+    int dev = 0, cus = 0;
+    if (hipGetDevice(&dev) == hipSuccess &&
+        hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess &&
+        cus > 0)
+        plan->p.num_cu = cus;
+    else
+        plan->p.num_cu = 256;
+    (void)hipGetLastError();
+    std::string err;
+    nmf_status st = build_plan(*desc, plan->p, err);
+    if (st != NMF_OK) {
+        delete plan;
+        return fail(nullptr, st, err);
+    }
+    *out = plan;
+    if (workspace_bytes) *workspace_bytes = plan->p.ws.total;
+    return NMF_OK;
+}
+
+nmf_status nmf_destroy(nmf_plan_t plan) {
+    if (plan)
+        for (hipEvent_t e : plan->p.prof.pool) (void)hipEventDestroy(e);
+    delete plan;
+    return NMF_OK;
+}
+
+nmf_status nmf_query_levels(nmf_plan_t plan, int32_t *hw, int32_t cap_levels) {
+    if (!plan || !hw) return fail(plan, NMF_E_ARG, "null argument");
+    const auto &lv = plan->p.lv;
+    for (size_t l = 0; l < lv.size() && (int32_t)l < cap_levels; ++l) {
+        hw[2 * l] = lv[l].h;
+        hw[2 * l + 1] = lv[l].w;
+    }
+    return NMF_OK;
+}
+
+nmf_status nmf_query_schedule(nmf_plan_t plan, int32_t iters, int32_t *steps, int32_t cap,
+                              int32_t *nsteps) {
+    if (!plan || !nsteps || iters < 0) return fail(plan, NMF_E_ARG, "bad argument");
+    auto s = make_schedule(plan->p.d.cycle, plan->p.d.levels, iters);
+    *nsteps = (int32_t)s.size();
+    for (size_t i = 0; i < s.size() && (int32_t)i < cap && steps; ++i) {
+        steps[3 * i] = s[i].kind;
+        steps[3 * i + 1] = s[i].depth;
+        steps[3 * i + 2] = s[i].count;
+    }
+    return NMF_OK;
+}
+
+nmf_status nmf_solve(nmf_plan_t plan, const float *dM, float *dV, float *dW, int32_t iters,
+                     void *dWorkspace, void *stream, nmf_result *hOut) {
+    if (!plan || !dM || !dV || !dW || !dWorkspace)
+        return fail(plan, NMF_E_ARG, "null plan or buffer");
+    if (iters < 0) return fail(plan, NMF_E_ARG, "iters must be >= 0");
+    if (reinterpret_cast<uintptr_t>(dWorkspace) & 255)
+        return fail(plan, NMF_E_ARG, "workspace must be 256-byte aligned");
+    const Plan &p = plan->p;
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    Ctx c = make_ctx(plan, dM, dV, dW, dWorkspace, s);
+    NMF_HIP(launch_state_reset(c.st, s));
+    nmf_status st;
+    if (p.d.check_input && (st = check_input(c)) != NMF_OK) return st;
+    if ((st = prepare_levels(c)) != NMF_OK) return st;
+    if ((st = gram_W(c)) != NMF_OK) return st;
+
+    const bool use_tol = p.d.tol > 0.0;
+    const int ce = p.d.check_every;
+    bool done = false;
+    int since_check = 0;
+    auto poll = [&](bool &stop_now) -> nmf_status {
+        DevState hs;
+        nmf_status e = read_state(c, hs);
+        stop_now = e == NMF_OK && hs.stop != 0;
+        return e;
+    };
+    for (const Step &stp : make_schedule(p.d.cycle, p.d.levels, iters)) {
+        if (done) break;
+        const int d = stp.depth;
+        if (stp.kind == 1) {
+            NMF_LAUNCH(K_RESTRICT, launch_restrict(p.d.xfer, p.lv[d].h, p.lv[d].w, p.d.r, c.V[d],
+                                                   p.lv[d].m, c.V[d + 1], c.stop, s));
+        } else if (stp.kind == 2) {
+            NMF_LAUNCH(K_PROLONG, launch_prolong(p.d.xfer, p.lv[d].h, p.lv[d].w, p.d.r, c.V[d + 1],
+                                                 c.V[d], c.stop, s));
+        } else {
+            for (int i = 0; i < stp.count && !done; ++i) {
+                if ((st = sweep(c, d)) != NMF_OK) return st;
+                if (use_tol && d == 0 && ++since_check >= ce) {
+                    since_check = 0;
+                    if ((st = poll(done)) != NMF_OK) return st;
+                }
+            }
+        }
+    }
+    if (use_tol && !done) {
+        if ((st = poll(done)) != NMF_OK) return st;
+        for (int i = 0; i < p.d.max_fine_iters && !done; ++i) {
+            if ((st = sweep(c, 0)) != NMF_OK) return st;
+            if (++since_check >= ce) {
+                since_check = 0;
+                if ((st = poll(done)) != NMF_OK) return st;
+            }
+        }
+    }
+    return finish(c, hOut);
+}
+
+nmf_status nmf_query_log(nmf_plan_t plan, const void *dWorkspace, void *stream, double *rel_err,
+                         int32_t *depth, int32_t cap) {
+    if (!plan || !dWorkspace) return fail(plan, NMF_E_ARG, "null argument");
+    const Plan &p = plan->p;
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    const char *ws = static_cast<const char *>(dWorkspace);
+    DevState hs;
+    NMF_HIP(hipMemcpyAsync(&hs, ws + p.ws.off_state, sizeof hs, hipMemcpyDeviceToHost, s));
+    NMF_HIP(hipStreamSynchronize(s));
+    int32_t n = hs.log_len < p.d.log_cap ? hs.log_len : p.d.log_cap;
+    if (n > cap) n = cap;
+    if (n > 0 && rel_err)
+        NMF_HIP(hipMemcpyAsync(rel_err, ws + p.ws.off_log, sizeof(double) * n,
+                               hipMemcpyDeviceToHost, s));
+    if (n > 0 && depth)
+        NMF_HIP(hipMemcpyAsync(depth, ws + p.ws.off_logdepth, sizeof(int32_t) * n,
+                               hipMemcpyDeviceToHost, s));
+    NMF_HIP(hipStreamSynchronize(s));
+    return NMF_OK;
+}
+
+nmf_status nmf_iterate(nmf_plan_t plan, const float *dM, float *dV, float *dW, int32_t count,
+                       void *dWorkspace, void *stream, double *hRelErr) {
+    if (!plan || !dM || !dV || !dW || !dWorkspace || count < 0)
+        return fail(plan, NMF_E_ARG, "bad argument");
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    Ctx c = make_ctx(plan, dM, dV, dW, dWorkspace, s);
+    NMF_HIP(launch_state_reset(c.st, s));
+    nmf_status st;
+    if ((st = prepare_levels(c)) != NMF_OK) return st;
+    if ((st = gram_W(c)) != NMF_OK) return st;
+    for (int i = 0; i < count; ++i)
+        if ((st = sweep(c, 0)) != NMF_OK) return st;
+    nmf_result res;
+    st = finish(c, &res);
+    if (hRelErr) *hRelErr = res.rel_err;
+    return st;
+}
+
+nmf_status nmf_profile(nmf_plan_t plan, uint32_t mask) {
+    if (!plan) return fail(plan, NMF_E_ARG, "null plan");
+    plan->p.prof.mask = mask;
+    return NMF_OK;
+}
+
+nmf_status nmf_profile_read(nmf_plan_t plan, int64_t *counts, double *total_ms, int32_t cap,
+                            int32_t reset) {
+    if (!plan) return fail(plan, NMF_E_ARG, "null plan");
+    Profiler &pf = plan->p.prof;
+    for (int k = 0; k < K_NUM_KINDS && k < cap; ++k) {
+        if (counts) counts[k] = pf.counts[k];
+        if (total_ms) total_ms[k] = pf.ms[k];
+    }
+    if (reset) {
+        for (int k = 0; k < K_NUM_KINDS; ++k) {
+            pf.counts[k] = 0;
+            pf.ms[k] = 0.0;
+        }
+    }
+    return NMF_OK;
+}
+
+nmf_status nmf_products(nmf_plan_t plan, const float *dM, const float *dV, const float *dW,
+                        float *dA, float *dC, void *dWorkspace, void *stream) {
+    if (!plan || !dM || !dV || !dW || !dA || !dC || !dWorkspace)
+        return fail(plan, NMF_E_ARG, "bad argument");
+    const Plan &p = plan->p;
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    Ctx c = make_ctx(plan, dM, const_cast<float *>(dV), const_cast<float *>(dW), dWorkspace, s);
+    const LevelInfo &li = p.lv[0];
+    NMF_HIP(launch_state_reset(c.st, s));
+    NMF_HIP(launch_apass(p.rpad, 2, dM, p.d.ldm, li.m, p.d.n, dW, nullptr, nullptr, dA, p.d.r,
+                         c.stop, s));
+    NMF_HIP(launch_cpass_partial(p.rpad, dM, p.d.ldm, li.m, p.d.n, dV, p.d.r, li.cp_chunks,
+                                 li.cp_chunk, c.Cp, c.stop, s));
+    NMF_LAUNCH(K_CFINAL, launch_cpass_final(p.rpad, 2, c.Cp, li.cp_chunks, p.d.n, p.d.r, nullptr, nullptr, dC,
+                               nullptr, c.stop, s));
+    return NMF_OK;
+}
+
+nmf_status nmf_restrict(int32_t xfer, int32_t h, int32_t w, int64_t ncols, const float *dX,
+                        int64_t ldx, float *dY, void *stream) {
+    nmf_plan_t plan = nullptr;
+    if (!dX || !dY || h < 2 || w < 2 || ncols < 0 || ldx < (int64_t)h * w ||
+        (xfer != NMF_XFER_FW && xfer != NMF_XFER_BLOCK2))
+        return fail(nullptr, NMF_E_ARG, "bad argument");
+    NMF_HIP(launch_restrict(xfer, h, w, ncols, dX, ldx, dY, nullptr,
+                            static_cast<hipStream_t>(stream)));
+    return NMF_OK;
+}
+
+nmf_status nmf_prolong(int32_t xfer, int32_t h, int32_t w, int64_t ncols, const float *dY,
+                       float *dX, void *stream) {
+    nmf_plan_t plan = nullptr;
+    if (!dX || !dY || h < 2 || w < 2 || ncols < 0 ||
+        (xfer != NMF_XFER_FW && xfer != NMF_XFER_BLOCK2))
+        return fail(nullptr, NMF_E_ARG, "bad argument");
+    NMF_HIP(launch_prolong(xfer, h, w, ncols, dY, dX, nullptr, static_cast<hipStream_t>(stream)));
+    return NMF_OK;
+}
+
+nmf_status nmf_gram(int32_t r, int64_t L, const float *dX, int64_t ldx, double *dG,
+                    void *dWorkspace, size_t ws_bytes, void *stream) {
+    nmf_plan_t plan = nullptr;
+    if (!dX || !dG || !dWorkspace || r < 1 || r > kMaxRank || L < 1 || ldx < L)
+        return fail(nullptr, NMF_E_ARG, "bad argument");
+    const int rpad = (r + 15) / 16 * 16;
+    int64_t parts = (L + 63) / 64;
+    if (parts > 256) parts = 256;
+    int64_t chunk = ((L + parts - 1) / parts + 63) / 64 * 64;
+    parts = (L + chunk - 1) / chunk;
+    if ((size_t)parts * rpad * rpad * sizeof(double) > ws_bytes)
+        return fail(nullptr, NMF_E_NOMEM, "gram workspace too small");
+    NMF_HIP(launch_gram(rpad, r, L, dX, ldx, (int)parts, chunk, static_cast<double *>(dWorkspace),
+                        dG, nullptr, nullptr, static_cast<hipStream_t>(stream)));
+    return NMF_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,135 @@
+// Internal declarations of libnmf: plan, workspace layout, device state and
+// the kernel launchers.  Host C++ only; the kernels live in *.hip files.
+#pragma once
+
+#include <cstddef>
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include <hip/hip_runtime.h>
+
+#include "../../include/nmf.h"
+
+namespace nmf {
+
+constexpr int kMaxRank = 64;
+constexpr int kMaxLevels = 12;
+
+// Device-side control block at the start of every workspace.
+struct DevState {
+    int32_t stop;        // 1: a stop condition was met; every later kernel returns at once
+    int32_t log_len;     // iterations logged so far (index of the next entry)
+    int32_t status;      // 0 or an nmf_status error code raised on the device
+    int32_t stopped;     // 1: the tolerance was reached
+    double last_rel;     // rel_err of the last executed iteration
+    int32_t flags;       // input check: bit0 negative entry, bit1 non-finite entry
+    int32_t pad[9];
+};
+static_assert(sizeof(DevState) <= 256, "state block");
+
+struct LevelInfo {
+    int32_t h, w;
+    int64_t m;
+    size_t off_M;        // workspace offset of M_l (levels >= 1)
+    size_t off_V;        // workspace offset of V_l (levels >= 1)
+    size_t off_Mbf;      // workspace offset of the bf16 copy of M_l (prec BF16)
+    int32_t cp_chunks;   // split of the m-reduction in V^T M
+    int64_t cp_chunk;    // rows per chunk (multiple of 16)
+    int32_t gram_parts;  // split of the length-m reduction of V^T V
+    int64_t gram_chunk;
+};
+
+struct Step {            // one schedule entry
+    int32_t kind;        // 0 run, 1 restrict V (depth -> depth+1), 2 prolong V (depth+1 -> depth)
+    int32_t depth;
+    int32_t count;
+};
+
+struct Workspace {
+    size_t off_state, off_log, off_logdepth, off_norm;
+    size_t off_Bd, off_Bf, off_Dd, off_Df;
+    size_t off_gparts, off_cparts, off_rparts, off_A, off_C, off_V0bf;
+    size_t gparts_cap;   // doubles
+    size_t rparts_cap;   // doubles
+    size_t total;
+};
+
+enum KernelKind {
+    K_APASS = 0, K_GRAM_V, K_CPART, K_CFINAL, K_GRAM_W, K_RESID, K_NNLS_ROWS, K_NNLS_COLS,
+    K_RESTRICT, K_PROLONG, K_SUMSQ, K_NUM_KINDS
+};
+
+// Optional HIP-event timing of selected kernel kinds.
+struct Profiler {
+    uint32_t mask = 0;
+    std::vector<hipEvent_t> pool;            // created lazily, reused
+    std::vector<int> pending_kind;           // kind of event pair i (pool[2i], pool[2i+1])
+    int64_t counts[K_NUM_KINDS] = {};
+    double ms[K_NUM_KINDS] = {};
+};
+
+struct Plan {
+    nmf_desc d;
+    Profiler prof;
+    std::vector<LevelInfo> lv;
+    Workspace ws;
+    int rpad;            // r rounded up to a multiple of 16
+    int num_cu;
+    int32_t gram_w_parts;
+    int64_t gram_w_chunk;
+    std::string err;
+};
+
+std::vector<Step> make_schedule(int cycle, int levels, int64_t iters);
+nmf_status build_plan(const nmf_desc &d, Plan &p, std::string &err);
+
+// ---- launchers (kernels.hip etc.) ------------------------------------------
+// All take a stop pointer (may be null): kernels return at once when *stop != 0.
+hipError_t launch_restrict(int xfer, int h, int w, int64_t ncols, const float *X, int64_t ldx,
+                           float *Y, const int32_t *stop, hipStream_t s);
+hipError_t launch_prolong(int xfer, int h, int w, int64_t ncols, const float *Y, float *X,
+                          const int32_t *stop, hipStream_t s);
+hipError_t launch_sumsq(const float *X, int64_t ld, int64_t rows, int64_t ncols, double *parts,
+                        int nparts, double *out, hipStream_t s);
+hipError_t launch_check_input(const float *M, int64_t ld, int64_t m, int64_t n, int32_t *flags,
+                              hipStream_t s);
+hipError_t launch_state_reset(DevState *st, hipStream_t s);
+
+hipError_t launch_gram(int rpad, int r, int64_t L, const float *X, int64_t ldx, int parts,
+                       int64_t chunk, double *gparts, double *Gd, float *Gf, const int32_t *stop,
+                       hipStream_t s);
+
+// A = M W^T with epilogue: mode 0 HALS V update, 1 MU V update, 2 store A (m x r).
+hipError_t launch_apass(int rpad, int mode, const float *M, int64_t ldm, int64_t m, int64_t n,
+                        const float *W, const double *Bd, float *V, float *Aout, int r,
+                        const int32_t *stop, hipStream_t s);
+// Split-m partials of C = V^T M into Cp[chunks][r][n] (FP64).
+hipError_t launch_cpass_partial(int rpad, const float *M, int64_t ldm, int64_t m, int64_t n,
+                                const float *V, int r, int chunks, int64_t chunk, double *Cp,
+                                const int32_t *stop, hipStream_t s);
+// Reduce the partials and update W: mode 0 HALS, 1 MU, 2 store C (r x n).
+// rparts[b] receives the FP64 partial <C, W_new> of column block b.
+hipError_t launch_cpass_final(int rpad, int mode, const double *Cp, int chunks, int64_t n, int r,
+                              const double *Dd, float *W, float *Cout, double *rparts,
+                              const int32_t *stop, hipStream_t s);
+int cpass_final_blocks(int64_t n);
+
+// ANLS: exact FP64 NNLS per row of V (G = W W^T, rhs = A rows) or per column
+// of W (G = V^T V, rhs = C columns); warm-started from the current factor.
+// A non-positive pivot sets bit 2 of *flags (the affected problem keeps its
+// last feasible iterate).
+hipError_t launch_nnls_rows(int rpad, const double *Gd, const float *A, int64_t m, int r,
+                            float *V, int32_t *flags, const int32_t *stop, hipStream_t s);
+hipError_t launch_nnls_cols(int rpad, const double *Gd, const float *C, int64_t n, int r,
+                            float *W, double *rparts, int32_t *flags, const int32_t *stop,
+                            hipStream_t s);
+int nnls_cols_blocks(int64_t n);
+
+// rel_err = sqrt(max(0, ||M||^2 - 2 sum(rparts) + <Dd, Bd>) / ||M||^2), logged.
+hipError_t launch_residual(const double *rparts, int nparts, const double *Dd, const double *Bd,
+                           int r, const double *normM2, int depth, double *log_rel,
+                           int32_t *log_depth, int log_idx, int log_cap, DevState *st, double tol,
+                           hipStream_t s);
+
+}  // namespace nmf

@@ -1,0 +1,204 @@
+// Host-side planner: level hierarchy, cycle schedule and workspace layout.
+#include <algorithm>
+#include <cstdio>
+#include <functional>
+
+#include "nmf_internal.h"
+
+namespace nmf {
+
+namespace {
+
+// Exact nonnegative rational (budgets of Alg. 4-6 are T * 3^a / 4^b).
+struct Rat {
+    int64_t num, den;
+};
+
+int64_t gcd64(int64_t a, int64_t b) {
+    while (b) {
+        int64_t t = a % b;
+        a = b;
+        b = t;
+    }
+    return a < 0 ? -a : a;
+}
+
+Rat mk(int64_t num, int64_t den) {
+    const int64_t g = gcd64(num, den);
+    return g ? Rat{num / g, den / g} : Rat{0, 1};
+}
+Rat mul(Rat a, int64_t p, int64_t q) { return mk(a.num * p, a.den * q); }
+
+size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
+
+}  // namespace
+
+// Schedule of Alg. 4 (NI), Alg. 5 (VC), Alg. 6 (FMG) with the Table 1 time
+// split, the budget counted in finest-iteration equivalents: Run(d, t)
+// performs floor(t * 4^d) iterations at depth d (depth 0 = finest) and
+// zero-iteration runs are dropped.
+std::vector<Step> make_schedule(int cycle, int levels, int64_t iters) {
+    std::vector<Step> out;
+    auto run = [&](int d, Rat t) {
+        int64_t scale = 1;
+        for (int i = 0; i < d; ++i) scale *= 4;
+        const int64_t c = (t.num * scale) / t.den;
+        if (c > 0) out.push_back(Step{0, d, (int32_t)c});
+    };
+    std::function<void(int, Rat, int)> ni, vc, fmg;
+    ni = [&](int L, Rat t, int d) {
+        if (L == 1) return run(d, t);
+        out.push_back(Step{1, d, 0});
+        ni(L - 1, mul(t, 1, 4), d + 1);
+        out.push_back(Step{2, d, 0});
+        run(d, mul(t, 3, 4));
+    };
+    vc = [&](int L, Rat t, int d) {
+        if (L == 1) return run(d, t);
+        run(d, mul(t, 1, 4));
+        out.push_back(Step{1, d, 0});
+        vc(L - 1, mul(t, 1, 4), d + 1);
+        out.push_back(Step{2, d, 0});
+        run(d, mul(t, 1, 2));
+    };
+    fmg = [&](int L, Rat t, int d) {
+        if (L == 1) return run(d, t);
+        out.push_back(Step{1, d, 0});
+        fmg(L - 1, mul(t, 1, 4), d + 1);
+        out.push_back(Step{2, d, 0});
+        vc(L, mul(t, 3, 4), d);
+    };
+    const Rat T{iters, 1};
+    if (cycle == NMF_VC) vc(levels, T, 0);
+    else if (cycle == NMF_FMG) fmg(levels, T, 0);
+    else ni(levels, T, 0);
+    return out;
+}
+
+nmf_status build_plan(const nmf_desc &d0, Plan &p, std::string &err) {
+    nmf_desc d = d0;
+    char buf[256];
+    if (d.algo < NMF_HALS || d.algo > NMF_ANLS || d.cycle < NMF_NI || d.cycle > NMF_FMG ||
+        d.xfer < NMF_XFER_FW || d.xfer > NMF_XFER_BLOCK2 || d.prec < NMF_FP32 || d.prec > NMF_BF16) {
+        err = "unknown algo / cycle / xfer / prec value";
+        return NMF_E_ARG;
+    }
+    if (d.ldm == 0) d.ldm = d.m;
+    if (d.check_every <= 0) d.check_every = 8;
+    if (d.log_cap <= 0) d.log_cap = 4096;
+    if (d.max_fine_iters < 0 || d.refine_iters < 0 || !(d.tol >= 0.0)) {
+        err = "negative max_fine_iters / refine_iters / tol";
+        return NMF_E_ARG;
+    }
+    if (d.h < 1 || d.w < 1 || d.m != (int64_t)d.h * d.w) {
+        snprintf(buf, sizeof buf, "m (%lld) must equal h*w (%d*%d)", (long long)d.m, d.h, d.w);
+        err = buf;
+        return NMF_E_SHAPE;
+    }
+    if (d.n < 1 || d.ldm < d.m) {
+        err = "n must be >= 1 and ldm >= m";
+        return NMF_E_SHAPE;
+    }
+    if (d.r < 1 || d.r > kMaxRank) {
+        err = "r must be in [1, 64]";
+        return NMF_E_SHAPE;
+    }
+    if (d.levels < 1 || d.levels > kMaxLevels) {
+        err = "levels must be in [1, 12]";
+        return NMF_E_SHAPE;
+    }
+    p.d = d;
+    p.rpad = (d.r + 15) / 16 * 16;
+    p.lv.clear();
+    int h = d.h, w = d.w;
+    for (int l = 0; l < d.levels; ++l) {
+        if (l > 0) {
+            if (h < 2 || w < 2) {
+                snprintf(buf, sizeof buf, "level %d: cannot restrict a %dx%d grid", l, h, w);
+                err = buf;
+                return NMF_E_SHAPE;
+            }
+            h = (h + 1) / 2;
+            w = (w + 1) / 2;
+        }
+        LevelInfo li{};
+        li.h = h;
+        li.w = w;
+        li.m = (int64_t)h * w;
+        if (d.algo == NMF_ANLS && li.m < d.r) {
+            snprintf(buf, sizeof buf,
+                     "ANLS: level %d has %lld pixels < r = %d (singular V^T V)", l,
+                     (long long)li.m, d.r);
+            err = buf;
+            return NMF_E_SHAPE;
+        }
+        p.lv.push_back(li);
+    }
+    if (p.num_cu <= 0) p.num_cu = 256;
+
+    // Split of the length-m reductions.  Target about one block per CU for
+    // V^T M (deterministic split-m partials) and at most 256 Gram partials.
+    const int64_t ntiles = (d.n + 63) / 64;
+    size_t max_cp = 0, max_gp = 0;
+    for (auto &li : p.lv) {
+        int64_t chunks = std::max<int64_t>(1, p.num_cu / std::max<int64_t>(1, ntiles));
+        chunks = std::min<int64_t>(chunks, std::max<int64_t>(1, (li.m + 63) / 64));
+        int64_t chunk = (li.m + chunks - 1) / chunks;
+        chunk = (chunk + 15) / 16 * 16;
+        li.cp_chunk = chunk;
+        li.cp_chunks = (int32_t)((li.m + chunk - 1) / chunk);
+        max_cp = std::max<size_t>(max_cp, (size_t)li.cp_chunks);
+        int64_t gp = std::min<int64_t>(256, (li.m + 63) / 64);
+        int64_t gc = (li.m + gp - 1) / gp;
+        gc = (gc + 63) / 64 * 64;
+        li.gram_chunk = gc;
+        li.gram_parts = (int32_t)((li.m + gc - 1) / gc);
+        max_gp = std::max<size_t>(max_gp, (size_t)li.gram_parts);
+    }
+    {
+        int64_t gp = std::min<int64_t>(256, (d.n + 63) / 64);
+        int64_t gc = (d.n + gp - 1) / gp;
+        gc = (gc + 63) / 64 * 64;
+        p.gram_w_chunk = gc;
+        p.gram_w_parts = (int32_t)((d.n + gc - 1) / gc);
+        max_gp = std::max<size_t>(max_gp, (size_t)p.gram_w_parts);
+    }
+
+    Workspace &ws = p.ws;
+    size_t off = 0;
+    auto take = [&](size_t bytes) {
+        const size_t o = off;
+        off = align256(off + bytes);
+        return o;
+    };
+    const size_t r = d.r, n = d.n, rr = r * r, rp2 = (size_t)p.rpad * p.rpad;
+    ws.off_state = take(256);
+    ws.off_log = take(sizeof(double) * d.log_cap);
+    ws.off_logdepth = take(sizeof(int32_t) * d.log_cap);
+    ws.off_norm = take(sizeof(double) * d.levels);
+    ws.off_Bd = take(sizeof(double) * rr);
+    ws.off_Dd = take(sizeof(double) * rr);
+    ws.off_Bf = take(sizeof(float) * rr);
+    ws.off_Df = take(sizeof(float) * rr);
+    ws.gparts_cap = max_gp * rp2;
+    ws.off_gparts = take(sizeof(double) * ws.gparts_cap);
+    ws.off_cparts = take(sizeof(double) * max_cp * r * n);
+    ws.rparts_cap = std::max<size_t>({(size_t)cpass_final_blocks(d.n),
+                                      (size_t)nnls_cols_blocks(d.n), (size_t)1024});
+    ws.off_rparts = take(sizeof(double) * ws.rparts_cap);
+    if (d.algo == NMF_ANLS) {
+        ws.off_A = take(sizeof(float) * (size_t)d.m * r);
+        ws.off_C = take(sizeof(float) * r * n);
+    } else {
+        ws.off_A = ws.off_C = 0;
+    }
+    for (size_t l = 1; l < p.lv.size(); ++l) {
+        p.lv[l].off_M = take(sizeof(float) * (size_t)p.lv[l].m * n);
+        p.lv[l].off_V = take(sizeof(float) * (size_t)p.lv[l].m * r);
+    }
+    ws.off_V0bf = 0;
+    ws.total = off;
+    return NMF_OK;
+}
+
+}  // namespace nmf

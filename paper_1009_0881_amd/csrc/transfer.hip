@@ -1,0 +1,230 @@
+// Grid-transfer stencils (Section 4.2) and whole-matrix reductions.
+//
+// Restriction (eq. restr): coarse node c of a fine axis of length N sits on
+// fine node 2c.  Full weighting (FW) uses the 1-D weights 1,2,1 on fine nodes
+// 2c-1, 2c, 2c+1; nodes outside the image are dropped and the remaining
+// weights are renormalised to sum 1 (the boundary rule "weights adapted
+// correspondingly").  The 2-D stencil is the product of the two 1-D ones, so
+// interior pixels get (1,2,1)x(1,2,1)/16.  BLOCK2 averages fine nodes 2c, 2c+1.
+//
+// Prolongation (eq. prol): fine node f takes the mean of the coarse nodes
+// rd(f/2) that exist ({f/2} for even f, {(f-1)/2, (f+1)/2} for odd f) per
+// axis; BLOCK2 copies coarse node floor(f/2).
+//
+// One thread per output pixel and image; the taps are recomputed from the
+// closed form (no tables), accumulated in FP64 and rounded once to FP32.
+
+#include "device_common.h"
+#include "nmf_internal.h"
+
+namespace nmf {
+
+namespace {
+
+struct Taps {
+    int idx[3];
+    double wt[3];
+    int cnt;
+};
+
+__device__ __forceinline__ Taps restrict_taps(int c, int N, int xfer) {
+    Taps t;
+    t.cnt = 0;
+    if (xfer == NMF_XFER_FW) {
+        double sum = 0.0;
+#pragma unroll
+        for (int d = -1; d <= 1; ++d) {
+            const int f = 2 * c + d;
+            if (f >= 0 && f < N) {
+                const double wgt = (d == 0) ? 2.0 : 1.0;
+                t.idx[t.cnt] = f;
+                t.wt[t.cnt] = wgt;
+                sum += wgt;
+                ++t.cnt;
+            }
+        }
+        for (int i = 0; i < t.cnt; ++i) t.wt[i] /= sum;
+    } else {
+        const int f0 = 2 * c;
+        t.idx[0] = f0;
+        t.cnt = 1;
+        if (f0 + 1 < N) {
+            t.idx[1] = f0 + 1;
+            t.cnt = 2;
+        }
+        for (int i = 0; i < t.cnt; ++i) t.wt[i] = 1.0 / t.cnt;
+    }
+    return t;
+}
+
+__device__ __forceinline__ Taps prolong_taps(int f, int Nc, int xfer) {
+    Taps t;
+    if (xfer == NMF_XFER_FW && (f & 1)) {
+        t.idx[0] = (f - 1) / 2;
+        t.cnt = 1;
+        if ((f + 1) / 2 < Nc) {
+            t.idx[1] = (f + 1) / 2;
+            t.cnt = 2;
+        }
+    } else {
+        t.idx[0] = f / 2;
+        t.cnt = 1;
+    }
+    for (int i = 0; i < t.cnt; ++i) t.wt[i] = 1.0 / t.cnt;
+    return t;
+}
+
+__global__ __launch_bounds__(256) void k_restrict(const float *__restrict__ X, int64_t ldx,
+                                                  float *__restrict__ Y, int h, int w, int hc,
+                                                  int wc, int64_t ncols, int xfer,
+                                                  const int32_t *stop) {
+    if (stopped(stop)) return;
+    const int64_t mc = (int64_t)hc * wc;
+    const int64_t total = mc * ncols;
+    for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < total;
+         e += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t col = e / mc;
+        const int p = (int)(e - col * mc);
+        const int cy = p / wc, cx = p - (p / wc) * wc;
+        const Taps ty = restrict_taps(cy, h, xfer);
+        const Taps tx = restrict_taps(cx, w, xfer);
+        const float *img = X + col * ldx;
+        double acc = 0.0;
+        for (int a = 0; a < ty.cnt; ++a) {
+            double row = 0.0;
+            for (int b = 0; b < tx.cnt; ++b)
+                row += tx.wt[b] * (double)img[(int64_t)ty.idx[a] * w + tx.idx[b]];
+            acc += ty.wt[a] * row;
+        }
+        Y[col * mc + p] = (float)acc;
+    }
+}
+
+__global__ __launch_bounds__(256) void k_prolong(const float *__restrict__ Y,
+                                                 float *__restrict__ X, int h, int w, int hc,
+                                                 int wc, int64_t ncols, int xfer,
+                                                 const int32_t *stop) {
+    if (stopped(stop)) return;
+    const int64_t mf = (int64_t)h * w;
+    const int64_t mc = (int64_t)hc * wc;
+    const int64_t total = mf * ncols;
+    for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < total;
+         e += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t col = e / mf;
+        const int p = (int)(e - col * mf);
+        const int y = p / w, x = p - (p / w) * w;
+        const Taps ty = prolong_taps(y, hc, xfer);
+        const Taps tx = prolong_taps(x, wc, xfer);
+        const float *img = Y + col * mc;
+        double acc = 0.0;
+        for (int a = 0; a < ty.cnt; ++a) {
+            double row = 0.0;
+            for (int b = 0; b < tx.cnt; ++b)
+                row += tx.wt[b] * (double)img[(int64_t)ty.idx[a] * wc + tx.idx[b]];
+            acc += ty.wt[a] * row;
+        }
+        X[col * mf + p] = (float)acc;
+    }
+}
+
+// Sum of squares of a column-major matrix in FP64: per-block partials, then a
+// single block adds them in index order (deterministic).
+__global__ __launch_bounds__(256) void k_sumsq_partial(const float *__restrict__ X, int64_t ld,
+                                                       int64_t rows, int64_t ncols,
+                                                       double *__restrict__ parts) {
+    __shared__ double scratch[4];
+    const int64_t total = rows * ncols;
+    double acc = 0.0;
+    for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < total;
+         e += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t c = e / rows;
+        const double v = X[c * ld + (e - c * rows)];
+        acc += v * v;
+    }
+    acc = block_sum_f64<256>(acc, scratch);
+    if (threadIdx.x == 0) parts[blockIdx.x] = acc;
+}
+
+__global__ __launch_bounds__(256) void k_sum_parts(const double *__restrict__ parts, int nparts,
+                                                   double *__restrict__ out) {
+    __shared__ double scratch[4];
+    double acc = 0.0;
+    for (int i = threadIdx.x; i < nparts; i += 256) acc += parts[i];
+    acc = block_sum_f64<256>(acc, scratch);
+    if (threadIdx.x == 0) *out = acc;
+}
+
+__global__ __launch_bounds__(256) void k_check_input(const float *__restrict__ M, int64_t ld,
+                                                     int64_t m, int64_t n,
+                                                     int32_t *__restrict__ flags) {
+    const int64_t total = m * n;
+    int32_t f = 0;
+    for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < total;
+         e += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t c = e / m;
+        const float v = M[c * ld + (e - c * m)];
+        if (!(v >= 0.0f)) f |= (v < 0.0f) ? 1 : 2;   // NaN fails both comparisons
+        else if (v == INFINITY) f |= 2;
+    }
+    if (f) atomicOr(flags, f);
+}
+
+__global__ void k_state_reset(DevState *st) {
+    if (threadIdx.x == 0) {
+        st->stop = 0;
+        st->log_len = 0;
+        st->status = 0;
+        st->stopped = 0;
+        st->last_rel = 0.0;
+        st->flags = 0;
+    }
+}
+
+inline int grid_for(int64_t total, int cap = 8192) {
+    int64_t g = (total + 255) / 256;
+    if (g < 1) g = 1;
+    if (g > cap) g = cap;
+    return (int)g;
+}
+
+}  // namespace
+
+hipError_t launch_restrict(int xfer, int h, int w, int64_t ncols, const float *X, int64_t ldx,
+                           float *Y, const int32_t *stop, hipStream_t s) {
+    const int hc = (h + 1) / 2, wc = (w + 1) / 2;
+    const int64_t total = (int64_t)hc * wc * ncols;
+    if (total == 0) return hipSuccess;
+    k_restrict<<<grid_for(total, 65536), 256, 0, s>>>(X, ldx, Y, h, w, hc, wc, ncols, xfer, stop);
+    return hipGetLastError();
+}
+
+hipError_t launch_prolong(int xfer, int h, int w, int64_t ncols, const float *Y, float *X,
+                          const int32_t *stop, hipStream_t s) {
+    const int hc = (h + 1) / 2, wc = (w + 1) / 2;
+    const int64_t total = (int64_t)h * w * ncols;
+    if (total == 0) return hipSuccess;
+    k_prolong<<<grid_for(total, 65536), 256, 0, s>>>(Y, X, h, w, hc, wc, ncols, xfer, stop);
+    return hipGetLastError();
+}
+
+hipError_t launch_sumsq(const float *X, int64_t ld, int64_t rows, int64_t ncols, double *parts,
+                        int nparts, double *out, hipStream_t s) {
+    k_sumsq_partial<<<nparts, 256, 0, s>>>(X, ld, rows, ncols, parts);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    k_sum_parts<<<1, 256, 0, s>>>(parts, nparts, out);
+    return hipGetLastError();
+}
+
+hipError_t launch_check_input(const float *M, int64_t ld, int64_t m, int64_t n, int32_t *flags,
+                              hipStream_t s) {
+    k_check_input<<<grid_for(m * n, 4096), 256, 0, s>>>(M, ld, m, n, flags);
+    return hipGetLastError();
+}
+
+hipError_t launch_state_reset(DevState *st, hipStream_t s) {
+    k_state_reset<<<1, 64, 0, s>>>(st);
+    return hipGetLastError();
+}
+
+}  // namespace nmf

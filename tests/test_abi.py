@@ -1,0 +1,85 @@
+"""CPU checks of the C ABI: the library loads, exports every declared symbol,
+validates plans, and its host-side level / schedule planner is bit-exact with
+the oracle.  No device work."""
+import ctypes
+import os
+import re
+import subprocess
+
+import pytest
+
+import oracle as O
+import paper_1009_0881_amd as P
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "nmf.h")
+
+
+def declared_symbols():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"^\s*(?:nmf_status|const char \*)\s*(nmf_\w+)\s*\(", text, re.M)))
+
+
+def test_header_declares_what_the_binding_lists():
+    assert declared_symbols() == sorted(P.EXPORTS)
+
+
+def test_library_exports_every_declared_symbol():
+    L = P.lib()
+    for name in declared_symbols():
+        assert hasattr(L, name), name
+    out = subprocess.run(["nm", "-D", "--defined-only", P.LIB_PATH], capture_output=True,
+                         text=True, check=True).stdout
+    exported = set(re.findall(r"\bT (nmf_\w+)$", out, re.M))
+    assert set(declared_symbols()) <= exported
+
+
+def test_status_strings():
+    L = P.lib()
+    for code in range(-7, 1):
+        assert L.nmf_status_string(code)
+
+
+@pytest.mark.parametrize("kw,status", [
+    (dict(m=100, n=4, h=10, w=11, r=3), -2),             # m != h*w
+    (dict(m=100, n=4, h=10, w=10, r=0), -2),             # r < 1
+    (dict(m=100, n=4, h=10, w=10, r=65), -2),            # r > 64
+    (dict(m=4, n=4, h=2, w=2, r=1, levels=3), -2),       # side 1 cannot be restricted
+    (dict(m=256, n=40, h=16, w=16, r=20, levels=3, algo="anls"), -2),   # 4x4 level < r
+    (dict(m=100, n=4, h=10, w=10, r=3, algo=7), -1),     # unknown algorithm
+    (dict(m=100, n=0, h=10, w=10, r=3), -2),             # n < 1
+])
+def test_plan_rejects_bad_descriptions(kw, status):
+    with pytest.raises(P.NmfError) as e:
+        P.Plan(**kw)
+    assert e.value.status == status
+
+
+def test_hals_allows_coarse_levels_smaller_than_r():
+    # 16 -> 8 -> 4 with r = 20: HALS/MU stay well defined
+    P.Plan(m=256, n=40, h=16, w=16, r=20, levels=3, algo="hals")
+
+
+@pytest.mark.parametrize("hw", [(16, 16), (112, 92), (256, 256), (17, 33), (48, 48), (5, 7)])
+@pytest.mark.parametrize("levels", [1, 2, 3])
+def test_level_sides_match_oracle(hw, levels):
+    h, w = hw
+    pl = P.Plan(m=h * w, n=10, h=h, w=w, r=3, levels=levels)
+    assert pl.level_sides() == O.level_sides(h, w, levels)
+
+
+@pytest.mark.parametrize("cycle", ["ni", "vc", "fmg"])
+@pytest.mark.parametrize("levels", [1, 2, 3, 4])
+@pytest.mark.parametrize("T", [0, 1, 5, 16, 40, 123, 200, 1000])
+def test_schedule_matches_oracle(cycle, levels, T):
+    pl = P.Plan(m=256 * 256, n=10, h=256, w=256, r=3, levels=levels, cycle=cycle)
+    assert pl.schedule(T) == O.schedule(P.CYCLES[cycle], levels, T)
+
+
+def test_workspace_grows_with_levels_and_algo():
+    a = P.Plan(m=10304, n=400, h=112, w=92, r=40, levels=1).workspace_bytes
+    b = P.Plan(m=10304, n=400, h=112, w=92, r=40, levels=3).workspace_bytes
+    c = P.Plan(m=10304, n=400, h=112, w=92, r=40, levels=3, algo="anls").workspace_bytes
+    assert 0 < a < b < c
+    assert b % 256 == 0
