@@ -40,8 +40,8 @@ struct Ctx {
     int32_t *log_depth;
     double *norm;
     double *Bd, *Dd, *gparts, *rparts;
-    float *Bf, *Df, *A, *C;
-    double *Cp;
+    float *Bf, *Df, *A, *C, *Wt;
+    double *Cp, *Dp, *Bp;
     std::vector<const float *> M;
     std::vector<int64_t> ldm;
     std::vector<float *> V;
@@ -115,6 +115,9 @@ Ctx make_ctx(nmf_plan_t plan, const float *dM, float *dV, float *dW, void *dws, 
     c.gparts = at<double>(c.ws, p.ws.off_gparts);
     c.rparts = at<double>(c.ws, p.ws.off_rparts);
     c.Cp = at<double>(c.ws, p.ws.off_cparts);
+    c.Dp = at<double>(c.ws, p.ws.off_Dp);
+    c.Bp = at<double>(c.ws, p.ws.off_Bp);
+    c.Wt = at<float>(c.ws, p.ws.off_Wt);
     c.A = p.ws.off_A ? at<float>(c.ws, p.ws.off_A) : nullptr;
     c.C = p.ws.off_C ? at<float>(c.ws, p.ws.off_C) : nullptr;
     for (size_t l = 0; l < p.lv.size(); ++l) {
@@ -132,6 +135,7 @@ Ctx make_ctx(nmf_plan_t plan, const float *dM, float *dV, float *dW, void *dws, 
     return c;
 }
 
+// B = W W^T with the standalone Gram kernels (start of a solve, ANLS).
 nmf_status gram_W(Ctx &c) {
     nmf_plan_t plan = c.plan;
     const Plan &p = *c.p;
@@ -151,33 +155,39 @@ nmf_status sweep(Ctx &c, int d) {
     const int64_t ld = c.ldm[d];
     float *V = c.V[d];
     int32_t *flags = &c.st->flags;
-    int nparts;
+    const int nfb = cpass_final_blocks(n);
     if (p.d.algo == NMF_ANLS) {
-        NMF_LAUNCH(K_APASS, launch_apass(p.rpad, 2, M, ld, m, n, c.W, c.Bd, V, c.A, r, c.stop, c.s));
+        NMF_LAUNCH(K_APASS, launch_apass(p.rpad, 2, M, ld, m, n, c.Wt, c.Bd, V, c.A, r, c.stop, c.s));
         NMF_LAUNCH(K_NNLS_ROWS, launch_nnls_rows(p.rpad, c.Bd, c.A, m, r, V, flags, c.stop, c.s));
-        NMF_LAUNCH(K_GRAM_V, launch_gram(p.rpad, r, m, V, m, li.gram_parts, li.gram_chunk, c.gparts, c.Dd,
-                            c.Df, c.stop, c.s));
-        NMF_LAUNCH(K_CPART, launch_cpass_partial(p.rpad, M, ld, m, n, V, r, li.cp_chunks, li.cp_chunk, c.Cp,
-                                     c.stop, c.s));
-        NMF_LAUNCH(K_CFINAL, launch_cpass_final(p.rpad, 2, c.Cp, li.cp_chunks, n, r, c.Dd, c.W, c.C, c.rparts,
-                                   c.stop, c.s));
-        NMF_LAUNCH(K_NNLS_COLS, launch_nnls_cols(p.rpad, c.Dd, c.C, n, r, c.W, c.rparts, flags, c.stop, c.s));
-        nparts = nnls_cols_blocks(n);
+        NMF_LAUNCH(K_CPART, launch_cpass_partial(p.rpad, M, ld, m, n, V, r, li.cp_chunks,
+                                                 li.cp_chunk, c.Cp, c.Dp, c.stop, c.s));
+        NMF_LAUNCH(K_GRAM_V, launch_reduce_gram(c.Dp, li.cp_chunks, p.rpad, r, c.Dd, false,
+                                                nullptr, 0, c.norm, d, c.log_rel, c.log_depth,
+                                                c.log_idx, p.d.log_cap, c.st, p.d.tol, c.s));
+        NMF_LAUNCH(K_CFINAL, launch_cpass_final(p.rpad, 2, c.Cp, li.cp_chunks, n, r, c.Dd, c.W,
+                                                c.Wt, c.C, c.Bp, c.rparts, c.stop, c.s));
+        NMF_LAUNCH(K_NNLS_COLS, launch_nnls_cols(p.rpad, c.Dd, c.C, n, r, c.W, c.Wt, c.rparts,
+                                                 flags, c.stop, c.s));
+        nmf_status st = gram_W(c);
+        if (st != NMF_OK) return st;
+        NMF_LAUNCH(K_RESID, launch_residual(c.rparts, nnls_cols_blocks(n), c.Dd, c.Bd, r, c.norm,
+                                            d, c.log_rel, c.log_depth, c.log_idx, p.d.log_cap,
+                                            c.st, p.d.tol, c.s));
     } else {
         const int mode = p.d.algo == NMF_HALS ? 0 : 1;
-        NMF_LAUNCH(K_APASS, launch_apass(p.rpad, mode, M, ld, m, n, c.W, c.Bd, V, nullptr, r, c.stop, c.s));
-        NMF_LAUNCH(K_GRAM_V, launch_gram(p.rpad, r, m, V, m, li.gram_parts, li.gram_chunk, c.gparts, c.Dd,
-                            c.Df, c.stop, c.s));
-        NMF_LAUNCH(K_CPART, launch_cpass_partial(p.rpad, M, ld, m, n, V, r, li.cp_chunks, li.cp_chunk, c.Cp,
-                                     c.stop, c.s));
-        NMF_LAUNCH(K_CFINAL, launch_cpass_final(p.rpad, mode, c.Cp, li.cp_chunks, n, r, c.Dd, c.W, nullptr,
-                                   c.rparts, c.stop, c.s));
-        nparts = cpass_final_blocks(n);
+        NMF_LAUNCH(K_APASS, launch_apass(p.rpad, mode, M, ld, m, n, c.Wt, c.Bd, V, nullptr, r,
+                                         c.stop, c.s));
+        NMF_LAUNCH(K_CPART, launch_cpass_partial(p.rpad, M, ld, m, n, V, r, li.cp_chunks,
+                                                 li.cp_chunk, c.Cp, c.Dp, c.stop, c.s));
+        NMF_LAUNCH(K_GRAM_V, launch_reduce_gram(c.Dp, li.cp_chunks, p.rpad, r, c.Dd, false,
+                                                nullptr, 0, c.norm, d, c.log_rel, c.log_depth,
+                                                c.log_idx, p.d.log_cap, c.st, p.d.tol, c.s));
+        NMF_LAUNCH(K_CFINAL, launch_cpass_final(p.rpad, mode, c.Cp, li.cp_chunks, n, r, c.Dd, c.W,
+                                                c.Wt, nullptr, c.Bp, c.rparts, c.stop, c.s));
+        NMF_LAUNCH(K_GRAM_W, launch_reduce_gram(c.Bp, nfb, p.rpad, r, c.Bd, true, c.rparts, nfb,
+                                                c.norm, d, c.log_rel, c.log_depth, c.log_idx,
+                                                p.d.log_cap, c.st, p.d.tol, c.s));
     }
-    nmf_status st = gram_W(c);
-    if (st != NMF_OK) return st;
-    NMF_LAUNCH(K_RESID, launch_residual(c.rparts, nparts, c.Dd, c.Bd, r, c.norm, d, c.log_rel,
-                                        c.log_depth, c.log_idx, p.d.log_cap, c.st, p.d.tol, c.s));
     c.log_idx++;
     c.depths.push_back((int8_t)d);
     return NMF_OK;
@@ -340,6 +350,7 @@ nmf_status nmf_solve(nmf_plan_t plan, const float *dM, float *dV, float *dW, int
     if (p.d.check_input && (st = check_input(c)) != NMF_OK) return st;
     if ((st = prepare_levels(c)) != NMF_OK) return st;
     if ((st = gram_W(c)) != NMF_OK) return st;
+    NMF_HIP(launch_make_wt(c.W, p.d.n, p.d.r, p.rpad, c.Wt, s));
 
     const bool use_tol = p.d.tol > 0.0;
     const int ce = p.d.check_every;
@@ -414,6 +425,7 @@ nmf_status nmf_iterate(nmf_plan_t plan, const float *dM, float *dV, float *dW, i
     nmf_status st;
     if ((st = prepare_levels(c)) != NMF_OK) return st;
     if ((st = gram_W(c)) != NMF_OK) return st;
+    NMF_HIP(launch_make_wt(c.W, plan->p.d.n, plan->p.d.r, plan->p.rpad, c.Wt, s));
     for (int i = 0; i < count; ++i)
         if ((st = sweep(c, 0)) != NMF_OK) return st;
     nmf_result res;
@@ -454,12 +466,13 @@ nmf_status nmf_products(nmf_plan_t plan, const float *dM, const float *dV, const
     Ctx c = make_ctx(plan, dM, const_cast<float *>(dV), const_cast<float *>(dW), dWorkspace, s);
     const LevelInfo &li = p.lv[0];
     NMF_HIP(launch_state_reset(c.st, s));
-    NMF_HIP(launch_apass(p.rpad, 2, dM, p.d.ldm, li.m, p.d.n, dW, nullptr, nullptr, dA, p.d.r,
+    NMF_HIP(launch_make_wt(dW, p.d.n, p.d.r, p.rpad, c.Wt, s));
+    NMF_HIP(launch_apass(p.rpad, 2, dM, p.d.ldm, li.m, p.d.n, c.Wt, nullptr, nullptr, dA, p.d.r,
                          c.stop, s));
     NMF_HIP(launch_cpass_partial(p.rpad, dM, p.d.ldm, li.m, p.d.n, dV, p.d.r, li.cp_chunks,
-                                 li.cp_chunk, c.Cp, c.stop, s));
-    NMF_LAUNCH(K_CFINAL, launch_cpass_final(p.rpad, 2, c.Cp, li.cp_chunks, p.d.n, p.d.r, nullptr, nullptr, dC,
-                               nullptr, c.stop, s));
+                                 li.cp_chunk, c.Cp, c.Dp, c.stop, s));
+    NMF_HIP(launch_cpass_final(p.rpad, 2, c.Cp, li.cp_chunks, p.d.n, p.d.r, nullptr, nullptr,
+                               c.Wt, dC, c.Bp, c.rparts, c.stop, s));
     return NMF_OK;
 }
 

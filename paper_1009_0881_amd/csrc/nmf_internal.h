@@ -50,6 +50,7 @@ struct Workspace {
     size_t off_state, off_log, off_logdepth, off_norm;
     size_t off_Bd, off_Bf, off_Dd, off_Df;
     size_t off_gparts, off_cparts, off_rparts, off_A, off_C, off_V0bf;
+    size_t off_Wt, off_Dp, off_Bp;
     size_t gparts_cap;   // doubles
     size_t rparts_cap;   // doubles
     size_t total;
@@ -101,19 +102,30 @@ hipError_t launch_gram(int rpad, int r, int64_t L, const float *X, int64_t ldx, 
                        hipStream_t s);
 
 // A = M W^T with epilogue: mode 0 HALS V update, 1 MU V update, 2 store A (m x r).
+// Reads W through its transposed zero-padded copy Wt (n x rpad).
 hipError_t launch_apass(int rpad, int mode, const float *M, int64_t ldm, int64_t m, int64_t n,
-                        const float *W, const double *Bd, float *V, float *Aout, int r,
+                        const float *Wt, const double *Bd, float *V, float *Aout, int r,
                         const int32_t *stop, hipStream_t s);
-// Split-m partials of C = V^T M into Cp[chunks][r][n] (FP64).
+int apass_rows_per_block(int64_t m);
+// Split-m partials of C = V^T M into Cp[chunks][r][n] (FP64) and of V^T V
+// into Dp[chunks][rpad][rpad] (upper-triangle 16x16 tiles, FP64).
 hipError_t launch_cpass_partial(int rpad, const float *M, int64_t ldm, int64_t m, int64_t n,
                                 const float *V, int r, int chunks, int64_t chunk, double *Cp,
-                                const int32_t *stop, hipStream_t s);
-// Reduce the partials and update W: mode 0 HALS, 1 MU, 2 store C (r x n).
-// rparts[b] receives the FP64 partial <C, W_new> of column block b.
+                                double *Dp, const int32_t *stop, hipStream_t s);
+// Gd = sum of nparts upper-triangle Gram partials; with resid also the
+// residual log entry from the scalar partials rparts[0..nr).
+hipError_t launch_reduce_gram(const double *parts, int nparts, int rpad, int r, double *Gd,
+                              bool resid, const double *rparts, int nr, const double *normM2,
+                              int depth, double *log_rel, int32_t *log_depth, int log_idx,
+                              int log_cap, DevState *st, double tol, hipStream_t s);
+// Reduce the C partials and update W (and Wt): mode 0 HALS, 1 MU, 2 store C
+// (r x n).  Emits per-block W W^T partials into Bp[blocks][rpad][rpad] and
+// the residual scalars <D, B_b> - 2 <C_b, W_b> into rparts[b].
 hipError_t launch_cpass_final(int rpad, int mode, const double *Cp, int chunks, int64_t n, int r,
-                              const double *Dd, float *W, float *Cout, double *rparts,
-                              const int32_t *stop, hipStream_t s);
+                              const double *Dd, float *W, float *Wt, float *Cout, double *Bp,
+                              double *rparts, const int32_t *stop, hipStream_t s);
 int cpass_final_blocks(int64_t n);
+hipError_t launch_make_wt(const float *W, int64_t n, int r, int rpad, float *Wt, hipStream_t s);
 
 // ANLS: exact FP64 NNLS per row of V (G = W W^T, rhs = A rows) or per column
 // of W (G = V^T V, rhs = C columns); warm-started from the current factor.
@@ -122,8 +134,8 @@ int cpass_final_blocks(int64_t n);
 hipError_t launch_nnls_rows(int rpad, const double *Gd, const float *A, int64_t m, int r,
                             float *V, int32_t *flags, const int32_t *stop, hipStream_t s);
 hipError_t launch_nnls_cols(int rpad, const double *Gd, const float *C, int64_t n, int r,
-                            float *W, double *rparts, int32_t *flags, const int32_t *stop,
-                            hipStream_t s);
+                            float *W, float *Wt, double *rparts, int32_t *flags,
+                            const int32_t *stop, hipStream_t s);
 int nnls_cols_blocks(int64_t n);
 
 // rel_err = sqrt(max(0, ||M||^2 - 2 sum(rparts) + <Dd, Bd>) / ||M||^2), logged.

@@ -177,6 +177,7 @@ template <int RPAD, int WAVES, bool COLS>
 __global__ __launch_bounds__(WAVES * 64) void k_nnls(const double *__restrict__ Gd,
                                                      const float *__restrict__ Rhs, int64_t count,
                                                      int r, float *__restrict__ X,
+                                                     float *__restrict__ Xt,
                                                      double *__restrict__ rparts,
                                                      int32_t *__restrict__ flags,
                                                      const int32_t *stop) {
@@ -206,6 +207,7 @@ __global__ __launch_bounds__(WAVES * 64) void k_nnls(const double *__restrict__ 
             X[idx] = xf;
             if (COLS) part += b * (double)xf;
         }
+        if (COLS && lane < RPAD) Xt[prob * RPAD + lane] = ok ? (float)x : 0.0f;
     }
     if (failed && lane == 0) atomicOr(flags, 4);
     if constexpr (COLS) {
@@ -223,10 +225,10 @@ __global__ __launch_bounds__(WAVES * 64) void k_nnls(const double *__restrict__ 
 
 template <int RPAD, bool COLS>
 hipError_t launch_nnls_t(const double *Gd, const float *Rhs, int64_t count, int r, float *X,
-                         double *rparts, int32_t *flags, const int32_t *stop, int blocks,
-                         hipStream_t s) {
+                         float *Xt, double *rparts, int32_t *flags, const int32_t *stop,
+                         int blocks, hipStream_t s) {
     constexpr int WAVES = (RPAD >= 64) ? 2 : 4;
-    k_nnls<RPAD, WAVES, COLS><<<blocks, WAVES * 64, 0, s>>>(Gd, Rhs, count, r, X, rparts, flags, stop);
+    k_nnls<RPAD, WAVES, COLS><<<blocks, WAVES * 64, 0, s>>>(Gd, Rhs, count, r, X, Xt, rparts, flags, stop);
     return hipGetLastError();
 }
 
@@ -238,17 +240,17 @@ int nnls_cols_blocks(int64_t n) {
 }
 
 static hipError_t nnls_dispatch(int rpad, bool cols, const double *Gd, const float *Rhs,
-                                int64_t count, int r, float *X, double *rparts, int32_t *flags,
-                                const int32_t *stop, int blocks, hipStream_t s) {
+                                int64_t count, int r, float *X, float *Xt, double *rparts,
+                                int32_t *flags, const int32_t *stop, int blocks, hipStream_t s) {
     switch (rpad) {
-        case 16: return cols ? launch_nnls_t<16, true>(Gd, Rhs, count, r, X, rparts, flags, stop, blocks, s)
-                             : launch_nnls_t<16, false>(Gd, Rhs, count, r, X, rparts, flags, stop, blocks, s);
-        case 32: return cols ? launch_nnls_t<32, true>(Gd, Rhs, count, r, X, rparts, flags, stop, blocks, s)
-                             : launch_nnls_t<32, false>(Gd, Rhs, count, r, X, rparts, flags, stop, blocks, s);
-        case 48: return cols ? launch_nnls_t<48, true>(Gd, Rhs, count, r, X, rparts, flags, stop, blocks, s)
-                             : launch_nnls_t<48, false>(Gd, Rhs, count, r, X, rparts, flags, stop, blocks, s);
-        case 64: return cols ? launch_nnls_t<64, true>(Gd, Rhs, count, r, X, rparts, flags, stop, blocks, s)
-                             : launch_nnls_t<64, false>(Gd, Rhs, count, r, X, rparts, flags, stop, blocks, s);
+        case 16: return cols ? launch_nnls_t<16, true>(Gd, Rhs, count, r, X, Xt, rparts, flags, stop, blocks, s)
+                             : launch_nnls_t<16, false>(Gd, Rhs, count, r, X, Xt, rparts, flags, stop, blocks, s);
+        case 32: return cols ? launch_nnls_t<32, true>(Gd, Rhs, count, r, X, Xt, rparts, flags, stop, blocks, s)
+                             : launch_nnls_t<32, false>(Gd, Rhs, count, r, X, Xt, rparts, flags, stop, blocks, s);
+        case 48: return cols ? launch_nnls_t<48, true>(Gd, Rhs, count, r, X, Xt, rparts, flags, stop, blocks, s)
+                             : launch_nnls_t<48, false>(Gd, Rhs, count, r, X, Xt, rparts, flags, stop, blocks, s);
+        case 64: return cols ? launch_nnls_t<64, true>(Gd, Rhs, count, r, X, Xt, rparts, flags, stop, blocks, s)
+                             : launch_nnls_t<64, false>(Gd, Rhs, count, r, X, Xt, rparts, flags, stop, blocks, s);
         default: return hipErrorInvalidValue;
     }
 }
@@ -257,13 +259,14 @@ hipError_t launch_nnls_rows(int rpad, const double *Gd, const float *A, int64_t 
                             float *V, int32_t *flags, const int32_t *stop, hipStream_t s) {
     int64_t b = (m + 3) / 4;
     const int blocks = (int)(b > 4096 ? 4096 : (b < 1 ? 1 : b));
-    return nnls_dispatch(rpad, false, Gd, A, m, r, V, nullptr, flags, stop, blocks, s);
+    return nnls_dispatch(rpad, false, Gd, A, m, r, V, nullptr, nullptr, flags, stop, blocks, s);
 }
 
 hipError_t launch_nnls_cols(int rpad, const double *Gd, const float *C, int64_t n, int r,
-                            float *W, double *rparts, int32_t *flags, const int32_t *stop,
-                            hipStream_t s) {
-    return nnls_dispatch(rpad, true, Gd, C, n, r, W, rparts, flags, stop, nnls_cols_blocks(n), s);
+                            float *W, float *Wt, double *rparts, int32_t *flags,
+                            const int32_t *stop, hipStream_t s) {
+    return nnls_dispatch(rpad, true, Gd, C, n, r, W, Wt, rparts, flags, stop, nnls_cols_blocks(n),
+                         s);
 }
 
 }  // namespace nmf

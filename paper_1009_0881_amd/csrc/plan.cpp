@@ -196,6 +196,9 @@ nmf_status build_plan(const nmf_desc &d0, Plan &p, std::string &err) {
         p.lv[l].off_M = take(sizeof(float) * (size_t)p.lv[l].m * n);
         p.lv[l].off_V = take(sizeof(float) * (size_t)p.lv[l].m * r);
     }
+    ws.off_Wt = take(sizeof(float) * n * p.rpad);
+    ws.off_Dp = take(sizeof(double) * max_cp * rp2);
+    ws.off_Bp = take(sizeof(double) * (size_t)cpass_final_blocks(d.n) * rp2);
     ws.off_V0bf = 0;
     ws.total = off;
     return NMF_OK;
