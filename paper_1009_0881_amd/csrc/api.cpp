@@ -46,7 +46,8 @@ struct Ctx {
     std::vector<int64_t> ldm;
     std::vector<float *> V;
     float *W;
-    int log_idx = 0;
+    Job *djobs;                   // device copy of `jobs` (workspace)
+    std::vector<Job> jobs;        // one job per level
     std::vector<int8_t> depths;   // depth of every executed iteration (host mirror)
 };
 
@@ -132,7 +133,53 @@ Ctx make_ctx(nmf_plan_t plan, const float *dM, float *dV, float *dW, void *dws, 
         }
     }
     c.W = dW;
+    c.djobs = at<Job>(c.ws, p.ws.off_jobs);
+    for (size_t l = 0; l < p.lv.size(); ++l) {
+        const LevelInfo &li = p.lv[l];
+        Job J{};
+        J.M = c.M[l];
+        J.ldm = c.ldm[l];
+        J.m = li.m;
+        J.n = p.d.n;
+        J.r = p.d.r;
+        J.rpad = p.rpad;
+        J.tm = apass_rows_per_block(li.m);
+        J.chunks = li.cp_chunks;
+        J.chunk = li.cp_chunk;
+        J.nA = (int32_t)((li.m + J.tm - 1) / J.tm);
+        J.nCx = (int32_t)((p.d.n + 63) / 64);
+        J.nC = J.nCx * li.cp_chunks;
+        J.nF = cpass_final_blocks(p.d.n);
+        J.nG = (p.d.r * p.d.r + 255) / 256;
+        J.depth = (int32_t)l;
+        J.log_cap = p.d.log_cap;
+        J.V = c.V[l];
+        J.W = dW;
+        J.Wt = c.Wt;
+        J.A = c.A;
+        J.C = c.C;
+        J.Bd = c.Bd;
+        J.Dd = c.Dd;
+        J.Cp = c.Cp;
+        J.Dp = c.Dp;
+        J.Bp = c.Bp;
+        J.rparts = c.rparts;
+        J.normM2 = c.norm + l;
+        J.log_rel = c.log_rel;
+        J.log_depth = c.log_depth;
+        J.st = c.st;
+        J.tol = p.d.tol;
+        c.jobs.push_back(J);
+    }
     return c;
+}
+
+nmf_status upload_jobs(Ctx &c) {
+    nmf_plan_t plan = c.plan;
+    NMF_HIP(enable_large_lds());
+    NMF_HIP(hipMemcpyAsync(c.djobs, c.jobs.data(), sizeof(Job) * c.jobs.size(),
+                           hipMemcpyHostToDevice, c.s));
+    return NMF_OK;
 }
 
 // B = W W^T with the standalone Gram kernels (start of a solve, ANLS).
@@ -148,47 +195,31 @@ nmf_status gram_W(Ctx &c) {
 nmf_status sweep(Ctx &c, int d) {
     nmf_plan_t plan = c.plan;
     const Plan &p = *c.p;
-    const LevelInfo &li = p.lv[d];
+    const Job &J = c.jobs[d];
+    const Job *dj = c.djobs + d;
     const int r = p.d.r;
-    const int64_t n = p.d.n, m = li.m;
-    const float *M = c.M[d];
-    const int64_t ld = c.ldm[d];
-    float *V = c.V[d];
+    const int64_t n = p.d.n;
     int32_t *flags = &c.st->flags;
-    const int nfb = cpass_final_blocks(n);
-    if (p.d.algo == NMF_ANLS) {
-        NMF_LAUNCH(K_APASS, launch_apass(p.rpad, 2, M, ld, m, n, c.Wt, c.Bd, V, c.A, r, c.stop, c.s));
-        NMF_LAUNCH(K_NNLS_ROWS, launch_nnls_rows(p.rpad, c.Bd, c.A, m, r, V, flags, c.stop, c.s));
-        NMF_LAUNCH(K_CPART, launch_cpass_partial(p.rpad, M, ld, m, n, V, r, li.cp_chunks,
-                                                 li.cp_chunk, c.Cp, c.Dp, c.stop, c.s));
-        NMF_LAUNCH(K_GRAM_V, launch_reduce_gram(c.Dp, li.cp_chunks, p.rpad, r, c.Dd, false,
-                                                nullptr, 0, c.norm, d, c.log_rel, c.log_depth,
-                                                c.log_idx, p.d.log_cap, c.st, p.d.tol, c.s));
-        NMF_LAUNCH(K_CFINAL, launch_cpass_final(p.rpad, 2, c.Cp, li.cp_chunks, n, r, c.Dd, c.W,
-                                                c.Wt, c.C, c.Bp, c.rparts, c.stop, c.s));
+    const int mode = p.d.algo == NMF_HALS ? 0 : (p.d.algo == NMF_MU ? 1 : 2);
+    NMF_LAUNCH(K_APASS, launch_apass_jobs(mode, J.rpad, J.tm, dj, nullptr, 1, J.nA,
+                                          apass_lds_bytes(J.rpad, J.tm, mode), c.s));
+    if (mode == 2)
+        NMF_LAUNCH(K_NNLS_ROWS, launch_nnls_rows(p.rpad, c.Bd, c.A, J.m, r, J.V, flags, c.stop, c.s));
+    NMF_LAUNCH(K_CPART, launch_cpass_jobs(J.rpad, dj, nullptr, 1, J.nC, c.s));
+    NMF_LAUNCH(K_GRAM_V, launch_reduce_jobs(0, dj, nullptr, 1, J.nG, c.s));
+    NMF_LAUNCH(K_CFINAL, launch_cfinal_jobs(mode, J.rpad, dj, nullptr, 1, J.nF,
+                                            cfinal_lds_bytes(J.rpad, mode), c.s));
+    if (mode == 2) {
         NMF_LAUNCH(K_NNLS_COLS, launch_nnls_cols(p.rpad, c.Dd, c.C, n, r, c.W, c.Wt, c.rparts,
                                                  flags, c.stop, c.s));
         nmf_status st = gram_W(c);
         if (st != NMF_OK) return st;
         NMF_LAUNCH(K_RESID, launch_residual(c.rparts, nnls_cols_blocks(n), c.Dd, c.Bd, r, c.norm,
-                                            d, c.log_rel, c.log_depth, c.log_idx, p.d.log_cap,
-                                            c.st, p.d.tol, c.s));
+                                            d, c.log_rel, c.log_depth, p.d.log_cap, c.st,
+                                            p.d.tol, c.s));
     } else {
-        const int mode = p.d.algo == NMF_HALS ? 0 : 1;
-        NMF_LAUNCH(K_APASS, launch_apass(p.rpad, mode, M, ld, m, n, c.Wt, c.Bd, V, nullptr, r,
-                                         c.stop, c.s));
-        NMF_LAUNCH(K_CPART, launch_cpass_partial(p.rpad, M, ld, m, n, V, r, li.cp_chunks,
-                                                 li.cp_chunk, c.Cp, c.Dp, c.stop, c.s));
-        NMF_LAUNCH(K_GRAM_V, launch_reduce_gram(c.Dp, li.cp_chunks, p.rpad, r, c.Dd, false,
-                                                nullptr, 0, c.norm, d, c.log_rel, c.log_depth,
-                                                c.log_idx, p.d.log_cap, c.st, p.d.tol, c.s));
-        NMF_LAUNCH(K_CFINAL, launch_cpass_final(p.rpad, mode, c.Cp, li.cp_chunks, n, r, c.Dd, c.W,
-                                                c.Wt, nullptr, c.Bp, c.rparts, c.stop, c.s));
-        NMF_LAUNCH(K_GRAM_W, launch_reduce_gram(c.Bp, nfb, p.rpad, r, c.Bd, true, c.rparts, nfb,
-                                                c.norm, d, c.log_rel, c.log_depth, c.log_idx,
-                                                p.d.log_cap, c.st, p.d.tol, c.s));
+        NMF_LAUNCH(K_GRAM_W, launch_reduce_jobs(1, dj, nullptr, 1, J.nG, c.s));
     }
-    c.log_idx++;
     c.depths.push_back((int8_t)d);
     return NMF_OK;
 }
@@ -351,6 +382,7 @@ nmf_status nmf_solve(nmf_plan_t plan, const float *dM, float *dV, float *dW, int
     if ((st = prepare_levels(c)) != NMF_OK) return st;
     if ((st = gram_W(c)) != NMF_OK) return st;
     NMF_HIP(launch_make_wt(c.W, p.d.n, p.d.r, p.rpad, c.Wt, s));
+    if ((st = upload_jobs(c)) != NMF_OK) return st;
 
     const bool use_tol = p.d.tol > 0.0;
     const int ce = p.d.check_every;
@@ -426,6 +458,7 @@ nmf_status nmf_iterate(nmf_plan_t plan, const float *dM, float *dV, float *dW, i
     if ((st = prepare_levels(c)) != NMF_OK) return st;
     if ((st = gram_W(c)) != NMF_OK) return st;
     NMF_HIP(launch_make_wt(c.W, plan->p.d.n, plan->p.d.r, plan->p.rpad, c.Wt, s));
+    if ((st = upload_jobs(c)) != NMF_OK) return st;
     for (int i = 0; i < count; ++i)
         if ((st = sweep(c, 0)) != NMF_OK) return st;
     nmf_result res;
@@ -464,15 +497,18 @@ nmf_status nmf_products(nmf_plan_t plan, const float *dM, const float *dV, const
     const Plan &p = plan->p;
     hipStream_t s = static_cast<hipStream_t>(stream);
     Ctx c = make_ctx(plan, dM, const_cast<float *>(dV), const_cast<float *>(dW), dWorkspace, s);
-    const LevelInfo &li = p.lv[0];
+    Job &J = c.jobs[0];
+    J.A = dA;
+    J.C = dC;
     NMF_HIP(launch_state_reset(c.st, s));
     NMF_HIP(launch_make_wt(dW, p.d.n, p.d.r, p.rpad, c.Wt, s));
-    NMF_HIP(launch_apass(p.rpad, 2, dM, p.d.ldm, li.m, p.d.n, c.Wt, nullptr, nullptr, dA, p.d.r,
-                         c.stop, s));
-    NMF_HIP(launch_cpass_partial(p.rpad, dM, p.d.ldm, li.m, p.d.n, dV, p.d.r, li.cp_chunks,
-                                 li.cp_chunk, c.Cp, c.Dp, c.stop, s));
-    NMF_HIP(launch_cpass_final(p.rpad, 2, c.Cp, li.cp_chunks, p.d.n, p.d.r, nullptr, nullptr,
-                               c.Wt, dC, c.Bp, c.rparts, c.stop, s));
+    nmf_status st = upload_jobs(c);
+    if (st != NMF_OK) return st;
+    NMF_HIP(launch_apass_jobs(2, J.rpad, J.tm, c.djobs, nullptr, 1, J.nA,
+                              apass_lds_bytes(J.rpad, J.tm, 2), s));
+    NMF_HIP(launch_cpass_jobs(J.rpad, c.djobs, nullptr, 1, J.nC, s));
+    NMF_HIP(launch_cfinal_jobs(2, J.rpad, c.djobs, nullptr, 1, J.nF, cfinal_lds_bytes(J.rpad, 2), s));
+    NMF_HIP(hipStreamSynchronize(s));
     return NMF_OK;
 }
 

@@ -1,0 +1,41 @@
+// Device-visible description of one NMF problem at one level of its hierarchy
+// (a "job").  Every sweep kernel takes an array of jobs plus, per phase, the
+// prefix sum of the jobs' tile counts: block b works on tile b - prefix[i] of
+// job i.  A single solve launches with one job; a batch or a serving tick
+// launches one grouped kernel per phase over all of its jobs.
+#pragma once
+
+#include <cstdint>
+
+namespace nmf {
+
+struct DevState;
+
+struct Job {
+    const float *M;      // level matrix, m x n column-major, column stride ldm
+    int64_t ldm, m, n;
+    int32_t r, rpad;     // rank and rank padded to 16
+    int32_t tm;          // A-pass rows per tile (16 or 64)
+    int32_t chunks;      // split of the length-m reduction of V^T M
+    int64_t chunk;       // rows per chunk (multiple of 16)
+    int32_t nA, nC, nF, nG;   // tiles of: A-pass, C-pass (nCx * chunks), W update, Gram reduce
+    int32_t nCx;         // 64-column tiles of the C-pass
+    int32_t depth, log_cap;
+    float *V;            // level factor, m x r column-major
+    float *W;            // r x n row-major
+    float *Wt;           // n x rpad, transposed and zero-padded copy of W
+    float *A;            // ANLS: M W^T (m x r)
+    float *C;            // ANLS: V^T M (r x n)
+    double *Bd, *Dd;     // W W^T and V^T V (r x r, FP64)
+    double *Cp;          // V^T M partials: chunks x r x n
+    double *Dp;          // V^T V partials: chunks x rpad x rpad (upper 16x16 tiles)
+    double *Bp;          // W W^T partials: nF x rpad x rpad
+    double *rparts;      // residual scalars, nF
+    const double *normM2;   // ||M_depth||^2
+    double *log_rel;
+    int32_t *log_depth;
+    DevState *st;
+    double tol;
+};
+
+}  // namespace nmf

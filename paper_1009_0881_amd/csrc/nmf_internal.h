@@ -10,6 +10,7 @@
 #include <hip/hip_runtime.h>
 
 #include "../../include/nmf.h"
+#include "job.h"
 
 namespace nmf {
 
@@ -50,7 +51,7 @@ struct Workspace {
     size_t off_state, off_log, off_logdepth, off_norm;
     size_t off_Bd, off_Bf, off_Dd, off_Df;
     size_t off_gparts, off_cparts, off_rparts, off_A, off_C, off_V0bf;
-    size_t off_Wt, off_Dp, off_Bp;
+    size_t off_Wt, off_Dp, off_Bp, off_jobs;
     size_t gparts_cap;   // doubles
     size_t rparts_cap;   // doubles
     size_t total;
@@ -101,31 +102,31 @@ hipError_t launch_gram(int rpad, int r, int64_t L, const float *X, int64_t ldx, 
                        int64_t chunk, double *gparts, double *Gd, float *Gf, const int32_t *stop,
                        hipStream_t s);
 
-// A = M W^T with epilogue: mode 0 HALS V update, 1 MU V update, 2 store A (m x r).
-// Reads W through its transposed zero-padded copy Wt (n x rpad).
-hipError_t launch_apass(int rpad, int mode, const float *M, int64_t ldm, int64_t m, int64_t n,
-                        const float *Wt, const double *Bd, float *V, float *Aout, int r,
-                        const int32_t *stop, hipStream_t s);
+// Job-table sweep kernels (job.h): one launch per phase over `njobs` jobs;
+// prefix[i] = first block of job i (may be null when njobs == 1).
+// mode: 0 HALS, 1 MU, 2 store the product (ANLS).
+// All jobs of one launch share rpad (and tm for the A-pass).
+hipError_t launch_apass_jobs(int mode, int rpad, int tm, const Job *jobs, const int *prefix,
+                             int njobs, int blocks, size_t lds, hipStream_t s);
+hipError_t launch_cpass_jobs(int rpad, const Job *jobs, const int *prefix, int njobs, int blocks,
+                             hipStream_t s);
+// which = 0: V^T V from the C-pass partials; 1: W W^T and the residual log.
+hipError_t launch_reduce_jobs(int which, const Job *jobs, const int *prefix, int njobs, int blocks,
+                              hipStream_t s);
+hipError_t launch_cfinal_jobs(int mode, int rpad, const Job *jobs, const int *prefix, int njobs,
+                              int blocks, size_t lds, hipStream_t s);
 int apass_rows_per_block(int64_t m);
-// Split-m partials of C = V^T M into Cp[chunks][r][n] (FP64) and of V^T V
-// into Dp[chunks][rpad][rpad] (upper-triangle 16x16 tiles, FP64).
-hipError_t launch_cpass_partial(int rpad, const float *M, int64_t ldm, int64_t m, int64_t n,
-                                const float *V, int r, int chunks, int64_t chunk, double *Cp,
-                                double *Dp, const int32_t *stop, hipStream_t s);
-// Gd = sum of nparts upper-triangle Gram partials; with resid also the
-// residual log entry from the scalar partials rparts[0..nr).
-hipError_t launch_reduce_gram(const double *parts, int nparts, int rpad, int r, double *Gd,
-                              bool resid, const double *rparts, int nr, const double *normM2,
-                              int depth, double *log_rel, int32_t *log_depth, int log_idx,
-                              int log_cap, DevState *st, double tol, hipStream_t s);
-// Reduce the C partials and update W (and Wt): mode 0 HALS, 1 MU, 2 store C
-// (r x n).  Emits per-block W W^T partials into Bp[blocks][rpad][rpad] and
-// the residual scalars <D, B_b> - 2 <C_b, W_b> into rparts[b].
-hipError_t launch_cpass_final(int rpad, int mode, const double *Cp, int chunks, int64_t n, int r,
-                              const double *Dd, float *W, float *Wt, float *Cout, double *Bp,
-                              double *rparts, const int32_t *stop, hipStream_t s);
+size_t apass_lds_bytes(int rpad, int tm, int mode);
+size_t cfinal_lds_bytes(int rpad, int mode);
 int cpass_final_blocks(int64_t n);
 hipError_t launch_make_wt(const float *W, int64_t n, int r, int rpad, float *Wt, hipStream_t s);
+// Residual from separately computed Grams (ANLS path): rel_err of
+// ||M||^2 - 2 sum(rparts) + <Dd, Bd>, logged at st->log_len.
+hipError_t launch_residual(const double *rparts, int nparts, const double *Dd, const double *Bd,
+                           int r, const double *normM2, int depth, double *log_rel,
+                           int32_t *log_depth, int log_cap, DevState *st, double tol,
+                           hipStream_t s);
+hipError_t enable_large_lds();
 
 // ANLS: exact FP64 NNLS per row of V (G = W W^T, rhs = A rows) or per column
 // of W (G = V^T V, rhs = C columns); warm-started from the current factor.
@@ -137,11 +138,5 @@ hipError_t launch_nnls_cols(int rpad, const double *Gd, const float *C, int64_t 
                             float *W, float *Wt, double *rparts, int32_t *flags,
                             const int32_t *stop, hipStream_t s);
 int nnls_cols_blocks(int64_t n);
-
-// rel_err = sqrt(max(0, ||M||^2 - 2 sum(rparts) + <Dd, Bd>) / ||M||^2), logged.
-hipError_t launch_residual(const double *rparts, int nparts, const double *Dd, const double *Bd,
-                           int r, const double *normM2, int depth, double *log_rel,
-                           int32_t *log_depth, int log_idx, int log_cap, DevState *st, double tol,
-                           hipStream_t s);
 
 }  // namespace nmf

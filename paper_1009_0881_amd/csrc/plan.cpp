@@ -199,6 +199,7 @@ nmf_status build_plan(const nmf_desc &d0, Plan &p, std::string &err) {
     ws.off_Wt = take(sizeof(float) * n * p.rpad);
     ws.off_Dp = take(sizeof(double) * max_cp * rp2);
     ws.off_Bp = take(sizeof(double) * (size_t)cpass_final_blocks(d.n) * rp2);
+    ws.off_jobs = take(sizeof(Job) * p.lv.size());
     ws.off_V0bf = 0;
     ws.total = off;
     return NMF_OK;

@@ -1,12 +1,16 @@
 // One NMF iteration on one level: the two M-streaming products and the
 // factor updates of Alg. 2 (MU) and Alg. 3 (HALS), plus the residual.
 //
-//   k_apass          A = M W^T (m x r), V update fused as epilogue
-//   k_cpass_partial  split-m partials of C = V^T M, and of D = V^T V (FP64)
-//   k_reduce_gram    D = sum of partials (fixed order)
-//   k_cpass_final    C = sum of partials, W update, partials of W W^T and of
-//                    the residual terms
-//   k_reduce_gram    B = W W^T, plus rel_err = sqrt(||M||^2 - 2<C,W> + <D,B>)/||M||
+//   k_apass    A = M W^T (m x r), V update fused as epilogue
+//   k_cpass    split-m partials of C = V^T M, and of D = V^T V (FP64)
+//   k_reduce   D = sum of partials (fixed order)
+//   k_cfinal   C = sum of partials, W update, partials of W W^T and of the
+//              residual terms
+//   k_reduce   B = W W^T, plus rel_err = sqrt(||M||^2 - 2<C,W> + <D,B>)/||M||
+//
+// Every kernel takes a job table (one entry per problem and level, see job.h):
+// block b of a launch works on tile b - prefix[i] of job i, so one launch per
+// phase serves a single solve or a whole batch of uneven problems.
 //
 // Both products run on the FP32 matrix cores (v_mfma_f32_16x16x4f32); the
 // Gram V^T V on the FP64 ones (v_mfma_f64_16x16x4f64).  Lane layout on a
@@ -25,7 +29,10 @@
 // k = 1..r in order using already-updated entries (Gauss-Seidel, Alg. 3);
 // MU updates all entries from the old values (Alg. 2).
 
+#include <type_traits>
+
 #include "device_common.h"
+#include "job.h"
 #include "nmf_internal.h"
 
 namespace nmf {
@@ -36,53 +43,130 @@ typedef double v4d __attribute__((ext_vector_type(4)));
 
 constexpr int MODE_HALS = 0, MODE_MU = 1, MODE_STORE = 2;
 
-// HALS / MU update of one factor row held by 4 lanes.  G is the r x r FP64
-// Gram of the other factor in LDS (row stride gs, zero-padded to RPAD), gi[k]
-// = 1/G_kk (0 when G_kk = 0), a[k] the matching row of the product (FP64,
-// LDS).  The r x r-sized update arithmetic runs in FP64 (the numerator
-// a_k - sum_l x_l G_lk cancels as the iterate converges); the row is read
-// from and written back to FP32 storage.
-//   HALS: x_k <- max(0, (a_k - sum_{l != k} x_l G_lk) / G_kk); G_kk = 0 keeps x_k.
-//   MU:   x_k <- x_k a_k / (sum_l x_l G_lk); a zero denominator keeps x_k.
+template <int N, int I = 0, class F>
+__device__ __forceinline__ void static_for(F &&f) {
+    if constexpr (I < N) {
+        f(std::integral_constant<int, I>{});
+        static_for<N, I + 1>(f);
+    }
+}
+
+__device__ __forceinline__ int find_job(const int *prefix, int njobs, int b) {
+    if (njobs <= 1) return 0;
+    int lo = 0, hi = njobs;
+    while (hi - lo > 1) {
+        const int mid = (lo + hi) >> 1;
+        if (prefix[mid] <= b) lo = mid;
+        else hi = mid;
+    }
+    return lo;
+}
+
+__device__ __forceinline__ int tile_of(const int *prefix, int njobs, int job, int b) {
+    return njobs <= 1 ? b : b - prefix[job];
+}
+
+// Broadcast lane QK of every quad (4 consecutive lanes) to the whole quad.
+template <int QK>
+__device__ __forceinline__ double quad_bcast(double v) {
+    constexpr int ctrl = QK | (QK << 2) | (QK << 4) | (QK << 6);   // DPP quad_perm
+    const int lo = __builtin_amdgcn_mov_dpp(__double2loint(v), ctrl, 0xF, 0xF, false);
+    const int hi = __builtin_amdgcn_mov_dpp(__double2hiint(v), ctrl, 0xF, 0xF, false);
+    return __hiloint2double(hi, lo);
+}
+
+__device__ __forceinline__ void wave_lds_fence() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// HALS / MU update of one factor row held by a quad of 4 lanes, lane q
+// holding entries k = q (mod 4).  G is the r x r FP64 Gram of the other
+// factor in LDS (row stride gs, zero-padded to RPAD), gi[k] = 1/G_kk (0 when
+// G_kk = 0), a[k] the matching row of the product (FP64, LDS).  The r x r-sized
+// update arithmetic runs in FP64 (the numerator a_k - sum_l x_l G_lk cancels
+// as the iterate converges); the row is read from and written back to FP32
+// storage by the caller.
+//
+// HALS (Alg. 3): x_k <- max(0, (a_k - sum_{l != k} x_l G_lk) / G_kk) for
+// k = 1..r in order, G_kk = 0 keeping x_k.  Computed in the equivalent
+// gradient form: g = a - G x once, then for each k the owner lane sets
+// x_k <- max(0, x_k + g_k / G_kk), broadcasts the change d to its quad, and
+// every lane applies g_l -= d G_kl for its l > k.  The sequential chain per k
+// is a few FP64 operations and one quad broadcast; the Gram row of step k+1 is
+// loaded during step k.
+// MU (Alg. 2): x_k <- x_k a_k / (sum_l x_l G_lk); a zero denominator keeps x_k.
+// Returns v unchanged, but only once dep has been computed: an empty asm that
+// takes dep as an input orders the instructions that use the result after
+// those that produce dep.  No instruction is emitted.
+__device__ __forceinline__ int ordered_after(int v, double dep) {
+    asm("" : "+v"(v) : "v"(dep));
+    return v;
+}
+
 template <int RPAD, int MODE>
 __device__ __forceinline__ void row_update(double (&x)[RPAD / 4], const double *G, int gs,
                                            const double *gi, const double *a, int r, int q) {
+    constexpr int NJ = RPAD / 4;
+    double acc[NJ];
+#pragma unroll
+    for (int jj = 0; jj < NJ; ++jj) acc[jj] = 0.0;
+    // Padded entries (k >= r) have x_k = 0, zero Gram rows and 1/G_kk = 0, so
+    // the mat-vec skips whole groups of 4 padded entries and the HALS loop runs
+    // over all RPAD entries with no runtime bound.
+    static_for<RPAD / 4>([&](auto lg_c) {      // acc_k = sum_l x_l G_lk, 4 l per group
+        constexpr int lg = decltype(lg_c)::value;
+        if (4 * lg < r) {
+            static_for<4>([&](auto lq_c) {
+                constexpr int l = 4 * lg + decltype(lq_c)::value;
+                const double xl = quad_bcast<l % 4>(x[lg]);
+                const double *gr = G + l * gs + q;
+#pragma unroll
+                for (int jj = 0; jj < NJ; ++jj) acc[jj] = fma(xl, gr[4 * jj], acc[jj]);
+            });
+        }
+    });
     if constexpr (MODE == MODE_HALS) {
+        double g[NJ], ginv[NJ], row0[NJ], row1[NJ];
 #pragma unroll
-        for (int k = 0; k < RPAD; ++k) {
-            if (k < r) {
-                double s = 0.0;
-#pragma unroll
-                for (int jj = 0; jj < RPAD / 4; ++jj) {
-                    const int l = 4 * jj + q;
-                    if (l != k) s = fma(x[jj], G[l * gs + k], s);
-                }
-                s += __shfl_xor(s, 1, kWave);
-                s += __shfl_xor(s, 2, kWave);
-                const double inv = gi[k];
-                if (inv > 0.0) {
-                    const double nv = fmax(0.0, (a[k] - s) * inv);
-                    if (q == (k & 3)) x[k >> 2] = nv;
-                }
-            }
+        for (int jj = 0; jj < NJ; ++jj) {
+            const int k = 4 * jj + q;
+            g[jj] = k < r ? a[k] - acc[jj] : 0.0;
+            ginv[jj] = gi[k];
+            row0[jj] = G[q + 4 * jj];                   // Gram row 0
+            row1[jj] = G[gs + q + 4 * jj];              // Gram row 1
         }
+        double dprev = acc[0];
+        static_for<RPAD>([&](auto k_c) {
+            constexpr int k = decltype(k_c)::value, kk = k / 4, qk = k % 4;
+            double row2[NJ];                            // Gram row k+2, two steps ahead
+            if constexpr (k + 2 < RPAD) {
+                const double *gr = G + ordered_after((k + 2) * gs + q, dprev);
+#pragma unroll
+                for (int jj = (k + 2) / 4; jj < NJ; ++jj) row2[jj] = gr[4 * jj];
+            }
+            const bool own = q == qk && ginv[kk] > 0.0;
+            const double cand = fmax(0.0, fma(g[kk], ginv[kk], x[kk]));
+            double d = own ? cand - x[kk] : 0.0;
+            x[kk] = own ? cand : x[kk];
+            d = quad_bcast<qk>(d);
+            dprev = d;
+            g[kk] = q > qk ? fma(-d, row0[kk], g[kk]) : g[kk];
+#pragma unroll
+            for (int jj = kk + 1; jj < NJ; ++jj) g[jj] = fma(-d, row0[jj], g[jj]);
+#pragma unroll
+            for (int jj = (k + 1) / 4; jj < NJ; ++jj) {
+                row0[jj] = row1[jj];
+                if constexpr (k + 2 < RPAD) row1[jj] = row2[jj];
+            }
+        });
     } else {
-        double nx[RPAD / 4];
 #pragma unroll
-        for (int jj = 0; jj < RPAD / 4; ++jj) nx[jj] = x[jj];
-#pragma unroll
-        for (int k = 0; k < RPAD; ++k) {
-            if (k < r) {
-                double den = 0.0;
-#pragma unroll
-                for (int jj = 0; jj < RPAD / 4; ++jj) den = fma(x[jj], G[(4 * jj + q) * gs + k], den);
-                den += __shfl_xor(den, 1, kWave);
-                den += __shfl_xor(den, 2, kWave);
-                if (q == (k & 3) && den > 0.0) nx[k >> 2] = x[k >> 2] * a[k] / den;
-            }
+        for (int jj = 0; jj < NJ; ++jj) {
+            const int k = 4 * jj + q;
+            if (k < r && acc[jj] > 0.0) x[jj] = x[jj] * a[k] / acc[jj];
         }
-#pragma unroll
-        for (int jj = 0; jj < RPAD / 4; ++jj) x[jj] = nx[jj];
     }
 }
 
@@ -101,34 +185,59 @@ __device__ __forceinline__ void load_gram(const double *__restrict__ Gd, int r, 
     }
 }
 
+// Sum of `count` FP64 values p0[0], p0[stride], ... in index order, with up
+// to 16 loads in flight.
+__device__ __forceinline__ double sum_strided(const double *__restrict__ p0, int64_t stride,
+                                              int count) {
+    double s = 0.0;
+    int p = 0;
+    for (; p + 16 <= count; p += 16) {
+        double t[16];
+#pragma unroll
+        for (int u = 0; u < 16; ++u) t[u] = p0[(p + u) * stride];
+#pragma unroll
+        for (int u = 0; u < 16; ++u) s += t[u];
+    }
+    for (; p + 4 <= count; p += 4) {
+        double t[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) t[u] = p0[(p + u) * stride];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) s += t[u];
+    }
+    for (; p < count; ++p) s += p0[p * stride];
+    return s;
+}
+
 // ---------------------------------------------------------------------------
-// A-pass.  Block = 4 waves; the waves form WR = 4/WN row groups of RW 16-row
-// tiles each, and the WN waves of a row group split the n columns into
+// A-pass tile.  Block = 4 waves; the waves form WR = 4/WN row groups of RW
+// 16-row tiles each, and the WN waves of a row group split the n columns into
 // contiguous ranges.  M (column j of a 16-row tile: 16 consecutive floats) and
 // the transposed factor Wt (n x RPAD, row j = column j of W) are loaded
-// straight into registers, four 4-column steps at a time, double buffered.
-// The WN partial tiles are added in LDS (fixed order) before the epilogue.
+// straight into registers, S 4-column steps at a time, double buffered.  The
+// WN partial tiles are added in LDS (fixed order) before the epilogue.
 // ---------------------------------------------------------------------------
-template <int RT, int RW, int WN, int MODE>
-__global__ __launch_bounds__(256) void k_apass(const float *__restrict__ M, int64_t ldm,
-                                               int64_t m, int64_t n,
-                                               const float *__restrict__ Wt,
-                                               const double *__restrict__ Bd,
-                                               float *__restrict__ V, float *__restrict__ Aout,
-                                               int r, const int32_t *stop) {
+template <int RT, int RW, int WN>
+constexpr int apass_lds_doubles(bool upd) {
+    return (upd ? (RT * 16) * (RT * 16 + 1) + RT * 16 : 0) + 4 * 16 * RW * (RT * 16 + 1);
+}
+
+template <int RT, int RW, int WN, int S, int MODE>
+__device__ void apass_tile(const Job &J, int tile, double *smem) {
     constexpr int RPAD = RT * 16, WR = 4 / WN, TMW = 16 * RW, TM = TMW * WR;
     constexpr int AS = RPAD + 1, GS = RPAD + 1;
     constexpr bool UPD = MODE != MODE_STORE;
-    __shared__ double Gs[UPD ? RPAD * GS : 1];
-    __shared__ double Gi[UPD ? RPAD : 1];
-    __shared__ double As[4 * TMW * AS];
-    if (stopped(stop)) return;
+    double *Gs = smem;
+    double *Gi = Gs + (UPD ? RPAD * GS : 0);
+    double *As = Gi + (UPD ? RPAD : 0);
     const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
     const int wr = wave / WN, wn = wave % WN;
     const int li = lane & 15, lk = lane >> 4;
-    const int64_t brow = (int64_t)blockIdx.x * TM;
+    const int64_t m = J.m, n = J.n, ldm = J.ldm;
+    const int r = J.r;
+    const int64_t brow = (int64_t)tile * TM;
     const int64_t row0 = brow + wr * TMW;
-    if constexpr (UPD) load_gram<RPAD>(Bd, r, Gs, GS, Gi);
+    const float *__restrict__ Wt = J.Wt;
 
     const int64_t nsteps = (n + 3) >> 2;
     const int64_t per = (nsteps + WN - 1) / WN;
@@ -140,7 +249,7 @@ __global__ __launch_bounds__(256) void k_apass(const float *__restrict__ M, int6
     for (int q = 0; q < RW; ++q) {
         const int64_t row = row0 + 16 * q + li;
         rok[q] = row < m;
-        Mr[q] = M + (rok[q] ? row : 0);
+        Mr[q] = J.M + (rok[q] ? row : 0);
     }
     v4f hi[RW][RT], lo[RW][RT];
 #pragma unroll
@@ -148,10 +257,10 @@ __global__ __launch_bounds__(256) void k_apass(const float *__restrict__ M, int6
 #pragma unroll
         for (int t = 0; t < RT; ++t) hi[q][t] = lo[q][t] = v4f{0.0f, 0.0f, 0.0f, 0.0f};
 
-    float a0[4][RW], b0[4][RT], a1[4][RW], b1[4][RT];
-    auto load = [&](int64_t s, float (&a)[4][RW], float (&b)[4][RT]) {
+    float a0[S][RW], b0[S][RT], a1[S][RW], b1[S][RT];
+    auto load = [&](int64_t s, float (&a)[S][RW], float (&b)[S][RT]) {
 #pragma unroll
-        for (int u = 0; u < 4; ++u) {
+        for (int u = 0; u < S; ++u) {
             const int64_t j = 4 * (s + u) + lk;
             const bool ok = (s + u) < s_end && j < n;
 #pragma unroll
@@ -160,33 +269,53 @@ __global__ __launch_bounds__(256) void k_apass(const float *__restrict__ M, int6
             for (int t = 0; t < RT; ++t) b[u][t] = ok ? Wt[j * RPAD + 16 * t + li] : 0.0f;
         }
     };
-    auto compute = [&](const float (&a)[4][RW], const float (&b)[4][RT]) {
-        v4f acc[RW][RT];
+    auto compute = [&](const float (&a)[S][RW], const float (&b)[S][RT]) {
 #pragma unroll
-        for (int q = 0; q < RW; ++q)
-#pragma unroll
-            for (int t = 0; t < RT; ++t) acc[q][t] = v4f{0.0f, 0.0f, 0.0f, 0.0f};
-#pragma unroll
-        for (int u = 0; u < 4; ++u)
+        for (int u0 = 0; u0 < S; u0 += 4) {      // 4 steps = 16 products per chain
+            v4f acc[RW][RT];
 #pragma unroll
             for (int q = 0; q < RW; ++q)
 #pragma unroll
-                for (int t = 0; t < RT; ++t)
-                    acc[q][t] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[u][q], b[u][t], acc[q][t], 0, 0, 0);
+                for (int t = 0; t < RT; ++t) acc[q][t] = v4f{0.0f, 0.0f, 0.0f, 0.0f};
 #pragma unroll
-        for (int q = 0; q < RW; ++q)
+            for (int u = u0; u < u0 + 4; ++u)
 #pragma unroll
-            for (int t = 0; t < RT; ++t) two_sum_acc(hi[q][t], lo[q][t], acc[q][t]);
-    };
-    if (s_begin < s_end) {
-        load(s_begin, a0, b0);
-        for (int64_t s = s_begin; s < s_end; s += 8) {
-            load(s + 4, a1, b1);
-            compute(a0, b0);
-            if (s + 4 >= s_end) break;
-            load(s + 8, a0, b0);
-            compute(a1, b1);
+                for (int q = 0; q < RW; ++q)
+#pragma unroll
+                    for (int t = 0; t < RT; ++t)
+                        acc[q][t] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[u][q], b[u][t],
+                                                                         acc[q][t], 0, 0, 0);
+#pragma unroll
+            for (int q = 0; q < RW; ++q)
+#pragma unroll
+                for (int t = 0; t < RT; ++t) two_sum_acc(hi[q][t], lo[q][t], acc[q][t]);
         }
+    };
+    // factor row of the epilogue (4 lanes per row, rows tid/4 + 64i)
+    constexpr int EPR = (TM + 63) / 64;
+    double xv[UPD ? EPR : 1][RPAD / 4];
+    if constexpr (UPD) {
+#pragma unroll
+        for (int i = 0; i < EPR; ++i) {
+            const int er = (tid >> 2) + 64 * i;
+            const int64_t vrow = brow + er;
+            const bool ok = er < TM && vrow < m;
+#pragma unroll
+            for (int jj = 0; jj < RPAD / 4; ++jj) {
+                const int k = 4 * jj + (tid & 3);
+                xv[i][jj] = (ok && k < r) ? (double)J.V[vrow + (int64_t)k * m] : 0.0;
+            }
+        }
+    }
+    if (s_begin < s_end) load(s_begin, a0, b0);
+    // the Gram goes to LDS while the first operand batch is in flight
+    if constexpr (UPD) load_gram<RPAD>(J.Bd, r, Gs, GS, Gi);
+    for (int64_t s = s_begin; s < s_end; s += 2 * S) {
+        if (s + S < s_end) load(s + S, a1, b1);
+        compute(a0, b0);
+        if (s + S >= s_end) break;
+        if (s + 2 * S < s_end) load(s + 2 * S, a0, b0);
+        compute(a1, b1);
     }
     // hi[q][t][v] + lo[q][t][v] = A[row0 + 16q + 4*lk + v][16t + li]
     double *Aw = As + wave * TMW * AS;
@@ -215,58 +344,63 @@ __global__ __launch_bounds__(256) void k_apass(const float *__restrict__ M, int6
         for (int e = tid; e < TM * r; e += 256) {
             const int rr = e % TM, k = e / TM;
             const int64_t row = brow + rr;
-            if (row < m) Aout[row + (int64_t)k * m] = (float)arow(rr)[k];
+            if (row < m) J.A[row + (int64_t)k * m] = (float)arow(rr)[k];
         }
     } else {
-        if (tid < 4 * TM) {
-            const int er = tid >> 2, q = tid & 3;
-            const int64_t vrow = brow + er;
-            const bool ok = vrow < m;
-            double x[RPAD / 4];
 #pragma unroll
-            for (int jj = 0; jj < RPAD / 4; ++jj) {
-                const int k = 4 * jj + q;
-                x[jj] = (ok && k < r) ? (double)V[vrow + (int64_t)k * m] : 0.0;
-            }
-            row_update<RPAD, MODE>(x, Gs, GS, Gi, arow(er), r, q);
+        for (int i = 0; i < EPR; ++i) {
+            const int er = (tid >> 2) + 64 * i;
+            if (er < TM) {      // whole quads and whole waves take this branch together
+                const int q = tid & 3;
+                const int64_t vrow = brow + er;
+                row_update<RPAD, MODE>(xv[i], Gs, GS, Gi, arow(er), r, q);
+                if (vrow < m) {
 #pragma unroll
-            for (int jj = 0; jj < RPAD / 4; ++jj) {
-                const int k = 4 * jj + q;
-                if (ok && k < r) V[vrow + (int64_t)k * m] = (float)x[jj];
+                    for (int jj = 0; jj < RPAD / 4; ++jj) {
+                        const int k = 4 * jj + q;
+                        if (k < r) J.V[vrow + (int64_t)k * m] = (float)xv[i][jj];
+                    }
+                }
             }
         }
     }
 }
 
+template <int RT, int RW, int WN, int S, int MODE>
+__global__ __launch_bounds__(256) void k_apass(const Job *__restrict__ jobs,
+                                               const int *__restrict__ prefix, int njobs) {
+    extern __shared__ double smem[];
+    const int ji = find_job(prefix, njobs, blockIdx.x);
+    const Job &J = jobs[ji];
+    if (J.st->stop) return;
+    apass_tile<RT, RW, WN, S, MODE>(J, tile_of(prefix, njobs, ji, blockIdx.x), smem);
+}
+
 // ---------------------------------------------------------------------------
-// C-pass partials: block (x = 64-column tile of n, y = chunk of m rows).
-// Each wave owns 16 columns; a lane loads 4 consecutive rows of M and of the
-// r columns of V (float4 each) and feeds them to 4 MFMAs, so the k-index of
-// MFMA s maps to row i0 + 4*(lane/16) + s.  Loads are double buffered.
+// C-pass tile: (x = 64-column tile of n, y = chunk of m rows).  Each wave owns
+// 16 columns; a lane loads 4 consecutive rows of M and of the r columns of V
+// (float4 each) and feeds them to 4 MFMAs, so the k-index of MFMA s maps to
+// row i0 + 4*(lane/16) + s.  Loads are double buffered two 16-row steps deep.
 // The same V registers feed the FP64 MFMAs of the chunk's partial V^T V: its
-// upper-triangle 16x16 tiles are spread over the waves of the chunk's blocks.
+// upper-triangle 16x16 tiles are spread over the waves of the chunk's tiles.
 // ---------------------------------------------------------------------------
-template <int RT>
-__global__ __launch_bounds__(256) void k_cpass_partial(const float *__restrict__ M, int64_t ldm,
-                                                       int64_t m, int64_t n,
-                                                       const float *__restrict__ V, int r,
-                                                       int64_t chunk, double *__restrict__ Cp,
-                                                       double *__restrict__ Dp,
-                                                       const int32_t *stop) {
+template <int RT, int SB>
+__device__ void cpass_tile(const Job &J, int tx, int ty, int ntx) {
     constexpr int RPAD = RT * 16, DMAX = 3;
-    if (stopped(stop)) return;
     const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
     const int lj = lane & 15, lg = lane >> 4;
-    const int64_t jb = (int64_t)blockIdx.x * 64 + wave * 16;
-    const int64_t i_begin = (int64_t)blockIdx.y * chunk;
-    const int64_t i_end = (i_begin + chunk < m) ? i_begin + chunk : m;
+    const int64_t m = J.m, n = J.n, ldm = J.ldm;
+    const int r = J.r;
+    const float *__restrict__ V = J.V;
+    const int64_t jb = (int64_t)tx * 64 + wave * 16;
+    const int64_t i_begin = (int64_t)ty * J.chunk;
+    const int64_t i_end = (i_begin + J.chunk < m) ? i_begin + J.chunk : m;
     const int64_t j = jb + lj;
     const bool jok = j < n;
-    const float *Mc = M + (jok ? j : 0) * ldm;
+    const float *Mc = J.M + (jok ? j : 0) * ldm;
     const bool vec = ((ldm & 3) == 0) && ((m & 3) == 0) &&
-                     (((uintptr_t)M & 15) == 0) && (((uintptr_t)V & 15) == 0);
-    // Gram tiles owned by this wave: tile indices slot, slot + nslots, ...
-    const int slot = blockIdx.x * 4 + wave, nslots = gridDim.x * 4;
+                     (((uintptr_t)J.M & 15) == 0) && (((uintptr_t)V & 15) == 0);
+    const int slot = tx * 4 + wave, nslots = ntx * 4;
     int dta[DMAX], dtb[DMAX];
     int nd = 0;
     {
@@ -286,7 +420,7 @@ __global__ __launch_bounds__(256) void k_cpass_partial(const float *__restrict__
 #pragma unroll
     for (int d = 0; d < DMAX; ++d) dacc[d] = v4d{0.0, 0.0, 0.0, 0.0};
 
-    auto load = [&](int64_t i0, v4f &mv, v4f (&vv)[RT]) {
+    auto load1 = [&](int64_t i0, v4f &mv, v4f (&vv)[RT]) {
         const int64_t ib = i0 + 4 * lg;
         if (vec && ib + 3 < i_end) {
             mv = jok ? *(const v4f *)(Mc + ib) : v4f{0.0f, 0.0f, 0.0f, 0.0f};
@@ -310,47 +444,54 @@ __global__ __launch_bounds__(256) void k_cpass_partial(const float *__restrict__
             }
         }
     };
-    auto compute = [&](const v4f &mv, const v4f (&vv)[RT]) {
-        v4f acc[RT];
+    auto load = [&](int64_t i0, v4f (&mv)[SB], v4f (&vv)[SB][RT]) {
 #pragma unroll
-        for (int t = 0; t < RT; ++t) acc[t] = v4f{0.0f, 0.0f, 0.0f, 0.0f};
+        for (int u = 0; u < SB; ++u) load1(i0 + 16 * u, mv[u], vv[u]);
+    };
+    auto compute = [&](const v4f (&mvs)[SB], const v4f (&vvs)[SB][RT]) {
 #pragma unroll
-        for (int s = 0; s < 4; ++s)
+        for (int u = 0; u < SB; ++u) {
+            v4f acc[RT];
 #pragma unroll
-            for (int t = 0; t < RT; ++t)
-                acc[t] = __builtin_amdgcn_mfma_f32_16x16x4f32(mv[s], vv[t][s], acc[t], 0, 0, 0);
+            for (int t = 0; t < RT; ++t) acc[t] = v4f{0.0f, 0.0f, 0.0f, 0.0f};
 #pragma unroll
-        for (int t = 0; t < RT; ++t) two_sum_acc(hi[t], lo[t], acc[t]);
+            for (int s = 0; s < 4; ++s)
 #pragma unroll
-        for (int d = 0; d < DMAX; ++d) {
-            if (d < nd) {
+                for (int t = 0; t < RT; ++t)
+                    acc[t] = __builtin_amdgcn_mfma_f32_16x16x4f32(mvs[u][s], vvs[u][t][s], acc[t], 0, 0, 0);
 #pragma unroll
-                for (int s = 0; s < 4; ++s) {
-                    double va = 0.0, vb = 0.0;
+            for (int t = 0; t < RT; ++t) two_sum_acc(hi[t], lo[t], acc[t]);
 #pragma unroll
-                    for (int t = 0; t < RT; ++t) {
-                        if (t == dta[d]) va = (double)vv[t][s];
-                        if (t == dtb[d]) vb = (double)vv[t][s];
+            for (int d = 0; d < DMAX; ++d) {
+                if (d < nd) {
+#pragma unroll
+                    for (int s = 0; s < 4; ++s) {
+                        double va = 0.0, vb = 0.0;
+#pragma unroll
+                        for (int t = 0; t < RT; ++t) {
+                            if (t == dta[d]) va = (double)vvs[u][t][s];
+                            if (t == dtb[d]) vb = (double)vvs[u][t][s];
+                        }
+                        dacc[d] = __builtin_amdgcn_mfma_f64_16x16x4f64(va, vb, dacc[d], 0, 0, 0);
                     }
-                    dacc[d] = __builtin_amdgcn_mfma_f64_16x16x4f64(va, vb, dacc[d], 0, 0, 0);
                 }
             }
         }
     };
     if (i_begin < i_end) {
-        v4f m0, m1, v0[RT], v1[RT];
+        v4f m0[SB], m1[SB], v0[SB][RT], v1[SB][RT];
         load(i_begin, m0, v0);
-        for (int64_t i0 = i_begin; i0 < i_end; i0 += 32) {
-            const bool more = i0 + 16 < i_end;
-            if (more) load(i0 + 16, m1, v1);
+        for (int64_t i0 = i_begin; i0 < i_end; i0 += 32 * SB) {
+            const bool more = i0 + 16 * SB < i_end;
+            if (more) load(i0 + 16 * SB, m1, v1);
             compute(m0, v0);
             if (!more) break;
-            if (i0 + 32 < i_end) load(i0 + 32, m0, v0);
+            if (i0 + 32 * SB < i_end) load(i0 + 32 * SB, m0, v0);
             compute(m1, v1);
         }
     }
     // hi[t][v] + lo[t][v] = C[k = 16t + lj][j = jb + 4*lg + v]
-    double *out = Cp + (int64_t)blockIdx.y * r * n;
+    double *out = J.Cp + (int64_t)ty * r * n;
 #pragma unroll
     for (int t = 0; t < RT; ++t) {
         const int k = 16 * t + lj;
@@ -363,7 +504,7 @@ __global__ __launch_bounds__(256) void k_cpass_partial(const float *__restrict__
         }
     }
     // dacc[d][v] = D[16*dta + 4*v + lg][16*dtb + lj]
-    double *dout = Dp + (int64_t)blockIdx.y * RPAD * RPAD;
+    double *dout = J.Dp + (int64_t)ty * RPAD * RPAD;
 #pragma unroll
     for (int d = 0; d < DMAX; ++d) {
         if (d < nd) {
@@ -374,58 +515,63 @@ __global__ __launch_bounds__(256) void k_cpass_partial(const float *__restrict__
     }
 }
 
+template <int RT, int SB>
+__global__ __launch_bounds__(256) void k_cpass(const Job *__restrict__ jobs,
+                                               const int *__restrict__ prefix, int njobs) {
+    const int ji = find_job(prefix, njobs, blockIdx.x);
+    const Job &J = jobs[ji];
+    if (J.st->stop) return;
+    const int tile = tile_of(prefix, njobs, ji, blockIdx.x);
+    cpass_tile<RT, SB>(J, tile % J.nCx, tile / J.nCx, J.nCx);
+}
+
 // ---------------------------------------------------------------------------
 // Sum of FP64 Gram partials stored as upper-triangle 16x16 tiles (row stride
 // rpad): G[a][b] = sum_p parts[p][min(a,b)][max(a,b)], added in index order.
-// With `resid` set, block 0 also assembles the residual of the iteration:
-// e^2 = ||M_d||^2 + sum_b rparts[b] (the partials carry <D, B_b> - 2 <C_b, W_b>).
+// which = 0: D from the C-pass partials.  which = 1: B from the W-update
+// partials, and tile 0 also assembles the residual of the iteration,
+// e^2 = ||M_d||^2 + sum_b rparts[b] (the partials carry <D,B_b> - 2<C_b,W_b>),
+// logs rel_err and sets the stop flag.
 // ---------------------------------------------------------------------------
-__global__ __launch_bounds__(256) void k_reduce_gram(const double *__restrict__ parts, int nparts,
-                                                     int rpad, int r, double *__restrict__ Gd,
-                                                     int resid, const double *__restrict__ rparts,
-                                                     int nr, const double *__restrict__ normM2,
-                                                     int depth, double *__restrict__ log_rel,
-                                                     int32_t *__restrict__ log_depth, int log_idx,
-                                                     int log_cap, DevState *st, double tol) {
+__global__ __launch_bounds__(256) void k_reduce(const Job *__restrict__ jobs,
+                                                const int *__restrict__ prefix, int njobs,
+                                                int which) {
     __shared__ double red[4];
-    if (st->stop) return;
-    const int e = blockIdx.x * 256 + threadIdx.x;
+    const int ji = find_job(prefix, njobs, blockIdx.x);
+    const Job &J = jobs[ji];
+    if (J.st->stop) return;
+    const int tile = tile_of(prefix, njobs, ji, blockIdx.x);
+    const int r = J.r, rpad = J.rpad;
+    const int e = tile * 256 + threadIdx.x;
+    const double *parts = which ? J.Bp : J.Dp;
+    const int nparts = which ? J.nF : J.chunks;
     if (e < r * r) {
         const int a = e / r, b = e % r;
         const int ua = a < b ? a : b, ub = a < b ? b : a;
-        const double *p0 = parts + ua * rpad + ub;
-        const int64_t stride = (int64_t)rpad * rpad;
-        double s = 0.0;
-        int p = 0;
-        for (; p + 8 <= nparts; p += 8) {
-            double t[8];
-#pragma unroll
-            for (int u = 0; u < 8; ++u) t[u] = p0[(p + u) * stride];
-#pragma unroll
-            for (int u = 0; u < 8; ++u) s += t[u];
-        }
-        for (; p < nparts; ++p) s += p0[p * stride];
-        Gd[e] = s;
+        const double s = sum_strided(parts + ua * rpad + ub, (int64_t)rpad * rpad, nparts);
+        (which ? J.Bd : J.Dd)[e] = s;
     }
-    if (resid && blockIdx.x == 0) {
+    if (which && tile == 0) {
         double s = 0.0;
-        for (int i = threadIdx.x; i < nr; i += 256) s += rparts[i];
+        for (int i = threadIdx.x; i < J.nF; i += 256) s += J.rparts[i];
         s = block_sum_f64<256>(s, red);
         if (threadIdx.x == 0) {
-            const double nm = normM2[depth];
+            DevState *st = J.st;
+            const double nm = *J.normM2;
             const double e2 = nm + s;
             const double e2c = e2 > 0.0 ? e2 : 0.0;
             const double rel = nm > 0.0 ? sqrt(e2c / nm) : sqrt(e2c);
-            if (log_idx < log_cap) {
-                log_rel[log_idx] = rel;
-                log_depth[log_idx] = depth;
+            const int idx = st->log_len;
+            if (idx < J.log_cap) {
+                J.log_rel[idx] = rel;
+                J.log_depth[idx] = J.depth;
             }
-            st->log_len = log_idx + 1;
+            st->log_len = idx + 1;
             st->last_rel = rel;
             if (!isfinite(e2)) {
                 st->status = NMF_E_NONFINITE;
                 st->stop = 1;
-            } else if (depth == 0 && tol > 0.0 && rel <= tol) {
+            } else if (J.depth == 0 && J.tol > 0.0 && rel <= J.tol) {
                 st->stopped = 1;
                 st->stop = 1;
             }
@@ -434,56 +580,47 @@ __global__ __launch_bounds__(256) void k_reduce_gram(const double *__restrict__ 
 }
 
 // ---------------------------------------------------------------------------
-// Reduce the C partials of 16 columns (fixed order) and update those columns
-// of W (and of its transposed copy Wt).  Also emits this block's FP64 partial
-// of B = W W^T (upper-triangle tiles) and the residual scalar
-// <D, B_block> - 2 <C_block, W_block>.
+// W-update tile: reduce the C partials of 16 columns (fixed order) and update
+// those columns of W (and of its transposed copy Wt).  Also emits this
+// tile's FP64 partial of B = W W^T (upper-triangle tiles) and the residual
+// scalar <D, B_tile> - 2 <C_tile, W_tile>.
 // ---------------------------------------------------------------------------
 template <int RT, int MODE>
-__global__ __launch_bounds__(256) void k_cpass_final(const double *__restrict__ Cp, int chunks,
-                                                     int64_t n, int r,
-                                                     const double *__restrict__ Dd,
-                                                     float *__restrict__ W, float *__restrict__ Wt,
-                                                     float *__restrict__ Cout,
-                                                     double *__restrict__ Bp,
-                                                     double *__restrict__ rparts,
-                                                     const int32_t *stop) {
+__device__ void cfinal_tile(const Job &J, int tile, double *smem) {
     constexpr int RPAD = RT * 16, GS = RPAD + 1, CS = RPAD + 1;
     constexpr bool UPD = MODE != MODE_STORE;
-    __shared__ double Gs[UPD ? RPAD * GS : 1];
-    __shared__ double Gi[UPD ? RPAD : 1];
-    __shared__ double Cs[16 * CS];
-    __shared__ double Wn[UPD ? 16 * CS : 1];
-    __shared__ double red[4];
-    if (stopped(stop)) return;
+    double *Gs = smem;
+    double *Gi = Gs + (UPD ? RPAD * GS : 0);
+    double *Cs = Gi + (UPD ? RPAD : 0);
+    double *Wn = Cs + 16 * CS;
+    double *red = Wn + (UPD ? 16 * CS : 0);
     const int tid = threadIdx.x;
-    const int64_t j0 = (int64_t)blockIdx.x * 16;
-    if constexpr (UPD) load_gram<RPAD>(Dd, r, Gs, GS, Gi);
+    const int64_t n = J.n;
+    const int r = J.r;
+    const int64_t j0 = (int64_t)tile * 16;
+    double xw[RPAD / 4];
+    if constexpr (UPD) {
+        const int64_t j = j0 + (tid >> 2);
+#pragma unroll
+        for (int t = 0; t < RPAD / 4; ++t) {
+            const int k = 4 * t + (tid & 3);
+            xw[t] = (tid < 64 && j < n && k < r) ? (double)J.W[(int64_t)k * n + j] : 0.0;
+        }
+    }
     for (int e = tid; e < 16 * RPAD; e += 256) {
         const int jj = e & 15, k = e >> 4;
         const int64_t j = j0 + jj;
         double s = 0.0;
-        if (k < r && j < n) {
-            const double *p0 = Cp + (int64_t)k * n + j;
-            const int64_t stride = (int64_t)r * n;
-            int p = 0;
-            for (; p + 8 <= chunks; p += 8) {
-                double t[8];
-#pragma unroll
-                for (int u = 0; u < 8; ++u) t[u] = p0[(p + u) * stride];
-#pragma unroll
-                for (int u = 0; u < 8; ++u) s += t[u];
-            }
-            for (; p < chunks; ++p) s += p0[p * stride];
-        }
+        if (k < r && j < n) s = sum_strided(J.Cp + (int64_t)k * n + j, (int64_t)r * n, J.chunks);
         Cs[jj * CS + k] = s;
     }
+    if constexpr (UPD) load_gram<RPAD>(J.Dd, r, Gs, GS, Gi);
     __syncthreads();
     if constexpr (MODE == MODE_STORE) {
         for (int e = tid; e < 16 * r; e += 256) {
             const int jj = e & 15, k = e >> 4;
             const int64_t j = j0 + jj;
-            if (j < n) Cout[(int64_t)k * n + j] = (float)Cs[jj * CS + k];
+            if (j < n) J.C[(int64_t)k * n + j] = (float)Cs[jj * CS + k];
         }
     } else {
         double part_cw = 0.0;
@@ -491,22 +628,16 @@ __global__ __launch_bounds__(256) void k_cpass_final(const double *__restrict__ 
             const int jj = tid >> 2, q = tid & 3;
             const int64_t j = j0 + jj;
             const bool ok = j < n;
-            double x[RPAD / 4];
+            row_update<RPAD, MODE>(xw, Gs, GS, Gi, Cs + jj * CS, r, q);
 #pragma unroll
             for (int t = 0; t < RPAD / 4; ++t) {
                 const int k = 4 * t + q;
-                x[t] = (ok && k < r) ? (double)W[(int64_t)k * n + j] : 0.0;
-            }
-            row_update<RPAD, MODE>(x, Gs, GS, Gi, Cs + jj * CS, r, q);
-#pragma unroll
-            for (int t = 0; t < RPAD / 4; ++t) {
-                const int k = 4 * t + q;
-                const float xf = (ok && k < r) ? (float)x[t] : 0.0f;
+                const float xf = (ok && k < r) ? (float)xw[t] : 0.0f;
                 Wn[jj * CS + k] = (double)xf;
                 if (ok) {
-                    Wt[j * RPAD + k] = xf;
+                    J.Wt[j * RPAD + k] = xf;
                     if (k < r) {
-                        W[(int64_t)k * n + j] = xf;
+                        J.W[(int64_t)k * n + j] = xf;
                         part_cw += Cs[jj * CS + k] * (double)xf;
                     }
                 }
@@ -514,7 +645,7 @@ __global__ __launch_bounds__(256) void k_cpass_final(const double *__restrict__ 
         }
         __syncthreads();
         double part_db = 0.0;
-        double *bout = Bp + (int64_t)blockIdx.x * RPAD * RPAD;
+        double *bout = J.Bp + (int64_t)tile * RPAD * RPAD;
         for (int e = tid; e < RPAD * RPAD; e += 256) {
             const int a = e / RPAD, b = e % RPAD;
             if (a <= b) {
@@ -526,8 +657,18 @@ __global__ __launch_bounds__(256) void k_cpass_final(const double *__restrict__ 
             }
         }
         const double tot = block_sum_f64<256>(part_db - 2.0 * part_cw, red);
-        if (tid == 0) rparts[blockIdx.x] = tot;
+        if (tid == 0) J.rparts[tile] = tot;
     }
+}
+
+template <int RT, int MODE>
+__global__ __launch_bounds__(256) void k_cfinal(const Job *__restrict__ jobs,
+                                                const int *__restrict__ prefix, int njobs) {
+    extern __shared__ double smem[];
+    const int ji = find_job(prefix, njobs, blockIdx.x);
+    const Job &J = jobs[ji];
+    if (J.st->stop) return;
+    cfinal_tile<RT, MODE>(J, tile_of(prefix, njobs, ji, blockIdx.x), smem);
 }
 
 __global__ __launch_bounds__(256) void k_make_wt(const float *__restrict__ W, int64_t n, int r,
@@ -544,8 +685,8 @@ __global__ __launch_bounds__(256) void k_residual(const double *__restrict__ rpa
                                                   const double *__restrict__ Bd, int r,
                                                   const double *__restrict__ normM2, int depth,
                                                   double *__restrict__ log_rel,
-                                                  int32_t *__restrict__ log_depth, int log_idx,
-                                                  int log_cap, DevState *st, double tol) {
+                                                  int32_t *__restrict__ log_depth, int log_cap,
+                                                  DevState *st, double tol) {
     __shared__ double red[4];
     if (st->stop) return;
     const int tid = threadIdx.x;
@@ -559,11 +700,12 @@ __global__ __launch_bounds__(256) void k_residual(const double *__restrict__ rpa
         const double e2 = nm - 2.0 * s1 + s2;
         const double e2c = e2 > 0.0 ? e2 : 0.0;
         const double rel = nm > 0.0 ? sqrt(e2c / nm) : sqrt(e2c);
-        if (log_idx < log_cap) {
-            log_rel[log_idx] = rel;
-            log_depth[log_idx] = depth;
+        const int idx = st->log_len;
+        if (idx < log_cap) {
+            log_rel[idx] = rel;
+            log_depth[idx] = depth;
         }
-        st->log_len = log_idx + 1;
+        st->log_len = idx + 1;
         st->last_rel = rel;
         if (!isfinite(e2)) {
             st->status = NMF_E_NONFINITE;
@@ -575,87 +717,95 @@ __global__ __launch_bounds__(256) void k_residual(const double *__restrict__ rpa
     }
 }
 
-template <int RT, int RW, int WN>
-void apass_launch(int mode, int grid, hipStream_t s, const float *M, int64_t ldm, int64_t m,
-                  int64_t n, const float *Wt, const double *Bd, float *V, float *Aout, int r,
-                  const int32_t *stop) {
-    if (mode == MODE_HALS)
-        k_apass<RT, RW, WN, MODE_HALS><<<grid, 256, 0, s>>>(M, ldm, m, n, Wt, Bd, V, Aout, r, stop);
-    else if (mode == MODE_MU)
-        k_apass<RT, RW, WN, MODE_MU><<<grid, 256, 0, s>>>(M, ldm, m, n, Wt, Bd, V, Aout, r, stop);
-    else
-        k_apass<RT, RW, WN, MODE_STORE><<<grid, 256, 0, s>>>(M, ldm, m, n, Wt, Bd, V, Aout, r, stop);
-}
-
 }  // namespace
 
-int cpass_final_blocks(int64_t n) { return (int)((n + 15) / 16); }
+// ---- host side -------------------------------------------------------------
 
-// Rows per A-pass block: 16-row blocks whose 4 waves split n for small m (the
-// sweep is latency bound there), 64-row blocks of two 32-row groups with two
-// waves each for large m (more reuse of each loaded W value).
 int apass_rows_per_block(int64_t m) { return m >= 32768 ? 64 : 16; }
 
-#define NMF_DISPATCH_RT(rpad, MACRO) \
-    switch (rpad) {                  \
-        case 16: MACRO(1); break;    \
-        case 32: MACRO(2); break;    \
-        case 48: MACRO(3); break;    \
-        case 64: MACRO(4); break;    \
-        default: return hipErrorInvalidValue; \
+size_t apass_lds_bytes(int rpad, int tm, int mode) {
+    const bool upd = mode != MODE_STORE;
+    const int rw = tm == 16 ? 1 : 2;
+    return sizeof(double) * ((upd ? rpad * (rpad + 1) + rpad : 0) + 4 * 16 * rw * (rpad + 1));
+}
+
+size_t cfinal_lds_bytes(int rpad, int mode) {
+    const bool upd = mode != MODE_STORE;
+    return sizeof(double) *
+           ((upd ? rpad * (rpad + 1) + rpad : 0) + 16 * (rpad + 1) * (upd ? 2 : 1) + 4);
+}
+
+// Tile configurations of the A-pass, by rank class and rows per tile: 16-row
+// tiles whose 4 waves split n with deep register batches (small m, latency
+// bound), or 64-row tiles of two 32-row groups with two waves each (large m).
+template <int RT, int MODE>
+static void apass_launch(int tm, const Job *jobs, const int *prefix, int njobs, int blocks,
+                         size_t lds, hipStream_t s) {
+    constexpr int S16 = 4;
+    constexpr int S64 = 4;
+    if (tm == 16) k_apass<RT, 1, 4, S16, MODE><<<blocks, 256, lds, s>>>(jobs, prefix, njobs);
+    else k_apass<RT, 2, 2, S64, MODE><<<blocks, 256, lds, s>>>(jobs, prefix, njobs);
+}
+
+template <int RT>
+static void apass_launch_mode(int mode, int tm, const Job *jobs, const int *prefix, int njobs,
+                              int blocks, size_t lds, hipStream_t s) {
+    if (mode == MODE_HALS) apass_launch<RT, MODE_HALS>(tm, jobs, prefix, njobs, blocks, lds, s);
+    else if (mode == MODE_MU) apass_launch<RT, MODE_MU>(tm, jobs, prefix, njobs, blocks, lds, s);
+    else apass_launch<RT, MODE_STORE>(tm, jobs, prefix, njobs, blocks, lds, s);
+}
+
+hipError_t launch_apass_jobs(int mode, int rpad, int tm, const Job *jobs, const int *prefix,
+                             int njobs, int blocks, size_t lds, hipStream_t s) {
+    if (blocks <= 0) return hipSuccess;
+    switch (rpad) {
+        case 16: apass_launch_mode<1>(mode, tm, jobs, prefix, njobs, blocks, lds, s); break;
+        case 32: apass_launch_mode<2>(mode, tm, jobs, prefix, njobs, blocks, lds, s); break;
+        case 48: apass_launch_mode<3>(mode, tm, jobs, prefix, njobs, blocks, lds, s); break;
+        case 64: apass_launch_mode<4>(mode, tm, jobs, prefix, njobs, blocks, lds, s); break;
+        default: return hipErrorInvalidValue;
     }
-
-hipError_t launch_apass(int rpad, int mode, const float *M, int64_t ldm, int64_t m, int64_t n,
-                        const float *Wt, const double *Bd, float *V, float *Aout, int r,
-                        const int32_t *stop, hipStream_t s) {
-    const int tm = apass_rows_per_block(m);
-    const int grid = (int)((m + tm - 1) / tm);
-    if (grid == 0) return hipSuccess;
-#define L_APASS(RT)                                                                              \
-    if (tm == 16) apass_launch<RT, 1, 4>(mode, grid, s, M, ldm, m, n, Wt, Bd, V, Aout, r, stop); \
-    else apass_launch<RT, 2, 2>(mode, grid, s, M, ldm, m, n, Wt, Bd, V, Aout, r, stop);
-    NMF_DISPATCH_RT(rpad, L_APASS)
-#undef L_APASS
     return hipGetLastError();
 }
 
-hipError_t launch_cpass_partial(int rpad, const float *M, int64_t ldm, int64_t m, int64_t n,
-                                const float *V, int r, int chunks, int64_t chunk, double *Cp,
-                                double *Dp, const int32_t *stop, hipStream_t s) {
-    dim3 grid((unsigned)((n + 63) / 64), (unsigned)chunks);
-    if (grid.x == 0 || grid.y == 0) return hipSuccess;
-#define L_CPART(RT) \
-    k_cpass_partial<RT><<<grid, 256, 0, s>>>(M, ldm, m, n, V, r, chunk, Cp, Dp, stop);
-    NMF_DISPATCH_RT(rpad, L_CPART)
-#undef L_CPART
+hipError_t launch_cpass_jobs(int rpad, const Job *jobs, const int *prefix, int njobs, int blocks,
+                             hipStream_t s) {
+    if (blocks <= 0) return hipSuccess;
+    switch (rpad) {
+        case 16: k_cpass<1, 2><<<blocks, 256, 0, s>>>(jobs, prefix, njobs); break;
+        case 32: k_cpass<2, 2><<<blocks, 256, 0, s>>>(jobs, prefix, njobs); break;
+        case 48: k_cpass<3, 1><<<blocks, 256, 0, s>>>(jobs, prefix, njobs); break;
+        case 64: k_cpass<4, 1><<<blocks, 256, 0, s>>>(jobs, prefix, njobs); break;
+        default: return hipErrorInvalidValue;
+    }
     return hipGetLastError();
 }
 
-hipError_t launch_reduce_gram(const double *parts, int nparts, int rpad, int r, double *Gd,
-                              bool resid, const double *rparts, int nr, const double *normM2,
-                              int depth, double *log_rel, int32_t *log_depth, int log_idx,
-                              int log_cap, DevState *st, double tol, hipStream_t s) {
-    const int grid = (r * r + 255) / 256;
-    k_reduce_gram<<<grid, 256, 0, s>>>(parts, nparts, rpad, r, Gd, resid ? 1 : 0, rparts, nr,
-                                       normM2, depth, log_rel, log_depth, log_idx, log_cap, st,
-                                       tol);
+hipError_t launch_reduce_jobs(int which, const Job *jobs, const int *prefix, int njobs, int blocks,
+                              hipStream_t s) {
+    if (blocks <= 0) return hipSuccess;
+    k_reduce<<<blocks, 256, 0, s>>>(jobs, prefix, njobs, which);
     return hipGetLastError();
 }
 
-hipError_t launch_cpass_final(int rpad, int mode, const double *Cp, int chunks, int64_t n, int r,
-                              const double *Dd, float *W, float *Wt, float *Cout, double *Bp,
-                              double *rparts, const int32_t *stop, hipStream_t s) {
-    const int grid = cpass_final_blocks(n);
-    if (grid == 0) return hipSuccess;
-#define L_CFIN(RT)                                                                          \
-    if (mode == MODE_HALS)                                                                  \
-        k_cpass_final<RT, MODE_HALS><<<grid, 256, 0, s>>>(Cp, chunks, n, r, Dd, W, Wt, Cout, Bp, rparts, stop); \
-    else if (mode == MODE_MU)                                                               \
-        k_cpass_final<RT, MODE_MU><<<grid, 256, 0, s>>>(Cp, chunks, n, r, Dd, W, Wt, Cout, Bp, rparts, stop);   \
-    else                                                                                    \
-        k_cpass_final<RT, MODE_STORE><<<grid, 256, 0, s>>>(Cp, chunks, n, r, Dd, W, Wt, Cout, Bp, rparts, stop);
-    NMF_DISPATCH_RT(rpad, L_CFIN)
-#undef L_CFIN
+template <int RT>
+static void cfinal_launch(int mode, const Job *jobs, const int *prefix, int njobs, int blocks,
+                          size_t lds, hipStream_t s) {
+    if (mode == MODE_HALS) k_cfinal<RT, MODE_HALS><<<blocks, 256, lds, s>>>(jobs, prefix, njobs);
+    else if (mode == MODE_MU) k_cfinal<RT, MODE_MU><<<blocks, 256, lds, s>>>(jobs, prefix, njobs);
+    else k_cfinal<RT, MODE_STORE><<<blocks, 256, lds, s>>>(jobs, prefix, njobs);
+}
+
+hipError_t launch_cfinal_jobs(int mode, int rpad, const Job *jobs, const int *prefix, int njobs,
+                              int blocks, size_t lds, hipStream_t s) {
+    if (blocks <= 0) return hipSuccess;
+    switch (rpad) {
+        case 16: cfinal_launch<1>(mode, jobs, prefix, njobs, blocks, lds, s); break;
+        case 32: cfinal_launch<2>(mode, jobs, prefix, njobs, blocks, lds, s); break;
+        case 48: cfinal_launch<3>(mode, jobs, prefix, njobs, blocks, lds, s); break;
+        case 64: cfinal_launch<4>(mode, jobs, prefix, njobs, blocks, lds, s); break;
+        default: return hipErrorInvalidValue;
+    }
     return hipGetLastError();
 }
 
@@ -668,11 +818,48 @@ hipError_t launch_make_wt(const float *W, int64_t n, int r, int rpad, float *Wt,
 
 hipError_t launch_residual(const double *rparts, int nparts, const double *Dd, const double *Bd,
                            int r, const double *normM2, int depth, double *log_rel,
-                           int32_t *log_depth, int log_idx, int log_cap, DevState *st, double tol,
+                           int32_t *log_depth, int log_cap, DevState *st, double tol,
                            hipStream_t s) {
     k_residual<<<1, 256, 0, s>>>(rparts, nparts, Dd, Bd, r, normM2, depth, log_rel, log_depth,
-                                 log_idx, log_cap, st, tol);
+                                 log_cap, st, tol);
     return hipGetLastError();
+}
+
+int cpass_final_blocks(int64_t n) { return (int)((n + 15) / 16); }
+
+// Allow the sweep kernels the LDS sizes apass_lds_bytes / cfinal_lds_bytes
+// can ask for (above the 64 KB default).
+template <int RT, int MODE>
+static void lds_attr(hipError_t &e) {
+    constexpr int S16 = 4;
+    constexpr int S64 = 4;
+    const int bytes = 160 * 1024;
+    auto set = [&](const void *f) {
+        hipError_t x = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
+        if (x != hipSuccess && e == hipSuccess) e = x;
+    };
+    set((const void *)k_apass<RT, 1, 4, S16, MODE>);
+    set((const void *)k_apass<RT, 2, 2, S64, MODE>);
+    set((const void *)k_cfinal<RT, MODE>);
+}
+
+template <int RT>
+static void lds_attr_modes(hipError_t &e) {
+    lds_attr<RT, MODE_HALS>(e);
+    lds_attr<RT, MODE_MU>(e);
+    lds_attr<RT, MODE_STORE>(e);
+}
+
+hipError_t enable_large_lds() {
+    static hipError_t done = [] {
+        hipError_t e = hipSuccess;
+        lds_attr_modes<1>(e);
+        lds_attr_modes<2>(e);
+        lds_attr_modes<3>(e);
+        lds_attr_modes<4>(e);
+        return e;
+    }();
+    return done;
 }
 
 }  // namespace nmf
