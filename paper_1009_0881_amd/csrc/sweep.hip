@@ -66,37 +66,15 @@ __device__ __forceinline__ int tile_of(const int *prefix, int njobs, int job, in
     return njobs <= 1 ? b : b - prefix[job];
 }
 
-// Broadcast lane QK of every quad (4 consecutive lanes) to the whole quad.
-template <int QK>
-__device__ __forceinline__ double quad_bcast(double v) {
-    constexpr int ctrl = QK | (QK << 2) | (QK << 4) | (QK << 6);   // DPP quad_perm
-    const int lo = __builtin_amdgcn_mov_dpp(__double2loint(v), ctrl, 0xF, 0xF, false);
-    const int hi = __builtin_amdgcn_mov_dpp(__double2hiint(v), ctrl, 0xF, 0xF, false);
+// Broadcast lane N of every row of 16 consecutive lanes to the whole row
+// (DPP row_newbcast).
+template <int N>
+__device__ __forceinline__ double row_bcast(double v) {
+    const int lo = __builtin_amdgcn_mov_dpp(__double2loint(v), 0x150 + N, 0xF, 0xF, false);
+    const int hi = __builtin_amdgcn_mov_dpp(__double2hiint(v), 0x150 + N, 0xF, 0xF, false);
     return __hiloint2double(hi, lo);
 }
 
-__device__ __forceinline__ void wave_lds_fence() {
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-    __builtin_amdgcn_wave_barrier();
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-}
-
-// HALS / MU update of one factor row held by a quad of 4 lanes, lane q
-// holding entries k = q (mod 4).  G is the r x r FP64 Gram of the other
-// factor in LDS (row stride gs, zero-padded to RPAD), gi[k] = 1/G_kk (0 when
-// G_kk = 0), a[k] the matching row of the product (FP64, LDS).  The r x r-sized
-// update arithmetic runs in FP64 (the numerator a_k - sum_l x_l G_lk cancels
-// as the iterate converges); the row is read from and written back to FP32
-// storage by the caller.
-//
-// HALS (Alg. 3): x_k <- max(0, (a_k - sum_{l != k} x_l G_lk) / G_kk) for
-// k = 1..r in order, G_kk = 0 keeping x_k.  Computed in the equivalent
-// gradient form: g = a - G x once, then for each k the owner lane sets
-// x_k <- max(0, x_k + g_k / G_kk), broadcasts the change d to its quad, and
-// every lane applies g_l -= d G_kl for its l > k.  The sequential chain per k
-// is a few FP64 operations and one quad broadcast; the Gram row of step k+1 is
-// loaded during step k.
-// MU (Alg. 2): x_k <- x_k a_k / (sum_l x_l G_lk); a zero denominator keeps x_k.
 // Returns v unchanged, but only once dep has been computed: an empty asm that
 // takes dep as an input orders the instructions that use the result after
 // those that produce dep.  No instruction is emitted.
@@ -105,67 +83,84 @@ __device__ __forceinline__ int ordered_after(int v, double dep) {
     return v;
 }
 
-template <int RPAD, int MODE>
-__device__ __forceinline__ void row_update(double (&x)[RPAD / 4], const double *G, int gs,
-                                           const double *gi, const double *a, int r, int q) {
-    constexpr int NJ = RPAD / 4;
-    double acc[NJ];
+// HALS / MU update of one factor row held by a row of 16 lanes, lane p
+// holding entries k = 16t + p.  G is the r x r FP64 Gram of the other factor
+// in LDS (row stride gs, zero-padded to RPAD), gi[k] = 1/G_kk (0 when
+// G_kk = 0 or k >= r), a[k] the matching row of the product (FP64, LDS).  The
+// r x r-sized update arithmetic runs in FP64 (the numerator
+// a_k - sum_l x_l G_lk cancels as the iterate converges); the row is read from
+// and written back to FP32 storage by the caller.
+//
+// HALS (Alg. 3): x_k <- max(0, (a_k - sum_{l != k} x_l G_lk) / G_kk) for
+// k = 1..r in order, G_kk = 0 keeping x_k.  Computed in the equivalent
+// gradient form: g = a - G x once, then for each k the owner lane sets
+// x_k <- max(0, x_k + g_k / G_kk), broadcasts the change d to its row, and
+// every lane applies g_l -= d G_kl for its l > k.
+// MU (Alg. 2): x_k <- x_k a_k / (sum_l x_l G_lk); a zero denominator keeps x_k.
+template <int RT, int MODE>
+__device__ __forceinline__ void row_update(double (&x)[RT], const double *G, int gs,
+                                           const double *gi, const double *a, int r, int p) {
+    constexpr int RPAD = 16 * RT;
+    double acc[RT];
 #pragma unroll
-    for (int jj = 0; jj < NJ; ++jj) acc[jj] = 0.0;
-    // Padded entries (k >= r) have x_k = 0, zero Gram rows and 1/G_kk = 0, so
-    // the mat-vec skips whole groups of 4 padded entries and the HALS loop runs
-    // over all RPAD entries with no runtime bound.
-    static_for<RPAD / 4>([&](auto lg_c) {      // acc_k = sum_l x_l G_lk, 4 l per group
+    for (int t = 0; t < RT; ++t) acc[t] = 0.0;
+    // acc_k = sum_l x_l G_lk.  Padded entries (k >= r) have x_k = 0, zero Gram
+    // rows and 1/G_kk = 0: the mat-vec skips whole groups of 4 of them, the
+    // HALS loop runs over all RPAD entries with no runtime bound.
+    static_for<RPAD / 4>([&](auto lg_c) {
         constexpr int lg = decltype(lg_c)::value;
         if (4 * lg < r) {
             static_for<4>([&](auto lq_c) {
                 constexpr int l = 4 * lg + decltype(lq_c)::value;
-                const double xl = quad_bcast<l % 4>(x[lg]);
-                const double *gr = G + l * gs + q;
+                const double xl = row_bcast<l % 16>(x[l / 16]);
+                const double *gr = G + l * gs + p;
 #pragma unroll
-                for (int jj = 0; jj < NJ; ++jj) acc[jj] = fma(xl, gr[4 * jj], acc[jj]);
+                for (int t = 0; t < RT; ++t) acc[t] = fma(xl, gr[16 * t], acc[t]);
             });
         }
     });
     if constexpr (MODE == MODE_HALS) {
-        double g[NJ], ginv[NJ], row0[NJ], row1[NJ];
+        double g[RT], ginv[RT], row0[RT], row1[RT];
 #pragma unroll
-        for (int jj = 0; jj < NJ; ++jj) {
-            const int k = 4 * jj + q;
-            g[jj] = k < r ? a[k] - acc[jj] : 0.0;
-            ginv[jj] = gi[k];
-            row0[jj] = G[q + 4 * jj];                   // Gram row 0
-            row1[jj] = G[gs + q + 4 * jj];              // Gram row 1
+        for (int t = 0; t < RT; ++t) {
+            const int k = 16 * t + p;
+            g[t] = k < r ? a[k] - acc[t] : 0.0;
+            ginv[t] = gi[k];
+            row0[t] = G[k];                  // Gram row 0
+            row1[t] = G[gs + k];             // Gram row 1
         }
+        // Each step loads the Gram row of step k+2 behind ordered_after() on
+        // the previous step's broadcast: loads run two steps ahead, hiding LDS
+        // latency, and the compiler cannot hoist all of them (and spill).
         double dprev = acc[0];
         static_for<RPAD>([&](auto k_c) {
-            constexpr int k = decltype(k_c)::value, kk = k / 4, qk = k % 4;
-            double row2[NJ];                            // Gram row k+2, two steps ahead
+            constexpr int k = decltype(k_c)::value, kt = k / 16, pk = k % 16;
+            double row2[RT];
             if constexpr (k + 2 < RPAD) {
-                const double *gr = G + ordered_after((k + 2) * gs + q, dprev);
+                const double *gr = G + ordered_after((k + 2) * gs + p, dprev);
 #pragma unroll
-                for (int jj = (k + 2) / 4; jj < NJ; ++jj) row2[jj] = gr[4 * jj];
+                for (int t = (k + 2) / 16; t < RT; ++t) row2[t] = gr[16 * t];
             }
-            const bool own = q == qk && ginv[kk] > 0.0;
-            const double cand = fmax(0.0, fma(g[kk], ginv[kk], x[kk]));
-            double d = own ? cand - x[kk] : 0.0;
-            x[kk] = own ? cand : x[kk];
-            d = quad_bcast<qk>(d);
+            const bool own = p == pk && ginv[kt] > 0.0;
+            const double cand = fmax(0.0, fma(g[kt], ginv[kt], x[kt]));
+            double d = own ? cand - x[kt] : 0.0;
+            x[kt] = own ? cand : x[kt];
+            d = row_bcast<pk>(d);
             dprev = d;
-            g[kk] = q > qk ? fma(-d, row0[kk], g[kk]) : g[kk];
+            g[kt] = p > pk ? fma(-d, row0[kt], g[kt]) : g[kt];
 #pragma unroll
-            for (int jj = kk + 1; jj < NJ; ++jj) g[jj] = fma(-d, row0[jj], g[jj]);
+            for (int t = kt + 1; t < RT; ++t) g[t] = fma(-d, row0[t], g[t]);
 #pragma unroll
-            for (int jj = (k + 1) / 4; jj < NJ; ++jj) {
-                row0[jj] = row1[jj];
-                if constexpr (k + 2 < RPAD) row1[jj] = row2[jj];
+            for (int t = (k + 1) / 16; t < RT; ++t) {
+                row0[t] = row1[t];
+                if constexpr (k + 2 < RPAD) row1[t] = row2[t];
             }
         });
     } else {
 #pragma unroll
-        for (int jj = 0; jj < NJ; ++jj) {
-            const int k = 4 * jj + q;
-            if (k < r && acc[jj] > 0.0) x[jj] = x[jj] * a[k] / acc[jj];
+        for (int t = 0; t < RT; ++t) {
+            const int k = 16 * t + p;
+            if (k < r && acc[t] > 0.0) x[t] = x[t] * a[k] / acc[t];
         }
     }
 }
@@ -291,19 +286,17 @@ __device__ void apass_tile(const Job &J, int tile, double *smem) {
                 for (int t = 0; t < RT; ++t) two_sum_acc(hi[q][t], lo[q][t], acc[q][t]);
         }
     };
-    // factor row of the epilogue (4 lanes per row, rows tid/4 + 64i)
-    constexpr int EPR = (TM + 63) / 64;
-    double xv[UPD ? EPR : 1][RPAD / 4];
+    // factor rows of the epilogue: 16 lanes per row, rows tid/16 + 16i
+    constexpr int EPR = TM / 16;
+    double xv[UPD ? EPR : 1][RT];
     if constexpr (UPD) {
 #pragma unroll
         for (int i = 0; i < EPR; ++i) {
-            const int er = (tid >> 2) + 64 * i;
-            const int64_t vrow = brow + er;
-            const bool ok = er < TM && vrow < m;
+            const int64_t vrow = brow + (tid >> 4) + 16 * i;
 #pragma unroll
-            for (int jj = 0; jj < RPAD / 4; ++jj) {
-                const int k = 4 * jj + (tid & 3);
-                xv[i][jj] = (ok && k < r) ? (double)J.V[vrow + (int64_t)k * m] : 0.0;
+            for (int t = 0; t < RT; ++t) {
+                const int k = 16 * t + (tid & 15);
+                xv[i][t] = (vrow < m && k < r) ? (double)J.V[vrow + (int64_t)k * m] : 0.0;
             }
         }
     }
@@ -349,17 +342,14 @@ __device__ void apass_tile(const Job &J, int tile, double *smem) {
     } else {
 #pragma unroll
         for (int i = 0; i < EPR; ++i) {
-            const int er = (tid >> 2) + 64 * i;
-            if (er < TM) {      // whole quads and whole waves take this branch together
-                const int q = tid & 3;
-                const int64_t vrow = brow + er;
-                row_update<RPAD, MODE>(xv[i], Gs, GS, Gi, arow(er), r, q);
-                if (vrow < m) {
+            const int er = (tid >> 4) + 16 * i, p = tid & 15;
+            const int64_t vrow = brow + er;
+            row_update<RT, MODE>(xv[i], Gs, GS, Gi, arow(er), r, p);
+            if (vrow < m) {
 #pragma unroll
-                    for (int jj = 0; jj < RPAD / 4; ++jj) {
-                        const int k = 4 * jj + q;
-                        if (k < r) J.V[vrow + (int64_t)k * m] = (float)xv[i][jj];
-                    }
+                for (int t = 0; t < RT; ++t) {
+                    const int k = 16 * t + p;
+                    if (k < r) J.V[vrow + (int64_t)k * m] = (float)xv[i][t];
                 }
             }
         }
@@ -598,13 +588,14 @@ __device__ void cfinal_tile(const Job &J, int tile, double *smem) {
     const int64_t n = J.n;
     const int r = J.r;
     const int64_t j0 = (int64_t)tile * 16;
-    double xw[RPAD / 4];
+    // factor columns of the update: 16 lanes per column, column j0 + tid/16
+    double xw[RT];
     if constexpr (UPD) {
-        const int64_t j = j0 + (tid >> 2);
+        const int64_t j = j0 + (tid >> 4);
 #pragma unroll
-        for (int t = 0; t < RPAD / 4; ++t) {
-            const int k = 4 * t + (tid & 3);
-            xw[t] = (tid < 64 && j < n && k < r) ? (double)J.W[(int64_t)k * n + j] : 0.0;
+        for (int t = 0; t < RT; ++t) {
+            const int k = 16 * t + (tid & 15);
+            xw[t] = (j < n && k < r) ? (double)J.W[(int64_t)k * n + j] : 0.0;
         }
     }
     for (int e = tid; e < 16 * RPAD; e += 256) {
@@ -624,14 +615,14 @@ __device__ void cfinal_tile(const Job &J, int tile, double *smem) {
         }
     } else {
         double part_cw = 0.0;
-        if (tid < 64) {
-            const int jj = tid >> 2, q = tid & 3;
+        {
+            const int jj = tid >> 4, p = tid & 15;
             const int64_t j = j0 + jj;
             const bool ok = j < n;
-            row_update<RPAD, MODE>(xw, Gs, GS, Gi, Cs + jj * CS, r, q);
+            row_update<RT, MODE>(xw, Gs, GS, Gi, Cs + jj * CS, r, p);
 #pragma unroll
-            for (int t = 0; t < RPAD / 4; ++t) {
-                const int k = 4 * t + q;
+            for (int t = 0; t < RT; ++t) {
+                const int k = 16 * t + p;
                 const float xf = (ok && k < r) ? (float)xw[t] : 0.0f;
                 Wn[jj * CS + k] = (double)xf;
                 if (ok) {
