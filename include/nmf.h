@@ -175,6 +175,32 @@ nmf_status nmf_profile(nmf_plan_t plan, uint32_t mask);
 nmf_status nmf_profile_read(nmf_plan_t plan, int64_t *counts, double *total_ms, int32_t cap,
                             int32_t reset);
 
+/* ---- batched solves ---------------------------------------------------------
+ * Many independent solves (each its own plan: uneven m, n, r, levels, cycle,
+ * budget and tolerance; HALS or MU) advanced together: every tick, each
+ * unfinished problem performs its pending V transfers and one sweep at its
+ * current level, and the work of all problems is issued as one launch per
+ * phase and tile configuration (rank class r padded to 16/32/48/64, A-pass
+ * tile rows, update rule).  A problem's arithmetic is exactly that of
+ * nmf_solve on its own plan, so its V, W and result are bitwise those of a
+ * single solve.
+ *
+ * nmf_batch_workspace: bytes of the one device workspace of a batch over
+ * these plans (their own workspaces, 256-byte aligned, back to back, then the
+ * executor's tables).  nmf_solve_batch: dM[i], dV[i], dW[i], iters[i] as in
+ * nmf_solve for problem i; hOut (count entries, may be null) receives the
+ * results.  flags: NMF_BATCH_GRAPH captures a steady tick (the same problems
+ * at the same levels as the tick before) into a hipGraph and replays it while
+ * the configuration lasts; the batch then runs on a stream of its own that
+ * first waits for `stream`.  Returns after the stream has synchronised.
+ * Errors: NMF_E_ARG (null pointer, negative iters, unaligned workspace, an
+ * ANLS plan), or the first failing problem's status (results still filled). */
+#define NMF_BATCH_GRAPH 1
+nmf_status nmf_batch_workspace(const nmf_plan_t *plans, int32_t count, size_t *bytes);
+nmf_status nmf_solve_batch(const nmf_plan_t *plans, int32_t count, const float *const *dM,
+                           float *const *dV, float *const *dW, const int32_t *iters,
+                           void *dWorkspace, void *stream, int32_t flags, nmf_result *hOut);
+
 #ifdef __cplusplus
 }
 #endif

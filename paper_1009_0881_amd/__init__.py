@@ -39,8 +39,10 @@ EXPORTS = [
     "nmf_plan", "nmf_solve", "nmf_destroy", "nmf_status_string", "nmf_last_error",
     "nmf_query_levels", "nmf_query_schedule", "nmf_query_log",
     "nmf_restrict", "nmf_prolong", "nmf_iterate", "nmf_products", "nmf_gram",
-    "nmf_profile", "nmf_profile_read",
+    "nmf_profile", "nmf_profile_read", "nmf_batch_workspace", "nmf_solve_batch",
 ]
+
+BATCH_GRAPH = 1
 
 # Kernel kinds of the event profiler (include/nmf.h).
 KERNEL_KINDS = ["apass", "gram_v", "cpass_partial", "cpass_final", "gram_w", "residual",
@@ -107,6 +109,10 @@ def lib() -> ctypes.CDLL:
         L.nmf_profile_read.argtypes = [vp, ctypes.POINTER(i64), ctypes.POINTER(ctypes.c_double),
                                        i32, i32]
         L.nmf_gram.argtypes = [i32, i64, vp, i64, vp, vp, sz, vp]
+        L.nmf_batch_workspace.argtypes = [ctypes.POINTER(vp), i32, ctypes.POINTER(sz)]
+        L.nmf_solve_batch.argtypes = [ctypes.POINTER(vp), i32, ctypes.POINTER(vp),
+                                      ctypes.POINTER(vp), ctypes.POINTER(vp),
+                                      ctypes.POINTER(i32), vp, vp, i32, ctypes.POINTER(Result)]
         for name in EXPORTS:
             if name not in ("nmf_status_string", "nmf_last_error"):
                 getattr(L, name).restype = i32
@@ -278,6 +284,38 @@ def gram(X, stream=None):
     ws = torch.empty(parts * rpad * rpad * 8 + 256, dtype=torch.uint8, device=X.device)
     _check(lib().nmf_gram(r, L, _ptr(X), L, _ptr(G), _ptr(ws), ws.numel(), _stream_handle(stream)))
     return G
+
+
+def batch_workspace(plans):
+    """Device workspace (uint8 tensor) of a batch over these plans."""
+    torch = _torch()
+    hs = (ctypes.c_void_p * len(plans))(*[p.handle for p in plans])
+    nb = ctypes.c_size_t()
+    _check(lib().nmf_batch_workspace(hs, len(plans), ctypes.byref(nb)))
+    return torch.empty(max(256, nb.value), dtype=torch.uint8, device="cuda")
+
+
+def solve_batch(plans, Ms, Vs, Ws, iters, workspace=None, graph=False, stream=None):
+    """Solve len(plans) independent problems in one batch (nmf_solve_batch).
+
+    Ms[i], Vs[i], Ws[i] as for Plan.solve (V, W updated in place); iters is an
+    int or one budget per problem.  Returns one result dict per problem."""
+    k = len(plans)
+    _need_cuda(*Ms, *Vs, *Ws)
+    if isinstance(iters, int):
+        iters = [iters] * k
+    ws = workspace if workspace is not None else batch_workspace(plans)
+    vp = ctypes.c_void_p
+    hs = (vp * k)(*[p.handle for p in plans])
+    pm = (vp * k)(*[M.data_ptr() for M in Ms])
+    pv = (vp * k)(*[V.data_ptr() for V in Vs])
+    pw = (vp * k)(*[W.data_ptr() for W in Ws])
+    it = (ctypes.c_int32 * k)(*[int(x) for x in iters])
+    res = (Result * k)()
+    st = lib().nmf_solve_batch(hs, k, pm, pv, pw, it, _ptr(ws), _stream_handle(stream),
+                               BATCH_GRAPH if graph else 0, res)
+    _check(st)
+    return [r.as_dict() for r in res]
 
 
 # ------------------------------------------------------------ array helpers

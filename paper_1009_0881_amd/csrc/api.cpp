@@ -3,17 +3,13 @@
 #include <cstring>
 #include <new>
 
-#include "nmf_internal.h"
-
-struct nmf_plan_s {
-    nmf::Plan p;
-};
+#include "exec.h"
 
 namespace nmf {
 
 namespace {
-
 thread_local std::string g_err;
+}  // namespace
 
 nmf_status fail(nmf_plan_t plan, nmf_status st, const std::string &msg) {
     if (plan) plan->p.err = msg;
@@ -21,35 +17,7 @@ nmf_status fail(nmf_plan_t plan, nmf_status st, const std::string &msg) {
     return st;
 }
 
-#define NMF_HIP(call)                                                                      \
-    do {                                                                                   \
-        hipError_t e_ = (call);                                                            \
-        if (e_ != hipSuccess)                                                              \
-            return fail(plan, NMF_E_DEVICE, std::string(#call) + ": " + hipGetErrorString(e_)); \
-    } while (0)
-
-// Pointers into one workspace, for one solve.
-struct Ctx {
-    nmf_plan_t plan;
-    const Plan *p;
-    hipStream_t s;
-    char *ws;
-    DevState *st;
-    const int32_t *stop;
-    double *log_rel;
-    int32_t *log_depth;
-    double *norm;
-    double *Bd, *Dd, *gparts, *rparts;
-    float *Bf, *Df, *A, *C, *Wt;
-    double *Cp, *Dp, *Bp;
-    std::vector<const float *> M;
-    std::vector<int64_t> ldm;
-    std::vector<float *> V;
-    float *W;
-    Job *djobs;                   // device copy of `jobs` (workspace)
-    std::vector<Job> jobs;        // one job per level
-    std::vector<int8_t> depths;   // depth of every executed iteration (host mirror)
-};
+namespace {
 
 template <class T>
 T *at(char *base, size_t off) {
@@ -96,6 +64,8 @@ void prof_collect(nmf_plan_t plan) {
         prof_end(c.plan, c.s, pi_);                         \
     } while (0)
 
+}  // namespace
+
 Ctx make_ctx(nmf_plan_t plan, const float *dM, float *dV, float *dW, void *dws, hipStream_t s) {
     const Plan &p = plan->p;
     plan->p.prof.pending_kind.clear();
@@ -109,6 +79,7 @@ Ctx make_ctx(nmf_plan_t plan, const float *dM, float *dV, float *dW, void *dws, 
     c.log_rel = at<double>(c.ws, p.ws.off_log);
     c.log_depth = at<int32_t>(c.ws, p.ws.off_logdepth);
     c.norm = at<double>(c.ws, p.ws.off_norm);
+    c.nparts = at<double>(c.ws, p.ws.off_nparts);
     c.Bd = at<double>(c.ws, p.ws.off_Bd);
     c.Dd = at<double>(c.ws, p.ws.off_Dd);
     c.Bf = at<float>(c.ws, p.ws.off_Bf);
@@ -174,6 +145,32 @@ Ctx make_ctx(nmf_plan_t plan, const float *dM, float *dV, float *dW, void *dws, 
     return c;
 }
 
+nmf_status result_from_state(nmf_plan_t plan, const DevState &hs,
+                             const std::vector<int8_t> &depths, nmf_result *out) {
+    if (out) {
+        memset(out, 0, sizeof *out);
+        const int n = hs.log_len;
+        out->log_len = n < plan->p.d.log_cap ? n : plan->p.d.log_cap;
+        out->total_iters = n;
+        out->stopped = hs.stopped;
+        out->rel_err = hs.last_rel;
+        for (int i = 0; i < n && i < (int)depths.size(); ++i) {
+            if (depths[i] == 0) out->fine_iters++;
+            double f = 1.0;
+            for (int k = 0; k < depths[i]; ++k) f *= 0.25;
+            out->fine_equiv += f;
+        }
+    }
+    if (hs.status != 0)
+        return fail(plan, (nmf_status)hs.status, "non-finite residual during the solve");
+    if (hs.flags & 4)
+        return fail(plan, NMF_E_NONFINITE,
+                    "NNLS met a non-positive pivot (collinear or singular Gram)");
+    return NMF_OK;
+}
+
+namespace {
+
 nmf_status upload_jobs(Ctx &c) {
     nmf_plan_t plan = c.plan;
     NMF_HIP(enable_large_lds());
@@ -191,6 +188,18 @@ nmf_status gram_W(Ctx &c) {
     return NMF_OK;
 }
 
+// Start of a solve: Wt (transposed, zero-padded W) and B = W W^T from the
+// W tile kernel's partials, reduced in fixed order.  The batch executor runs
+// the same two kernels, so single and batched solves agree bitwise.
+nmf_status init_w(Ctx &c) {
+    nmf_plan_t plan = c.plan;
+    const Job &J = c.jobs[0];
+    NMF_LAUNCH(K_GRAM_W, launch_cfinal_jobs(3, J.rpad, c.djobs, nullptr, J.nF,
+                                            cfinal_lds_bytes(J.rpad, 3), c.s));
+    NMF_LAUNCH(K_GRAM_W, launch_reduce_jobs(2, c.djobs, nullptr, J.nG, c.s));
+    return NMF_OK;
+}
+
 // One iteration of the inner algorithm at depth d, then the residual.
 nmf_status sweep(Ctx &c, int d) {
     nmf_plan_t plan = c.plan;
@@ -201,13 +210,13 @@ nmf_status sweep(Ctx &c, int d) {
     const int64_t n = p.d.n;
     int32_t *flags = &c.st->flags;
     const int mode = p.d.algo == NMF_HALS ? 0 : (p.d.algo == NMF_MU ? 1 : 2);
-    NMF_LAUNCH(K_APASS, launch_apass_jobs(mode, J.rpad, J.tm, dj, nullptr, 1, J.nA,
+    NMF_LAUNCH(K_APASS, launch_apass_jobs(mode, J.rpad, J.tm, dj, nullptr, J.nA,
                                           apass_lds_bytes(J.rpad, J.tm, mode), c.s));
     if (mode == 2)
         NMF_LAUNCH(K_NNLS_ROWS, launch_nnls_rows(p.rpad, c.Bd, c.A, J.m, r, J.V, flags, c.stop, c.s));
-    NMF_LAUNCH(K_CPART, launch_cpass_jobs(J.rpad, dj, nullptr, 1, J.nC, c.s));
-    NMF_LAUNCH(K_GRAM_V, launch_reduce_jobs(0, dj, nullptr, 1, J.nG, c.s));
-    NMF_LAUNCH(K_CFINAL, launch_cfinal_jobs(mode, J.rpad, dj, nullptr, 1, J.nF,
+    NMF_LAUNCH(K_CPART, launch_cpass_jobs(J.rpad, dj, nullptr, J.nC, c.s));
+    NMF_LAUNCH(K_GRAM_V, launch_reduce_jobs(0, dj, nullptr, J.nG, c.s));
+    NMF_LAUNCH(K_CFINAL, launch_cfinal_jobs(mode, J.rpad, dj, nullptr, J.nF,
                                             cfinal_lds_bytes(J.rpad, mode), c.s));
     if (mode == 2) {
         NMF_LAUNCH(K_NNLS_COLS, launch_nnls_cols(p.rpad, c.Dd, c.C, n, r, c.W, c.Wt, c.rparts,
@@ -218,7 +227,7 @@ nmf_status sweep(Ctx &c, int d) {
                                             d, c.log_rel, c.log_depth, p.d.log_cap, c.st,
                                             p.d.tol, c.s));
     } else {
-        NMF_LAUNCH(K_GRAM_W, launch_reduce_jobs(1, dj, nullptr, 1, J.nG, c.s));
+        NMF_LAUNCH(K_GRAM_W, launch_reduce_jobs(1, dj, nullptr, J.nG, c.s));
     }
     c.depths.push_back((int8_t)d);
     return NMF_OK;
@@ -235,8 +244,9 @@ nmf_status prepare_levels(Ctx &c) {
                                                const_cast<float *>(c.M[l]), nullptr, c.s));
     }
     for (size_t l = 0; l < p.lv.size(); ++l) {
-        NMF_LAUNCH(K_SUMSQ,
-                   launch_sumsq(c.M[l], c.ldm[l], p.lv[l].m, p.d.n, c.rparts, 1024, c.norm + l, c.s));
+        NMF_LAUNCH(K_SUMSQ, launch_sumsq(c.M[l], c.ldm[l], p.lv[l].m, p.d.n,
+                                         c.nparts + l * kNormParts, norm_parts(p.lv[l].m, p.d.n),
+                                         c.norm + l, c.s));
     }
     return NMF_OK;
 }
@@ -266,26 +276,7 @@ nmf_status finish(Ctx &c, nmf_result *out) {
     nmf_status st = read_state(c, hs);
     if (st != NMF_OK) return st;
     prof_collect(plan);
-    if (out) {
-        memset(out, 0, sizeof *out);
-        const int n = hs.log_len;
-        out->log_len = n < c.p->d.log_cap ? n : c.p->d.log_cap;
-        out->total_iters = n;
-        out->stopped = hs.stopped;
-        out->rel_err = hs.last_rel;
-        for (int i = 0; i < n && i < (int)c.depths.size(); ++i) {
-            if (c.depths[i] == 0) out->fine_iters++;
-            double f = 1.0;
-            for (int k = 0; k < c.depths[i]; ++k) f *= 0.25;
-            out->fine_equiv += f;
-        }
-    }
-    if (hs.status != 0)
-        return fail(plan, hs.status, "non-finite residual during the solve");
-    if (hs.flags & 4)
-        return fail(plan, NMF_E_NONFINITE,
-                    "NNLS met a non-positive pivot (collinear or singular Gram)");
-    return NMF_OK;
+    return result_from_state(plan, hs, c.depths, out);
 }
 
 }  // namespace
@@ -380,9 +371,8 @@ nmf_status nmf_solve(nmf_plan_t plan, const float *dM, float *dV, float *dW, int
     nmf_status st;
     if (p.d.check_input && (st = check_input(c)) != NMF_OK) return st;
     if ((st = prepare_levels(c)) != NMF_OK) return st;
-    if ((st = gram_W(c)) != NMF_OK) return st;
-    NMF_HIP(launch_make_wt(c.W, p.d.n, p.d.r, p.rpad, c.Wt, s));
     if ((st = upload_jobs(c)) != NMF_OK) return st;
+    if ((st = init_w(c)) != NMF_OK) return st;
 
     const bool use_tol = p.d.tol > 0.0;
     const int ce = p.d.check_every;
@@ -456,9 +446,8 @@ nmf_status nmf_iterate(nmf_plan_t plan, const float *dM, float *dV, float *dW, i
     NMF_HIP(launch_state_reset(c.st, s));
     nmf_status st;
     if ((st = prepare_levels(c)) != NMF_OK) return st;
-    if ((st = gram_W(c)) != NMF_OK) return st;
-    NMF_HIP(launch_make_wt(c.W, plan->p.d.n, plan->p.d.r, plan->p.rpad, c.Wt, s));
     if ((st = upload_jobs(c)) != NMF_OK) return st;
+    if ((st = init_w(c)) != NMF_OK) return st;
     for (int i = 0; i < count; ++i)
         if ((st = sweep(c, 0)) != NMF_OK) return st;
     nmf_result res;
@@ -504,10 +493,10 @@ nmf_status nmf_products(nmf_plan_t plan, const float *dM, const float *dV, const
     NMF_HIP(launch_make_wt(dW, p.d.n, p.d.r, p.rpad, c.Wt, s));
     nmf_status st = upload_jobs(c);
     if (st != NMF_OK) return st;
-    NMF_HIP(launch_apass_jobs(2, J.rpad, J.tm, c.djobs, nullptr, 1, J.nA,
+    NMF_HIP(launch_apass_jobs(2, J.rpad, J.tm, c.djobs, nullptr, J.nA,
                               apass_lds_bytes(J.rpad, J.tm, 2), s));
-    NMF_HIP(launch_cpass_jobs(J.rpad, c.djobs, nullptr, 1, J.nC, s));
-    NMF_HIP(launch_cfinal_jobs(2, J.rpad, c.djobs, nullptr, 1, J.nF, cfinal_lds_bytes(J.rpad, 2), s));
+    NMF_HIP(launch_cpass_jobs(J.rpad, c.djobs, nullptr, J.nC, s));
+    NMF_HIP(launch_cfinal_jobs(2, J.rpad, c.djobs, nullptr, J.nF, cfinal_lds_bytes(J.rpad, 2), s));
     NMF_HIP(hipStreamSynchronize(s));
     return NMF_OK;
 }

@@ -1,0 +1,100 @@
+// Batch / serving executor (batch.cpp): many independent solves advanced in
+// lock-step ticks with one grouped launch per phase.
+#pragma once
+
+#include <map>
+#include <tuple>
+#include <vector>
+
+#include "exec.h"
+
+namespace nmf {
+
+// Device area of an executor, after the problems' own workspaces.
+struct BatchArea {
+    size_t off_stptr;    // DevState* of every slot (for the state gather)
+    size_t off_gather;   // gathered DevState copies
+    size_t off_arena;    // job tables and block maps, bump-allocated
+    size_t arena_cap;
+    size_t end;
+};
+
+size_t batch_table_bytes(const nmf_plan_t *plans, int count);
+BatchArea batch_area_layout(size_t base, int capacity, size_t table_bytes);
+
+class Executor {
+public:
+    Executor(char *base, const BatchArea &area, int capacity, hipStream_t s, bool graphs);
+    ~Executor();
+    Executor(const Executor &) = delete;
+    Executor &operator=(const Executor &) = delete;
+
+    // Queue a problem (schedule budget `iters`) with its own workspace `dws`;
+    // it starts on the next tick.  `id` is the caller's handle.
+    nmf_status add(nmf_plan_t plan, const float *dM, float *dV, float *dW, int32_t iters,
+                   void *dws, int id);
+    // One unit of work for every active problem.
+    nmf_status tick();
+    nmf_status poll();
+    bool all_done() const;
+    bool empty() const { return insts_.empty(); }
+    // Results of the finished problems (all problems when only_done is false).
+    nmf_status results(std::vector<int> &ids, std::vector<nmf_result> &res,
+                       std::vector<nmf_status> &status, bool only_done);
+    void remove(int id);
+    int64_t ticks() const { return ticks_; }
+
+private:
+    struct Inst {
+        int id = 0;
+        nmf_plan_t plan = nullptr;
+        Ctx c;
+        std::vector<Step> sched;
+        size_t cur = 0;
+        int left = -1;        // iterations left in the run step at `cur`
+        int stage = 0;        // 0 schedule, 1 fine iterations after it, 2 done
+        int cont_left = 0;
+        int since_check = 0;
+        int depth = 0;
+        int mode = 0;         // 0 HALS, 1 MU
+        bool use_tol = false;
+    };
+    struct G {
+        int rpad, tm, mode;
+        const Job *dj;
+        const int2 *bA, *bC, *bG, *bF;
+        int nA, nC, nG, nF;
+    };
+
+    template <class T>
+    nmf_status upload(const std::vector<T> &v, const T **out);
+    nmf_status sync_reset();
+    nmf_status setup_fresh();
+    void advance(Inst &I, std::vector<Step> &xfers);
+    nmf_status launch_xfers(std::vector<std::pair<Inst *, std::vector<Step>>> &todo);
+    nmf_status launch_sweeps(const std::vector<Inst *> &active, bool capture_ok);
+    nmf_status gather(std::vector<DevState> &hs);
+    int slot_of(int id) const;
+    void drop_graph();
+
+    char *base_;
+    BatchArea area_;
+    int capacity_;
+    hipStream_t s_;
+    bool use_graph_;
+    DevState **dstptr_;
+    DevState *dgather_;
+    char *arena_;
+    size_t arena_off_ = 0;
+    int64_t generation_ = 0;
+    int64_t ticks_ = 0;
+    std::vector<std::vector<char>> staged_;
+    std::map<std::vector<int64_t>, G> cache_;
+    std::vector<Inst> insts_;
+    std::vector<int> fresh_;
+    std::vector<int64_t> last_key_, graph_key_;
+    hipGraphExec_t gexec_ = nullptr;
+    int stable_ticks_ = 0;
+};
+
+}  // namespace nmf

@@ -1,0 +1,55 @@
+// Host executor internals shared by the single-solve entry points and the
+// batch / serving executor: per-solve device pointers, error and profiling
+// helpers, and the building blocks of a solve (level preparation, one sweep).
+#pragma once
+
+#include <string>
+#include <vector>
+
+#include "nmf_internal.h"
+
+struct nmf_plan_s {
+    nmf::Plan p;
+};
+
+namespace nmf {
+
+nmf_status fail(nmf_plan_t plan, nmf_status st, const std::string &msg);
+
+#define NMF_HIP(call)                                                                      \
+    do {                                                                                   \
+        hipError_t e_ = (call);                                                            \
+        if (e_ != hipSuccess)                                                              \
+            return fail(plan, NMF_E_DEVICE, std::string(#call) + ": " + hipGetErrorString(e_)); \
+    } while (0)
+
+// Pointers into one workspace, for one solve.
+struct Ctx {
+    nmf_plan_t plan;
+    const Plan *p;
+    hipStream_t s;
+    char *ws;
+    DevState *st;
+    const int32_t *stop;
+    double *log_rel;
+    int32_t *log_depth;
+    double *norm;
+    double *nparts;               // norm partials, kNormParts per level
+    double *Bd, *Dd, *gparts, *rparts;
+    float *Bf, *Df, *A, *C, *Wt;
+    double *Cp, *Dp, *Bp;
+    std::vector<const float *> M;
+    std::vector<int64_t> ldm;
+    std::vector<float *> V;
+    float *W;
+    Job *djobs;                   // device copy of `jobs` (workspace)
+    std::vector<Job> jobs;        // one job per level
+    std::vector<int8_t> depths;   // depth of every executed iteration (host mirror)
+};
+
+Ctx make_ctx(nmf_plan_t plan, const float *dM, float *dV, float *dW, void *dws, hipStream_t s);
+// Fill an nmf_result from the final device state and the host depth log.
+nmf_status result_from_state(nmf_plan_t plan, const DevState &hs,
+                             const std::vector<int8_t> &depths, nmf_result *out);
+
+}  // namespace nmf

@@ -16,6 +16,14 @@ namespace nmf {
 
 constexpr int kMaxRank = 64;
 constexpr int kMaxLevels = 12;
+constexpr int kNormParts = 1024;   // max partial sums of ||M_l||^2 (per level)
+
+// Number of partial sums of ||X||^2 for a rows x ncols matrix (work items are
+// (column, 2048-row chunk)); every path uses this split, so norms agree bitwise.
+inline int norm_parts(int64_t rows, int64_t ncols) {
+    const int64_t items = ncols * ((rows + 2047) / 2048);
+    return (int)(items < 1 ? 1 : (items > kNormParts ? kNormParts : items));
+}
 
 // Device-side control block at the start of every workspace.
 struct DevState {
@@ -48,7 +56,7 @@ struct Step {            // one schedule entry
 };
 
 struct Workspace {
-    size_t off_state, off_log, off_logdepth, off_norm;
+    size_t off_state, off_log, off_logdepth, off_norm, off_nparts;
     size_t off_Bd, off_Bf, off_Dd, off_Df;
     size_t off_gparts, off_cparts, off_rparts, off_A, off_C, off_V0bf;
     size_t off_Wt, off_Dp, off_Bp, off_jobs;
@@ -102,19 +110,49 @@ hipError_t launch_gram(int rpad, int r, int64_t L, const float *X, int64_t ldx, 
                        int64_t chunk, double *gparts, double *Gd, float *Gf, const int32_t *stop,
                        hipStream_t s);
 
-// Job-table sweep kernels (job.h): one launch per phase over `njobs` jobs;
-// prefix[i] = first block of job i (may be null when njobs == 1).
-// mode: 0 HALS, 1 MU, 2 store the product (ANLS).
+// Job-table sweep kernels (job.h): one launch per phase over the jobs of a
+// table; block b works on tile bmap[b].y of job bmap[b].x (bmap null: job 0,
+// tile b).  mode: 0 HALS, 1 MU, 2 store the product (ANLS), 3 (W tile kernel
+// only) initialise: Wt and the W W^T partials from the current W, no update.
 // All jobs of one launch share rpad (and tm for the A-pass).
-hipError_t launch_apass_jobs(int mode, int rpad, int tm, const Job *jobs, const int *prefix,
-                             int njobs, int blocks, size_t lds, hipStream_t s);
-hipError_t launch_cpass_jobs(int rpad, const Job *jobs, const int *prefix, int njobs, int blocks,
+hipError_t launch_apass_jobs(int mode, int rpad, int tm, const Job *jobs, const int2 *bmap,
+                             int blocks, size_t lds, hipStream_t s);
+hipError_t launch_cpass_jobs(int rpad, const Job *jobs, const int2 *bmap, int blocks,
                              hipStream_t s);
-// which = 0: V^T V from the C-pass partials; 1: W W^T and the residual log.
-hipError_t launch_reduce_jobs(int which, const Job *jobs, const int *prefix, int njobs, int blocks,
+// which = 0: V^T V from the C-pass partials; 1: W W^T and the residual log;
+// 2: W W^T only.
+hipError_t launch_reduce_jobs(int which, const Job *jobs, const int2 *bmap, int blocks,
                               hipStream_t s);
-hipError_t launch_cfinal_jobs(int mode, int rpad, const Job *jobs, const int *prefix, int njobs,
-                              int blocks, size_t lds, hipStream_t s);
+hipError_t launch_cfinal_jobs(int mode, int rpad, const Job *jobs, const int2 *bmap, int blocks,
+                              size_t lds, hipStream_t s);
+
+// Grouped setup kernels for batches (one launch over many problems).
+struct XferJob {             // restrict (kind 1) or prolong (kind 2) of ncols images
+    const float *X;          // source, column stride ldx
+    int64_t ldx;
+    float *Y;                // destination, contiguous columns
+    int32_t h, w;            // fine grid
+    int32_t kind, xfer;
+    int64_t ncols;
+    const int32_t *stop;     // skip when *stop (may be null)
+};
+// bmap[b] = (job, tile): tile t covers 256 output pixels (t % pt) of columns
+// 16 * (t / pt) .. +15, pt = tiles per column of that job.
+hipError_t launch_xfer_many(const XferJob *jobs, const int2 *bmap, int blocks, hipStream_t s);
+struct NormJob {             // ||X||_F^2 in FP64 of a rows x ncols matrix
+    const float *X;
+    int64_t ld, rows, ncols;
+    double *parts;           // nparts partial sums
+    int32_t nparts;
+    double *out;
+};
+// Two launches: partials (blocks = sum of nparts, bmap as above), then one
+// block per job adds its partials in index order.
+hipError_t launch_norms_many(const NormJob *jobs, const int2 *bmap, int blocks, int njobs,
+                             hipStream_t s);
+hipError_t launch_state_reset_many(DevState *const *states, int count, hipStream_t s);
+hipError_t launch_gather_states(DevState *const *states, int count, DevState *out,
+                                hipStream_t s);
 int apass_rows_per_block(int64_t m);
 size_t apass_lds_bytes(int rpad, int tm, int mode);
 size_t cfinal_lds_bytes(int rpad, int mode);

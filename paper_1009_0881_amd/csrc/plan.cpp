@@ -176,6 +176,7 @@ nmf_status build_plan(const nmf_desc &d0, Plan &p, std::string &err) {
     ws.off_log = take(sizeof(double) * d.log_cap);
     ws.off_logdepth = take(sizeof(int32_t) * d.log_cap);
     ws.off_norm = take(sizeof(double) * d.levels);
+    ws.off_nparts = take(sizeof(double) * kNormParts * d.levels);
     ws.off_Bd = take(sizeof(double) * rr);
     ws.off_Dd = take(sizeof(double) * rr);
     ws.off_Bf = take(sizeof(float) * rr);

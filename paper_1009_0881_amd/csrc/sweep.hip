@@ -8,9 +8,9 @@
 //              residual terms
 //   k_reduce   B = W W^T, plus rel_err = sqrt(||M||^2 - 2<C,W> + <D,B>)/||M||
 //
-// Every kernel takes a job table (one entry per problem and level, see job.h):
-// block b of a launch works on tile b - prefix[i] of job i, so one launch per
-// phase serves a single solve or a whole batch of uneven problems.
+// Every kernel takes a job table (one entry per problem and level, see job.h)
+// and a block map: block b works on tile bmap[b].y of job bmap[b].x, so one
+// launch per phase serves a single solve or a whole batch of uneven problems.
 //
 // Both products run on the FP32 matrix cores (v_mfma_f32_16x16x4f32); the
 // Gram V^T V on the FP64 ones (v_mfma_f64_16x16x4f64).  Lane layout on a
@@ -24,8 +24,8 @@
 // chain (the HALS numerator a_k - sum_l x_l G_lk cancels and would amplify
 // that error).
 //
-// Factor updates: one factor row (a row of V, or a column of W) is owned by 4
-// consecutive lanes, lane q holding the entries k = q (mod 4).  HALS walks
+// Factor updates: one factor row (a row of V, or a column of W) is owned by 16
+// consecutive lanes, lane p holding the entries k = p (mod 16).  HALS walks
 // k = 1..r in order using already-updated entries (Gauss-Seidel, Alg. 3);
 // MU updates all entries from the old values (Alg. 2).
 
@@ -41,7 +41,7 @@ namespace {
 
 typedef double v4d __attribute__((ext_vector_type(4)));
 
-constexpr int MODE_HALS = 0, MODE_MU = 1, MODE_STORE = 2;
+constexpr int MODE_HALS = 0, MODE_MU = 1, MODE_STORE = 2, MODE_INIT = 3;
 
 template <int N, int I = 0, class F>
 __device__ __forceinline__ void static_for(F &&f) {
@@ -51,19 +51,10 @@ __device__ __forceinline__ void static_for(F &&f) {
     }
 }
 
-__device__ __forceinline__ int find_job(const int *prefix, int njobs, int b) {
-    if (njobs <= 1) return 0;
-    int lo = 0, hi = njobs;
-    while (hi - lo > 1) {
-        const int mid = (lo + hi) >> 1;
-        if (prefix[mid] <= b) lo = mid;
-        else hi = mid;
-    }
-    return lo;
-}
-
-__device__ __forceinline__ int tile_of(const int *prefix, int njobs, int job, int b) {
-    return njobs <= 1 ? b : b - prefix[job];
+// (job, tile) of this block: entry blockIdx.x of the launch's block map, or
+// (0, blockIdx.x) for a launch over a single job (null map).
+__device__ __forceinline__ int2 block_job(const int2 *bmap) {
+    return bmap ? bmap[blockIdx.x] : make_int2(0, (int)blockIdx.x);
 }
 
 // Broadcast lane N of every row of 16 consecutive lanes to the whole row
@@ -358,12 +349,12 @@ __device__ void apass_tile(const Job &J, int tile, double *smem) {
 
 template <int RT, int RW, int WN, int S, int MODE>
 __global__ __launch_bounds__(256) void k_apass(const Job *__restrict__ jobs,
-                                               const int *__restrict__ prefix, int njobs) {
+                                               const int2 *__restrict__ bmap) {
     extern __shared__ double smem[];
-    const int ji = find_job(prefix, njobs, blockIdx.x);
-    const Job &J = jobs[ji];
+    const int2 jt = block_job(bmap);
+    const Job &J = jobs[jt.x];
     if (J.st->stop) return;
-    apass_tile<RT, RW, WN, S, MODE>(J, tile_of(prefix, njobs, ji, blockIdx.x), smem);
+    apass_tile<RT, RW, WN, S, MODE>(J, jt.y, smem);
 }
 
 // ---------------------------------------------------------------------------
@@ -507,11 +498,11 @@ __device__ void cpass_tile(const Job &J, int tx, int ty, int ntx) {
 
 template <int RT, int SB>
 __global__ __launch_bounds__(256) void k_cpass(const Job *__restrict__ jobs,
-                                               const int *__restrict__ prefix, int njobs) {
-    const int ji = find_job(prefix, njobs, blockIdx.x);
-    const Job &J = jobs[ji];
+                                               const int2 *__restrict__ bmap) {
+    const int2 jt = block_job(bmap);
+    const Job &J = jobs[jt.x];
     if (J.st->stop) return;
-    const int tile = tile_of(prefix, njobs, ji, blockIdx.x);
+    const int tile = jt.y;
     cpass_tile<RT, SB>(J, tile % J.nCx, tile / J.nCx, J.nCx);
 }
 
@@ -524,24 +515,24 @@ __global__ __launch_bounds__(256) void k_cpass(const Job *__restrict__ jobs,
 // logs rel_err and sets the stop flag.
 // ---------------------------------------------------------------------------
 __global__ __launch_bounds__(256) void k_reduce(const Job *__restrict__ jobs,
-                                                const int *__restrict__ prefix, int njobs,
+                                                const int2 *__restrict__ bmap,
                                                 int which) {
     __shared__ double red[4];
-    const int ji = find_job(prefix, njobs, blockIdx.x);
-    const Job &J = jobs[ji];
+    const int2 jt = block_job(bmap);
+    const Job &J = jobs[jt.x];
     if (J.st->stop) return;
-    const int tile = tile_of(prefix, njobs, ji, blockIdx.x);
+    const int tile = jt.y;
     const int r = J.r, rpad = J.rpad;
     const int e = tile * 256 + threadIdx.x;
     const double *parts = which ? J.Bp : J.Dp;
-    const int nparts = which ? J.nF : J.chunks;
+    const int nparts = which ? J.nF : J.chunks;   // which 2: W W^T only (start of a solve)
     if (e < r * r) {
         const int a = e / r, b = e % r;
         const int ua = a < b ? a : b, ub = a < b ? b : a;
         const double s = sum_strided(parts + ua * rpad + ub, (int64_t)rpad * rpad, nparts);
         (which ? J.Bd : J.Dd)[e] = s;
     }
-    if (which && tile == 0) {
+    if (which == 1 && tile == 0) {
         double s = 0.0;
         for (int i = threadIdx.x; i < J.nF; i += 256) s += J.rparts[i];
         s = block_sum_f64<256>(s, red);
@@ -578,19 +569,20 @@ __global__ __launch_bounds__(256) void k_reduce(const Job *__restrict__ jobs,
 template <int RT, int MODE>
 __device__ void cfinal_tile(const Job &J, int tile, double *smem) {
     constexpr int RPAD = RT * 16, GS = RPAD + 1, CS = RPAD + 1;
-    constexpr bool UPD = MODE != MODE_STORE;
+    constexpr bool UPD = MODE == MODE_HALS || MODE == MODE_MU;
+    constexpr bool INIT = MODE == MODE_INIT;     // no C, no update: Wt and W W^T partials
     double *Gs = smem;
     double *Gi = Gs + (UPD ? RPAD * GS : 0);
     double *Cs = Gi + (UPD ? RPAD : 0);
-    double *Wn = Cs + 16 * CS;
-    double *red = Wn + (UPD ? 16 * CS : 0);
+    double *Wn = Cs + (INIT ? 0 : 16 * CS);
+    double *red = Wn + (MODE == MODE_STORE ? 0 : 16 * CS);
     const int tid = threadIdx.x;
     const int64_t n = J.n;
     const int r = J.r;
     const int64_t j0 = (int64_t)tile * 16;
     // factor columns of the update: 16 lanes per column, column j0 + tid/16
     double xw[RT];
-    if constexpr (UPD) {
+    if constexpr (MODE != MODE_STORE) {
         const int64_t j = j0 + (tid >> 4);
 #pragma unroll
         for (int t = 0; t < RT; ++t) {
@@ -598,15 +590,17 @@ __device__ void cfinal_tile(const Job &J, int tile, double *smem) {
             xw[t] = (j < n && k < r) ? (double)J.W[(int64_t)k * n + j] : 0.0;
         }
     }
-    for (int e = tid; e < 16 * RPAD; e += 256) {
-        const int jj = e & 15, k = e >> 4;
-        const int64_t j = j0 + jj;
-        double s = 0.0;
-        if (k < r && j < n) s = sum_strided(J.Cp + (int64_t)k * n + j, (int64_t)r * n, J.chunks);
-        Cs[jj * CS + k] = s;
+    if constexpr (!INIT) {
+        for (int e = tid; e < 16 * RPAD; e += 256) {
+            const int jj = e & 15, k = e >> 4;
+            const int64_t j = j0 + jj;
+            double s = 0.0;
+            if (k < r && j < n) s = sum_strided(J.Cp + (int64_t)k * n + j, (int64_t)r * n, J.chunks);
+            Cs[jj * CS + k] = s;
+        }
     }
     if constexpr (UPD) load_gram<RPAD>(J.Dd, r, Gs, GS, Gi);
-    __syncthreads();
+    if constexpr (!INIT) __syncthreads();
     if constexpr (MODE == MODE_STORE) {
         for (int e = tid; e < 16 * r; e += 256) {
             const int jj = e & 15, k = e >> 4;
@@ -619,7 +613,7 @@ __device__ void cfinal_tile(const Job &J, int tile, double *smem) {
             const int jj = tid >> 4, p = tid & 15;
             const int64_t j = j0 + jj;
             const bool ok = j < n;
-            row_update<RT, MODE>(xw, Gs, GS, Gi, Cs + jj * CS, r, p);
+            if constexpr (UPD) row_update<RT, MODE>(xw, Gs, GS, Gi, Cs + jj * CS, r, p);
 #pragma unroll
             for (int t = 0; t < RT; ++t) {
                 const int k = 16 * t + p;
@@ -627,7 +621,7 @@ __device__ void cfinal_tile(const Job &J, int tile, double *smem) {
                 Wn[jj * CS + k] = (double)xf;
                 if (ok) {
                     J.Wt[j * RPAD + k] = xf;
-                    if (k < r) {
+                    if (UPD && k < r) {
                         J.W[(int64_t)k * n + j] = xf;
                         part_cw += Cs[jj * CS + k] * (double)xf;
                     }
@@ -644,22 +638,24 @@ __device__ void cfinal_tile(const Job &J, int tile, double *smem) {
 #pragma unroll
                 for (int jj = 0; jj < 16; ++jj) s = fma(Wn[jj * CS + a], Wn[jj * CS + b], s);
                 bout[a * RPAD + b] = s;
-                part_db += (a == b ? 1.0 : 2.0) * Gs[a * GS + b] * s;
+                if constexpr (UPD) part_db += (a == b ? 1.0 : 2.0) * Gs[a * GS + b] * s;
             }
         }
-        const double tot = block_sum_f64<256>(part_db - 2.0 * part_cw, red);
-        if (tid == 0) J.rparts[tile] = tot;
+        if constexpr (UPD) {
+            const double tot = block_sum_f64<256>(part_db - 2.0 * part_cw, red);
+            if (tid == 0) J.rparts[tile] = tot;
+        }
     }
 }
 
 template <int RT, int MODE>
 __global__ __launch_bounds__(256) void k_cfinal(const Job *__restrict__ jobs,
-                                                const int *__restrict__ prefix, int njobs) {
+                                                const int2 *__restrict__ bmap) {
     extern __shared__ double smem[];
-    const int ji = find_job(prefix, njobs, blockIdx.x);
-    const Job &J = jobs[ji];
+    const int2 jt = block_job(bmap);
+    const Job &J = jobs[jt.x];
     if (J.st->stop) return;
-    cfinal_tile<RT, MODE>(J, tile_of(prefix, njobs, ji, blockIdx.x), smem);
+    cfinal_tile<RT, MODE>(J, jt.y, smem);
 }
 
 __global__ __launch_bounds__(256) void k_make_wt(const float *__restrict__ W, int64_t n, int r,
@@ -721,80 +717,83 @@ size_t apass_lds_bytes(int rpad, int tm, int mode) {
 }
 
 size_t cfinal_lds_bytes(int rpad, int mode) {
-    const bool upd = mode != MODE_STORE;
-    return sizeof(double) *
-           ((upd ? rpad * (rpad + 1) + rpad : 0) + 16 * (rpad + 1) * (upd ? 2 : 1) + 4);
+    const bool upd = mode == MODE_HALS || mode == MODE_MU;
+    const size_t g = upd ? (size_t)rpad * (rpad + 1) + rpad : 0;     // Gram and 1/G_kk
+    const size_t c = mode == MODE_INIT ? 0 : 16 * (size_t)(rpad + 1);  // C rows
+    const size_t w = mode == MODE_STORE ? 0 : 16 * (size_t)(rpad + 1); // new W rows
+    return sizeof(double) * (g + c + w + 4);
 }
 
 // Tile configurations of the A-pass, by rank class and rows per tile: 16-row
 // tiles whose 4 waves split n with deep register batches (small m, latency
 // bound), or 64-row tiles of two 32-row groups with two waves each (large m).
 template <int RT, int MODE>
-static void apass_launch(int tm, const Job *jobs, const int *prefix, int njobs, int blocks,
+static void apass_launch(int tm, const Job *jobs, const int2 *bmap, int blocks,
                          size_t lds, hipStream_t s) {
     constexpr int S16 = 4;
     constexpr int S64 = 4;
-    if (tm == 16) k_apass<RT, 1, 4, S16, MODE><<<blocks, 256, lds, s>>>(jobs, prefix, njobs);
-    else k_apass<RT, 2, 2, S64, MODE><<<blocks, 256, lds, s>>>(jobs, prefix, njobs);
+    if (tm == 16) k_apass<RT, 1, 4, S16, MODE><<<blocks, 256, lds, s>>>(jobs, bmap);
+    else k_apass<RT, 2, 2, S64, MODE><<<blocks, 256, lds, s>>>(jobs, bmap);
 }
 
 template <int RT>
-static void apass_launch_mode(int mode, int tm, const Job *jobs, const int *prefix, int njobs,
+static void apass_launch_mode(int mode, int tm, const Job *jobs, const int2 *bmap,
                               int blocks, size_t lds, hipStream_t s) {
-    if (mode == MODE_HALS) apass_launch<RT, MODE_HALS>(tm, jobs, prefix, njobs, blocks, lds, s);
-    else if (mode == MODE_MU) apass_launch<RT, MODE_MU>(tm, jobs, prefix, njobs, blocks, lds, s);
-    else apass_launch<RT, MODE_STORE>(tm, jobs, prefix, njobs, blocks, lds, s);
+    if (mode == MODE_HALS) apass_launch<RT, MODE_HALS>(tm, jobs, bmap, blocks, lds, s);
+    else if (mode == MODE_MU) apass_launch<RT, MODE_MU>(tm, jobs, bmap, blocks, lds, s);
+    else apass_launch<RT, MODE_STORE>(tm, jobs, bmap, blocks, lds, s);
 }
 
-hipError_t launch_apass_jobs(int mode, int rpad, int tm, const Job *jobs, const int *prefix,
-                             int njobs, int blocks, size_t lds, hipStream_t s) {
+hipError_t launch_apass_jobs(int mode, int rpad, int tm, const Job *jobs, const int2 *bmap,
+                             int blocks, size_t lds, hipStream_t s) {
     if (blocks <= 0) return hipSuccess;
     switch (rpad) {
-        case 16: apass_launch_mode<1>(mode, tm, jobs, prefix, njobs, blocks, lds, s); break;
-        case 32: apass_launch_mode<2>(mode, tm, jobs, prefix, njobs, blocks, lds, s); break;
-        case 48: apass_launch_mode<3>(mode, tm, jobs, prefix, njobs, blocks, lds, s); break;
-        case 64: apass_launch_mode<4>(mode, tm, jobs, prefix, njobs, blocks, lds, s); break;
+        case 16: apass_launch_mode<1>(mode, tm, jobs, bmap, blocks, lds, s); break;
+        case 32: apass_launch_mode<2>(mode, tm, jobs, bmap, blocks, lds, s); break;
+        case 48: apass_launch_mode<3>(mode, tm, jobs, bmap, blocks, lds, s); break;
+        case 64: apass_launch_mode<4>(mode, tm, jobs, bmap, blocks, lds, s); break;
         default: return hipErrorInvalidValue;
     }
     return hipGetLastError();
 }
 
-hipError_t launch_cpass_jobs(int rpad, const Job *jobs, const int *prefix, int njobs, int blocks,
+hipError_t launch_cpass_jobs(int rpad, const Job *jobs, const int2 *bmap, int blocks,
                              hipStream_t s) {
     if (blocks <= 0) return hipSuccess;
     switch (rpad) {
-        case 16: k_cpass<1, 2><<<blocks, 256, 0, s>>>(jobs, prefix, njobs); break;
-        case 32: k_cpass<2, 2><<<blocks, 256, 0, s>>>(jobs, prefix, njobs); break;
-        case 48: k_cpass<3, 1><<<blocks, 256, 0, s>>>(jobs, prefix, njobs); break;
-        case 64: k_cpass<4, 1><<<blocks, 256, 0, s>>>(jobs, prefix, njobs); break;
+        case 16: k_cpass<1, 2><<<blocks, 256, 0, s>>>(jobs, bmap); break;
+        case 32: k_cpass<2, 2><<<blocks, 256, 0, s>>>(jobs, bmap); break;
+        case 48: k_cpass<3, 1><<<blocks, 256, 0, s>>>(jobs, bmap); break;
+        case 64: k_cpass<4, 1><<<blocks, 256, 0, s>>>(jobs, bmap); break;
         default: return hipErrorInvalidValue;
     }
     return hipGetLastError();
 }
 
-hipError_t launch_reduce_jobs(int which, const Job *jobs, const int *prefix, int njobs, int blocks,
+hipError_t launch_reduce_jobs(int which, const Job *jobs, const int2 *bmap, int blocks,
                               hipStream_t s) {
     if (blocks <= 0) return hipSuccess;
-    k_reduce<<<blocks, 256, 0, s>>>(jobs, prefix, njobs, which);
+    k_reduce<<<blocks, 256, 0, s>>>(jobs, bmap, which);
     return hipGetLastError();
 }
 
 template <int RT>
-static void cfinal_launch(int mode, const Job *jobs, const int *prefix, int njobs, int blocks,
+static void cfinal_launch(int mode, const Job *jobs, const int2 *bmap, int blocks,
                           size_t lds, hipStream_t s) {
-    if (mode == MODE_HALS) k_cfinal<RT, MODE_HALS><<<blocks, 256, lds, s>>>(jobs, prefix, njobs);
-    else if (mode == MODE_MU) k_cfinal<RT, MODE_MU><<<blocks, 256, lds, s>>>(jobs, prefix, njobs);
-    else k_cfinal<RT, MODE_STORE><<<blocks, 256, lds, s>>>(jobs, prefix, njobs);
+    if (mode == MODE_HALS) k_cfinal<RT, MODE_HALS><<<blocks, 256, lds, s>>>(jobs, bmap);
+    else if (mode == MODE_MU) k_cfinal<RT, MODE_MU><<<blocks, 256, lds, s>>>(jobs, bmap);
+    else if (mode == MODE_INIT) k_cfinal<RT, MODE_INIT><<<blocks, 256, lds, s>>>(jobs, bmap);
+    else k_cfinal<RT, MODE_STORE><<<blocks, 256, lds, s>>>(jobs, bmap);
 }
 
-hipError_t launch_cfinal_jobs(int mode, int rpad, const Job *jobs, const int *prefix, int njobs,
+hipError_t launch_cfinal_jobs(int mode, int rpad, const Job *jobs, const int2 *bmap,
                               int blocks, size_t lds, hipStream_t s) {
     if (blocks <= 0) return hipSuccess;
     switch (rpad) {
-        case 16: cfinal_launch<1>(mode, jobs, prefix, njobs, blocks, lds, s); break;
-        case 32: cfinal_launch<2>(mode, jobs, prefix, njobs, blocks, lds, s); break;
-        case 48: cfinal_launch<3>(mode, jobs, prefix, njobs, blocks, lds, s); break;
-        case 64: cfinal_launch<4>(mode, jobs, prefix, njobs, blocks, lds, s); break;
+        case 16: cfinal_launch<1>(mode, jobs, bmap, blocks, lds, s); break;
+        case 32: cfinal_launch<2>(mode, jobs, bmap, blocks, lds, s); break;
+        case 48: cfinal_launch<3>(mode, jobs, bmap, blocks, lds, s); break;
+        case 64: cfinal_launch<4>(mode, jobs, bmap, blocks, lds, s); break;
         default: return hipErrorInvalidValue;
     }
     return hipGetLastError();
@@ -839,6 +838,9 @@ static void lds_attr_modes(hipError_t &e) {
     lds_attr<RT, MODE_HALS>(e);
     lds_attr<RT, MODE_MU>(e);
     lds_attr<RT, MODE_STORE>(e);
+    hipError_t x = hipFuncSetAttribute((const void *)k_cfinal<RT, MODE_INIT>,
+                                       hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
+    if (x != hipSuccess && e == hipSuccess) e = x;
 }
 
 hipError_t enable_large_lds() {

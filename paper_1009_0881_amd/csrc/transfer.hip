@@ -74,29 +74,33 @@ __device__ __forceinline__ Taps prolong_taps(int f, int Nc, int xfer) {
     return t;
 }
 
+// One output pixel of a separable transfer: sum_a ty_a sum_b tx_b img[iy_a * rowlen + ix_b],
+// accumulated in FP64 in tap order.
+__device__ __forceinline__ float stencil(const float *img, int rowlen, const Taps &ty,
+                                         const Taps &tx) {
+    double acc = 0.0;
+    for (int a = 0; a < ty.cnt; ++a) {
+        double row = 0.0;
+        for (int b = 0; b < tx.cnt; ++b) row += tx.wt[b] * (double)img[(int64_t)ty.idx[a] * rowlen + tx.idx[b]];
+        acc += ty.wt[a] * row;
+    }
+    return (float)acc;
+}
+
 __global__ __launch_bounds__(256) void k_restrict(const float *__restrict__ X, int64_t ldx,
                                                   float *__restrict__ Y, int h, int w, int hc,
                                                   int wc, int64_t ncols, int xfer,
                                                   const int32_t *stop) {
     if (stopped(stop)) return;
-    const int64_t mc = (int64_t)hc * wc;
-    const int64_t total = mc * ncols;
-    for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < total;
-         e += (int64_t)gridDim.x * blockDim.x) {
-        const int64_t col = e / mc;
-        const int p = (int)(e - col * mc);
-        const int cy = p / wc, cx = p - (p / wc) * wc;
+    // grid: x over coarse pixels, y over columns (strided); 32-bit pixel math
+    const int mc = hc * wc;
+    const int p = blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= mc) return;
+    const int cy = p / wc, cx = p - cy * wc;
+    for (int64_t col = blockIdx.y; col < ncols; col += gridDim.y) {
         const Taps ty = restrict_taps(cy, h, xfer);
         const Taps tx = restrict_taps(cx, w, xfer);
-        const float *img = X + col * ldx;
-        double acc = 0.0;
-        for (int a = 0; a < ty.cnt; ++a) {
-            double row = 0.0;
-            for (int b = 0; b < tx.cnt; ++b)
-                row += tx.wt[b] * (double)img[(int64_t)ty.idx[a] * w + tx.idx[b]];
-            acc += ty.wt[a] * row;
-        }
-        Y[col * mc + p] = (float)acc;
+        Y[col * mc + p] = stencil(X + col * ldx, w, ty, tx);
     }
 }
 
@@ -105,42 +109,44 @@ __global__ __launch_bounds__(256) void k_prolong(const float *__restrict__ Y,
                                                  int wc, int64_t ncols, int xfer,
                                                  const int32_t *stop) {
     if (stopped(stop)) return;
-    const int64_t mf = (int64_t)h * w;
-    const int64_t mc = (int64_t)hc * wc;
-    const int64_t total = mf * ncols;
-    for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < total;
-         e += (int64_t)gridDim.x * blockDim.x) {
-        const int64_t col = e / mf;
-        const int p = (int)(e - col * mf);
-        const int y = p / w, x = p - (p / w) * w;
+    // grid: x over fine pixels, y over columns (strided); 32-bit pixel math
+    const int mf = h * w, mc = hc * wc;
+    const int p = blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= mf) return;
+    const int y = p / w, x = p - y * w;
+    for (int64_t col = blockIdx.y; col < ncols; col += gridDim.y) {
         const Taps ty = prolong_taps(y, hc, xfer);
         const Taps tx = prolong_taps(x, wc, xfer);
-        const float *img = Y + col * mc;
-        double acc = 0.0;
-        for (int a = 0; a < ty.cnt; ++a) {
-            double row = 0.0;
-            for (int b = 0; b < tx.cnt; ++b)
-                row += tx.wt[b] * (double)img[(int64_t)ty.idx[a] * wc + tx.idx[b]];
-            acc += ty.wt[a] * row;
-        }
-        X[col * mf + p] = (float)acc;
+        X[col * mf + p] = stencil(Y + col * mc, wc, ty, tx);
     }
 }
 
 // Sum of squares of a column-major matrix in FP64: per-block partials, then a
 // single block adds them in index order (deterministic).
+// Partial part (of nparts) of ||X||_F^2: work items (column, 2048-row chunk),
+// part p takes items p, p + nparts, ...
+__device__ __forceinline__ double sumsq_part(const float *X, int64_t ld, int64_t rows,
+                                             int64_t ncols, int part, int nparts) {
+    constexpr int64_t CH = 2048;
+    const int64_t nrc = (rows + CH - 1) / CH;
+    double acc = 0.0;
+    for (int64_t it = part; it < ncols * nrc; it += nparts) {
+        const int64_t c = it / nrc, r0 = (it - c * nrc) * CH;
+        const int64_t r1 = r0 + CH < rows ? r0 + CH : rows;
+        const float *col = X + c * ld;
+        for (int64_t i = r0 + threadIdx.x; i < r1; i += 256) {
+            const double v = col[i];
+            acc += v * v;
+        }
+    }
+    return acc;
+}
+
 __global__ __launch_bounds__(256) void k_sumsq_partial(const float *__restrict__ X, int64_t ld,
                                                        int64_t rows, int64_t ncols,
                                                        double *__restrict__ parts) {
     __shared__ double scratch[4];
-    const int64_t total = rows * ncols;
-    double acc = 0.0;
-    for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < total;
-         e += (int64_t)gridDim.x * blockDim.x) {
-        const int64_t c = e / rows;
-        const double v = X[c * ld + (e - c * rows)];
-        acc += v * v;
-    }
+    double acc = sumsq_part(X, ld, rows, ncols, blockIdx.x, gridDim.x);
     acc = block_sum_f64<256>(acc, scratch);
     if (threadIdx.x == 0) parts[blockIdx.x] = acc;
 }
@@ -180,6 +186,67 @@ __global__ void k_state_reset(DevState *st) {
     }
 }
 
+// ---- grouped setup kernels (one launch over many problems) ------------------
+
+__global__ __launch_bounds__(256) void k_xfer_many(const XferJob *__restrict__ jobs,
+                                                   const int2 *__restrict__ bmap) {
+    const int2 jt = bmap[blockIdx.x];
+    const XferJob &J = jobs[jt.x];
+    if (stopped(J.stop)) return;
+    const int hc = (J.h + 1) / 2, wc = (J.w + 1) / 2;
+    const bool down = J.kind == 1;
+    const int ho = down ? hc : J.h, wo = down ? wc : J.w;
+    const int mo = ho * wo;
+    const int pt = (mo + 255) / 256;
+    const int p = (jt.y % pt) * 256 + threadIdx.x;
+    if (p >= mo) return;
+    const int64_t c0 = (int64_t)(jt.y / pt) * 16;
+    const int y = p / wo, x = p - y * wo;
+    const Taps ty = down ? restrict_taps(y, J.h, J.xfer) : prolong_taps(y, hc, J.xfer);
+    const Taps tx = down ? restrict_taps(x, J.w, J.xfer) : prolong_taps(x, wc, J.xfer);
+    const int rowlen = down ? J.w : wc;
+    for (int64_t col = c0; col < c0 + 16 && col < J.ncols; ++col)
+        J.Y[col * mo + p] = stencil(J.X + col * J.ldx, rowlen, ty, tx);
+}
+
+__global__ __launch_bounds__(256) void k_norm_parts_many(const NormJob *__restrict__ jobs,
+                                                         const int2 *__restrict__ bmap) {
+    __shared__ double scratch[4];
+    const int2 jt = bmap[blockIdx.x];
+    const NormJob &J = jobs[jt.x];
+    double acc = sumsq_part(J.X, J.ld, J.rows, J.ncols, jt.y, J.nparts);
+    acc = block_sum_f64<256>(acc, scratch);
+    if (threadIdx.x == 0) J.parts[jt.y] = acc;
+}
+
+__global__ __launch_bounds__(256) void k_norm_final_many(const NormJob *__restrict__ jobs) {
+    __shared__ double scratch[4];
+    const NormJob &J = jobs[blockIdx.x];
+    double acc = 0.0;
+    for (int i = threadIdx.x; i < J.nparts; i += 256) acc += J.parts[i];
+    acc = block_sum_f64<256>(acc, scratch);
+    if (threadIdx.x == 0) *J.out = acc;
+}
+
+__global__ void k_state_reset_many(DevState *const *__restrict__ sts, int count) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < count) {
+        DevState *st = sts[i];
+        st->stop = 0;
+        st->log_len = 0;
+        st->status = 0;
+        st->stopped = 0;
+        st->last_rel = 0.0;
+        st->flags = 0;
+    }
+}
+
+__global__ void k_gather_states(DevState *const *__restrict__ sts, int count,
+                                DevState *__restrict__ out) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < count) out[i] = *sts[i];
+}
+
 inline int grid_for(int64_t total, int cap = 8192) {
     int64_t g = (total + 255) / 256;
     if (g < 1) g = 1;
@@ -192,18 +259,20 @@ inline int grid_for(int64_t total, int cap = 8192) {
 hipError_t launch_restrict(int xfer, int h, int w, int64_t ncols, const float *X, int64_t ldx,
                            float *Y, const int32_t *stop, hipStream_t s) {
     const int hc = (h + 1) / 2, wc = (w + 1) / 2;
-    const int64_t total = (int64_t)hc * wc * ncols;
-    if (total == 0) return hipSuccess;
-    k_restrict<<<grid_for(total, 65536), 256, 0, s>>>(X, ldx, Y, h, w, hc, wc, ncols, xfer, stop);
+    const int mc = hc * wc;
+    if (mc == 0 || ncols == 0) return hipSuccess;
+    const dim3 grid((mc + 255) / 256, (unsigned)std::min<int64_t>(ncols, 65535));
+    k_restrict<<<grid, 256, 0, s>>>(X, ldx, Y, h, w, hc, wc, ncols, xfer, stop);
     return hipGetLastError();
 }
 
 hipError_t launch_prolong(int xfer, int h, int w, int64_t ncols, const float *Y, float *X,
                           const int32_t *stop, hipStream_t s) {
     const int hc = (h + 1) / 2, wc = (w + 1) / 2;
-    const int64_t total = (int64_t)h * w * ncols;
-    if (total == 0) return hipSuccess;
-    k_prolong<<<grid_for(total, 65536), 256, 0, s>>>(Y, X, h, w, hc, wc, ncols, xfer, stop);
+    const int mf = h * w;
+    if (mf == 0 || ncols == 0) return hipSuccess;
+    const dim3 grid((mf + 255) / 256, (unsigned)std::min<int64_t>(ncols, 65535));
+    k_prolong<<<grid, 256, 0, s>>>(Y, X, h, w, hc, wc, ncols, xfer, stop);
     return hipGetLastError();
 }
 
@@ -219,6 +288,35 @@ hipError_t launch_sumsq(const float *X, int64_t ld, int64_t rows, int64_t ncols,
 hipError_t launch_check_input(const float *M, int64_t ld, int64_t m, int64_t n, int32_t *flags,
                               hipStream_t s) {
     k_check_input<<<grid_for(m * n, 4096), 256, 0, s>>>(M, ld, m, n, flags);
+    return hipGetLastError();
+}
+
+hipError_t launch_xfer_many(const XferJob *jobs, const int2 *bmap, int blocks, hipStream_t s) {
+    if (blocks <= 0) return hipSuccess;
+    k_xfer_many<<<blocks, 256, 0, s>>>(jobs, bmap);
+    return hipGetLastError();
+}
+
+hipError_t launch_norms_many(const NormJob *jobs, const int2 *bmap, int blocks, int njobs,
+                             hipStream_t s) {
+    if (njobs <= 0) return hipSuccess;
+    k_norm_parts_many<<<blocks, 256, 0, s>>>(jobs, bmap);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    k_norm_final_many<<<njobs, 256, 0, s>>>(jobs);
+    return hipGetLastError();
+}
+
+hipError_t launch_state_reset_many(DevState *const *states, int count, hipStream_t s) {
+    if (count <= 0) return hipSuccess;
+    k_state_reset_many<<<(count + 255) / 256, 256, 0, s>>>(states, count);
+    return hipGetLastError();
+}
+
+hipError_t launch_gather_states(DevState *const *states, int count, DevState *out,
+                                hipStream_t s) {
+    if (count <= 0) return hipSuccess;
+    k_gather_states<<<(count + 255) / 256, 256, 0, s>>>(states, count, out);
     return hipGetLastError();
 }
 
