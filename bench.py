@@ -11,6 +11,10 @@ Prints ONE JSON line.  Workloads (seeded, synthetic):
   orl   (default) 112x92 images, n=400, r=40, 3 levels of full weighting
   small           16x16 images, n=500, r=10, 2 levels of 2x2 block restriction
   large           256x256 images, n=2000, r=50, 4 levels of full weighting
+  batch           512 uneven problems (sides 16-64, n 100-2000, r 5-40), 3 levels,
+                  HALS, one batched solve (grouped launches) per step
+  serve           Poisson arrivals (default 200 req/s) of problems drawn like
+                  `batch`, served with continuous batching; p50/p99 latency
 Target: rel_err <= eps_E + tau, eps_E the exact planted-noise level of the
 instance (the literal 1e-2 lies below the rank-r error floor of this data).
 """
@@ -30,6 +34,8 @@ sys.path.insert(0, ROOT)
 
 PEAK_HBM_GBS = 8000.0          # MI355X HBM3E
 PEAK_FP32_MFMA_TFLOPS = 157.3  # MI355X dense FP32 matrix
+
+EXTRA_WORKLOADS = ("batch", "serve")
 
 WORKLOADS = {
     "orl": dict(spec="CFG_ORL", h=112, w=92, levels=3, xfer="fw"),
@@ -63,12 +69,163 @@ def kernel_bytes_flops(kind, m, n, r):
     return 0, 0
 
 
+def _make_one(a):
+    import synth
+    spec, s = a
+    return spec, synth.make_instance(spec, s)
+
+
+def _pool_instances(count, seed):
+    """Seeded problems of the uneven batch distribution, drawn in worker
+    processes (call before the GPU is touched)."""
+    import concurrent.futures as cf
+    import synth
+    specs = synth.batch_specs(count, seed)
+    workers = max(1, min(8, len(os.sched_getaffinity(0))))
+    out = []
+    with cf.ProcessPoolExecutor(max_workers=workers) as ex:
+        for k, item in enumerate(ex.map(_make_one, specs, chunksize=8)):
+            out.append(item)
+            if (k + 1) % 128 == 0:
+                print(f"generated {k + 1}/{count} problems", file=sys.stderr, flush=True)
+    return out
+
+
+def bench_batch(args) -> int:
+    """512 uneven problems solved as one batch per step (to eps_E + tau)."""
+    pool = _pool_instances(args.count, 1000)
+    import torch
+    import paper_1009_0881_amd as P
+    torch.cuda.set_device(0)
+    plans, dev = [], []
+    for spec, inst in pool:
+        plans.append(P.Plan(m=spec.m, n=spec.n, h=spec.h, w=spec.w, r=spec.r, levels=3,
+                            algo="hals", cycle=args.cycle, xfer="fw", tol=inst.eps_E + args.tau,
+                            max_fine_iters=args.max_fine_iters, check_every=4))
+        dev.append(P.to_device(inst.M, inst.V0, inst.W0))
+    V0 = [d[1].clone() for d in dev]
+    W0 = [d[2].clone() for d in dev]
+    ws = P.batch_workspace(plans)
+
+    def one():
+        for i, d in enumerate(dev):
+            d[1].copy_(V0[i])
+            d[2].copy_(W0[i])
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        res = P.solve_batch(plans, [d[0] for d in dev], [d[1] for d in dev], [d[2] for d in dev],
+                            args.budget, workspace=ws, graph=args.graph)
+        return time.perf_counter() - t0, res
+
+    for _ in range(args.warmup):
+        one()
+    times, res = [], None
+    for _ in range(args.steps):
+        dt, res = one()
+        times.append(dt)
+    ms = np.array(times) * 1e3
+    # algorithmic HBM bytes of the run: 2 FP32 passes over M_l per iteration
+    sides = {}
+    tot_bytes = 0
+    for (spec, inst), r in zip(pool, res):
+        fe = r["fine_equiv"]
+        tot_bytes += fe * (8 * spec.m * spec.n)
+    ms50 = float(np.percentile(ms, 50))
+    ok = all(r["stopped"] for r in res)
+    out = {
+        "metric": "time to rel. err 1e-2 vs plain FP32 single-level; solves/s + p50/p99 latency",
+        "value": round(args.count / (ms50 * 1e-3), 2), "unit": "solves/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(float(np.mean(ms)), 3),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": f"batch: {args.count} uneven planted-blob problems (sides 16-64, "
+                               f"n 100-2000, r 5-40), 3 levels FW, {args.cycle.upper()} HALS FP32, "
+                               f"T={args.budget}, each to rel_err <= eps_E+{args.tau:g}, one "
+                               f"batched solve per step{' (hipGraph)' if args.graph else ''}"},
+        "batch_ms": {"p50": round(ms50, 3), "p99": round(float(np.percentile(ms, 99)), 3)},
+        "all_reached_target": bool(ok),
+        "iterations_total": int(sum(r["total_iters"] for r in res)),
+        "fine_equiv_total": round(float(sum(r["fine_equiv"] for r in res)), 2),
+        "algorithmic_hbm_gbs": round(tot_bytes / (ms50 * 1e-3) / 1e9, 1),
+    }
+    print(json.dumps(out), flush=True)
+    return 0 if ok else 1
+
+
+def bench_serve(args) -> int:
+    """Poisson arrivals served with continuous batching; latency arrival -> host result."""
+    pool = _pool_instances(128, 5000)
+    import torch
+    import paper_1009_0881_amd as P
+    torch.cuda.set_device(0)
+    srv = P.Server(hbm_budget=16 << 30, slots=64)
+    rng = np.random.default_rng(7)
+    warm = 3.0
+    total = warm + args.duration
+    gaps = rng.exponential(1.0 / args.rate, size=int(total * args.rate * 1.5) + 16)
+    arrivals = np.cumsum(gaps)
+    arrivals = arrivals[arrivals < total]
+    pending, done = {}, []
+    t0 = time.perf_counter()
+    k = 0
+    try:
+        while k < len(arrivals) or pending:
+            now = time.perf_counter() - t0
+            while k < len(arrivals) and arrivals[k] <= now:
+                spec, inst = pool[k % len(pool)]
+                t = srv.submit(inst.M, inst.V0, inst.W0, args.budget, spec.h, spec.w, spec.r,
+                               levels=3, algo="hals", cycle=args.cycle, xfer="fw",
+                               tol=inst.eps_E + 2e-2, max_fine_iters=args.max_fine_iters,
+                               check_every=4)
+                pending[t] = (arrivals[k], k)
+                k += 1
+            for t in list(pending):
+                r = srv.poll(t)
+                if r is not None:
+                    arr, idx = pending.pop(t)
+                    done.append((arr, time.perf_counter() - t0, r[2]))
+            time.sleep(0.0005)
+        st = srv.stats()
+    finally:
+        srv.close()
+    meas = [d for d in done if d[0] >= warm]
+    lat = np.array([d[2]["latency_ms"] for d in meas])
+    lat_host = np.array([(d[1] - d[0]) * 1e3 for d in meas])
+    q = np.array([d[2]["queue_ms"] for d in meas])
+    span = max(d[1] for d in meas) - min(d[0] for d in meas)
+    ok = all(d[2]["stopped"] for d in meas)
+    out = {
+        "metric": "time to rel. err 1e-2 vs plain FP32 single-level; solves/s + p50/p99 latency",
+        "value": round(len(meas) / span, 2), "unit": "solves/s", "n_gpus": 1,
+        "steps": len(meas), "warmup": len(done) - len(meas),
+        "ms_per_step": round(float(np.mean(lat)), 3), "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+        "config": {"workload": f"serve: Poisson {args.rate:g} req/s for {args.duration:g} s after "
+                               f"{warm:g} s warm-up, problems drawn like the 512-problem batch "
+                               f"(3 levels FW, {args.cycle.upper()} HALS FP32, T={args.budget}), "
+                               f"each to rel_err <= eps_E+0.02, 64 slots, 16 GiB pool"},
+        "latency_ms": {"p50": round(float(np.percentile(lat, 50)), 3),
+                       "p99": round(float(np.percentile(lat, 99)), 3),
+                       "host_poll_p50": round(float(np.percentile(lat_host, 50)), 3),
+                       "host_poll_p99": round(float(np.percentile(lat_host, 99)), 3)},
+        "queue_ms": {"p50": round(float(np.percentile(q, 50)), 3),
+                     "p99": round(float(np.percentile(q, 99)), 3)},
+        "offered_rate": args.rate, "server": st, "all_reached_target": bool(ok),
+    }
+    print(json.dumps(out), flush=True)
+    return 0 if ok else 1
+
+
 def main() -> int:
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=50)
     ap.add_argument("--warmup", type=int, default=5)
-    ap.add_argument("--workload", default="orl", choices=sorted(WORKLOADS))
+    ap.add_argument("--workload", default="orl", choices=sorted(WORKLOADS) + list(EXTRA_WORKLOADS))
+    ap.add_argument("--count", type=int, default=512, help="batch: problems per batch")
+    ap.add_argument("--rate", type=float, default=200.0, help="serve: arrivals per second")
+    ap.add_argument("--duration", type=float, default=20.0, help="serve: measured seconds")
+    ap.add_argument("--graph", action="store_true", help="batch: replay steady ticks as hipGraphs")
     ap.add_argument("--algo", default="hals", choices=["hals", "mu", "anls"])
     ap.add_argument("--cycle", default="vc", choices=["ni", "vc", "fmg"])
     ap.add_argument("--levels", type=int, default=None)
@@ -94,6 +251,10 @@ def main() -> int:
         print("bench.py needs a GPU", file=sys.stderr)
         return 1
     torch.cuda.set_device(0)
+    if args.workload == "batch":
+        return bench_batch(args)
+    if args.workload == "serve":
+        return bench_serve(args)
     wl = WORKLOADS[args.workload]
     spec = getattr(synth, wl["spec"])
     levels = args.levels or wl["levels"]

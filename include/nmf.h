@@ -46,7 +46,9 @@ enum {
     NMF_E_DEVICE = -4,     /* a HIP call failed (message has the HIP error)         */
     NMF_E_NONFINITE = -5,  /* NaN/Inf in M (input check) or in a residual           */
     NMF_E_NEGATIVE = -6,   /* M has a negative entry (input check)                  */
-    NMF_E_BUSY = -7        /* server: request does not fit the admission budget     */
+    NMF_E_BUSY = -7,       /* server: request does not fit the admission budget     */
+    NMF_PENDING = 1        /* server poll: the request has not finished yet (not an
+                              error)                                                 */
 };
 
 enum { NMF_HALS = 0, NMF_MU = 1, NMF_ANLS = 2 };          /* Alg. 3, Alg. 2, Alg. 1 */
@@ -89,6 +91,8 @@ typedef struct {
     int32_t stopped;         /* 1 if tol was reached                                */
     double rel_err;          /* rel_err of the last iteration executed              */
     double fine_equiv;       /* work in finest-iteration equivalents: sum 4^-depth  */
+    double queue_ms;         /* server: submit -> admission (0 elsewhere)           */
+    double latency_ms;       /* server: submit -> factors in host memory            */
 } nmf_result;
 
 /* Validate a problem description and build a plan (host only, no device
@@ -200,6 +204,38 @@ nmf_status nmf_batch_workspace(const nmf_plan_t *plans, int32_t count, size_t *b
 nmf_status nmf_solve_batch(const nmf_plan_t *plans, int32_t count, const float *const *dM,
                            float *const *dV, float *const *dW, const int32_t *iters,
                            void *dWorkspace, void *stream, int32_t flags, nmf_result *hOut);
+
+/* ---- serving with continuous batching -------------------------------------
+ * A server owns one device pool of hbm_budget bytes (allocated once, here) and
+ * a worker thread.  nmf_server_submit plans the request (errors of nmf_plan
+ * are returned at once; ANLS and ldm != m are rejected with NMF_E_ARG, a
+ * footprint above the budget with NMF_E_BUSY) and queues it; hM (m x n,
+ * column-major), hV0 (m x r, column-major) and hW0 (r x n, row-major) are
+ * host arrays that must stay valid until the request has finished.  The
+ * worker admits queued requests in arrival order while at most `slots` run
+ * and the pool has room for their footprint (M, V, W and the plan's
+ * workspace), copies them in, and advances every admitted request with the
+ * batch executor; requests that arrive while others run join at the next
+ * tick.  A finished request's factors are copied to server-owned host memory
+ * and its device memory is released at once.  Results are bitwise those of
+ * nmf_solve on the same plan, whatever else runs alongside.
+ *
+ * nmf_server_poll: NMF_PENDING while the request runs or waits; otherwise
+ * copies V (m x r) and W (r x n) to hV / hW (may be null), fills *out and
+ * returns the request's status; the ticket is then retired.
+ * nmf_server_stats: up to 6 counters: admitted, completed, running, peak
+ * running, peak pool bytes in use, executor ticks.
+ * nmf_server_destroy: drops queued requests, waits for running ones, frees the
+ * pool.  Calls on one server may come from any host thread. */
+typedef struct nmf_server_s nmf_server;
+nmf_status nmf_server_create(size_t hbm_budget, int32_t slots, nmf_server **out);
+nmf_status nmf_server_submit(nmf_server *server, const nmf_desc *desc, const float *hM,
+                             const float *hV0, const float *hW0, int32_t iters,
+                             uint64_t *ticket);
+nmf_status nmf_server_poll(nmf_server *server, uint64_t ticket, float *hV, float *hW,
+                           nmf_result *out);
+nmf_status nmf_server_stats(nmf_server *server, int64_t *stats, int32_t cap);
+nmf_status nmf_server_destroy(nmf_server *server);
 
 #ifdef __cplusplus
 }

@@ -32,7 +32,9 @@ XFERS = {"fw": XFER_FW, "block2": XFER_BLOCK2}
 PRECS = {"fp32": FP32, "bf16": BF16}
 
 STATUS = {0: "NMF_OK", -1: "NMF_E_ARG", -2: "NMF_E_SHAPE", -3: "NMF_E_NOMEM",
-          -4: "NMF_E_DEVICE", -5: "NMF_E_NONFINITE", -6: "NMF_E_NEGATIVE", -7: "NMF_E_BUSY"}
+          -4: "NMF_E_DEVICE", -5: "NMF_E_NONFINITE", -6: "NMF_E_NEGATIVE", -7: "NMF_E_BUSY",
+          1: "NMF_PENDING"}
+PENDING = 1
 
 # Every symbol include/nmf.h declares.
 EXPORTS = [
@@ -40,6 +42,8 @@ EXPORTS = [
     "nmf_query_levels", "nmf_query_schedule", "nmf_query_log",
     "nmf_restrict", "nmf_prolong", "nmf_iterate", "nmf_products", "nmf_gram",
     "nmf_profile", "nmf_profile_read", "nmf_batch_workspace", "nmf_solve_batch",
+    "nmf_server_create", "nmf_server_submit", "nmf_server_poll", "nmf_server_stats",
+    "nmf_server_destroy",
 ]
 
 BATCH_GRAPH = 1
@@ -72,6 +76,7 @@ class Result(ctypes.Structure):
         ("log_len", ctypes.c_int32), ("total_iters", ctypes.c_int32),
         ("fine_iters", ctypes.c_int32), ("stopped", ctypes.c_int32),
         ("rel_err", ctypes.c_double), ("fine_equiv", ctypes.c_double),
+        ("queue_ms", ctypes.c_double), ("latency_ms", ctypes.c_double),
     ]
 
     def as_dict(self) -> dict:
@@ -109,6 +114,12 @@ def lib() -> ctypes.CDLL:
         L.nmf_profile_read.argtypes = [vp, ctypes.POINTER(i64), ctypes.POINTER(ctypes.c_double),
                                        i32, i32]
         L.nmf_gram.argtypes = [i32, i64, vp, i64, vp, vp, sz, vp]
+        L.nmf_server_create.argtypes = [sz, i32, ctypes.POINTER(vp)]
+        L.nmf_server_submit.argtypes = [vp, ctypes.POINTER(Desc), vp, vp, vp, i32,
+                                        ctypes.POINTER(ctypes.c_uint64)]
+        L.nmf_server_poll.argtypes = [vp, ctypes.c_uint64, vp, vp, ctypes.POINTER(Result)]
+        L.nmf_server_stats.argtypes = [vp, ctypes.POINTER(i64), i32]
+        L.nmf_server_destroy.argtypes = [vp]
         L.nmf_batch_workspace.argtypes = [ctypes.POINTER(vp), i32, ctypes.POINTER(sz)]
         L.nmf_solve_batch.argtypes = [ctypes.POINTER(vp), i32, ctypes.POINTER(vp),
                                       ctypes.POINTER(vp), ctypes.POINTER(vp),
@@ -149,6 +160,21 @@ def _need_cuda(*ts) -> None:
 
 # --------------------------------------------------------------------- plans
 
+def make_desc(m, n, h, w, r, levels=1, algo="hals", cycle="ni", xfer="fw", prec="fp32",
+              tol=0.0, max_fine_iters=0, check_every=8, log_cap=4096, check_input=False,
+              refine_iters=0, ldm=0) -> Desc:
+    """nmf_desc from Python values (names as in include/nmf.h)."""
+    d = Desc()
+    d.m, d.n, d.ldm, d.h, d.w, d.r, d.levels = m, n, ldm, h, w, r, levels
+    d.algo = ALGOS.get(algo, algo) if isinstance(algo, str) else algo
+    d.cycle = CYCLES.get(cycle, cycle) if isinstance(cycle, str) else cycle
+    d.xfer = XFERS.get(xfer, xfer) if isinstance(xfer, str) else xfer
+    d.prec = PRECS.get(prec, prec) if isinstance(prec, str) else prec
+    d.tol, d.max_fine_iters, d.check_every = tol, max_fine_iters, check_every
+    d.log_cap, d.check_input, d.refine_iters = log_cap, int(check_input), refine_iters
+    return d
+
+
 class Plan:
     """A validated problem description (host only) and its workspace size."""
 
@@ -156,14 +182,8 @@ class Plan:
                  algo="hals", cycle="ni", xfer="fw", prec="fp32", tol: float = 0.0,
                  max_fine_iters: int = 0, check_every: int = 8, log_cap: int = 4096,
                  check_input: bool = False, refine_iters: int = 0, ldm: int = 0):
-        d = Desc()
-        d.m, d.n, d.ldm, d.h, d.w, d.r, d.levels = m, n, ldm, h, w, r, levels
-        d.algo = ALGOS.get(algo, algo) if isinstance(algo, str) else algo
-        d.cycle = CYCLES.get(cycle, cycle) if isinstance(cycle, str) else cycle
-        d.xfer = XFERS.get(xfer, xfer) if isinstance(xfer, str) else xfer
-        d.prec = PRECS.get(prec, prec) if isinstance(prec, str) else prec
-        d.tol, d.max_fine_iters, d.check_every = tol, max_fine_iters, check_every
-        d.log_cap, d.check_input, d.refine_iters = log_cap, int(check_input), refine_iters
+        d = make_desc(m, n, h, w, r, levels, algo, cycle, xfer, prec, tol, max_fine_iters,
+                      check_every, log_cap, check_input, refine_iters, ldm)
         self.desc = d
         self.handle = ctypes.c_void_p()
         wsb = ctypes.c_size_t()
@@ -316,6 +336,62 @@ def solve_batch(plans, Ms, Vs, Ws, iters, workspace=None, graph=False, stream=No
                                BATCH_GRAPH if graph else 0, res)
     _check(st)
     return [r.as_dict() for r in res]
+
+
+class Server:
+    """Serving loop with continuous batching (nmf_server_*).
+
+    submit() takes host numpy arrays in the library layout (M m x n and V0
+    m x r Fortran-ordered float32, W0 r x n C-ordered) and keeps references to
+    them until the request is retired; poll() returns None while it runs,
+    else (V, W, result) with V m x r and W r x n (float32)."""
+
+    def __init__(self, hbm_budget: int, slots: int):
+        self.handle = ctypes.c_void_p()
+        _check(lib().nmf_server_create(int(hbm_budget), int(slots), ctypes.byref(self.handle)))
+        self._keep = {}
+
+    def submit(self, M: np.ndarray, V0: np.ndarray, W0: np.ndarray, iters: int, h: int, w: int,
+               r: int, **desc) -> int:
+        M = np.asfortranarray(M, dtype=np.float32)
+        V0 = np.asfortranarray(V0, dtype=np.float32)
+        W0 = np.ascontiguousarray(W0, dtype=np.float32)
+        m, n = M.shape
+        d = make_desc(m, n, h, w, r, **desc)
+        t = ctypes.c_uint64()
+        _check(lib().nmf_server_submit(self.handle, ctypes.byref(d), M.ctypes.data,
+                                       V0.ctypes.data, W0.ctypes.data, int(iters),
+                                       ctypes.byref(t)))
+        self._keep[t.value] = (M, V0, W0, d, m, n, r)
+        return t.value
+
+    def poll(self, ticket: int):
+        M, V0, W0, d, m, n, r = self._keep[ticket]
+        V = np.empty((m, r), dtype=np.float32, order="F")
+        W = np.empty((r, n), dtype=np.float32)
+        res = Result()
+        st = lib().nmf_server_poll(self.handle, ticket, V.ctypes.data, W.ctypes.data,
+                                   ctypes.byref(res))
+        if st == PENDING:
+            return None
+        del self._keep[ticket]
+        _check(st)
+        return V, W, res.as_dict()
+
+    def stats(self) -> dict:
+        buf = (ctypes.c_int64 * 6)()
+        _check(lib().nmf_server_stats(self.handle, buf, 6))
+        keys = ["admitted", "completed", "running", "peak_running", "peak_pool_bytes", "ticks"]
+        return dict(zip(keys, list(buf)))
+
+    def close(self):
+        if self.handle is not None and self.handle.value and _LIB is not None:
+            _LIB.nmf_server_destroy(self.handle)
+            self.handle = ctypes.c_void_p()
+        self._keep.clear()
+
+    def __del__(self):
+        self.close()
 
 
 # ------------------------------------------------------------ array helpers

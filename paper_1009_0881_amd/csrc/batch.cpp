@@ -468,6 +468,12 @@ bool Executor::all_done() const {
     return fresh_.empty();
 }
 
+bool Executor::any_done() const {
+    for (const Inst &I : insts_)
+        if (I.stage == 2) return true;
+    return false;
+}
+
 nmf_status Executor::results(std::vector<int> &ids, std::vector<nmf_result> &res,
                              std::vector<nmf_status> &status, bool only_done) {
     std::vector<DevState> hs;

@@ -37,6 +37,7 @@ public:
     nmf_status tick();
     nmf_status poll();
     bool all_done() const;
+    bool any_done() const;
     bool empty() const { return insts_.empty(); }
     // Results of the finished problems (all problems when only_done is false).
     nmf_status results(std::vector<int> &ids, std::vector<nmf_result> &res,
