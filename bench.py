@@ -37,6 +37,29 @@ PEAK_FP32_MFMA_TFLOPS = 157.3  # MI355X dense FP32 matrix
 
 EXTRA_WORKLOADS = ("batch", "serve")
 
+# HBM traffic per launch (bytes) of the sweep kernels on the orl workload, by
+# kernel kind and level size m: rocprofv3 --pmc FETCH_SIZE and WRITE_SIZE
+# passes (KiB per dispatch), scaled by what the same counters read for a
+# 256 MiB device-to-device copy (FETCH_SIZE x2.0, WRITE_SIZE x1.0).  Valid
+# for the kernel sources whose SHA-256 prefix is `sha`; null otherwise.
+TRAFFIC = {
+    "sha": "9da6defdf0f648f3",
+    "orl": {
+        "apass": {10304: 19991708, 2576: 6153662, 644: 2448532},
+        "cpass_partial": {10304: 22283722, 2576: 10276575, 644: 3420448},
+        "cpass_final": {10304: 5205462, 2576: 5080136, 644: 2263395},
+    },
+}
+
+
+def kernel_sources_sha() -> str:
+    import hashlib
+    h = hashlib.sha256()
+    for f in ("sweep.hip", "job.h"):
+        with open(os.path.join(ROOT, "paper_1009_0881_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
 WORKLOADS = {
     "orl": dict(spec="CFG_ORL", h=112, w=92, levels=3, xfer="fw"),
     "small": dict(spec="CFG_SMALL", h=16, w=16, levels=2, xfer="block2"),
@@ -226,6 +249,9 @@ def main() -> int:
     ap.add_argument("--rate", type=float, default=200.0, help="serve: arrivals per second")
     ap.add_argument("--duration", type=float, default=20.0, help="serve: measured seconds")
     ap.add_argument("--graph", action="store_true", help="batch: replay steady ticks as hipGraphs")
+    ap.add_argument("--copy-calibration", type=int, default=0, metavar="BYTES",
+                    help="only run 3 device-to-device copies of BYTES bytes (reference for "
+                         "the FETCH_SIZE / WRITE_SIZE counters) and exit")
     ap.add_argument("--algo", default="hals", choices=["hals", "mu", "anls"])
     ap.add_argument("--cycle", default="vc", choices=["ni", "vc", "fmg"])
     ap.add_argument("--levels", type=int, default=None)
@@ -251,6 +277,17 @@ def main() -> int:
         print("bench.py needs a GPU", file=sys.stderr)
         return 1
     torch.cuda.set_device(0)
+    if args.copy_calibration > 0:
+        import torch
+        torch.cuda.set_device(0)
+        nb = args.copy_calibration // 4 * 4
+        src = torch.ones(nb // 4, dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_bytes": nb, "copies": 3}), flush=True)
+        return 0
     if args.workload == "batch":
         return bench_batch(args)
     if args.workload == "serve":
@@ -332,6 +369,12 @@ def main() -> int:
         b, f = kernel_bytes_flops(dominant, sides[d][0] * sides[d][1], n, r)
         tot_bytes += b
         tot_flops += f
+    traffic = None
+    tab = TRAFFIC.get(args.workload, {}).get(dominant)
+    if tab and kernel_sources_sha() == TRAFFIC["sha"] and levels == wl["levels"]:
+        ms_ = [sides[d][0] * sides[d][1] for d in dep_log]
+        if all(m_ in tab for m_ in ms_):
+            traffic = int(sum(tab[m_] for m_ in ms_) / max(1, len(ms_)))
     cnt, ms_tot = prof_dom.get(dominant, (0, 0.0))
     solves = len(results)
     launches_per_solve = cnt / max(1, solves)
@@ -346,7 +389,8 @@ def main() -> int:
         "peak": PEAK_HBM_GBS,
         "unit": "GB/s",
         "frac": round(achieved / PEAK_HBM_GBS, 4),
-        "traffic": None,
+        "traffic": traffic,
+        "traffic_unit": "bytes per launch (HBM, rocprofv3 FETCH_SIZE + WRITE_SIZE, copy-scaled)",
         "avg_launch_us": round(avg_s * 1e6, 3),
         "launches_per_solve": launches_per_solve,
         "algorithmic_bytes_per_launch": int(per_launch_bytes),

@@ -210,11 +210,11 @@ nmf_status sweep(Ctx &c, int d) {
     const int64_t n = p.d.n;
     int32_t *flags = &c.st->flags;
     const int mode = p.d.algo == NMF_HALS ? 0 : (p.d.algo == NMF_MU ? 1 : 2);
-    NMF_LAUNCH(K_APASS, launch_apass_jobs(mode, J.rpad, J.tm, dj, nullptr, J.nA,
+    NMF_LAUNCH(K_APASS, launch_apass_jobs(mode, J.rpad, J.tm, dj, nullptr, apass_grid_single(J.nA),
                                           apass_lds_bytes(J.rpad, J.tm, mode), c.s));
     if (mode == 2)
         NMF_LAUNCH(K_NNLS_ROWS, launch_nnls_rows(p.rpad, c.Bd, c.A, J.m, r, J.V, flags, c.stop, c.s));
-    NMF_LAUNCH(K_CPART, launch_cpass_jobs(J.rpad, dj, nullptr, J.nC, c.s));
+    NMF_LAUNCH(K_CPART, launch_cpass_jobs(J.rpad, dj, nullptr, cpass_grid_single(J.nCx, J.chunks), c.s));
     NMF_LAUNCH(K_GRAM_V, launch_reduce_jobs(0, dj, nullptr, J.nG, c.s));
     NMF_LAUNCH(K_CFINAL, launch_cfinal_jobs(mode, J.rpad, dj, nullptr, J.nF,
                                             cfinal_lds_bytes(J.rpad, mode), c.s));
@@ -493,9 +493,9 @@ nmf_status nmf_products(nmf_plan_t plan, const float *dM, const float *dV, const
     NMF_HIP(launch_make_wt(dW, p.d.n, p.d.r, p.rpad, c.Wt, s));
     nmf_status st = upload_jobs(c);
     if (st != NMF_OK) return st;
-    NMF_HIP(launch_apass_jobs(2, J.rpad, J.tm, c.djobs, nullptr, J.nA,
+    NMF_HIP(launch_apass_jobs(2, J.rpad, J.tm, c.djobs, nullptr, apass_grid_single(J.nA),
                               apass_lds_bytes(J.rpad, J.tm, 2), s));
-    NMF_HIP(launch_cpass_jobs(J.rpad, c.djobs, nullptr, J.nC, s));
+    NMF_HIP(launch_cpass_jobs(J.rpad, c.djobs, nullptr, cpass_grid_single(J.nCx, J.chunks), s));
     NMF_HIP(launch_cfinal_jobs(2, J.rpad, c.djobs, nullptr, J.nF, cfinal_lds_bytes(J.rpad, 2), s));
     NMF_HIP(hipStreamSynchronize(s));
     return NMF_OK;

@@ -157,6 +157,10 @@ int apass_rows_per_block(int64_t m);
 size_t apass_lds_bytes(int rpad, int tm, int mode);
 size_t cfinal_lds_bytes(int rpad, int mode);
 int cpass_final_blocks(int64_t n);
+// Grids of single-problem (null block map) A-pass / C-pass launches, whose
+// blocks are mapped to tiles XCD by XCD.
+int apass_grid_single(int nA);
+int cpass_grid_single(int nCx, int chunks);
 hipError_t launch_make_wt(const float *W, int64_t n, int r, int rpad, float *Wt, hipStream_t s);
 // Residual from separately computed Grams (ANLS path): rel_err of
 // ||M||^2 - 2 sum(rparts) + <Dd, Bd>, logged at st->log_len.

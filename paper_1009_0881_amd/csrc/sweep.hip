@@ -351,8 +351,16 @@ template <int RT, int RW, int WN, int S, int MODE>
 __global__ __launch_bounds__(256) void k_apass(const Job *__restrict__ jobs,
                                                const int2 *__restrict__ bmap) {
     extern __shared__ double smem[];
-    const int2 jt = block_job(bmap);
+    int2 jt = block_job(bmap);
     const Job &J = jobs[jt.x];
+    if (!bmap) {
+        // single problem: XCD x (= block % 8) takes a contiguous range of row
+        // tiles, so neighbouring tiles, which share 128-byte lines of M, meet
+        // in one L2
+        const int per = (J.nA + 7) / 8;
+        jt.y = (int)(blockIdx.x & 7) * per + (int)(blockIdx.x >> 3);
+        if (jt.y >= J.nA) return;
+    }
     if (J.st->stop) return;
     apass_tile<RT, RW, WN, S, MODE>(J, jt.y, smem);
 }
@@ -501,9 +509,17 @@ __global__ __launch_bounds__(256) void k_cpass(const Job *__restrict__ jobs,
                                                const int2 *__restrict__ bmap) {
     const int2 jt = block_job(bmap);
     const Job &J = jobs[jt.x];
+    int tx = jt.y % J.nCx, ty = jt.y / J.nCx;
+    if (!bmap) {
+        // single problem: all column tiles of a row chunk run on one XCD
+        // (= block % 8), so the chunk's V rows are read from HBM once
+        const int l = (int)(blockIdx.x >> 3);
+        ty = (int)(blockIdx.x & 7) + 8 * (l / J.nCx);
+        tx = l % J.nCx;
+        if (ty >= J.chunks) return;
+    }
     if (J.st->stop) return;
-    const int tile = jt.y;
-    cpass_tile<RT, SB>(J, tile % J.nCx, tile / J.nCx, J.nCx);
+    cpass_tile<RT, SB>(J, tx, ty, J.nCx);
 }
 
 // ---------------------------------------------------------------------------
@@ -816,6 +832,10 @@ hipError_t launch_residual(const double *rparts, int nparts, const double *Dd, c
 }
 
 int cpass_final_blocks(int64_t n) { return (int)((n + 15) / 16); }
+
+int apass_grid_single(int nA) { return 8 * ((nA + 7) / 8); }
+
+int cpass_grid_single(int nCx, int chunks) { return 8 * nCx * ((chunks + 7) / 8); }
 
 // Allow the sweep kernels the LDS sizes apass_lds_bytes / cfinal_lds_bytes
 // can ask for (above the 64 KB default).

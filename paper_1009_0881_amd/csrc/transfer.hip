@@ -21,38 +21,41 @@ namespace nmf {
 
 namespace {
 
+// Up to three taps of a 1-D transfer.  Unused taps carry weight 0 and repeat
+// a valid index, so every loop has a fixed trip count and the taps stay in
+// registers; a zero-weight tap adds +0.0 to a finite nonnegative sum, which
+// leaves the result bitwise unchanged.
 struct Taps {
     int idx[3];
     double wt[3];
-    int cnt;
 };
 
 __device__ __forceinline__ Taps restrict_taps(int c, int N, int xfer) {
     Taps t;
-    t.cnt = 0;
     if (xfer == NMF_XFER_FW) {
-        double sum = 0.0;
+        // weights (1, 2, 1) on fine nodes 2c-1, 2c, 2c+1 that exist, renormalised
+        const bool lo = 2 * c - 1 >= 0, hi = 2 * c + 1 < N;
+        const double sum = 2.0 + (lo ? 1.0 : 0.0) + (hi ? 1.0 : 0.0);
+        int k = 0;
+        double w[3] = {0.0, 0.0, 0.0};
+        int ix[3] = {2 * c, 2 * c, 2 * c};
+        if (lo) { ix[k] = 2 * c - 1; w[k] = 1.0 / sum; ++k; }
+        ix[k] = 2 * c; w[k] = 2.0 / sum; ++k;
+        if (hi) { ix[k] = 2 * c + 1; w[k] = 1.0 / sum; ++k; }
 #pragma unroll
-        for (int d = -1; d <= 1; ++d) {
-            const int f = 2 * c + d;
-            if (f >= 0 && f < N) {
-                const double wgt = (d == 0) ? 2.0 : 1.0;
-                t.idx[t.cnt] = f;
-                t.wt[t.cnt] = wgt;
-                sum += wgt;
-                ++t.cnt;
-            }
+        for (int i = 0; i < 3; ++i) {
+            t.idx[i] = ix[i];
+            t.wt[i] = w[i];
         }
-        for (int i = 0; i < t.cnt; ++i) t.wt[i] /= sum;
     } else {
         const int f0 = 2 * c;
+        const bool two = f0 + 1 < N;
         t.idx[0] = f0;
-        t.cnt = 1;
-        if (f0 + 1 < N) {
-            t.idx[1] = f0 + 1;
-            t.cnt = 2;
-        }
-        for (int i = 0; i < t.cnt; ++i) t.wt[i] = 1.0 / t.cnt;
+        t.idx[1] = two ? f0 + 1 : f0;
+        t.idx[2] = f0;
+        t.wt[0] = two ? 0.5 : 1.0;
+        t.wt[1] = two ? 0.5 : 0.0;
+        t.wt[2] = 0.0;
     }
     return t;
 }
@@ -60,17 +63,19 @@ __device__ __forceinline__ Taps restrict_taps(int c, int N, int xfer) {
 __device__ __forceinline__ Taps prolong_taps(int f, int Nc, int xfer) {
     Taps t;
     if (xfer == NMF_XFER_FW && (f & 1)) {
+        const bool two = (f + 1) / 2 < Nc;
         t.idx[0] = (f - 1) / 2;
-        t.cnt = 1;
-        if ((f + 1) / 2 < Nc) {
-            t.idx[1] = (f + 1) / 2;
-            t.cnt = 2;
-        }
+        t.idx[1] = two ? (f + 1) / 2 : (f - 1) / 2;
+        t.wt[0] = two ? 0.5 : 1.0;
+        t.wt[1] = two ? 0.5 : 0.0;
     } else {
         t.idx[0] = f / 2;
-        t.cnt = 1;
+        t.idx[1] = f / 2;
+        t.wt[0] = 1.0;
+        t.wt[1] = 0.0;
     }
-    for (int i = 0; i < t.cnt; ++i) t.wt[i] = 1.0 / t.cnt;
+    t.idx[2] = t.idx[0];
+    t.wt[2] = 0.0;
     return t;
 }
 
@@ -79,9 +84,11 @@ __device__ __forceinline__ Taps prolong_taps(int f, int Nc, int xfer) {
 __device__ __forceinline__ float stencil(const float *img, int rowlen, const Taps &ty,
                                          const Taps &tx) {
     double acc = 0.0;
-    for (int a = 0; a < ty.cnt; ++a) {
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
         double row = 0.0;
-        for (int b = 0; b < tx.cnt; ++b) row += tx.wt[b] * (double)img[(int64_t)ty.idx[a] * rowlen + tx.idx[b]];
+#pragma unroll
+        for (int b = 0; b < 3; ++b) row += tx.wt[b] * (double)img[(int64_t)ty.idx[a] * rowlen + tx.idx[b]];
         acc += ty.wt[a] * row;
     }
     return (float)acc;
