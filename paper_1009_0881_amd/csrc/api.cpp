@@ -140,8 +140,24 @@ Ctx make_ctx(nmf_plan_t plan, const float *dM, float *dV, float *dW, void *dws, 
         J.log_depth = c.log_depth;
         J.st = c.st;
         J.tol = p.d.tol;
+        J.prec = 0;
+        if (p.d.prec == NMF_BF16) {
+            J.prec = 1;
+            J.mpad = li.mpad;
+            J.npad = (p.d.n + 31) / 32 * 32;
+            J.Mbp = at<uint16_t>(c.ws, li.off_Mbp);
+            J.Mbc = at<uint16_t>(c.ws, li.off_Mbc);
+            J.Vb = at<uint16_t>(c.ws, li.off_Vb);
+            J.Wb = at<uint16_t>(c.ws, p.ws.off_Wb);
+        }
         c.jobs.push_back(J);
     }
+    // entry L: the finest level in FP32 (refinement iterations of BF16 mode)
+    Job J0 = c.jobs[0];
+    J0.prec = 0;
+    J0.Mbp = J0.Mbc = nullptr;
+    J0.Vb = J0.Wb = nullptr;
+    c.jobs.push_back(J0);
     return c;
 }
 
@@ -201,20 +217,24 @@ nmf_status init_w(Ctx &c) {
 }
 
 // One iteration of the inner algorithm at depth d, then the residual.
-nmf_status sweep(Ctx &c, int d) {
+// fp32: use the FP32 finest-level job (refinement iterations of BF16 mode).
+nmf_status sweep(Ctx &c, int d, bool fp32 = false) {
     nmf_plan_t plan = c.plan;
     const Plan &p = *c.p;
-    const Job &J = c.jobs[d];
-    const Job *dj = c.djobs + d;
+    const int ji = fp32 ? (int)p.lv.size() : d;
+    const Job &J = c.jobs[ji];
+    const Job *dj = c.djobs + ji;
+    const bool bf = J.prec == 1;
     const int r = p.d.r;
     const int64_t n = p.d.n;
     int32_t *flags = &c.st->flags;
     const int mode = p.d.algo == NMF_HALS ? 0 : (p.d.algo == NMF_MU ? 1 : 2);
     NMF_LAUNCH(K_APASS, launch_apass_jobs(mode, J.rpad, J.tm, dj, nullptr, apass_grid_single(J.nA),
-                                          apass_lds_bytes(J.rpad, J.tm, mode), c.s));
+                                          apass_lds_bytes(J.rpad, J.tm, mode), c.s, bf));
     if (mode == 2)
         NMF_LAUNCH(K_NNLS_ROWS, launch_nnls_rows(p.rpad, c.Bd, c.A, J.m, r, J.V, flags, c.stop, c.s));
-    NMF_LAUNCH(K_CPART, launch_cpass_jobs(J.rpad, dj, nullptr, cpass_grid_single(J.nCx, J.chunks), c.s));
+    NMF_LAUNCH(K_CPART, launch_cpass_jobs(J.rpad, dj, nullptr, cpass_grid_single(J.nCx, J.chunks),
+                                          c.s, bf));
     NMF_LAUNCH(K_GRAM_V, launch_reduce_jobs(0, dj, nullptr, J.nG, c.s));
     NMF_LAUNCH(K_CFINAL, launch_cfinal_jobs(mode, J.rpad, dj, nullptr, J.nF,
                                             cfinal_lds_bytes(J.rpad, mode), c.s));
@@ -248,6 +268,27 @@ nmf_status prepare_levels(Ctx &c) {
                                          c.nparts + l * kNormParts, norm_parts(p.lv[l].m, p.d.n),
                                          c.norm + l, c.s));
     }
+    return NMF_OK;
+}
+
+// BF16 mode: operand copies of every M_l (A-pass and C-pass layouts) and the
+// zero padding of the V and W copies (their live part is written by the
+// kernels that update V and W).
+nmf_status prepare_bf16(Ctx &c) {
+    nmf_plan_t plan = c.plan;
+    const Plan &p = *c.p;
+    if (p.d.prec != NMF_BF16) return NMF_OK;
+    const Job &J0 = c.jobs[0];
+    for (size_t l = 0; l < p.lv.size(); ++l) {
+        const Job &J = c.jobs[l];
+        NMF_HIP(launch_pack_bf16(c.M[l], c.ldm[l], J.m, J.n, const_cast<uint16_t *>(J.Mbp),
+                                 J.npad, c.s));
+        NMF_HIP(launch_to_bf16_cols(c.M[l], c.ldm[l], J.m, J.n, const_cast<uint16_t *>(J.Mbc),
+                                    J.mpad, J.n, c.s));
+        NMF_HIP(launch_to_bf16_cols(c.V[l], J.m, J.m, J.r, J.Vb, J.mpad, J.rpad, c.s));
+    }
+    // W (r x n row-major) read as n x r column-major: Wb is rpad x npad row-major
+    NMF_HIP(launch_to_bf16_cols(c.W, J0.n, J0.n, J0.r, J0.Wb, J0.npad, J0.rpad, c.s));
     return NMF_OK;
 }
 
@@ -371,10 +412,12 @@ nmf_status nmf_solve(nmf_plan_t plan, const float *dM, float *dV, float *dW, int
     nmf_status st;
     if (p.d.check_input && (st = check_input(c)) != NMF_OK) return st;
     if ((st = prepare_levels(c)) != NMF_OK) return st;
+    if ((st = prepare_bf16(c)) != NMF_OK) return st;
     if ((st = upload_jobs(c)) != NMF_OK) return st;
     if ((st = init_w(c)) != NMF_OK) return st;
 
     const bool use_tol = p.d.tol > 0.0;
+    const bool bf16 = p.d.prec == NMF_BF16;
     const int ce = p.d.check_every;
     bool done = false;
     int since_check = 0;
@@ -403,10 +446,19 @@ nmf_status nmf_solve(nmf_plan_t plan, const float *dM, float *dV, float *dW, int
             }
         }
     }
+    // BF16 mode: finish on the finest level in FP32 (the tolerance applies to
+    // these iterations only)
+    for (int i = 0; bf16 && i < p.d.refine_iters && !done; ++i) {
+        if ((st = sweep(c, 0, true)) != NMF_OK) return st;
+        if (use_tol && ++since_check >= ce) {
+            since_check = 0;
+            if ((st = poll(done)) != NMF_OK) return st;
+        }
+    }
     if (use_tol && !done) {
         if ((st = poll(done)) != NMF_OK) return st;
         for (int i = 0; i < p.d.max_fine_iters && !done; ++i) {
-            if ((st = sweep(c, 0)) != NMF_OK) return st;
+            if ((st = sweep(c, 0, bf16)) != NMF_OK) return st;
             if (++since_check >= ce) {
                 since_check = 0;
                 if ((st = poll(done)) != NMF_OK) return st;
@@ -446,6 +498,7 @@ nmf_status nmf_iterate(nmf_plan_t plan, const float *dM, float *dV, float *dW, i
     NMF_HIP(launch_state_reset(c.st, s));
     nmf_status st;
     if ((st = prepare_levels(c)) != NMF_OK) return st;
+    if ((st = prepare_bf16(c)) != NMF_OK) return st;
     if ((st = upload_jobs(c)) != NMF_OK) return st;
     if ((st = init_w(c)) != NMF_OK) return st;
     for (int i = 0; i < count; ++i)

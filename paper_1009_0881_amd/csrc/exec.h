@@ -43,7 +43,7 @@ struct Ctx {
     std::vector<float *> V;
     float *W;
     Job *djobs;                   // device copy of `jobs` (workspace)
-    std::vector<Job> jobs;        // one job per level
+    std::vector<Job> jobs;        // one job per level, then the FP32 finest-level job
     std::vector<int8_t> depths;   // depth of every executed iteration (host mirror)
 };
 

@@ -36,6 +36,19 @@ struct Job {
     int32_t *log_depth;
     DevState *st;
     double tol;
+    // BF16 precision mode (prec = 1): operand copies for the MFMA passes.
+    // Mbp: A-pass copy of M, K-packed: element (i, j) at
+    //      ((i/16 * G + j/8) * 16 + i%16) * 8 + j%8, G = npad / 8, zero padded to
+    //      16-row panels and npad columns.
+    // Mbc: C-pass copy of M, column-major with column stride mpad (rows >= m zero).
+    // Vb:  V, column-major with stride mpad, rpad columns (k >= r zero).
+    // Wb:  W, rpad x npad row-major (k >= r or j >= n zero).
+    // mpad = m and npad = n rounded up to 32.
+    // The stop test is applied only to FP32 (prec = 0) iterations.
+    const uint16_t *Mbp, *Mbc;
+    uint16_t *Vb, *Wb;
+    int64_t mpad, npad;
+    int32_t prec, pad_;
 };
 
 }  // namespace nmf

@@ -42,7 +42,8 @@ struct LevelInfo {
     int64_t m;
     size_t off_M;        // workspace offset of M_l (levels >= 1)
     size_t off_V;        // workspace offset of V_l (levels >= 1)
-    size_t off_Mbf;      // workspace offset of the bf16 copy of M_l (prec BF16)
+    size_t off_Mbp, off_Mbc, off_Vb;   // BF16 mode: copies of M_l (A-pass, C-pass layouts), V_l
+    int64_t mpad;        // m rounded up to 32 (column stride of the BF16 copies)
     int32_t cp_chunks;   // split of the m-reduction in V^T M
     int64_t cp_chunk;    // rows per chunk (multiple of 16)
     int32_t gram_parts;  // split of the length-m reduction of V^T V
@@ -58,7 +59,7 @@ struct Step {            // one schedule entry
 struct Workspace {
     size_t off_state, off_log, off_logdepth, off_norm, off_nparts;
     size_t off_Bd, off_Bf, off_Dd, off_Df;
-    size_t off_gparts, off_cparts, off_rparts, off_A, off_C, off_V0bf;
+    size_t off_gparts, off_cparts, off_rparts, off_A, off_C, off_Wb;
     size_t off_Wt, off_Dp, off_Bp, off_jobs;
     size_t gparts_cap;   // doubles
     size_t rparts_cap;   // doubles
@@ -105,6 +106,13 @@ hipError_t launch_sumsq(const float *X, int64_t ld, int64_t rows, int64_t ncols,
 hipError_t launch_check_input(const float *M, int64_t ld, int64_t m, int64_t n, int32_t *flags,
                               hipStream_t s);
 hipError_t launch_state_reset(DevState *st, hipStream_t s);
+// BF16 operand copies (job.h layouts).  to_bf16_cols: column-major X (rows x
+// cols, stride ldx) -> column-major Y (rows_pad x cols_pad), zero padded.
+// pack_bf16: the K-packed A-pass layout with cols_pad columns.
+hipError_t launch_to_bf16_cols(const float *X, int64_t ldx, int64_t rows, int64_t cols,
+                               uint16_t *Y, int64_t rows_pad, int64_t cols_pad, hipStream_t s);
+hipError_t launch_pack_bf16(const float *X, int64_t ldx, int64_t rows, int64_t cols, uint16_t *Y,
+                            int64_t cols_pad, hipStream_t s);
 
 hipError_t launch_gram(int rpad, int r, int64_t L, const float *X, int64_t ldx, int parts,
                        int64_t chunk, double *gparts, double *Gd, float *Gf, const int32_t *stop,
@@ -115,10 +123,11 @@ hipError_t launch_gram(int rpad, int r, int64_t L, const float *X, int64_t ldx, 
 // tile b).  mode: 0 HALS, 1 MU, 2 store the product (ANLS), 3 (W tile kernel
 // only) initialise: Wt and the W W^T partials from the current W, no update.
 // All jobs of one launch share rpad (and tm for the A-pass).
+// bf: BF16 operand copies (job.h) on v_mfma_f32_16x16x32_bf16 (HALS / MU only).
 hipError_t launch_apass_jobs(int mode, int rpad, int tm, const Job *jobs, const int2 *bmap,
-                             int blocks, size_t lds, hipStream_t s);
+                             int blocks, size_t lds, hipStream_t s, bool bf = false);
 hipError_t launch_cpass_jobs(int rpad, const Job *jobs, const int2 *bmap, int blocks,
-                             hipStream_t s);
+                             hipStream_t s, bool bf = false);
 // which = 0: V^T V from the C-pass partials; 1: W W^T and the residual log;
 // 2: W W^T only.
 hipError_t launch_reduce_jobs(int which, const Job *jobs, const int2 *bmap, int blocks,

@@ -90,6 +90,10 @@ nmf_status build_plan(const nmf_desc &d0, Plan &p, std::string &err) {
         err = "negative max_fine_iters / refine_iters / tol";
         return NMF_E_ARG;
     }
+    if (d.prec == NMF_BF16 && d.algo == NMF_ANLS) {
+        err = "BF16 precision is available for HALS and MU";
+        return NMF_E_ARG;
+    }
     if (d.h < 1 || d.w < 1 || d.m != (int64_t)d.h * d.w) {
         snprintf(buf, sizeof buf, "m (%lld) must equal h*w (%d*%d)", (long long)d.m, d.h, d.w);
         err = buf;
@@ -144,7 +148,8 @@ nmf_status build_plan(const nmf_desc &d0, Plan &p, std::string &err) {
         int64_t chunks = std::max<int64_t>(1, p.num_cu / std::max<int64_t>(1, ntiles));
         chunks = std::min<int64_t>(chunks, std::max<int64_t>(1, (li.m + 63) / 64));
         int64_t chunk = (li.m + chunks - 1) / chunks;
-        chunk = (chunk + 15) / 16 * 16;
+        const int64_t q = d.prec == NMF_BF16 ? 32 : 16;   // BF16 MFMA steps are 32 rows
+        chunk = (chunk + q - 1) / q * q;
         li.cp_chunk = chunk;
         li.cp_chunks = (int32_t)((li.m + chunk - 1) / chunk);
         max_cp = std::max<size_t>(max_cp, (size_t)li.cp_chunks);
@@ -200,8 +205,20 @@ nmf_status build_plan(const nmf_desc &d0, Plan &p, std::string &err) {
     ws.off_Wt = take(sizeof(float) * n * p.rpad);
     ws.off_Dp = take(sizeof(double) * max_cp * rp2);
     ws.off_Bp = take(sizeof(double) * (size_t)cpass_final_blocks(d.n) * rp2);
-    ws.off_jobs = take(sizeof(Job) * p.lv.size());
-    ws.off_V0bf = 0;
+    ws.off_jobs = take(sizeof(Job) * (p.lv.size() + 1));   // + FP32 refinement job
+    ws.off_Wb = 0;
+    const int64_t npad = (d.n + 31) / 32 * 32;
+    if (d.prec == NMF_BF16) {
+        // BF16 operand copies (job.h): per level M in the A-pass (K-packed) and
+        // C-pass (column-major, stride mpad) layouts and V; W once
+        for (auto &li : p.lv) {
+            li.mpad = (li.m + 31) / 32 * 32;
+            li.off_Mbp = take(sizeof(uint16_t) * (size_t)((li.m + 15) / 16 * 16) * npad);
+            li.off_Mbc = take(sizeof(uint16_t) * (size_t)li.mpad * n);
+            li.off_Vb = take(sizeof(uint16_t) * (size_t)li.mpad * p.rpad);
+        }
+        ws.off_Wb = take(sizeof(uint16_t) * (size_t)p.rpad * npad);
+    }
     ws.total = off;
     return NMF_OK;
 }

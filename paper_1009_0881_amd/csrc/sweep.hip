@@ -40,6 +40,14 @@ namespace nmf {
 namespace {
 
 typedef double v4d __attribute__((ext_vector_type(4)));
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+
+// FP32 -> BF16 bits, round to nearest even (finite inputs).
+__device__ __forceinline__ uint16_t bf16_rne(float x) {
+    uint32_t u = __float_as_uint(x);
+    u += 0x7FFFu + ((u >> 16) & 1u);
+    return (uint16_t)(u >> 16);
+}
 
 constexpr int MODE_HALS = 0, MODE_MU = 1, MODE_STORE = 2, MODE_INIT = 3;
 
@@ -208,7 +216,7 @@ constexpr int apass_lds_doubles(bool upd) {
     return (upd ? (RT * 16) * (RT * 16 + 1) + RT * 16 : 0) + 4 * 16 * RW * (RT * 16 + 1);
 }
 
-template <int RT, int RW, int WN, int S, int MODE>
+template <int RT, int RW, int WN, int S, int MODE, bool BF>
 __device__ void apass_tile(const Job &J, int tile, double *smem) {
     constexpr int RPAD = RT * 16, WR = 4 / WN, TMW = 16 * RW, TM = TMW * WR;
     constexpr int AS = RPAD + 1, GS = RPAD + 1;
@@ -291,25 +299,94 @@ __device__ void apass_tile(const Job &J, int tile, double *smem) {
             }
         }
     }
-    if (s_begin < s_end) load(s_begin, a0, b0);
-    // the Gram goes to LDS while the first operand batch is in flight
-    if constexpr (UPD) load_gram<RPAD>(J.Bd, r, Gs, GS, Gi);
-    for (int64_t s = s_begin; s < s_end; s += 2 * S) {
-        if (s + S < s_end) load(s + S, a1, b1);
-        compute(a0, b0);
-        if (s + S >= s_end) break;
-        if (s + 2 * S < s_end) load(s + 2 * S, a0, b0);
-        compute(a1, b1);
-    }
-    // hi[q][t][v] + lo[q][t][v] = A[row0 + 16q + 4*lk + v][16t + li]
     double *Aw = As + wave * TMW * AS;
+    if constexpr (!BF) {
+        if (s_begin < s_end) load(s_begin, a0, b0);
+        // the Gram goes to LDS while the first operand batch is in flight
+        if constexpr (UPD) load_gram<RPAD>(J.Bd, r, Gs, GS, Gi);
+        for (int64_t s = s_begin; s < s_end; s += 2 * S) {
+            if (s + S < s_end) load(s + S, a1, b1);
+            compute(a0, b0);
+            if (s + S >= s_end) break;
+            if (s + 2 * S < s_end) load(s + 2 * S, a0, b0);
+            compute(a1, b1);
+        }
+        // hi[q][t][v] + lo[q][t][v] = A[row0 + 16q + 4*lk + v][16t + li]
 #pragma unroll
-    for (int q = 0; q < RW; ++q)
+        for (int q = 0; q < RW; ++q)
 #pragma unroll
-        for (int t = 0; t < RT; ++t)
+            for (int t = 0; t < RT; ++t)
 #pragma unroll
-            for (int v = 0; v < 4; ++v)
-                Aw[(16 * q + 4 * lk + v) * AS + 16 * t + li] = (double)hi[q][t][v] + (double)lo[q][t][v];
+                for (int v = 0; v < 4; ++v)
+                    Aw[(16 * q + 4 * lk + v) * AS + 16 * t + li] = (double)hi[q][t][v] + (double)lo[q][t][v];
+    } else {
+        // BF16 operands (v_mfma_f32_16x16x32_bf16, FP32 accumulation): K-steps of
+        // 32 columns; lane (li, lk) supplies row li of a 16-row panel at columns
+        // 8*lk..8*lk+7 from the K-packed copy of M (16 bytes), and row 16t + li of
+        // W at the same columns from its BF16 copy.
+        constexpr int SB = 2;
+        const int64_t ksteps = J.npad / 32, kper = (ksteps + WN - 1) / WN;
+        const int64_t k_begin = wn * kper;
+        const int64_t k_end = (k_begin + kper < ksteps) ? k_begin + kper : ksteps;
+        const int64_t G = J.npad / 8;
+        const uint16_t *Mp[RW];
+        bool pok[RW];
+#pragma unroll
+        for (int q = 0; q < RW; ++q) {
+            const int64_t pr = row0 + 16 * q;          // first row of the panel
+            pok[q] = pr < m;
+            Mp[q] = J.Mbp + (pok[q] ? ((pr / 16) * G * 16 + li) * 8 + lk * 128 : 0);
+        }
+        const uint16_t *Wr[RT];
+#pragma unroll
+        for (int t = 0; t < RT; ++t) Wr[t] = J.Wb + (int64_t)(16 * t + li) * J.npad + 8 * lk;
+        v4f acc[RW][RT];
+#pragma unroll
+        for (int q = 0; q < RW; ++q)
+#pragma unroll
+            for (int t = 0; t < RT; ++t) acc[q][t] = v4f{0.0f, 0.0f, 0.0f, 0.0f};
+        bf16x8 ma0[SB][RW], wb0[SB][RT], ma1[SB][RW], wb1[SB][RT];
+        const bf16x8 z8 = {};
+        auto loadb = [&](int64_t k0, bf16x8 (&a)[SB][RW], bf16x8 (&b)[SB][RT]) {
+#pragma unroll
+            for (int u = 0; u < SB; ++u) {
+                const int64_t kk = k0 + u;
+                const bool ok = kk < k_end;
+#pragma unroll
+                for (int q = 0; q < RW; ++q)
+                    a[u][q] = (ok && pok[q]) ? *(const bf16x8 *)(Mp[q] + kk * 512) : z8;
+#pragma unroll
+                for (int t = 0; t < RT; ++t) b[u][t] = ok ? *(const bf16x8 *)(Wr[t] + 32 * kk) : z8;
+            }
+        };
+        auto computeb = [&](const bf16x8 (&a)[SB][RW], const bf16x8 (&b)[SB][RT]) {
+#pragma unroll
+            for (int u = 0; u < SB; ++u)
+#pragma unroll
+                for (int q = 0; q < RW; ++q)
+#pragma unroll
+                    for (int t = 0; t < RT; ++t)
+                        acc[q][t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[u][q], b[u][t],
+                                                                            acc[q][t], 0, 0, 0);
+        };
+        if (k_begin < k_end) loadb(k_begin, ma0, wb0);
+        if constexpr (UPD) load_gram<RPAD>(J.Bd, r, Gs, GS, Gi);
+        for (int64_t k0 = k_begin; k0 < k_end; k0 += 2 * SB) {
+            if (k0 + SB < k_end) loadb(k0 + SB, ma1, wb1);
+            computeb(ma0, wb0);
+            if (k0 + SB >= k_end) break;
+            if (k0 + 2 * SB < k_end) loadb(k0 + 2 * SB, ma0, wb0);
+            computeb(ma1, wb1);
+        }
+        // acc[q][t][v] = A[row0 + 16q + 4*lk + v][16t + li]
+#pragma unroll
+        for (int q = 0; q < RW; ++q)
+#pragma unroll
+            for (int t = 0; t < RT; ++t)
+#pragma unroll
+                for (int v = 0; v < 4; ++v)
+                    Aw[(16 * q + 4 * lk + v) * AS + 16 * t + li] = (double)acc[q][t][v];
+    }
     __syncthreads();
     if constexpr (WN > 1) {
         for (int e = tid; e < TM * RPAD; e += 256) {
@@ -341,13 +418,15 @@ __device__ void apass_tile(const Job &J, int tile, double *smem) {
                 for (int t = 0; t < RT; ++t) {
                     const int k = 16 * t + p;
                     if (k < r) J.V[vrow + (int64_t)k * m] = (float)xv[i][t];
+                    // BF16 copy of the new row for the C-pass (k >= r stays 0)
+                    if constexpr (BF) J.Vb[vrow + (int64_t)k * J.mpad] = bf16_rne((float)xv[i][t]);
                 }
             }
         }
     }
 }
 
-template <int RT, int RW, int WN, int S, int MODE>
+template <int RT, int RW, int WN, int S, int MODE, bool BF>
 __global__ __launch_bounds__(256) void k_apass(const Job *__restrict__ jobs,
                                                const int2 *__restrict__ bmap) {
     extern __shared__ double smem[];
@@ -362,7 +441,7 @@ __global__ __launch_bounds__(256) void k_apass(const Job *__restrict__ jobs,
         if (jt.y >= J.nA) return;
     }
     if (J.st->stop) return;
-    apass_tile<RT, RW, WN, S, MODE>(J, jt.y, smem);
+    apass_tile<RT, RW, WN, S, MODE, BF>(J, jt.y, smem);
 }
 
 // ---------------------------------------------------------------------------
@@ -373,7 +452,7 @@ __global__ __launch_bounds__(256) void k_apass(const Job *__restrict__ jobs,
 // The same V registers feed the FP64 MFMAs of the chunk's partial V^T V: its
 // upper-triangle 16x16 tiles are spread over the waves of the chunk's tiles.
 // ---------------------------------------------------------------------------
-template <int RT, int SB>
+template <int RT, int SB, bool BF>
 __device__ void cpass_tile(const Job &J, int tx, int ty, int ntx) {
     constexpr int RPAD = RT * 16, DMAX = 3;
     const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
@@ -467,16 +546,83 @@ __device__ void cpass_tile(const Job &J, int tx, int ty, int ntx) {
             }
         }
     };
-    if (i_begin < i_end) {
-        v4f m0[SB], m1[SB], v0[SB][RT], v1[SB][RT];
-        load(i_begin, m0, v0);
-        for (int64_t i0 = i_begin; i0 < i_end; i0 += 32 * SB) {
-            const bool more = i0 + 16 * SB < i_end;
-            if (more) load(i0 + 16 * SB, m1, v1);
-            compute(m0, v0);
-            if (!more) break;
-            if (i0 + 32 * SB < i_end) load(i0 + 32 * SB, m0, v0);
-            compute(m1, v1);
+    if constexpr (!BF) {
+        if (i_begin < i_end) {
+            v4f m0[SB], m1[SB], v0[SB][RT], v1[SB][RT];
+            load(i_begin, m0, v0);
+            for (int64_t i0 = i_begin; i0 < i_end; i0 += 32 * SB) {
+                const bool more = i0 + 16 * SB < i_end;
+                if (more) load(i0 + 16 * SB, m1, v1);
+                compute(m0, v0);
+                if (!more) break;
+                if (i0 + 32 * SB < i_end) load(i0 + 32 * SB, m0, v0);
+                compute(m1, v1);
+            }
+        }
+    } else {
+        // C on BF16 operands, K-steps of 32 rows (chunks are multiples of 32,
+        // the copies are zero past row m): lane (lj, lg) supplies rows
+        // i0 + 8*lg..+7 of column j from the column-major BF16 M, and of
+        // column 16t + lj from the BF16 V (16 bytes each).
+        constexpr int KB = 2;
+        const int64_t mp = J.mpad;
+        const uint16_t *Mb = J.Mbc + (jok ? j : 0) * mp + 8 * lg;
+        const uint16_t *Vr[RT];
+#pragma unroll
+        for (int t = 0; t < RT; ++t) Vr[t] = J.Vb + (int64_t)(16 * t + lj) * mp + 8 * lg;
+        const bf16x8 z8 = {};
+        v4f acc[RT];
+#pragma unroll
+        for (int t = 0; t < RT; ++t) acc[t] = v4f{0.0f, 0.0f, 0.0f, 0.0f};
+        bf16x8 ma0[KB], vb0[KB][RT], ma1[KB], vb1[KB][RT];
+        auto loadb = [&](int64_t i0, bf16x8 (&a)[KB], bf16x8 (&b)[KB][RT]) {
+#pragma unroll
+            for (int u = 0; u < KB; ++u) {
+                const int64_t ik = i0 + 32 * u;
+                const bool ok = ik < i_end;
+                a[u] = (ok && jok) ? *(const bf16x8 *)(Mb + ik) : z8;
+#pragma unroll
+                for (int t = 0; t < RT; ++t) b[u][t] = ok ? *(const bf16x8 *)(Vr[t] + ik) : z8;
+            }
+        };
+        auto computeb = [&](const bf16x8 (&a)[KB], const bf16x8 (&b)[KB][RT]) {
+#pragma unroll
+            for (int u = 0; u < KB; ++u)
+#pragma unroll
+                for (int t = 0; t < RT; ++t)
+                    acc[t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[u], b[u][t], acc[t], 0, 0, 0);
+        };
+        if (i_begin < i_end) {
+            loadb(i_begin, ma0, vb0);
+            for (int64_t i0 = i_begin; i0 < i_end; i0 += 64 * KB) {
+                const bool more = i0 + 32 * KB < i_end;
+                if (more) loadb(i0 + 32 * KB, ma1, vb1);
+                computeb(ma0, vb0);
+                if (!more) break;
+                if (i0 + 64 * KB < i_end) loadb(i0 + 64 * KB, ma0, vb0);
+                computeb(ma1, vb1);
+            }
+        }
+#pragma unroll
+        for (int t = 0; t < RT; ++t) hi[t] = acc[t];
+        // D = V^T V partial in FP64 from the FP32 V (waves that own D tiles)
+        if (nd > 0) {
+            for (int64_t i0 = i_begin; i0 < i_end; i0 += 16) {
+#pragma unroll
+                for (int d = 0; d < DMAX; ++d) {
+                    if (d < nd) {
+                        const int ka = 16 * dta[d] + lj, kb = 16 * dtb[d] + lj;
+#pragma unroll
+                        for (int s2 = 0; s2 < 4; ++s2) {
+                            const int64_t i = i0 + 4 * lg + s2;
+                            const bool iok = i < i_end;
+                            const double va = (iok && ka < r) ? (double)V[i + (int64_t)ka * m] : 0.0;
+                            const double vb = (iok && kb < r) ? (double)V[i + (int64_t)kb * m] : 0.0;
+                            dacc[d] = __builtin_amdgcn_mfma_f64_16x16x4f64(va, vb, dacc[d], 0, 0, 0);
+                        }
+                    }
+                }
+            }
         }
     }
     // hi[t][v] + lo[t][v] = C[k = 16t + lj][j = jb + 4*lg + v]
@@ -504,7 +650,7 @@ __device__ void cpass_tile(const Job &J, int tx, int ty, int ntx) {
     }
 }
 
-template <int RT, int SB>
+template <int RT, int SB, bool BF>
 __global__ __launch_bounds__(256) void k_cpass(const Job *__restrict__ jobs,
                                                const int2 *__restrict__ bmap) {
     const int2 jt = block_job(bmap);
@@ -519,7 +665,7 @@ __global__ __launch_bounds__(256) void k_cpass(const Job *__restrict__ jobs,
         if (ty >= J.chunks) return;
     }
     if (J.st->stop) return;
-    cpass_tile<RT, SB>(J, tx, ty, J.nCx);
+    cpass_tile<RT, SB, BF>(J, tx, ty, J.nCx);
 }
 
 // ---------------------------------------------------------------------------
@@ -568,7 +714,7 @@ __global__ __launch_bounds__(256) void k_reduce(const Job *__restrict__ jobs,
             if (!isfinite(e2)) {
                 st->status = NMF_E_NONFINITE;
                 st->stop = 1;
-            } else if (J.depth == 0 && J.tol > 0.0 && rel <= J.tol) {
+            } else if (J.depth == 0 && J.prec == 0 && J.tol > 0.0 && rel <= J.tol) {
                 st->stopped = 1;
                 st->stop = 1;
             }
@@ -637,6 +783,7 @@ __device__ void cfinal_tile(const Job &J, int tile, double *smem) {
                 Wn[jj * CS + k] = (double)xf;
                 if (ok) {
                     J.Wt[j * RPAD + k] = xf;
+                    if (J.Wb) J.Wb[(int64_t)k * J.npad + j] = bf16_rne(xf);   // BF16 mode
                     if (UPD && k < r) {
                         J.W[(int64_t)k * n + j] = xf;
                         part_cw += Cs[jj * CS + k] * (double)xf;
@@ -743,44 +890,64 @@ size_t cfinal_lds_bytes(int rpad, int mode) {
 // Tile configurations of the A-pass, by rank class and rows per tile: 16-row
 // tiles whose 4 waves split n with deep register batches (small m, latency
 // bound), or 64-row tiles of two 32-row groups with two waves each (large m).
-template <int RT, int MODE>
+template <int RT, int MODE, bool BF>
 static void apass_launch(int tm, const Job *jobs, const int2 *bmap, int blocks,
                          size_t lds, hipStream_t s) {
     constexpr int S16 = 4;
     constexpr int S64 = 4;
-    if (tm == 16) k_apass<RT, 1, 4, S16, MODE><<<blocks, 256, lds, s>>>(jobs, bmap);
-    else k_apass<RT, 2, 2, S64, MODE><<<blocks, 256, lds, s>>>(jobs, bmap);
+    if (tm == 16) k_apass<RT, 1, 4, S16, MODE, BF><<<blocks, 256, lds, s>>>(jobs, bmap);
+    else k_apass<RT, 2, 2, S64, MODE, BF><<<blocks, 256, lds, s>>>(jobs, bmap);
 }
 
 template <int RT>
-static void apass_launch_mode(int mode, int tm, const Job *jobs, const int2 *bmap,
+static void apass_launch_mode(int mode, int tm, bool bf, const Job *jobs, const int2 *bmap,
                               int blocks, size_t lds, hipStream_t s) {
-    if (mode == MODE_HALS) apass_launch<RT, MODE_HALS>(tm, jobs, bmap, blocks, lds, s);
-    else if (mode == MODE_MU) apass_launch<RT, MODE_MU>(tm, jobs, bmap, blocks, lds, s);
-    else apass_launch<RT, MODE_STORE>(tm, jobs, bmap, blocks, lds, s);
+    if (bf) {
+        if (mode == MODE_HALS) apass_launch<RT, MODE_HALS, true>(tm, jobs, bmap, blocks, lds, s);
+        else apass_launch<RT, MODE_MU, true>(tm, jobs, bmap, blocks, lds, s);
+    } else if (mode == MODE_HALS) {
+        apass_launch<RT, MODE_HALS, false>(tm, jobs, bmap, blocks, lds, s);
+    } else if (mode == MODE_MU) {
+        apass_launch<RT, MODE_MU, false>(tm, jobs, bmap, blocks, lds, s);
+    } else {
+        apass_launch<RT, MODE_STORE, false>(tm, jobs, bmap, blocks, lds, s);
+    }
 }
 
 hipError_t launch_apass_jobs(int mode, int rpad, int tm, const Job *jobs, const int2 *bmap,
-                             int blocks, size_t lds, hipStream_t s) {
+                             int blocks, size_t lds, hipStream_t s, bool bf) {
     if (blocks <= 0) return hipSuccess;
+    if (bf && mode == MODE_STORE) return hipErrorInvalidValue;
     switch (rpad) {
-        case 16: apass_launch_mode<1>(mode, tm, jobs, bmap, blocks, lds, s); break;
-        case 32: apass_launch_mode<2>(mode, tm, jobs, bmap, blocks, lds, s); break;
-        case 48: apass_launch_mode<3>(mode, tm, jobs, bmap, blocks, lds, s); break;
-        case 64: apass_launch_mode<4>(mode, tm, jobs, bmap, blocks, lds, s); break;
+        case 16: apass_launch_mode<1>(mode, tm, bf, jobs, bmap, blocks, lds, s); break;
+        case 32: apass_launch_mode<2>(mode, tm, bf, jobs, bmap, blocks, lds, s); break;
+        case 48: apass_launch_mode<3>(mode, tm, bf, jobs, bmap, blocks, lds, s); break;
+        case 64: apass_launch_mode<4>(mode, tm, bf, jobs, bmap, blocks, lds, s); break;
         default: return hipErrorInvalidValue;
     }
     return hipGetLastError();
 }
 
 hipError_t launch_cpass_jobs(int rpad, const Job *jobs, const int2 *bmap, int blocks,
-                             hipStream_t s) {
+                             hipStream_t s, bool bf) {
     if (blocks <= 0) return hipSuccess;
     switch (rpad) {
-        case 16: k_cpass<1, 2><<<blocks, 256, 0, s>>>(jobs, bmap); break;
-        case 32: k_cpass<2, 2><<<blocks, 256, 0, s>>>(jobs, bmap); break;
-        case 48: k_cpass<3, 1><<<blocks, 256, 0, s>>>(jobs, bmap); break;
-        case 64: k_cpass<4, 1><<<blocks, 256, 0, s>>>(jobs, bmap); break;
+        case 16:
+            if (bf) k_cpass<1, 2, true><<<blocks, 256, 0, s>>>(jobs, bmap);
+            else k_cpass<1, 2, false><<<blocks, 256, 0, s>>>(jobs, bmap);
+            break;
+        case 32:
+            if (bf) k_cpass<2, 2, true><<<blocks, 256, 0, s>>>(jobs, bmap);
+            else k_cpass<2, 2, false><<<blocks, 256, 0, s>>>(jobs, bmap);
+            break;
+        case 48:
+            if (bf) k_cpass<3, 1, true><<<blocks, 256, 0, s>>>(jobs, bmap);
+            else k_cpass<3, 1, false><<<blocks, 256, 0, s>>>(jobs, bmap);
+            break;
+        case 64:
+            if (bf) k_cpass<4, 1, true><<<blocks, 256, 0, s>>>(jobs, bmap);
+            else k_cpass<4, 1, false><<<blocks, 256, 0, s>>>(jobs, bmap);
+            break;
         default: return hipErrorInvalidValue;
     }
     return hipGetLastError();
@@ -848,8 +1015,12 @@ static void lds_attr(hipError_t &e) {
         hipError_t x = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
         if (x != hipSuccess && e == hipSuccess) e = x;
     };
-    set((const void *)k_apass<RT, 1, 4, S16, MODE>);
-    set((const void *)k_apass<RT, 2, 2, S64, MODE>);
+    set((const void *)k_apass<RT, 1, 4, S16, MODE, false>);
+    set((const void *)k_apass<RT, 2, 2, S64, MODE, false>);
+    if constexpr (MODE != MODE_STORE) {
+        set((const void *)k_apass<RT, 1, 4, S16, MODE, true>);
+        set((const void *)k_apass<RT, 2, 2, S64, MODE, true>);
+    }
     set((const void *)k_cfinal<RT, MODE>);
 }
 

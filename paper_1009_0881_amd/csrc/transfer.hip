@@ -193,6 +193,54 @@ __global__ void k_state_reset(DevState *st) {
     }
 }
 
+// ---- BF16 operand copies ---------------------------------------------------------
+
+// FP32 -> BF16, round to nearest even (inputs are finite).
+__device__ __forceinline__ uint16_t bf16_rne(float x) {
+    uint32_t u = __float_as_uint(x);
+    u += 0x7FFFu + ((u >> 16) & 1u);
+    return (uint16_t)(u >> 16);
+}
+
+// Y (rows_pad x cols_pad, column stride rows_pad) = BF16 of X (rows x cols,
+// column stride ldx), zero outside.  Grid: x over rows_pad, y over cols_pad.
+__global__ __launch_bounds__(256) void k_to_bf16_cols(const float *__restrict__ X, int64_t ldx,
+                                                      int64_t rows, int64_t cols,
+                                                      uint16_t *__restrict__ Y, int64_t rows_pad,
+                                                      int64_t cols_pad) {
+    const int64_t i = blockIdx.x * (int64_t)256 + threadIdx.x;
+    if (i >= rows_pad) return;
+    for (int64_t c = blockIdx.y; c < cols_pad; c += gridDim.y)
+        Y[c * rows_pad + i] = (i < rows && c < cols) ? bf16_rne(X[c * ldx + i]) : (uint16_t)0;
+}
+
+// K-packed copy for the A-pass: element (i, j) of X (rows x cols, column
+// stride ldx) at ((i/16 * G + j/8) * 16 + i%16) * 8 + j%8, G = cols_pad / 8,
+// zero outside.  One thread per 8-column group of one row.
+__global__ __launch_bounds__(256) void k_pack_bf16(const float *__restrict__ X, int64_t ldx,
+                                                   int64_t rows, int64_t cols,
+                                                   uint16_t *__restrict__ Y, int64_t rows16,
+                                                   int64_t cols_pad) {
+    const int64_t G = cols_pad / 8;
+    const int64_t e = blockIdx.x * (int64_t)256 + threadIdx.x;   // (panel, group, row in panel)
+    if (e >= rows16 / 16 * G * 16) return;
+    const int ii = (int)(e & 15);
+    const int64_t pg = e >> 4, p = pg / G, g = pg - p * G;
+    const int64_t i = p * 16 + ii;
+    uint16_t v[8];
+#pragma unroll
+    for (int q = 0; q < 8; ++q) {
+        const int64_t j = g * 8 + q;
+        v[q] = (i < rows && j < cols) ? bf16_rne(X[j * ldx + i]) : (uint16_t)0;
+    }
+    uint4 w;
+    w.x = v[0] | ((uint32_t)v[1] << 16);
+    w.y = v[2] | ((uint32_t)v[3] << 16);
+    w.z = v[4] | ((uint32_t)v[5] << 16);
+    w.w = v[6] | ((uint32_t)v[7] << 16);
+    *reinterpret_cast<uint4 *>(Y + e * 8) = w;
+}
+
 // ---- grouped setup kernels (one launch over many problems) ------------------
 
 __global__ __launch_bounds__(256) void k_xfer_many(const XferJob *__restrict__ jobs,
@@ -324,6 +372,24 @@ hipError_t launch_gather_states(DevState *const *states, int count, DevState *ou
                                 hipStream_t s) {
     if (count <= 0) return hipSuccess;
     k_gather_states<<<(count + 255) / 256, 256, 0, s>>>(states, count, out);
+    return hipGetLastError();
+}
+
+hipError_t launch_to_bf16_cols(const float *X, int64_t ldx, int64_t rows, int64_t cols,
+                               uint16_t *Y, int64_t rows_pad, int64_t cols_pad, hipStream_t s) {
+    if (rows_pad <= 0 || cols_pad <= 0) return hipSuccess;
+    const dim3 grid((unsigned)((rows_pad + 255) / 256), (unsigned)std::min<int64_t>(cols_pad, 65535));
+    k_to_bf16_cols<<<grid, 256, 0, s>>>(X, ldx, rows, cols, Y, rows_pad, cols_pad);
+    return hipGetLastError();
+}
+
+hipError_t launch_pack_bf16(const float *X, int64_t ldx, int64_t rows, int64_t cols, uint16_t *Y,
+                            int64_t cols_pad, hipStream_t s) {
+    const int64_t rows16 = (rows + 15) / 16 * 16;
+    const int64_t total = rows16 / 16 * (cols_pad / 8) * 16;
+    if (total <= 0) return hipSuccess;
+    k_pack_bf16<<<(unsigned)((total + 255) / 256), 256, 0, s>>>(X, ldx, rows, cols, Y, rows16,
+                                                                cols_pad);
     return hipGetLastError();
 }
 
