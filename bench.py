@@ -34,6 +34,7 @@ sys.path.insert(0, ROOT)
 
 PEAK_HBM_GBS = 8000.0          # MI355X HBM3E
 PEAK_FP32_MFMA_TFLOPS = 157.3  # MI355X dense FP32 matrix
+PEAK_BF16_MFMA_TFLOPS = 2500.0  # MI355X dense BF16 matrix
 
 EXTRA_WORKLOADS = ("batch", "serve")
 
@@ -75,7 +76,7 @@ def level_sides(h, w, levels):
     return out
 
 
-def kernel_bytes_flops(kind, m, n, r):
+def kernel_bytes_flops(kind, m, n, r, bf=False):
     """Algorithmic HBM bytes and flops of one launch at a level with m pixels.
 
     Only what the method must move counts: M streamed once per pass (FP32),
@@ -83,10 +84,13 @@ def kernel_bytes_flops(kind, m, n, r):
     partials are overhead of this implementation and show up in the measured
     traffic instead.
     """
+    b = 2 if bf else 4            # bytes per element of the M / W / V operand copies
     if kind == "apass":           # A = M W^T fused with the V update: read M, W, V; write V
-        return 4 * m * n + 4 * r * n + 8 * m * r + 8 * r * r, 2 * m * n * r + 4 * m * r * r
+        return (b * m * n + b * r * n + 8 * m * r + (2 * m * r if bf else 0) + 8 * r * r,
+                2 * m * n * r + 4 * m * r * r)
     if kind == "cpass_partial":   # C = V^T M and D = V^T V: read M, V; write C
-        return 4 * m * n + 4 * m * r + 4 * r * n, 2 * m * n * r + 2 * m * r * r
+        return (b * m * n + b * m * r + (4 * m * r if bf else 0) + 4 * r * n,
+                2 * m * n * r + 2 * m * r * r)
     if kind == "cpass_final":     # W update and W W^T: read C, read/write W
         return 4 * r * n + 8 * r * n + 8 * r * r, 6 * n * r * r
     return 0, 0
@@ -260,6 +264,10 @@ def main() -> int:
     ap.add_argument("--tau", type=float, default=1e-2)
     ap.add_argument("--seed", type=int, default=0)
     ap.add_argument("--max-fine-iters", type=int, default=20000)
+    ap.add_argument("--prec", default="fp32", choices=["fp32", "bf16"],
+                    help="multilevel solve precision (bf16: BF16 MFMA passes, then FP32 "
+                         "refinement on the finest level)")
+    ap.add_argument("--refine", type=int, default=4, help="bf16: FP32 refinement iterations")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     args = ap.parse_args()
@@ -305,13 +313,15 @@ def main() -> int:
     Vs = [V0d.clone() for _ in range(nbuf)]
     Ws = [W0d.clone() for _ in range(nbuf)]
 
-    def make_plan(L):
+    def make_plan(L, prec="fp32"):
         return P.Plan(m=m, n=n, h=wl["h"], w=wl["w"], r=r, levels=L, algo=args.algo,
                       cycle=args.cycle, xfer=wl["xfer"], tol=target,
-                      max_fine_iters=args.max_fine_iters, check_every=4)
+                      max_fine_iters=args.max_fine_iters, check_every=4, prec=prec,
+                      refine_iters=args.refine if prec == "bf16" else 0)
 
-    ml = make_plan(levels)
+    ml = make_plan(levels, args.prec)
     sl = make_plan(1)
+    n_sched = sum(c for k, _, c in ml.schedule(args.budget) if k == "run")
     ws_ml, ws_sl = ml.workspace(), sl.workspace()
     stream = torch.cuda.current_stream()
 
@@ -365,13 +375,15 @@ def main() -> int:
     # --- roofline of the dominant kernel --------------------------------------
     sides = level_sides(wl["h"], wl["w"], levels)
     tot_bytes = tot_flops = 0
-    for d in dep_log:
-        b, f = kernel_bytes_flops(dominant, sides[d][0] * sides[d][1], n, r)
+    for it, d in enumerate(dep_log):
+        b, f = kernel_bytes_flops(dominant, sides[d][0] * sides[d][1], n, r,
+                                  bf=args.prec == "bf16" and it < n_sched)
         tot_bytes += b
         tot_flops += f
     traffic = None
     tab = TRAFFIC.get(args.workload, {}).get(dominant)
-    if tab and kernel_sources_sha() == TRAFFIC["sha"] and levels == wl["levels"]:
+    if (tab and kernel_sources_sha() == TRAFFIC["sha"] and levels == wl["levels"]
+            and args.prec == "fp32"):
         ms_ = [sides[d][0] * sides[d][1] for d in dep_log]
         if all(m_ in tab for m_ in ms_):
             traffic = int(sum(tab[m_] for m_ in ms_) / max(1, len(ms_)))
@@ -395,7 +407,9 @@ def main() -> int:
         "launches_per_solve": launches_per_solve,
         "algorithmic_bytes_per_launch": int(per_launch_bytes),
         "mfma_tflops": round(per_launch_flops / avg_s / 1e12, 3) if avg_s > 0 else 0.0,
-        "mfma_frac": round(per_launch_flops / avg_s / 1e12 / PEAK_FP32_MFMA_TFLOPS, 4) if avg_s > 0 else 0.0,
+        "mfma_frac": round(per_launch_flops / avg_s / 1e12 / (PEAK_BF16_MFMA_TFLOPS if args.prec == "bf16"
+                                                              else PEAK_FP32_MFMA_TFLOPS), 4)
+        if avg_s > 0 else 0.0,
     }
     kernels = {k: {"launches_per_solve": v[0], "avg_us": round(v[1] / max(1, v[0]) * 1e3, 3),
                    "ms_per_solve": round(v[1], 4)} for k, v in prof_all.items()}
@@ -441,12 +455,14 @@ def main() -> int:
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f32",
+        "dtype": "bf16+f32" if args.prec == "bf16" else "f32",
         "data": "synthetic",
         "config": {
             "workload": f"{args.workload}: {wl['h']}x{wl['w']} planted-blob images, n={n}, r={r}, "
                         f"{levels} levels ({wl['xfer']}), {args.cycle.upper()} {args.algo.upper()} "
-                        f"FP32, budget T={args.budget}, target rel_err <= eps_E+{args.tau:g}",
+                        + ("BF16 GEMMs, FP32 accumulation, " + str(args.refine) + " FP32 refinement "
+                           "iterations on the finest level" if args.prec == "bf16" else "FP32")
+                        + f", budget T={args.budget}, target rel_err <= eps_E+{args.tau:g}",
             "m": m, "n": n, "r": r, "levels": levels, "algo": args.algo, "cycle": args.cycle,
             "seed": args.seed,
         },
