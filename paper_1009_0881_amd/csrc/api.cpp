@@ -141,8 +141,18 @@ Ctx make_ctx(nmf_plan_t plan, const float *dM, float *dV, float *dW, void *dws, 
         J.st = c.st;
         J.tol = p.d.tol;
         J.prec = 0;
+        J.stream = 0;
         if (p.d.prec == NMF_BF16) {
             J.prec = 1;
+            if (li.stream) {     // streaming kernels: 256-row / 256-column tiles
+                J.stream = 1;
+                J.tm = 256;
+                J.nA = (int32_t)((li.m + 255) / 256);
+                J.nCx = (int32_t)((p.d.n + 255) / 256);
+                J.chunks = li.scp_chunks;
+                J.chunk = li.scp_chunk;
+                J.nC = J.nCx * J.chunks;
+            }
             J.mpad = li.mpad;
             J.npad = (p.d.n + 31) / 32 * 32;
             J.Mbp = at<uint16_t>(c.ws, li.off_Mbp);
@@ -154,6 +164,16 @@ Ctx make_ctx(nmf_plan_t plan, const float *dM, float *dV, float *dW, void *dws, 
     }
     // entry L: the finest level in FP32 (refinement iterations of BF16 mode)
     Job J0 = c.jobs[0];
+    if (J0.stream) {     // the FP32 job uses the regular tiling of level 0
+        const LevelInfo &l0 = p.lv[0];
+        J0.stream = 0;
+        J0.tm = apass_rows_per_block(l0.m);
+        J0.nA = (int32_t)((l0.m + J0.tm - 1) / J0.tm);
+        J0.nCx = (int32_t)((p.d.n + 63) / 64);
+        J0.chunks = l0.cp_chunks;
+        J0.chunk = l0.cp_chunk;
+        J0.nC = J0.nCx * J0.chunks;
+    }
     J0.prec = 0;
     J0.Mbp = J0.Mbc = nullptr;
     J0.Vb = J0.Wb = nullptr;
@@ -229,12 +249,20 @@ nmf_status sweep(Ctx &c, int d, bool fp32 = false) {
     const int64_t n = p.d.n;
     int32_t *flags = &c.st->flags;
     const int mode = p.d.algo == NMF_HALS ? 0 : (p.d.algo == NMF_MU ? 1 : 2);
-    NMF_LAUNCH(K_APASS, launch_apass_jobs(mode, J.rpad, J.tm, dj, nullptr, apass_grid_single(J.nA),
-                                          apass_lds_bytes(J.rpad, J.tm, mode), c.s, bf));
+    if (J.stream)
+        NMF_LAUNCH(K_APASS, launch_apass_stream(mode, J.rpad, dj, nullptr, J.nA, c.s));
+    else
+        NMF_LAUNCH(K_APASS, launch_apass_jobs(mode, J.rpad, J.tm, dj, nullptr,
+                                              apass_grid_single(J.nA),
+                                              apass_lds_bytes(J.rpad, J.tm, mode), c.s, bf));
     if (mode == 2)
         NMF_LAUNCH(K_NNLS_ROWS, launch_nnls_rows(p.rpad, c.Bd, c.A, J.m, r, J.V, flags, c.stop, c.s));
-    NMF_LAUNCH(K_CPART, launch_cpass_jobs(J.rpad, dj, nullptr, cpass_grid_single(J.nCx, J.chunks),
-                                          c.s, bf));
+    if (J.stream)
+        NMF_LAUNCH(K_CPART, launch_cpass_stream(J.rpad, dj, nullptr,
+                                                cpass_stream_grid(J.nCx, J.chunks), c.s));
+    else
+        NMF_LAUNCH(K_CPART, launch_cpass_jobs(J.rpad, dj, nullptr,
+                                              cpass_grid_single(J.nCx, J.chunks), c.s, bf));
     NMF_LAUNCH(K_GRAM_V, launch_reduce_jobs(0, dj, nullptr, J.nG, c.s));
     NMF_LAUNCH(K_CFINAL, launch_cfinal_jobs(mode, J.rpad, dj, nullptr, J.nF,
                                             cfinal_lds_bytes(J.rpad, mode), c.s));

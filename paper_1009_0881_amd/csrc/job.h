@@ -48,7 +48,9 @@ struct Job {
     const uint16_t *Mbp, *Mbc;
     uint16_t *Vb, *Wb;
     int64_t mpad, npad;
-    int32_t prec, pad_;
+    int32_t prec;
+    int32_t stream;      // 1: streaming A/C-pass kernels (large BF16 levels): A-pass
+                         // tiles of 256 rows, C-pass tiles of 256 columns
 };
 
 }  // namespace nmf

@@ -45,7 +45,10 @@ struct LevelInfo {
     size_t off_Mbp, off_Mbc, off_Vb;   // BF16 mode: copies of M_l (A-pass, C-pass layouts), V_l
     int64_t mpad;        // m rounded up to 32 (column stride of the BF16 copies)
     int32_t cp_chunks;   // split of the m-reduction in V^T M
-    int64_t cp_chunk;    // rows per chunk (multiple of 16)
+    int64_t cp_chunk;    // rows per chunk (multiple of 16; 32 in BF16 mode)
+    bool stream;         // BF16 mode, large level: streaming A/C-pass kernels
+    int32_t scp_chunks;  // split of the m-reduction for the streaming C-pass
+    int64_t scp_chunk;
     int32_t gram_parts;  // split of the length-m reduction of V^T V
     int64_t gram_chunk;
 };
@@ -170,6 +173,15 @@ int cpass_final_blocks(int64_t n);
 // blocks are mapped to tiles XCD by XCD.
 int apass_grid_single(int nA);
 int cpass_grid_single(int nCx, int chunks);
+// Streaming BF16 passes (job.stream): A-pass tiles of 256 rows (nA blocks),
+// C-pass tiles of 256 columns x one row chunk (XCD-ordered grid).
+constexpr int64_t kStreamMinRows = 32768;
+hipError_t launch_apass_stream(int mode, int rpad, const Job *jobs, const int2 *bmap, int blocks,
+                               hipStream_t s);
+hipError_t launch_cpass_stream(int rpad, const Job *jobs, const int2 *bmap, int blocks,
+                               hipStream_t s);
+int cpass_stream_grid(int nCx, int chunks);
+size_t apass_stream_lds_bytes(int rpad);
 hipError_t launch_make_wt(const float *W, int64_t n, int r, int rpad, float *Wt, hipStream_t s);
 // Residual from separately computed Grams (ANLS path): rel_err of
 // ||M||^2 - 2 sum(rparts) + <Dd, Bd>, logged at st->log_len.

@@ -85,7 +85,7 @@ __device__ __forceinline__ int ordered_after(int v, double dep) {
 // HALS / MU update of one factor row held by a row of 16 lanes, lane p
 // holding entries k = 16t + p.  G is the r x r FP64 Gram of the other factor
 // in LDS (row stride gs, zero-padded to RPAD), gi[k] = 1/G_kk (0 when
-// G_kk = 0 or k >= r), a[k] the matching row of the product (FP64, LDS).  The
+// G_kk = 0 or k >= r), a[t] entry 16t + p of the matching row of the product.  The
 // r x r-sized update arithmetic runs in FP64 (the numerator
 // a_k - sum_l x_l G_lk cancels as the iterate converges); the row is read from
 // and written back to FP32 storage by the caller.
@@ -98,7 +98,8 @@ __device__ __forceinline__ int ordered_after(int v, double dep) {
 // MU (Alg. 2): x_k <- x_k a_k / (sum_l x_l G_lk); a zero denominator keeps x_k.
 template <int RT, int MODE>
 __device__ __forceinline__ void row_update(double (&x)[RT], const double *G, int gs,
-                                           const double *gi, const double *a, int r, int p) {
+                                           const double *gi, const double (&a)[RT], int r,
+                                           int p) {
     constexpr int RPAD = 16 * RT;
     double acc[RT];
 #pragma unroll
@@ -123,7 +124,7 @@ __device__ __forceinline__ void row_update(double (&x)[RT], const double *G, int
 #pragma unroll
         for (int t = 0; t < RT; ++t) {
             const int k = 16 * t + p;
-            g[t] = k < r ? a[k] - acc[t] : 0.0;
+            g[t] = k < r ? a[t] - acc[t] : 0.0;
             ginv[t] = gi[k];
             row0[t] = G[k];                  // Gram row 0
             row1[t] = G[gs + k];             // Gram row 1
@@ -159,7 +160,7 @@ __device__ __forceinline__ void row_update(double (&x)[RT], const double *G, int
 #pragma unroll
         for (int t = 0; t < RT; ++t) {
             const int k = 16 * t + p;
-            if (k < r && acc[t] > 0.0) x[t] = x[t] * a[k] / acc[t];
+            if (k < r && acc[t] > 0.0) x[t] = x[t] * a[t] / acc[t];
         }
     }
 }
@@ -412,7 +413,10 @@ __device__ void apass_tile(const Job &J, int tile, double *smem) {
         for (int i = 0; i < EPR; ++i) {
             const int er = (tid >> 4) + 16 * i, p = tid & 15;
             const int64_t vrow = brow + er;
-            row_update<RT, MODE>(xv[i], Gs, GS, Gi, arow(er), r, p);
+            double av[RT];
+#pragma unroll
+            for (int t = 0; t < RT; ++t) av[t] = arow(er)[16 * t + p];
+            row_update<RT, MODE>(xv[i], Gs, GS, Gi, av, r, p);
             if (vrow < m) {
 #pragma unroll
                 for (int t = 0; t < RT; ++t) {
@@ -775,7 +779,12 @@ __device__ void cfinal_tile(const Job &J, int tile, double *smem) {
             const int jj = tid >> 4, p = tid & 15;
             const int64_t j = j0 + jj;
             const bool ok = j < n;
-            if constexpr (UPD) row_update<RT, MODE>(xw, Gs, GS, Gi, Cs + jj * CS, r, p);
+            if constexpr (UPD) {
+                double cv[RT];
+#pragma unroll
+                for (int t = 0; t < RT; ++t) cv[t] = Cs[jj * CS + 16 * t + p];
+                row_update<RT, MODE>(xw, Gs, GS, Gi, cv, r, p);
+            }
 #pragma unroll
             for (int t = 0; t < RT; ++t) {
                 const int k = 16 * t + p;
@@ -865,6 +874,260 @@ __global__ __launch_bounds__(256) void k_residual(const double *__restrict__ rpa
             st->stop = 1;
         }
     }
+}
+
+// ---------------------------------------------------------------------------
+// Streaming passes for large levels in BF16 mode (job.stream = 1).
+//
+// A-pass: a block of 4 waves owns 256 rows; each wave owns 64 rows (four
+// 16-row panels) over all of n, so every W operand feeds four MFMAs and no
+// partial tiles are combined.  Operands are loaded two 32-column K-steps per
+// batch, double buffered.  The wave's A rows then go to a wave-private LDS
+// region (FP32) and are updated four at a time: row 16q + 4lk + v over the 16
+// lanes of lane group lk, entry 16t + li in lane li (the layout of
+// row_update).  The next row group's V entries are loaded while the current
+// one is updated.
+// ---------------------------------------------------------------------------
+template <int RT, int MODE>
+__device__ void apass_stream_tile(const Job &J, int tile, double *smem) {
+    constexpr int RPAD = RT * 16, GS = RPAD + 1, AS = RPAD + 1, RW = 4, SB = 2;
+    double *Gs = smem;
+    double *Gi = Gs + RPAD * GS;
+    const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+    const int li = lane & 15, lk = lane >> 4;
+    const int64_t m = J.m;
+    const int r = J.r;
+    const int64_t row0 = (int64_t)tile * 256 + wave * 64;
+    const int64_t ksteps = J.npad / 32, G = J.npad / 8;
+    const uint16_t *Mp[RW];
+    bool pok[RW];
+#pragma unroll
+    for (int q = 0; q < RW; ++q) {
+        const int64_t pr = row0 + 16 * q;
+        pok[q] = pr < m;
+        Mp[q] = J.Mbp + (pok[q] ? ((pr / 16) * G * 16 + li) * 8 + lk * 128 : 0);
+    }
+    const uint16_t *Wr[RT];
+#pragma unroll
+    for (int t = 0; t < RT; ++t) Wr[t] = J.Wb + (int64_t)(16 * t + li) * J.npad + 8 * lk;
+    v4f acc[RW][RT];
+#pragma unroll
+    for (int q = 0; q < RW; ++q)
+#pragma unroll
+        for (int t = 0; t < RT; ++t) acc[q][t] = v4f{0.0f, 0.0f, 0.0f, 0.0f};
+    const bf16x8 z8 = {};
+    bf16x8 a0[SB][RW], b0[SB][RT], a1[SB][RW], b1[SB][RT];
+    auto load = [&](int64_t k0, bf16x8 (&a)[SB][RW], bf16x8 (&b)[SB][RT]) {
+#pragma unroll
+        for (int u = 0; u < SB; ++u) {
+            const int64_t kk = k0 + u;
+            const bool ok = kk < ksteps;
+#pragma unroll
+            for (int q = 0; q < RW; ++q)
+                a[u][q] = (ok && pok[q]) ? *(const bf16x8 *)(Mp[q] + kk * 512) : z8;
+#pragma unroll
+            for (int t = 0; t < RT; ++t) b[u][t] = ok ? *(const bf16x8 *)(Wr[t] + 32 * kk) : z8;
+        }
+    };
+    auto compute = [&](const bf16x8 (&a)[SB][RW], const bf16x8 (&b)[SB][RT]) {
+#pragma unroll
+        for (int u = 0; u < SB; ++u)
+#pragma unroll
+            for (int q = 0; q < RW; ++q)
+#pragma unroll
+                for (int t = 0; t < RT; ++t)
+                    acc[q][t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[u][q], b[u][t], acc[q][t],
+                                                                        0, 0, 0);
+    };
+    if (ksteps > 0) load(0, a0, b0);
+    load_gram<RPAD>(J.Bd, r, Gs, GS, Gi);
+    for (int64_t k0 = 0; k0 < ksteps; k0 += 2 * SB) {
+        if (k0 + SB < ksteps) load(k0 + SB, a1, b1);
+        compute(a0, b0);
+        if (k0 + SB >= ksteps) break;
+        if (k0 + 2 * SB < ksteps) load(k0 + 2 * SB, a0, b0);
+        compute(a1, b1);
+    }
+    float *Aw = reinterpret_cast<float *>(Gi + RPAD) + wave * 64 * AS;
+#pragma unroll
+    for (int q = 0; q < RW; ++q)
+#pragma unroll
+        for (int t = 0; t < RT; ++t)
+#pragma unroll
+            for (int v = 0; v < 4; ++v) Aw[(16 * q + 4 * lk + v) * AS + 16 * t + li] = acc[q][t][v];
+    __syncthreads();   // Gram and A rows in LDS
+    auto load_x = [&](int g, double (&x)[RT]) {
+        const int64_t row = row0 + 16 * (g >> 2) + 4 * lk + (g & 3);
+#pragma unroll
+        for (int t = 0; t < RT; ++t) {
+            const int k = 16 * t + li;
+            x[t] = (row < m && k < r) ? (double)J.V[row + (int64_t)k * m] : 0.0;
+        }
+    };
+    double xc[RT], xn[RT];
+    load_x(0, xc);
+#pragma unroll 1
+    for (int g = 0; g < RW * 4; ++g) {
+        const int q = g >> 2, v = g & 3;
+        if (g + 1 < RW * 4) load_x(g + 1, xn);
+        double a[RT];
+#pragma unroll
+        for (int t = 0; t < RT; ++t) a[t] = (double)Aw[(16 * q + 4 * lk + v) * AS + 16 * t + li];
+        row_update<RT, MODE>(xc, Gs, GS, Gi, a, r, li);
+        const int64_t row = row0 + 16 * q + 4 * lk + v;
+        if (row < m) {
+#pragma unroll
+            for (int t = 0; t < RT; ++t) {
+                const int k = 16 * t + li;
+                if (k < r) J.V[row + (int64_t)k * m] = (float)xc[t];
+                J.Vb[row + (int64_t)k * J.mpad] = bf16_rne((float)xc[t]);
+            }
+        }
+#pragma unroll
+        for (int t = 0; t < RT; ++t) xc[t] = xn[t];
+    }
+}
+
+template <int RT, int MODE>
+__global__ __launch_bounds__(256) void k_apass_stream(const Job *__restrict__ jobs,
+                                                      const int2 *__restrict__ bmap) {
+    extern __shared__ double smem[];
+    const int2 jt = block_job(bmap);
+    const Job &J = jobs[jt.x];
+    if (jt.y >= J.nA || J.st->stop) return;
+    apass_stream_tile<RT, MODE>(J, jt.y, smem);
+}
+
+// C-pass: a block of 4 waves owns 256 columns of one row chunk; each wave owns
+// 64 columns (four 16-column tiles), so every V operand feeds four MFMAs.  The
+// first column block of each chunk also forms the chunk's partial D = V^T V
+// from the same V operands (upper-triangle 16x16 tiles spread over its waves).
+template <int RT>
+__device__ void cpass_stream_tile(const Job &J, int tx, int ty) {
+    constexpr int RPAD = RT * 16, RN = 4, SB = 2, DMAX = 3;
+    const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+    const int lj = lane & 15, lg = lane >> 4;
+    const int64_t m = J.m, n = J.n, mp = J.mpad;
+    const int r = J.r;
+    const int64_t jb = (int64_t)tx * 256 + wave * 64;
+    const int64_t i_begin = (int64_t)ty * J.chunk;
+    const int64_t i_end = (i_begin + J.chunk < m) ? i_begin + J.chunk : m;
+    const uint16_t *Mb[RN];
+    bool jok[RN];
+#pragma unroll
+    for (int c = 0; c < RN; ++c) {
+        const int64_t j = jb + 16 * c + lj;
+        jok[c] = j < n;
+        Mb[c] = J.Mbc + (jok[c] ? j : 0) * mp + 8 * lg;
+    }
+    const uint16_t *Vr[RT];
+#pragma unroll
+    for (int t = 0; t < RT; ++t) Vr[t] = J.Vb + (int64_t)(16 * t + lj) * mp + 8 * lg;
+    int dta[DMAX], dtb[DMAX], nd = 0;
+    if (tx == 0) {
+        int idx = 0;
+        for (int ta = 0; ta < RT; ++ta)
+            for (int tb = ta; tb < RT; ++tb, ++idx)
+                if (idx % 4 == wave && nd < DMAX) {
+                    dta[nd] = ta;
+                    dtb[nd] = tb;
+                    ++nd;
+                }
+    }
+    v4f acc[RN][RT], dacc[DMAX];
+#pragma unroll
+    for (int c = 0; c < RN; ++c)
+#pragma unroll
+        for (int t = 0; t < RT; ++t) acc[c][t] = v4f{0.0f, 0.0f, 0.0f, 0.0f};
+#pragma unroll
+    for (int d = 0; d < DMAX; ++d) dacc[d] = v4f{0.0f, 0.0f, 0.0f, 0.0f};
+    const bf16x8 z8 = {};
+    bf16x8 a0[SB][RN], b0[SB][RT], a1[SB][RN], b1[SB][RT];
+    auto load = [&](int64_t i0, bf16x8 (&a)[SB][RN], bf16x8 (&b)[SB][RT]) {
+#pragma unroll
+        for (int u = 0; u < SB; ++u) {
+            const int64_t ik = i0 + 32 * u;
+            const bool ok = ik < i_end;
+#pragma unroll
+            for (int c = 0; c < RN; ++c) a[u][c] = (ok && jok[c]) ? *(const bf16x8 *)(Mb[c] + ik) : z8;
+#pragma unroll
+            for (int t = 0; t < RT; ++t) b[u][t] = ok ? *(const bf16x8 *)(Vr[t] + ik) : z8;
+        }
+    };
+    auto compute = [&](const bf16x8 (&a)[SB][RN], const bf16x8 (&b)[SB][RT]) {
+#pragma unroll
+        for (int u = 0; u < SB; ++u) {
+#pragma unroll
+            for (int c = 0; c < RN; ++c)
+#pragma unroll
+                for (int t = 0; t < RT; ++t)
+                    acc[c][t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[u][c], b[u][t], acc[c][t],
+                                                                        0, 0, 0);
+#pragma unroll
+            for (int d = 0; d < DMAX; ++d) {
+                if (d < nd) {
+                    bf16x8 va = z8, vb = z8;
+#pragma unroll
+                    for (int t = 0; t < RT; ++t) {
+                        if (t == dta[d]) va = b[u][t];
+                        if (t == dtb[d]) vb = b[u][t];
+                    }
+                    dacc[d] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(va, vb, dacc[d], 0, 0, 0);
+                }
+            }
+        }
+    };
+    if (i_begin < i_end) {
+        load(i_begin, a0, b0);
+        for (int64_t i0 = i_begin; i0 < i_end; i0 += 64 * SB) {
+            const bool more = i0 + 32 * SB < i_end;
+            if (more) load(i0 + 32 * SB, a1, b1);
+            compute(a0, b0);
+            if (!more) break;
+            if (i0 + 64 * SB < i_end) load(i0 + 64 * SB, a0, b0);
+            compute(a1, b1);
+        }
+    }
+    // acc[c][t][v] = C[k = 16t + lj][j = jb + 16c + 4lg + v]
+    double *out = J.Cp + (int64_t)ty * r * n;
+#pragma unroll
+    for (int t = 0; t < RT; ++t) {
+        const int k = 16 * t + lj;
+        if (k < r) {
+#pragma unroll
+            for (int c = 0; c < RN; ++c)
+#pragma unroll
+                for (int v = 0; v < 4; ++v) {
+                    const int64_t j = jb + 16 * c + 4 * lg + v;
+                    if (j < n) out[(int64_t)k * n + j] = (double)acc[c][t][v];
+                }
+        }
+    }
+    // dacc[d][v] = D[16 dta + 4lg + v][16 dtb + lj]
+    double *dout = J.Dp + (int64_t)ty * RPAD * RPAD;
+#pragma unroll
+    for (int d = 0; d < DMAX; ++d) {
+        if (d < nd) {
+#pragma unroll
+            for (int v = 0; v < 4; ++v)
+                dout[(16 * dta[d] + 4 * lg + v) * RPAD + 16 * dtb[d] + lj] = (double)dacc[d][v];
+        }
+    }
+}
+
+template <int RT>
+__global__ __launch_bounds__(256) void k_cpass_stream(const Job *__restrict__ jobs,
+                                                      const int2 *__restrict__ bmap) {
+    const int2 jt = block_job(bmap);
+    const Job &J = jobs[jt.x];
+    int tx = jt.y % J.nCx, ty = jt.y / J.nCx;
+    if (!bmap) {   // single problem: the column blocks of a chunk run on one XCD
+        const int l = (int)(blockIdx.x >> 3);
+        ty = (int)(blockIdx.x & 7) + 8 * (l / J.nCx);
+        tx = l % J.nCx;
+    }
+    if (ty >= J.chunks || J.st->stop) return;
+    cpass_stream_tile<RT>(J, tx, ty);
 }
 
 }  // namespace
@@ -1002,6 +1265,47 @@ int cpass_final_blocks(int64_t n) { return (int)((n + 15) / 16); }
 
 int apass_grid_single(int nA) { return 8 * ((nA + 7) / 8); }
 
+int cpass_stream_grid(int nCx, int chunks) { return 8 * nCx * ((chunks + 7) / 8); }
+
+// Gram and 1/G_kk (FP64), then 4 waves x 64 rows of A (FP32, stride rpad + 1).
+size_t apass_stream_lds_bytes(int rpad) {
+    return sizeof(double) * ((size_t)rpad * (rpad + 1) + rpad) +
+           sizeof(float) * 4 * 64 * (size_t)(rpad + 1);
+}
+
+hipError_t launch_apass_stream(int mode, int rpad, const Job *jobs, const int2 *bmap, int blocks,
+                               hipStream_t s) {
+    if (blocks <= 0) return hipSuccess;
+    if (mode != MODE_HALS && mode != MODE_MU) return hipErrorInvalidValue;
+    const size_t lds = apass_stream_lds_bytes(rpad);
+    const bool h = mode == MODE_HALS;
+    switch (rpad) {
+        case 16: h ? k_apass_stream<1, MODE_HALS><<<blocks, 256, lds, s>>>(jobs, bmap)
+                   : k_apass_stream<1, MODE_MU><<<blocks, 256, lds, s>>>(jobs, bmap); break;
+        case 32: h ? k_apass_stream<2, MODE_HALS><<<blocks, 256, lds, s>>>(jobs, bmap)
+                   : k_apass_stream<2, MODE_MU><<<blocks, 256, lds, s>>>(jobs, bmap); break;
+        case 48: h ? k_apass_stream<3, MODE_HALS><<<blocks, 256, lds, s>>>(jobs, bmap)
+                   : k_apass_stream<3, MODE_MU><<<blocks, 256, lds, s>>>(jobs, bmap); break;
+        case 64: h ? k_apass_stream<4, MODE_HALS><<<blocks, 256, lds, s>>>(jobs, bmap)
+                   : k_apass_stream<4, MODE_MU><<<blocks, 256, lds, s>>>(jobs, bmap); break;
+        default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_cpass_stream(int rpad, const Job *jobs, const int2 *bmap, int blocks,
+                               hipStream_t s) {
+    if (blocks <= 0) return hipSuccess;
+    switch (rpad) {
+        case 16: k_cpass_stream<1><<<blocks, 256, 0, s>>>(jobs, bmap); break;
+        case 32: k_cpass_stream<2><<<blocks, 256, 0, s>>>(jobs, bmap); break;
+        case 48: k_cpass_stream<3><<<blocks, 256, 0, s>>>(jobs, bmap); break;
+        case 64: k_cpass_stream<4><<<blocks, 256, 0, s>>>(jobs, bmap); break;
+        default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
 int cpass_grid_single(int nCx, int chunks) { return 8 * nCx * ((chunks + 7) / 8); }
 
 // Allow the sweep kernels the LDS sizes apass_lds_bytes / cfinal_lds_bytes
@@ -1032,6 +1336,11 @@ static void lds_attr_modes(hipError_t &e) {
     hipError_t x = hipFuncSetAttribute((const void *)k_cfinal<RT, MODE_INIT>,
                                        hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
     if (x != hipSuccess && e == hipSuccess) e = x;
+    for (const void *f : {(const void *)k_apass_stream<RT, MODE_HALS>,
+                          (const void *)k_apass_stream<RT, MODE_MU>}) {
+        x = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
+        if (x != hipSuccess && e == hipSuccess) e = x;
+    }
 }
 
 hipError_t enable_large_lds() {

@@ -40,7 +40,9 @@ def _direct_rel(M, V, W):
     (32, 32, 257, 20, "hals"),     # 32
     (28, 23, 400, 40, "mu"),       # 48
     (40, 40, 500, 50, "hals"),     # 64
-    (192, 192, 120, 24, "hals"),   # m >= 32768: 64-row A-pass tiles
+    (192, 192, 120, 24, "hals"),   # m >= 32768: streaming passes, rank class 32
+    (182, 182, 130, 40, "hals"),   # streaming, rank class 48
+    (184, 184, 150, 50, "mu"),     # streaming, rank class 64
 ])
 def test_bf16_tracks_fp32(h, w, n, r, algo):
     """One iteration from the same start: BF16 factors within the operand
