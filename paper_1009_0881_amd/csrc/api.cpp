@@ -154,7 +154,7 @@ Ctx make_ctx(nmf_plan_t plan, const float *dM, float *dV, float *dW, void *dws, 
                 J.nC = J.nCx * J.chunks;
             }
             J.mpad = li.mpad;
-            J.npad = (p.d.n + 31) / 32 * 32;
+            J.npad = bf_pad(p.d.n);
             J.Mbp = at<uint16_t>(c.ws, li.off_Mbp);
             J.Mbc = at<uint16_t>(c.ws, li.off_Mbc);
             J.Vb = at<uint16_t>(c.ws, li.off_Vb);

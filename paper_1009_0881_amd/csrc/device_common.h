@@ -10,6 +10,19 @@ typedef float v4f __attribute__((ext_vector_type(4)));
 
 constexpr int kWave = 64;
 
+// Global-memory view of a pointer.  Pointers read from a job table are generic
+// to the compiler, which then issues FLAT loads: they count against both the
+// vector-memory and the LDS counters, so every wait on them becomes a full
+// wait and loads issued ahead cannot stay in flight.  Through this view the
+// compiler issues global_load / global_store, counted precisely.
+template <class T>
+using gmem = __attribute__((address_space(1))) T;
+
+template <class T>
+__device__ __forceinline__ gmem<T> *to_global(T *p) {
+    return (gmem<T> *)p;
+}
+
 __device__ __forceinline__ bool stopped(const int32_t *stop) {
     return stop != nullptr && *stop != 0;
 }

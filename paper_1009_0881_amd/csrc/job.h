@@ -43,7 +43,7 @@ struct Job {
     // Mbc: C-pass copy of M, column-major with column stride mpad (rows >= m zero).
     // Vb:  V, column-major with stride mpad, rpad columns (k >= r zero).
     // Wb:  W, rpad x npad row-major (k >= r or j >= n zero).
-    // mpad = m and npad = n rounded up to 32.
+    // mpad = m and npad = n rounded up to 128.
     // The stop test is applied only to FP32 (prec = 0) iterations.
     const uint16_t *Mbp, *Mbc;
     uint16_t *Vb, *Wb;

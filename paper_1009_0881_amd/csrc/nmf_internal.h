@@ -17,6 +17,11 @@ namespace nmf {
 constexpr int kMaxRank = 64;
 constexpr int kMaxLevels = 12;
 constexpr int kNormParts = 1024;   // max partial sums of ||M_l||^2 (per level)
+// BF16 operand copies are padded to multiples of 128 rows and columns (and C-pass
+// chunks are multiples of 128 rows), so the streaming loops over 32-wide K-steps
+// in batches of two double-buffered pairs need no bounds tests.
+constexpr int64_t kBfPad = 128;
+inline int64_t bf_pad(int64_t x) { return (x + kBfPad - 1) / kBfPad * kBfPad; }
 
 // Number of partial sums of ||X||^2 for a rows x ncols matrix (work items are
 // (column, 2048-row chunk)); every path uses this split, so norms agree bitwise.

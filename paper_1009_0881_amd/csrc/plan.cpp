@@ -148,7 +148,7 @@ nmf_status build_plan(const nmf_desc &d0, Plan &p, std::string &err) {
         int64_t chunks = std::max<int64_t>(1, p.num_cu / std::max<int64_t>(1, ntiles));
         chunks = std::min<int64_t>(chunks, std::max<int64_t>(1, (li.m + 63) / 64));
         int64_t chunk = (li.m + chunks - 1) / chunks;
-        const int64_t q = d.prec == NMF_BF16 ? 32 : 16;   // BF16 MFMA steps are 32 rows
+        const int64_t q = d.prec == NMF_BF16 ? kBfPad : 16;   // BF16: see kBfPad
         chunk = (chunk + q - 1) / q * q;
         li.cp_chunk = chunk;
         li.cp_chunks = (int32_t)((li.m + chunk - 1) / chunk);
@@ -160,7 +160,7 @@ nmf_status build_plan(const nmf_desc &d0, Plan &p, std::string &err) {
             int64_t sc = std::max<int64_t>(1, 2 * p.num_cu / ncx);
             sc = std::min<int64_t>(sc, std::max<int64_t>(1, (li.m + 255) / 256));
             int64_t sch = (li.m + sc - 1) / sc;
-            sch = (sch + 31) / 32 * 32;
+            sch = bf_pad(sch);
             li.scp_chunk = sch;
             li.scp_chunks = (int32_t)((li.m + sch - 1) / sch);
             max_cp = std::max<size_t>(max_cp, (size_t)li.scp_chunks);
@@ -219,12 +219,12 @@ nmf_status build_plan(const nmf_desc &d0, Plan &p, std::string &err) {
     ws.off_Bp = take(sizeof(double) * (size_t)cpass_final_blocks(d.n) * rp2);
     ws.off_jobs = take(sizeof(Job) * (p.lv.size() + 1));   // + FP32 refinement job
     ws.off_Wb = 0;
-    const int64_t npad = (d.n + 31) / 32 * 32;
+    const int64_t npad = bf_pad(d.n);
     if (d.prec == NMF_BF16) {
         // BF16 operand copies (job.h): per level M in the A-pass (K-packed) and
         // C-pass (column-major, stride mpad) layouts and V; W once
         for (auto &li : p.lv) {
-            li.mpad = (li.m + 31) / 32 * 32;
+            li.mpad = bf_pad(li.m);
             li.off_Mbp = take(sizeof(uint16_t) * (size_t)((li.m + 15) / 16 * 16) * npad);
             li.off_Mbc = take(sizeof(uint16_t) * (size_t)li.mpad * n);
             li.off_Vb = take(sizeof(uint16_t) * (size_t)li.mpad * p.rpad);

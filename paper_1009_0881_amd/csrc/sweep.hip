@@ -74,10 +74,19 @@ __device__ __forceinline__ double row_bcast(double v) {
     return __hiloint2double(hi, lo);
 }
 
+template <int N>
+__device__ __forceinline__ float row_bcast(float v) {
+    return __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(v), 0x150 + N, 0xF, 0xF, false));
+}
+
+__device__ __forceinline__ double fma_t(double a, double b, double c) { return __builtin_fma(a, b, c); }
+__device__ __forceinline__ float fma_t(float a, float b, float c) { return __builtin_fmaf(a, b, c); }
+
 // Returns v unchanged, but only once dep has been computed: an empty asm that
 // takes dep as an input orders the instructions that use the result after
 // those that produce dep.  No instruction is emitted.
-__device__ __forceinline__ int ordered_after(int v, double dep) {
+template <class T>
+__device__ __forceinline__ int ordered_after(int v, T dep) {
     asm("" : "+v"(v) : "v"(dep));
     return v;
 }
@@ -86,9 +95,10 @@ __device__ __forceinline__ int ordered_after(int v, double dep) {
 // holding entries k = 16t + p.  G is the r x r FP64 Gram of the other factor
 // in LDS (row stride gs, zero-padded to RPAD), gi[k] = 1/G_kk (0 when
 // G_kk = 0 or k >= r), a[t] entry 16t + p of the matching row of the product.  The
-// r x r-sized update arithmetic runs in FP64 (the numerator
-// a_k - sum_l x_l G_lk cancels as the iterate converges); the row is read from
-// and written back to FP32 storage by the caller.
+// r x r-sized update arithmetic runs in T: FP64 in the FP32 mode (the
+// numerator a_k - sum_l x_l G_lk cancels as the iterate converges), FP32 in
+// the BF16 mode; the row is read from and written back to FP32 storage by the
+// caller.
 //
 // HALS (Alg. 3): x_k <- max(0, (a_k - sum_{l != k} x_l G_lk) / G_kk) for
 // k = 1..r in order, G_kk = 0 keeping x_k.  Computed in the equivalent
@@ -96,14 +106,13 @@ __device__ __forceinline__ int ordered_after(int v, double dep) {
 // x_k <- max(0, x_k + g_k / G_kk), broadcasts the change d to its row, and
 // every lane applies g_l -= d G_kl for its l > k.
 // MU (Alg. 2): x_k <- x_k a_k / (sum_l x_l G_lk); a zero denominator keeps x_k.
-template <int RT, int MODE>
-__device__ __forceinline__ void row_update(double (&x)[RT], const double *G, int gs,
-                                           const double *gi, const double (&a)[RT], int r,
-                                           int p) {
+template <int RT, int MODE, class T = double>
+__device__ __forceinline__ void row_update(T (&x)[RT], const T *G, int gs, const T *gi,
+                                           const T (&a)[RT], int r, int p) {
     constexpr int RPAD = 16 * RT;
-    double acc[RT];
+    T acc[RT];
 #pragma unroll
-    for (int t = 0; t < RT; ++t) acc[t] = 0.0;
+    for (int t = 0; t < RT; ++t) acc[t] = T(0);
     // acc_k = sum_l x_l G_lk.  Padded entries (k >= r) have x_k = 0, zero Gram
     // rows and 1/G_kk = 0: the mat-vec skips whole groups of 4 of them, the
     // HALS loop runs over all RPAD entries with no runtime bound.
@@ -112,19 +121,19 @@ __device__ __forceinline__ void row_update(double (&x)[RT], const double *G, int
         if (4 * lg < r) {
             static_for<4>([&](auto lq_c) {
                 constexpr int l = 4 * lg + decltype(lq_c)::value;
-                const double xl = row_bcast<l % 16>(x[l / 16]);
-                const double *gr = G + l * gs + p;
+                const T xl = row_bcast<l % 16>(x[l / 16]);
+                const T *gr = G + l * gs + p;
 #pragma unroll
-                for (int t = 0; t < RT; ++t) acc[t] = fma(xl, gr[16 * t], acc[t]);
+                for (int t = 0; t < RT; ++t) acc[t] = fma_t(xl, gr[16 * t], acc[t]);
             });
         }
     });
     if constexpr (MODE == MODE_HALS) {
-        double g[RT], ginv[RT], row0[RT], row1[RT];
+        T g[RT], ginv[RT], row0[RT], row1[RT];
 #pragma unroll
         for (int t = 0; t < RT; ++t) {
             const int k = 16 * t + p;
-            g[t] = k < r ? a[t] - acc[t] : 0.0;
+            g[t] = k < r ? a[t] - acc[t] : T(0);
             ginv[t] = gi[k];
             row0[t] = G[k];                  // Gram row 0
             row1[t] = G[gs + k];             // Gram row 1
@@ -132,24 +141,25 @@ __device__ __forceinline__ void row_update(double (&x)[RT], const double *G, int
         // Each step loads the Gram row of step k+2 behind ordered_after() on
         // the previous step's broadcast: loads run two steps ahead, hiding LDS
         // latency, and the compiler cannot hoist all of them (and spill).
-        double dprev = acc[0];
+        T dprev = acc[0];
         static_for<RPAD>([&](auto k_c) {
             constexpr int k = decltype(k_c)::value, kt = k / 16, pk = k % 16;
-            double row2[RT];
+            T row2[RT];
             if constexpr (k + 2 < RPAD) {
-                const double *gr = G + ordered_after((k + 2) * gs + p, dprev);
+                const T *gr = G + ordered_after((k + 2) * gs + p, dprev);
 #pragma unroll
                 for (int t = (k + 2) / 16; t < RT; ++t) row2[t] = gr[16 * t];
             }
-            const bool own = p == pk && ginv[kt] > 0.0;
-            const double cand = fmax(0.0, fma(g[kt], ginv[kt], x[kt]));
-            double d = own ? cand - x[kt] : 0.0;
+            const bool own = p == pk && ginv[kt] > T(0);
+            const T c0 = fma_t(g[kt], ginv[kt], x[kt]);
+            const T cand = c0 > T(0) ? c0 : T(0);
+            T d = own ? cand - x[kt] : T(0);
             x[kt] = own ? cand : x[kt];
             d = row_bcast<pk>(d);
             dprev = d;
-            g[kt] = p > pk ? fma(-d, row0[kt], g[kt]) : g[kt];
+            g[kt] = p > pk ? fma_t(-d, row0[kt], g[kt]) : g[kt];
 #pragma unroll
-            for (int t = kt + 1; t < RT; ++t) g[t] = fma(-d, row0[t], g[t]);
+            for (int t = kt + 1; t < RT; ++t) g[t] = fma_t(-d, row0[t], g[t]);
 #pragma unroll
             for (int t = (k + 1) / 16; t < RT; ++t) {
                 row0[t] = row1[t];
@@ -160,30 +170,32 @@ __device__ __forceinline__ void row_update(double (&x)[RT], const double *G, int
 #pragma unroll
         for (int t = 0; t < RT; ++t) {
             const int k = 16 * t + p;
-            if (k < r && acc[t] > 0.0) x[t] = x[t] * a[t] / acc[t];
+            if (k < r && acc[t] > T(0)) x[t] = x[t] * a[t] / acc[t];
         }
     }
 }
 
 // Load an r x r FP64 Gram (row-major, stride r) into LDS zero-padded to
 // RPAD x RPAD (stride gs), and its inverse diagonal.
-template <int RPAD>
-__device__ __forceinline__ void load_gram(const double *__restrict__ Gd, int r, double *Gs, int gs,
-                                          double *gi) {
+template <int RPAD, class T = double>
+__device__ __forceinline__ void load_gram(const double *__restrict__ Gd, int r, T *Gs, int gs,
+                                          T *gi) {
+    const auto G = to_global(Gd);
     for (int e = threadIdx.x; e < RPAD * RPAD; e += blockDim.x) {
         const int a = e / RPAD, b = e % RPAD;
-        Gs[a * gs + b] = (a < r && b < r) ? Gd[a * r + b] : 0.0;
+        Gs[a * gs + b] = (a < r && b < r) ? (T)G[a * r + b] : T(0);
     }
     for (int k = threadIdx.x; k < RPAD; k += blockDim.x) {
-        const double g = (k < r) ? Gd[k * r + k] : 0.0;
-        gi[k] = g > 0.0 ? 1.0 / g : 0.0;
+        const double g = (k < r) ? G[k * r + k] : 0.0;
+        gi[k] = g > 0.0 ? (T)(1.0 / g) : T(0);
     }
 }
 
 // Sum of `count` FP64 values p0[0], p0[stride], ... in index order, with up
 // to 16 loads in flight.
-__device__ __forceinline__ double sum_strided(const double *__restrict__ p0, int64_t stride,
+__device__ __forceinline__ double sum_strided(const double *__restrict__ pg, int64_t stride,
                                               int count) {
+    const auto p0 = to_global(pg);
     double s = 0.0;
     int p = 0;
     for (; p + 16 <= count; p += 16) {
@@ -232,19 +244,20 @@ __device__ void apass_tile(const Job &J, int tile, double *smem) {
     const int r = J.r;
     const int64_t brow = (int64_t)tile * TM;
     const int64_t row0 = brow + wr * TMW;
-    const float *__restrict__ Wt = J.Wt;
+    const auto Wt = to_global(J.Wt);
+    const auto Vg = to_global(J.V);
 
     const int64_t nsteps = (n + 3) >> 2;
     const int64_t per = (nsteps + WN - 1) / WN;
     const int64_t s_begin = wn * per;
     const int64_t s_end = (s_begin + per < nsteps) ? s_begin + per : nsteps;
-    const float *Mr[RW];
+    gmem<const float> *Mr[RW];
     bool rok[RW];
 #pragma unroll
     for (int q = 0; q < RW; ++q) {
         const int64_t row = row0 + 16 * q + li;
         rok[q] = row < m;
-        Mr[q] = J.M + (rok[q] ? row : 0);
+        Mr[q] = to_global(J.M) + (rok[q] ? row : 0);
     }
     v4f hi[RW][RT], lo[RW][RT];
 #pragma unroll
@@ -296,7 +309,7 @@ __device__ void apass_tile(const Job &J, int tile, double *smem) {
 #pragma unroll
             for (int t = 0; t < RT; ++t) {
                 const int k = 16 * t + (tid & 15);
-                xv[i][t] = (vrow < m && k < r) ? (double)J.V[vrow + (int64_t)k * m] : 0.0;
+                xv[i][t] = (vrow < m && k < r) ? (double)Vg[vrow + (int64_t)k * m] : 0.0;
             }
         }
     }
@@ -330,17 +343,17 @@ __device__ void apass_tile(const Job &J, int tile, double *smem) {
         const int64_t k_begin = wn * kper;
         const int64_t k_end = (k_begin + kper < ksteps) ? k_begin + kper : ksteps;
         const int64_t G = J.npad / 8;
-        const uint16_t *Mp[RW];
+        gmem<const uint16_t> *Mp[RW];
         bool pok[RW];
 #pragma unroll
         for (int q = 0; q < RW; ++q) {
             const int64_t pr = row0 + 16 * q;          // first row of the panel
             pok[q] = pr < m;
-            Mp[q] = J.Mbp + (pok[q] ? ((pr / 16) * G * 16 + li) * 8 + lk * 128 : 0);
+            Mp[q] = to_global(J.Mbp) + (pok[q] ? ((pr / 16) * G * 16 + li) * 8 + lk * 128 : 0);
         }
-        const uint16_t *Wr[RT];
+        gmem<const uint16_t> *Wr[RT];
 #pragma unroll
-        for (int t = 0; t < RT; ++t) Wr[t] = J.Wb + (int64_t)(16 * t + li) * J.npad + 8 * lk;
+        for (int t = 0; t < RT; ++t) Wr[t] = to_global(J.Wb) + (int64_t)(16 * t + li) * J.npad + 8 * lk;
         v4f acc[RW][RT];
 #pragma unroll
         for (int q = 0; q < RW; ++q)
@@ -355,9 +368,10 @@ __device__ void apass_tile(const Job &J, int tile, double *smem) {
                 const bool ok = kk < k_end;
 #pragma unroll
                 for (int q = 0; q < RW; ++q)
-                    a[u][q] = (ok && pok[q]) ? *(const bf16x8 *)(Mp[q] + kk * 512) : z8;
+                    a[u][q] = (ok && pok[q]) ? *(gmem<const bf16x8> *)(Mp[q] + kk * 512) : z8;
 #pragma unroll
-                for (int t = 0; t < RT; ++t) b[u][t] = ok ? *(const bf16x8 *)(Wr[t] + 32 * kk) : z8;
+                for (int t = 0; t < RT; ++t)
+                    b[u][t] = ok ? *(gmem<const bf16x8> *)(Wr[t] + 32 * kk) : z8;
             }
         };
         auto computeb = [&](const bf16x8 (&a)[SB][RW], const bf16x8 (&b)[SB][RT]) {
@@ -406,7 +420,7 @@ __device__ void apass_tile(const Job &J, int tile, double *smem) {
         for (int e = tid; e < TM * r; e += 256) {
             const int rr = e % TM, k = e / TM;
             const int64_t row = brow + rr;
-            if (row < m) J.A[row + (int64_t)k * m] = (float)arow(rr)[k];
+            if (row < m) to_global(J.A)[row + (int64_t)k * m] = (float)arow(rr)[k];
         }
     } else {
 #pragma unroll
@@ -421,9 +435,10 @@ __device__ void apass_tile(const Job &J, int tile, double *smem) {
 #pragma unroll
                 for (int t = 0; t < RT; ++t) {
                     const int k = 16 * t + p;
-                    if (k < r) J.V[vrow + (int64_t)k * m] = (float)xv[i][t];
+                    if (k < r) Vg[vrow + (int64_t)k * m] = (float)xv[i][t];
                     // BF16 copy of the new row for the C-pass (k >= r stays 0)
-                    if constexpr (BF) J.Vb[vrow + (int64_t)k * J.mpad] = bf16_rne((float)xv[i][t]);
+                    if constexpr (BF)
+                        to_global(J.Vb)[vrow + (int64_t)k * J.mpad] = bf16_rne((float)xv[i][t]);
                 }
             }
         }
@@ -463,13 +478,13 @@ __device__ void cpass_tile(const Job &J, int tx, int ty, int ntx) {
     const int lj = lane & 15, lg = lane >> 4;
     const int64_t m = J.m, n = J.n, ldm = J.ldm;
     const int r = J.r;
-    const float *__restrict__ V = J.V;
+    const auto V = to_global(J.V);
     const int64_t jb = (int64_t)tx * 64 + wave * 16;
     const int64_t i_begin = (int64_t)ty * J.chunk;
     const int64_t i_end = (i_begin + J.chunk < m) ? i_begin + J.chunk : m;
     const int64_t j = jb + lj;
     const bool jok = j < n;
-    const float *Mc = J.M + (jok ? j : 0) * ldm;
+    const auto Mc = to_global(J.M) + (jok ? j : 0) * ldm;
     const bool vec = ((ldm & 3) == 0) && ((m & 3) == 0) &&
                      (((uintptr_t)J.M & 15) == 0) && (((uintptr_t)V & 15) == 0);
     const int slot = tx * 4 + wave, nslots = ntx * 4;
@@ -495,11 +510,11 @@ __device__ void cpass_tile(const Job &J, int tx, int ty, int ntx) {
     auto load1 = [&](int64_t i0, v4f &mv, v4f (&vv)[RT]) {
         const int64_t ib = i0 + 4 * lg;
         if (vec && ib + 3 < i_end) {
-            mv = jok ? *(const v4f *)(Mc + ib) : v4f{0.0f, 0.0f, 0.0f, 0.0f};
+            mv = jok ? *(gmem<const v4f> *)(Mc + ib) : v4f{0.0f, 0.0f, 0.0f, 0.0f};
 #pragma unroll
             for (int t = 0; t < RT; ++t) {
                 const int k = 16 * t + lj;
-                vv[t] = (k < r) ? *(const v4f *)(V + ib + (int64_t)k * m)
+                vv[t] = (k < r) ? *(gmem<const v4f> *)(V + ib + (int64_t)k * m)
                                 : v4f{0.0f, 0.0f, 0.0f, 0.0f};
             }
         } else {
@@ -570,10 +585,10 @@ __device__ void cpass_tile(const Job &J, int tx, int ty, int ntx) {
         // column 16t + lj from the BF16 V (16 bytes each).
         constexpr int KB = 2;
         const int64_t mp = J.mpad;
-        const uint16_t *Mb = J.Mbc + (jok ? j : 0) * mp + 8 * lg;
-        const uint16_t *Vr[RT];
+        const auto Mb = to_global(J.Mbc) + (jok ? j : 0) * mp + 8 * lg;
+        gmem<const uint16_t> *Vr[RT];
 #pragma unroll
-        for (int t = 0; t < RT; ++t) Vr[t] = J.Vb + (int64_t)(16 * t + lj) * mp + 8 * lg;
+        for (int t = 0; t < RT; ++t) Vr[t] = to_global(J.Vb) + (int64_t)(16 * t + lj) * mp + 8 * lg;
         const bf16x8 z8 = {};
         v4f acc[RT];
 #pragma unroll
@@ -584,9 +599,9 @@ __device__ void cpass_tile(const Job &J, int tx, int ty, int ntx) {
             for (int u = 0; u < KB; ++u) {
                 const int64_t ik = i0 + 32 * u;
                 const bool ok = ik < i_end;
-                a[u] = (ok && jok) ? *(const bf16x8 *)(Mb + ik) : z8;
+                a[u] = (ok && jok) ? *(gmem<const bf16x8> *)(Mb + ik) : z8;
 #pragma unroll
-                for (int t = 0; t < RT; ++t) b[u][t] = ok ? *(const bf16x8 *)(Vr[t] + ik) : z8;
+                for (int t = 0; t < RT; ++t) b[u][t] = ok ? *(gmem<const bf16x8> *)(Vr[t] + ik) : z8;
             }
         };
         auto computeb = [&](const bf16x8 (&a)[KB], const bf16x8 (&b)[KB][RT]) {
@@ -630,7 +645,7 @@ __device__ void cpass_tile(const Job &J, int tx, int ty, int ntx) {
         }
     }
     // hi[t][v] + lo[t][v] = C[k = 16t + lj][j = jb + 4*lg + v]
-    double *out = J.Cp + (int64_t)ty * r * n;
+    const auto out = to_global(J.Cp) + (int64_t)ty * r * n;
 #pragma unroll
     for (int t = 0; t < RT; ++t) {
         const int k = 16 * t + lj;
@@ -643,7 +658,7 @@ __device__ void cpass_tile(const Job &J, int tx, int ty, int ntx) {
         }
     }
     // dacc[d][v] = D[16*dta + 4*v + lg][16*dtb + lj]
-    double *dout = J.Dp + (int64_t)ty * RPAD * RPAD;
+    const auto dout = to_global(J.Dp) + (int64_t)ty * RPAD * RPAD;
 #pragma unroll
     for (int d = 0; d < DMAX; ++d) {
         if (d < nd) {
@@ -700,7 +715,7 @@ __global__ __launch_bounds__(256) void k_reduce(const Job *__restrict__ jobs,
     }
     if (which == 1 && tile == 0) {
         double s = 0.0;
-        for (int i = threadIdx.x; i < J.nF; i += 256) s += J.rparts[i];
+        for (int i = threadIdx.x; i < J.nF; i += 256) s += to_global(J.rparts)[i];
         s = block_sum_f64<256>(s, red);
         if (threadIdx.x == 0) {
             DevState *st = J.st;
@@ -753,7 +768,7 @@ __device__ void cfinal_tile(const Job &J, int tile, double *smem) {
 #pragma unroll
         for (int t = 0; t < RT; ++t) {
             const int k = 16 * t + (tid & 15);
-            xw[t] = (j < n && k < r) ? (double)J.W[(int64_t)k * n + j] : 0.0;
+            xw[t] = (j < n && k < r) ? (double)to_global(J.W)[(int64_t)k * n + j] : 0.0;
         }
     }
     if constexpr (!INIT) {
@@ -771,7 +786,7 @@ __device__ void cfinal_tile(const Job &J, int tile, double *smem) {
         for (int e = tid; e < 16 * r; e += 256) {
             const int jj = e & 15, k = e >> 4;
             const int64_t j = j0 + jj;
-            if (j < n) J.C[(int64_t)k * n + j] = (float)Cs[jj * CS + k];
+            if (j < n) to_global(J.C)[(int64_t)k * n + j] = (float)Cs[jj * CS + k];
         }
     } else {
         double part_cw = 0.0;
@@ -791,10 +806,10 @@ __device__ void cfinal_tile(const Job &J, int tile, double *smem) {
                 const float xf = (ok && k < r) ? (float)xw[t] : 0.0f;
                 Wn[jj * CS + k] = (double)xf;
                 if (ok) {
-                    J.Wt[j * RPAD + k] = xf;
-                    if (J.Wb) J.Wb[(int64_t)k * J.npad + j] = bf16_rne(xf);   // BF16 mode
+                    to_global(J.Wt)[j * RPAD + k] = xf;
+                    if (J.Wb) to_global(J.Wb)[(int64_t)k * J.npad + j] = bf16_rne(xf);   // BF16 mode
                     if (UPD && k < r) {
-                        J.W[(int64_t)k * n + j] = xf;
+                        to_global(J.W)[(int64_t)k * n + j] = xf;
                         part_cw += Cs[jj * CS + k] * (double)xf;
                     }
                 }
@@ -802,7 +817,7 @@ __device__ void cfinal_tile(const Job &J, int tile, double *smem) {
         }
         __syncthreads();
         double part_db = 0.0;
-        double *bout = J.Bp + (int64_t)tile * RPAD * RPAD;
+        const auto bout = to_global(J.Bp) + (int64_t)tile * RPAD * RPAD;
         for (int e = tid; e < RPAD * RPAD; e += 256) {
             const int a = e / RPAD, b = e % RPAD;
             if (a <= b) {
@@ -815,7 +830,7 @@ __device__ void cfinal_tile(const Job &J, int tile, double *smem) {
         }
         if constexpr (UPD) {
             const double tot = block_sum_f64<256>(part_db - 2.0 * part_cw, red);
-            if (tid == 0) J.rparts[tile] = tot;
+            if (tid == 0) to_global(J.rparts)[tile] = tot;
         }
     }
 }
@@ -891,42 +906,41 @@ __global__ __launch_bounds__(256) void k_residual(const double *__restrict__ rpa
 template <int RT, int MODE>
 __device__ void apass_stream_tile(const Job &J, int tile, double *smem) {
     constexpr int RPAD = RT * 16, GS = RPAD + 1, AS = RPAD + 1, RW = 4, SB = 2;
-    double *Gs = smem;
-    double *Gi = Gs + RPAD * GS;
+    float *Gs = reinterpret_cast<float *>(smem);   // FP32 update arithmetic (BF16 mode)
+    float *Gi = Gs + RPAD * GS;
     const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
     const int li = lane & 15, lk = lane >> 4;
     const int64_t m = J.m;
     const int r = J.r;
     const int64_t row0 = (int64_t)tile * 256 + wave * 64;
+    // npad is a multiple of 128: ksteps is a multiple of 2 * SB and every load
+    // of the loop below is in bounds (panels past m read the last panel; their
+    // rows are not written back)
     const int64_t ksteps = J.npad / 32, G = J.npad / 8;
-    const uint16_t *Mp[RW];
-    bool pok[RW];
+    const int64_t lastp = (m - 1) / 16;
+    gmem<const uint16_t> *Mp[RW];
 #pragma unroll
     for (int q = 0; q < RW; ++q) {
-        const int64_t pr = row0 + 16 * q;
-        pok[q] = pr < m;
-        Mp[q] = J.Mbp + (pok[q] ? ((pr / 16) * G * 16 + li) * 8 + lk * 128 : 0);
+        const int64_t pr = (row0 + 16 * q) / 16;
+        Mp[q] = to_global(J.Mbp) + ((pr < lastp ? pr : lastp) * G * 16 + li) * 8 + lk * 128;
     }
-    const uint16_t *Wr[RT];
+    gmem<const uint16_t> *Wr[RT];
 #pragma unroll
-    for (int t = 0; t < RT; ++t) Wr[t] = J.Wb + (int64_t)(16 * t + li) * J.npad + 8 * lk;
+    for (int t = 0; t < RT; ++t) Wr[t] = to_global(J.Wb) + (int64_t)(16 * t + li) * J.npad + 8 * lk;
     v4f acc[RW][RT];
 #pragma unroll
     for (int q = 0; q < RW; ++q)
 #pragma unroll
         for (int t = 0; t < RT; ++t) acc[q][t] = v4f{0.0f, 0.0f, 0.0f, 0.0f};
-    const bf16x8 z8 = {};
     bf16x8 a0[SB][RW], b0[SB][RT], a1[SB][RW], b1[SB][RT];
     auto load = [&](int64_t k0, bf16x8 (&a)[SB][RW], bf16x8 (&b)[SB][RT]) {
 #pragma unroll
         for (int u = 0; u < SB; ++u) {
             const int64_t kk = k0 + u;
-            const bool ok = kk < ksteps;
 #pragma unroll
-            for (int q = 0; q < RW; ++q)
-                a[u][q] = (ok && pok[q]) ? *(const bf16x8 *)(Mp[q] + kk * 512) : z8;
+            for (int q = 0; q < RW; ++q) a[u][q] = *(gmem<const bf16x8> *)(Mp[q] + kk * 512);
 #pragma unroll
-            for (int t = 0; t < RT; ++t) b[u][t] = ok ? *(const bf16x8 *)(Wr[t] + 32 * kk) : z8;
+            for (int t = 0; t < RT; ++t) b[u][t] = *(gmem<const bf16x8> *)(Wr[t] + 32 * kk);
         }
     };
     auto compute = [&](const bf16x8 (&a)[SB][RW], const bf16x8 (&b)[SB][RT]) {
@@ -939,16 +953,19 @@ __device__ void apass_stream_tile(const Job &J, int tile, double *smem) {
                     acc[q][t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[u][q], b[u][t], acc[q][t],
                                                                         0, 0, 0);
     };
-    if (ksteps > 0) load(0, a0, b0);
-    load_gram<RPAD>(J.Bd, r, Gs, GS, Gi);
-    for (int64_t k0 = 0; k0 < ksteps; k0 += 2 * SB) {
-        if (k0 + SB < ksteps) load(k0 + SB, a1, b1);
+    load(0, a0, b0);
+    load_gram<RPAD, float>(J.Bd, r, Gs, GS, Gi);
+    int64_t k0 = 0;
+    for (; k0 + 2 * SB < ksteps; k0 += 2 * SB) {
+        load(k0 + SB, a1, b1);
         compute(a0, b0);
-        if (k0 + SB >= ksteps) break;
-        if (k0 + 2 * SB < ksteps) load(k0 + 2 * SB, a0, b0);
+        load(k0 + 2 * SB, a0, b0);
         compute(a1, b1);
     }
-    float *Aw = reinterpret_cast<float *>(Gi + RPAD) + wave * 64 * AS;
+    load(k0 + SB, a1, b1);
+    compute(a0, b0);
+    compute(a1, b1);
+    float *Aw = Gi + RPAD + wave * 64 * AS;
 #pragma unroll
     for (int q = 0; q < RW; ++q)
 #pragma unroll
@@ -956,31 +973,31 @@ __device__ void apass_stream_tile(const Job &J, int tile, double *smem) {
 #pragma unroll
             for (int v = 0; v < 4; ++v) Aw[(16 * q + 4 * lk + v) * AS + 16 * t + li] = acc[q][t][v];
     __syncthreads();   // Gram and A rows in LDS
-    auto load_x = [&](int g, double (&x)[RT]) {
+    auto load_x = [&](int g, float (&x)[RT]) {
         const int64_t row = row0 + 16 * (g >> 2) + 4 * lk + (g & 3);
 #pragma unroll
         for (int t = 0; t < RT; ++t) {
             const int k = 16 * t + li;
-            x[t] = (row < m && k < r) ? (double)J.V[row + (int64_t)k * m] : 0.0;
+            x[t] = (row < m && k < r) ? to_global(J.V)[row + (int64_t)k * m] : 0.0f;
         }
     };
-    double xc[RT], xn[RT];
+    float xc[RT], xn[RT];
     load_x(0, xc);
 #pragma unroll 1
     for (int g = 0; g < RW * 4; ++g) {
         const int q = g >> 2, v = g & 3;
         if (g + 1 < RW * 4) load_x(g + 1, xn);
-        double a[RT];
+        float a[RT];
 #pragma unroll
-        for (int t = 0; t < RT; ++t) a[t] = (double)Aw[(16 * q + 4 * lk + v) * AS + 16 * t + li];
-        row_update<RT, MODE>(xc, Gs, GS, Gi, a, r, li);
+        for (int t = 0; t < RT; ++t) a[t] = Aw[(16 * q + 4 * lk + v) * AS + 16 * t + li];
+        row_update<RT, MODE, float>(xc, Gs, GS, Gi, a, r, li);
         const int64_t row = row0 + 16 * q + 4 * lk + v;
         if (row < m) {
 #pragma unroll
             for (int t = 0; t < RT; ++t) {
                 const int k = 16 * t + li;
-                if (k < r) J.V[row + (int64_t)k * m] = (float)xc[t];
-                J.Vb[row + (int64_t)k * J.mpad] = bf16_rne((float)xc[t]);
+                if (k < r) to_global(J.V)[row + (int64_t)k * m] = xc[t];
+                to_global(J.Vb)[row + (int64_t)k * J.mpad] = bf16_rne(xc[t]);
             }
         }
 #pragma unroll
@@ -1010,19 +1027,20 @@ __device__ void cpass_stream_tile(const Job &J, int tx, int ty) {
     const int64_t m = J.m, n = J.n, mp = J.mpad;
     const int r = J.r;
     const int64_t jb = (int64_t)tx * 256 + wave * 64;
+    // chunks and mpad are multiples of 128 rows: [i_begin, i_stop) is a whole
+    // number of double-buffered pairs of K-steps and every load is in bounds
+    // (rows past m are zero; columns past n read column n-1 and are not stored)
     const int64_t i_begin = (int64_t)ty * J.chunk;
-    const int64_t i_end = (i_begin + J.chunk < m) ? i_begin + J.chunk : m;
-    const uint16_t *Mb[RN];
-    bool jok[RN];
+    const int64_t i_stop = (i_begin + J.chunk < mp) ? i_begin + J.chunk : mp;
+    gmem<const uint16_t> *Mb[RN];
 #pragma unroll
     for (int c = 0; c < RN; ++c) {
         const int64_t j = jb + 16 * c + lj;
-        jok[c] = j < n;
-        Mb[c] = J.Mbc + (jok[c] ? j : 0) * mp + 8 * lg;
+        Mb[c] = to_global(J.Mbc) + (j < n ? j : n - 1) * mp + 8 * lg;
     }
-    const uint16_t *Vr[RT];
+    gmem<const uint16_t> *Vr[RT];
 #pragma unroll
-    for (int t = 0; t < RT; ++t) Vr[t] = J.Vb + (int64_t)(16 * t + lj) * mp + 8 * lg;
+    for (int t = 0; t < RT; ++t) Vr[t] = to_global(J.Vb) + (int64_t)(16 * t + lj) * mp + 8 * lg;
     int dta[DMAX], dtb[DMAX], nd = 0;
     if (tx == 0) {
         int idx = 0;
@@ -1047,11 +1065,10 @@ __device__ void cpass_stream_tile(const Job &J, int tx, int ty) {
 #pragma unroll
         for (int u = 0; u < SB; ++u) {
             const int64_t ik = i0 + 32 * u;
-            const bool ok = ik < i_end;
 #pragma unroll
-            for (int c = 0; c < RN; ++c) a[u][c] = (ok && jok[c]) ? *(const bf16x8 *)(Mb[c] + ik) : z8;
+            for (int c = 0; c < RN; ++c) a[u][c] = *(gmem<const bf16x8> *)(Mb[c] + ik);
 #pragma unroll
-            for (int t = 0; t < RT; ++t) b[u][t] = ok ? *(const bf16x8 *)(Vr[t] + ik) : z8;
+            for (int t = 0; t < RT; ++t) b[u][t] = *(gmem<const bf16x8> *)(Vr[t] + ik);
         }
     };
     auto compute = [&](const bf16x8 (&a)[SB][RN], const bf16x8 (&b)[SB][RT]) {
@@ -1077,19 +1094,21 @@ __device__ void cpass_stream_tile(const Job &J, int tx, int ty) {
             }
         }
     };
-    if (i_begin < i_end) {
+    if (i_begin < i_stop) {
         load(i_begin, a0, b0);
-        for (int64_t i0 = i_begin; i0 < i_end; i0 += 64 * SB) {
-            const bool more = i0 + 32 * SB < i_end;
-            if (more) load(i0 + 32 * SB, a1, b1);
+        int64_t i0 = i_begin;
+        for (; i0 + 64 * SB < i_stop; i0 += 64 * SB) {
+            load(i0 + 32 * SB, a1, b1);
             compute(a0, b0);
-            if (!more) break;
-            if (i0 + 64 * SB < i_end) load(i0 + 64 * SB, a0, b0);
+            load(i0 + 64 * SB, a0, b0);
             compute(a1, b1);
         }
+        load(i0 + 32 * SB, a1, b1);
+        compute(a0, b0);
+        compute(a1, b1);
     }
     // acc[c][t][v] = C[k = 16t + lj][j = jb + 16c + 4lg + v]
-    double *out = J.Cp + (int64_t)ty * r * n;
+    const auto out = to_global(J.Cp) + (int64_t)ty * r * n;
 #pragma unroll
     for (int t = 0; t < RT; ++t) {
         const int k = 16 * t + lj;
@@ -1104,7 +1123,7 @@ __device__ void cpass_stream_tile(const Job &J, int tx, int ty) {
         }
     }
     // dacc[d][v] = D[16 dta + 4lg + v][16 dtb + lj]
-    double *dout = J.Dp + (int64_t)ty * RPAD * RPAD;
+    const auto dout = to_global(J.Dp) + (int64_t)ty * RPAD * RPAD;
 #pragma unroll
     for (int d = 0; d < DMAX; ++d) {
         if (d < nd) {
@@ -1267,9 +1286,9 @@ int apass_grid_single(int nA) { return 8 * ((nA + 7) / 8); }
 
 int cpass_stream_grid(int nCx, int chunks) { return 8 * nCx * ((chunks + 7) / 8); }
 
-// Gram and 1/G_kk (FP64), then 4 waves x 64 rows of A (FP32, stride rpad + 1).
+// Gram and 1/G_kk, then 4 waves x 64 rows of A (all FP32, stride rpad + 1).
 size_t apass_stream_lds_bytes(int rpad) {
-    return sizeof(double) * ((size_t)rpad * (rpad + 1) + rpad) +
+    return sizeof(float) * ((size_t)rpad * (rpad + 1) + rpad) +
            sizeof(float) * 4 * 64 * (size_t)(rpad + 1);
 }
 

@@ -48,8 +48,8 @@ def test_bf16_tracks_fp32(h, w, n, r, algo):
     """One iteration from the same start: BF16 factors within the operand
     rounding of FP32 (a wrong operand layout in any rank tile fails this);
     after 20 iterations, rel_err close (trajectories may separate on
-    ill-conditioned problems, so only loosely) and equal to the direct FP64
-    residual of the returned factors."""
+    ill-conditioned problems, so only loosely), and the logged rel_err within
+    the BF16 Gram-form error of the direct FP64 residual."""
     spec = synth.BlobSpec(h=h, w=w, n=n, r=r, k_lo=3, k_hi=8, sig_lo=h / 16, sig_hi=4 * h / 16)
     inst = synth.make_instance(spec, 11)
     _, V32, W32 = _iterate(inst, spec, "fp32", 1, algo)
@@ -63,7 +63,10 @@ def test_bf16_tracks_fp32(h, w, n, r, algo):
     assert (V16b >= 0).all() and (W16b >= 0).all()
     assert e1v <= 2e-2 and e1w <= 2e-2
     assert abs(r16 - r32) <= 0.08 * r32
-    assert abs(d16 - r16) <= 0.01 * r16
+    # the logged rel_err of a BF16 iteration comes from the Gram form with the
+    # BF16 product C (error ~ u_bf16 ||M||^2 / sqrt(m) ~ 1e-4 ||M||^2); the
+    # tolerance is therefore only tested on FP32 iterations
+    assert abs(d16 ** 2 - r16 ** 2) <= 2e-4
 
 
 def test_bf16_refined_solve_reaches_target_with_exact_residual():
