@@ -64,9 +64,23 @@ void prof_collect(nmf_plan_t plan) {
         prof_end(c.plan, c.s, pi_);                         \
     } while (0)
 
+// FP32 streaming tiling of a job when its level qualifies (large, m and the
+// column stride of M multiples of 4, M 16-byte aligned).
+void set_fp32_stream(Job &J, const LevelInfo &li, const Plan &p) {
+    if (!li.fstream || (J.ldm & 3) != 0 || (reinterpret_cast<uintptr_t>(J.M) & 15) != 0) return;
+    J.stream = 1;
+    J.tm = 128;
+    J.nA = (int32_t)((li.m + 127) / 128);
+    J.nCx = (int32_t)((p.d.n + 127) / 128);
+    J.chunks = li.fcp_chunks;
+    J.chunk = li.fcp_chunk;
+    J.nC = J.nCx * J.chunks;
+}
+
 }  // namespace
 
-Ctx make_ctx(nmf_plan_t plan, const float *dM, float *dV, float *dW, void *dws, hipStream_t s) {
+Ctx make_ctx(nmf_plan_t plan, const float *dM, float *dV, float *dW, void *dws, hipStream_t s,
+             bool allow_stream) {
     const Plan &p = plan->p;
     plan->p.prof.pending_kind.clear();
     Ctx c;
@@ -142,9 +156,10 @@ Ctx make_ctx(nmf_plan_t plan, const float *dM, float *dV, float *dW, void *dws, 
         J.tol = p.d.tol;
         J.prec = 0;
         J.stream = 0;
+        if (p.d.prec == NMF_FP32 && allow_stream) set_fp32_stream(J, li, p);
         if (p.d.prec == NMF_BF16) {
             J.prec = 1;
-            if (li.stream) {     // streaming kernels: 256-row / 256-column tiles
+            if (li.stream && allow_stream) {   // streaming kernels: 256-row / 256-column tiles
                 J.stream = 1;
                 J.tm = 256;
                 J.nA = (int32_t)((li.m + 255) / 256);
@@ -174,6 +189,7 @@ Ctx make_ctx(nmf_plan_t plan, const float *dM, float *dV, float *dW, void *dws, 
         J0.chunk = l0.cp_chunk;
         J0.nC = J0.nCx * J0.chunks;
     }
+    if (allow_stream) set_fp32_stream(J0, p.lv[0], p);
     J0.prec = 0;
     J0.Mbp = J0.Mbc = nullptr;
     J0.Vb = J0.Wb = nullptr;
@@ -249,17 +265,22 @@ nmf_status sweep(Ctx &c, int d, bool fp32 = false) {
     const int64_t n = p.d.n;
     int32_t *flags = &c.st->flags;
     const int mode = p.d.algo == NMF_HALS ? 0 : (p.d.algo == NMF_MU ? 1 : 2);
-    if (J.stream)
+    if (J.stream && bf)
         NMF_LAUNCH(K_APASS, launch_apass_stream(mode, J.rpad, dj, nullptr, J.nA, c.s));
+    else if (J.stream)
+        NMF_LAUNCH(K_APASS, launch_apass_s32(mode, J.rpad, dj, nullptr, J.nA, c.s));
     else
         NMF_LAUNCH(K_APASS, launch_apass_jobs(mode, J.rpad, J.tm, dj, nullptr,
                                               apass_grid_single(J.nA),
                                               apass_lds_bytes(J.rpad, J.tm, mode), c.s, bf));
     if (mode == 2)
         NMF_LAUNCH(K_NNLS_ROWS, launch_nnls_rows(p.rpad, c.Bd, c.A, J.m, r, J.V, flags, c.stop, c.s));
-    if (J.stream)
+    if (J.stream && bf)
         NMF_LAUNCH(K_CPART, launch_cpass_stream(J.rpad, dj, nullptr,
                                                 cpass_stream_grid(J.nCx, J.chunks), c.s));
+    else if (J.stream)
+        NMF_LAUNCH(K_CPART, launch_cpass_s32(J.rpad, dj, nullptr,
+                                             cpass_stream_grid(J.nCx, J.chunks), c.s));
     else
         NMF_LAUNCH(K_CPART, launch_cpass_jobs(J.rpad, dj, nullptr,
                                               cpass_grid_single(J.nCx, J.chunks), c.s, bf));

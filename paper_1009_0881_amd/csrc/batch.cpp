@@ -126,7 +126,7 @@ nmf_status Executor::add(nmf_plan_t plan, const float *dM, float *dV, float *dW,
     Inst I;
     I.id = id;
     I.plan = plan;
-    I.c = make_ctx(plan, dM, dV, dW, dws, s_);
+    I.c = make_ctx(plan, dM, dV, dW, dws, s_, false);
     I.sched = make_schedule(p.d.cycle, p.d.levels, iters);
     I.use_tol = p.d.tol > 0.0;
     I.mode = p.d.algo == NMF_HALS ? 0 : 1;

@@ -23,6 +23,28 @@ __device__ __forceinline__ gmem<T> *to_global(T *p) {
     return (gmem<T> *)p;
 }
 
+// Position of entry k within a row of Wt (the transposed W, rpad = 16 rt
+// entries per row): interleaved so that entries 16t + p, t = 0..rt-1, of lane
+// p are contiguous and one vector load gives a lane all of its W operands.
+__host__ __device__ __forceinline__ int wt_pos(int k, int rt) { return (k & 15) * rt + (k >> 4); }
+
+// The RT operands 16t + li (t = 0..RT-1) of a row of Wt.
+template <int RT>
+__device__ __forceinline__ void load_wt(gmem<const float> *row, int li, float (&out)[RT]) {
+    typedef float v2 __attribute__((ext_vector_type(2)));
+    gmem<const float> *p = row + li * RT;
+    if constexpr (RT == 4) {
+        const v4f x = *(gmem<const v4f> *)p;
+        out[0] = x[0]; out[1] = x[1]; out[2] = x[2]; out[3] = x[3];
+    } else if constexpr (RT == 2) {
+        const v2 x = *(gmem<const v2> *)p;
+        out[0] = x[0]; out[1] = x[1];
+    } else {
+#pragma unroll
+        for (int t = 0; t < RT; ++t) out[t] = p[t];
+    }
+}
+
 __device__ __forceinline__ bool stopped(const int32_t *stop) {
     return stop != nullptr && *stop != 0;
 }

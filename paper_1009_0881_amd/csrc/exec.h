@@ -47,7 +47,10 @@ struct Ctx {
     std::vector<int8_t> depths;   // depth of every executed iteration (host mirror)
 };
 
-Ctx make_ctx(nmf_plan_t plan, const float *dM, float *dV, float *dW, void *dws, hipStream_t s);
+// allow_stream: jobs of large levels may use the streaming kernels (single
+// solves); grouped batch launches use the regular tiling.
+Ctx make_ctx(nmf_plan_t plan, const float *dM, float *dV, float *dW, void *dws, hipStream_t s,
+             bool allow_stream = true);
 // Fill an nmf_result from the final device state and the host depth log.
 nmf_status result_from_state(nmf_plan_t plan, const DevState &hs,
                              const std::vector<int8_t> &depths, nmf_result *out);

@@ -23,7 +23,8 @@ struct Job {
     int32_t depth, log_cap;
     float *V;            // level factor, m x r column-major
     float *W;            // r x n row-major
-    float *Wt;           // n x rpad, transposed and zero-padded copy of W
+    float *Wt;           // n x rpad, transposed and zero-padded copy of W; entry k of row
+                         // j at j * rpad + wt_pos(k, rpad / 16) (device_common.h)
     float *A;            // ANLS: M W^T (m x r)
     float *C;            // ANLS: V^T M (r x n)
     double *Bd, *Dd;     // W W^T and V^T V (r x r, FP64)

@@ -54,6 +54,9 @@ struct LevelInfo {
     bool stream;         // BF16 mode, large level: streaming A/C-pass kernels
     int32_t scp_chunks;  // split of the m-reduction for the streaming C-pass
     int64_t scp_chunk;
+    bool fstream;        // large level: FP32 streaming kernels possible (m % 4 == 0)
+    int32_t fcp_chunks;  // split of the m-reduction for the FP32 streaming C-pass
+    int64_t fcp_chunk;
     int32_t gram_parts;  // split of the length-m reduction of V^T V
     int64_t gram_chunk;
 };
@@ -186,6 +189,13 @@ hipError_t launch_apass_stream(int mode, int rpad, const Job *jobs, const int2 *
 hipError_t launch_cpass_stream(int rpad, const Job *jobs, const int2 *bmap, int blocks,
                                hipStream_t s);
 int cpass_stream_grid(int nCx, int chunks);
+// FP32 streaming passes (job.stream with prec 0): A-pass tiles of 128 rows,
+// C-pass tiles of 128 columns x one row chunk.  HALS / MU.
+hipError_t launch_apass_s32(int mode, int rpad, const Job *jobs, const int2 *bmap, int blocks,
+                            hipStream_t s);
+hipError_t launch_cpass_s32(int rpad, const Job *jobs, const int2 *bmap, int blocks,
+                            hipStream_t s);
+size_t apass_s32_lds_bytes(int rpad);
 size_t apass_stream_lds_bytes(int rpad);
 hipError_t launch_make_wt(const float *W, int64_t n, int r, int rpad, float *Wt, hipStream_t s);
 // Residual from separately computed Grams (ANLS path): rel_err of

@@ -207,7 +207,7 @@ __global__ __launch_bounds__(WAVES * 64) void k_nnls(const double *__restrict__ 
             X[idx] = xf;
             if (COLS) part += b * (double)xf;
         }
-        if (COLS && lane < RPAD) Xt[prob * RPAD + lane] = ok ? (float)x : 0.0f;
+        if (COLS && lane < RPAD) Xt[prob * RPAD + wt_pos(lane, RPAD / 16)] = ok ? (float)x : 0.0f;
     }
     if (failed && lane == 0) atomicOr(flags, 4);
     if constexpr (COLS) {

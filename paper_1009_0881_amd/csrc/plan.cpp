@@ -153,6 +153,18 @@ nmf_status build_plan(const nmf_desc &d0, Plan &p, std::string &err) {
         li.cp_chunk = chunk;
         li.cp_chunks = (int32_t)((li.m + chunk - 1) / chunk);
         max_cp = std::max<size_t>(max_cp, (size_t)li.cp_chunks);
+        // FP32 streaming C-pass (large levels): about two blocks per CU
+        li.fstream = d.algo != NMF_ANLS && li.m >= kStreamMinRows && li.m % 4 == 0;
+        if (li.fstream) {
+            const int64_t ncx = (d.n + 127) / 128;
+            int64_t sc = std::max<int64_t>(1, 2 * p.num_cu / ncx);
+            sc = std::min<int64_t>(sc, std::max<int64_t>(1, li.m / 64));
+            int64_t sch = (li.m + sc - 1) / sc;
+            sch = (sch + 63) / 64 * 64;
+            li.fcp_chunk = sch;
+            li.fcp_chunks = (int32_t)((li.m + sch - 1) / sch);
+            max_cp = std::max<size_t>(max_cp, (size_t)li.fcp_chunks);
+        }
         // streaming C-pass (large BF16 levels): about two blocks per CU
         li.stream = d.prec == NMF_BF16 && li.m >= kStreamMinRows;
         if (li.stream) {

@@ -273,8 +273,12 @@ __device__ void apass_tile(const Job &J, int tile, double *smem) {
             const bool ok = (s + u) < s_end && j < n;
 #pragma unroll
             for (int q = 0; q < RW; ++q) a[u][q] = (ok && rok[q]) ? Mr[q][j * ldm] : 0.0f;
+            {
+                float w[RT];
+                load_wt<RT>(Wt + (ok ? j : 0) * RPAD, li, w);
 #pragma unroll
-            for (int t = 0; t < RT; ++t) b[u][t] = ok ? Wt[j * RPAD + 16 * t + li] : 0.0f;
+                for (int t = 0; t < RT; ++t) b[u][t] = ok ? w[t] : 0.0f;
+            }
         }
     };
     auto compute = [&](const float (&a)[S][RW], const float (&b)[S][RT]) {
@@ -806,7 +810,7 @@ __device__ void cfinal_tile(const Job &J, int tile, double *smem) {
                 const float xf = (ok && k < r) ? (float)xw[t] : 0.0f;
                 Wn[jj * CS + k] = (double)xf;
                 if (ok) {
-                    to_global(J.Wt)[j * RPAD + k] = xf;
+                    to_global(J.Wt)[j * RPAD + wt_pos(k, RT)] = xf;
                     if (J.Wb) to_global(J.Wb)[(int64_t)k * J.npad + j] = bf16_rne(xf);   // BF16 mode
                     if (UPD && k < r) {
                         to_global(J.W)[(int64_t)k * n + j] = xf;
@@ -851,7 +855,7 @@ __global__ __launch_bounds__(256) void k_make_wt(const float *__restrict__ W, in
     if (e >= n * rpad) return;
     const int64_t j = e / rpad;
     const int k = (int)(e % rpad);
-    Wt[e] = k < r ? W[(int64_t)k * n + j] : 0.0f;
+    Wt[j * rpad + wt_pos(k, rpad / 16)] = k < r ? W[(int64_t)k * n + j] : 0.0f;
 }
 
 __global__ __launch_bounds__(256) void k_residual(const double *__restrict__ rparts, int nparts,
@@ -1149,6 +1153,323 @@ __global__ __launch_bounds__(256) void k_cpass_stream(const Job *__restrict__ jo
     cpass_stream_tile<RT>(J, tx, ty);
 }
 
+// ---------------------------------------------------------------------------
+// Streaming passes for large levels in FP32 mode (job.stream = 1, prec = 0):
+// m >= kStreamMinRows, m and the column stride of M multiples of 4, M 16-byte
+// aligned.  FP32 products are MFMA-bound (v_mfma_f32_16x16x4f32), so the
+// design keeps the matrix cores busy and M in flight to feed them: batches of
+// 4 K-steps, double buffered in registers.
+//
+// A-pass: a wave owns 32 rows.  Lane (li, lk) loads rows row0 + 2li, 2li + 1
+// of column 4ks + lk (8 bytes) and feeds them to two MFMAs, so MFMA s maps its
+// row index li to row row0 + 2li + s; its accumulator v of lane (li', lk')
+// holds A[row0 + 8lk' + 2v + s][16t + li'].  Every 4 K-steps (16 products per
+// chain) the accumulators are added into FP64 sums.  Past n the W operand is
+// zero (the M column read is clamped), so no load is conditional.  The V
+// update (FP64, as in the regular kernels) takes the wave's rows 4 at a time
+// from a wave-private LDS slot, one s at a time.
+// ---------------------------------------------------------------------------
+template <int RT, int MODE>
+__device__ void apass_s32_tile(const Job &J, int tile, double *smem) {
+    constexpr int RPAD = RT * 16, GS = RPAD + 1, AS = RPAD + 1, RS = 2, SB = 4;
+    typedef float v2f __attribute__((ext_vector_type(2)));
+    double *Gs = smem;
+    double *Gi = Gs + RPAD * GS;
+    const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+    const int li = lane & 15, lk = lane >> 4;
+    const int64_t m = J.m, n = J.n, ldm = J.ldm;
+    const int r = J.r;
+    const int64_t row0 = (int64_t)tile * 128 + wave * 32;
+    const int64_t rl = row0 + 2 * li;
+    const auto Mw = to_global(J.M) + (rl < m ? rl : m - 2);
+    const auto Wt = to_global(J.Wt);
+    const int64_t nsteps = (n + 3) / 4;
+    const int64_t nb = (nsteps + SB - 1) / SB;            // batches (last one padded)
+    v4f acc[RS][RT];
+    double hs[RS][RT][4];
+#pragma unroll
+    for (int s2 = 0; s2 < RS; ++s2)
+#pragma unroll
+        for (int t = 0; t < RT; ++t) {
+            acc[s2][t] = v4f{0.0f, 0.0f, 0.0f, 0.0f};
+#pragma unroll
+            for (int v = 0; v < 4; ++v) hs[s2][t][v] = 0.0;
+        }
+    v2f a0[SB], a1[SB];
+    float b0[SB][RT], b1[SB][RT];
+    auto load = [&](int64_t bidx, v2f (&a)[SB], float (&b)[SB][RT]) {
+#pragma unroll
+        for (int u = 0; u < SB; ++u) {
+            const int64_t j = 4 * (bidx * SB + u) + lk;
+            const int64_t jc = j < n ? j : n - 1;
+            a[u] = *(gmem<const v2f> *)(Mw + jc * ldm);
+            float w[RT];
+            load_wt<RT>(Wt + jc * RPAD, li, w);
+#pragma unroll
+            for (int t = 0; t < RT; ++t) b[u][t] = j < n ? w[t] : 0.0f;
+        }
+    };
+    auto compute = [&](const v2f (&a)[SB], const float (&b)[SB][RT]) {
+#pragma unroll
+        for (int u = 0; u < SB; ++u) {
+#pragma unroll
+            for (int s2 = 0; s2 < RS; ++s2)
+#pragma unroll
+                for (int t = 0; t < RT; ++t)
+                    acc[s2][t] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[u][s2], b[u][t], acc[s2][t], 0, 0, 0);
+            if ((u & 3) == 3) {        // chains of 4 K-steps (16 products) into FP64
+#pragma unroll
+                for (int s2 = 0; s2 < RS; ++s2)
+#pragma unroll
+                    for (int t = 0; t < RT; ++t) {
+#pragma unroll
+                        for (int v = 0; v < 4; ++v) hs[s2][t][v] += (double)acc[s2][t][v];
+                        acc[s2][t] = v4f{0.0f, 0.0f, 0.0f, 0.0f};
+                    }
+            }
+        }
+    };
+    load(0, a0, b0);
+    if constexpr (MODE != MODE_STORE) load_gram<RPAD>(J.Bd, r, Gs, GS, Gi);
+    int64_t bi = 0;
+    for (; bi + 2 < nb; bi += 2) {
+        load(bi + 1, a1, b1);
+        compute(a0, b0);
+        load(bi + 2, a0, b0);
+        compute(a1, b1);
+    }
+    if (bi + 1 < nb) {
+        load(bi + 1, a1, b1);
+        compute(a0, b0);
+        compute(a1, b1);
+    } else {
+        compute(a0, b0);
+    }
+    double *Aw = Gi + RPAD + wave * 16 * AS;   // 16 rows of this wave (one s)
+    __syncthreads();                            // Gram in LDS
+    auto load_x = [&](int g, double (&x)[RT]) {   // g = 4 s + v: rows row0 + 8lk + 2v + s
+        const int64_t row = row0 + 8 * lk + 2 * (g & 3) + (g >> 2);
+#pragma unroll
+        for (int t = 0; t < RT; ++t) {
+            const int k = 16 * t + li;
+            x[t] = (row < m && k < r) ? (double)to_global(J.V)[row + (int64_t)k * m] : 0.0;
+        }
+    };
+    double xc[RT], xn[RT];
+    load_x(0, xc);
+    static_for<RS>([&](auto s_c) {
+        constexpr int s2 = decltype(s_c)::value;
+        __builtin_amdgcn_wave_barrier();
+#pragma unroll
+        for (int t = 0; t < RT; ++t)
+#pragma unroll
+            for (int v = 0; v < 4; ++v) Aw[(4 * lk + v) * AS + 16 * t + li] = hs[s2][t][v];
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+#pragma unroll 1
+        for (int v = 0; v < 4; ++v) {
+            const int g = 4 * s2 + v;
+            if (g + 1 < RS * 4) load_x(g + 1, xn);
+            double a[RT];
+#pragma unroll
+            for (int t = 0; t < RT; ++t) a[t] = Aw[(4 * lk + v) * AS + 16 * t + li];
+            const int64_t row = row0 + 8 * lk + 2 * v + s2;
+            if constexpr (MODE == MODE_STORE) {
+                if (row < m) {
+#pragma unroll
+                    for (int t = 0; t < RT; ++t) {
+                        const int k = 16 * t + li;
+                        if (k < r) to_global(J.A)[row + (int64_t)k * m] = (float)a[t];
+                    }
+                }
+            } else {
+                row_update<RT, MODE>(xc, Gs, GS, Gi, a, r, li);
+                if (row < m) {
+#pragma unroll
+                    for (int t = 0; t < RT; ++t) {
+                        const int k = 16 * t + li;
+                        if (k < r) to_global(J.V)[row + (int64_t)k * m] = (float)xc[t];
+                    }
+                }
+            }
+#pragma unroll
+            for (int t = 0; t < RT; ++t) xc[t] = xn[t];
+        }
+    });
+}
+
+template <int RT, int MODE>
+__global__ __launch_bounds__(256) void k_apass_s32(const Job *__restrict__ jobs,
+                                                   const int2 *__restrict__ bmap) {
+    extern __shared__ double smem[];
+    const int2 jt = block_job(bmap);
+    const Job &J = jobs[jt.x];
+    if (jt.y >= J.nA || J.st->stop) return;
+    apass_s32_tile<RT, MODE>(J, jt.y, smem);
+}
+
+// C-pass (FP32): a block of 4 waves owns 128 columns of one row chunk; a wave
+// owns 32 columns (two 16-column tiles).  Per 16-row step a lane loads 4
+// consecutive rows of M (per column tile) and of V (per rank tile) as float4
+// and feeds them to 4 MFMAs, whose K index lk maps to row i0 + 4lk + s.  Each
+// step's chains (16 products) are added into FP64 sums.  Rows past the chunk
+// read a clamped row with a zero V operand.  The first column block of each
+// chunk also forms the chunk's V^T V partial on the FP64 matrix cores.
+template <int RT>
+__device__ void cpass_s32_tile(const Job &J, int tx, int ty) {
+    constexpr int RPAD = RT * 16, RN = 2, SB = 2, DMAX = 3;
+    const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+    const int lj = lane & 15, lg = lane >> 4;
+    const int64_t m = J.m, n = J.n, ldm = J.ldm;
+    const int r = J.r;
+    const auto V = to_global(J.V);
+    const int64_t jb = (int64_t)tx * 128 + wave * 32;
+    const int64_t i_begin = (int64_t)ty * J.chunk;
+    const int64_t i_end = (i_begin + J.chunk < m) ? i_begin + J.chunk : m;
+    const int64_t nsteps = (i_end - i_begin + 15) / 16;
+    gmem<const float> *Mc[RN];
+#pragma unroll
+    for (int c = 0; c < RN; ++c) {
+        const int64_t j = jb + 16 * c + lj;
+        Mc[c] = to_global(J.M) + (j < n ? j : n - 1) * ldm;
+    }
+    int dta[DMAX], dtb[DMAX], nd = 0;
+    if (tx == 0) {
+        int idx = 0;
+        for (int ta = 0; ta < RT; ++ta)
+            for (int tb = ta; tb < RT; ++tb, ++idx)
+                if (idx % 4 == wave && nd < DMAX) {
+                    dta[nd] = ta;
+                    dtb[nd] = tb;
+                    ++nd;
+                }
+    }
+    v4f acc[RN][RT];
+    double hs[RN][RT][4];
+    v4d dacc[DMAX];
+#pragma unroll
+    for (int c = 0; c < RN; ++c)
+#pragma unroll
+        for (int t = 0; t < RT; ++t) {
+            acc[c][t] = v4f{0.0f, 0.0f, 0.0f, 0.0f};
+#pragma unroll
+            for (int v = 0; v < 4; ++v) hs[c][t][v] = 0.0;
+        }
+#pragma unroll
+    for (int d = 0; d < DMAX; ++d) dacc[d] = v4d{0.0, 0.0, 0.0, 0.0};
+    v4f ma0[SB][RN], vb0[SB][RT], ma1[SB][RN], vb1[SB][RT];
+    auto load = [&](int64_t st0, v4f (&a)[SB][RN], v4f (&b)[SB][RT]) {
+#pragma unroll
+        for (int u = 0; u < SB; ++u) {
+            const int64_t ib = i_begin + 16 * (st0 + u) + 4 * lg;   // rows ib .. ib+3
+            const bool ok = ib < i_end;                             // whole groups of 4 (m % 4 == 0)
+            const int64_t ic = ok ? ib : i_begin;
+#pragma unroll
+            for (int c = 0; c < RN; ++c) a[u][c] = *(gmem<const v4f> *)(Mc[c] + ic);
+#pragma unroll
+            for (int t = 0; t < RT; ++t) {
+                const int k = 16 * t + lj;
+                const v4f x = *(gmem<const v4f> *)(V + ic + (int64_t)(k < r ? k : 0) * m);
+                b[u][t] = (ok && k < r) ? x : v4f{0.0f, 0.0f, 0.0f, 0.0f};
+            }
+        }
+    };
+    auto compute = [&](const v4f (&a)[SB][RN], const v4f (&b)[SB][RT]) {
+#pragma unroll
+        for (int u = 0; u < SB; ++u) {
+#pragma unroll
+            for (int s = 0; s < 4; ++s)
+#pragma unroll
+                for (int c = 0; c < RN; ++c)
+#pragma unroll
+                    for (int t = 0; t < RT; ++t)
+                        acc[c][t] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[u][c][s], b[u][t][s], acc[c][t], 0, 0, 0);
+#pragma unroll
+            for (int c = 0; c < RN; ++c)
+#pragma unroll
+                for (int t = 0; t < RT; ++t) {
+#pragma unroll
+                    for (int v = 0; v < 4; ++v) hs[c][t][v] += (double)acc[c][t][v];
+                    acc[c][t] = v4f{0.0f, 0.0f, 0.0f, 0.0f};
+                }
+#pragma unroll
+            for (int d = 0; d < DMAX; ++d) {
+                if (d < nd) {
+#pragma unroll
+                    for (int s = 0; s < 4; ++s) {
+                        double va = 0.0, vb = 0.0;
+#pragma unroll
+                        for (int t = 0; t < RT; ++t) {
+                            if (t == dta[d]) va = (double)b[u][t][s];
+                            if (t == dtb[d]) vb = (double)b[u][t][s];
+                        }
+                        dacc[d] = __builtin_amdgcn_mfma_f64_16x16x4f64(va, vb, dacc[d], 0, 0, 0);
+                    }
+                }
+            }
+        }
+    };
+    const int64_t nb = (nsteps + SB - 1) / SB;
+    if (nb > 0) {
+        load(0, ma0, vb0);
+        int64_t bi = 0;
+        for (; bi + 2 < nb; bi += 2) {
+            load(SB * (bi + 1), ma1, vb1);
+            compute(ma0, vb0);
+            load(SB * (bi + 2), ma0, vb0);
+            compute(ma1, vb1);
+        }
+        if (bi + 1 < nb) {
+            load(SB * (bi + 1), ma1, vb1);
+            compute(ma0, vb0);
+            compute(ma1, vb1);
+        } else {
+            compute(ma0, vb0);
+        }
+    }
+    // hs[c][t][v] = C[k = 16t + lj][j = jb + 16c + 4lg + v]
+    const auto out = to_global(J.Cp) + (int64_t)ty * r * n;
+#pragma unroll
+    for (int t = 0; t < RT; ++t) {
+        const int k = 16 * t + lj;
+        if (k < r) {
+#pragma unroll
+            for (int c = 0; c < RN; ++c)
+#pragma unroll
+                for (int v = 0; v < 4; ++v) {
+                    const int64_t j = jb + 16 * c + 4 * lg + v;
+                    if (j < n) out[(int64_t)k * n + j] = hs[c][t][v];
+                }
+        }
+    }
+    // dacc[d][v] = D[16 dta + 4v + lg][16 dtb + lj]  (FP64 MFMA layout)
+    const auto dout = to_global(J.Dp) + (int64_t)ty * RPAD * RPAD;
+#pragma unroll
+    for (int d = 0; d < DMAX; ++d) {
+        if (d < nd) {
+#pragma unroll
+            for (int v = 0; v < 4; ++v)
+                dout[(16 * dta[d] + 4 * v + lg) * RPAD + 16 * dtb[d] + lj] = dacc[d][v];
+        }
+    }
+}
+
+template <int RT>
+__global__ __launch_bounds__(256) void k_cpass_s32(const Job *__restrict__ jobs,
+                                                   const int2 *__restrict__ bmap) {
+    const int2 jt = block_job(bmap);
+    const Job &J = jobs[jt.x];
+    int tx = jt.y % J.nCx, ty = jt.y / J.nCx;
+    if (!bmap) {   // single problem: the column blocks of a chunk run on one XCD
+        const int l = (int)(blockIdx.x >> 3);
+        ty = (int)(blockIdx.x & 7) + 8 * (l / J.nCx);
+        tx = l % J.nCx;
+    }
+    if (ty >= J.chunks || J.st->stop) return;
+    cpass_s32_tile<RT>(J, tx, ty);
+}
+
 }  // namespace
 
 // ---- host side -------------------------------------------------------------
@@ -1286,6 +1607,44 @@ int apass_grid_single(int nA) { return 8 * ((nA + 7) / 8); }
 
 int cpass_stream_grid(int nCx, int chunks) { return 8 * nCx * ((chunks + 7) / 8); }
 
+// FP64 Gram and 1/G_kk, then 4 waves x 16 rows of A (FP64, stride rpad + 1).
+size_t apass_s32_lds_bytes(int rpad) {
+    return sizeof(double) * ((size_t)rpad * (rpad + 1) + rpad + 4 * 16 * (size_t)(rpad + 1));
+}
+
+hipError_t launch_apass_s32(int mode, int rpad, const Job *jobs, const int2 *bmap, int blocks,
+                            hipStream_t s) {
+    if (blocks <= 0) return hipSuccess;
+    if (mode != MODE_HALS && mode != MODE_MU) return hipErrorInvalidValue;
+    const size_t lds = apass_s32_lds_bytes(rpad);
+    const bool h = mode == MODE_HALS;
+    switch (rpad) {
+        case 16: h ? k_apass_s32<1, MODE_HALS><<<blocks, 256, lds, s>>>(jobs, bmap)
+                   : k_apass_s32<1, MODE_MU><<<blocks, 256, lds, s>>>(jobs, bmap); break;
+        case 32: h ? k_apass_s32<2, MODE_HALS><<<blocks, 256, lds, s>>>(jobs, bmap)
+                   : k_apass_s32<2, MODE_MU><<<blocks, 256, lds, s>>>(jobs, bmap); break;
+        case 48: h ? k_apass_s32<3, MODE_HALS><<<blocks, 256, lds, s>>>(jobs, bmap)
+                   : k_apass_s32<3, MODE_MU><<<blocks, 256, lds, s>>>(jobs, bmap); break;
+        case 64: h ? k_apass_s32<4, MODE_HALS><<<blocks, 256, lds, s>>>(jobs, bmap)
+                   : k_apass_s32<4, MODE_MU><<<blocks, 256, lds, s>>>(jobs, bmap); break;
+        default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_cpass_s32(int rpad, const Job *jobs, const int2 *bmap, int blocks,
+                            hipStream_t s) {
+    if (blocks <= 0) return hipSuccess;
+    switch (rpad) {
+        case 16: k_cpass_s32<1><<<blocks, 256, 0, s>>>(jobs, bmap); break;
+        case 32: k_cpass_s32<2><<<blocks, 256, 0, s>>>(jobs, bmap); break;
+        case 48: k_cpass_s32<3><<<blocks, 256, 0, s>>>(jobs, bmap); break;
+        case 64: k_cpass_s32<4><<<blocks, 256, 0, s>>>(jobs, bmap); break;
+        default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
 // Gram and 1/G_kk, then 4 waves x 64 rows of A (all FP32, stride rpad + 1).
 size_t apass_stream_lds_bytes(int rpad) {
     return sizeof(float) * ((size_t)rpad * (rpad + 1) + rpad) +
@@ -1356,7 +1715,9 @@ static void lds_attr_modes(hipError_t &e) {
                                        hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
     if (x != hipSuccess && e == hipSuccess) e = x;
     for (const void *f : {(const void *)k_apass_stream<RT, MODE_HALS>,
-                          (const void *)k_apass_stream<RT, MODE_MU>}) {
+                          (const void *)k_apass_stream<RT, MODE_MU>,
+                          (const void *)k_apass_s32<RT, MODE_HALS>,
+                          (const void *)k_apass_s32<RT, MODE_MU>}) {
         x = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
         if (x != hipSuccess && e == hipSuccess) e = x;
     }

@@ -112,6 +112,32 @@ def test_single_level_iterations_match_oracle(algo, h, w, n, r):
     assert frob_rel(W, ores.W) <= TOL_FACTOR
 
 
+@pytest.mark.parametrize("algo", ["hals", "mu"])
+@pytest.mark.parametrize("h,w,n,r", [(184, 184, 70, 10), (184, 184, 66, 20), (182, 184, 61, 40),
+                                     (184, 184, 64, 50)])
+def test_streaming_fp32_iterations_match_oracle(algo, h, w, n, r):
+    """Levels with m >= 32768 use the FP32 streaming A- and C-pass kernels
+    (every rank class here); same parity bar as the regular kernels."""
+    say("streaming fp32", algo, h, w, n, r)
+    spec = synth.BlobSpec(h=h, w=w, n=n, r=r, k_lo=1, k_hi=max(1, min(5, r)),
+                          sig_lo=2.0, sig_hi=max(2.5, h / 4))
+    inst = synth.make_instance(spec, seed=5)
+    iters = 12
+    pl = P.Plan(m=h * w, n=n, h=h, w=w, r=r, algo=algo)
+    Md, Vd, Wd = P.to_device(inst.M, inst.V0, inst.W0)
+    res = pl.solve(Md, Vd, Wd, iters)
+    rel, _ = pl.log(res["_workspace"])
+    V, W = P.factors_to_host(Vd, Wd)
+    ores = O.solve(inst.M, h, w, r, 1, P.ALGOS[algo], O.NI, O.XFER_FW, iters, inst.V0, inst.W0)
+    orel = ores.rel_errs
+    assert res["log_len"] == iters
+    d = np.max(np.abs(rel[:iters] - orel))
+    say("  max |d rel_err|", d, "V", frob_rel(V, ores.V), "W", frob_rel(W, ores.W))
+    assert d <= TOL_REL_ERR
+    assert frob_rel(V, ores.V) <= TOL_FACTOR
+    assert frob_rel(W, ores.W) <= TOL_FACTOR
+
+
 @pytest.mark.parametrize("h,w,n,r", [(16, 16, 500, 10), (5, 7, 37, 3), (9, 9, 130, 17),
                                      (8, 8, 20, 1), (16, 16, 80, 64), (28, 23, 120, 40)])
 def test_anls_iterations_match_oracle(h, w, n, r):
