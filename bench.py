@@ -192,6 +192,7 @@ def bench_serve(args) -> int:
     gaps = rng.exponential(1.0 / args.rate, size=int(total * args.rate * 1.5) + 16)
     arrivals = np.cumsum(gaps)
     arrivals = arrivals[arrivals < total]
+    is_bf16 = rng.random(len(arrivals)) < args.bf16_share
     pending, done = {}, []
     t0 = time.perf_counter()
     k = 0
@@ -200,17 +201,18 @@ def bench_serve(args) -> int:
             now = time.perf_counter() - t0
             while k < len(arrivals) and arrivals[k] <= now:
                 spec, inst = pool[k % len(pool)]
+                prec = dict(prec="bf16", refine_iters=2) if is_bf16[k] else {}
                 t = srv.submit(inst.M, inst.V0, inst.W0, args.budget, spec.h, spec.w, spec.r,
                                levels=3, algo="hals", cycle=args.cycle, xfer="fw",
                                tol=inst.eps_E + 2e-2, max_fine_iters=args.max_fine_iters,
-                               check_every=4)
+                               check_every=4, **prec)
                 pending[t] = (arrivals[k], k)
                 k += 1
             for t in list(pending):
                 r = srv.poll(t)
                 if r is not None:
                     arr, idx = pending.pop(t)
-                    done.append((arr, time.perf_counter() - t0, r[2]))
+                    done.append((arr, time.perf_counter() - t0, r[2], bool(is_bf16[idx])))
             time.sleep(0.0005)
         st = srv.stats()
     finally:
@@ -226,11 +228,14 @@ def bench_serve(args) -> int:
         "value": round(len(meas) / span, 2), "unit": "solves/s", "n_gpus": 1,
         "steps": len(meas), "warmup": len(done) - len(meas),
         "ms_per_step": round(float(np.mean(lat)), 3), "higher_is_better": True,
-        "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+        "scaling": "weak", "vs_baseline": None, "dtype": "f32+bf16", "data": "synthetic",
         "config": {"workload": f"serve: Poisson {args.rate:g} req/s for {args.duration:g} s after "
                                f"{warm:g} s warm-up, problems drawn like the 512-problem batch "
-                               f"(3 levels FW, {args.cycle.upper()} HALS FP32, T={args.budget}), "
-                               f"each to rel_err <= eps_E+0.02, 64 slots, 16 GiB pool"},
+                               f"(3 levels FW, {args.cycle.upper()} HALS, T={args.budget}; "
+                               f"{100 * args.bf16_share:g}% BF16 with 2 FP32 refinement "
+                               f"iterations, the rest FP32), each to rel_err <= eps_E+0.02, "
+                               f"64 slots, 16 GiB pool"},
+        "bf16_requests": int(sum(1 for d in meas if d[3])),
         "latency_ms": {"p50": round(float(np.percentile(lat, 50)), 3),
                        "p99": round(float(np.percentile(lat, 99)), 3),
                        "host_poll_p50": round(float(np.percentile(lat_host, 50)), 3),
@@ -252,6 +257,8 @@ def main() -> int:
     ap.add_argument("--count", type=int, default=512, help="batch: problems per batch")
     ap.add_argument("--rate", type=float, default=200.0, help="serve: arrivals per second")
     ap.add_argument("--duration", type=float, default=20.0, help="serve: measured seconds")
+    ap.add_argument("--bf16-share", type=float, default=0.3,
+                    help="serve: fraction of requests in BF16 with FP32 refinement")
     ap.add_argument("--graph", action="store_true", help="batch: replay steady ticks as hipGraphs")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="BYTES",
                     help="only run 3 device-to-device copies of BYTES bytes (reference for "

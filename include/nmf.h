@@ -181,13 +181,16 @@ nmf_status nmf_profile_read(nmf_plan_t plan, int64_t *counts, double *total_ms, 
 
 /* ---- batched solves ---------------------------------------------------------
  * Many independent solves (each its own plan: uneven m, n, r, levels, cycle,
- * budget and tolerance; HALS or MU) advanced together: every tick, each
- * unfinished problem performs its pending V transfers and one sweep at its
- * current level, and the work of all problems is issued as one launch per
- * phase and tile configuration (rank class r padded to 16/32/48/64, A-pass
- * tile rows, update rule).  A problem's arithmetic is exactly that of
- * nmf_solve on its own plan, so its V, W and result are bitwise those of a
- * single solve.
+ * budget, tolerance and precision; HALS or MU) advanced together: every tick,
+ * each unfinished problem performs its pending V transfers and one sweep at
+ * its current level (BF16 problems: the BF16 schedule, then the FP32
+ * refinement and continuation, as in nmf_solve), and the work of all problems
+ * is issued as one launch per phase and tile configuration (rank class r
+ * padded to 16/32/48/64, A-pass tile rows, update rule, precision).  A
+ * problem's arithmetic is that of nmf_solve on its own plan, so its V, W and
+ * result are bitwise those of a single solve -- except for levels with
+ * m >= 32768, which nmf_solve runs on its streaming kernels and a batch on the
+ * regular tiling (both within the FP32 parity bar of the oracle).
  *
  * nmf_batch_workspace: bytes of the one device workspace of a batch over
  * these plans (their own workspaces, 256-byte aligned, back to back, then the

@@ -221,6 +221,28 @@ nmf_status result_from_state(nmf_plan_t plan, const DevState &hs,
     return NMF_OK;
 }
 
+// BF16 mode: operand copies of every M_l (A-pass and C-pass layouts) and the
+// zero padding of the V and W copies (their live part is written by the
+// kernels that update V and W).
+nmf_status prepare_bf16(Ctx &c) {
+    nmf_plan_t plan = c.plan;
+    const Plan &p = *c.p;
+    if (p.d.prec != NMF_BF16) return NMF_OK;
+    const Job &J0 = c.jobs[0];
+    for (size_t l = 0; l < p.lv.size(); ++l) {
+        const Job &J = c.jobs[l];
+        NMF_HIP(launch_pack_bf16(c.M[l], c.ldm[l], J.m, J.n, const_cast<uint16_t *>(J.Mbp),
+                                 J.npad, c.s));
+        NMF_HIP(launch_to_bf16_cols(c.M[l], c.ldm[l], J.m, J.n, const_cast<uint16_t *>(J.Mbc),
+                                    J.mpad, J.n, c.s));
+        NMF_HIP(launch_to_bf16_cols(c.V[l], J.m, J.m, J.r, J.Vb, J.mpad, J.rpad, c.s));
+    }
+    // W (r x n row-major) read as n x r column-major: Wb is rpad x npad row-major
+    NMF_HIP(launch_to_bf16_cols(c.W, J0.n, J0.n, J0.r, J0.Wb, J0.npad, J0.rpad, c.s));
+    return NMF_OK;
+}
+
+
 namespace {
 
 nmf_status upload_jobs(Ctx &c) {
@@ -317,27 +339,6 @@ nmf_status prepare_levels(Ctx &c) {
                                          c.nparts + l * kNormParts, norm_parts(p.lv[l].m, p.d.n),
                                          c.norm + l, c.s));
     }
-    return NMF_OK;
-}
-
-// BF16 mode: operand copies of every M_l (A-pass and C-pass layouts) and the
-// zero padding of the V and W copies (their live part is written by the
-// kernels that update V and W).
-nmf_status prepare_bf16(Ctx &c) {
-    nmf_plan_t plan = c.plan;
-    const Plan &p = *c.p;
-    if (p.d.prec != NMF_BF16) return NMF_OK;
-    const Job &J0 = c.jobs[0];
-    for (size_t l = 0; l < p.lv.size(); ++l) {
-        const Job &J = c.jobs[l];
-        NMF_HIP(launch_pack_bf16(c.M[l], c.ldm[l], J.m, J.n, const_cast<uint16_t *>(J.Mbp),
-                                 J.npad, c.s));
-        NMF_HIP(launch_to_bf16_cols(c.M[l], c.ldm[l], J.m, J.n, const_cast<uint16_t *>(J.Mbc),
-                                    J.mpad, J.n, c.s));
-        NMF_HIP(launch_to_bf16_cols(c.V[l], J.m, J.m, J.r, J.Vb, J.mpad, J.rpad, c.s));
-    }
-    // W (r x n row-major) read as n x r column-major: Wb is rpad x npad row-major
-    NMF_HIP(launch_to_bf16_cols(c.W, J0.n, J0.n, J0.r, J0.Wb, J0.npad, J0.rpad, c.s));
     return NMF_OK;
 }
 

@@ -120,8 +120,6 @@ nmf_status Executor::add(nmf_plan_t plan, const float *dM, float *dV, float *dW,
     const Plan &p = plan->p;
     if (p.d.algo == NMF_ANLS)
         return fail(plan, NMF_E_ARG, "batched solves support HALS and MU (ANLS: use nmf_solve)");
-    if (p.d.prec != NMF_FP32)
-        return fail(plan, NMF_E_ARG, "batched solves run in FP32 (BF16: use nmf_solve)");
     if ((int)insts_.size() >= capacity_) return fail(plan, NMF_E_BUSY, "batch capacity reached");
     Inst I;
     I.id = id;
@@ -130,6 +128,7 @@ nmf_status Executor::add(nmf_plan_t plan, const float *dM, float *dV, float *dW,
     I.sched = make_schedule(p.d.cycle, p.d.levels, iters);
     I.use_tol = p.d.tol > 0.0;
     I.mode = p.d.algo == NMF_HALS ? 0 : 1;
+    I.bf16 = p.d.prec == NMF_BF16;
     insts_.push_back(std::move(I));
     fresh_.push_back(id);
     return NMF_OK;
@@ -207,6 +206,9 @@ nmf_status Executor::setup_fresh() {
         if ((st = upload(nj, &dn)) != NMF_OK || (st = upload(bm, &db)) != NMF_OK) return st;
         NMF_HIP(launch_norms_many(dn, db, (int)bm.size(), (int)nj.size(), s_));
     }
+    // BF16 problems: operand copies of every level (per problem)
+    for (Inst *I : F)
+        if (I->bf16 && (st = prepare_bf16(I->c)) != NMF_OK) return st;
     // Wt and B = W W^T: W tile kernel in init mode, then the B-only reduce,
     // grouped by rank class
     std::map<int, std::vector<Inst *>> by_rpad;
@@ -233,15 +235,25 @@ nmf_status Executor::setup_fresh() {
 }
 
 // Move a problem's cursor over transfer steps (collected in order) to its next
-// sweep; after the schedule, fine iterations continue while a tolerance is set.
+// sweep; after the schedule, BF16 problems run their FP32 refinement, and fine
+// iterations continue while a tolerance is set (the order of nmf_solve).
 void Executor::advance(Inst &I, std::vector<Step> &xfers) {
+    auto after_schedule = [&]() {
+        if (I.use_tol && I.c.p->d.max_fine_iters > 0) {
+            I.stage = 1;
+            I.cont_left = I.c.p->d.max_fine_iters;
+        } else {
+            I.stage = 2;
+        }
+    };
+    if (I.stage == 3 && I.refine_left <= 0) after_schedule();
     while (I.stage == 0) {
         if (I.cur >= I.sched.size()) {
-            if (I.use_tol && I.c.p->d.max_fine_iters > 0) {
-                I.stage = 1;
-                I.cont_left = I.c.p->d.max_fine_iters;
+            if (I.bf16 && I.c.p->d.refine_iters > 0) {
+                I.stage = 3;
+                I.refine_left = I.c.p->d.refine_iters;
             } else {
-                I.stage = 2;
+                after_schedule();
             }
             break;
         }
@@ -264,6 +276,8 @@ void Executor::advance(Inst &I, std::vector<Step> &xfers) {
         if (I.cont_left <= 0) I.stage = 2;
         I.depth = 0;
     }
+    if (I.stage == 3) I.depth = 0;
+    I.fp32job = I.bf16 && (I.stage == 1 || I.stage == 3);
 }
 
 nmf_status Executor::launch_xfers(std::vector<std::pair<Inst *, std::vector<Step>>> &todo) {
@@ -313,10 +327,13 @@ nmf_status Executor::launch_xfers(std::vector<std::pair<Inst *, std::vector<Step
 // the five phases of each group.
 nmf_status Executor::launch_sweeps(const std::vector<Inst *> &active, bool capture_ok) {
     nmf_plan_t plan = nullptr;
-    std::map<std::tuple<int, int, int>, std::vector<Inst *>> groups;
+    std::map<std::tuple<int, int, int, int>, std::vector<Inst *>> groups;
+    auto job_of = [](const Inst *I) -> const Job & {
+        return I->fp32job ? I->c.jobs.back() : I->c.jobs[I->depth];
+    };
     for (Inst *I : active) {
-        const Job &J = I->c.jobs[I->depth];
-        groups[std::make_tuple(J.rpad, J.tm, I->mode)].push_back(I);
+        const Job &J = job_of(I);
+        groups[std::make_tuple(J.rpad, J.tm, I->mode, J.prec)].push_back(I);
     }
     std::vector<G> gl;
     std::vector<int64_t> key;
@@ -326,10 +343,11 @@ nmf_status Executor::launch_sweeps(const std::vector<Inst *> &active, bool captu
         g.rpad = std::get<0>(kv.first);
         g.tm = std::get<1>(kv.first);
         g.mode = std::get<2>(kv.first);
-        std::vector<int64_t> gkey{g.rpad, g.tm, g.mode};
+        g.bf = std::get<3>(kv.first) == 1;
+        std::vector<int64_t> gkey{g.rpad, g.tm, g.mode, g.bf ? 1 : 0};
         for (Inst *I : kv.second) {
             gkey.push_back(I->id);
-            gkey.push_back(I->depth);
+            gkey.push_back(I->fp32job ? -1 : I->depth);
         }
         key.insert(key.end(), gkey.begin(), gkey.end());
         auto it = cache_.find(gkey);
@@ -339,7 +357,7 @@ nmf_status Executor::launch_sweeps(const std::vector<Inst *> &active, bool captu
             std::vector<Job> jobs;
             std::vector<int2> bA, bC, bG, bF;
             for (Inst *I : kv.second) {
-                const Job &J = I->c.jobs[I->depth];
+                const Job &J = job_of(I);
                 const int j = (int)jobs.size();
                 for (int k = 0; k < J.nA; ++k) bA.push_back(make_int2(j, k));
                 for (int k = 0; k < J.nC; ++k) bC.push_back(make_int2(j, k));
@@ -362,8 +380,8 @@ nmf_status Executor::launch_sweeps(const std::vector<Inst *> &active, bool captu
     auto launch_all = [&]() -> nmf_status {
         for (const G &g : gl) {
             NMF_HIP(launch_apass_jobs(g.mode, g.rpad, g.tm, g.dj, g.bA, g.nA,
-                                      apass_lds_bytes(g.rpad, g.tm, g.mode), s_));
-            NMF_HIP(launch_cpass_jobs(g.rpad, g.dj, g.bC, g.nC, s_));
+                                      apass_lds_bytes(g.rpad, g.tm, g.mode), s_, g.bf));
+            NMF_HIP(launch_cpass_jobs(g.rpad, g.dj, g.bC, g.nC, s_, g.bf));
             NMF_HIP(launch_reduce_jobs(0, g.dj, g.bG, g.nG, s_));
             NMF_HIP(launch_cfinal_jobs(g.mode, g.rpad, g.dj, g.bF, g.nF,
                                        cfinal_lds_bytes(g.rpad, g.mode), s_));
@@ -426,6 +444,8 @@ nmf_status Executor::tick() {
                 ++I->cur;
                 I->left = -1;
             }
+        } else if (I->stage == 3) {
+            --I->refine_left;
         } else {
             --I->cont_left;
         }

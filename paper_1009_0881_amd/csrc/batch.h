@@ -53,15 +53,20 @@ private:
         std::vector<Step> sched;
         size_t cur = 0;
         int left = -1;        // iterations left in the run step at `cur`
-        int stage = 0;        // 0 schedule, 1 fine iterations after it, 2 done
+        int stage = 0;        // 0 schedule, 3 FP32 refinement (BF16 mode), 1 fine
+                              // iterations after the schedule, 2 done
         int cont_left = 0;
         int since_check = 0;
         int depth = 0;
         int mode = 0;         // 0 HALS, 1 MU
         bool use_tol = false;
+        bool bf16 = false;    // BF16 schedule, then FP32 refinement / continuation
+        int refine_left = 0;  // stage 3: FP32 refinement iterations left
+        bool fp32job = false; // this tick's sweep uses the FP32 finest-level job
     };
     struct G {
         int rpad, tm, mode;
+        bool bf;
         const Job *dj;
         const int2 *bA, *bC, *bG, *bF;
         int nA, nC, nG, nF;

@@ -51,6 +51,9 @@ struct Ctx {
 // solves); grouped batch launches use the regular tiling.
 Ctx make_ctx(nmf_plan_t plan, const float *dM, float *dV, float *dW, void *dws, hipStream_t s,
              bool allow_stream = true);
+// BF16 mode: the BF16 operand copies of every level (and padding of the V
+// and W copies); nothing in FP32 mode.
+nmf_status prepare_bf16(Ctx &c);
 // Fill an nmf_result from the final device state and the host depth log.
 nmf_status result_from_state(nmf_plan_t plan, const DevState &hs,
                              const std::vector<int8_t> &depths, nmf_result *out);

@@ -26,6 +26,8 @@ MIX = [
     (16, 16, 100, 12, 1, "mu", "ni", "fw", 10, 0.0),
     (20, 28, 411, 40, 3, "hals", "fmg", "fw", 8, 2e-2),
     (64, 64, 200, 9, 3, "hals", "vc", "fw", 8, 1e-2),
+    (32, 32, 320, 24, 3, "hals-bf16", "vc", "fw", 8, 1e-2),   # BF16 + FP32 refinement
+    (24, 24, 150, 12, 2, "mu-bf16", "ni", "fw", 10, 0.0),
 ]
 
 
@@ -42,9 +44,11 @@ def _instances(mix, seed0=300):
 
 
 def _plan(d):
+    algo, _, prec = d["algo"].partition("-")
     return P.Plan(m=d["h"] * d["w"], n=d["n"], h=d["h"], w=d["w"], r=d["r"], levels=d["L"],
-                  algo=d["algo"], cycle=d["cyc"], xfer=d["xf"], tol=d["tol"],
-                  max_fine_iters=200 if d["tol"] > 0 else 0, check_every=4)
+                  algo=algo, cycle=d["cyc"], xfer=d["xf"], tol=d["tol"],
+                  max_fine_iters=200 if d["tol"] > 0 else 0, check_every=4,
+                  prec=prec or "fp32", refine_iters=3 if prec else 0)
 
 
 def _run_single(d):

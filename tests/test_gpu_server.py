@@ -31,6 +31,8 @@ def _requests(count, seed):
         desc = dict(levels=3, algo=algo, cycle="vc" if i % 2 else "ni", xfer="fw",
                     tol=inst.eps_E + tau if tau else 0.0,
                     max_fine_iters=300 if tau else 0, check_every=4)
+        if i % 10 in (2, 5, 8):          # 30% BF16 with FP32 refinement
+            desc.update(prec="bf16", refine_iters=2)
         out.append((spec, inst, desc, 8))
     return out
 
