@@ -233,8 +233,12 @@ nmf_status prepare_bf16(Ctx &c) {
         const Job &J = c.jobs[l];
         NMF_HIP(launch_pack_bf16(c.M[l], c.ldm[l], J.m, J.n, const_cast<uint16_t *>(J.Mbp),
                                  J.npad, c.s));
-        NMF_HIP(launch_to_bf16_cols(c.M[l], c.ldm[l], J.m, J.n, const_cast<uint16_t *>(J.Mbc),
-                                    J.mpad, J.n, c.s));
+        if (J.stream)
+            NMF_HIP(launch_pack_bf16_cpanel(c.M[l], c.ldm[l], J.m, J.n,
+                                            const_cast<uint16_t *>(J.Mbc), J.mpad, c.s));
+        else
+            NMF_HIP(launch_to_bf16_cols(c.M[l], c.ldm[l], J.m, J.n,
+                                        const_cast<uint16_t *>(J.Mbc), J.mpad, J.n, c.s));
         NMF_HIP(launch_to_bf16_cols(c.V[l], J.m, J.m, J.r, J.Vb, J.mpad, J.rpad, c.s));
     }
     // W (r x n row-major) read as n x r column-major: Wb is rpad x npad row-major

@@ -41,7 +41,10 @@ struct Job {
     // Mbp: A-pass copy of M, K-packed: element (i, j) at
     //      ((i/16 * G + j/8) * 16 + i%16) * 8 + j%8, G = npad / 8, zero padded to
     //      16-row panels and npad columns.
-    // Mbc: C-pass copy of M, column-major with column stride mpad (rows >= m zero).
+    // Mbc: C-pass copy of M, column-major with column stride mpad (rows >= m zero);
+    //      on streaming levels column-panelled instead: element (i, j) at
+    //      ((j/16 * (mpad/32) + i/32) * 4 + i%32/8) * 128 + j%16 * 8 + i%8, so the
+    //      32 x 16 block of a C-pass K-step is 1 KB contiguous (columns >= n zero).
     // Vb:  V, column-major with stride mpad, rpad columns (k >= r zero).
     // Wb:  W, rpad x npad row-major (k >= r or j >= n zero).
     // mpad = m and npad = n rounded up to 128.

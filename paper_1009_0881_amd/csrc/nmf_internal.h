@@ -124,6 +124,10 @@ hipError_t launch_to_bf16_cols(const float *X, int64_t ldx, int64_t rows, int64_
                                uint16_t *Y, int64_t rows_pad, int64_t cols_pad, hipStream_t s);
 hipError_t launch_pack_bf16(const float *X, int64_t ldx, int64_t rows, int64_t cols, uint16_t *Y,
                             int64_t cols_pad, hipStream_t s);
+// pack_bf16_cpanel: the column-panelled C-pass layout of streaming levels
+// (rows_pad a multiple of 32, columns padded to 16).
+hipError_t launch_pack_bf16_cpanel(const float *X, int64_t ldx, int64_t rows, int64_t cols,
+                                   uint16_t *Y, int64_t rows_pad, hipStream_t s);
 
 hipError_t launch_gram(int rpad, int r, int64_t L, const float *X, int64_t ldx, int parts,
                        int64_t chunk, double *gparts, double *Gd, float *Gf, const int32_t *stop,
@@ -205,6 +209,7 @@ hipError_t launch_residual(const double *rparts, int nparts, const double *Dd, c
                            int32_t *log_depth, int log_cap, DevState *st, double tol,
                            hipStream_t s);
 hipError_t enable_large_lds();
+hipError_t enable_stream_lds();   // streaming A-passes (called by enable_large_lds)
 
 // ANLS: exact FP64 NNLS per row of V (G = W W^T, rhs = A rows) or per column
 // of W (G = V^T V, rhs = C columns); warm-started from the current factor.

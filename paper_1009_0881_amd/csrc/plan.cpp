@@ -148,7 +148,9 @@ nmf_status build_plan(const nmf_desc &d0, Plan &p, std::string &err) {
         int64_t chunks = std::max<int64_t>(1, p.num_cu / std::max<int64_t>(1, ntiles));
         chunks = std::min<int64_t>(chunks, std::max<int64_t>(1, (li.m + 63) / 64));
         int64_t chunk = (li.m + chunks - 1) / chunks;
-        const int64_t q = d.prec == NMF_BF16 ? kBfPad : 16;   // BF16: see kBfPad
+        // FP32: whole 16-row steps for each of up to 4 row groups of a C-pass
+        // tile; BF16: see kBfPad
+        const int64_t q = d.prec == NMF_BF16 ? kBfPad : 64;
         chunk = (chunk + q - 1) / q * q;
         li.cp_chunk = chunk;
         li.cp_chunks = (int32_t)((li.m + chunk - 1) / chunk);
@@ -238,7 +240,7 @@ nmf_status build_plan(const nmf_desc &d0, Plan &p, std::string &err) {
         for (auto &li : p.lv) {
             li.mpad = bf_pad(li.m);
             li.off_Mbp = take(sizeof(uint16_t) * (size_t)((li.m + 15) / 16 * 16) * npad);
-            li.off_Mbc = take(sizeof(uint16_t) * (size_t)li.mpad * n);
+            li.off_Mbc = take(sizeof(uint16_t) * (size_t)li.mpad * (size_t)((n + 15) / 16 * 16));
             li.off_Vb = take(sizeof(uint16_t) * (size_t)li.mpad * p.rpad);
         }
         ws.off_Wb = take(sizeof(uint16_t) * (size_t)p.rpad * npad);

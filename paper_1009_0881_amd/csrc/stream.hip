@@ -1,0 +1,804 @@
+// Streaming passes for large levels (m >= kStreamMinRows): the A-pass and
+// C-pass of one iteration (Alg. 2 / Alg. 3) as long register-pipelined loops
+// over the whole of n (A-pass) or a long row chunk (C-pass), in BF16 (k_*_stream)
+// or FP32 (k_*_s32).  The Gram, reduction and W-update kernels are those of
+// the regular path.
+
+#include "sweep_device.h"
+
+namespace nmf {
+
+namespace {
+
+// ---------------------------------------------------------------------------
+// Operand staging through LDS by DMA (global_load_lds_dwordx4): lane l's 16
+// bytes at src land at dst + 16 l, dst uniform over the wave.  The copies are
+// counted by the wave's vector-memory counter like loads, but the compiler
+// places no wait for them: a reader first waits until at most N of the wave's
+// vector-memory operations are still in flight, where N counts the copies the
+// wave issued after the ones it needs.  Copies complete in issue order, so
+// every wait also covers the wave's own earlier loads.
+// ---------------------------------------------------------------------------
+template <class T>
+using lmem = __attribute__((address_space(3))) T;
+
+__device__ __forceinline__ void lds_dma16(gmem<const uint16_t> *src, char *dst) {
+    __builtin_amdgcn_global_load_lds((gmem<const void> *)src, (lmem<void> *)dst, 16, 0, 0);
+}
+
+// Wait until at most N vector-memory operations of this wave are in flight,
+// then meet the other waves of the block (no other counter is waited for).
+template <int N>
+__device__ __forceinline__ void vm_wait_barrier() {
+    asm volatile("s_waitcnt vmcnt(%0)\n\ts_barrier" ::"n"(N) : "memory");
+}
+
+__device__ __forceinline__ bf16x8 lds_bf16x8(const char *p) { return *(const lmem<bf16x8> *)p; }
+
+// Streaming BF16 passes: kStreamStages stages of one 32-wide K-step each, so
+// kStreamStages - 1 K-steps are in flight while one is multiplied.  A stage
+// holds 4 x 1 KB of the big operand per wave (its four 16-row or 16-column
+// panels) and four 1 KB slots of the small one, one copied by each wave.
+constexpr int kStreamStages = 4;
+constexpr int kStreamStage = 20 * 1024;
+constexpr int kStageOps = 5;   // copies one wave issues per stage
+
+// The r x r FP64 Gram Gd (row-major, stride r) into LDS as FP32, zero-padded
+// to RPAD x RPAD (stride RPAD), and gi[k] = 1/G_kk (0 when G_kk = 0 or
+// k >= r).  Every thread issues all of its loads before its first store, so
+// the block waits for one memory latency.
+template <int RPAD>
+__device__ __forceinline__ void load_gram_f32(const double *__restrict__ Gd, int r, float *Gs,
+                                              float *gi) {
+    constexpr int PER = (RPAD * RPAD + 255) / 256;
+    const auto G = to_global(Gd);
+    const int tid = threadIdx.x;
+    double v[PER];
+#pragma unroll
+    for (int i = 0; i < PER; ++i) {
+        const int e = tid + 256 * i, a = e / RPAD, b = e % RPAD;
+        v[i] = (e < RPAD * RPAD && a < r && b < r) ? G[a * r + b] : 0.0;
+    }
+    const double d = (tid < r) ? G[tid * r + tid] : 0.0;
+#pragma unroll
+    for (int i = 0; i < PER; ++i) {
+        const int e = tid + 256 * i;
+        if (e < RPAD * RPAD) Gs[e] = (float)v[i];
+    }
+    if (tid < RPAD) gi[tid] = d > 0.0 ? (float)(1.0 / d) : 0.0f;
+}
+
+// One factor row held by one lane (x, with arow the lane's row of the
+// product in LDS), updated against the RPAD x RPAD Gram G (row-major, zero-padded,
+// in LDS; every lane reads the same entry, a broadcast) and gi[k] = 1/G_kk
+// (0 when G_kk = 0 or k >= r).  FP32 arithmetic.
+// HALS (Alg. 3): for k = 1..r in order, x_k <- max(0, (a_k - sum_{l != k}
+// x_l G_lk) / G_kk) with the entries l < k already updated; G_kk = 0 keeps x_k.
+// MU (Alg. 2): x_k <- x_k a_k / (sum_l x_l G_lk) from the old x; a zero
+// denominator keeps x_k.
+// Dot products use four interleaved partial sums (entries l = 0, 1, 2, 3 mod
+// 4), added as (s0 + s1) + (s2 + s3).  The Gram row of step k is read only
+// once step k - 2 is done (ordered_after), so loads run two steps ahead
+// without all of them being hoisted into registers.
+template <int RPAD, int MODE>
+__device__ __forceinline__ void stream_row_update(float (&x)[RPAD], const float *arow,
+                                                  const float *G, const float *gi, int r) {
+    auto dot = [&](int k_row, auto skip_c, float dep) -> float {
+        constexpr int skip = decltype(skip_c)::value;
+        float s0 = 0.0f, s1 = 0.0f, s2 = 0.0f, s3 = 0.0f;
+        const float *g = G + ordered_after(k_row * RPAD, dep);
+        static_for<RPAD / 4>([&](auto lg_c) {
+            constexpr int l = 4 * decltype(lg_c)::value;
+            if (l < r) {
+                const v4f gv = *(const lmem<v4f> *)(g + l);
+                s0 = (l + 0 == skip) ? s0 : __builtin_fmaf(x[l + 0], gv[0], s0);
+                s1 = (l + 1 == skip) ? s1 : __builtin_fmaf(x[l + 1], gv[1], s1);
+                s2 = (l + 2 == skip) ? s2 : __builtin_fmaf(x[l + 2], gv[2], s2);
+                s3 = (l + 3 == skip) ? s3 : __builtin_fmaf(x[l + 3], gv[3], s3);
+            }
+        });
+        return (s0 + s1) + (s2 + s3);
+    };
+    if constexpr (MODE == MODE_HALS) {
+        static_for<RPAD>([&](auto k_c) {
+            constexpr int k = decltype(k_c)::value;
+            if (k < r) {
+                const float num = arow[k] - dot(k, k_c, x[k >= 2 ? k - 2 : 0]);
+                const float gk = gi[k];
+                if (gk > 0.0f) x[k] = fmaxf(num * gk, 0.0f);
+            }
+        });
+    } else {
+        float den[RPAD] = {};
+        static_for<RPAD>([&](auto k_c) {
+            constexpr int k = decltype(k_c)::value;
+            den[k] = k < r ? dot(k, std::integral_constant<int, -1>{}, den[k >= 2 ? k - 2 : 0])
+                           : 0.0f;
+        });
+#pragma unroll
+        for (int k = 0; k < RPAD; ++k)
+            if (k < r && den[k] > 0.0f) x[k] = x[k] * arow[k] / den[k];
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Streaming passes for large levels in BF16 mode (job.stream = 1).
+//
+// A-pass: a block of 4 waves owns 256 rows; each wave owns 64 rows (four
+// 16-row panels of the K-packed copy of M) over all of n, so every W operand
+// feeds four MFMAs and no partial tiles are combined.  M panels and W tiles
+// reach LDS by DMA, kStreamStages K-steps deep, one barrier per K-step.  The
+// wave's A rows then go to a wave-private LDS region (FP32, aliasing the
+// stages) and each lane updates one row: x = row `lane` of V, read and written
+// with one coalesced access per entry, the r x r arithmetic in FP32 against
+// the Gram in LDS.
+// ---------------------------------------------------------------------------
+template <int RT, int MODE>
+__device__ __forceinline__ void apass_stream_tile(const Job &J, int tile, double *smem) {
+    constexpr int RPAD = RT * 16, AS = RPAD + 1, NST = kStreamStages;
+    char *pipe = reinterpret_cast<char *>(smem);
+    float *Gs = reinterpret_cast<float *>(pipe + NST * kStreamStage);   // RPAD x RPAD
+    float *Gi = Gs + RPAD * RPAD;
+    const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+    const int li = lane & 15, lk = lane >> 4;
+    const int64_t m = J.m;
+    const int r = J.r;
+    const int64_t row0 = (int64_t)tile * 256 + wave * 64;
+    // npad is a multiple of 128, so ksteps >= 4 >= NST - 1; panels past m
+    // read the last panel (their rows are not written back)
+    const int ksteps = (int)(J.npad / 32);
+    const int64_t G = J.npad / 8;
+    const int64_t lastp = (m - 1) / 16;
+    gmem<const uint16_t> *Mp[4];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+        const int64_t pr = row0 / 16 + q;
+        Mp[q] = to_global(J.Mbp) + ((pr < lastp ? pr : lastp) * G * 16 + li) * 8 + lk * 128;
+    }
+    // wave w copies W tile w % RT into W slot w
+    gmem<const uint16_t> *Wr =
+        to_global(J.Wb) + (int64_t)(16 * (wave % RT) + li) * J.npad + 8 * lk;
+    auto issue = [&](int kk) {
+        char *st = pipe + (kk % NST) * kStreamStage;
+#pragma unroll
+        for (int q = 0; q < 4; ++q) lds_dma16(Mp[q] + (int64_t)kk * 512, st + (wave * 4 + q) * 1024);
+        lds_dma16(Wr + 32 * kk, st + 16384 + wave * 1024);
+    };
+    v4f acc[4][RT];
+#pragma unroll
+    for (int q = 0; q < 4; ++q)
+#pragma unroll
+        for (int t = 0; t < RT; ++t) acc[q][t] = v4f{0.0f, 0.0f, 0.0f, 0.0f};
+    auto mma = [&](int kk) {
+        const char *st = pipe + (kk % NST) * kStreamStage;
+        bf16x8 a[4], b[RT];
+#pragma unroll
+        for (int q = 0; q < 4; ++q) a[q] = lds_bf16x8(st + (wave * 4 + q) * 1024 + lane * 16);
+#pragma unroll
+        for (int t = 0; t < RT; ++t) b[t] = lds_bf16x8(st + 16384 + t * 1024 + lane * 16);
+#pragma unroll
+        for (int q = 0; q < 4; ++q)
+#pragma unroll
+            for (int t = 0; t < RT; ++t)
+                acc[q][t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[q], b[t], acc[q][t], 0, 0, 0);
+    };
+#pragma unroll
+    for (int kk = 0; kk < NST - 1; ++kk) issue(kk);
+    int kk = 0;
+    for (; kk < ksteps - (NST - 1); ++kk) {
+        vm_wait_barrier<kStageOps * (NST - 2)>();   // stage kk landed, stage kk - 1 read
+        issue(kk + NST - 1);
+        mma(kk);
+    }
+    static_for<NST - 1>([&](auto j_c) {             // drain: nothing left to issue
+        constexpr int j = decltype(j_c)::value;
+        vm_wait_barrier<kStageOps * (NST - 2 - j)>();
+        mma(kk + j);
+    });
+    __syncthreads();   // every wave done with the stages
+    load_gram_f32<RPAD>(J.Bd, r, Gs, Gi);
+    float *Aw = reinterpret_cast<float *>(pipe) + wave * 64 * AS;
+#pragma unroll
+    for (int q = 0; q < 4; ++q)
+#pragma unroll
+        for (int t = 0; t < RT; ++t)
+#pragma unroll
+            for (int v = 0; v < 4; ++v) Aw[(16 * q + 4 * lk + v) * AS + 16 * t + li] = acc[q][t][v];
+    __syncthreads();   // Gram and A rows in LDS
+
+    const int64_t row = row0 + lane;
+    const bool live = row < m;
+    const auto V = to_global(J.V);
+    float x[RPAD];
+#pragma unroll
+    for (int k = 0; k < RPAD; ++k) x[k] = (live && k < r) ? V[row + (int64_t)k * m] : 0.0f;
+    stream_row_update<RPAD, MODE>(x, Aw + lane * AS, Gs, Gi, r);
+    if (live) {
+        const auto Vb = to_global(J.Vb);
+#pragma unroll
+        for (int k = 0; k < RPAD; ++k) {
+            if (k < r) V[row + (int64_t)k * m] = x[k];
+            Vb[row + (int64_t)k * J.mpad] = bf16_rne(x[k]);
+        }
+    }
+}
+
+template <int RT, int MODE>
+__global__ __launch_bounds__(256) void k_apass_stream(const Job *__restrict__ jobs,
+                                                      const int2 *__restrict__ bmap) {
+    extern __shared__ double smem[];
+    const int2 jt = block_job(bmap);
+    const Job &J = jobs[jt.x];
+    if (jt.y >= J.nA || J.st->stop) return;
+    apass_stream_tile<RT, MODE>(J, jt.y, smem);
+}
+
+// C-pass: a block of 4 waves owns 256 columns of one row chunk; each wave owns
+// 64 columns (four 16-column panels of the column-panelled copy of M), so
+// every V operand feeds four MFMAs.  M panels and V tiles reach LDS by DMA as
+// in the A-pass.  The first column block of each chunk also forms the chunk's
+// partial D = V^T V from the same V operands (upper-triangle 16x16 tiles
+// spread over its waves).
+template <int RT>
+__device__ __forceinline__ void cpass_stream_tile(const Job &J, int tx, int ty, double *smem) {
+    constexpr int RPAD = RT * 16, NST = kStreamStages, DMAX = 3;
+    char *pipe = reinterpret_cast<char *>(smem);
+    const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+    const int lj = lane & 15, lg = lane >> 4;
+    const int64_t n = J.n, mp = J.mpad;
+    const int r = J.r;
+    const int64_t jb = (int64_t)tx * 256 + wave * 64;
+    // chunks and mpad are multiples of 128 rows: the chunk is a whole number
+    // of >= 4 K-steps and every copy is in bounds (rows past m are zero;
+    // panels past the last read the last one and are not stored)
+    const int64_t i_begin = (int64_t)ty * J.chunk;
+    const int64_t i_stop = (i_begin + J.chunk < mp) ? i_begin + J.chunk : mp;
+    const int ksteps = (int)((i_stop - i_begin) / 32);
+    const int64_t lastp = (n - 1) / 16;
+    gmem<const uint16_t> *Mb[4];
+#pragma unroll
+    for (int c = 0; c < 4; ++c) {
+        const int64_t pc = jb / 16 + c;
+        Mb[c] = to_global(J.Mbc) + (pc < lastp ? pc : lastp) * mp * 16 + i_begin * 16 + lane * 8;
+    }
+    // wave w copies V tile w % RT (rows 16t + lj of Vb) into V slot w
+    gmem<const uint16_t> *Vr =
+        to_global(J.Vb) + (int64_t)(16 * (wave % RT) + lj) * mp + i_begin + 8 * lg;
+    // D tiles (ta <= tb), numbered row by row: wave w takes numbers w + 4d
+    constexpr int NPAIR = RT * (RT + 1) / 2;
+    int dta[DMAX], dtb[DMAX];
+    bool dok[DMAX];
+#pragma unroll
+    for (int d = 0; d < DMAX; ++d) {
+        const int target = wave + 4 * d;
+        dok[d] = tx == 0 && target < NPAIR;
+        int fa = 0, fb = 0, idx = 0;
+#pragma unroll
+        for (int ta = 0; ta < RT; ++ta)
+#pragma unroll
+            for (int tb = ta; tb < RT; ++tb, ++idx)
+                if (idx == target) {
+                    fa = ta;
+                    fb = tb;
+                }
+        dta[d] = fa;
+        dtb[d] = fb;
+    }
+    auto issue = [&](int kk) {
+        char *st = pipe + (kk % NST) * kStreamStage;
+#pragma unroll
+        for (int c = 0; c < 4; ++c) lds_dma16(Mb[c] + (int64_t)kk * 512, st + (wave * 4 + c) * 1024);
+        lds_dma16(Vr + 32 * kk, st + 16384 + wave * 1024);
+    };
+    v4f acc[4][RT], dacc[DMAX];
+#pragma unroll
+    for (int c = 0; c < 4; ++c)
+#pragma unroll
+        for (int t = 0; t < RT; ++t) acc[c][t] = v4f{0.0f, 0.0f, 0.0f, 0.0f};
+#pragma unroll
+    for (int d = 0; d < DMAX; ++d) dacc[d] = v4f{0.0f, 0.0f, 0.0f, 0.0f};
+    auto mma = [&](int kk) {
+        const char *st = pipe + (kk % NST) * kStreamStage;
+        bf16x8 a[4], b[RT];
+#pragma unroll
+        for (int c = 0; c < 4; ++c) a[c] = lds_bf16x8(st + (wave * 4 + c) * 1024 + lane * 16);
+#pragma unroll
+        for (int t = 0; t < RT; ++t) b[t] = lds_bf16x8(st + 16384 + t * 1024 + lane * 16);
+#pragma unroll
+        for (int c = 0; c < 4; ++c)
+#pragma unroll
+            for (int t = 0; t < RT; ++t)
+                acc[c][t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[c], b[t], acc[c][t], 0, 0, 0);
+#pragma unroll
+        for (int d = 0; d < DMAX; ++d) {
+            if (dok[d]) {
+                const bf16x8 va = lds_bf16x8(st + 16384 + dta[d] * 1024 + lane * 16);
+                const bf16x8 vb = lds_bf16x8(st + 16384 + dtb[d] * 1024 + lane * 16);
+                dacc[d] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(va, vb, dacc[d], 0, 0, 0);
+            }
+        }
+    };
+#pragma unroll
+    for (int kk = 0; kk < NST - 1; ++kk) issue(kk);
+    int kk = 0;
+    for (; kk < ksteps - (NST - 1); ++kk) {
+        vm_wait_barrier<kStageOps * (NST - 2)>();   // stage kk landed, stage kk - 1 read
+        issue(kk + NST - 1);
+        mma(kk);
+    }
+    static_for<NST - 1>([&](auto j_c) {             // drain: nothing left to issue
+        constexpr int j = decltype(j_c)::value;
+        vm_wait_barrier<kStageOps * (NST - 2 - j)>();
+        mma(kk + j);
+    });
+    // acc[c][t][v] = C[k = 16t + lj][j = jb + 16c + 4lg + v]
+    const auto out = to_global(J.Cp) + (int64_t)ty * r * n;
+#pragma unroll
+    for (int t = 0; t < RT; ++t) {
+        const int k = 16 * t + lj;
+        if (k < r) {
+#pragma unroll
+            for (int c = 0; c < 4; ++c)
+#pragma unroll
+                for (int v = 0; v < 4; ++v) {
+                    const int64_t j = jb + 16 * c + 4 * lg + v;
+                    if (j < n) out[(int64_t)k * n + j] = (double)acc[c][t][v];
+                }
+        }
+    }
+    // dacc[d][v] = D[16 dta + 4lg + v][16 dtb + lj]
+    const auto dout = to_global(J.Dp) + (int64_t)ty * RPAD * RPAD;
+#pragma unroll
+    for (int d = 0; d < DMAX; ++d) {
+        if (dok[d]) {
+#pragma unroll
+            for (int v = 0; v < 4; ++v)
+                dout[(16 * dta[d] + 4 * lg + v) * RPAD + 16 * dtb[d] + lj] = (double)dacc[d][v];
+        }
+    }
+}
+
+template <int RT>
+__global__ __launch_bounds__(256) void k_cpass_stream(const Job *__restrict__ jobs,
+                                                      const int2 *__restrict__ bmap) {
+    const int2 jt = block_job(bmap);
+    const Job &J = jobs[jt.x];
+    int tx = jt.y % J.nCx, ty = jt.y / J.nCx;
+    if (!bmap) {   // single problem: the column blocks of a chunk run on one XCD
+        const int l = (int)(blockIdx.x >> 3);
+        ty = (int)(blockIdx.x & 7) + 8 * (l / J.nCx);
+        tx = l % J.nCx;
+    }
+    if (ty >= J.chunks || J.st->stop) return;
+    extern __shared__ double smem[];
+    cpass_stream_tile<RT>(J, tx, ty, smem);
+}
+
+// ---------------------------------------------------------------------------
+// Streaming passes for large levels in FP32 mode (job.stream = 1, prec = 0):
+// m >= kStreamMinRows, m and the column stride of M multiples of 4, M 16-byte
+// aligned.  FP32 products are MFMA-bound (v_mfma_f32_16x16x4f32), so the
+// design keeps the matrix cores busy and M in flight to feed them: batches of
+// 4 K-steps, double buffered in registers.
+//
+// A-pass: a wave owns 32 rows.  Lane (li, lk) loads rows row0 + 2li, 2li + 1
+// of column 4ks + lk (8 bytes) and feeds them to two MFMAs, so MFMA s maps its
+// row index li to row row0 + 2li + s; its accumulator v of lane (li', lk')
+// holds A[row0 + 8lk' + 2v + s][16t + li'].  Every 4 K-steps (16 products per
+// chain) the accumulators are added into FP64 sums.  Past n the W operand is
+// zero (the M column read is clamped), so no load is conditional.  The V
+// update (FP64, as in the regular kernels) takes the wave's rows 4 at a time
+// from a wave-private LDS slot, one s at a time.
+// ---------------------------------------------------------------------------
+template <int RT, int MODE>
+__device__ void apass_s32_tile(const Job &J, int tile, double *smem) {
+    constexpr int RPAD = RT * 16, GS = RPAD + 1, AS = RPAD + 1, RS = 2, SB = 4;
+    typedef float v2f __attribute__((ext_vector_type(2)));
+    double *Gs = smem;
+    double *Gi = Gs + RPAD * GS;
+    const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+    const int li = lane & 15, lk = lane >> 4;
+    const int64_t m = J.m, n = J.n, ldm = J.ldm;
+    const int r = J.r;
+    const int64_t row0 = (int64_t)tile * 128 + wave * 32;
+    const int64_t rl = row0 + 2 * li;
+    const auto Mw = to_global(J.M) + (rl < m ? rl : m - 2);
+    const auto Wt = to_global(J.Wt);
+    const int64_t nsteps = (n + 3) / 4;
+    const int64_t nb = (nsteps + SB - 1) / SB;            // batches (last one padded)
+    v4f acc[RS][RT];
+    double hs[RS][RT][4];
+#pragma unroll
+    for (int s2 = 0; s2 < RS; ++s2)
+#pragma unroll
+        for (int t = 0; t < RT; ++t) {
+            acc[s2][t] = v4f{0.0f, 0.0f, 0.0f, 0.0f};
+#pragma unroll
+            for (int v = 0; v < 4; ++v) hs[s2][t][v] = 0.0;
+        }
+    v2f a0[SB], a1[SB];
+    float b0[SB][RT], b1[SB][RT];
+    auto load = [&](int64_t bidx, v2f (&a)[SB], float (&b)[SB][RT]) {
+#pragma unroll
+        for (int u = 0; u < SB; ++u) {
+            const int64_t j = 4 * (bidx * SB + u) + lk;
+            const int64_t jc = j < n ? j : n - 1;
+            a[u] = *(gmem<const v2f> *)(Mw + jc * ldm);
+            float w[RT];
+            load_wt<RT>(Wt + jc * RPAD, li, w);
+#pragma unroll
+            for (int t = 0; t < RT; ++t) b[u][t] = j < n ? w[t] : 0.0f;
+        }
+    };
+    auto compute = [&](const v2f (&a)[SB], const float (&b)[SB][RT]) {
+#pragma unroll
+        for (int u = 0; u < SB; ++u) {
+#pragma unroll
+            for (int s2 = 0; s2 < RS; ++s2)
+#pragma unroll
+                for (int t = 0; t < RT; ++t)
+                    acc[s2][t] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[u][s2], b[u][t], acc[s2][t], 0, 0, 0);
+            if ((u & 3) == 3) {        // chains of 4 K-steps (16 products) into FP64
+#pragma unroll
+                for (int s2 = 0; s2 < RS; ++s2)
+#pragma unroll
+                    for (int t = 0; t < RT; ++t) {
+#pragma unroll
+                        for (int v = 0; v < 4; ++v) hs[s2][t][v] += (double)acc[s2][t][v];
+                        acc[s2][t] = v4f{0.0f, 0.0f, 0.0f, 0.0f};
+                    }
+            }
+        }
+    };
+    load(0, a0, b0);
+    if constexpr (MODE != MODE_STORE) load_gram<RPAD>(J.Bd, r, Gs, GS, Gi);
+    int64_t bi = 0;
+    for (; bi + 2 < nb; bi += 2) {
+        load(bi + 1, a1, b1);
+        compute(a0, b0);
+        load(bi + 2, a0, b0);
+        compute(a1, b1);
+    }
+    if (bi + 1 < nb) {
+        load(bi + 1, a1, b1);
+        compute(a0, b0);
+        compute(a1, b1);
+    } else {
+        compute(a0, b0);
+    }
+    double *Aw = Gi + RPAD + wave * 16 * AS;   // 16 rows of this wave (one s)
+    __syncthreads();                            // Gram in LDS
+    auto load_x = [&](int g, double (&x)[RT]) {   // g = 4 s + v: rows row0 + 8lk + 2v + s
+        const int64_t row = row0 + 8 * lk + 2 * (g & 3) + (g >> 2);
+#pragma unroll
+        for (int t = 0; t < RT; ++t) {
+            const int k = 16 * t + li;
+            x[t] = (row < m && k < r) ? (double)to_global(J.V)[row + (int64_t)k * m] : 0.0;
+        }
+    };
+    double xc[RT], xn[RT];
+    load_x(0, xc);
+    static_for<RS>([&](auto s_c) {
+        constexpr int s2 = decltype(s_c)::value;
+        __builtin_amdgcn_wave_barrier();
+#pragma unroll
+        for (int t = 0; t < RT; ++t)
+#pragma unroll
+            for (int v = 0; v < 4; ++v) Aw[(4 * lk + v) * AS + 16 * t + li] = hs[s2][t][v];
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+#pragma unroll 1
+        for (int v = 0; v < 4; ++v) {
+            const int g = 4 * s2 + v;
+            if (g + 1 < RS * 4) load_x(g + 1, xn);
+            double a[RT];
+#pragma unroll
+            for (int t = 0; t < RT; ++t) a[t] = Aw[(4 * lk + v) * AS + 16 * t + li];
+            const int64_t row = row0 + 8 * lk + 2 * v + s2;
+            if constexpr (MODE == MODE_STORE) {
+                if (row < m) {
+#pragma unroll
+                    for (int t = 0; t < RT; ++t) {
+                        const int k = 16 * t + li;
+                        if (k < r) to_global(J.A)[row + (int64_t)k * m] = (float)a[t];
+                    }
+                }
+            } else {
+                row_update<RT, MODE>(xc, Gs, GS, Gi, a, r, li);
+                if (row < m) {
+#pragma unroll
+                    for (int t = 0; t < RT; ++t) {
+                        const int k = 16 * t + li;
+                        if (k < r) to_global(J.V)[row + (int64_t)k * m] = (float)xc[t];
+                    }
+                }
+            }
+#pragma unroll
+            for (int t = 0; t < RT; ++t) xc[t] = xn[t];
+        }
+    });
+}
+
+template <int RT, int MODE>
+__global__ __launch_bounds__(256) void k_apass_s32(const Job *__restrict__ jobs,
+                                                   const int2 *__restrict__ bmap) {
+    extern __shared__ double smem[];
+    const int2 jt = block_job(bmap);
+    const Job &J = jobs[jt.x];
+    if (jt.y >= J.nA || J.st->stop) return;
+    apass_s32_tile<RT, MODE>(J, jt.y, smem);
+}
+
+// C-pass (FP32): a block of 4 waves owns 128 columns of one row chunk; a wave
+// owns 32 columns (two 16-column tiles).  Per 16-row step a lane loads 4
+// consecutive rows of M (per column tile) and of V (per rank tile) as float4
+// and feeds them to 4 MFMAs, whose K index lk maps to row i0 + 4lk + s.  Each
+// step's chains (16 products) are added into FP64 sums.  Rows past the chunk
+// read a clamped row with a zero V operand.  The first column block of each
+// chunk also forms the chunk's V^T V partial on the FP64 matrix cores.
+template <int RT>
+__device__ void cpass_s32_tile(const Job &J, int tx, int ty) {
+    constexpr int RPAD = RT * 16, RN = 2, SB = 2, DMAX = 3;
+    const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+    const int lj = lane & 15, lg = lane >> 4;
+    const int64_t m = J.m, n = J.n, ldm = J.ldm;
+    const int r = J.r;
+    const auto V = to_global(J.V);
+    const int64_t jb = (int64_t)tx * 128 + wave * 32;
+    const int64_t i_begin = (int64_t)ty * J.chunk;
+    const int64_t i_end = (i_begin + J.chunk < m) ? i_begin + J.chunk : m;
+    const int64_t nsteps = (i_end - i_begin + 15) / 16;
+    gmem<const float> *Mc[RN];
+#pragma unroll
+    for (int c = 0; c < RN; ++c) {
+        const int64_t j = jb + 16 * c + lj;
+        Mc[c] = to_global(J.M) + (j < n ? j : n - 1) * ldm;
+    }
+    int dta[DMAX], dtb[DMAX], nd = 0;
+    if (tx == 0) {
+        int idx = 0;
+        for (int ta = 0; ta < RT; ++ta)
+            for (int tb = ta; tb < RT; ++tb, ++idx)
+                if (idx % 4 == wave && nd < DMAX) {
+                    dta[nd] = ta;
+                    dtb[nd] = tb;
+                    ++nd;
+                }
+    }
+    v4f acc[RN][RT];
+    double hs[RN][RT][4];
+    v4d dacc[DMAX];
+#pragma unroll
+    for (int c = 0; c < RN; ++c)
+#pragma unroll
+        for (int t = 0; t < RT; ++t) {
+            acc[c][t] = v4f{0.0f, 0.0f, 0.0f, 0.0f};
+#pragma unroll
+            for (int v = 0; v < 4; ++v) hs[c][t][v] = 0.0;
+        }
+#pragma unroll
+    for (int d = 0; d < DMAX; ++d) dacc[d] = v4d{0.0, 0.0, 0.0, 0.0};
+    v4f ma0[SB][RN], vb0[SB][RT], ma1[SB][RN], vb1[SB][RT];
+    auto load = [&](int64_t st0, v4f (&a)[SB][RN], v4f (&b)[SB][RT]) {
+#pragma unroll
+        for (int u = 0; u < SB; ++u) {
+            const int64_t ib = i_begin + 16 * (st0 + u) + 4 * lg;   // rows ib .. ib+3
+            const bool ok = ib < i_end;                             // whole groups of 4 (m % 4 == 0)
+            const int64_t ic = ok ? ib : i_begin;
+#pragma unroll
+            for (int c = 0; c < RN; ++c) a[u][c] = *(gmem<const v4f> *)(Mc[c] + ic);
+#pragma unroll
+            for (int t = 0; t < RT; ++t) {
+                const int k = 16 * t + lj;
+                const v4f x = *(gmem<const v4f> *)(V + ic + (int64_t)(k < r ? k : 0) * m);
+                b[u][t] = (ok && k < r) ? x : v4f{0.0f, 0.0f, 0.0f, 0.0f};
+            }
+        }
+    };
+    auto compute = [&](const v4f (&a)[SB][RN], const v4f (&b)[SB][RT]) {
+#pragma unroll
+        for (int u = 0; u < SB; ++u) {
+#pragma unroll
+            for (int s = 0; s < 4; ++s)
+#pragma unroll
+                for (int c = 0; c < RN; ++c)
+#pragma unroll
+                    for (int t = 0; t < RT; ++t)
+                        acc[c][t] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[u][c][s], b[u][t][s], acc[c][t], 0, 0, 0);
+#pragma unroll
+            for (int c = 0; c < RN; ++c)
+#pragma unroll
+                for (int t = 0; t < RT; ++t) {
+#pragma unroll
+                    for (int v = 0; v < 4; ++v) hs[c][t][v] += (double)acc[c][t][v];
+                    acc[c][t] = v4f{0.0f, 0.0f, 0.0f, 0.0f};
+                }
+#pragma unroll
+            for (int d = 0; d < DMAX; ++d) {
+                if (d < nd) {
+#pragma unroll
+                    for (int s = 0; s < 4; ++s) {
+                        double va = 0.0, vb = 0.0;
+#pragma unroll
+                        for (int t = 0; t < RT; ++t) {
+                            if (t == dta[d]) va = (double)b[u][t][s];
+                            if (t == dtb[d]) vb = (double)b[u][t][s];
+                        }
+                        dacc[d] = __builtin_amdgcn_mfma_f64_16x16x4f64(va, vb, dacc[d], 0, 0, 0);
+                    }
+                }
+            }
+        }
+    };
+    const int64_t nb = (nsteps + SB - 1) / SB;
+    if (nb > 0) {
+        load(0, ma0, vb0);
+        int64_t bi = 0;
+        for (; bi + 2 < nb; bi += 2) {
+            load(SB * (bi + 1), ma1, vb1);
+            compute(ma0, vb0);
+            load(SB * (bi + 2), ma0, vb0);
+            compute(ma1, vb1);
+        }
+        if (bi + 1 < nb) {
+            load(SB * (bi + 1), ma1, vb1);
+            compute(ma0, vb0);
+            compute(ma1, vb1);
+        } else {
+            compute(ma0, vb0);
+        }
+    }
+    // hs[c][t][v] = C[k = 16t + lj][j = jb + 16c + 4lg + v]
+    const auto out = to_global(J.Cp) + (int64_t)ty * r * n;
+#pragma unroll
+    for (int t = 0; t < RT; ++t) {
+        const int k = 16 * t + lj;
+        if (k < r) {
+#pragma unroll
+            for (int c = 0; c < RN; ++c)
+#pragma unroll
+                for (int v = 0; v < 4; ++v) {
+                    const int64_t j = jb + 16 * c + 4 * lg + v;
+                    if (j < n) out[(int64_t)k * n + j] = hs[c][t][v];
+                }
+        }
+    }
+    // dacc[d][v] = D[16 dta + 4v + lg][16 dtb + lj]  (FP64 MFMA layout)
+    const auto dout = to_global(J.Dp) + (int64_t)ty * RPAD * RPAD;
+#pragma unroll
+    for (int d = 0; d < DMAX; ++d) {
+        if (d < nd) {
+#pragma unroll
+            for (int v = 0; v < 4; ++v)
+                dout[(16 * dta[d] + 4 * v + lg) * RPAD + 16 * dtb[d] + lj] = dacc[d][v];
+        }
+    }
+}
+
+template <int RT>
+__global__ __launch_bounds__(256) void k_cpass_s32(const Job *__restrict__ jobs,
+                                                   const int2 *__restrict__ bmap) {
+    const int2 jt = block_job(bmap);
+    const Job &J = jobs[jt.x];
+    int tx = jt.y % J.nCx, ty = jt.y / J.nCx;
+    if (!bmap) {   // single problem: the column blocks of a chunk run on one XCD
+        const int l = (int)(blockIdx.x >> 3);
+        ty = (int)(blockIdx.x & 7) + 8 * (l / J.nCx);
+        tx = l % J.nCx;
+    }
+    if (ty >= J.chunks || J.st->stop) return;
+    cpass_s32_tile<RT>(J, tx, ty);
+}
+
+}  // namespace
+
+// ---- host side -------------------------------------------------------------
+
+int cpass_stream_grid(int nCx, int chunks) { return 8 * nCx * ((chunks + 7) / 8); }
+
+// FP64 Gram and 1/G_kk, then 4 waves x 16 rows of A (FP64, stride rpad + 1).
+size_t apass_s32_lds_bytes(int rpad) {
+    return sizeof(double) * ((size_t)rpad * (rpad + 1) + rpad + 4 * 16 * (size_t)(rpad + 1));
+}
+
+hipError_t launch_apass_s32(int mode, int rpad, const Job *jobs, const int2 *bmap, int blocks,
+                            hipStream_t s) {
+    if (blocks <= 0) return hipSuccess;
+    if (mode != MODE_HALS && mode != MODE_MU) return hipErrorInvalidValue;
+    const size_t lds = apass_s32_lds_bytes(rpad);
+    const bool h = mode == MODE_HALS;
+    switch (rpad) {
+        case 16: h ? k_apass_s32<1, MODE_HALS><<<blocks, 256, lds, s>>>(jobs, bmap)
+                   : k_apass_s32<1, MODE_MU><<<blocks, 256, lds, s>>>(jobs, bmap); break;
+        case 32: h ? k_apass_s32<2, MODE_HALS><<<blocks, 256, lds, s>>>(jobs, bmap)
+                   : k_apass_s32<2, MODE_MU><<<blocks, 256, lds, s>>>(jobs, bmap); break;
+        case 48: h ? k_apass_s32<3, MODE_HALS><<<blocks, 256, lds, s>>>(jobs, bmap)
+                   : k_apass_s32<3, MODE_MU><<<blocks, 256, lds, s>>>(jobs, bmap); break;
+        case 64: h ? k_apass_s32<4, MODE_HALS><<<blocks, 256, lds, s>>>(jobs, bmap)
+                   : k_apass_s32<4, MODE_MU><<<blocks, 256, lds, s>>>(jobs, bmap); break;
+        default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_cpass_s32(int rpad, const Job *jobs, const int2 *bmap, int blocks,
+                            hipStream_t s) {
+    if (blocks <= 0) return hipSuccess;
+    switch (rpad) {
+        case 16: k_cpass_s32<1><<<blocks, 256, 0, s>>>(jobs, bmap); break;
+        case 32: k_cpass_s32<2><<<blocks, 256, 0, s>>>(jobs, bmap); break;
+        case 48: k_cpass_s32<3><<<blocks, 256, 0, s>>>(jobs, bmap); break;
+        case 64: k_cpass_s32<4><<<blocks, 256, 0, s>>>(jobs, bmap); break;
+        default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+// The DMA stages (later holding 4 waves x 64 rows of A, FP32, stride
+// rpad + 1), then the FP32 Gram and 1/G_kk.
+size_t apass_stream_lds_bytes(int rpad) {
+    static_assert(4 * 64 * 65 * sizeof(float) <= kStreamStages * kStreamStage,
+                  "A rows must fit in the stages");
+    return (size_t)kStreamStages * kStreamStage + sizeof(float) * ((size_t)rpad * rpad + rpad);
+}
+
+hipError_t launch_apass_stream(int mode, int rpad, const Job *jobs, const int2 *bmap, int blocks,
+                               hipStream_t s) {
+    if (blocks <= 0) return hipSuccess;
+    if (mode != MODE_HALS && mode != MODE_MU) return hipErrorInvalidValue;
+    const size_t lds = apass_stream_lds_bytes(rpad);
+    const bool h = mode == MODE_HALS;
+    switch (rpad) {
+        case 16: h ? k_apass_stream<1, MODE_HALS><<<blocks, 256, lds, s>>>(jobs, bmap)
+                   : k_apass_stream<1, MODE_MU><<<blocks, 256, lds, s>>>(jobs, bmap); break;
+        case 32: h ? k_apass_stream<2, MODE_HALS><<<blocks, 256, lds, s>>>(jobs, bmap)
+                   : k_apass_stream<2, MODE_MU><<<blocks, 256, lds, s>>>(jobs, bmap); break;
+        case 48: h ? k_apass_stream<3, MODE_HALS><<<blocks, 256, lds, s>>>(jobs, bmap)
+                   : k_apass_stream<3, MODE_MU><<<blocks, 256, lds, s>>>(jobs, bmap); break;
+        case 64: h ? k_apass_stream<4, MODE_HALS><<<blocks, 256, lds, s>>>(jobs, bmap)
+                   : k_apass_stream<4, MODE_MU><<<blocks, 256, lds, s>>>(jobs, bmap); break;
+        default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_cpass_stream(int rpad, const Job *jobs, const int2 *bmap, int blocks,
+                               hipStream_t s) {
+    if (blocks <= 0) return hipSuccess;
+    const size_t lds = (size_t)kStreamStages * kStreamStage;
+    switch (rpad) {
+        case 16: k_cpass_stream<1><<<blocks, 256, lds, s>>>(jobs, bmap); break;
+        case 32: k_cpass_stream<2><<<blocks, 256, lds, s>>>(jobs, bmap); break;
+        case 48: k_cpass_stream<3><<<blocks, 256, lds, s>>>(jobs, bmap); break;
+        case 64: k_cpass_stream<4><<<blocks, 256, lds, s>>>(jobs, bmap); break;
+        default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+// Allow the streaming passes the LDS their DMA stages, Gram and row staging
+// take (above the 64 KB default).
+template <int RT>
+static void stream_lds_attr(hipError_t &e) {
+    for (const void *f : {(const void *)k_apass_stream<RT, MODE_HALS>,
+                          (const void *)k_apass_stream<RT, MODE_MU>,
+                          (const void *)k_cpass_stream<RT>,
+                          (const void *)k_apass_s32<RT, MODE_HALS>,
+                          (const void *)k_apass_s32<RT, MODE_MU>}) {
+        const hipError_t x = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                                 160 * 1024);
+        if (x != hipSuccess && e == hipSuccess) e = x;
+    }
+}
+
+hipError_t enable_stream_lds() {
+    hipError_t e = hipSuccess;
+    stream_lds_attr<1>(e);
+    stream_lds_attr<2>(e);
+    stream_lds_attr<3>(e);
+    stream_lds_attr<4>(e);
+    return e;
+}
+
+}  // namespace nmf

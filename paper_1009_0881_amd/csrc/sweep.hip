@@ -35,186 +35,11 @@
 #include "job.h"
 #include "nmf_internal.h"
 
+#include "sweep_device.h"
+
 namespace nmf {
 
 namespace {
-
-typedef double v4d __attribute__((ext_vector_type(4)));
-typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
-
-// FP32 -> BF16 bits, round to nearest even (finite inputs).
-__device__ __forceinline__ uint16_t bf16_rne(float x) {
-    uint32_t u = __float_as_uint(x);
-    u += 0x7FFFu + ((u >> 16) & 1u);
-    return (uint16_t)(u >> 16);
-}
-
-constexpr int MODE_HALS = 0, MODE_MU = 1, MODE_STORE = 2, MODE_INIT = 3;
-
-template <int N, int I = 0, class F>
-__device__ __forceinline__ void static_for(F &&f) {
-    if constexpr (I < N) {
-        f(std::integral_constant<int, I>{});
-        static_for<N, I + 1>(f);
-    }
-}
-
-// (job, tile) of this block: entry blockIdx.x of the launch's block map, or
-// (0, blockIdx.x) for a launch over a single job (null map).
-__device__ __forceinline__ int2 block_job(const int2 *bmap) {
-    return bmap ? bmap[blockIdx.x] : make_int2(0, (int)blockIdx.x);
-}
-
-// Broadcast lane N of every row of 16 consecutive lanes to the whole row
-// (DPP row_newbcast).
-template <int N>
-__device__ __forceinline__ double row_bcast(double v) {
-    const int lo = __builtin_amdgcn_mov_dpp(__double2loint(v), 0x150 + N, 0xF, 0xF, false);
-    const int hi = __builtin_amdgcn_mov_dpp(__double2hiint(v), 0x150 + N, 0xF, 0xF, false);
-    return __hiloint2double(hi, lo);
-}
-
-template <int N>
-__device__ __forceinline__ float row_bcast(float v) {
-    return __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(v), 0x150 + N, 0xF, 0xF, false));
-}
-
-__device__ __forceinline__ double fma_t(double a, double b, double c) { return __builtin_fma(a, b, c); }
-__device__ __forceinline__ float fma_t(float a, float b, float c) { return __builtin_fmaf(a, b, c); }
-
-// Returns v unchanged, but only once dep has been computed: an empty asm that
-// takes dep as an input orders the instructions that use the result after
-// those that produce dep.  No instruction is emitted.
-template <class T>
-__device__ __forceinline__ int ordered_after(int v, T dep) {
-    asm("" : "+v"(v) : "v"(dep));
-    return v;
-}
-
-// HALS / MU update of one factor row held by a row of 16 lanes, lane p
-// holding entries k = 16t + p.  G is the r x r FP64 Gram of the other factor
-// in LDS (row stride gs, zero-padded to RPAD), gi[k] = 1/G_kk (0 when
-// G_kk = 0 or k >= r), a[t] entry 16t + p of the matching row of the product.  The
-// r x r-sized update arithmetic runs in T: FP64 in the FP32 mode (the
-// numerator a_k - sum_l x_l G_lk cancels as the iterate converges), FP32 in
-// the BF16 mode; the row is read from and written back to FP32 storage by the
-// caller.
-//
-// HALS (Alg. 3): x_k <- max(0, (a_k - sum_{l != k} x_l G_lk) / G_kk) for
-// k = 1..r in order, G_kk = 0 keeping x_k.  Computed in the equivalent
-// gradient form: g = a - G x once, then for each k the owner lane sets
-// x_k <- max(0, x_k + g_k / G_kk), broadcasts the change d to its row, and
-// every lane applies g_l -= d G_kl for its l > k.
-// MU (Alg. 2): x_k <- x_k a_k / (sum_l x_l G_lk); a zero denominator keeps x_k.
-template <int RT, int MODE, class T = double>
-__device__ __forceinline__ void row_update(T (&x)[RT], const T *G, int gs, const T *gi,
-                                           const T (&a)[RT], int r, int p) {
-    constexpr int RPAD = 16 * RT;
-    T acc[RT];
-#pragma unroll
-    for (int t = 0; t < RT; ++t) acc[t] = T(0);
-    // acc_k = sum_l x_l G_lk.  Padded entries (k >= r) have x_k = 0, zero Gram
-    // rows and 1/G_kk = 0: the mat-vec skips whole groups of 4 of them, the
-    // HALS loop runs over all RPAD entries with no runtime bound.
-    static_for<RPAD / 4>([&](auto lg_c) {
-        constexpr int lg = decltype(lg_c)::value;
-        if (4 * lg < r) {
-            static_for<4>([&](auto lq_c) {
-                constexpr int l = 4 * lg + decltype(lq_c)::value;
-                const T xl = row_bcast<l % 16>(x[l / 16]);
-                const T *gr = G + l * gs + p;
-#pragma unroll
-                for (int t = 0; t < RT; ++t) acc[t] = fma_t(xl, gr[16 * t], acc[t]);
-            });
-        }
-    });
-    if constexpr (MODE == MODE_HALS) {
-        T g[RT], ginv[RT], row0[RT], row1[RT];
-#pragma unroll
-        for (int t = 0; t < RT; ++t) {
-            const int k = 16 * t + p;
-            g[t] = k < r ? a[t] - acc[t] : T(0);
-            ginv[t] = gi[k];
-            row0[t] = G[k];                  // Gram row 0
-            row1[t] = G[gs + k];             // Gram row 1
-        }
-        // Each step loads the Gram row of step k+2 behind ordered_after() on
-        // the previous step's broadcast: loads run two steps ahead, hiding LDS
-        // latency, and the compiler cannot hoist all of them (and spill).
-        T dprev = acc[0];
-        static_for<RPAD>([&](auto k_c) {
-            constexpr int k = decltype(k_c)::value, kt = k / 16, pk = k % 16;
-            T row2[RT];
-            if constexpr (k + 2 < RPAD) {
-                const T *gr = G + ordered_after((k + 2) * gs + p, dprev);
-#pragma unroll
-                for (int t = (k + 2) / 16; t < RT; ++t) row2[t] = gr[16 * t];
-            }
-            const bool own = p == pk && ginv[kt] > T(0);
-            const T c0 = fma_t(g[kt], ginv[kt], x[kt]);
-            const T cand = c0 > T(0) ? c0 : T(0);
-            T d = own ? cand - x[kt] : T(0);
-            x[kt] = own ? cand : x[kt];
-            d = row_bcast<pk>(d);
-            dprev = d;
-            g[kt] = p > pk ? fma_t(-d, row0[kt], g[kt]) : g[kt];
-#pragma unroll
-            for (int t = kt + 1; t < RT; ++t) g[t] = fma_t(-d, row0[t], g[t]);
-#pragma unroll
-            for (int t = (k + 1) / 16; t < RT; ++t) {
-                row0[t] = row1[t];
-                if constexpr (k + 2 < RPAD) row1[t] = row2[t];
-            }
-        });
-    } else {
-#pragma unroll
-        for (int t = 0; t < RT; ++t) {
-            const int k = 16 * t + p;
-            if (k < r && acc[t] > T(0)) x[t] = x[t] * a[t] / acc[t];
-        }
-    }
-}
-
-// Load an r x r FP64 Gram (row-major, stride r) into LDS zero-padded to
-// RPAD x RPAD (stride gs), and its inverse diagonal.
-template <int RPAD, class T = double>
-__device__ __forceinline__ void load_gram(const double *__restrict__ Gd, int r, T *Gs, int gs,
-                                          T *gi) {
-    const auto G = to_global(Gd);
-    for (int e = threadIdx.x; e < RPAD * RPAD; e += blockDim.x) {
-        const int a = e / RPAD, b = e % RPAD;
-        Gs[a * gs + b] = (a < r && b < r) ? (T)G[a * r + b] : T(0);
-    }
-    for (int k = threadIdx.x; k < RPAD; k += blockDim.x) {
-        const double g = (k < r) ? G[k * r + k] : 0.0;
-        gi[k] = g > 0.0 ? (T)(1.0 / g) : T(0);
-    }
-}
-
-// Sum of `count` FP64 values p0[0], p0[stride], ... in index order, with up
-// to 16 loads in flight.
-__device__ __forceinline__ double sum_strided(const double *__restrict__ pg, int64_t stride,
-                                              int count) {
-    const auto p0 = to_global(pg);
-    double s = 0.0;
-    int p = 0;
-    for (; p + 16 <= count; p += 16) {
-        double t[16];
-#pragma unroll
-        for (int u = 0; u < 16; ++u) t[u] = p0[(p + u) * stride];
-#pragma unroll
-        for (int u = 0; u < 16; ++u) s += t[u];
-    }
-    for (; p + 4 <= count; p += 4) {
-        double t[4];
-#pragma unroll
-        for (int u = 0; u < 4; ++u) t[u] = p0[(p + u) * stride];
-#pragma unroll
-        for (int u = 0; u < 4; ++u) s += t[u];
-    }
-    for (; p < count; ++p) s += p0[p * stride];
-    return s;
-}
 
 // ---------------------------------------------------------------------------
 // A-pass tile.  Block = 4 waves; the waves form WR = 4/WN row groups of RW
@@ -468,53 +293,91 @@ __global__ __launch_bounds__(256) void k_apass(const Job *__restrict__ jobs,
 }
 
 // ---------------------------------------------------------------------------
-// C-pass tile: (x = 64-column tile of n, y = chunk of m rows).  Each wave owns
-// 16 columns; a lane loads 4 consecutive rows of M and of the r columns of V
-// (float4 each) and feeds them to 4 MFMAs, so the k-index of MFMA s maps to
-// row i0 + 4*(lane/16) + s.  Loads are double buffered two 16-row steps deep.
-// The same V registers feed the FP64 MFMAs of the chunk's partial V^T V: its
-// upper-triangle 16x16 tiles are spread over the waves of the chunk's tiles.
+// C-pass tile: (x = 64-column tile of n, y = chunk of m rows).  The 4 waves
+// form 4/WC column groups of WC 16-column tiles times WC row groups: each
+// wave covers its columns over 1/WC of the chunk's rows, so a wave's chain of
+// dependent loads is WC times shorter than one wave per column tile over the
+// whole chunk, and the WC row-group partials are added in LDS (fixed order).
+//
+// FP32 operands: a lane loads 4 consecutive rows of M and of the r columns of
+// V (float4 each) and feeds them to 4 MFMAs, so the k-index of MFMA s maps to
+// row i0 + 4*(lane/16) + s; loads are double buffered SB 16-row steps deep.
+// The same V registers feed the FP64 MFMAs of the chunk's partial V^T V.
+// BF16 operands (prec = 1): K-steps of 32 rows from the column-major BF16
+// copies; V^T V from the same BF16 V operands (products exact in FP32).
+// The upper-triangle 16x16 tiles of V^T V are numbered row by row and dealt
+// to the (block, column group) slots of the chunk, three per slot fused into
+// the main loop; a block whose slots own more (only when n is tiny) forms the
+// rest in extra passes over its rows.
 // ---------------------------------------------------------------------------
-template <int RT, int SB, bool BF>
-__device__ void cpass_tile(const Job &J, int tx, int ty, int ntx) {
-    constexpr int RPAD = RT * 16, DMAX = 3;
+template <int RT, int WC>
+constexpr size_t cpass_lds_doubles() {
+    // row-group partials of C (per wave: WC tiles x RT x 4 x 64 lanes) and of
+    // the fused V^T V tiles (3 x 4 x 64)
+    return (size_t)(WC - 1) * 4 * (RT * 4 * 64) + (size_t)(WC - 1) * (4 / WC) * 3 * 4 * 64;
+}
+
+template <int RT, int WC, int SB, bool BF>
+__device__ __forceinline__ void cpass_tile(const Job &J, int tx, int ty, int ntx, double *smem) {
+    constexpr int RPAD = RT * 16, DMAX = 3, NCG = 4 / WC, NPAIR = RT * (RT + 1) / 2;
     const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
     const int lj = lane & 15, lg = lane >> 4;
+    const int cg = wave % NCG, rg = wave / NCG;
     const int64_t m = J.m, n = J.n, ldm = J.ldm;
     const int r = J.r;
     const auto V = to_global(J.V);
-    const int64_t jb = (int64_t)tx * 64 + wave * 16;
+    const int64_t jb = (int64_t)tx * 64 + cg * 16 * WC;
     const int64_t i_begin = (int64_t)ty * J.chunk;
     const int64_t i_end = (i_begin + J.chunk < m) ? i_begin + J.chunk : m;
-    const int64_t j = jb + lj;
-    const bool jok = j < n;
-    const auto Mc = to_global(J.M) + (jok ? j : 0) * ldm;
+    // chunk is a multiple of 64 (FP32) or 128 (BF16): row groups start on
+    // 16-row (FP32) or 32-row (BF16) steps
+    const int64_t sub = J.chunk / WC;
+    const int64_t ra = i_begin + rg * sub;
+    const int64_t rb = (ra + sub < i_end) ? ra + sub : i_end;
+    const int slot0 = tx * NCG, nslots = ntx * NCG, slot = slot0 + cg;
+    auto tile_pair = [&](int idx, int &ta, int &tb) {
+        int fa = 0, fb = 0, q = 0;
+#pragma unroll
+        for (int a2 = 0; a2 < RT; ++a2)
+#pragma unroll
+            for (int b2 = a2; b2 < RT; ++b2, ++q)
+                if (q == idx) {
+                    fa = a2;
+                    fb = b2;
+                }
+        ta = fa;
+        tb = fb;
+    };
+    int dta[DMAX], dtb[DMAX];
+    bool dok[DMAX];
+#pragma unroll
+    for (int d = 0; d < DMAX; ++d) {
+        const int idx = slot + nslots * d;
+        dok[d] = idx < NPAIR;
+        tile_pair(idx, dta[d], dtb[d]);
+    }
+    gmem<const float> *Mc[WC];
+    bool jok[WC];
+#pragma unroll
+    for (int c = 0; c < WC; ++c) {
+        const int64_t j = jb + 16 * c + lj;
+        jok[c] = j < n;
+        Mc[c] = to_global(J.M) + (jok[c] ? j : 0) * ldm;
+    }
     const bool vec = ((ldm & 3) == 0) && ((m & 3) == 0) &&
                      (((uintptr_t)J.M & 15) == 0) && (((uintptr_t)V & 15) == 0);
-    const int slot = tx * 4 + wave, nslots = ntx * 4;
-    int dta[DMAX], dtb[DMAX];
-    int nd = 0;
-    {
-        int idx = 0;
-        for (int ta = 0; ta < RT; ++ta)
-            for (int tb = ta; tb < RT; ++tb, ++idx)
-                if (idx % nslots == slot && nd < DMAX) {
-                    dta[nd] = ta;
-                    dtb[nd] = tb;
-                    ++nd;
-                }
-    }
-    v4f hi[RT], lo[RT];
+    v4f hi[WC][RT], lo[WC][RT];
     v4d dacc[DMAX];
 #pragma unroll
-    for (int t = 0; t < RT; ++t) hi[t] = lo[t] = v4f{0.0f, 0.0f, 0.0f, 0.0f};
+    for (int c = 0; c < WC; ++c)
+#pragma unroll
+        for (int t = 0; t < RT; ++t) hi[c][t] = lo[c][t] = v4f{0.0f, 0.0f, 0.0f, 0.0f};
 #pragma unroll
     for (int d = 0; d < DMAX; ++d) dacc[d] = v4d{0.0, 0.0, 0.0, 0.0};
 
-    auto load1 = [&](int64_t i0, v4f &mv, v4f (&vv)[RT]) {
-        const int64_t ib = i0 + 4 * lg;
-        if (vec && ib + 3 < i_end) {
-            mv = jok ? *(gmem<const v4f> *)(Mc + ib) : v4f{0.0f, 0.0f, 0.0f, 0.0f};
+    // FP32: rows ib..ib+3 (ib = i0 + 4 lg) of the wave's M columns and of V
+    auto load_v = [&](int64_t ib, v4f (&vv)[RT]) {
+        if (vec && ib + 3 < rb) {
 #pragma unroll
             for (int t = 0; t < RT; ++t) {
                 const int k = 16 * t + lj;
@@ -523,159 +386,299 @@ __device__ void cpass_tile(const Job &J, int tx, int ty, int ntx) {
             }
         } else {
 #pragma unroll
-            for (int s = 0; s < 4; ++s) {
-                const int64_t i = ib + s;
-                const bool iok = i < i_end;
-                mv[s] = (jok && iok) ? Mc[i] : 0.0f;
+            for (int s2 = 0; s2 < 4; ++s2) {
+                const int64_t i = ib + s2;
 #pragma unroll
                 for (int t = 0; t < RT; ++t) {
                     const int k = 16 * t + lj;
-                    vv[t][s] = (k < r && iok) ? V[i + (int64_t)k * m] : 0.0f;
+                    vv[t][s2] = (k < r && i < rb) ? V[i + (int64_t)k * m] : 0.0f;
                 }
             }
         }
     };
-    auto load = [&](int64_t i0, v4f (&mv)[SB], v4f (&vv)[SB][RT]) {
+    auto load1 = [&](int64_t i0, v4f (&mv)[WC], v4f (&vv)[RT]) {
+        const int64_t ib = i0 + 4 * lg;
+        if (vec && ib + 3 < rb) {
 #pragma unroll
-        for (int u = 0; u < SB; ++u) load1(i0 + 16 * u, mv[u], vv[u]);
+            for (int c = 0; c < WC; ++c)
+                mv[c] = jok[c] ? *(gmem<const v4f> *)(Mc[c] + ib) : v4f{0.0f, 0.0f, 0.0f, 0.0f};
+        } else {
+#pragma unroll
+            for (int s2 = 0; s2 < 4; ++s2) {
+                const int64_t i = ib + s2;
+#pragma unroll
+                for (int c = 0; c < WC; ++c) mv[c][s2] = (jok[c] && i < rb) ? Mc[c][i] : 0.0f;
+            }
+        }
+        load_v(ib, vv);
     };
-    auto compute = [&](const v4f (&mvs)[SB], const v4f (&vvs)[SB][RT]) {
+    auto dtile_f64 = [&](const v4f (&vv)[RT], const int (&ta)[DMAX], const int (&tb)[DMAX],
+                         const bool (&ok)[DMAX]) {
 #pragma unroll
-        for (int u = 0; u < SB; ++u) {
-            v4f acc[RT];
+        for (int d = 0; d < DMAX; ++d) {
+            if (ok[d]) {
 #pragma unroll
-            for (int t = 0; t < RT; ++t) acc[t] = v4f{0.0f, 0.0f, 0.0f, 0.0f};
+                for (int s2 = 0; s2 < 4; ++s2) {
+                    double va = 0.0, vb = 0.0;
 #pragma unroll
-            for (int s = 0; s < 4; ++s)
-#pragma unroll
-                for (int t = 0; t < RT; ++t)
-                    acc[t] = __builtin_amdgcn_mfma_f32_16x16x4f32(mvs[u][s], vvs[u][t][s], acc[t], 0, 0, 0);
-#pragma unroll
-            for (int t = 0; t < RT; ++t) two_sum_acc(hi[t], lo[t], acc[t]);
-#pragma unroll
-            for (int d = 0; d < DMAX; ++d) {
-                if (d < nd) {
-#pragma unroll
-                    for (int s = 0; s < 4; ++s) {
-                        double va = 0.0, vb = 0.0;
-#pragma unroll
-                        for (int t = 0; t < RT; ++t) {
-                            if (t == dta[d]) va = (double)vvs[u][t][s];
-                            if (t == dtb[d]) vb = (double)vvs[u][t][s];
-                        }
-                        dacc[d] = __builtin_amdgcn_mfma_f64_16x16x4f64(va, vb, dacc[d], 0, 0, 0);
+                    for (int t = 0; t < RT; ++t) {
+                        if (t == ta[d]) va = (double)vv[t][s2];
+                        if (t == tb[d]) vb = (double)vv[t][s2];
                     }
+                    dacc[d] = __builtin_amdgcn_mfma_f64_16x16x4f64(va, vb, dacc[d], 0, 0, 0);
                 }
             }
         }
     };
+    const bf16x8 z8 = {};
+    const int64_t mp = J.mpad;
+    gmem<const uint16_t> *Vr[RT];
+#pragma unroll
+    for (int t = 0; t < RT; ++t)
+        Vr[t] = BF ? to_global(J.Vb) + (int64_t)(16 * t + lj) * mp + 8 * lg : nullptr;
+    v4f dacc32[DMAX];
+#pragma unroll
+    for (int d = 0; d < DMAX; ++d) dacc32[d] = v4f{0.0f, 0.0f, 0.0f, 0.0f};
+    auto dtile_bf16 = [&](const bf16x8 (&b)[RT], const int (&ta)[DMAX], const int (&tb)[DMAX],
+                          const bool (&ok)[DMAX]) {
+#pragma unroll
+        for (int d = 0; d < DMAX; ++d) {
+            if (ok[d]) {
+                bf16x8 va = z8, vb = z8;
+#pragma unroll
+                for (int t = 0; t < RT; ++t) {
+                    if (t == ta[d]) va = b[t];
+                    if (t == tb[d]) vb = b[t];
+                }
+                dacc32[d] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(va, vb, dacc32[d], 0, 0, 0);
+            }
+        }
+    };
+
     if constexpr (!BF) {
-        if (i_begin < i_end) {
-            v4f m0[SB], m1[SB], v0[SB][RT], v1[SB][RT];
-            load(i_begin, m0, v0);
-            for (int64_t i0 = i_begin; i0 < i_end; i0 += 32 * SB) {
-                const bool more = i0 + 16 * SB < i_end;
+        auto load = [&](int64_t i0, v4f (&mv)[SB][WC], v4f (&vv)[SB][RT]) {
+#pragma unroll
+            for (int u = 0; u < SB; ++u) load1(i0 + 16 * u, mv[u], vv[u]);
+        };
+        auto compute = [&](const v4f (&mvs)[SB][WC], const v4f (&vvs)[SB][RT]) {
+#pragma unroll
+            for (int u = 0; u < SB; ++u) {
+                v4f acc[WC][RT];
+#pragma unroll
+                for (int c = 0; c < WC; ++c)
+#pragma unroll
+                    for (int t = 0; t < RT; ++t) acc[c][t] = v4f{0.0f, 0.0f, 0.0f, 0.0f};
+#pragma unroll
+                for (int s2 = 0; s2 < 4; ++s2)
+#pragma unroll
+                    for (int c = 0; c < WC; ++c)
+#pragma unroll
+                        for (int t = 0; t < RT; ++t)
+                            acc[c][t] = __builtin_amdgcn_mfma_f32_16x16x4f32(mvs[u][c][s2], vvs[u][t][s2],
+                                                                             acc[c][t], 0, 0, 0);
+#pragma unroll
+                for (int c = 0; c < WC; ++c)
+#pragma unroll
+                    for (int t = 0; t < RT; ++t) two_sum_acc(hi[c][t], lo[c][t], acc[c][t]);
+                dtile_f64(vvs[u], dta, dtb, dok);
+            }
+        };
+        if (ra < rb) {
+            v4f m0[SB][WC], m1[SB][WC], v0[SB][RT], v1[SB][RT];
+            load(ra, m0, v0);
+            for (int64_t i0 = ra; i0 < rb; i0 += 32 * SB) {
+                const bool more = i0 + 16 * SB < rb;
                 if (more) load(i0 + 16 * SB, m1, v1);
                 compute(m0, v0);
                 if (!more) break;
-                if (i0 + 32 * SB < i_end) load(i0 + 32 * SB, m0, v0);
+                if (i0 + 32 * SB < rb) load(i0 + 32 * SB, m0, v0);
                 compute(m1, v1);
             }
         }
     } else {
-        // C on BF16 operands, K-steps of 32 rows (chunks are multiples of 32,
-        // the copies are zero past row m): lane (lj, lg) supplies rows
-        // i0 + 8*lg..+7 of column j from the column-major BF16 M, and of
-        // column 16t + lj from the BF16 V (16 bytes each).
+        // rows m..mpad of the copies are zero: K-steps may run past m
         constexpr int KB = 2;
-        const int64_t mp = J.mpad;
-        const auto Mb = to_global(J.Mbc) + (jok ? j : 0) * mp + 8 * lg;
-        gmem<const uint16_t> *Vr[RT];
+        gmem<const uint16_t> *Mb[WC];
 #pragma unroll
-        for (int t = 0; t < RT; ++t) Vr[t] = to_global(J.Vb) + (int64_t)(16 * t + lj) * mp + 8 * lg;
-        const bf16x8 z8 = {};
-        v4f acc[RT];
+        for (int c = 0; c < WC; ++c)
+            Mb[c] = to_global(J.Mbc) + (jok[c] ? jb + 16 * c + lj : 0) * mp + 8 * lg;
+        v4f acc[WC][RT];
 #pragma unroll
-        for (int t = 0; t < RT; ++t) acc[t] = v4f{0.0f, 0.0f, 0.0f, 0.0f};
-        bf16x8 ma0[KB], vb0[KB][RT], ma1[KB], vb1[KB][RT];
-        auto loadb = [&](int64_t i0, bf16x8 (&a)[KB], bf16x8 (&b)[KB][RT]) {
+        for (int c = 0; c < WC; ++c)
+#pragma unroll
+            for (int t = 0; t < RT; ++t) acc[c][t] = v4f{0.0f, 0.0f, 0.0f, 0.0f};
+        bf16x8 ma0[KB][WC], vb0[KB][RT], ma1[KB][WC], vb1[KB][RT];
+        auto loadb = [&](int64_t i0, bf16x8 (&a)[KB][WC], bf16x8 (&b)[KB][RT]) {
 #pragma unroll
             for (int u = 0; u < KB; ++u) {
                 const int64_t ik = i0 + 32 * u;
-                const bool ok = ik < i_end;
-                a[u] = (ok && jok) ? *(gmem<const bf16x8> *)(Mb + ik) : z8;
+                const bool ok = ik < rb;
+#pragma unroll
+                for (int c = 0; c < WC; ++c)
+                    a[u][c] = (ok && jok[c]) ? *(gmem<const bf16x8> *)(Mb[c] + ik) : z8;
 #pragma unroll
                 for (int t = 0; t < RT; ++t) b[u][t] = ok ? *(gmem<const bf16x8> *)(Vr[t] + ik) : z8;
             }
         };
-        auto computeb = [&](const bf16x8 (&a)[KB], const bf16x8 (&b)[KB][RT]) {
+        auto computeb = [&](const bf16x8 (&a)[KB][WC], const bf16x8 (&b)[KB][RT]) {
 #pragma unroll
-            for (int u = 0; u < KB; ++u)
+            for (int u = 0; u < KB; ++u) {
 #pragma unroll
-                for (int t = 0; t < RT; ++t)
-                    acc[t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[u], b[u][t], acc[t], 0, 0, 0);
+                for (int c = 0; c < WC; ++c)
+#pragma unroll
+                    for (int t = 0; t < RT; ++t)
+                        acc[c][t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[u][c], b[u][t], acc[c][t],
+                                                                            0, 0, 0);
+                dtile_bf16(b[u], dta, dtb, dok);
+            }
         };
-        if (i_begin < i_end) {
-            loadb(i_begin, ma0, vb0);
-            for (int64_t i0 = i_begin; i0 < i_end; i0 += 64 * KB) {
-                const bool more = i0 + 32 * KB < i_end;
+        if (ra < rb) {
+            loadb(ra, ma0, vb0);
+            for (int64_t i0 = ra; i0 < rb; i0 += 64 * KB) {
+                const bool more = i0 + 32 * KB < rb;
                 if (more) loadb(i0 + 32 * KB, ma1, vb1);
                 computeb(ma0, vb0);
                 if (!more) break;
-                if (i0 + 64 * KB < i_end) loadb(i0 + 64 * KB, ma0, vb0);
+                if (i0 + 64 * KB < rb) loadb(i0 + 64 * KB, ma0, vb0);
                 computeb(ma1, vb1);
             }
         }
 #pragma unroll
-        for (int t = 0; t < RT; ++t) hi[t] = acc[t];
-        // D = V^T V partial in FP64 from the FP32 V (waves that own D tiles)
-        if (nd > 0) {
-            for (int64_t i0 = i_begin; i0 < i_end; i0 += 16) {
+        for (int c = 0; c < WC; ++c)
 #pragma unroll
-                for (int d = 0; d < DMAX; ++d) {
-                    if (d < nd) {
-                        const int ka = 16 * dta[d] + lj, kb = 16 * dtb[d] + lj;
-#pragma unroll
-                        for (int s2 = 0; s2 < 4; ++s2) {
-                            const int64_t i = i0 + 4 * lg + s2;
-                            const bool iok = i < i_end;
-                            const double va = (iok && ka < r) ? (double)V[i + (int64_t)ka * m] : 0.0;
-                            const double vb = (iok && kb < r) ? (double)V[i + (int64_t)kb * m] : 0.0;
-                            dacc[d] = __builtin_amdgcn_mfma_f64_16x16x4f64(va, vb, dacc[d], 0, 0, 0);
-                        }
-                    }
-                }
-            }
-        }
+            for (int t = 0; t < RT; ++t) hi[c][t] = acc[c][t];
     }
-    // hi[t][v] + lo[t][v] = C[k = 16t + lj][j = jb + 4*lg + v]
-    const auto out = to_global(J.Cp) + (int64_t)ty * r * n;
+
+    // ---- row-group partials -> one sum per output, added in row-group order
+    double *redc = smem;                                          // [WC-1][4/WC][WC*RT*4][64]
+    double *redd = smem + (size_t)(WC - 1) * 4 * (RT * 4 * 64);   // [WC-1][4/WC][3*4][64]
+    const int cslot = (rg - 1) * NCG + cg;
+    if (WC > 1 && rg > 0) {
 #pragma unroll
-    for (int t = 0; t < RT; ++t) {
-        const int k = 16 * t + lj;
-        if (k < r) {
+        for (int c = 0; c < WC; ++c)
+#pragma unroll
+            for (int t = 0; t < RT; ++t)
+#pragma unroll
+                for (int v = 0; v < 4; ++v)
+                    redc[((size_t)cslot * WC * RT * 4 + (c * RT + t) * 4 + v) * 64 + lane] =
+                        (double)hi[c][t][v] + (double)lo[c][t][v];
+    }
+    // D partials in the FP64 MFMA layout: dacc[d][v] = D[16 dta + 4v + lg][16 dtb + lj]
+    auto d_value = [&](int d, int v) -> double {
+        if constexpr (BF) {
+            // FP32 MFMA layout D[16 dta + 4 lg + v][16 dtb + lj]: entry (4v + lg)
+            // sits in register lg of lane lj + 16 v
+            const float x = __shfl(dacc32[d][0], lj + 16 * v, 64);
+            const float y = __shfl(dacc32[d][1], lj + 16 * v, 64);
+            const float z = __shfl(dacc32[d][2], lj + 16 * v, 64);
+            const float w = __shfl(dacc32[d][3], lj + 16 * v, 64);
+            return (double)(lg == 0 ? x : lg == 1 ? y : lg == 2 ? z : w);
+        } else {
+            return dacc[d][v];
+        }
+    };
+    if (WC > 1 && rg > 0) {
+        const int dslot = (rg - 1) * NCG + cg;
+#pragma unroll
+        for (int d = 0; d < DMAX; ++d)
 #pragma unroll
             for (int v = 0; v < 4; ++v) {
-                const int64_t jj = jb + 4 * lg + v;
-                if (jj < n) out[(int64_t)k * n + jj] = (double)hi[t][v] + (double)lo[t][v];
+                const double x = d_value(d, v);
+                if (dok[d]) redd[((size_t)dslot * DMAX * 4 + d * 4 + v) * 64 + lane] = x;
+            }
+    }
+    if (WC > 1) __syncthreads();
+    if (rg == 0) {
+        // hi + lo (+ row groups 1..WC-1) = C[k = 16t + lj][j = jb + 16c + 4*lg + v]
+        const auto out = to_global(J.Cp) + (int64_t)ty * r * n;
+#pragma unroll
+        for (int c = 0; c < WC; ++c)
+#pragma unroll
+            for (int t = 0; t < RT; ++t) {
+                const int k = 16 * t + lj;
+#pragma unroll
+                for (int v = 0; v < 4; ++v) {
+                    double sum = (double)hi[c][t][v] + (double)lo[c][t][v];
+#pragma unroll
+                    for (int q = 1; q < WC; ++q)
+                        sum += redc[((size_t)((q - 1) * NCG + cg) * WC * RT * 4 + (c * RT + t) * 4 + v) * 64 +
+                                    lane];
+                    const int64_t jj = jb + 16 * c + 4 * lg + v;
+                    if (k < r && jj < n) out[(int64_t)k * n + jj] = sum;
+                }
+            }
+        const auto dout = to_global(J.Dp) + (int64_t)ty * RPAD * RPAD;
+#pragma unroll
+        for (int d = 0; d < DMAX; ++d)
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+                double sum = d_value(d, v);
+#pragma unroll
+                for (int q = 1; q < WC; ++q)
+                    sum += redd[((size_t)((q - 1) * NCG + cg) * DMAX * 4 + d * 4 + v) * 64 + lane];
+                if (dok[d]) dout[(16 * dta[d] + 4 * v + lg) * RPAD + 16 * dtb[d] + lj] = sum;
+            }
+    }
+
+    // ---- V^T V tiles beyond the three fused ones (tiny n only): block-uniform
+    // passes over the wave's rows, three tiles per slot each
+    for (int g = 1; slot0 + nslots * DMAX * g < NPAIR; ++g) {
+        int eta[DMAX], etb[DMAX];
+        bool eok[DMAX];
+#pragma unroll
+        for (int d = 0; d < DMAX; ++d) {
+            const int idx = slot + nslots * (DMAX * g + d);
+            eok[d] = idx < NPAIR;
+            tile_pair(idx, eta[d], etb[d]);
+            dacc[d] = v4d{0.0, 0.0, 0.0, 0.0};
+            dacc32[d] = v4f{0.0f, 0.0f, 0.0f, 0.0f};
+        }
+        if constexpr (!BF) {
+            for (int64_t i0 = ra; i0 < rb; i0 += 16) {
+                v4f vv[RT];
+                load_v(i0 + 4 * lg, vv);
+                dtile_f64(vv, eta, etb, eok);
+            }
+        } else {
+            for (int64_t ik = ra; ik < rb; ik += 32) {
+                bf16x8 b[RT];
+#pragma unroll
+                for (int t = 0; t < RT; ++t) b[t] = *(gmem<const bf16x8> *)(Vr[t] + ik);
+                dtile_bf16(b, eta, etb, eok);
             }
         }
-    }
-    // dacc[d][v] = D[16*dta + 4*v + lg][16*dtb + lj]
-    const auto dout = to_global(J.Dp) + (int64_t)ty * RPAD * RPAD;
+        if (WC > 1) __syncthreads();   // previous readers of redd are done
+        if (WC > 1 && rg > 0) {
+            const int dslot = (rg - 1) * NCG + cg;
 #pragma unroll
-    for (int d = 0; d < DMAX; ++d) {
-        if (d < nd) {
+            for (int d = 0; d < DMAX; ++d)
 #pragma unroll
-            for (int v = 0; v < 4; ++v)
-                dout[(16 * dta[d] + 4 * v + lg) * RPAD + 16 * dtb[d] + lj] = dacc[d][v];
+                for (int v = 0; v < 4; ++v) {
+                    const double x = d_value(d, v);
+                    if (eok[d]) redd[((size_t)dslot * DMAX * 4 + d * 4 + v) * 64 + lane] = x;
+                }
+        }
+        if (WC > 1) __syncthreads();
+        if (rg == 0) {
+            const auto dout = to_global(J.Dp) + (int64_t)ty * RPAD * RPAD;
+#pragma unroll
+            for (int d = 0; d < DMAX; ++d)
+#pragma unroll
+                for (int v = 0; v < 4; ++v) {
+                    double sum = d_value(d, v);
+#pragma unroll
+                    for (int q = 1; q < WC; ++q)
+                        sum += redd[((size_t)((q - 1) * NCG + cg) * DMAX * 4 + d * 4 + v) * 64 + lane];
+                    if (eok[d]) dout[(16 * eta[d] + 4 * v + lg) * RPAD + 16 * etb[d] + lj] = sum;
+                }
         }
     }
 }
 
-template <int RT, int SB, bool BF>
+template <int RT, int WC, int SB, bool BF>
 __global__ __launch_bounds__(256) void k_cpass(const Job *__restrict__ jobs,
                                                const int2 *__restrict__ bmap) {
+    extern __shared__ double smem[];
     const int2 jt = block_job(bmap);
     const Job &J = jobs[jt.x];
     int tx = jt.y % J.nCx, ty = jt.y / J.nCx;
@@ -688,7 +691,7 @@ __global__ __launch_bounds__(256) void k_cpass(const Job *__restrict__ jobs,
         if (ty >= J.chunks) return;
     }
     if (J.st->stop) return;
-    cpass_tile<RT, SB, BF>(J, tx, ty, J.nCx);
+    cpass_tile<RT, WC, SB, BF>(J, tx, ty, J.nCx, smem);
 }
 
 // ---------------------------------------------------------------------------
@@ -895,582 +898,8 @@ __global__ __launch_bounds__(256) void k_residual(const double *__restrict__ rpa
     }
 }
 
-// ---------------------------------------------------------------------------
-// Streaming passes for large levels in BF16 mode (job.stream = 1).
-//
-// A-pass: a block of 4 waves owns 256 rows; each wave owns 64 rows (four
-// 16-row panels) over all of n, so every W operand feeds four MFMAs and no
-// partial tiles are combined.  Operands are loaded two 32-column K-steps per
-// batch, double buffered.  The wave's A rows then go to a wave-private LDS
-// region (FP32) and are updated four at a time: row 16q + 4lk + v over the 16
-// lanes of lane group lk, entry 16t + li in lane li (the layout of
-// row_update).  The next row group's V entries are loaded while the current
-// one is updated.
-// ---------------------------------------------------------------------------
-template <int RT, int MODE>
-__device__ void apass_stream_tile(const Job &J, int tile, double *smem) {
-    constexpr int RPAD = RT * 16, GS = RPAD + 1, AS = RPAD + 1, RW = 4, SB = 2;
-    float *Gs = reinterpret_cast<float *>(smem);   // FP32 update arithmetic (BF16 mode)
-    float *Gi = Gs + RPAD * GS;
-    const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
-    const int li = lane & 15, lk = lane >> 4;
-    const int64_t m = J.m;
-    const int r = J.r;
-    const int64_t row0 = (int64_t)tile * 256 + wave * 64;
-    // npad is a multiple of 128: ksteps is a multiple of 2 * SB and every load
-    // of the loop below is in bounds (panels past m read the last panel; their
-    // rows are not written back)
-    const int64_t ksteps = J.npad / 32, G = J.npad / 8;
-    const int64_t lastp = (m - 1) / 16;
-    gmem<const uint16_t> *Mp[RW];
-#pragma unroll
-    for (int q = 0; q < RW; ++q) {
-        const int64_t pr = (row0 + 16 * q) / 16;
-        Mp[q] = to_global(J.Mbp) + ((pr < lastp ? pr : lastp) * G * 16 + li) * 8 + lk * 128;
-    }
-    gmem<const uint16_t> *Wr[RT];
-#pragma unroll
-    for (int t = 0; t < RT; ++t) Wr[t] = to_global(J.Wb) + (int64_t)(16 * t + li) * J.npad + 8 * lk;
-    v4f acc[RW][RT];
-#pragma unroll
-    for (int q = 0; q < RW; ++q)
-#pragma unroll
-        for (int t = 0; t < RT; ++t) acc[q][t] = v4f{0.0f, 0.0f, 0.0f, 0.0f};
-    bf16x8 a0[SB][RW], b0[SB][RT], a1[SB][RW], b1[SB][RT];
-    auto load = [&](int64_t k0, bf16x8 (&a)[SB][RW], bf16x8 (&b)[SB][RT]) {
-#pragma unroll
-        for (int u = 0; u < SB; ++u) {
-            const int64_t kk = k0 + u;
-#pragma unroll
-            for (int q = 0; q < RW; ++q) a[u][q] = *(gmem<const bf16x8> *)(Mp[q] + kk * 512);
-#pragma unroll
-            for (int t = 0; t < RT; ++t) b[u][t] = *(gmem<const bf16x8> *)(Wr[t] + 32 * kk);
-        }
-    };
-    auto compute = [&](const bf16x8 (&a)[SB][RW], const bf16x8 (&b)[SB][RT]) {
-#pragma unroll
-        for (int u = 0; u < SB; ++u)
-#pragma unroll
-            for (int q = 0; q < RW; ++q)
-#pragma unroll
-                for (int t = 0; t < RT; ++t)
-                    acc[q][t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[u][q], b[u][t], acc[q][t],
-                                                                        0, 0, 0);
-    };
-    load(0, a0, b0);
-    load_gram<RPAD, float>(J.Bd, r, Gs, GS, Gi);
-    int64_t k0 = 0;
-    for (; k0 + 2 * SB < ksteps; k0 += 2 * SB) {
-        load(k0 + SB, a1, b1);
-        compute(a0, b0);
-        load(k0 + 2 * SB, a0, b0);
-        compute(a1, b1);
-    }
-    load(k0 + SB, a1, b1);
-    compute(a0, b0);
-    compute(a1, b1);
-    float *Aw = Gi + RPAD + wave * 64 * AS;
-#pragma unroll
-    for (int q = 0; q < RW; ++q)
-#pragma unroll
-        for (int t = 0; t < RT; ++t)
-#pragma unroll
-            for (int v = 0; v < 4; ++v) Aw[(16 * q + 4 * lk + v) * AS + 16 * t + li] = acc[q][t][v];
-    __syncthreads();   // Gram and A rows in LDS
-    auto load_x = [&](int g, float (&x)[RT]) {
-        const int64_t row = row0 + 16 * (g >> 2) + 4 * lk + (g & 3);
-#pragma unroll
-        for (int t = 0; t < RT; ++t) {
-            const int k = 16 * t + li;
-            x[t] = (row < m && k < r) ? to_global(J.V)[row + (int64_t)k * m] : 0.0f;
-        }
-    };
-    float xc[RT], xn[RT];
-    load_x(0, xc);
-#pragma unroll 1
-    for (int g = 0; g < RW * 4; ++g) {
-        const int q = g >> 2, v = g & 3;
-        if (g + 1 < RW * 4) load_x(g + 1, xn);
-        float a[RT];
-#pragma unroll
-        for (int t = 0; t < RT; ++t) a[t] = Aw[(16 * q + 4 * lk + v) * AS + 16 * t + li];
-        row_update<RT, MODE, float>(xc, Gs, GS, Gi, a, r, li);
-        const int64_t row = row0 + 16 * q + 4 * lk + v;
-        if (row < m) {
-#pragma unroll
-            for (int t = 0; t < RT; ++t) {
-                const int k = 16 * t + li;
-                if (k < r) to_global(J.V)[row + (int64_t)k * m] = xc[t];
-                to_global(J.Vb)[row + (int64_t)k * J.mpad] = bf16_rne(xc[t]);
-            }
-        }
-#pragma unroll
-        for (int t = 0; t < RT; ++t) xc[t] = xn[t];
-    }
-}
-
-template <int RT, int MODE>
-__global__ __launch_bounds__(256) void k_apass_stream(const Job *__restrict__ jobs,
-                                                      const int2 *__restrict__ bmap) {
-    extern __shared__ double smem[];
-    const int2 jt = block_job(bmap);
-    const Job &J = jobs[jt.x];
-    if (jt.y >= J.nA || J.st->stop) return;
-    apass_stream_tile<RT, MODE>(J, jt.y, smem);
-}
-
-// C-pass: a block of 4 waves owns 256 columns of one row chunk; each wave owns
-// 64 columns (four 16-column tiles), so every V operand feeds four MFMAs.  The
-// first column block of each chunk also forms the chunk's partial D = V^T V
-// from the same V operands (upper-triangle 16x16 tiles spread over its waves).
-template <int RT>
-__device__ void cpass_stream_tile(const Job &J, int tx, int ty) {
-    constexpr int RPAD = RT * 16, RN = 4, SB = 2, DMAX = 3;
-    const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
-    const int lj = lane & 15, lg = lane >> 4;
-    const int64_t m = J.m, n = J.n, mp = J.mpad;
-    const int r = J.r;
-    const int64_t jb = (int64_t)tx * 256 + wave * 64;
-    // chunks and mpad are multiples of 128 rows: [i_begin, i_stop) is a whole
-    // number of double-buffered pairs of K-steps and every load is in bounds
-    // (rows past m are zero; columns past n read column n-1 and are not stored)
-    const int64_t i_begin = (int64_t)ty * J.chunk;
-    const int64_t i_stop = (i_begin + J.chunk < mp) ? i_begin + J.chunk : mp;
-    gmem<const uint16_t> *Mb[RN];
-#pragma unroll
-    for (int c = 0; c < RN; ++c) {
-        const int64_t j = jb + 16 * c + lj;
-        Mb[c] = to_global(J.Mbc) + (j < n ? j : n - 1) * mp + 8 * lg;
-    }
-    gmem<const uint16_t> *Vr[RT];
-#pragma unroll
-    for (int t = 0; t < RT; ++t) Vr[t] = to_global(J.Vb) + (int64_t)(16 * t + lj) * mp + 8 * lg;
-    int dta[DMAX], dtb[DMAX], nd = 0;
-    if (tx == 0) {
-        int idx = 0;
-        for (int ta = 0; ta < RT; ++ta)
-            for (int tb = ta; tb < RT; ++tb, ++idx)
-                if (idx % 4 == wave && nd < DMAX) {
-                    dta[nd] = ta;
-                    dtb[nd] = tb;
-                    ++nd;
-                }
-    }
-    v4f acc[RN][RT], dacc[DMAX];
-#pragma unroll
-    for (int c = 0; c < RN; ++c)
-#pragma unroll
-        for (int t = 0; t < RT; ++t) acc[c][t] = v4f{0.0f, 0.0f, 0.0f, 0.0f};
-#pragma unroll
-    for (int d = 0; d < DMAX; ++d) dacc[d] = v4f{0.0f, 0.0f, 0.0f, 0.0f};
-    const bf16x8 z8 = {};
-    bf16x8 a0[SB][RN], b0[SB][RT], a1[SB][RN], b1[SB][RT];
-    auto load = [&](int64_t i0, bf16x8 (&a)[SB][RN], bf16x8 (&b)[SB][RT]) {
-#pragma unroll
-        for (int u = 0; u < SB; ++u) {
-            const int64_t ik = i0 + 32 * u;
-#pragma unroll
-            for (int c = 0; c < RN; ++c) a[u][c] = *(gmem<const bf16x8> *)(Mb[c] + ik);
-#pragma unroll
-            for (int t = 0; t < RT; ++t) b[u][t] = *(gmem<const bf16x8> *)(Vr[t] + ik);
-        }
-    };
-    auto compute = [&](const bf16x8 (&a)[SB][RN], const bf16x8 (&b)[SB][RT]) {
-#pragma unroll
-        for (int u = 0; u < SB; ++u) {
-#pragma unroll
-            for (int c = 0; c < RN; ++c)
-#pragma unroll
-                for (int t = 0; t < RT; ++t)
-                    acc[c][t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[u][c], b[u][t], acc[c][t],
-                                                                        0, 0, 0);
-#pragma unroll
-            for (int d = 0; d < DMAX; ++d) {
-                if (d < nd) {
-                    bf16x8 va = z8, vb = z8;
-#pragma unroll
-                    for (int t = 0; t < RT; ++t) {
-                        if (t == dta[d]) va = b[u][t];
-                        if (t == dtb[d]) vb = b[u][t];
-                    }
-                    dacc[d] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(va, vb, dacc[d], 0, 0, 0);
-                }
-            }
-        }
-    };
-    if (i_begin < i_stop) {
-        load(i_begin, a0, b0);
-        int64_t i0 = i_begin;
-        for (; i0 + 64 * SB < i_stop; i0 += 64 * SB) {
-            load(i0 + 32 * SB, a1, b1);
-            compute(a0, b0);
-            load(i0 + 64 * SB, a0, b0);
-            compute(a1, b1);
-        }
-        load(i0 + 32 * SB, a1, b1);
-        compute(a0, b0);
-        compute(a1, b1);
-    }
-    // acc[c][t][v] = C[k = 16t + lj][j = jb + 16c + 4lg + v]
-    const auto out = to_global(J.Cp) + (int64_t)ty * r * n;
-#pragma unroll
-    for (int t = 0; t < RT; ++t) {
-        const int k = 16 * t + lj;
-        if (k < r) {
-#pragma unroll
-            for (int c = 0; c < RN; ++c)
-#pragma unroll
-                for (int v = 0; v < 4; ++v) {
-                    const int64_t j = jb + 16 * c + 4 * lg + v;
-                    if (j < n) out[(int64_t)k * n + j] = (double)acc[c][t][v];
-                }
-        }
-    }
-    // dacc[d][v] = D[16 dta + 4lg + v][16 dtb + lj]
-    const auto dout = to_global(J.Dp) + (int64_t)ty * RPAD * RPAD;
-#pragma unroll
-    for (int d = 0; d < DMAX; ++d) {
-        if (d < nd) {
-#pragma unroll
-            for (int v = 0; v < 4; ++v)
-                dout[(16 * dta[d] + 4 * lg + v) * RPAD + 16 * dtb[d] + lj] = (double)dacc[d][v];
-        }
-    }
-}
-
-template <int RT>
-__global__ __launch_bounds__(256) void k_cpass_stream(const Job *__restrict__ jobs,
-                                                      const int2 *__restrict__ bmap) {
-    const int2 jt = block_job(bmap);
-    const Job &J = jobs[jt.x];
-    int tx = jt.y % J.nCx, ty = jt.y / J.nCx;
-    if (!bmap) {   // single problem: the column blocks of a chunk run on one XCD
-        const int l = (int)(blockIdx.x >> 3);
-        ty = (int)(blockIdx.x & 7) + 8 * (l / J.nCx);
-        tx = l % J.nCx;
-    }
-    if (ty >= J.chunks || J.st->stop) return;
-    cpass_stream_tile<RT>(J, tx, ty);
-}
-
-// ---------------------------------------------------------------------------
-// Streaming passes for large levels in FP32 mode (job.stream = 1, prec = 0):
-// m >= kStreamMinRows, m and the column stride of M multiples of 4, M 16-byte
-// aligned.  FP32 products are MFMA-bound (v_mfma_f32_16x16x4f32), so the
-// design keeps the matrix cores busy and M in flight to feed them: batches of
-// 4 K-steps, double buffered in registers.
-//
-// A-pass: a wave owns 32 rows.  Lane (li, lk) loads rows row0 + 2li, 2li + 1
-// of column 4ks + lk (8 bytes) and feeds them to two MFMAs, so MFMA s maps its
-// row index li to row row0 + 2li + s; its accumulator v of lane (li', lk')
-// holds A[row0 + 8lk' + 2v + s][16t + li'].  Every 4 K-steps (16 products per
-// chain) the accumulators are added into FP64 sums.  Past n the W operand is
-// zero (the M column read is clamped), so no load is conditional.  The V
-// update (FP64, as in the regular kernels) takes the wave's rows 4 at a time
-// from a wave-private LDS slot, one s at a time.
-// ---------------------------------------------------------------------------
-template <int RT, int MODE>
-__device__ void apass_s32_tile(const Job &J, int tile, double *smem) {
-    constexpr int RPAD = RT * 16, GS = RPAD + 1, AS = RPAD + 1, RS = 2, SB = 4;
-    typedef float v2f __attribute__((ext_vector_type(2)));
-    double *Gs = smem;
-    double *Gi = Gs + RPAD * GS;
-    const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
-    const int li = lane & 15, lk = lane >> 4;
-    const int64_t m = J.m, n = J.n, ldm = J.ldm;
-    const int r = J.r;
-    const int64_t row0 = (int64_t)tile * 128 + wave * 32;
-    const int64_t rl = row0 + 2 * li;
-    const auto Mw = to_global(J.M) + (rl < m ? rl : m - 2);
-    const auto Wt = to_global(J.Wt);
-    const int64_t nsteps = (n + 3) / 4;
-    const int64_t nb = (nsteps + SB - 1) / SB;            // batches (last one padded)
-    v4f acc[RS][RT];
-    double hs[RS][RT][4];
-#pragma unroll
-    for (int s2 = 0; s2 < RS; ++s2)
-#pragma unroll
-        for (int t = 0; t < RT; ++t) {
-            acc[s2][t] = v4f{0.0f, 0.0f, 0.0f, 0.0f};
-#pragma unroll
-            for (int v = 0; v < 4; ++v) hs[s2][t][v] = 0.0;
-        }
-    v2f a0[SB], a1[SB];
-    float b0[SB][RT], b1[SB][RT];
-    auto load = [&](int64_t bidx, v2f (&a)[SB], float (&b)[SB][RT]) {
-#pragma unroll
-        for (int u = 0; u < SB; ++u) {
-            const int64_t j = 4 * (bidx * SB + u) + lk;
-            const int64_t jc = j < n ? j : n - 1;
-            a[u] = *(gmem<const v2f> *)(Mw + jc * ldm);
-            float w[RT];
-            load_wt<RT>(Wt + jc * RPAD, li, w);
-#pragma unroll
-            for (int t = 0; t < RT; ++t) b[u][t] = j < n ? w[t] : 0.0f;
-        }
-    };
-    auto compute = [&](const v2f (&a)[SB], const float (&b)[SB][RT]) {
-#pragma unroll
-        for (int u = 0; u < SB; ++u) {
-#pragma unroll
-            for (int s2 = 0; s2 < RS; ++s2)
-#pragma unroll
-                for (int t = 0; t < RT; ++t)
-                    acc[s2][t] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[u][s2], b[u][t], acc[s2][t], 0, 0, 0);
-            if ((u & 3) == 3) {        // chains of 4 K-steps (16 products) into FP64
-#pragma unroll
-                for (int s2 = 0; s2 < RS; ++s2)
-#pragma unroll
-                    for (int t = 0; t < RT; ++t) {
-#pragma unroll
-                        for (int v = 0; v < 4; ++v) hs[s2][t][v] += (double)acc[s2][t][v];
-                        acc[s2][t] = v4f{0.0f, 0.0f, 0.0f, 0.0f};
-                    }
-            }
-        }
-    };
-    load(0, a0, b0);
-    if constexpr (MODE != MODE_STORE) load_gram<RPAD>(J.Bd, r, Gs, GS, Gi);
-    int64_t bi = 0;
-    for (; bi + 2 < nb; bi += 2) {
-        load(bi + 1, a1, b1);
-        compute(a0, b0);
-        load(bi + 2, a0, b0);
-        compute(a1, b1);
-    }
-    if (bi + 1 < nb) {
-        load(bi + 1, a1, b1);
-        compute(a0, b0);
-        compute(a1, b1);
-    } else {
-        compute(a0, b0);
-    }
-    double *Aw = Gi + RPAD + wave * 16 * AS;   // 16 rows of this wave (one s)
-    __syncthreads();                            // Gram in LDS
-    auto load_x = [&](int g, double (&x)[RT]) {   // g = 4 s + v: rows row0 + 8lk + 2v + s
-        const int64_t row = row0 + 8 * lk + 2 * (g & 3) + (g >> 2);
-#pragma unroll
-        for (int t = 0; t < RT; ++t) {
-            const int k = 16 * t + li;
-            x[t] = (row < m && k < r) ? (double)to_global(J.V)[row + (int64_t)k * m] : 0.0;
-        }
-    };
-    double xc[RT], xn[RT];
-    load_x(0, xc);
-    static_for<RS>([&](auto s_c) {
-        constexpr int s2 = decltype(s_c)::value;
-        __builtin_amdgcn_wave_barrier();
-#pragma unroll
-        for (int t = 0; t < RT; ++t)
-#pragma unroll
-            for (int v = 0; v < 4; ++v) Aw[(4 * lk + v) * AS + 16 * t + li] = hs[s2][t][v];
-        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-        __builtin_amdgcn_wave_barrier();
-        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-#pragma unroll 1
-        for (int v = 0; v < 4; ++v) {
-            const int g = 4 * s2 + v;
-            if (g + 1 < RS * 4) load_x(g + 1, xn);
-            double a[RT];
-#pragma unroll
-            for (int t = 0; t < RT; ++t) a[t] = Aw[(4 * lk + v) * AS + 16 * t + li];
-            const int64_t row = row0 + 8 * lk + 2 * v + s2;
-            if constexpr (MODE == MODE_STORE) {
-                if (row < m) {
-#pragma unroll
-                    for (int t = 0; t < RT; ++t) {
-                        const int k = 16 * t + li;
-                        if (k < r) to_global(J.A)[row + (int64_t)k * m] = (float)a[t];
-                    }
-                }
-            } else {
-                row_update<RT, MODE>(xc, Gs, GS, Gi, a, r, li);
-                if (row < m) {
-#pragma unroll
-                    for (int t = 0; t < RT; ++t) {
-                        const int k = 16 * t + li;
-                        if (k < r) to_global(J.V)[row + (int64_t)k * m] = (float)xc[t];
-                    }
-                }
-            }
-#pragma unroll
-            for (int t = 0; t < RT; ++t) xc[t] = xn[t];
-        }
-    });
-}
-
-template <int RT, int MODE>
-__global__ __launch_bounds__(256) void k_apass_s32(const Job *__restrict__ jobs,
-                                                   const int2 *__restrict__ bmap) {
-    extern __shared__ double smem[];
-    const int2 jt = block_job(bmap);
-    const Job &J = jobs[jt.x];
-    if (jt.y >= J.nA || J.st->stop) return;
-    apass_s32_tile<RT, MODE>(J, jt.y, smem);
-}
-
-// C-pass (FP32): a block of 4 waves owns 128 columns of one row chunk; a wave
-// owns 32 columns (two 16-column tiles).  Per 16-row step a lane loads 4
-// consecutive rows of M (per column tile) and of V (per rank tile) as float4
-// and feeds them to 4 MFMAs, whose K index lk maps to row i0 + 4lk + s.  Each
-// step's chains (16 products) are added into FP64 sums.  Rows past the chunk
-// read a clamped row with a zero V operand.  The first column block of each
-// chunk also forms the chunk's V^T V partial on the FP64 matrix cores.
-template <int RT>
-__device__ void cpass_s32_tile(const Job &J, int tx, int ty) {
-    constexpr int RPAD = RT * 16, RN = 2, SB = 2, DMAX = 3;
-    const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
-    const int lj = lane & 15, lg = lane >> 4;
-    const int64_t m = J.m, n = J.n, ldm = J.ldm;
-    const int r = J.r;
-    const auto V = to_global(J.V);
-    const int64_t jb = (int64_t)tx * 128 + wave * 32;
-    const int64_t i_begin = (int64_t)ty * J.chunk;
-    const int64_t i_end = (i_begin + J.chunk < m) ? i_begin + J.chunk : m;
-    const int64_t nsteps = (i_end - i_begin + 15) / 16;
-    gmem<const float> *Mc[RN];
-#pragma unroll
-    for (int c = 0; c < RN; ++c) {
-        const int64_t j = jb + 16 * c + lj;
-        Mc[c] = to_global(J.M) + (j < n ? j : n - 1) * ldm;
-    }
-    int dta[DMAX], dtb[DMAX], nd = 0;
-    if (tx == 0) {
-        int idx = 0;
-        for (int ta = 0; ta < RT; ++ta)
-            for (int tb = ta; tb < RT; ++tb, ++idx)
-                if (idx % 4 == wave && nd < DMAX) {
-                    dta[nd] = ta;
-                    dtb[nd] = tb;
-                    ++nd;
-                }
-    }
-    v4f acc[RN][RT];
-    double hs[RN][RT][4];
-    v4d dacc[DMAX];
-#pragma unroll
-    for (int c = 0; c < RN; ++c)
-#pragma unroll
-        for (int t = 0; t < RT; ++t) {
-            acc[c][t] = v4f{0.0f, 0.0f, 0.0f, 0.0f};
-#pragma unroll
-            for (int v = 0; v < 4; ++v) hs[c][t][v] = 0.0;
-        }
-#pragma unroll
-    for (int d = 0; d < DMAX; ++d) dacc[d] = v4d{0.0, 0.0, 0.0, 0.0};
-    v4f ma0[SB][RN], vb0[SB][RT], ma1[SB][RN], vb1[SB][RT];
-    auto load = [&](int64_t st0, v4f (&a)[SB][RN], v4f (&b)[SB][RT]) {
-#pragma unroll
-        for (int u = 0; u < SB; ++u) {
-            const int64_t ib = i_begin + 16 * (st0 + u) + 4 * lg;   // rows ib .. ib+3
-            const bool ok = ib < i_end;                             // whole groups of 4 (m % 4 == 0)
-            const int64_t ic = ok ? ib : i_begin;
-#pragma unroll
-            for (int c = 0; c < RN; ++c) a[u][c] = *(gmem<const v4f> *)(Mc[c] + ic);
-#pragma unroll
-            for (int t = 0; t < RT; ++t) {
-                const int k = 16 * t + lj;
-                const v4f x = *(gmem<const v4f> *)(V + ic + (int64_t)(k < r ? k : 0) * m);
-                b[u][t] = (ok && k < r) ? x : v4f{0.0f, 0.0f, 0.0f, 0.0f};
-            }
-        }
-    };
-    auto compute = [&](const v4f (&a)[SB][RN], const v4f (&b)[SB][RT]) {
-#pragma unroll
-        for (int u = 0; u < SB; ++u) {
-#pragma unroll
-            for (int s = 0; s < 4; ++s)
-#pragma unroll
-                for (int c = 0; c < RN; ++c)
-#pragma unroll
-                    for (int t = 0; t < RT; ++t)
-                        acc[c][t] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[u][c][s], b[u][t][s], acc[c][t], 0, 0, 0);
-#pragma unroll
-            for (int c = 0; c < RN; ++c)
-#pragma unroll
-                for (int t = 0; t < RT; ++t) {
-#pragma unroll
-                    for (int v = 0; v < 4; ++v) hs[c][t][v] += (double)acc[c][t][v];
-                    acc[c][t] = v4f{0.0f, 0.0f, 0.0f, 0.0f};
-                }
-#pragma unroll
-            for (int d = 0; d < DMAX; ++d) {
-                if (d < nd) {
-#pragma unroll
-                    for (int s = 0; s < 4; ++s) {
-                        double va = 0.0, vb = 0.0;
-#pragma unroll
-                        for (int t = 0; t < RT; ++t) {
-                            if (t == dta[d]) va = (double)b[u][t][s];
-                            if (t == dtb[d]) vb = (double)b[u][t][s];
-                        }
-                        dacc[d] = __builtin_amdgcn_mfma_f64_16x16x4f64(va, vb, dacc[d], 0, 0, 0);
-                    }
-                }
-            }
-        }
-    };
-    const int64_t nb = (nsteps + SB - 1) / SB;
-    if (nb > 0) {
-        load(0, ma0, vb0);
-        int64_t bi = 0;
-        for (; bi + 2 < nb; bi += 2) {
-            load(SB * (bi + 1), ma1, vb1);
-            compute(ma0, vb0);
-            load(SB * (bi + 2), ma0, vb0);
-            compute(ma1, vb1);
-        }
-        if (bi + 1 < nb) {
-            load(SB * (bi + 1), ma1, vb1);
-            compute(ma0, vb0);
-            compute(ma1, vb1);
-        } else {
-            compute(ma0, vb0);
-        }
-    }
-    // hs[c][t][v] = C[k = 16t + lj][j = jb + 16c + 4lg + v]
-    const auto out = to_global(J.Cp) + (int64_t)ty * r * n;
-#pragma unroll
-    for (int t = 0; t < RT; ++t) {
-        const int k = 16 * t + lj;
-        if (k < r) {
-#pragma unroll
-            for (int c = 0; c < RN; ++c)
-#pragma unroll
-                for (int v = 0; v < 4; ++v) {
-                    const int64_t j = jb + 16 * c + 4 * lg + v;
-                    if (j < n) out[(int64_t)k * n + j] = hs[c][t][v];
-                }
-        }
-    }
-    // dacc[d][v] = D[16 dta + 4v + lg][16 dtb + lj]  (FP64 MFMA layout)
-    const auto dout = to_global(J.Dp) + (int64_t)ty * RPAD * RPAD;
-#pragma unroll
-    for (int d = 0; d < DMAX; ++d) {
-        if (d < nd) {
-#pragma unroll
-            for (int v = 0; v < 4; ++v)
-                dout[(16 * dta[d] + 4 * v + lg) * RPAD + 16 * dtb[d] + lj] = dacc[d][v];
-        }
-    }
-}
-
-template <int RT>
-__global__ __launch_bounds__(256) void k_cpass_s32(const Job *__restrict__ jobs,
-                                                   const int2 *__restrict__ bmap) {
-    const int2 jt = block_job(bmap);
-    const Job &J = jobs[jt.x];
-    int tx = jt.y % J.nCx, ty = jt.y / J.nCx;
-    if (!bmap) {   // single problem: the column blocks of a chunk run on one XCD
-        const int l = (int)(blockIdx.x >> 3);
-        ty = (int)(blockIdx.x & 7) + 8 * (l / J.nCx);
-        tx = l % J.nCx;
-    }
-    if (ty >= J.chunks || J.st->stop) return;
-    cpass_s32_tile<RT>(J, tx, ty);
-}
-
 }  // namespace
+
 
 // ---- host side -------------------------------------------------------------
 
@@ -1531,26 +960,31 @@ hipError_t launch_apass_jobs(int mode, int rpad, int tm, const Job *jobs, const 
     return hipGetLastError();
 }
 
+// C-pass configurations by rank class: WC column tiles (and row groups) per
+// wave -- 4 for r <= 32, 2 above (register budget of the FP32 TwoSum pairs) --
+// and SB 16-row steps per FP32 load batch.
+template <int RT>
+struct CpassCfg {
+    static constexpr int WC = RT <= 2 ? 4 : 2;
+    static constexpr int SB = RT <= 2 ? 2 : 1;
+};
+
+template <int RT>
+static void cpass_launch(bool bf, const Job *jobs, const int2 *bmap, int blocks, hipStream_t s) {
+    constexpr int WC = CpassCfg<RT>::WC, SB = CpassCfg<RT>::SB;
+    const size_t lds = sizeof(double) * cpass_lds_doubles<RT, WC>();
+    if (bf) k_cpass<RT, WC, SB, true><<<blocks, 256, lds, s>>>(jobs, bmap);
+    else k_cpass<RT, WC, SB, false><<<blocks, 256, lds, s>>>(jobs, bmap);
+}
+
 hipError_t launch_cpass_jobs(int rpad, const Job *jobs, const int2 *bmap, int blocks,
                              hipStream_t s, bool bf) {
     if (blocks <= 0) return hipSuccess;
     switch (rpad) {
-        case 16:
-            if (bf) k_cpass<1, 2, true><<<blocks, 256, 0, s>>>(jobs, bmap);
-            else k_cpass<1, 2, false><<<blocks, 256, 0, s>>>(jobs, bmap);
-            break;
-        case 32:
-            if (bf) k_cpass<2, 2, true><<<blocks, 256, 0, s>>>(jobs, bmap);
-            else k_cpass<2, 2, false><<<blocks, 256, 0, s>>>(jobs, bmap);
-            break;
-        case 48:
-            if (bf) k_cpass<3, 1, true><<<blocks, 256, 0, s>>>(jobs, bmap);
-            else k_cpass<3, 1, false><<<blocks, 256, 0, s>>>(jobs, bmap);
-            break;
-        case 64:
-            if (bf) k_cpass<4, 1, true><<<blocks, 256, 0, s>>>(jobs, bmap);
-            else k_cpass<4, 1, false><<<blocks, 256, 0, s>>>(jobs, bmap);
-            break;
+        case 16: cpass_launch<1>(bf, jobs, bmap, blocks, s); break;
+        case 32: cpass_launch<2>(bf, jobs, bmap, blocks, s); break;
+        case 48: cpass_launch<3>(bf, jobs, bmap, blocks, s); break;
+        case 64: cpass_launch<4>(bf, jobs, bmap, blocks, s); break;
         default: return hipErrorInvalidValue;
     }
     return hipGetLastError();
@@ -1605,86 +1039,8 @@ int cpass_final_blocks(int64_t n) { return (int)((n + 15) / 16); }
 
 int apass_grid_single(int nA) { return 8 * ((nA + 7) / 8); }
 
-int cpass_stream_grid(int nCx, int chunks) { return 8 * nCx * ((chunks + 7) / 8); }
-
-// FP64 Gram and 1/G_kk, then 4 waves x 16 rows of A (FP64, stride rpad + 1).
-size_t apass_s32_lds_bytes(int rpad) {
-    return sizeof(double) * ((size_t)rpad * (rpad + 1) + rpad + 4 * 16 * (size_t)(rpad + 1));
-}
-
-hipError_t launch_apass_s32(int mode, int rpad, const Job *jobs, const int2 *bmap, int blocks,
-                            hipStream_t s) {
-    if (blocks <= 0) return hipSuccess;
-    if (mode != MODE_HALS && mode != MODE_MU) return hipErrorInvalidValue;
-    const size_t lds = apass_s32_lds_bytes(rpad);
-    const bool h = mode == MODE_HALS;
-    switch (rpad) {
-        case 16: h ? k_apass_s32<1, MODE_HALS><<<blocks, 256, lds, s>>>(jobs, bmap)
-                   : k_apass_s32<1, MODE_MU><<<blocks, 256, lds, s>>>(jobs, bmap); break;
-        case 32: h ? k_apass_s32<2, MODE_HALS><<<blocks, 256, lds, s>>>(jobs, bmap)
-                   : k_apass_s32<2, MODE_MU><<<blocks, 256, lds, s>>>(jobs, bmap); break;
-        case 48: h ? k_apass_s32<3, MODE_HALS><<<blocks, 256, lds, s>>>(jobs, bmap)
-                   : k_apass_s32<3, MODE_MU><<<blocks, 256, lds, s>>>(jobs, bmap); break;
-        case 64: h ? k_apass_s32<4, MODE_HALS><<<blocks, 256, lds, s>>>(jobs, bmap)
-                   : k_apass_s32<4, MODE_MU><<<blocks, 256, lds, s>>>(jobs, bmap); break;
-        default: return hipErrorInvalidValue;
-    }
-    return hipGetLastError();
-}
-
-hipError_t launch_cpass_s32(int rpad, const Job *jobs, const int2 *bmap, int blocks,
-                            hipStream_t s) {
-    if (blocks <= 0) return hipSuccess;
-    switch (rpad) {
-        case 16: k_cpass_s32<1><<<blocks, 256, 0, s>>>(jobs, bmap); break;
-        case 32: k_cpass_s32<2><<<blocks, 256, 0, s>>>(jobs, bmap); break;
-        case 48: k_cpass_s32<3><<<blocks, 256, 0, s>>>(jobs, bmap); break;
-        case 64: k_cpass_s32<4><<<blocks, 256, 0, s>>>(jobs, bmap); break;
-        default: return hipErrorInvalidValue;
-    }
-    return hipGetLastError();
-}
-
-// Gram and 1/G_kk, then 4 waves x 64 rows of A (all FP32, stride rpad + 1).
-size_t apass_stream_lds_bytes(int rpad) {
-    return sizeof(float) * ((size_t)rpad * (rpad + 1) + rpad) +
-           sizeof(float) * 4 * 64 * (size_t)(rpad + 1);
-}
-
-hipError_t launch_apass_stream(int mode, int rpad, const Job *jobs, const int2 *bmap, int blocks,
-                               hipStream_t s) {
-    if (blocks <= 0) return hipSuccess;
-    if (mode != MODE_HALS && mode != MODE_MU) return hipErrorInvalidValue;
-    const size_t lds = apass_stream_lds_bytes(rpad);
-    const bool h = mode == MODE_HALS;
-    switch (rpad) {
-        case 16: h ? k_apass_stream<1, MODE_HALS><<<blocks, 256, lds, s>>>(jobs, bmap)
-                   : k_apass_stream<1, MODE_MU><<<blocks, 256, lds, s>>>(jobs, bmap); break;
-        case 32: h ? k_apass_stream<2, MODE_HALS><<<blocks, 256, lds, s>>>(jobs, bmap)
-                   : k_apass_stream<2, MODE_MU><<<blocks, 256, lds, s>>>(jobs, bmap); break;
-        case 48: h ? k_apass_stream<3, MODE_HALS><<<blocks, 256, lds, s>>>(jobs, bmap)
-                   : k_apass_stream<3, MODE_MU><<<blocks, 256, lds, s>>>(jobs, bmap); break;
-        case 64: h ? k_apass_stream<4, MODE_HALS><<<blocks, 256, lds, s>>>(jobs, bmap)
-                   : k_apass_stream<4, MODE_MU><<<blocks, 256, lds, s>>>(jobs, bmap); break;
-        default: return hipErrorInvalidValue;
-    }
-    return hipGetLastError();
-}
-
-hipError_t launch_cpass_stream(int rpad, const Job *jobs, const int2 *bmap, int blocks,
-                               hipStream_t s) {
-    if (blocks <= 0) return hipSuccess;
-    switch (rpad) {
-        case 16: k_cpass_stream<1><<<blocks, 256, 0, s>>>(jobs, bmap); break;
-        case 32: k_cpass_stream<2><<<blocks, 256, 0, s>>>(jobs, bmap); break;
-        case 48: k_cpass_stream<3><<<blocks, 256, 0, s>>>(jobs, bmap); break;
-        case 64: k_cpass_stream<4><<<blocks, 256, 0, s>>>(jobs, bmap); break;
-        default: return hipErrorInvalidValue;
-    }
-    return hipGetLastError();
-}
-
 int cpass_grid_single(int nCx, int chunks) { return 8 * nCx * ((chunks + 7) / 8); }
+
 
 // Allow the sweep kernels the LDS sizes apass_lds_bytes / cfinal_lds_bytes
 // can ask for (above the 64 KB default).
@@ -1704,6 +1060,8 @@ static void lds_attr(hipError_t &e) {
         set((const void *)k_apass<RT, 2, 2, S64, MODE, true>);
     }
     set((const void *)k_cfinal<RT, MODE>);
+    set((const void *)k_cpass<RT, CpassCfg<RT>::WC, CpassCfg<RT>::SB, false>);
+    set((const void *)k_cpass<RT, CpassCfg<RT>::WC, CpassCfg<RT>::SB, true>);
 }
 
 template <int RT>
@@ -1714,13 +1072,6 @@ static void lds_attr_modes(hipError_t &e) {
     hipError_t x = hipFuncSetAttribute((const void *)k_cfinal<RT, MODE_INIT>,
                                        hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
     if (x != hipSuccess && e == hipSuccess) e = x;
-    for (const void *f : {(const void *)k_apass_stream<RT, MODE_HALS>,
-                          (const void *)k_apass_stream<RT, MODE_MU>,
-                          (const void *)k_apass_s32<RT, MODE_HALS>,
-                          (const void *)k_apass_s32<RT, MODE_MU>}) {
-        x = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
-        if (x != hipSuccess && e == hipSuccess) e = x;
-    }
 }
 
 hipError_t enable_large_lds() {
@@ -1730,7 +1081,8 @@ hipError_t enable_large_lds() {
         lds_attr_modes<2>(e);
         lds_attr_modes<3>(e);
         lds_attr_modes<4>(e);
-        return e;
+        const hipError_t x = enable_stream_lds();
+        return e == hipSuccess ? x : e;
     }();
     return done;
 }

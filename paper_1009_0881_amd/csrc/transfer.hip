@@ -241,6 +241,36 @@ __global__ __launch_bounds__(256) void k_pack_bf16(const float *__restrict__ X, 
     *reinterpret_cast<uint4 *>(Y + e * 8) = w;
 }
 
+// Column-panelled copy for the streaming C-pass: element (i, j) of X at
+// ((j/16 * S + i/32) * 4 + i%32/8) * 128 + j%16 * 8 + i%8, S = rows_pad / 32,
+// zero outside.  One thread per 8-row group of one column; consecutive threads
+// take consecutive columns of a panel, so each writes 16 contiguous bytes next
+// to its neighbour's.
+__global__ __launch_bounds__(256) void k_pack_bf16_cpanel(const float *__restrict__ X, int64_t ldx,
+                                                          int64_t rows, int64_t cols,
+                                                          uint16_t *__restrict__ Y,
+                                                          int64_t rows_pad, int64_t total) {
+    const int64_t e = blockIdx.x * (int64_t)256 + threadIdx.x;   // (panel, step, group, col)
+    if (e >= total) return;
+    const int jj = (int)(e & 15);
+    const int64_t q = e >> 4;                 // (panel * S + step) * 4 + group
+    const int64_t S = rows_pad / 32;
+    const int64_t pst = q >> 2, panel = pst / S, step = pst - panel * S;
+    const int64_t j = panel * 16 + jj, i0 = step * 32 + (q & 3) * 8;
+    uint16_t v[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+        const int64_t i = i0 + u;
+        v[u] = (i < rows && j < cols) ? bf16_rne(X[j * ldx + i]) : (uint16_t)0;
+    }
+    uint4 w;
+    w.x = v[0] | ((uint32_t)v[1] << 16);
+    w.y = v[2] | ((uint32_t)v[3] << 16);
+    w.z = v[4] | ((uint32_t)v[5] << 16);
+    w.w = v[6] | ((uint32_t)v[7] << 16);
+    *reinterpret_cast<uint4 *>(Y + e * 8) = w;
+}
+
 // ---- grouped setup kernels (one launch over many problems) ------------------
 
 __global__ __launch_bounds__(256) void k_xfer_many(const XferJob *__restrict__ jobs,
@@ -390,6 +420,16 @@ hipError_t launch_pack_bf16(const float *X, int64_t ldx, int64_t rows, int64_t c
     if (total <= 0) return hipSuccess;
     k_pack_bf16<<<(unsigned)((total + 255) / 256), 256, 0, s>>>(X, ldx, rows, cols, Y, rows16,
                                                                 cols_pad);
+    return hipGetLastError();
+}
+
+hipError_t launch_pack_bf16_cpanel(const float *X, int64_t ldx, int64_t rows, int64_t cols,
+                                   uint16_t *Y, int64_t rows_pad, hipStream_t s) {
+    const int64_t total = (cols + 15) / 16 * (rows_pad / 32) * 4 * 16;
+    if (total <= 0) return hipSuccess;
+    if (rows_pad % 32 != 0 || rows_pad < rows) return hipErrorInvalidValue;
+    k_pack_bf16_cpanel<<<(unsigned)((total + 255) / 256), 256, 0, s>>>(X, ldx, rows, cols, Y,
+                                                                       rows_pad, total);
     return hipGetLastError();
 }
 
