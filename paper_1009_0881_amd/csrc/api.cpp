@@ -102,7 +102,6 @@ Ctx make_ctx(nmf_plan_t plan, const float *dM, float *dV, float *dW, void *dws, 
     c.rparts = at<double>(c.ws, p.ws.off_rparts);
     c.Cp = at<double>(c.ws, p.ws.off_cparts);
     c.Dp = at<double>(c.ws, p.ws.off_Dp);
-    c.Bp = at<double>(c.ws, p.ws.off_Bp);
     c.Wt = at<float>(c.ws, p.ws.off_Wt);
     c.A = p.ws.off_A ? at<float>(c.ws, p.ws.off_A) : nullptr;
     c.C = p.ws.off_C ? at<float>(c.ws, p.ws.off_C) : nullptr;
@@ -135,7 +134,7 @@ Ctx make_ctx(nmf_plan_t plan, const float *dM, float *dV, float *dW, void *dws, 
         J.nCx = (int32_t)((p.d.n + 63) / 64);
         J.nC = J.nCx * li.cp_chunks;
         J.nF = cpass_final_blocks(p.d.n);
-        J.nG = (p.d.r * p.d.r + 255) / 256;
+        J.nG = gram_tiles(p.rpad);
         J.depth = (int32_t)l;
         J.log_cap = p.d.log_cap;
         J.V = c.V[l];
@@ -147,7 +146,6 @@ Ctx make_ctx(nmf_plan_t plan, const float *dM, float *dV, float *dW, void *dws, 
         J.Dd = c.Dd;
         J.Cp = c.Cp;
         J.Dp = c.Dp;
-        J.Bp = c.Bp;
         J.rparts = c.rparts;
         J.normM2 = c.norm + l;
         J.log_rel = c.log_rel;
@@ -266,15 +264,15 @@ nmf_status gram_W(Ctx &c) {
     return NMF_OK;
 }
 
-// Start of a solve: Wt (transposed, zero-padded W) and B = W W^T from the
-// W tile kernel's partials, reduced in fixed order.  The batch executor runs
-// the same two kernels, so single and batched solves agree bitwise.
+// Start of a solve: Wt (transposed, zero-padded W) from the W tile kernel and
+// B = W W^T from the B tile kernel.  The batch executor runs the same two
+// kernels, so single and batched solves agree bitwise.
 nmf_status init_w(Ctx &c) {
     nmf_plan_t plan = c.plan;
     const Job &J = c.jobs[0];
     NMF_LAUNCH(K_GRAM_W, launch_cfinal_jobs(3, J.rpad, c.djobs, nullptr, J.nF,
                                             cfinal_lds_bytes(J.rpad, 3), c.s));
-    NMF_LAUNCH(K_GRAM_W, launch_reduce_jobs(2, c.djobs, nullptr, J.nG, c.s));
+    NMF_LAUNCH(K_GRAM_W, launch_gram_w_jobs(0, c.djobs, nullptr, J.nG, c.s));
     return NMF_OK;
 }
 
@@ -310,7 +308,7 @@ nmf_status sweep(Ctx &c, int d, bool fp32 = false) {
     else
         NMF_LAUNCH(K_CPART, launch_cpass_jobs(J.rpad, dj, nullptr,
                                               cpass_grid_single(J.nCx, J.chunks), c.s, bf));
-    NMF_LAUNCH(K_GRAM_V, launch_reduce_jobs(0, dj, nullptr, J.nG, c.s));
+    NMF_LAUNCH(K_GRAM_V, launch_reduce_jobs(dj, nullptr, J.nG, c.s));
     NMF_LAUNCH(K_CFINAL, launch_cfinal_jobs(mode, J.rpad, dj, nullptr, J.nF,
                                             cfinal_lds_bytes(J.rpad, mode), c.s));
     if (mode == 2) {
@@ -322,7 +320,7 @@ nmf_status sweep(Ctx &c, int d, bool fp32 = false) {
                                             d, c.log_rel, c.log_depth, p.d.log_cap, c.st,
                                             p.d.tol, c.s));
     } else {
-        NMF_LAUNCH(K_GRAM_W, launch_reduce_jobs(1, dj, nullptr, J.nG, c.s));
+        NMF_LAUNCH(K_GRAM_W, launch_gram_w_jobs(1, dj, nullptr, J.nG, c.s));
     }
     c.depths.push_back((int8_t)d);
     return NMF_OK;

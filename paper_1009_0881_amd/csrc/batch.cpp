@@ -34,7 +34,7 @@ size_t batch_table_bytes(const nmf_plan_t *plans, int count) {
         const LevelInfo &l0 = p.lv[0];
         const int64_t tm = apass_rows_per_block(l0.m);
         const int64_t nCx = cdiv(n, 64);
-        blocks += cdiv(l0.m, tm) + nCx * l0.cp_chunks + 2 * cdiv(r * r, 256) +
+        blocks += cdiv(l0.m, tm) + nCx * l0.cp_chunks + 2 * gram_tiles(p.rpad) +
                   cpass_final_blocks(n);
         int64_t xt = 0;
         for (size_t l = 1; l < p.lv.size(); ++l)
@@ -229,7 +229,7 @@ nmf_status Executor::setup_fresh() {
             return st;
         NMF_HIP(launch_cfinal_jobs(3, kv.first, dj, dF, (int)bF.size(),
                                    cfinal_lds_bytes(kv.first, 3), s_));
-        NMF_HIP(launch_reduce_jobs(2, dj, dG, (int)bG.size(), s_));
+        NMF_HIP(launch_gram_w_jobs(0, dj, dG, (int)bG.size(), s_));
     }
     return NMF_OK;
 }
@@ -382,10 +382,10 @@ nmf_status Executor::launch_sweeps(const std::vector<Inst *> &active, bool captu
             NMF_HIP(launch_apass_jobs(g.mode, g.rpad, g.tm, g.dj, g.bA, g.nA,
                                       apass_lds_bytes(g.rpad, g.tm, g.mode), s_, g.bf));
             NMF_HIP(launch_cpass_jobs(g.rpad, g.dj, g.bC, g.nC, s_, g.bf));
-            NMF_HIP(launch_reduce_jobs(0, g.dj, g.bG, g.nG, s_));
+            NMF_HIP(launch_reduce_jobs(g.dj, g.bG, g.nG, s_));
             NMF_HIP(launch_cfinal_jobs(g.mode, g.rpad, g.dj, g.bF, g.nF,
                                        cfinal_lds_bytes(g.rpad, g.mode), s_));
-            NMF_HIP(launch_reduce_jobs(1, g.dj, g.bG, g.nG, s_));
+            NMF_HIP(launch_gram_w_jobs(1, g.dj, g.bG, g.nG, s_));
         }
         return NMF_OK;
     };

@@ -37,7 +37,7 @@ struct Ctx {
     double *nparts;               // norm partials, kNormParts per level
     double *Bd, *Dd, *gparts, *rparts;
     float *Bf, *Df, *A, *C, *Wt;
-    double *Cp, *Dp, *Bp;
+    double *Cp, *Dp;
     std::vector<const float *> M;
     std::vector<int64_t> ldm;
     std::vector<float *> V;

@@ -18,7 +18,8 @@ struct Job {
     int32_t tm;          // A-pass rows per tile (16 or 64)
     int32_t chunks;      // split of the length-m reduction of V^T M
     int64_t chunk;       // rows per chunk (multiple of 16)
-    int32_t nA, nC, nF, nG;   // tiles of: A-pass, C-pass (nCx * chunks), W update, Gram reduce
+    int32_t nA, nC, nF, nG;   // tiles of: A-pass, C-pass (nCx * chunks), W update (4
+                              // columns each), Gram kernels (upper 16x16 tiles)
     int32_t nCx;         // 64-column tiles of the C-pass
     int32_t depth, log_cap;
     float *V;            // level factor, m x r column-major
@@ -28,10 +29,10 @@ struct Job {
     float *A;            // ANLS: M W^T (m x r)
     float *C;            // ANLS: V^T M (r x n)
     double *Bd, *Dd;     // W W^T and V^T V (r x r, FP64)
-    double *Cp;          // V^T M partials: chunks x r x n
+    double *Cp;          // V^T M partials: chunks x (n x r, entry (k, j) at j * r + k),
+                         // FP64 (prec 0) or FP32 (prec 1, a float view of the buffer)
     double *Dp;          // V^T V partials: chunks x rpad x rpad (upper 16x16 tiles)
-    double *Bp;          // W W^T partials: nF x rpad x rpad
-    double *rparts;      // residual scalars, nF
+    double *rparts;      // residual partials of the W-update tiles, nF
     const double *normM2;   // ||M_depth||^2
     double *log_rel;
     int32_t *log_depth;

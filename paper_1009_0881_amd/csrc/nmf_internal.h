@@ -71,7 +71,7 @@ struct Workspace {
     size_t off_state, off_log, off_logdepth, off_norm, off_nparts;
     size_t off_Bd, off_Bf, off_Dd, off_Df;
     size_t off_gparts, off_cparts, off_rparts, off_A, off_C, off_Wb;
-    size_t off_Wt, off_Dp, off_Bp, off_jobs;
+    size_t off_Wt, off_Dp, off_jobs;
     size_t gparts_cap;   // doubles
     size_t rparts_cap;   // doubles
     size_t total;
@@ -145,8 +145,8 @@ hipError_t launch_cpass_jobs(int rpad, const Job *jobs, const int2 *bmap, int bl
                              hipStream_t s, bool bf = false);
 // which = 0: V^T V from the C-pass partials; 1: W W^T and the residual log;
 // 2: W W^T only.
-hipError_t launch_reduce_jobs(int which, const Job *jobs, const int2 *bmap, int blocks,
-                              hipStream_t s);
+// D = V^T V from the C-pass partials, one block per upper tile (gram_tiles).
+hipError_t launch_reduce_jobs(const Job *jobs, const int2 *bmap, int blocks, hipStream_t s);
 hipError_t launch_cfinal_jobs(int mode, int rpad, const Job *jobs, const int2 *bmap, int blocks,
                               size_t lds, hipStream_t s);
 
@@ -180,7 +180,15 @@ hipError_t launch_gather_states(DevState *const *states, int count, DevState *ou
 int apass_rows_per_block(int64_t m);
 size_t apass_lds_bytes(int rpad, int tm, int mode);
 size_t cfinal_lds_bytes(int rpad, int mode);
-int cpass_final_blocks(int64_t n);
+int cpass_final_blocks(int64_t n);   // W-update tiles of 4 columns
+// Upper-triangle 16x16 tiles of an rpad x rpad Gram: blocks of the Gram
+// reduction (D) and of the B = W W^T kernel.
+inline int gram_tiles(int rpad) { return (rpad / 16) * (rpad / 16 + 1) / 2; }
+// B = W W^T (FP64) from the current W, one block per upper tile.  with_resid:
+// block 0 also assembles the residual of the iteration from the W-update
+// partials, logs rel_err and sets the stop flag.
+hipError_t launch_gram_w_jobs(int with_resid, const Job *jobs, const int2 *bmap, int blocks,
+                              hipStream_t s);
 // Grids of single-problem (null block map) A-pass / C-pass launches, whose
 // blocks are mapped to tiles XCD by XCD.
 int apass_grid_single(int nA);

@@ -230,7 +230,6 @@ nmf_status build_plan(const nmf_desc &d0, Plan &p, std::string &err) {
     }
     ws.off_Wt = take(sizeof(float) * n * p.rpad);
     ws.off_Dp = take(sizeof(double) * max_cp * rp2);
-    ws.off_Bp = take(sizeof(double) * (size_t)cpass_final_blocks(d.n) * rp2);
     ws.off_jobs = take(sizeof(Job) * (p.lv.size() + 1));   // + FP32 refinement job
     ws.off_Wb = 0;
     const int64_t npad = bf_pad(d.n);

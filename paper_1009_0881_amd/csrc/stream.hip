@@ -331,8 +331,8 @@ __device__ __forceinline__ void cpass_stream_tile(const Job &J, int tx, int ty, 
         vm_wait_barrier<kStageOps * (NST - 2 - j)>();
         mma(kk + j);
     });
-    // acc[c][t][v] = C[k = 16t + lj][j = jb + 16c + 4lg + v]
-    const auto out = to_global(J.Cp) + (int64_t)ty * r * n;
+    // acc[c][t][v] = C[k = 16t + lj][j = jb + 16c + 4lg + v]; FP32 partials
+    const auto out = to_global(reinterpret_cast<float *>(J.Cp)) + (int64_t)ty * r * n;
 #pragma unroll
     for (int t = 0; t < RT; ++t) {
         const int k = 16 * t + lj;
@@ -342,7 +342,7 @@ __device__ __forceinline__ void cpass_stream_tile(const Job &J, int tx, int ty, 
 #pragma unroll
                 for (int v = 0; v < 4; ++v) {
                     const int64_t j = jb + 16 * c + 4 * lg + v;
-                    if (j < n) out[(int64_t)k * n + j] = (double)acc[c][t][v];
+                    if (j < n) out[j * r + k] = acc[c][t][v];
                 }
         }
     }
@@ -660,7 +660,7 @@ __device__ void cpass_s32_tile(const Job &J, int tx, int ty) {
 #pragma unroll
                 for (int v = 0; v < 4; ++v) {
                     const int64_t j = jb + 16 * c + 4 * lg + v;
-                    if (j < n) out[(int64_t)k * n + j] = hs[c][t][v];
+                    if (j < n) out[j * r + k] = hs[c][t][v];
                 }
         }
     }

@@ -589,8 +589,10 @@ __device__ __forceinline__ void cpass_tile(const Job &J, int tx, int ty, int ntx
     }
     if (WC > 1) __syncthreads();
     if (rg == 0) {
-        // hi + lo (+ row groups 1..WC-1) = C[k = 16t + lj][j = jb + 16c + 4*lg + v]
+        // hi + lo (+ row groups 1..WC-1) = C[k = 16t + lj][j = jb + 16c + 4*lg + v];
+        // FP32 partials in BF16 mode
         const auto out = to_global(J.Cp) + (int64_t)ty * r * n;
+        const auto outf = to_global(reinterpret_cast<float *>(J.Cp)) + (int64_t)ty * r * n;
 #pragma unroll
         for (int c = 0; c < WC; ++c)
 #pragma unroll
@@ -604,7 +606,10 @@ __device__ __forceinline__ void cpass_tile(const Job &J, int tx, int ty, int ntx
                         sum += redc[((size_t)((q - 1) * NCG + cg) * WC * RT * 4 + (c * RT + t) * 4 + v) * 64 +
                                     lane];
                     const int64_t jj = jb + 16 * c + 4 * lg + v;
-                    if (k < r && jj < n) out[(int64_t)k * n + jj] = sum;
+                    if (k < r && jj < n) {
+                        if constexpr (BF) outf[jj * r + k] = (float)sum;
+                        else out[jj * r + k] = sum;
+                    }
                 }
             }
         const auto dout = to_global(J.Dp) + (int64_t)ty * RPAD * RPAD;
@@ -695,109 +700,209 @@ __global__ __launch_bounds__(256) void k_cpass(const Job *__restrict__ jobs,
 }
 
 // ---------------------------------------------------------------------------
-// Sum of FP64 Gram partials stored as upper-triangle 16x16 tiles (row stride
-// rpad): G[a][b] = sum_p parts[p][min(a,b)][max(a,b)], added in index order.
-// which = 0: D from the C-pass partials.  which = 1: B from the W-update
-// partials, and tile 0 also assembles the residual of the iteration,
-// e^2 = ||M_d||^2 + sum_b rparts[b] (the partials carry <D,B_b> - 2<C_b,W_b>),
-// logs rel_err and sets the stop flag.
+// Upper-triangle 16x16 tile number `idx` (numbered row by row) of an RT x RT
+// grid of tiles: (ta, tb) with ta <= tb.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ void gram_tile_pair(int idx, int rt, int &ta, int &tb) {
+    int a = 0;
+    while (idx >= rt - a) {
+        idx -= rt - a;
+        ++a;
+    }
+    ta = a;
+    tb = a + idx;
+}
+
+// ---------------------------------------------------------------------------
+// D = V^T V from the C-pass partials (upper-triangle 16x16 tiles, row stride
+// rpad): one block per upper tile; D[a][b] = sum_p parts[p][a'][b'] with
+// (a', b') = (min, max)(a, b), added in index order, written to both halves.
 // ---------------------------------------------------------------------------
 __global__ __launch_bounds__(256) void k_reduce(const Job *__restrict__ jobs,
-                                                const int2 *__restrict__ bmap,
-                                                int which) {
-    __shared__ double red[4];
+                                                const int2 *__restrict__ bmap) {
     const int2 jt = block_job(bmap);
     const Job &J = jobs[jt.x];
     if (J.st->stop) return;
-    const int tile = jt.y;
     const int r = J.r, rpad = J.rpad;
-    const int e = tile * 256 + threadIdx.x;
-    const double *parts = which ? J.Bp : J.Dp;
-    const int nparts = which ? J.nF : J.chunks;   // which 2: W W^T only (start of a solve)
-    if (e < r * r) {
-        const int a = e / r, b = e % r;
-        const int ua = a < b ? a : b, ub = a < b ? b : a;
-        const double s = sum_strided(parts + ua * rpad + ub, (int64_t)rpad * rpad, nparts);
-        (which ? J.Bd : J.Dd)[e] = s;
+    int ta, tb;
+    gram_tile_pair(jt.y, rpad / 16, ta, tb);
+    const int ra = 16 * ta + (threadIdx.x >> 4), rb = 16 * tb + (threadIdx.x & 15);
+    const int ua = ra < rb ? ra : rb, ub = ra < rb ? rb : ra;
+    if (ra < r && rb < r) {
+        const double s = sum_strided<64>(J.Dp + ua * rpad + ub, (int64_t)rpad * rpad, J.chunks);
+        J.Dd[ra * r + rb] = s;
+        if (ta != tb) J.Dd[rb * r + ra] = s;
     }
-    if (which == 1 && tile == 0) {
-        double s = 0.0;
-        for (int i = threadIdx.x; i < J.nF; i += 256) s += to_global(J.rparts)[i];
-        s = block_sum_f64<256>(s, red);
-        if (threadIdx.x == 0) {
-            DevState *st = J.st;
-            const double nm = *J.normM2;
-            const double e2 = nm + s;
-            const double e2c = e2 > 0.0 ? e2 : 0.0;
-            const double rel = nm > 0.0 ? sqrt(e2c / nm) : sqrt(e2c);
-            const int idx = st->log_len;
-            if (idx < J.log_cap) {
-                J.log_rel[idx] = rel;
-                J.log_depth[idx] = J.depth;
+}
+
+// ---------------------------------------------------------------------------
+// B = W W^T in FP64 from the FP32 W (r x n, row-major): block = upper tile
+// (ta, tb); its 8 waves split n into contiguous ranges and run FP64 MFMAs
+// (products of FP32 values are exact), lane (li, lk) supplying columns
+// j0 + 4 lk + s of rows 16 ta + li and 16 tb + li to MFMA s; the loads of 8
+// 16-column steps go out together.  The wave partials are added in LDS in
+// wave order.  with_resid: block 0 also assembles the residual of the
+// iteration, e^2 = ||M_d||^2 + sum of the W-update partials (index order),
+// logs rel_err and sets the stop flag.
+// ---------------------------------------------------------------------------
+constexpr int kGramWWaves = 8;
+
+__global__ __launch_bounds__(64 * kGramWWaves) void k_gram_w(const Job *__restrict__ jobs,
+                                                             const int2 *__restrict__ bmap,
+                                                             int with_resid) {
+    constexpr int NW = kGramWWaves, NT = 64 * NW, U = 8;
+    __shared__ double part[NW - 1][256];
+    __shared__ double red[NW];
+    const int2 jt = block_job(bmap);
+    const Job &J = jobs[jt.x];
+    if (J.st->stop) return;
+    const int r = J.r, rpad = J.rpad;
+    const int64_t n = J.n;
+    int ta, tb;
+    gram_tile_pair(jt.y, rpad / 16, ta, tb);
+    const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+    const int li = lane & 15, lk = lane >> 4;
+    const int ka = 16 * ta + li, kb = 16 * tb + li;
+    const auto W = to_global(J.W);
+    const gmem<const float> *wa = W + (int64_t)(ka < r ? ka : 0) * n;
+    const gmem<const float> *wb = W + (int64_t)(kb < r ? kb : 0) * n;
+    const bool va = ka < r, vb = kb < r;
+    const bool vec = (n & 3) == 0 && ((uintptr_t)J.W & 15) == 0;
+    // residual (block 0): the W-update partials of the previous kernel
+    double rs = 0.0;
+    if (with_resid && jt.y == 0)
+        for (int i = tid; i < J.nF; i += NT) rs += to_global(J.rparts)[i];
+    // columns per wave, a multiple of 16
+    const int64_t per = (n + 16 * NW - 1) / (16 * NW) * 16;
+    const int64_t c0 = wave * per, c1 = (c0 + per < n) ? c0 + per : n;
+    v4d acc = {0.0, 0.0, 0.0, 0.0};
+    for (int64_t jg = c0; jg < c1; jg += 16 * U) {
+        v4f xa[U], xb[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const int64_t jb = jg + 16 * u + 4 * lk;
+            if (vec && jb + 3 < c1) {
+                xa[u] = va ? *(gmem<const v4f> *)(wa + jb) : v4f{0.0f, 0.0f, 0.0f, 0.0f};
+                xb[u] = vb ? *(gmem<const v4f> *)(wb + jb) : v4f{0.0f, 0.0f, 0.0f, 0.0f};
+            } else {
+#pragma unroll
+                for (int s2 = 0; s2 < 4; ++s2) {
+                    const bool ok = jb + s2 < c1;
+                    xa[u][s2] = (va && ok) ? wa[jb + s2] : 0.0f;
+                    xb[u][s2] = (vb && ok) ? wb[jb + s2] : 0.0f;
+                }
             }
-            st->log_len = idx + 1;
-            st->last_rel = rel;
-            if (!isfinite(e2)) {
-                st->status = NMF_E_NONFINITE;
-                st->stop = 1;
-            } else if (J.depth == 0 && J.prec == 0 && J.tol > 0.0 && rel <= J.tol) {
-                st->stopped = 1;
-                st->stop = 1;
+        }
+#pragma unroll
+        for (int u = 0; u < U; ++u)
+#pragma unroll
+            for (int s2 = 0; s2 < 4; ++s2)
+                acc = __builtin_amdgcn_mfma_f64_16x16x4f64((double)xa[u][s2], (double)xb[u][s2], acc,
+                                                           0, 0, 0);
+    }
+    // acc[v] = B[16 ta + 4 v + lk][16 tb + li]
+    if (wave > 0)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) part[wave - 1][v * 64 + lane] = acc[v];
+    __syncthreads();
+    if (wave == 0) {
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+            double b = acc[v];
+#pragma unroll
+            for (int w2 = 0; w2 < NW - 1; ++w2) b += part[w2][v * 64 + lane];
+            const int a1 = 16 * ta + 4 * v + lk, b1 = 16 * tb + li;
+            // a diagonal tile keeps exact symmetry: its lower half copies the upper
+            if (a1 < r && b1 < r && (ta != tb || a1 <= b1)) {
+                J.Bd[a1 * r + b1] = b;
+                J.Bd[b1 * r + a1] = b;
             }
+        }
+    }
+    if (!with_resid || jt.y != 0) return;
+    rs = block_sum_f64<NT>(rs, red);
+    if (tid == 0) {
+        DevState *st = J.st;
+        const double nm = *J.normM2;
+        const double e2 = nm + rs;
+        const double e2c = e2 > 0.0 ? e2 : 0.0;
+        const double rel = nm > 0.0 ? sqrt(e2c / nm) : sqrt(e2c);
+        const int idx = st->log_len;
+        if (idx < J.log_cap) {
+            J.log_rel[idx] = rel;
+            J.log_depth[idx] = J.depth;
+        }
+        st->log_len = idx + 1;
+        st->last_rel = rel;
+        if (!isfinite(e2)) {
+            st->status = NMF_E_NONFINITE;
+            st->stop = 1;
+        } else if (J.depth == 0 && J.prec == 0 && J.tol > 0.0 && rel <= J.tol) {
+            st->stopped = 1;
+            st->stop = 1;
         }
     }
 }
 
 // ---------------------------------------------------------------------------
-// W-update tile: reduce the C partials of 16 columns (fixed order) and update
-// those columns of W (and of its transposed copy Wt).  Also emits this
-// tile's FP64 partial of B = W W^T (upper-triangle tiles) and the residual
-// scalar <D, B_tile> - 2 <C_tile, W_tile>.
+// W-update tile: 4 columns of W.  Each thread reduces one entry of those
+// columns of C from the C-pass partials (chunk-major, n x r per chunk: the
+// tile's entries are contiguous; fixed order, one batch of loads); then 16
+// lanes per column update it (HALS / MU against D) and write W, its
+// transposed copy Wt (and the BF16 copy).  Also emits the tile's residual
+// partial sum_j (w_j^T D w_j - 2 c_j^T w_j), j over its columns: the first
+// term is the tile's share of <D, B> (B = sum_j w_j w_j^T).
 // ---------------------------------------------------------------------------
+constexpr int kCfCols = 4;
+
 template <int RT, int MODE>
-__device__ void cfinal_tile(const Job &J, int tile, double *smem) {
-    constexpr int RPAD = RT * 16, GS = RPAD + 1, CS = RPAD + 1;
+__device__ __forceinline__ void cfinal_tile(const Job &J, int tile, double *smem) {
+    constexpr int RPAD = RT * 16, GS = RPAD + 1, CS = RPAD + 1, CF = kCfCols;
     constexpr bool UPD = MODE == MODE_HALS || MODE == MODE_MU;
-    constexpr bool INIT = MODE == MODE_INIT;     // no C, no update: Wt and W W^T partials
+    constexpr bool INIT = MODE == MODE_INIT;     // no C, no update: Wt (and Wb) only
+    static_assert(CF * RPAD <= 256, "one C entry per thread");
     double *Gs = smem;
     double *Gi = Gs + (UPD ? RPAD * GS : 0);
     double *Cs = Gi + (UPD ? RPAD : 0);
-    double *Wn = Cs + (INIT ? 0 : 16 * CS);
-    double *red = Wn + (MODE == MODE_STORE ? 0 : 16 * CS);
+    double *red = Cs + (INIT ? 0 : CF * CS);
     const int tid = threadIdx.x;
     const int64_t n = J.n;
     const int r = J.r;
-    const int64_t j0 = (int64_t)tile * 16;
+    const int64_t j0 = (int64_t)tile * CF;
     // factor columns of the update: 16 lanes per column, column j0 + tid/16
+    // (wave 0)
+    const bool colt = tid < 16 * CF;
     double xw[RT];
     if constexpr (MODE != MODE_STORE) {
         const int64_t j = j0 + (tid >> 4);
 #pragma unroll
         for (int t = 0; t < RT; ++t) {
             const int k = 16 * t + (tid & 15);
-            xw[t] = (j < n && k < r) ? (double)to_global(J.W)[(int64_t)k * n + j] : 0.0;
+            xw[t] = (colt && j < n && k < r) ? (double)to_global(J.W)[(int64_t)k * n + j] : 0.0;
         }
     }
     if constexpr (!INIT) {
-        for (int e = tid; e < 16 * RPAD; e += 256) {
-            const int jj = e & 15, k = e >> 4;
-            const int64_t j = j0 + jj;
-            double s = 0.0;
-            if (k < r && j < n) s = sum_strided(J.Cp + (int64_t)k * n + j, (int64_t)r * n, J.chunks);
-            Cs[jj * CS + k] = s;
+        const int jj = tid / RPAD, k = tid % RPAD;
+        const int64_t j = j0 + jj;
+        double s = 0.0;
+        if (jj < CF && k < r && j < n) {
+            const int64_t off = j * r + k, str = (int64_t)r * n;
+            s = J.prec ? sum_strided<64>(reinterpret_cast<const float *>(J.Cp) + off, str, J.chunks)
+                       : sum_strided<64>(J.Cp + off, str, J.chunks);
         }
+        if (jj < CF) Cs[jj * CS + k] = s;
     }
     if constexpr (UPD) load_gram<RPAD>(J.Dd, r, Gs, GS, Gi);
     if constexpr (!INIT) __syncthreads();
     if constexpr (MODE == MODE_STORE) {
-        for (int e = tid; e < 16 * r; e += 256) {
-            const int jj = e & 15, k = e >> 4;
+        for (int e = tid; e < CF * r; e += 256) {
+            const int jj = e % CF, k = e / CF;
             const int64_t j = j0 + jj;
             if (j < n) to_global(J.C)[(int64_t)k * n + j] = (float)Cs[jj * CS + k];
         }
     } else {
-        double part_cw = 0.0;
-        {
+        double part = 0.0;
+        if (colt) {
             const int jj = tid >> 4, p = tid & 15;
             const int64_t j = j0 + jj;
             const bool ok = j < n;
@@ -807,36 +912,30 @@ __device__ void cfinal_tile(const Job &J, int tile, double *smem) {
                 for (int t = 0; t < RT; ++t) cv[t] = Cs[jj * CS + 16 * t + p];
                 row_update<RT, MODE>(xw, Gs, GS, Gi, cv, r, p);
             }
+            double xs[RT];
 #pragma unroll
             for (int t = 0; t < RT; ++t) {
                 const int k = 16 * t + p;
                 const float xf = (ok && k < r) ? (float)xw[t] : 0.0f;
-                Wn[jj * CS + k] = (double)xf;
+                xs[t] = (double)xf;
                 if (ok) {
                     to_global(J.Wt)[j * RPAD + wt_pos(k, RT)] = xf;
                     if (J.Wb) to_global(J.Wb)[(int64_t)k * J.npad + j] = bf16_rne(xf);   // BF16 mode
-                    if (UPD && k < r) {
-                        to_global(J.W)[(int64_t)k * n + j] = xf;
-                        part_cw += Cs[jj * CS + k] * (double)xf;
-                    }
+                    if (UPD && k < r) to_global(J.W)[(int64_t)k * n + j] = xf;
+                }
+            }
+            if constexpr (UPD) {
+                double dx[RT];
+                gram_matvec<RT>(xs, Gs, GS, r, p, dx);
+#pragma unroll
+                for (int t = 0; t < RT; ++t) {
+                    const int k = 16 * t + p;
+                    if (k < r) part += xs[t] * (dx[t] - 2.0 * Cs[jj * CS + k]);
                 }
             }
         }
-        __syncthreads();
-        double part_db = 0.0;
-        const auto bout = to_global(J.Bp) + (int64_t)tile * RPAD * RPAD;
-        for (int e = tid; e < RPAD * RPAD; e += 256) {
-            const int a = e / RPAD, b = e % RPAD;
-            if (a <= b) {
-                double s = 0.0;
-#pragma unroll
-                for (int jj = 0; jj < 16; ++jj) s = fma(Wn[jj * CS + a], Wn[jj * CS + b], s);
-                bout[a * RPAD + b] = s;
-                if constexpr (UPD) part_db += (a == b ? 1.0 : 2.0) * Gs[a * GS + b] * s;
-            }
-        }
         if constexpr (UPD) {
-            const double tot = block_sum_f64<256>(part_db - 2.0 * part_cw, red);
+            const double tot = block_sum_f64<256>(part, red);
             if (tid == 0) to_global(J.rparts)[tile] = tot;
         }
     }
@@ -913,10 +1012,9 @@ size_t apass_lds_bytes(int rpad, int tm, int mode) {
 
 size_t cfinal_lds_bytes(int rpad, int mode) {
     const bool upd = mode == MODE_HALS || mode == MODE_MU;
-    const size_t g = upd ? (size_t)rpad * (rpad + 1) + rpad : 0;     // Gram and 1/G_kk
-    const size_t c = mode == MODE_INIT ? 0 : 16 * (size_t)(rpad + 1);  // C rows
-    const size_t w = mode == MODE_STORE ? 0 : 16 * (size_t)(rpad + 1); // new W rows
-    return sizeof(double) * (g + c + w + 4);
+    const size_t g = upd ? (size_t)rpad * (rpad + 1) + rpad : 0;           // Gram and 1/G_kk
+    const size_t c = mode == MODE_INIT ? 0 : kCfCols * (size_t)(rpad + 1);  // C columns
+    return sizeof(double) * (g + c + 4);
 }
 
 // Tile configurations of the A-pass, by rank class and rows per tile: 16-row
@@ -990,10 +1088,16 @@ hipError_t launch_cpass_jobs(int rpad, const Job *jobs, const int2 *bmap, int bl
     return hipGetLastError();
 }
 
-hipError_t launch_reduce_jobs(int which, const Job *jobs, const int2 *bmap, int blocks,
+hipError_t launch_reduce_jobs(const Job *jobs, const int2 *bmap, int blocks, hipStream_t s) {
+    if (blocks <= 0) return hipSuccess;
+    k_reduce<<<blocks, 256, 0, s>>>(jobs, bmap);
+    return hipGetLastError();
+}
+
+hipError_t launch_gram_w_jobs(int with_resid, const Job *jobs, const int2 *bmap, int blocks,
                               hipStream_t s) {
     if (blocks <= 0) return hipSuccess;
-    k_reduce<<<blocks, 256, 0, s>>>(jobs, bmap, which);
+    k_gram_w<<<blocks, 64 * kGramWWaves, 0, s>>>(jobs, bmap, with_resid);
     return hipGetLastError();
 }
 
@@ -1035,7 +1139,7 @@ hipError_t launch_residual(const double *rparts, int nparts, const double *Dd, c
     return hipGetLastError();
 }
 
-int cpass_final_blocks(int64_t n) { return (int)((n + 15) / 16); }
+int cpass_final_blocks(int64_t n) { return (int)((n + kCfCols - 1) / kCfCols); }
 
 int apass_grid_single(int nA) { return 8 * ((nA + 7) / 8); }
 

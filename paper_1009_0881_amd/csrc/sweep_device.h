@@ -25,6 +25,9 @@ __device__ __forceinline__ uint16_t bf16_rne(float x) {
 
 constexpr int MODE_HALS = 0, MODE_MU = 1, MODE_STORE = 2, MODE_INIT = 3;
 
+// Prefetch distance (in HALS steps) of the Gram rows in row_update.
+constexpr int kGramAhead = 2;
+
 template <int N, int I = 0, class F>
 __device__ __forceinline__ void static_for(F &&f) {
     if constexpr (I < N) {
@@ -65,6 +68,30 @@ __device__ __forceinline__ int ordered_after(int v, T dep) {
     return v;
 }
 
+// acc[t] = sum_l x_l G[l][16t + p] for a factor row held by a row of 16 lanes
+// (lane p holding entries 16t + p) and the r x r Gram G in LDS (row stride
+// gs, zero-padded).  Padded entries (l >= r) are zero and skipped in whole
+// groups of 4.
+template <int RT, class T>
+__device__ __forceinline__ void gram_matvec(const T (&x)[RT], const T *G, int gs, int r, int p,
+                                            T (&acc)[RT]) {
+    constexpr int RPAD = 16 * RT;
+#pragma unroll
+    for (int t = 0; t < RT; ++t) acc[t] = T(0);
+    static_for<RPAD / 4>([&](auto lg_c) {
+        constexpr int lg = decltype(lg_c)::value;
+        if (4 * lg < r) {
+            static_for<4>([&](auto lq_c) {
+                constexpr int l = 4 * lg + decltype(lq_c)::value;
+                const T xl = row_bcast<l % 16>(x[l / 16]);
+                const T *gr = G + l * gs + p;
+#pragma unroll
+                for (int t = 0; t < RT; ++t) acc[t] = fma_t(xl, gr[16 * t], acc[t]);
+            });
+        }
+    });
+}
+
 // HALS / MU update of one factor row held by a row of 16 lanes, lane p
 // holding entries k = 16t + p.  G is the r x r FP64 Gram of the other factor
 // in LDS (row stride gs, zero-padded to RPAD), gi[k] = 1/G_kk (0 when
@@ -84,45 +111,35 @@ template <int RT, int MODE, class T = double>
 __device__ __forceinline__ void row_update(T (&x)[RT], const T *G, int gs, const T *gi,
                                            const T (&a)[RT], int r, int p) {
     constexpr int RPAD = 16 * RT;
+    // acc_k = sum_l x_l G_lk; the HALS loop then runs over the RPAD entries
+    // with the padded ones (x_k = 0, zero Gram rows, 1/G_kk = 0) skipped.
     T acc[RT];
-#pragma unroll
-    for (int t = 0; t < RT; ++t) acc[t] = T(0);
-    // acc_k = sum_l x_l G_lk.  Padded entries (k >= r) have x_k = 0, zero Gram
-    // rows and 1/G_kk = 0: the mat-vec skips whole groups of 4 of them, the
-    // HALS loop runs over all RPAD entries with no runtime bound.
-    static_for<RPAD / 4>([&](auto lg_c) {
-        constexpr int lg = decltype(lg_c)::value;
-        if (4 * lg < r) {
-            static_for<4>([&](auto lq_c) {
-                constexpr int l = 4 * lg + decltype(lq_c)::value;
-                const T xl = row_bcast<l % 16>(x[l / 16]);
-                const T *gr = G + l * gs + p;
-#pragma unroll
-                for (int t = 0; t < RT; ++t) acc[t] = fma_t(xl, gr[16 * t], acc[t]);
-            });
-        }
-    });
+    gram_matvec<RT>(x, G, gs, r, p, acc);
     if constexpr (MODE == MODE_HALS) {
-        T g[RT], ginv[RT], row0[RT], row1[RT];
+        // Gram rows ahead of step k: rows[i] holds row k + i.  Step k loads
+        // row k + PD behind ordered_after() on the previous step's broadcast,
+        // so loads run PD steps ahead (hiding LDS latency) and the compiler
+        // cannot hoist all of them (and spill).  Steps k >= r change nothing
+        // (padded entries) and are skipped: each step runs the next one only
+        // while k + 1 < r, a nest of uniform branches.
+        constexpr int PD = kGramAhead < RPAD ? kGramAhead : RPAD;
+        T g[RT], ginv[RT], rows[PD][RT];
 #pragma unroll
         for (int t = 0; t < RT; ++t) {
             const int k = 16 * t + p;
             g[t] = k < r ? a[t] - acc[t] : T(0);
             ginv[t] = gi[k];
-            row0[t] = G[k];                  // Gram row 0
-            row1[t] = G[gs + k];             // Gram row 1
-        }
-        // Each step loads the Gram row of step k+2 behind ordered_after() on
-        // the previous step's broadcast: loads run two steps ahead, hiding LDS
-        // latency, and the compiler cannot hoist all of them (and spill).
-        T dprev = acc[0];
-        static_for<RPAD>([&](auto k_c) {
-            constexpr int k = decltype(k_c)::value, kt = k / 16, pk = k % 16;
-            T row2[RT];
-            if constexpr (k + 2 < RPAD) {
-                const T *gr = G + ordered_after((k + 2) * gs + p, dprev);
 #pragma unroll
-                for (int t = (k + 2) / 16; t < RT; ++t) row2[t] = gr[16 * t];
+            for (int i = 0; i < PD; ++i) rows[i][t] = G[i * gs + k];
+        }
+        T dprev = acc[0];
+        auto step = [&](auto self, auto k_c) -> void {
+            constexpr int k = decltype(k_c)::value, kt = k / 16, pk = k % 16;
+            T rnew[RT];
+            if constexpr (k + PD < RPAD) {
+                const T *gr = G + ordered_after((k + PD) * gs + p, dprev);
+#pragma unroll
+                for (int t = (k + PD) / 16; t < RT; ++t) rnew[t] = gr[16 * t];
             }
             const bool own = p == pk && ginv[kt] > T(0);
             const T c0 = fma_t(g[kt], ginv[kt], x[kt]);
@@ -131,15 +148,20 @@ __device__ __forceinline__ void row_update(T (&x)[RT], const T *G, int gs, const
             x[kt] = own ? cand : x[kt];
             d = row_bcast<pk>(d);
             dprev = d;
-            g[kt] = p > pk ? fma_t(-d, row0[kt], g[kt]) : g[kt];
+            g[kt] = p > pk ? fma_t(-d, rows[0][kt], g[kt]) : g[kt];
 #pragma unroll
-            for (int t = kt + 1; t < RT; ++t) g[t] = fma_t(-d, row0[t], g[t]);
+            for (int t = kt + 1; t < RT; ++t) g[t] = fma_t(-d, rows[0][t], g[t]);
 #pragma unroll
             for (int t = (k + 1) / 16; t < RT; ++t) {
-                row0[t] = row1[t];
-                if constexpr (k + 2 < RPAD) row1[t] = row2[t];
+#pragma unroll
+                for (int i = 0; i + 1 < PD; ++i) rows[i][t] = rows[i + 1][t];
+                if constexpr (k + PD < RPAD) rows[PD - 1][t] = rnew[t];
             }
-        });
+            if constexpr (k + 1 < RPAD) {
+                if (k + 1 < r) self(self, std::integral_constant<int, k + 1>{});
+            }
+        };
+        if (r > 0) step(step, std::integral_constant<int, 0>{});
     } else {
 #pragma unroll
         for (int t = 0; t < RT; ++t) {
@@ -150,46 +172,78 @@ __device__ __forceinline__ void row_update(T (&x)[RT], const T *G, int gs, const
 }
 
 // Load an r x r FP64 Gram (row-major, stride r) into LDS zero-padded to
-// RPAD x RPAD (stride gs), and its inverse diagonal.
+// RPAD x RPAD (stride gs), and its inverse diagonal.  Blocks of 256 threads:
+// every thread issues all of its loads before its first store, so the block
+// waits for one memory latency.
 template <int RPAD, class T = double>
 __device__ __forceinline__ void load_gram(const double *__restrict__ Gd, int r, T *Gs, int gs,
                                           T *gi) {
+    constexpr int PER = (RPAD * RPAD + 255) / 256;
     const auto G = to_global(Gd);
-    for (int e = threadIdx.x; e < RPAD * RPAD; e += blockDim.x) {
-        const int a = e / RPAD, b = e % RPAD;
-        Gs[a * gs + b] = (a < r && b < r) ? (T)G[a * r + b] : T(0);
+    const int tid = threadIdx.x;
+    double v[PER];
+#pragma unroll
+    for (int i = 0; i < PER; ++i) {
+        const int e = tid + 256 * i, a = e / RPAD, b = e % RPAD;
+        v[i] = (e < RPAD * RPAD && a < r && b < r) ? G[a * r + b] : 0.0;
     }
-    for (int k = threadIdx.x; k < RPAD; k += blockDim.x) {
-        const double g = (k < r) ? G[k * r + k] : 0.0;
-        gi[k] = g > 0.0 ? (T)(1.0 / g) : T(0);
+    const double g = (tid < r) ? G[tid * r + tid] : 0.0;
+#pragma unroll
+    for (int i = 0; i < PER; ++i) {
+        const int e = tid + 256 * i, a = e / RPAD, b = e % RPAD;
+        if (e < RPAD * RPAD) Gs[a * gs + b] = (T)v[i];
     }
+    if (tid < RPAD) gi[tid] = g > 0.0 ? (T)(1.0 / g) : T(0);
 }
 
-// Sum of `count` FP64 values p0[0], p0[stride], ... in index order, with up
-// to 16 loads in flight.
-__device__ __forceinline__ double sum_strided(const double *__restrict__ pg, int64_t stride,
+// Sum of `count` values p0[0], p0[stride], ... (FP64 or FP32) in FP64, in
+// index order, with up to W loads in flight.
+template <int W = 16, class T = double>
+__device__ __forceinline__ double sum_strided(const T *__restrict__ pg, int64_t stride,
                                               int count) {
     const auto p0 = to_global(pg);
     double s = 0.0;
     int p = 0;
-    for (; p + 16 <= count; p += 16) {
-        double t[16];
+    for (; p + W <= count; p += W) {
+        double t[W];
 #pragma unroll
-        for (int u = 0; u < 16; ++u) t[u] = p0[(p + u) * stride];
+        for (int u = 0; u < W; ++u) t[u] = (double)p0[(p + u) * stride];
 #pragma unroll
-        for (int u = 0; u < 16; ++u) s += t[u];
+        for (int u = 0; u < W; ++u) s += t[u];
     }
-    for (; p + 4 <= count; p += 4) {
-        double t[4];
+    if (p < count) {   // the rest in one batch
+        double t[W];
 #pragma unroll
-        for (int u = 0; u < 4; ++u) t[u] = p0[(p + u) * stride];
+        for (int u = 0; u < W; ++u) t[u] = (p + u < count) ? (double)p0[(p + u) * stride] : 0.0;
 #pragma unroll
-        for (int u = 0; u < 4; ++u) s += t[u];
+        for (int u = 0; u < W; ++u)
+            if (p + u < count) s += t[u];
     }
-    for (; p < count; ++p) s += p0[p * stride];
     return s;
 }
 
+// Sums of `count` FP64 values for N outputs at once: out[e] = sum over
+// p = 0..count-1 of pg[e][p * stride] in index order (pg[e] null: 0).  The
+// loads of all N outputs go out together in batches of B chunks.
+template <int N, int B = 16>
+__device__ __forceinline__ void sum_strided_n(const double *const (&pg)[N], int64_t stride,
+                                              int count, double (&out)[N]) {
+#pragma unroll
+    for (int e = 0; e < N; ++e) out[e] = 0.0;
+    for (int p = 0; p < count; p += B) {
+        double t[N][B];
+#pragma unroll
+        for (int e = 0; e < N; ++e)
+#pragma unroll
+            for (int u = 0; u < B; ++u)
+                t[e][u] = (pg[e] && p + u < count) ? to_global(pg[e])[(int64_t)(p + u) * stride] : 0.0;
+#pragma unroll
+        for (int e = 0; e < N; ++e)
+#pragma unroll
+            for (int u = 0; u < B; ++u)
+                if (p + u < count) out[e] += t[e][u];
+    }
+}
 
 }  // namespace
 
