@@ -38,25 +38,31 @@ PEAK_BF16_MFMA_TFLOPS = 2500.0  # MI355X dense BF16 matrix
 
 EXTRA_WORKLOADS = ("batch", "serve")
 
-# HBM traffic per launch (bytes) of the sweep kernels on the orl workload, by
+# HBM traffic per launch (bytes) of the sweep kernels, by (workload, precision),
 # kernel kind and level size m: rocprofv3 --pmc FETCH_SIZE and WRITE_SIZE
 # passes (KiB per dispatch), scaled by what the same counters read for a
-# 256 MiB device-to-device copy (FETCH_SIZE x2.0, WRITE_SIZE x1.0).  Valid
-# for the kernel sources whose SHA-256 prefix is `sha`; null otherwise.
+# 256 MiB device-to-device copy (FETCH_SIZE x2.0, WRITE_SIZE x1.0).  An entry
+# holds while the SHA-256 prefix of the kernel sources its kernels come from
+# is `sha`; traffic is null otherwise.
+SWEEP_SOURCES = ("sweep.hip", "sweep_device.h", "device_common.h", "job.h")
+STREAM_SOURCES = SWEEP_SOURCES + ("stream.hip",)
 TRAFFIC = {
-    "sha": "9da6defdf0f648f3",
-    "orl": {
-        "apass": {10304: 19991708, 2576: 6153662, 644: 2448532},
-        "cpass_partial": {10304: 22283722, 2576: 10276575, 644: 3420448},
-        "cpass_final": {10304: 5205462, 2576: 5080136, 644: 2263395},
+    ("orl", "fp32"): {
+        "sha": "ba12d811c8d72a7f",
+        "files": SWEEP_SOURCES,
+        "apass": {10304: 20016958, 2576: 6178816, 644: 2470272},
+        "cpass_partial": {10304: 21944398, 2576: 8346880, 644: 3493376},
+        "cpass_final": {10304: 5189266, 2576: 3910784, 644: 2630784},
+        "gram_v": {10304: 460190, 2576: 346880, 644: 234240},
+        "gram_w": {10304: 298269, 2576: 311392, 644: 311392},
     },
 }
 
 
-def kernel_sources_sha() -> str:
+def kernel_sources_sha(files) -> str:
     import hashlib
     h = hashlib.sha256()
-    for f in ("sweep.hip", "job.h"):
+    for f in files:
         with open(os.path.join(ROOT, "paper_1009_0881_amd", "csrc", f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]
@@ -388,9 +394,10 @@ def main() -> int:
         tot_bytes += b
         tot_flops += f
     traffic = None
-    tab = TRAFFIC.get(args.workload, {}).get(dominant)
-    if (tab and kernel_sources_sha() == TRAFFIC["sha"] and levels == wl["levels"]
-            and args.prec == "fp32"):
+    entry = TRAFFIC.get((args.workload, args.prec))
+    tab = entry.get(dominant) if entry else None
+    if (tab and kernel_sources_sha(entry["files"]) == entry["sha"] and levels == wl["levels"]
+            and args.refine == entry.get("refine", args.refine)):
         ms_ = [sides[d][0] * sides[d][1] for d in dep_log]
         if all(m_ in tab for m_ in ms_):
             traffic = int(sum(tab[m_] for m_ in ms_) / max(1, len(ms_)))

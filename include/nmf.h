@@ -61,6 +61,7 @@ enum { NMF_XFER_FW = 0, NMF_XFER_BLOCK2 = 1 };
  * an extra bf16 copy of every level of M in the workspace and accumulates in
  * FP32; Grams, updates and residuals stay FP32/FP64 as in FP32 mode. */
 enum { NMF_FP32 = 0, NMF_BF16 = 1 };
+#define NMF_TILE(wc, cf) ((int32_t)(wc) | ((int32_t)(cf) << 8))   /* nmf_desc.tile_cfg */
 
 typedef struct {
     int64_t m, n;          /* M is m x n; m must equal h*w                          */
@@ -79,7 +80,14 @@ typedef struct {
                               many continuation iterations (0 = 8)                  */
     int32_t log_cap;       /* capacity of the per-iteration rel_err log (0 = 4096)  */
     int32_t check_input;   /* 1: scan M for negative / non-finite entries first    */
-    int32_t reserved;
+    int32_t tile_cfg;      /* tile shapes of the C-pass and W-update kernels: 0 = the
+                              library's choice (latency tiles when m >= 8192, throughput
+                              tiles below), else NMF_TILE(wc, cf): wc in {1, 2, 4} C-pass
+                              row groups per tile, cf in {4, 16} W-update columns per
+                              tile.  Single and batched solves of one plan run the same
+                              tiles, hence the same arithmetic; plans with different
+                              tiles agree to rounding (the C-pass sum order depends on
+                              wc).  Chosen by paper_1009_0881_amd.tune for a workload. */
     double tol;            /* > 0: stop after the first finest-level iteration with
                               rel_err <= tol (absolute threshold on rel_err)        */
 } nmf_desc;

@@ -134,6 +134,9 @@ Ctx make_ctx(nmf_plan_t plan, const float *dM, float *dV, float *dW, void *dws, 
         J.nCx = (int32_t)((p.d.n + 63) / 64);
         J.nC = J.nCx * li.cp_chunks;
         J.nF = cpass_final_blocks(p.d.n);
+        J.wc = p.wc;
+        J.cf = p.cf;
+        J.nFb = cfinal_tile_blocks(p.d.n, p.cf);
         J.nG = gram_tiles(p.rpad);
         J.depth = (int32_t)l;
         J.log_cap = p.d.log_cap;
@@ -270,8 +273,8 @@ nmf_status gram_W(Ctx &c) {
 nmf_status init_w(Ctx &c) {
     nmf_plan_t plan = c.plan;
     const Job &J = c.jobs[0];
-    NMF_LAUNCH(K_GRAM_W, launch_cfinal_jobs(3, J.rpad, c.djobs, nullptr, J.nF,
-                                            cfinal_lds_bytes(J.rpad, 3), c.s));
+    NMF_LAUNCH(K_GRAM_W, launch_cfinal_jobs(3, J.rpad, J.cf, c.djobs, nullptr, J.nFb,
+                                            cfinal_lds_bytes(J.rpad, 3, J.cf), c.s));
     NMF_LAUNCH(K_GRAM_W, launch_gram_w_jobs(0, c.djobs, nullptr, J.nG, c.s));
     return NMF_OK;
 }
@@ -306,11 +309,11 @@ nmf_status sweep(Ctx &c, int d, bool fp32 = false) {
         NMF_LAUNCH(K_CPART, launch_cpass_s32(J.rpad, dj, nullptr,
                                              cpass_stream_grid(J.nCx, J.chunks), c.s));
     else
-        NMF_LAUNCH(K_CPART, launch_cpass_jobs(J.rpad, dj, nullptr,
+        NMF_LAUNCH(K_CPART, launch_cpass_jobs(J.rpad, J.wc, dj, nullptr,
                                               cpass_grid_single(J.nCx, J.chunks), c.s, bf));
     NMF_LAUNCH(K_GRAM_V, launch_reduce_jobs(dj, nullptr, J.nG, c.s));
-    NMF_LAUNCH(K_CFINAL, launch_cfinal_jobs(mode, J.rpad, dj, nullptr, J.nF,
-                                            cfinal_lds_bytes(J.rpad, mode), c.s));
+    NMF_LAUNCH(K_CFINAL, launch_cfinal_jobs(mode, J.rpad, J.cf, dj, nullptr, J.nFb,
+                                            cfinal_lds_bytes(J.rpad, mode, J.cf), c.s));
     if (mode == 2) {
         NMF_LAUNCH(K_NNLS_COLS, launch_nnls_cols(p.rpad, c.Dd, c.C, n, r, c.W, c.Wt, c.rparts,
                                                  flags, c.stop, c.s));
@@ -600,8 +603,10 @@ nmf_status nmf_products(nmf_plan_t plan, const float *dM, const float *dV, const
     if (st != NMF_OK) return st;
     NMF_HIP(launch_apass_jobs(2, J.rpad, J.tm, c.djobs, nullptr, apass_grid_single(J.nA),
                               apass_lds_bytes(J.rpad, J.tm, 2), s));
-    NMF_HIP(launch_cpass_jobs(J.rpad, c.djobs, nullptr, cpass_grid_single(J.nCx, J.chunks), s));
-    NMF_HIP(launch_cfinal_jobs(2, J.rpad, c.djobs, nullptr, J.nF, cfinal_lds_bytes(J.rpad, 2), s));
+    NMF_HIP(launch_cpass_jobs(J.rpad, J.wc, c.djobs, nullptr, cpass_grid_single(J.nCx, J.chunks),
+                              s));
+    NMF_HIP(launch_cfinal_jobs(2, J.rpad, J.cf, c.djobs, nullptr, J.nFb,
+                               cfinal_lds_bytes(J.rpad, 2, J.cf), s));
     NMF_HIP(hipStreamSynchronize(s));
     return NMF_OK;
 }

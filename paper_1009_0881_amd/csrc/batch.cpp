@@ -211,14 +211,15 @@ nmf_status Executor::setup_fresh() {
         if (I->bf16 && (st = prepare_bf16(I->c)) != NMF_OK) return st;
     // Wt and B = W W^T: W tile kernel in init mode, then the B-only reduce,
     // grouped by rank class
-    std::map<int, std::vector<Inst *>> by_rpad;
-    for (Inst *I : F) by_rpad[I->c.p->rpad].push_back(I);
+    std::map<std::pair<int, int>, std::vector<Inst *>> by_rpad;
+    for (Inst *I : F) by_rpad[{I->c.p->rpad, I->c.p->cf}].push_back(I);
     for (auto &kv : by_rpad) {
+        const int rpad = kv.first.first, cf = kv.first.second;
         std::vector<Job> jobs;
         std::vector<int2> bF, bG;
         for (Inst *I : kv.second) {
             const Job &J = I->c.jobs[0];
-            for (int k = 0; k < J.nF; ++k) bF.push_back(make_int2((int)jobs.size(), k));
+            for (int k = 0; k < J.nFb; ++k) bF.push_back(make_int2((int)jobs.size(), k));
             for (int k = 0; k < J.nG; ++k) bG.push_back(make_int2((int)jobs.size(), k));
             jobs.push_back(J);
         }
@@ -227,8 +228,8 @@ nmf_status Executor::setup_fresh() {
         if ((st = upload(jobs, &dj)) != NMF_OK || (st = upload(bF, &dF)) != NMF_OK ||
             (st = upload(bG, &dG)) != NMF_OK)
             return st;
-        NMF_HIP(launch_cfinal_jobs(3, kv.first, dj, dF, (int)bF.size(),
-                                   cfinal_lds_bytes(kv.first, 3), s_));
+        NMF_HIP(launch_cfinal_jobs(3, rpad, cf, dj, dF, (int)bF.size(),
+                                   cfinal_lds_bytes(rpad, 3, cf), s_));
         NMF_HIP(launch_gram_w_jobs(0, dj, dG, (int)bG.size(), s_));
     }
     return NMF_OK;
@@ -327,13 +328,13 @@ nmf_status Executor::launch_xfers(std::vector<std::pair<Inst *, std::vector<Step
 // the five phases of each group.
 nmf_status Executor::launch_sweeps(const std::vector<Inst *> &active, bool capture_ok) {
     nmf_plan_t plan = nullptr;
-    std::map<std::tuple<int, int, int, int>, std::vector<Inst *>> groups;
+    std::map<std::tuple<int, int, int, int, int, int>, std::vector<Inst *>> groups;
     auto job_of = [](const Inst *I) -> const Job & {
         return I->fp32job ? I->c.jobs.back() : I->c.jobs[I->depth];
     };
     for (Inst *I : active) {
         const Job &J = job_of(I);
-        groups[std::make_tuple(J.rpad, J.tm, I->mode, J.prec)].push_back(I);
+        groups[std::make_tuple(J.rpad, J.tm, I->mode, J.prec, J.wc, J.cf)].push_back(I);
     }
     std::vector<G> gl;
     std::vector<int64_t> key;
@@ -344,7 +345,9 @@ nmf_status Executor::launch_sweeps(const std::vector<Inst *> &active, bool captu
         g.tm = std::get<1>(kv.first);
         g.mode = std::get<2>(kv.first);
         g.bf = std::get<3>(kv.first) == 1;
-        std::vector<int64_t> gkey{g.rpad, g.tm, g.mode, g.bf ? 1 : 0};
+        g.wc = std::get<4>(kv.first);
+        g.cf = std::get<5>(kv.first);
+        std::vector<int64_t> gkey{g.rpad, g.tm, g.mode, g.bf ? 1 : 0, g.wc, g.cf};
         for (Inst *I : kv.second) {
             gkey.push_back(I->id);
             gkey.push_back(I->fp32job ? -1 : I->depth);
@@ -362,7 +365,7 @@ nmf_status Executor::launch_sweeps(const std::vector<Inst *> &active, bool captu
                 for (int k = 0; k < J.nA; ++k) bA.push_back(make_int2(j, k));
                 for (int k = 0; k < J.nC; ++k) bC.push_back(make_int2(j, k));
                 for (int k = 0; k < J.nG; ++k) bG.push_back(make_int2(j, k));
-                for (int k = 0; k < J.nF; ++k) bF.push_back(make_int2(j, k));
+                for (int k = 0; k < J.nFb; ++k) bF.push_back(make_int2(j, k));
                 jobs.push_back(J);
             }
             if ((st = upload(jobs, &g.dj)) != NMF_OK || (st = upload(bA, &g.bA)) != NMF_OK ||
@@ -381,10 +384,10 @@ nmf_status Executor::launch_sweeps(const std::vector<Inst *> &active, bool captu
         for (const G &g : gl) {
             NMF_HIP(launch_apass_jobs(g.mode, g.rpad, g.tm, g.dj, g.bA, g.nA,
                                       apass_lds_bytes(g.rpad, g.tm, g.mode), s_, g.bf));
-            NMF_HIP(launch_cpass_jobs(g.rpad, g.dj, g.bC, g.nC, s_, g.bf));
+            NMF_HIP(launch_cpass_jobs(g.rpad, g.wc, g.dj, g.bC, g.nC, s_, g.bf));
             NMF_HIP(launch_reduce_jobs(g.dj, g.bG, g.nG, s_));
-            NMF_HIP(launch_cfinal_jobs(g.mode, g.rpad, g.dj, g.bF, g.nF,
-                                       cfinal_lds_bytes(g.rpad, g.mode), s_));
+            NMF_HIP(launch_cfinal_jobs(g.mode, g.rpad, g.cf, g.dj, g.bF, g.nF,
+                                       cfinal_lds_bytes(g.rpad, g.mode, g.cf), s_));
             NMF_HIP(launch_gram_w_jobs(1, g.dj, g.bG, g.nG, s_));
         }
         return NMF_OK;

@@ -65,7 +65,7 @@ private:
         bool fp32job = false; // this tick's sweep uses the FP32 finest-level job
     };
     struct G {
-        int rpad, tm, mode;
+        int rpad, tm, mode, wc, cf;
         bool bf;
         const Job *dj;
         const int2 *bA, *bC, *bG, *bF;

@@ -21,6 +21,8 @@ struct Job {
     int32_t nA, nC, nF, nG;   // tiles of: A-pass, C-pass (nCx * chunks), W update (4
                               // columns each), Gram kernels (upper 16x16 tiles)
     int32_t nCx;         // 64-column tiles of the C-pass
+    int32_t wc, cf;      // C-pass row groups per tile; W-update columns per tile
+    int32_t nFb;         // W-update blocks (n / cf; nF counts its 4-column partials)
     int32_t depth, log_cap;
     float *V;            // level factor, m x r column-major
     float *W;            // r x n row-major

@@ -97,6 +97,7 @@ struct Plan {
     std::vector<LevelInfo> lv;
     Workspace ws;
     int rpad;            // r rounded up to a multiple of 16
+    int wc, cf;          // tiles: C-pass row groups per tile, W-update columns per tile
     int num_cu;
     int32_t gram_w_parts;
     int64_t gram_w_chunk;
@@ -141,14 +142,14 @@ hipError_t launch_gram(int rpad, int r, int64_t L, const float *X, int64_t ldx, 
 // bf: BF16 operand copies (job.h) on v_mfma_f32_16x16x32_bf16 (HALS / MU only).
 hipError_t launch_apass_jobs(int mode, int rpad, int tm, const Job *jobs, const int2 *bmap,
                              int blocks, size_t lds, hipStream_t s, bool bf = false);
-hipError_t launch_cpass_jobs(int rpad, const Job *jobs, const int2 *bmap, int blocks,
+hipError_t launch_cpass_jobs(int rpad, int wc, const Job *jobs, const int2 *bmap, int blocks,
                              hipStream_t s, bool bf = false);
 // which = 0: V^T V from the C-pass partials; 1: W W^T and the residual log;
 // 2: W W^T only.
 // D = V^T V from the C-pass partials, one block per upper tile (gram_tiles).
 hipError_t launch_reduce_jobs(const Job *jobs, const int2 *bmap, int blocks, hipStream_t s);
-hipError_t launch_cfinal_jobs(int mode, int rpad, const Job *jobs, const int2 *bmap, int blocks,
-                              size_t lds, hipStream_t s);
+hipError_t launch_cfinal_jobs(int mode, int rpad, int cf, const Job *jobs, const int2 *bmap,
+                              int blocks, size_t lds, hipStream_t s);
 
 // Grouped setup kernels for batches (one launch over many problems).
 struct XferJob {             // restrict (kind 1) or prolong (kind 2) of ncols images
@@ -179,8 +180,9 @@ hipError_t launch_gather_states(DevState *const *states, int count, DevState *ou
                                 hipStream_t s);
 int apass_rows_per_block(int64_t m);
 size_t apass_lds_bytes(int rpad, int tm, int mode);
-size_t cfinal_lds_bytes(int rpad, int mode);
-int cpass_final_blocks(int64_t n);   // W-update tiles of 4 columns
+size_t cfinal_lds_bytes(int rpad, int mode, int cf);
+int cpass_final_blocks(int64_t n);   // W-update residual partials (one per 4 columns)
+int cfinal_tile_blocks(int64_t n, int cf);   // W-update blocks of cf columns
 // Upper-triangle 16x16 tiles of an rpad x rpad Gram: blocks of the Gram
 // reduction (D) and of the B = W W^T kernel.
 inline int gram_tiles(int rpad) { return (rpad / 16) * (rpad / 16 + 1) / 2; }

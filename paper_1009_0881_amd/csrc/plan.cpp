@@ -113,6 +113,21 @@ nmf_status build_plan(const nmf_desc &d0, Plan &p, std::string &err) {
     }
     p.d = d;
     p.rpad = (d.r + 15) / 16 * 16;
+    // Tile shapes: latency tiles (row-split C-pass, narrow W-update tiles) for
+    // problems large enough to run alone, throughput tiles below.
+    if (d.tile_cfg == 0) {
+        const bool big = d.m >= 8192;
+        p.wc = big ? (p.rpad <= 32 ? 4 : 2) : 1;
+        p.cf = big ? 4 : 16;
+    } else {
+        p.wc = d.tile_cfg & 0xff;
+        p.cf = (d.tile_cfg >> 8) & 0xff;
+        if ((p.wc != 1 && p.wc != 2 && p.wc != 4) || (p.cf != 4 && p.cf != 16) ||
+            (d.tile_cfg >> 16) != 0) {
+            err = "tile_cfg must be 0 or NMF_TILE(wc, cf) with wc in {1, 2, 4}, cf in {4, 16}";
+            return NMF_E_ARG;
+        }
+    }
     p.lv.clear();
     int h = d.h, w = d.w;
     for (int l = 0; l < d.levels; ++l) {

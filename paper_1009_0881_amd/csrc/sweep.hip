@@ -845,22 +845,22 @@ __global__ __launch_bounds__(64 * kGramWWaves) void k_gram_w(const Job *__restri
 }
 
 // ---------------------------------------------------------------------------
-// W-update tile: 4 columns of W.  Each thread reduces one entry of those
-// columns of C from the C-pass partials (chunk-major, n x r per chunk: the
-// tile's entries are contiguous; fixed order, one batch of loads); then 16
-// lanes per column update it (HALS / MU against D) and write W, its
-// transposed copy Wt (and the BF16 copy).  Also emits the tile's residual
-// partial sum_j (w_j^T D w_j - 2 c_j^T w_j), j over its columns: the first
-// term is the tile's share of <D, B> (B = sum_j w_j w_j^T).
+// W-update tile: CF (4 or 16) columns of W.  The threads reduce the entries
+// of those columns of C from the C-pass partials (chunk-major, n x r per
+// chunk: the tile's entries are contiguous; fixed order, batched loads); then
+// 16 lanes per column update it (HALS / MU against D) and write W, its
+// transposed copy Wt (and the BF16 copy).  Also emits, per 4 columns (one
+// wave), the residual partial sum_j (w_j^T D w_j - 2 c_j^T w_j): the first
+// term is those columns' share of <D, B> (B = sum_j w_j w_j^T).  Every column
+// and every 4-column partial is computed the same way for both CF.
 // ---------------------------------------------------------------------------
-constexpr int kCfCols = 4;
-
-template <int RT, int MODE>
+template <int RT, int MODE, int CF>
 __device__ __forceinline__ void cfinal_tile(const Job &J, int tile, double *smem) {
-    constexpr int RPAD = RT * 16, GS = RPAD + 1, CS = RPAD + 1, CF = kCfCols;
+    constexpr int RPAD = RT * 16, GS = RPAD + 1, CS = RPAD + 1;
     constexpr bool UPD = MODE == MODE_HALS || MODE == MODE_MU;
     constexpr bool INIT = MODE == MODE_INIT;     // no C, no update: Wt (and Wb) only
-    static_assert(CF * RPAD <= 256, "one C entry per thread");
+    constexpr int PER = (CF * RPAD + 255) / 256;   // C entries per thread
+    static_assert(CF == 4 || CF == 16, "W-update tile width");
     double *Gs = smem;
     double *Gi = Gs + (UPD ? RPAD * GS : 0);
     double *Cs = Gi + (UPD ? RPAD : 0);
@@ -870,7 +870,7 @@ __device__ __forceinline__ void cfinal_tile(const Job &J, int tile, double *smem
     const int r = J.r;
     const int64_t j0 = (int64_t)tile * CF;
     // factor columns of the update: 16 lanes per column, column j0 + tid/16
-    // (wave 0)
+    // (all waves for CF = 16, wave 0 for CF = 4)
     const bool colt = tid < 16 * CF;
     double xw[RT];
     if constexpr (MODE != MODE_STORE) {
@@ -882,15 +882,33 @@ __device__ __forceinline__ void cfinal_tile(const Job &J, int tile, double *smem
         }
     }
     if constexpr (!INIT) {
-        const int jj = tid / RPAD, k = tid % RPAD;
-        const int64_t j = j0 + jj;
-        double s = 0.0;
-        if (jj < CF && k < r && j < n) {
-            const int64_t off = j * r + k, str = (int64_t)r * n;
-            s = J.prec ? sum_strided<64>(reinterpret_cast<const float *>(J.Cp) + off, str, J.chunks)
-                       : sum_strided<64>(J.Cp + off, str, J.chunks);
+        constexpr int B = CF == 4 ? 64 : 16;
+        const int64_t str = (int64_t)r * n;
+        double cs[PER];
+        int64_t off[PER];
+#pragma unroll
+        for (int i = 0; i < PER; ++i) {
+            const int e = tid + 256 * i, jj = e / RPAD, k = e % RPAD;
+            const int64_t j = j0 + jj;
+            off[i] = (jj < CF && k < r && j < n) ? j * r + k : -1;
         }
-        if (jj < CF) Cs[jj * CS + k] = s;
+        if (J.prec) {
+            const float *src[PER];
+#pragma unroll
+            for (int i = 0; i < PER; ++i)
+                src[i] = off[i] >= 0 ? reinterpret_cast<const float *>(J.Cp) + off[i] : nullptr;
+            sum_strided_n<PER, B>(src, str, J.chunks, cs);
+        } else {
+            const double *src[PER];
+#pragma unroll
+            for (int i = 0; i < PER; ++i) src[i] = off[i] >= 0 ? J.Cp + off[i] : nullptr;
+            sum_strided_n<PER, B>(src, str, J.chunks, cs);
+        }
+#pragma unroll
+        for (int i = 0; i < PER; ++i) {
+            const int e = tid + 256 * i, jj = e / RPAD, k = e % RPAD;
+            if (jj < CF) Cs[jj * CS + k] = cs[i];
+        }
     }
     if constexpr (UPD) load_gram<RPAD>(J.Dd, r, Gs, GS, Gi);
     if constexpr (!INIT) __syncthreads();
@@ -935,20 +953,24 @@ __device__ __forceinline__ void cfinal_tile(const Job &J, int tile, double *smem
             }
         }
         if constexpr (UPD) {
-            const double tot = block_sum_f64<256>(part, red);
-            if (tid == 0) to_global(J.rparts)[tile] = tot;
+            // one partial per 4 columns: the 64 lanes of one wave
+            if (colt) {
+                const double tot = wave_sum_f64(part);
+                const int64_t quad = j0 / 4 + (tid >> 6);
+                if ((tid & 63) == 0 && quad < J.nF) to_global(J.rparts)[quad] = tot;
+            }
         }
     }
 }
 
-template <int RT, int MODE>
+template <int RT, int MODE, int CF>
 __global__ __launch_bounds__(256) void k_cfinal(const Job *__restrict__ jobs,
                                                 const int2 *__restrict__ bmap) {
     extern __shared__ double smem[];
     const int2 jt = block_job(bmap);
     const Job &J = jobs[jt.x];
     if (J.st->stop) return;
-    cfinal_tile<RT, MODE>(J, jt.y, smem);
+    cfinal_tile<RT, MODE, CF>(J, jt.y, smem);
 }
 
 __global__ __launch_bounds__(256) void k_make_wt(const float *__restrict__ W, int64_t n, int r,
@@ -1010,10 +1032,10 @@ size_t apass_lds_bytes(int rpad, int tm, int mode) {
     return sizeof(double) * ((upd ? rpad * (rpad + 1) + rpad : 0) + 4 * 16 * rw * (rpad + 1));
 }
 
-size_t cfinal_lds_bytes(int rpad, int mode) {
+size_t cfinal_lds_bytes(int rpad, int mode, int cf) {
     const bool upd = mode == MODE_HALS || mode == MODE_MU;
-    const size_t g = upd ? (size_t)rpad * (rpad + 1) + rpad : 0;           // Gram and 1/G_kk
-    const size_t c = mode == MODE_INIT ? 0 : kCfCols * (size_t)(rpad + 1);  // C columns
+    const size_t g = upd ? (size_t)rpad * (rpad + 1) + rpad : 0;      // Gram and 1/G_kk
+    const size_t c = mode == MODE_INIT ? 0 : (size_t)cf * (rpad + 1);  // C columns
     return sizeof(double) * (g + c + 4);
 }
 
@@ -1058,31 +1080,40 @@ hipError_t launch_apass_jobs(int mode, int rpad, int tm, const Job *jobs, const 
     return hipGetLastError();
 }
 
-// C-pass configurations by rank class: WC column tiles (and row groups) per
-// wave -- 4 for r <= 32, 2 above (register budget of the FP32 TwoSum pairs) --
-// and SB 16-row steps per FP32 load batch.
+// C-pass configurations: WC column tiles (and row groups) per wave, from the
+// plan (1: one wave per column tile over the whole chunk, for throughput; 2
+// or 4: shorter per-wave chains, for latency), and SB 16-row steps per FP32
+// load batch by rank class.
 template <int RT>
 struct CpassCfg {
-    static constexpr int WC = RT <= 2 ? 4 : 2;
     static constexpr int SB = RT <= 2 ? 2 : 1;
 };
 
-template <int RT>
+template <int RT, int WC>
 static void cpass_launch(bool bf, const Job *jobs, const int2 *bmap, int blocks, hipStream_t s) {
-    constexpr int WC = CpassCfg<RT>::WC, SB = CpassCfg<RT>::SB;
+    constexpr int SB = CpassCfg<RT>::SB;
     const size_t lds = sizeof(double) * cpass_lds_doubles<RT, WC>();
     if (bf) k_cpass<RT, WC, SB, true><<<blocks, 256, lds, s>>>(jobs, bmap);
     else k_cpass<RT, WC, SB, false><<<blocks, 256, lds, s>>>(jobs, bmap);
 }
 
-hipError_t launch_cpass_jobs(int rpad, const Job *jobs, const int2 *bmap, int blocks,
+template <int RT>
+static void cpass_launch_wc(int wc, bool bf, const Job *jobs, const int2 *bmap, int blocks,
+                            hipStream_t s) {
+    if (wc == 4) cpass_launch<RT, 4>(bf, jobs, bmap, blocks, s);
+    else if (wc == 2) cpass_launch<RT, 2>(bf, jobs, bmap, blocks, s);
+    else cpass_launch<RT, 1>(bf, jobs, bmap, blocks, s);
+}
+
+hipError_t launch_cpass_jobs(int rpad, int wc, const Job *jobs, const int2 *bmap, int blocks,
                              hipStream_t s, bool bf) {
     if (blocks <= 0) return hipSuccess;
+    if (wc != 1 && wc != 2 && wc != 4) return hipErrorInvalidValue;
     switch (rpad) {
-        case 16: cpass_launch<1>(bf, jobs, bmap, blocks, s); break;
-        case 32: cpass_launch<2>(bf, jobs, bmap, blocks, s); break;
-        case 48: cpass_launch<3>(bf, jobs, bmap, blocks, s); break;
-        case 64: cpass_launch<4>(bf, jobs, bmap, blocks, s); break;
+        case 16: cpass_launch_wc<1>(wc, bf, jobs, bmap, blocks, s); break;
+        case 32: cpass_launch_wc<2>(wc, bf, jobs, bmap, blocks, s); break;
+        case 48: cpass_launch_wc<3>(wc, bf, jobs, bmap, blocks, s); break;
+        case 64: cpass_launch_wc<4>(wc, bf, jobs, bmap, blocks, s); break;
         default: return hipErrorInvalidValue;
     }
     return hipGetLastError();
@@ -1101,23 +1132,31 @@ hipError_t launch_gram_w_jobs(int with_resid, const Job *jobs, const int2 *bmap,
     return hipGetLastError();
 }
 
-template <int RT>
+template <int RT, int CF>
 static void cfinal_launch(int mode, const Job *jobs, const int2 *bmap, int blocks,
                           size_t lds, hipStream_t s) {
-    if (mode == MODE_HALS) k_cfinal<RT, MODE_HALS><<<blocks, 256, lds, s>>>(jobs, bmap);
-    else if (mode == MODE_MU) k_cfinal<RT, MODE_MU><<<blocks, 256, lds, s>>>(jobs, bmap);
-    else if (mode == MODE_INIT) k_cfinal<RT, MODE_INIT><<<blocks, 256, lds, s>>>(jobs, bmap);
-    else k_cfinal<RT, MODE_STORE><<<blocks, 256, lds, s>>>(jobs, bmap);
+    if (mode == MODE_HALS) k_cfinal<RT, MODE_HALS, CF><<<blocks, 256, lds, s>>>(jobs, bmap);
+    else if (mode == MODE_MU) k_cfinal<RT, MODE_MU, CF><<<blocks, 256, lds, s>>>(jobs, bmap);
+    else if (mode == MODE_INIT) k_cfinal<RT, MODE_INIT, CF><<<blocks, 256, lds, s>>>(jobs, bmap);
+    else k_cfinal<RT, MODE_STORE, CF><<<blocks, 256, lds, s>>>(jobs, bmap);
 }
 
-hipError_t launch_cfinal_jobs(int mode, int rpad, const Job *jobs, const int2 *bmap,
+template <int RT>
+static void cfinal_launch_cf(int mode, int cf, const Job *jobs, const int2 *bmap, int blocks,
+                             size_t lds, hipStream_t s) {
+    if (cf == 16) cfinal_launch<RT, 16>(mode, jobs, bmap, blocks, lds, s);
+    else cfinal_launch<RT, 4>(mode, jobs, bmap, blocks, lds, s);
+}
+
+hipError_t launch_cfinal_jobs(int mode, int rpad, int cf, const Job *jobs, const int2 *bmap,
                               int blocks, size_t lds, hipStream_t s) {
     if (blocks <= 0) return hipSuccess;
+    if (cf != 4 && cf != 16) return hipErrorInvalidValue;
     switch (rpad) {
-        case 16: cfinal_launch<1>(mode, jobs, bmap, blocks, lds, s); break;
-        case 32: cfinal_launch<2>(mode, jobs, bmap, blocks, lds, s); break;
-        case 48: cfinal_launch<3>(mode, jobs, bmap, blocks, lds, s); break;
-        case 64: cfinal_launch<4>(mode, jobs, bmap, blocks, lds, s); break;
+        case 16: cfinal_launch_cf<1>(mode, cf, jobs, bmap, blocks, lds, s); break;
+        case 32: cfinal_launch_cf<2>(mode, cf, jobs, bmap, blocks, lds, s); break;
+        case 48: cfinal_launch_cf<3>(mode, cf, jobs, bmap, blocks, lds, s); break;
+        case 64: cfinal_launch_cf<4>(mode, cf, jobs, bmap, blocks, lds, s); break;
         default: return hipErrorInvalidValue;
     }
     return hipGetLastError();
@@ -1139,7 +1178,9 @@ hipError_t launch_residual(const double *rparts, int nparts, const double *Dd, c
     return hipGetLastError();
 }
 
-int cpass_final_blocks(int64_t n) { return (int)((n + kCfCols - 1) / kCfCols); }
+int cpass_final_blocks(int64_t n) { return (int)((n + 3) / 4); }
+
+int cfinal_tile_blocks(int64_t n, int cf) { return (int)((n + cf - 1) / cf); }
 
 int apass_grid_single(int nA) { return 8 * ((nA + 7) / 8); }
 
@@ -1163,9 +1204,13 @@ static void lds_attr(hipError_t &e) {
         set((const void *)k_apass<RT, 1, 4, S16, MODE, true>);
         set((const void *)k_apass<RT, 2, 2, S64, MODE, true>);
     }
-    set((const void *)k_cfinal<RT, MODE>);
-    set((const void *)k_cpass<RT, CpassCfg<RT>::WC, CpassCfg<RT>::SB, false>);
-    set((const void *)k_cpass<RT, CpassCfg<RT>::WC, CpassCfg<RT>::SB, true>);
+    set((const void *)k_cfinal<RT, MODE, 4>);
+    set((const void *)k_cfinal<RT, MODE, 16>);
+    constexpr int SB = CpassCfg<RT>::SB;
+    for (const void *f : {(const void *)k_cpass<RT, 1, SB, false>, (const void *)k_cpass<RT, 1, SB, true>,
+                          (const void *)k_cpass<RT, 2, SB, false>, (const void *)k_cpass<RT, 2, SB, true>,
+                          (const void *)k_cpass<RT, 4, SB, false>, (const void *)k_cpass<RT, 4, SB, true>})
+        set(f);
 }
 
 template <int RT>
@@ -1173,9 +1218,11 @@ static void lds_attr_modes(hipError_t &e) {
     lds_attr<RT, MODE_HALS>(e);
     lds_attr<RT, MODE_MU>(e);
     lds_attr<RT, MODE_STORE>(e);
-    hipError_t x = hipFuncSetAttribute((const void *)k_cfinal<RT, MODE_INIT>,
-                                       hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
-    if (x != hipSuccess && e == hipSuccess) e = x;
+    for (const void *f : {(const void *)k_cfinal<RT, MODE_INIT, 4>,
+                          (const void *)k_cfinal<RT, MODE_INIT, 16>}) {
+        hipError_t x = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
+        if (x != hipSuccess && e == hipSuccess) e = x;
+    }
 }
 
 hipError_t enable_large_lds() {

@@ -222,12 +222,12 @@ __device__ __forceinline__ double sum_strided(const T *__restrict__ pg, int64_t 
     return s;
 }
 
-// Sums of `count` FP64 values for N outputs at once: out[e] = sum over
-// p = 0..count-1 of pg[e][p * stride] in index order (pg[e] null: 0).  The
-// loads of all N outputs go out together in batches of B chunks.
-template <int N, int B = 16>
-__device__ __forceinline__ void sum_strided_n(const double *const (&pg)[N], int64_t stride,
-                                              int count, double (&out)[N]) {
+// Sums of `count` values (FP64 or FP32) for N outputs at once, in FP64:
+// out[e] = sum over p = 0..count-1 of pg[e][p * stride] in index order (pg[e]
+// null: 0).  The loads of all N outputs go out together in batches of B.
+template <int N, int B = 16, class T = double>
+__device__ __forceinline__ void sum_strided_n(const T *const (&pg)[N], int64_t stride, int count,
+                                              double (&out)[N]) {
 #pragma unroll
     for (int e = 0; e < N; ++e) out[e] = 0.0;
     for (int p = 0; p < count; p += B) {
@@ -236,7 +236,9 @@ __device__ __forceinline__ void sum_strided_n(const double *const (&pg)[N], int6
         for (int e = 0; e < N; ++e)
 #pragma unroll
             for (int u = 0; u < B; ++u)
-                t[e][u] = (pg[e] && p + u < count) ? to_global(pg[e])[(int64_t)(p + u) * stride] : 0.0;
+                t[e][u] = (pg[e] && p + u < count)
+                              ? (double)to_global(pg[e])[(int64_t)(p + u) * stride]
+                              : 0.0;
 #pragma unroll
         for (int e = 0; e < N; ++e)
 #pragma unroll

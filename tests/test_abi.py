@@ -49,6 +49,9 @@ def test_status_strings():
     (dict(m=256, n=40, h=16, w=16, r=20, levels=3, algo="anls"), -2),   # 4x4 level < r
     (dict(m=100, n=4, h=10, w=10, r=3, algo=7), -1),     # unknown algorithm
     (dict(m=100, n=0, h=10, w=10, r=3), -2),             # n < 1
+    (dict(m=100, n=4, h=10, w=10, r=3, tile_cfg=(3, 4)), -1),    # wc not in {1, 2, 4}
+    (dict(m=100, n=4, h=10, w=10, r=3, tile_cfg=(2, 8)), -1),    # cf not in {4, 16}
+    (dict(m=100, n=4, h=10, w=10, r=3, tile_cfg=(1 | 16 << 8 | 1 << 16)), -1),
 ])
 def test_plan_rejects_bad_descriptions(kw, status):
     with pytest.raises(P.NmfError) as e:
@@ -83,3 +86,22 @@ def test_workspace_grows_with_levels_and_algo():
     c = P.Plan(m=10304, n=400, h=112, w=92, r=40, levels=3, algo="anls").workspace_bytes
     assert 0 < a < b < c
     assert b % 256 == 0
+
+
+def test_plan_accepts_every_tile_candidate():
+    from paper_1009_0881_amd import tune
+    for wc, cf in tune.CANDIDATES:
+        pl = P.Plan(m=256, n=40, h=16, w=16, r=20, levels=2, tile_cfg=(wc, cf))
+        assert pl.desc.tile_cfg == P.tile(wc, cf) == (wc | cf << 8)
+
+
+def test_tune_cache_round_trip(tmp_path):
+    from paper_1009_0881_amd import tune
+    kw = dict(m=256, n=40, h=16, w=16, r=20, levels=2, algo="hals")
+    path = str(tmp_path / "tiles.json")
+    assert tune.choose(kw, "solve", path) == 0               # nothing tuned yet
+    tune.save_result(path, tune.shape_key(kw, "solve"),
+                     {"best": (2, 4), "tile_cfg": P.tile(2, 4), "ms": {"2,4": 1.0}})
+    assert tune.choose(kw, "solve", path) == P.tile(2, 4)
+    assert tune.choose(kw, "batch", path) == 0               # other context
+    assert tune.choose(dict(kw, r=21), "solve", path) == 0   # other shape class
