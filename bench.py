@@ -82,6 +82,18 @@ def level_sides(h, w, levels):
     return out
 
 
+def parse_tile(text):
+    """--tile "wc,cf" -> NMF_TILE value; empty -> 0 (library default)."""
+    if not text:
+        return 0
+    wc, cf = (int(x) for x in text.split(","))
+    return wc | (cf << 8)
+
+
+def tile_desc(tile_cfg):
+    return "default" if not tile_cfg else f"wc={tile_cfg & 0xff},cf={tile_cfg >> 8}"
+
+
 def kernel_bytes_flops(kind, m, n, r, bf=False):
     """Algorithmic HBM bytes and flops of one launch at a level with m pixels.
 
@@ -130,11 +142,23 @@ def bench_batch(args) -> int:
     import torch
     import paper_1009_0881_amd as P
     torch.cuda.set_device(0)
+
+    def kwargs(spec, inst):
+        return dict(m=spec.m, n=spec.n, h=spec.h, w=spec.w, r=spec.r, levels=3, algo="hals",
+                    cycle=args.cycle, xfer="fw", tol=inst.eps_E + args.tau,
+                    max_fine_iters=args.max_fine_iters, check_every=4)
+
+    tile_cfg, tuning = parse_tile(args.tile), None
+    if args.tune:   # tile autotuner on every 8th problem of the batch
+        from paper_1009_0881_amd import tune
+        sample = pool[::8]
+        tuning = tune.tune_batch([kwargs(sp, it) for sp, it in sample], [it.M for _, it in sample],
+                                 [it.V0 for _, it in sample], [it.W0 for _, it in sample],
+                                 [args.budget] * len(sample))
+        tile_cfg = tuning["tile_cfg"]
     plans, dev = [], []
     for spec, inst in pool:
-        plans.append(P.Plan(m=spec.m, n=spec.n, h=spec.h, w=spec.w, r=spec.r, levels=3,
-                            algo="hals", cycle=args.cycle, xfer="fw", tol=inst.eps_E + args.tau,
-                            max_fine_iters=args.max_fine_iters, check_every=4))
+        plans.append(P.Plan(**kwargs(spec, inst), tile_cfg=tile_cfg))
         dev.append(P.to_device(inst.M, inst.V0, inst.W0))
     V0 = [d[1].clone() for d in dev]
     W0 = [d[2].clone() for d in dev]
@@ -180,7 +204,10 @@ def bench_batch(args) -> int:
         "iterations_total": int(sum(r["total_iters"] for r in res)),
         "fine_equiv_total": round(float(sum(r["fine_equiv"] for r in res)), 2),
         "algorithmic_hbm_gbs": round(tot_bytes / (ms50 * 1e-3) / 1e9, 1),
+        "tile_cfg": tile_desc(tile_cfg),
     }
+    if tuning:
+        out["tuning_ms"] = {k: round(v, 3) for k, v in tuning["ms"].items()}
     print(json.dumps(out), flush=True)
     return 0 if ok else 1
 
@@ -266,6 +293,9 @@ def main() -> int:
     ap.add_argument("--bf16-share", type=float, default=0.3,
                     help="serve: fraction of requests in BF16 with FP32 refinement")
     ap.add_argument("--graph", action="store_true", help="batch: replay steady ticks as hipGraphs")
+    ap.add_argument("--tile", default="", help="tile shapes 'wc,cf' (default: the library's)")
+    ap.add_argument("--tune", action="store_true",
+                    help="batch: pick the tile shapes with the autotuner first")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="BYTES",
                     help="only run 3 device-to-device copies of BYTES bytes (reference for "
                          "the FETCH_SIZE / WRITE_SIZE counters) and exit")
@@ -330,7 +360,8 @@ def main() -> int:
         return P.Plan(m=m, n=n, h=wl["h"], w=wl["w"], r=r, levels=L, algo=args.algo,
                       cycle=args.cycle, xfer=wl["xfer"], tol=target,
                       max_fine_iters=args.max_fine_iters, check_every=4, prec=prec,
-                      refine_iters=args.refine if prec == "bf16" else 0)
+                      refine_iters=args.refine if prec == "bf16" else 0,
+                      tile_cfg=parse_tile(args.tile))
 
     ml = make_plan(levels, args.prec)
     sl = make_plan(1)
@@ -492,6 +523,7 @@ def main() -> int:
                        "multilevel_fine_equiv": round(last["fine_equiv"], 3),
                        "single_level": sl_res["total_iters"]},
         "all_reached_target": bool(ok),
+        "tile_cfg": tile_desc(parse_tile(args.tile)),
         "roofline": roofline,
         "kernels": kernels,
         "cpu_baseline": cpu,
