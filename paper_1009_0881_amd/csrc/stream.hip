@@ -69,55 +69,66 @@ __device__ __forceinline__ void load_gram_f32(const double *__restrict__ Gd, int
 }
 
 // One factor row held by one lane (x, with arow the lane's row of the
-// product in LDS), updated against the RPAD x RPAD Gram G (row-major, zero-padded,
-// in LDS; every lane reads the same entry, a broadcast) and gi[k] = 1/G_kk
-// (0 when G_kk = 0 or k >= r).  FP32 arithmetic.
+// product in LDS), updated against the RPAD x RPAD Gram G (row-major,
+// zero-padded, in LDS; every lane reads the same entry, a broadcast) and
+// gi[k] = 1/G_kk (0 when G_kk = 0 or k >= r), in T: FP32 in the BF16 mode,
+// FP64 in the FP32 mode.
 // HALS (Alg. 3): for k = 1..r in order, x_k <- max(0, (a_k - sum_{l != k}
 // x_l G_lk) / G_kk) with the entries l < k already updated; G_kk = 0 keeps x_k.
 // MU (Alg. 2): x_k <- x_k a_k / (sum_l x_l G_lk) from the old x; a zero
 // denominator keeps x_k.
 // Dot products use four interleaved partial sums (entries l = 0, 1, 2, 3 mod
-// 4), added as (s0 + s1) + (s2 + s3).  The Gram row of step k is read only
-// once step k - 2 is done (ordered_after), so loads run two steps ahead
-// without all of them being hoisted into registers.
-template <int RPAD, int MODE>
-__device__ __forceinline__ void stream_row_update(float (&x)[RPAD], const float *arow,
-                                                  const float *G, const float *gi, int r) {
-    auto dot = [&](int k_row, auto skip_c, float dep) -> float {
+// 4), added as (s0 + s1) + (s2 + s3).  The code is straight-line over all
+// RPAD entries and steps: padded entries are zero (x_l = 0, zero Gram rows and
+// 1/G_kk = 0), so they change nothing, and a branch per group or step would
+// make the compiler wait for every LDS load in flight at each branch.  The
+// Gram row of step k is read only once step k - AHEAD is done
+// (ordered_after), so its loads overlap the previous steps without all of
+// them being hoisted into registers.
+template <int RPAD, int MODE, class T>
+__device__ __forceinline__ void stream_row_update(T (&x)[RPAD], const T *arow, const T *G,
+                                                  const T *gi, int r) {
+    typedef double v2d __attribute__((ext_vector_type(2)));
+    constexpr int AHEAD = std::is_same<T, float>::value ? 2 : 1;
+    auto dot = [&](int k_row, auto skip_c, T dep) -> T {
         constexpr int skip = decltype(skip_c)::value;
-        float s0 = 0.0f, s1 = 0.0f, s2 = 0.0f, s3 = 0.0f;
-        const float *g = G + ordered_after(k_row * RPAD, dep);
+        T s0 = T(0), s1 = T(0), s2 = T(0), s3 = T(0);
+        const T *g = G + ordered_after(k_row * RPAD, dep);
         static_for<RPAD / 4>([&](auto lg_c) {
             constexpr int l = 4 * decltype(lg_c)::value;
-            if (l < r) {
+            T g0, g1, g2, g3;
+            if constexpr (std::is_same<T, float>::value) {
                 const v4f gv = *(const lmem<v4f> *)(g + l);
-                s0 = (l + 0 == skip) ? s0 : __builtin_fmaf(x[l + 0], gv[0], s0);
-                s1 = (l + 1 == skip) ? s1 : __builtin_fmaf(x[l + 1], gv[1], s1);
-                s2 = (l + 2 == skip) ? s2 : __builtin_fmaf(x[l + 2], gv[2], s2);
-                s3 = (l + 3 == skip) ? s3 : __builtin_fmaf(x[l + 3], gv[3], s3);
+                g0 = gv[0]; g1 = gv[1]; g2 = gv[2]; g3 = gv[3];
+            } else {
+                const v2d ga = *(const lmem<v2d> *)(g + l);
+                const v2d gb = *(const lmem<v2d> *)(g + l + 2);
+                g0 = ga[0]; g1 = ga[1]; g2 = gb[0]; g3 = gb[1];
             }
+            s0 = (l + 0 == skip) ? s0 : fma_t(x[l + 0], g0, s0);
+            s1 = (l + 1 == skip) ? s1 : fma_t(x[l + 1], g1, s1);
+            s2 = (l + 2 == skip) ? s2 : fma_t(x[l + 2], g2, s2);
+            s3 = (l + 3 == skip) ? s3 : fma_t(x[l + 3], g3, s3);
         });
         return (s0 + s1) + (s2 + s3);
     };
     if constexpr (MODE == MODE_HALS) {
         static_for<RPAD>([&](auto k_c) {
             constexpr int k = decltype(k_c)::value;
-            if (k < r) {
-                const float num = arow[k] - dot(k, k_c, x[k >= 2 ? k - 2 : 0]);
-                const float gk = gi[k];
-                if (gk > 0.0f) x[k] = fmaxf(num * gk, 0.0f);
-            }
+            const T num = arow[k] - dot(k, k_c, x[k >= AHEAD ? k - AHEAD : 0]);
+            const T gk = gi[k];
+            const T c = num * gk;
+            x[k] = gk > T(0) ? (c > T(0) ? c : T(0)) : x[k];
         });
     } else {
-        float den[RPAD] = {};
+        T den[RPAD] = {};
         static_for<RPAD>([&](auto k_c) {
             constexpr int k = decltype(k_c)::value;
-            den[k] = k < r ? dot(k, std::integral_constant<int, -1>{}, den[k >= 2 ? k - 2 : 0])
-                           : 0.0f;
+            den[k] = dot(k, std::integral_constant<int, -1>{}, den[k >= AHEAD ? k - AHEAD : 0]);
         });
 #pragma unroll
         for (int k = 0; k < RPAD; ++k)
-            if (k < r && den[k] > 0.0f) x[k] = x[k] * arow[k] / den[k];
+            if (k < r && den[k] > T(0)) x[k] = x[k] * arow[k] / den[k];
     }
 }
 
@@ -212,7 +223,7 @@ __device__ __forceinline__ void apass_stream_tile(const Job &J, int tile, double
     float x[RPAD];
 #pragma unroll
     for (int k = 0; k < RPAD; ++k) x[k] = (live && k < r) ? V[row + (int64_t)k * m] : 0.0f;
-    stream_row_update<RPAD, MODE>(x, Aw + lane * AS, Gs, Gi, r);
+    stream_row_update<RPAD, MODE, float>(x, Aw + lane * AS, Gs, Gi, r);
     if (live) {
         const auto Vb = to_global(J.Vb);
 #pragma unroll
@@ -387,12 +398,13 @@ __global__ __launch_bounds__(256) void k_cpass_stream(const Job *__restrict__ jo
 // holds A[row0 + 8lk' + 2v + s][16t + li'].  Every 4 K-steps (16 products per
 // chain) the accumulators are added into FP64 sums.  Past n the W operand is
 // zero (the M column read is clamped), so no load is conditional.  The V
-// update (FP64, as in the regular kernels) takes the wave's rows 4 at a time
-// from a wave-private LDS slot, one s at a time.
+// update (FP64, as in the regular kernels) runs one s at a time: the wave's 16
+// rows of that s go to a wave-private LDS slot and lane q updates row
+// row0 + 2q + s, reading and writing V with one coalesced access per entry.
 // ---------------------------------------------------------------------------
 template <int RT, int MODE>
-__device__ void apass_s32_tile(const Job &J, int tile, double *smem) {
-    constexpr int RPAD = RT * 16, GS = RPAD + 1, AS = RPAD + 1, RS = 2, SB = 4;
+__device__ __forceinline__ void apass_s32_tile(const Job &J, int tile, double *smem) {
+    constexpr int RPAD = RT * 16, GS = RPAD, AS = RPAD + 1, RS = 2, SB = 4;
     typedef float v2f __attribute__((ext_vector_type(2)));
     double *Gs = smem;
     double *Gi = Gs + RPAD * GS;
@@ -468,19 +480,11 @@ __device__ void apass_s32_tile(const Job &J, int tile, double *smem) {
     }
     double *Aw = Gi + RPAD + wave * 16 * AS;   // 16 rows of this wave (one s)
     __syncthreads();                            // Gram in LDS
-    auto load_x = [&](int g, double (&x)[RT]) {   // g = 4 s + v: rows row0 + 8lk + 2v + s
-        const int64_t row = row0 + 8 * lk + 2 * (g & 3) + (g >> 2);
-#pragma unroll
-        for (int t = 0; t < RT; ++t) {
-            const int k = 16 * t + li;
-            x[t] = (row < m && k < r) ? (double)to_global(J.V)[row + (int64_t)k * m] : 0.0;
-        }
-    };
-    double xc[RT], xn[RT];
-    load_x(0, xc);
+    const auto V = to_global(J.V);
     static_for<RS>([&](auto s_c) {
         constexpr int s2 = decltype(s_c)::value;
         __builtin_amdgcn_wave_barrier();
+        // hs[s2][t][v] = A[row0 + 2 q + s2][16t + li] with q = 4 lk + v
 #pragma unroll
         for (int t = 0; t < RT; ++t)
 #pragma unroll
@@ -488,40 +492,34 @@ __device__ void apass_s32_tile(const Job &J, int tile, double *smem) {
         __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
         __builtin_amdgcn_wave_barrier();
         __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-#pragma unroll 1
-        for (int v = 0; v < 4; ++v) {
-            const int g = 4 * s2 + v;
-            if (g + 1 < RS * 4) load_x(g + 1, xn);
-            double a[RT];
-#pragma unroll
-            for (int t = 0; t < RT; ++t) a[t] = Aw[(4 * lk + v) * AS + 16 * t + li];
-            const int64_t row = row0 + 8 * lk + 2 * v + s2;
+        if (lane < 16) {
+            const int64_t row = row0 + 2 * lane + s2;
+            const bool live = row < m;
+            const double *arow = Aw + lane * AS;
             if constexpr (MODE == MODE_STORE) {
-                if (row < m) {
+                if (live) {
 #pragma unroll
-                    for (int t = 0; t < RT; ++t) {
-                        const int k = 16 * t + li;
-                        if (k < r) to_global(J.A)[row + (int64_t)k * m] = (float)a[t];
-                    }
+                    for (int k = 0; k < RPAD; ++k)
+                        if (k < r) to_global(J.A)[row + (int64_t)k * m] = (float)arow[k];
                 }
             } else {
-                row_update<RT, MODE>(xc, Gs, GS, Gi, a, r, li);
-                if (row < m) {
+                double x[RPAD];
 #pragma unroll
-                    for (int t = 0; t < RT; ++t) {
-                        const int k = 16 * t + li;
-                        if (k < r) to_global(J.V)[row + (int64_t)k * m] = (float)xc[t];
-                    }
+                for (int k = 0; k < RPAD; ++k)
+                    x[k] = (live && k < r) ? (double)V[row + (int64_t)k * m] : 0.0;
+                stream_row_update<RPAD, MODE, double>(x, arow, Gs, Gi, r);
+                if (live) {
+#pragma unroll
+                    for (int k = 0; k < RPAD; ++k)
+                        if (k < r) V[row + (int64_t)k * m] = (float)x[k];
                 }
             }
-#pragma unroll
-            for (int t = 0; t < RT; ++t) xc[t] = xn[t];
         }
     });
 }
 
 template <int RT, int MODE>
-__global__ __launch_bounds__(256) void k_apass_s32(const Job *__restrict__ jobs,
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k_apass_s32(const Job *__restrict__ jobs,
                                                    const int2 *__restrict__ bmap) {
     extern __shared__ double smem[];
     const int2 jt = block_job(bmap);
@@ -697,9 +695,10 @@ __global__ __launch_bounds__(256) void k_cpass_s32(const Job *__restrict__ jobs,
 
 int cpass_stream_grid(int nCx, int chunks) { return 8 * nCx * ((chunks + 7) / 8); }
 
-// FP64 Gram and 1/G_kk, then 4 waves x 16 rows of A (FP64, stride rpad + 1).
+// FP64 Gram (stride rpad) and 1/G_kk, then 4 waves x 16 rows of A (FP64,
+// stride rpad + 1).
 size_t apass_s32_lds_bytes(int rpad) {
-    return sizeof(double) * ((size_t)rpad * (rpad + 1) + rpad + 4 * 16 * (size_t)(rpad + 1));
+    return sizeof(double) * ((size_t)rpad * rpad + rpad + 4 * 16 * (size_t)(rpad + 1));
 }
 
 hipError_t launch_apass_s32(int mode, int rpad, const Job *jobs, const int2 *bmap, int blocks,
