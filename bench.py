@@ -48,13 +48,13 @@ SWEEP_SOURCES = ("sweep.hip", "sweep_device.h", "device_common.h", "job.h")
 STREAM_SOURCES = SWEEP_SOURCES + ("stream.hip",)
 TRAFFIC = {
     ("orl", "fp32"): {
-        "sha": "ba12d811c8d72a7f",
+        "sha": "3accac8295ae162d",
         "files": SWEEP_SOURCES,
-        "apass": {10304: 20016958, 2576: 6178816, 644: 2470272},
-        "cpass_partial": {10304: 21944398, 2576: 8346880, 644: 3493376},
-        "cpass_final": {10304: 5189266, 2576: 3910784, 644: 2630784},
-        "gram_v": {10304: 460190, 2576: 346880, 644: 234240},
-        "gram_w": {10304: 298269, 2576: 311392, 644: 311392},
+        "apass": {10304: 20016962, 2576: 6178816, 644: 2470272},
+        "cpass_partial": {10304: 21960635, 2576: 8363008, 644: 3509504},
+        "cpass_final": {10304: 5200969, 2576: 3923072, 644: 2643072},
+        "gram_v": {10304: 463262, 2576: 349952, 644: 237312},
+        "gram_w": {10304: 297676, 2576: 310624, 644: 310624},
     },
 }
 
