@@ -162,8 +162,8 @@ Ctx make_ctx(nmf_plan_t plan, const float *dM, float *dV, float *dW, void *dws, 
             J.prec = 1;
             if (li.stream && allow_stream) {   // streaming kernels: 256-row / 256-column tiles
                 J.stream = 1;
-                J.tm = 256;
-                J.nA = (int32_t)((li.m + 255) / 256);
+                J.tm = kStreamARows;
+                J.nA = (int32_t)((li.m + kStreamARows - 1) / kStreamARows);
                 J.nCx = (int32_t)((p.d.n + 255) / 256);
                 J.chunks = li.scp_chunks;
                 J.chunk = li.scp_chunk;

@@ -57,7 +57,7 @@ struct Job {
     int64_t mpad, npad;
     int32_t prec;
     int32_t stream;      // 1: streaming A/C-pass kernels (large BF16 levels): A-pass
-                         // tiles of 256 rows, C-pass tiles of 256 columns
+                         // tiles of kStreamARows rows, C-pass tiles of 256 columns
 };
 
 }  // namespace nmf

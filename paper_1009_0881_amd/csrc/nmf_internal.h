@@ -195,9 +195,10 @@ hipError_t launch_gram_w_jobs(int with_resid, const Job *jobs, const int2 *bmap,
 // blocks are mapped to tiles XCD by XCD.
 int apass_grid_single(int nA);
 int cpass_grid_single(int nCx, int chunks);
-// Streaming BF16 passes (job.stream): A-pass tiles of 256 rows (nA blocks),
+// Streaming BF16 passes (job.stream): A-pass tiles of kStreamARows rows (nA blocks),
 // C-pass tiles of 256 columns x one row chunk (XCD-ordered grid).
 constexpr int64_t kStreamMinRows = 32768;
+constexpr int kStreamARows = 256;   // rows per block of the streaming BF16 A-pass
 hipError_t launch_apass_stream(int mode, int rpad, const Job *jobs, const int2 *bmap, int blocks,
                                hipStream_t s);
 hipError_t launch_cpass_stream(int rpad, const Job *jobs, const int2 *bmap, int blocks,

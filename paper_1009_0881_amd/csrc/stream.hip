@@ -135,60 +135,78 @@ __device__ __forceinline__ void stream_row_update(T (&x)[RPAD], const T *arow, c
 // ---------------------------------------------------------------------------
 // Streaming passes for large levels in BF16 mode (job.stream = 1).
 //
-// A-pass: a block of 4 waves owns 256 rows; each wave owns 64 rows (four
-// 16-row panels of the K-packed copy of M) over all of n, so every W operand
-// feeds four MFMAs and no partial tiles are combined.  M panels and W tiles
-// reach LDS by DMA, kStreamStages K-steps deep, one barrier per K-step.  The
-// wave's A rows then go to a wave-private LDS region (FP32, aliasing the
-// stages) and each lane updates one row: x = row `lane` of V, read and written
-// with one coalesced access per entry, the r x r arithmetic in FP32 against
-// the Gram in LDS.
+// A-pass: a block of 4 waves owns kStreamARows = 256 rows; each wave owns 64
+// rows (four 16-row panels of the K-packed copy of M) over all of n, so every
+// W operand feeds four MFMAs and no partial tiles are combined.  M panels and
+// W tiles reach LDS by DMA, kStreamStages K-steps deep, one barrier per
+// K-step.  Each lane's V row is loaded before the M stream starts (its latency
+// hides behind it).  The wave's A rows then go to a wave-private LDS region
+// (FP32, aliasing the stages) and lane q updates row q of the wave: V read and
+// written with one coalesced access per entry, the r x r arithmetic in FP32
+// against the Gram in LDS.  (128-row blocks, two per CU, measured the same:
+// the blocks of a CU run in step, so their updates overlap each other, not the
+// M stream.)
 // ---------------------------------------------------------------------------
+constexpr int kStreamAPanels = kStreamARows / 64;                 // 16-row panels per wave
+constexpr int kStreamAStage = (4 * kStreamAPanels + 4) * 1024;       // M panels, then 4 W slots
+constexpr int kStreamAOps = kStreamAPanels + 1;                      // copies per wave per stage
+
 template <int RT, int MODE>
 __device__ __forceinline__ void apass_stream_tile(const Job &J, int tile, double *smem) {
-    constexpr int RPAD = RT * 16, AS = RPAD + 1, NST = kStreamStages;
+    constexpr int RPAD = RT * 16, AS = RPAD + 1, NST = kStreamStages, PW = kStreamAPanels;
+    constexpr int STAGE = kStreamAStage, WSLOT = 4 * PW * 1024, WR = 16 * PW;
     char *pipe = reinterpret_cast<char *>(smem);
-    float *Gs = reinterpret_cast<float *>(pipe + NST * kStreamStage);   // RPAD x RPAD
+    float *Gs = reinterpret_cast<float *>(pipe + NST * STAGE);   // RPAD x RPAD
     float *Gi = Gs + RPAD * RPAD;
     const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
     const int li = lane & 15, lk = lane >> 4;
     const int64_t m = J.m;
     const int r = J.r;
-    const int64_t row0 = (int64_t)tile * 256 + wave * 64;
+    const int64_t row0 = (int64_t)tile * kStreamARows + wave * WR;
     // npad is a multiple of 128, so ksteps >= 4 >= NST - 1; panels past m
     // read the last panel (their rows are not written back)
     const int ksteps = (int)(J.npad / 32);
     const int64_t G = J.npad / 8;
     const int64_t lastp = (m - 1) / 16;
-    gmem<const uint16_t> *Mp[4];
+    gmem<const uint16_t> *Mp[PW];
 #pragma unroll
-    for (int q = 0; q < 4; ++q) {
+    for (int q = 0; q < PW; ++q) {
         const int64_t pr = row0 / 16 + q;
         Mp[q] = to_global(J.Mbp) + ((pr < lastp ? pr : lastp) * G * 16 + li) * 8 + lk * 128;
     }
     // wave w copies W tile w % RT into W slot w
     gmem<const uint16_t> *Wr =
         to_global(J.Wb) + (int64_t)(16 * (wave % RT) + li) * J.npad + 8 * lk;
+    // the V row of the update (lane q: row row0 + q) is loaded before the
+    // M stream starts, so its latency hides behind it; these loads are older
+    // than every copy, so the copy waits below also cover them
+    const int64_t row = row0 + lane;
+    const bool live = lane < WR && row < m;
+    const auto V = to_global(J.V);
+    float x[RPAD];
+#pragma unroll
+    for (int k = 0; k < RPAD; ++k) x[k] = (live && k < r) ? V[row + (int64_t)k * m] : 0.0f;
     auto issue = [&](int kk) {
-        char *st = pipe + (kk % NST) * kStreamStage;
+        char *st = pipe + (kk % NST) * STAGE;
 #pragma unroll
-        for (int q = 0; q < 4; ++q) lds_dma16(Mp[q] + (int64_t)kk * 512, st + (wave * 4 + q) * 1024);
-        lds_dma16(Wr + 32 * kk, st + 16384 + wave * 1024);
+        for (int q = 0; q < PW; ++q)
+            lds_dma16(Mp[q] + (int64_t)kk * 512, st + (wave * PW + q) * 1024);
+        lds_dma16(Wr + 32 * kk, st + WSLOT + wave * 1024);
     };
-    v4f acc[4][RT];
+    v4f acc[PW][RT];
 #pragma unroll
-    for (int q = 0; q < 4; ++q)
+    for (int q = 0; q < PW; ++q)
 #pragma unroll
         for (int t = 0; t < RT; ++t) acc[q][t] = v4f{0.0f, 0.0f, 0.0f, 0.0f};
     auto mma = [&](int kk) {
-        const char *st = pipe + (kk % NST) * kStreamStage;
-        bf16x8 a[4], b[RT];
+        const char *st = pipe + (kk % NST) * STAGE;
+        bf16x8 a[PW], b[RT];
 #pragma unroll
-        for (int q = 0; q < 4; ++q) a[q] = lds_bf16x8(st + (wave * 4 + q) * 1024 + lane * 16);
+        for (int q = 0; q < PW; ++q) a[q] = lds_bf16x8(st + (wave * PW + q) * 1024 + lane * 16);
 #pragma unroll
-        for (int t = 0; t < RT; ++t) b[t] = lds_bf16x8(st + 16384 + t * 1024 + lane * 16);
+        for (int t = 0; t < RT; ++t) b[t] = lds_bf16x8(st + WSLOT + t * 1024 + lane * 16);
 #pragma unroll
-        for (int q = 0; q < 4; ++q)
+        for (int q = 0; q < PW; ++q)
 #pragma unroll
             for (int t = 0; t < RT; ++t)
                 acc[q][t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[q], b[t], acc[q][t], 0, 0, 0);
@@ -197,32 +215,26 @@ __device__ __forceinline__ void apass_stream_tile(const Job &J, int tile, double
     for (int kk = 0; kk < NST - 1; ++kk) issue(kk);
     int kk = 0;
     for (; kk < ksteps - (NST - 1); ++kk) {
-        vm_wait_barrier<kStageOps * (NST - 2)>();   // stage kk landed, stage kk - 1 read
+        vm_wait_barrier<kStreamAOps * (NST - 2)>();   // stage kk landed, stage kk - 1 read
         issue(kk + NST - 1);
         mma(kk);
     }
-    static_for<NST - 1>([&](auto j_c) {             // drain: nothing left to issue
+    static_for<NST - 1>([&](auto j_c) {               // drain: nothing left to issue
         constexpr int j = decltype(j_c)::value;
-        vm_wait_barrier<kStageOps * (NST - 2 - j)>();
+        vm_wait_barrier<kStreamAOps * (NST - 2 - j)>();
         mma(kk + j);
     });
     __syncthreads();   // every wave done with the stages
     load_gram_f32<RPAD>(J.Bd, r, Gs, Gi);
-    float *Aw = reinterpret_cast<float *>(pipe) + wave * 64 * AS;
+    float *Aw = reinterpret_cast<float *>(pipe) + wave * WR * AS;
 #pragma unroll
-    for (int q = 0; q < 4; ++q)
+    for (int q = 0; q < PW; ++q)
 #pragma unroll
         for (int t = 0; t < RT; ++t)
 #pragma unroll
             for (int v = 0; v < 4; ++v) Aw[(16 * q + 4 * lk + v) * AS + 16 * t + li] = acc[q][t][v];
     __syncthreads();   // Gram and A rows in LDS
-
-    const int64_t row = row0 + lane;
-    const bool live = row < m;
-    const auto V = to_global(J.V);
-    float x[RPAD];
-#pragma unroll
-    for (int k = 0; k < RPAD; ++k) x[k] = (live && k < r) ? V[row + (int64_t)k * m] : 0.0f;
+    if (lane >= WR) return;
     stream_row_update<RPAD, MODE, float>(x, Aw + lane * AS, Gs, Gi, r);
     if (live) {
         const auto Vb = to_global(J.Vb);
@@ -734,12 +746,12 @@ hipError_t launch_cpass_s32(int rpad, const Job *jobs, const int2 *bmap, int blo
     return hipGetLastError();
 }
 
-// The DMA stages (later holding 4 waves x 64 rows of A, FP32, stride
+// The DMA stages (later holding the 4 waves' rows of A, FP32, stride
 // rpad + 1), then the FP32 Gram and 1/G_kk.
 size_t apass_stream_lds_bytes(int rpad) {
-    static_assert(4 * 64 * 65 * sizeof(float) <= kStreamStages * kStreamStage,
+    static_assert(4 * 16 * kStreamAPanels * 65 * sizeof(float) <= kStreamStages * kStreamAStage,
                   "A rows must fit in the stages");
-    return (size_t)kStreamStages * kStreamStage + sizeof(float) * ((size_t)rpad * rpad + rpad);
+    return (size_t)kStreamStages * kStreamAStage + sizeof(float) * ((size_t)rpad * rpad + rpad);
 }
 
 hipError_t launch_apass_stream(int mode, int rpad, const Job *jobs, const int2 *bmap, int blocks,
