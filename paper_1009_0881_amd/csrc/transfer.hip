@@ -81,8 +81,9 @@ __device__ __forceinline__ Taps prolong_taps(int f, int Nc, int xfer) {
 
 // One output pixel of a separable transfer: sum_a ty_a sum_b tx_b img[iy_a * rowlen + ix_b],
 // accumulated in FP64 in tap order.
-__device__ __forceinline__ float stencil(const float *img, int rowlen, const Taps &ty,
+__device__ __forceinline__ float stencil(const float *imgp, int rowlen, const Taps &ty,
                                          const Taps &tx) {
+    const auto img = to_global(imgp);   // global (not FLAT) loads: the 9 taps stay in flight
     double acc = 0.0;
 #pragma unroll
     for (int a = 0; a < 3; ++a) {
@@ -131,22 +132,52 @@ __global__ __launch_bounds__(256) void k_prolong(const float *__restrict__ Y,
 // Sum of squares of a column-major matrix in FP64: per-block partials, then a
 // single block adds them in index order (deterministic).
 // Partial part (of nparts) of ||X||_F^2: work items (column, 2048-row chunk),
-// part p takes items p, p + nparts, ...
-__device__ __forceinline__ double sumsq_part(const float *X, int64_t ld, int64_t rows,
+// part p takes items p, p + nparts, ...  Full chunks of a 16-byte-aligned
+// matrix with ld % 4 == 0 are read as two float4 per thread, four items per
+// batch with every load issued before the sums; other items element-wise.
+__device__ __forceinline__ double sumsq_part(const float *Xg, int64_t ld, int64_t rows,
                                              int64_t ncols, int part, int nparts) {
-    constexpr int64_t CH = 2048;
-    const int64_t nrc = (rows + CH - 1) / CH;
-    double acc = 0.0;
-    for (int64_t it = part; it < ncols * nrc; it += nparts) {
-        const int64_t c = it / nrc, r0 = (it - c * nrc) * CH;
-        const int64_t r1 = r0 + CH < rows ? r0 + CH : rows;
-        const float *col = X + c * ld;
-        for (int64_t i = r0 + threadIdx.x; i < r1; i += 256) {
-            const double v = col[i];
-            acc += v * v;
+    constexpr int64_t CH = 2048, U = 4;
+    const auto X = to_global(Xg);
+    const int64_t nrc = (rows + CH - 1) / CH, total = ncols * nrc;
+    const bool vec = (ld & 3) == 0 && ((uintptr_t)Xg & 15) == 0;
+    const int tid = threadIdx.x;
+    double acc[4] = {0.0, 0.0, 0.0, 0.0};
+    auto full = [&](int64_t it) { return it < total && (it % nrc) * CH + CH <= rows; };
+    auto sq4 = [&](const v4f &v, double &a) {
+#pragma unroll
+        for (int e = 0; e < 4; ++e) a += (double)v[e] * (double)v[e];
+    };
+    int64_t it = part;
+    for (; vec && it + (U - 1) * nparts < total; it += U * nparts) {
+        bool all = true;
+#pragma unroll
+        for (int u = 0; u < U; ++u) all = all && full(it + u * nparts);
+        if (!all) break;
+        v4f a[U], b[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const int64_t iu = it + u * nparts, c = iu / nrc, r0 = (iu - c * nrc) * CH;
+            const auto col = X + c * ld + r0;
+            a[u] = *(gmem<const v4f> *)(col + 4 * tid);
+            b[u] = *(gmem<const v4f> *)(col + 1024 + 4 * tid);
+        }
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            sq4(a[u], acc[u]);
+            sq4(b[u], acc[u]);
         }
     }
-    return acc;
+    for (; it < total; it += nparts) {
+        const int64_t c = it / nrc, r0 = (it - c * nrc) * CH;
+        const int64_t r1 = r0 + CH < rows ? r0 + CH : rows;
+        const auto col = X + c * ld;
+        for (int64_t i = r0 + tid; i < r1; i += 256) {
+            const double v = col[i];
+            acc[0] += v * v;
+        }
+    }
+    return (acc[0] + acc[1]) + (acc[2] + acc[3]);
 }
 
 __global__ __launch_bounds__(256) void k_sumsq_partial(const float *__restrict__ X, int64_t ld,
