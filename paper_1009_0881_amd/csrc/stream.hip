@@ -540,17 +540,75 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k
     apass_s32_tile<RT, MODE>(J, jt.y, smem);
 }
 
+// (ta, tb) of upper 16x16 tile idx of an RT x RT tile grid, row by row.
+__device__ __forceinline__ void upper_tile(int idx, int rt, int &ta, int &tb) {
+    int a = 0;
+    while (idx >= rt - a) {
+        idx -= rt - a;
+        ++a;
+    }
+    ta = a;
+    tb = a + idx;
+}
+
+// Sum of the 4 waves' FP64-MFMA partials of D tile (ta, tb) (layout
+// d[v] = D[4v + lg][lj]) in fixed wave order, stored by wave 0.  dl: 1024
+// doubles of LDS; the block must be free to reuse them.
+template <int RPAD>
+__device__ __forceinline__ void store_d_tile(const v4d &d, double *dl, gmem<double> *dout, int ta,
+                                             int tb) {
+    const int tid = threadIdx.x, wave = tid >> 6, lj = tid & 15, lg = (tid >> 4) & 3;
+#pragma unroll
+    for (int v = 0; v < 4; ++v) dl[wave * 256 + (4 * v + lg) * 16 + lj] = d[v];
+    __syncthreads();
+    if (wave == 0) {
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+            const int e = (4 * v + lg) * 16 + lj;
+            dout[(16 * ta + 4 * v + lg) * RPAD + 16 * tb + lj] =
+                ((dl[e] + dl[256 + e]) + dl[512 + e]) + dl[768 + e];
+        }
+    }
+    __syncthreads();
+}
+
+// FP32 streaming C-pass stages: one 16-row K-step each, holding the 4 waves'
+// two 1 KB M panels and four 1 KB V slots (slot w copied by wave w, tile
+// w % RT); kS32Stages - 1 K-steps are in flight while one is multiplied.
+constexpr int kS32Stages = 6;
+constexpr int kS32Stage = 12 * 1024;
+constexpr int kS32Ops = 3;   // copies one wave issues per stage
+
+__device__ __forceinline__ void lds_dma16f(gmem<const float> *src, char *dst) {
+    __builtin_amdgcn_global_load_lds((gmem<const void> *)src, (lmem<void> *)dst, 16, 0, 0);
+}
+
+__device__ __forceinline__ v4f lds_v4f(const char *p) { return *(const lmem<v4f> *)p; }
+
 // C-pass (FP32): a block of 4 waves owns 128 columns of one row chunk; a wave
-// owns 32 columns (two 16-column tiles).  Per 16-row step a lane loads 4
-// consecutive rows of M (per column tile) and of V (per rank tile) as float4
-// and feeds them to 4 MFMAs, whose K index lk maps to row i0 + 4lk + s.  Each
-// step's chains (16 products) are added into FP64 sums.  Rows past the chunk
-// read a clamped row with a zero V operand.  The first column block of each
-// chunk also forms the chunk's V^T V partial on the FP64 matrix cores.
-template <int RT>
-__device__ void cpass_s32_tile(const Job &J, int tx, int ty) {
-    constexpr int RPAD = RT * 16, RN = 2, SB = 2, DMAX = 3;
-    const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+// owns 32 columns (two 16-column panels).  Per 16-row K-step lane (lj, g) of
+// a wave copies, by DMA, 4 consecutive rows 4g .. 4g+3 of column lj of each
+// of its panels, and one wave per rank tile copies the same rows of V; the
+// lane reads back its own 16 bytes, which feed 4 MFMAs whose K index g maps
+// to row i0 + 4g + s.  Each step's chains (16 products) are added into FP64
+// sums.  Copies past the chunk's end read its last 4 rows; the V operand of
+// such rows is zeroed (only the last kS32Stages - 1 steps can hold them).
+// Rank columns k >= r copy column 0: they feed only C rows and D entries that
+// are never stored or read.
+//
+// The chunk's upper 16x16 tiles of D = V^T V are spread over its column
+// blocks.  With FD, block tx forms tile tx from the V operands it already
+// reads: per step, wave w takes the FP64 MFMA of rows 4g + w (g = 0..3) of
+// the step, so the four waves' partials cover every row once and are added
+// in LDS.  Tiles tx + nCx, tx + 2 nCx, ... (only when there are fewer column
+// blocks than tiles) take a pass over V alone, the waves taking every fourth
+// step.
+template <int RT, bool FD>
+__device__ __forceinline__ void cpass_s32_tile(const Job &J, int tx, int ty, double *smem) {
+    constexpr int RPAD = RT * 16, RN = 2, NT = RT * (RT + 1) / 2, NST = kS32Stages;
+    char *pipe = reinterpret_cast<char *>(smem);
+    const int tid = threadIdx.x, lane = tid & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
     const int lj = lane & 15, lg = lane >> 4;
     const int64_t m = J.m, n = J.n, ldm = J.ldm;
     const int r = J.r;
@@ -558,27 +616,29 @@ __device__ void cpass_s32_tile(const Job &J, int tx, int ty) {
     const int64_t jb = (int64_t)tx * 128 + wave * 32;
     const int64_t i_begin = (int64_t)ty * J.chunk;
     const int64_t i_end = (i_begin + J.chunk < m) ? i_begin + J.chunk : m;
-    const int64_t nsteps = (i_end - i_begin + 15) / 16;
+    const int ksteps = (int)((i_end - i_begin + 15) / 16);
+    const int64_t i_last = i_end - 4;   // m % 4 == 0: a whole group of 4 rows
     gmem<const float> *Mc[RN];
 #pragma unroll
     for (int c = 0; c < RN; ++c) {
         const int64_t j = jb + 16 * c + lj;
-        Mc[c] = to_global(J.M) + (j < n ? j : n - 1) * ldm;
+        Mc[c] = to_global(J.M) + (j < n ? j : n - 1) * ldm + 4 * lg;
     }
-    int dta[DMAX], dtb[DMAX], nd = 0;
-    if (tx == 0) {
-        int idx = 0;
-        for (int ta = 0; ta < RT; ++ta)
-            for (int tb = ta; tb < RT; ++tb, ++idx)
-                if (idx % 4 == wave && nd < DMAX) {
-                    dta[nd] = ta;
-                    dtb[nd] = tb;
-                    ++nd;
-                }
-    }
+    const int kv = 16 * (wave % RT) + lj;
+    gmem<const float> *Vr = V + (int64_t)(kv < r ? kv : 0) * m + 4 * lg;
+    auto issue = [&](int kk) {
+        char *st = pipe + (kk % NST) * kS32Stage;
+        int64_t i0 = i_begin + 16 * (int64_t)kk;
+        i0 = i0 + 4 * lg <= i_last ? i0 : i_last - 4 * lg;   // rows i0 + 4lg .. +3 stay in the chunk
+#pragma unroll
+        for (int c = 0; c < RN; ++c) lds_dma16f(Mc[c] + i0, st + (wave * RN + c) * 1024);
+        lds_dma16f(Vr + i0, st + 8192 + wave * 1024);
+    };
+    int ta = 0, tb = 0;
+    if (FD) upper_tile(tx, RT, ta, tb);
     v4f acc[RN][RT];
     double hs[RN][RT][4];
-    v4d dacc[DMAX];
+    v4d dacc = v4d{0.0, 0.0, 0.0, 0.0};
 #pragma unroll
     for (int c = 0; c < RN; ++c)
 #pragma unroll
@@ -587,78 +647,54 @@ __device__ void cpass_s32_tile(const Job &J, int tx, int ty) {
 #pragma unroll
             for (int v = 0; v < 4; ++v) hs[c][t][v] = 0.0;
         }
+    auto mma = [&](int kk, bool tail) {
+        const char *st = pipe + (kk % NST) * kS32Stage;
+        v4f a[RN], b[RT];
 #pragma unroll
-    for (int d = 0; d < DMAX; ++d) dacc[d] = v4d{0.0, 0.0, 0.0, 0.0};
-    v4f ma0[SB][RN], vb0[SB][RT], ma1[SB][RN], vb1[SB][RT];
-    auto load = [&](int64_t st0, v4f (&a)[SB][RN], v4f (&b)[SB][RT]) {
+        for (int c = 0; c < RN; ++c) a[c] = lds_v4f(st + (wave * RN + c) * 1024 + lane * 16);
 #pragma unroll
-        for (int u = 0; u < SB; ++u) {
-            const int64_t ib = i_begin + 16 * (st0 + u) + 4 * lg;   // rows ib .. ib+3
-            const bool ok = ib < i_end;                             // whole groups of 4 (m % 4 == 0)
-            const int64_t ic = ok ? ib : i_begin;
+        for (int t = 0; t < RT; ++t) b[t] = lds_v4f(st + 8192 + t * 1024 + lane * 16);
+        const bool dead = tail && i_begin + 16 * (int64_t)kk + 4 * lg >= i_end;
 #pragma unroll
-            for (int c = 0; c < RN; ++c) a[u][c] = *(gmem<const v4f> *)(Mc[c] + ic);
+        for (int t = 0; t < RT; ++t)
 #pragma unroll
-            for (int t = 0; t < RT; ++t) {
-                const int k = 16 * t + lj;
-                const v4f x = *(gmem<const v4f> *)(V + ic + (int64_t)(k < r ? k : 0) * m);
-                b[u][t] = (ok && k < r) ? x : v4f{0.0f, 0.0f, 0.0f, 0.0f};
-            }
-        }
-    };
-    auto compute = [&](const v4f (&a)[SB][RN], const v4f (&b)[SB][RT]) {
+            for (int s = 0; s < 4; ++s) b[t][s] = dead ? 0.0f : b[t][s];
 #pragma unroll
-        for (int u = 0; u < SB; ++u) {
-#pragma unroll
-            for (int s = 0; s < 4; ++s)
-#pragma unroll
-                for (int c = 0; c < RN; ++c)
-#pragma unroll
-                    for (int t = 0; t < RT; ++t)
-                        acc[c][t] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[u][c][s], b[u][t][s], acc[c][t], 0, 0, 0);
+        for (int s = 0; s < 4; ++s)
 #pragma unroll
             for (int c = 0; c < RN; ++c)
 #pragma unroll
-                for (int t = 0; t < RT; ++t) {
+                for (int t = 0; t < RT; ++t)
+                    acc[c][t] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[c][s], b[t][s], acc[c][t], 0, 0, 0);
+        if constexpr (FD) {   // row 4g + wave of V tiles ta and tb (V slot t holds tile t)
+            const char *vw = st + 8192 + lane * 16 + wave * 4;
+            const float fa = *(const lmem<float> *)(vw + ta * 1024);
+            const float fb = *(const lmem<float> *)(vw + tb * 1024);
+            dacc = __builtin_amdgcn_mfma_f64_16x16x4f64(dead ? 0.0 : (double)fa, (double)fb, dacc, 0, 0, 0);
+        }
 #pragma unroll
-                    for (int v = 0; v < 4; ++v) hs[c][t][v] += (double)acc[c][t][v];
-                    acc[c][t] = v4f{0.0f, 0.0f, 0.0f, 0.0f};
-                }
+        for (int c = 0; c < RN; ++c)
 #pragma unroll
-            for (int d = 0; d < DMAX; ++d) {
-                if (d < nd) {
+            for (int t = 0; t < RT; ++t) {
 #pragma unroll
-                    for (int s = 0; s < 4; ++s) {
-                        double va = 0.0, vb = 0.0;
-#pragma unroll
-                        for (int t = 0; t < RT; ++t) {
-                            if (t == dta[d]) va = (double)b[u][t][s];
-                            if (t == dtb[d]) vb = (double)b[u][t][s];
-                        }
-                        dacc[d] = __builtin_amdgcn_mfma_f64_16x16x4f64(va, vb, dacc[d], 0, 0, 0);
-                    }
-                }
+                for (int v = 0; v < 4; ++v) hs[c][t][v] += (double)acc[c][t][v];
+                acc[c][t] = v4f{0.0f, 0.0f, 0.0f, 0.0f};
             }
-        }
     };
-    const int64_t nb = (nsteps + SB - 1) / SB;
-    if (nb > 0) {
-        load(0, ma0, vb0);
-        int64_t bi = 0;
-        for (; bi + 2 < nb; bi += 2) {
-            load(SB * (bi + 1), ma1, vb1);
-            compute(ma0, vb0);
-            load(SB * (bi + 2), ma0, vb0);
-            compute(ma1, vb1);
-        }
-        if (bi + 1 < nb) {
-            load(SB * (bi + 1), ma1, vb1);
-            compute(ma0, vb0);
-            compute(ma1, vb1);
-        } else {
-            compute(ma0, vb0);
-        }
+#pragma unroll
+    for (int kk = 0; kk < NST - 1; ++kk) issue(kk);
+    int kk = 0;
+    // steps kk <= ksteps - NST end at or before row 16 (ksteps - 1) < i_end - i_begin
+    for (; kk < ksteps - (NST - 1); ++kk) {
+        vm_wait_barrier<kS32Ops * (NST - 2)>();   // stage kk landed, stage kk - 1 read
+        issue(kk + NST - 1);
+        mma(kk, false);
     }
+    static_for<NST - 1>([&](auto j_c) {   // drain (steps past ksteps are wholly masked)
+        constexpr int j = decltype(j_c)::value;
+        vm_wait_barrier<kS32Ops * (NST - 2 - j)>();
+        mma(kk + j, true);
+    });
     // hs[c][t][v] = C[k = 16t + lj][j = jb + 16c + 4lg + v]
     const auto out = to_global(J.Cp) + (int64_t)ty * r * n;
 #pragma unroll
@@ -674,21 +710,35 @@ __device__ void cpass_s32_tile(const Job &J, int tx, int ty) {
                 }
         }
     }
-    // dacc[d][v] = D[16 dta + 4v + lg][16 dtb + lj]  (FP64 MFMA layout)
-    const auto dout = to_global(J.Dp) + (int64_t)ty * RPAD * RPAD;
+    if constexpr (FD) {
+        __syncthreads();   // every wave done with the stages
+        const auto dout = to_global(J.Dp) + (int64_t)ty * RPAD * RPAD;
+        store_d_tile<RPAD>(dacc, smem, dout, ta, tb);
+        for (int idx = tx + J.nCx; idx < NT; idx += J.nCx) {
+            upper_tile(idx, RT, ta, tb);
+            const int ka = 16 * ta + lj, kb = 16 * tb + lj;
+            const auto Va = V + (int64_t)(ka < r ? ka : 0) * m;
+            const auto Vb = V + (int64_t)(kb < r ? kb : 0) * m;
+            v4d d = v4d{0.0, 0.0, 0.0, 0.0};
+            for (int st = wave; st < ksteps; st += 4) {
+                const int64_t ib = i_begin + 16 * (int64_t)st + 4 * lg;
+                const bool ok = ib < i_end;
+                const int64_t ic = ok ? ib : i_last;
+                v4f xa = *(gmem<const v4f> *)(Va + ic), xb = *(gmem<const v4f> *)(Vb + ic);
+                if (!ok) xa = v4f{0.0f, 0.0f, 0.0f, 0.0f};
 #pragma unroll
-    for (int d = 0; d < DMAX; ++d) {
-        if (d < nd) {
-#pragma unroll
-            for (int v = 0; v < 4; ++v)
-                dout[(16 * dta[d] + 4 * v + lg) * RPAD + 16 * dtb[d] + lj] = dacc[d][v];
+                for (int s = 0; s < 4; ++s)
+                    d = __builtin_amdgcn_mfma_f64_16x16x4f64((double)xa[s], (double)xb[s], d, 0, 0, 0);
+            }
+            store_d_tile<RPAD>(d, smem, dout, ta, tb);
         }
     }
 }
 
 template <int RT>
-__global__ __launch_bounds__(256) void k_cpass_s32(const Job *__restrict__ jobs,
-                                                   const int2 *__restrict__ bmap) {
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k_cpass_s32(
+    const Job *__restrict__ jobs, const int2 *__restrict__ bmap) {
+    extern __shared__ double smem[];
     const int2 jt = block_job(bmap);
     const Job &J = jobs[jt.x];
     int tx = jt.y % J.nCx, ty = jt.y / J.nCx;
@@ -698,7 +748,10 @@ __global__ __launch_bounds__(256) void k_cpass_s32(const Job *__restrict__ jobs,
         tx = l % J.nCx;
     }
     if (ty >= J.chunks || J.st->stop) return;
-    cpass_s32_tile<RT>(J, tx, ty);
+    if (tx < RT * (RT + 1) / 2)
+        cpass_s32_tile<RT, true>(J, tx, ty, smem);
+    else
+        cpass_s32_tile<RT, false>(J, tx, ty, smem);
 }
 
 }  // namespace
@@ -736,11 +789,12 @@ hipError_t launch_apass_s32(int mode, int rpad, const Job *jobs, const int2 *bma
 hipError_t launch_cpass_s32(int rpad, const Job *jobs, const int2 *bmap, int blocks,
                             hipStream_t s) {
     if (blocks <= 0) return hipSuccess;
+    const size_t lds = (size_t)kS32Stages * kS32Stage;
     switch (rpad) {
-        case 16: k_cpass_s32<1><<<blocks, 256, 0, s>>>(jobs, bmap); break;
-        case 32: k_cpass_s32<2><<<blocks, 256, 0, s>>>(jobs, bmap); break;
-        case 48: k_cpass_s32<3><<<blocks, 256, 0, s>>>(jobs, bmap); break;
-        case 64: k_cpass_s32<4><<<blocks, 256, 0, s>>>(jobs, bmap); break;
+        case 16: k_cpass_s32<1><<<blocks, 256, lds, s>>>(jobs, bmap); break;
+        case 32: k_cpass_s32<2><<<blocks, 256, lds, s>>>(jobs, bmap); break;
+        case 48: k_cpass_s32<3><<<blocks, 256, lds, s>>>(jobs, bmap); break;
+        case 64: k_cpass_s32<4><<<blocks, 256, lds, s>>>(jobs, bmap); break;
         default: return hipErrorInvalidValue;
     }
     return hipGetLastError();
@@ -796,7 +850,8 @@ static void stream_lds_attr(hipError_t &e) {
                           (const void *)k_apass_stream<RT, MODE_MU>,
                           (const void *)k_cpass_stream<RT>,
                           (const void *)k_apass_s32<RT, MODE_HALS>,
-                          (const void *)k_apass_s32<RT, MODE_MU>}) {
+                          (const void *)k_apass_s32<RT, MODE_MU>,
+                          (const void *)k_cpass_s32<RT>}) {
         const hipError_t x = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize,
                                                  160 * 1024);
         if (x != hipSuccess && e == hipSuccess) e = x;

@@ -114,10 +114,16 @@ def test_single_level_iterations_match_oracle(algo, h, w, n, r):
 
 @pytest.mark.parametrize("algo", ["hals", "mu"])
 @pytest.mark.parametrize("h,w,n,r", [(184, 184, 70, 10), (184, 184, 66, 20), (182, 184, 61, 40),
-                                     (184, 184, 64, 50)])
+                                     (184, 184, 64, 50), (182, 186, 300, 50),
+                                     (184, 184, 1300, 50)])
 def test_streaming_fp32_iterations_match_oracle(algo, h, w, n, r):
     """Levels with m >= 32768 use the FP32 streaming A- and C-pass kernels
-    (every rank class here); same parity bar as the regular kernels."""
+    (every rank class here); same parity bar as the regular kernels.  The
+    C-pass's D tiles ride on column blocks 0 .. nCx-1 and the rest take passes
+    over V alone: n <= 128 (one column block, all extra), n = 300 (three
+    blocks, mixed, with m = 33852 ending in a partial 16-row step) and
+    n = 1300 (eleven blocks: every tile fused, the last block partly past
+    n)."""
     say("streaming fp32", algo, h, w, n, r)
     spec = synth.BlobSpec(h=h, w=w, n=n, r=r, k_lo=1, k_hi=max(1, min(5, r)),
                           sig_lo=2.0, sig_hi=max(2.5, h / 4))
