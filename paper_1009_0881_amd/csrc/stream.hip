@@ -401,35 +401,70 @@ __global__ __launch_bounds__(256) void k_cpass_stream(const Job *__restrict__ jo
 // Streaming passes for large levels in FP32 mode (job.stream = 1, prec = 0):
 // m >= kStreamMinRows, m and the column stride of M multiples of 4, M 16-byte
 // aligned.  FP32 products are MFMA-bound (v_mfma_f32_16x16x4f32), so the
-// design keeps the matrix cores busy and M in flight to feed them: batches of
-// 4 K-steps, double buffered in registers.
-//
-// A-pass: a wave owns 32 rows.  Lane (li, lk) loads rows row0 + 2li, 2li + 1
-// of column 4ks + lk (8 bytes) and feeds them to two MFMAs, so MFMA s maps its
-// row index li to row row0 + 2li + s; its accumulator v of lane (li', lk')
-// holds A[row0 + 8lk' + 2v + s][16t + li'].  Every 4 K-steps (16 products per
-// chain) the accumulators are added into FP64 sums.  Past n the W operand is
-// zero (the M column read is clamped), so no load is conditional.  The V
-// update (FP64, as in the regular kernels) runs one s at a time: the wave's 16
-// rows of that s go to a wave-private LDS slot and lane q updates row
-// row0 + 2q + s, reading and writing V with one coalesced access per entry.
+// design keeps the matrix cores busy and M in flight to feed them: both
+// passes stage their operands in LDS by DMA, kS32Stages stages of 12 KB (one
+// K-step of 16 rows or columns: the 4 waves' 8 KB of M, 4 KB of the small
+// operand), kS32Stages - 1 of them in flight while one is multiplied, and
+// every wave issues kS32Ops copies per stage.  256 VGPRs, two waves per SIMD.
+// ---------------------------------------------------------------------------
+constexpr int kS32Stages = 6;
+constexpr int kS32Stage = 12 * 1024;
+constexpr int kS32Ops = 3;
+
+__device__ __forceinline__ void lds_dma16f(gmem<const float> *src, char *dst) {
+    __builtin_amdgcn_global_load_lds((gmem<const void> *)src, (lmem<void> *)dst, 16, 0, 0);
+}
+
+__device__ __forceinline__ v4f lds_v4f(const char *p) { return *(const lmem<v4f> *)p; }
+
+// A-pass: a wave owns 32 rows; the M columns and the rows of Wt (W
+// transposed, stride rpad) reach LDS by DMA, kS32Stages stages of 16 columns
+// (4 K-steps) deep.  Per stage a wave copies its 32 rows x 16 columns as two
+// 1 KB tiles (lane l: column 8h + l/8, rows 4(l%8) .. +3; LDS column-major,
+// 32 rows per column), and 1 KB w % rpad/16 of the stage's 16 x rpad block of
+// Wt (the 4 slots hold the block contiguously).  Lane (li, lk) then reads
+// rows 2li, 2li + 1 of column 4q + lk (K-step q) and W entries 16t + li of
+// that column (adjacent in a row of Wt, wt_pos) and feeds two MFMAs, so MFMA s maps its row index li to row
+// row0 + 2li + s; its accumulator v of lane (li', lk') holds
+// A[row0 + 8lk' + 2v + s][16t + li'].  Once per stage (16 products per chain)
+// the accumulators are added into FP64 sums.  Copies past n or m read a
+// clamped column or row; the W operand of columns past n is zeroed (only the
+// last kS32Stages - 1 stages can hold them) and rows past m are not stored.
+// The V update (FP64, as in the regular kernels) runs one s at a time: the
+// wave's 16 rows of that s go to a wave-private LDS slot and lane q updates
+// row row0 + 2q + s, reading and writing V with one coalesced access per
+// entry.  The Gram and the row slots reuse the stage memory.
 // ---------------------------------------------------------------------------
 template <int RT, int MODE>
 __device__ __forceinline__ void apass_s32_tile(const Job &J, int tile, double *smem) {
-    constexpr int RPAD = RT * 16, GS = RPAD, AS = RPAD + 1, RS = 2, SB = 4;
+    constexpr int RPAD = RT * 16, GS = RPAD, AS = RPAD + 1, RS = 2, NST = kS32Stages;
     typedef float v2f __attribute__((ext_vector_type(2)));
-    double *Gs = smem;
-    double *Gi = Gs + RPAD * GS;
-    const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+    char *pipe = reinterpret_cast<char *>(smem);
+    const int tid = threadIdx.x, lane = tid & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
     const int li = lane & 15, lk = lane >> 4;
     const int64_t m = J.m, n = J.n, ldm = J.ldm;
     const int r = J.r;
     const int64_t row0 = (int64_t)tile * 128 + wave * 32;
-    const int64_t rl = row0 + 2 * li;
-    const auto Mw = to_global(J.M) + (rl < m ? rl : m - 2);
+    const int ksteps = (int)((n + 15) / 16);
+    // copy sources: lane l takes column 8h + l/8 of the stage, rows 4(l%8) .. +3
+    int64_t rc = row0 + 4 * (lane & 7);
+    rc = rc < m ? rc : m - 4;   // m % 4 == 0
+    const auto Mr = to_global(J.M) + rc;
+    const int cl = lane >> 3;
     const auto Wt = to_global(J.Wt);
-    const int64_t nsteps = (n + 3) / 4;
-    const int64_t nb = (nsteps + SB - 1) / SB;            // batches (last one padded)
+    const int64_t wlast = n * RPAD - 4;   // last 16 bytes of Wt
+    const int64_t woff = 256 * (wave % RT) + 4 * lane;
+    auto issue = [&](int kk) {
+        char *st = pipe + (kk % NST) * kS32Stage;
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+            const int64_t j = 16 * (int64_t)kk + 8 * h + cl;
+            lds_dma16f(Mr + (j < n ? j : n - 1) * ldm, st + wave * 2048 + h * 1024);
+        }
+        const int64_t e = 16 * (int64_t)kk * RPAD + woff;
+        lds_dma16f(Wt + (e < wlast ? e : wlast), st + 8192 + wave * 1024);
+    };
     v4f acc[RS][RT];
     double hs[RS][RT][4];
 #pragma unroll
@@ -440,56 +475,61 @@ __device__ __forceinline__ void apass_s32_tile(const Job &J, int tile, double *s
 #pragma unroll
             for (int v = 0; v < 4; ++v) hs[s2][t][v] = 0.0;
         }
-    v2f a0[SB], a1[SB];
-    float b0[SB][RT], b1[SB][RT];
-    auto load = [&](int64_t bidx, v2f (&a)[SB], float (&b)[SB][RT]) {
+    auto mma = [&](int kk, bool tail) {
+        const char *st = pipe + (kk % NST) * kS32Stage;
 #pragma unroll
-        for (int u = 0; u < SB; ++u) {
-            const int64_t j = 4 * (bidx * SB + u) + lk;
-            const int64_t jc = j < n ? j : n - 1;
-            a[u] = *(gmem<const v2f> *)(Mw + jc * ldm);
-            float w[RT];
-            load_wt<RT>(Wt + jc * RPAD, li, w);
+        for (int q = 0; q < 4; ++q) {
+            const int c = 4 * q + lk;
+            const v2f a = *(const lmem<v2f> *)(st + wave * 2048 + c * 128 + 8 * li);
+            const bool dead = tail && 16 * (int64_t)kk + c >= n;
+            // W entries 16t + li of column c: contiguous in the interleaved Wt row
+            const char *wp = st + 8192 + (c * RPAD + li * RT) * 4;
+            float b[RT];
+            if constexpr (RT == 4) {
+                const v4f x = *(const lmem<v4f> *)wp;
+                b[0] = x[0]; b[1] = x[1]; b[2] = x[2]; b[3] = x[3];
+            } else if constexpr (RT == 2) {
+                const v2f x = *(const lmem<v2f> *)wp;
+                b[0] = x[0]; b[1] = x[1];
+            } else {
 #pragma unroll
-            for (int t = 0; t < RT; ++t) b[u][t] = j < n ? w[t] : 0.0f;
-        }
-    };
-    auto compute = [&](const v2f (&a)[SB], const float (&b)[SB][RT]) {
+                for (int t = 0; t < RT; ++t) b[t] = *(const lmem<float> *)(wp + 4 * t);
+            }
 #pragma unroll
-        for (int u = 0; u < SB; ++u) {
+            for (int t = 0; t < RT; ++t) b[t] = dead ? 0.0f : b[t];
 #pragma unroll
             for (int s2 = 0; s2 < RS; ++s2)
 #pragma unroll
                 for (int t = 0; t < RT; ++t)
-                    acc[s2][t] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[u][s2], b[u][t], acc[s2][t], 0, 0, 0);
-            if ((u & 3) == 3) {        // chains of 4 K-steps (16 products) into FP64
-#pragma unroll
-                for (int s2 = 0; s2 < RS; ++s2)
-#pragma unroll
-                    for (int t = 0; t < RT; ++t) {
-#pragma unroll
-                        for (int v = 0; v < 4; ++v) hs[s2][t][v] += (double)acc[s2][t][v];
-                        acc[s2][t] = v4f{0.0f, 0.0f, 0.0f, 0.0f};
-                    }
-            }
+                    acc[s2][t] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[s2], b[t], acc[s2][t], 0, 0, 0);
         }
+#pragma unroll
+        for (int s2 = 0; s2 < RS; ++s2)
+#pragma unroll
+            for (int t = 0; t < RT; ++t) {
+#pragma unroll
+                for (int v = 0; v < 4; ++v) hs[s2][t][v] += (double)acc[s2][t][v];
+                acc[s2][t] = v4f{0.0f, 0.0f, 0.0f, 0.0f};
+            }
     };
-    load(0, a0, b0);
+#pragma unroll
+    for (int kk = 0; kk < NST - 1; ++kk) issue(kk);
+    int kk = 0;
+    // stages kk <= ksteps - NST end at or before column 16 (ksteps - 1) < n
+    for (; kk < ksteps - (NST - 1); ++kk) {
+        vm_wait_barrier<kS32Ops * (NST - 2)>();   // stage kk landed, stage kk - 1 read
+        issue(kk + NST - 1);
+        mma(kk, false);
+    }
+    static_for<NST - 1>([&](auto j_c) {   // drain (stages past ksteps are wholly masked)
+        constexpr int j = decltype(j_c)::value;
+        vm_wait_barrier<kS32Ops * (NST - 2 - j)>();
+        mma(kk + j, true);
+    });
+    __syncthreads();   // every wave done with the stages
+    double *Gs = smem;
+    double *Gi = Gs + RPAD * GS;
     if constexpr (MODE != MODE_STORE) load_gram<RPAD>(J.Bd, r, Gs, GS, Gi);
-    int64_t bi = 0;
-    for (; bi + 2 < nb; bi += 2) {
-        load(bi + 1, a1, b1);
-        compute(a0, b0);
-        load(bi + 2, a0, b0);
-        compute(a1, b1);
-    }
-    if (bi + 1 < nb) {
-        load(bi + 1, a1, b1);
-        compute(a0, b0);
-        compute(a1, b1);
-    } else {
-        compute(a0, b0);
-    }
     double *Aw = Gi + RPAD + wave * 16 * AS;   // 16 rows of this wave (one s)
     __syncthreads();                            // Gram in LDS
     const auto V = to_global(J.V);
@@ -571,19 +611,6 @@ __device__ __forceinline__ void store_d_tile(const v4d &d, double *dl, gmem<doub
     }
     __syncthreads();
 }
-
-// FP32 streaming C-pass stages: one 16-row K-step each, holding the 4 waves'
-// two 1 KB M panels and four 1 KB V slots (slot w copied by wave w, tile
-// w % RT); kS32Stages - 1 K-steps are in flight while one is multiplied.
-constexpr int kS32Stages = 6;
-constexpr int kS32Stage = 12 * 1024;
-constexpr int kS32Ops = 3;   // copies one wave issues per stage
-
-__device__ __forceinline__ void lds_dma16f(gmem<const float> *src, char *dst) {
-    __builtin_amdgcn_global_load_lds((gmem<const void> *)src, (lmem<void> *)dst, 16, 0, 0);
-}
-
-__device__ __forceinline__ v4f lds_v4f(const char *p) { return *(const lmem<v4f> *)p; }
 
 // C-pass (FP32): a block of 4 waves owns 128 columns of one row chunk; a wave
 // owns 32 columns (two 16-column panels).  Per 16-row K-step lane (lj, g) of
@@ -760,10 +787,12 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k
 
 int cpass_stream_grid(int nCx, int chunks) { return 8 * nCx * ((chunks + 7) / 8); }
 
-// FP64 Gram (stride rpad) and 1/G_kk, then 4 waves x 16 rows of A (FP64,
-// stride rpad + 1).
+// The DMA stages, later the FP64 Gram (stride rpad) and 1/G_kk, then 4 waves
+// x 16 rows of A (FP64, stride rpad + 1).
 size_t apass_s32_lds_bytes(int rpad) {
-    return sizeof(double) * ((size_t)rpad * rpad + rpad + 4 * 16 * (size_t)(rpad + 1));
+    const size_t epi = sizeof(double) * ((size_t)rpad * rpad + rpad + 4 * 16 * (size_t)(rpad + 1));
+    const size_t pipe = (size_t)kS32Stages * kS32Stage;
+    return epi > pipe ? epi : pipe;
 }
 
 hipError_t launch_apass_s32(int mode, int rpad, const Job *jobs, const int2 *bmap, int blocks,
