@@ -555,10 +555,15 @@ __device__ __forceinline__ void apass_s32_tile(const Job &J, int tile, double *s
                         if (k < r) to_global(J.A)[row + (int64_t)k * m] = (float)arow[k];
                 }
             } else {
+                // all loads unconditional (clamped row and column), then masked,
+                // so that they are in flight together
+                const int64_t rc = live ? row : m - 1;
+                float xv[RPAD];
+#pragma unroll
+                for (int k = 0; k < RPAD; ++k) xv[k] = V[rc + (int64_t)(k < r ? k : 0) * m];
                 double x[RPAD];
 #pragma unroll
-                for (int k = 0; k < RPAD; ++k)
-                    x[k] = (live && k < r) ? (double)V[row + (int64_t)k * m] : 0.0;
+                for (int k = 0; k < RPAD; ++k) x[k] = (live && k < r) ? (double)xv[k] : 0.0;
                 stream_row_update<RPAD, MODE, double>(x, arow, Gs, Gi, r);
                 if (live) {
 #pragma unroll
