@@ -397,6 +397,73 @@ __global__ __launch_bounds__(256) void k_cpass_stream(const Job *__restrict__ jo
     cpass_stream_tile<RT>(J, tx, ty, smem);
 }
 
+// v summed over the 4 lanes of its quad (lanes 4q .. 4q+3), by two DPP
+// quad permutations; every lane of the quad gets the same sum.
+template <int CTRL>
+__device__ __forceinline__ double quad_dpp(double v) {
+    const int lo = __builtin_amdgcn_mov_dpp(__double2loint(v), CTRL, 0xF, 0xF, true);
+    const int hi = __builtin_amdgcn_mov_dpp(__double2hiint(v), CTRL, 0xF, 0xF, true);
+    return __hiloint2double(hi, lo);
+}
+
+__device__ __forceinline__ double quad_sum(double v) {
+    v += quad_dpp<0xB1>(v);   // quad_perm [1, 0, 3, 2]
+    return v + quad_dpp<0x4E>(v);   // quad_perm [2, 3, 0, 1]
+}
+
+// HALS (Alg. 3) or MU (Alg. 2) update of one row of V in FP64 by the 4 lanes
+// of a quad: lane p holds entries EP p .. EP p + EP - 1 (EP = RPAD / 4) of the
+// row in x.  Each Gram dot product sum_l x_l G_kl is split over the quad and
+// summed by DPP.  HALS takes k = 0 .. RPAD-1 in turn, x_k <- max(0, x_k +
+// (a_k - sum_l x_l G_kl) / G_kk), formed by the lane that owns k; MU forms all
+// the sums from the old x, then x_k <- x_k a_k / sum_l x_l G_kl.  Steps with
+// 1/G_kk = 0 (k >= r, or G_kk = 0) leave x_k as it is.  The loads of Gram row
+// k wait for the sum of step k - 2, so that at most two rows are in flight.
+template <int RPAD, int MODE>
+__device__ __forceinline__ void quad_row_update(double (&x)[RPAD / 4], const double *arow,
+                                                const double *G, const double *gi, int p, int r) {
+    typedef double v2d __attribute__((ext_vector_type(2)));
+    constexpr int EP = RPAD / 4;
+    double prev[2] = {0.0, 0.0};
+    auto dot = [&](int k, double dep) {
+        const double *g = G + ordered_after(k * RPAD + EP * p, dep);
+        double s0 = 0.0, s1 = 0.0;
+#pragma unroll
+        for (int i = 0; i < EP; i += 2) {
+            const v2d gv = *(const lmem<v2d> *)(g + i);
+            s0 = fma_t(x[i], gv[0], s0);
+            s1 = fma_t(x[i + 1], gv[1], s1);
+        }
+        return quad_sum(s0 + s1);
+    };
+    if constexpr (MODE == MODE_HALS) {
+        static_for<RPAD>([&](auto k_c) {
+            constexpr int k = decltype(k_c)::value, ik = k % EP;
+            const double d = dot(k, prev[k & 1]);
+            prev[k & 1] = d;
+            const double gk = gi[k];
+            const double c = x[ik] + (arow[k] - d) * gk;
+            const double nx = gk > 0.0 ? (c > 0.0 ? c : 0.0) : x[ik];
+            x[ik] = p == k / EP ? nx : x[ik];
+        });
+    } else {
+        double den[EP];
+#pragma unroll
+        for (int i = 0; i < EP; ++i) den[i] = 0.0;
+        static_for<RPAD>([&](auto k_c) {
+            constexpr int k = decltype(k_c)::value, ik = k % EP;
+            const double d = dot(k, prev[k & 1]);
+            prev[k & 1] = d;
+            den[ik] = p == k / EP ? d : den[ik];
+        });
+#pragma unroll
+        for (int i = 0; i < EP; ++i) {
+            const int k = EP * p + i;
+            if (k < r && den[i] > 0.0) x[i] = x[i] * arow[k] / den[i];
+        }
+    }
+}
+
 // ---------------------------------------------------------------------------
 // Streaming passes for large levels in FP32 mode (job.stream = 1, prec = 0):
 // m >= kStreamMinRows, m and the column stride of M multiples of 4, M 16-byte
@@ -431,9 +498,9 @@ __device__ __forceinline__ v4f lds_v4f(const char *p) { return *(const lmem<v4f>
 // clamped column or row; the W operand of columns past n is zeroed (only the
 // last kS32Stages - 1 stages can hold them) and rows past m are not stored.
 // The V update (FP64, as in the regular kernels) runs one s at a time: the
-// wave's 16 rows of that s go to a wave-private LDS slot and lane q updates
-// row row0 + 2q + s, reading and writing V with one coalesced access per
-// entry.  The Gram and the row slots reuse the stage memory.
+// wave's 16 rows of that s go to a wave-private LDS slot and the quad of
+// lanes 4q .. 4q+3 updates row row0 + 2q + s (quad_row_update).  The Gram and
+// the row slots reuse the stage memory.
 // ---------------------------------------------------------------------------
 template <int RT, int MODE>
 __device__ __forceinline__ void apass_s32_tile(const Job &J, int tile, double *smem) {
@@ -544,31 +611,39 @@ __device__ __forceinline__ void apass_s32_tile(const Job &J, int tile, double *s
         __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
         __builtin_amdgcn_wave_barrier();
         __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-        if (lane < 16) {
-            const int64_t row = row0 + 2 * lane + s2;
-            const bool live = row < m;
-            const double *arow = Aw + lane * AS;
-            if constexpr (MODE == MODE_STORE) {
-                if (live) {
+        // lane 4q + p: entries EP p .. EP p + EP - 1 of row row0 + 2q + s2
+        constexpr int EP = RPAD / 4;
+        const int q = lane >> 2, p = lane & 3;
+        const int64_t row = row0 + 2 * q + s2;
+        const bool live = row < m;
+        const double *arow = Aw + q * AS;
+        if constexpr (MODE == MODE_STORE) {
+            if (live) {
 #pragma unroll
-                    for (int k = 0; k < RPAD; ++k)
-                        if (k < r) to_global(J.A)[row + (int64_t)k * m] = (float)arow[k];
+                for (int i = 0; i < EP; ++i) {
+                    const int k = EP * p + i;
+                    if (k < r) to_global(J.A)[row + (int64_t)k * m] = (float)arow[k];
                 }
-            } else {
-                // all loads unconditional (clamped row and column), then masked,
-                // so that they are in flight together
-                const int64_t rc = live ? row : m - 1;
-                float xv[RPAD];
+            }
+        } else {
+            // all loads unconditional (clamped row and column), then masked,
+            // so that they are in flight together
+            const int64_t rc = live ? row : m - 1;
+            float xv[EP];
 #pragma unroll
-                for (int k = 0; k < RPAD; ++k) xv[k] = V[rc + (int64_t)(k < r ? k : 0) * m];
-                double x[RPAD];
+            for (int i = 0; i < EP; ++i) {
+                const int k = EP * p + i;
+                xv[i] = V[rc + (int64_t)(k < r ? k : 0) * m];
+            }
+            double x[EP];
 #pragma unroll
-                for (int k = 0; k < RPAD; ++k) x[k] = (live && k < r) ? (double)xv[k] : 0.0;
-                stream_row_update<RPAD, MODE, double>(x, arow, Gs, Gi, r);
-                if (live) {
+            for (int i = 0; i < EP; ++i) x[i] = (live && EP * p + i < r) ? (double)xv[i] : 0.0;
+            quad_row_update<RPAD, MODE>(x, arow, Gs, Gi, p, r);
+            if (live) {
 #pragma unroll
-                    for (int k = 0; k < RPAD; ++k)
-                        if (k < r) V[row + (int64_t)k * m] = (float)x[k];
+                for (int i = 0; i < EP; ++i) {
+                    const int k = EP * p + i;
+                    if (k < r) V[row + (int64_t)k * m] = (float)x[i];
                 }
             }
         }
