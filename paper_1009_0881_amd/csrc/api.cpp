@@ -69,8 +69,8 @@ void prof_collect(nmf_plan_t plan) {
 void set_fp32_stream(Job &J, const LevelInfo &li, const Plan &p) {
     if (!li.fstream || (J.ldm & 3) != 0 || (reinterpret_cast<uintptr_t>(J.M) & 15) != 0) return;
     J.stream = 1;
-    J.tm = 128;
-    J.nA = (int32_t)((li.m + 127) / 128);
+    J.tm = li.m >= 65536 ? 128 : 64;   // A-pass rows per block (RS = 2 or 1)
+    J.nA = (int32_t)((li.m + J.tm - 1) / J.tm);
     J.nCx = (int32_t)((p.d.n + 127) / 128);
     J.chunks = li.fcp_chunks;
     J.chunk = li.fcp_chunk;

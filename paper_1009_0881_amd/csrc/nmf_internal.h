@@ -198,6 +198,8 @@ int cpass_grid_single(int nCx, int chunks);
 // Streaming BF16 passes (job.stream): A-pass tiles of kStreamARows rows (nA blocks),
 // C-pass tiles of 256 columns x one row chunk (XCD-ordered grid).
 constexpr int64_t kStreamMinRows = 32768;
+// FP32 streaming passes (job.stream with prec = 0): levels with m >= 16384.
+constexpr int64_t kFStreamMinRows = 16384;
 constexpr int kStreamARows = 256;   // rows per block of the streaming BF16 A-pass
 hipError_t launch_apass_stream(int mode, int rpad, const Job *jobs, const int2 *bmap, int blocks,
                                hipStream_t s);

@@ -171,7 +171,7 @@ nmf_status build_plan(const nmf_desc &d0, Plan &p, std::string &err) {
         li.cp_chunks = (int32_t)((li.m + chunk - 1) / chunk);
         max_cp = std::max<size_t>(max_cp, (size_t)li.cp_chunks);
         // FP32 streaming C-pass (large levels): about two blocks per CU
-        li.fstream = d.algo != NMF_ANLS && li.m >= kStreamMinRows && li.m % 4 == 0;
+        li.fstream = d.algo != NMF_ANLS && li.m >= kFStreamMinRows && li.m % 4 == 0;
         if (li.fstream) {
             const int64_t ncx = (d.n + 127) / 128;
             int64_t sc = std::max<int64_t>(1, 2 * p.num_cu / ncx);

@@ -1,7 +1,7 @@
-// Streaming passes for large levels (m >= kStreamMinRows): the A-pass and
-// C-pass of one iteration (Alg. 2 / Alg. 3) as long register-pipelined loops
-// over the whole of n (A-pass) or a long row chunk (C-pass), in BF16 (k_*_stream)
-// or FP32 (k_*_s32).  The Gram, reduction and W-update kernels are those of
+// Streaming passes for large levels: the A-pass and C-pass of one iteration
+// (Alg. 2 / Alg. 3) as long LDS-pipelined loops over the whole of n (A-pass)
+// or a long row chunk (C-pass), in BF16 (k_*_stream, m >= kStreamMinRows) or
+// FP32 (k_*_s32, m >= kFStreamMinRows).  The Gram, reduction and W-update kernels are those of
 // the regular path.
 
 #include "sweep_device.h"
@@ -466,13 +466,14 @@ __device__ __forceinline__ void quad_row_update(double (&x)[RPAD / 4], const dou
 
 // ---------------------------------------------------------------------------
 // Streaming passes for large levels in FP32 mode (job.stream = 1, prec = 0):
-// m >= kStreamMinRows, m and the column stride of M multiples of 4, M 16-byte
+// m >= kFStreamMinRows, m and the column stride of M multiples of 4, M 16-byte
 // aligned.  FP32 products are MFMA-bound (v_mfma_f32_16x16x4f32), so the
 // design keeps the matrix cores busy and M in flight to feed them: both
 // passes stage their operands in LDS by DMA, kS32Stages stages of 12 KB (one
 // K-step of 16 rows or columns: the 4 waves' 8 KB of M, 4 KB of the small
 // operand), kS32Stages - 1 of them in flight while one is multiplied, and
-// every wave issues kS32Ops copies per stage.  256 VGPRs, two waves per SIMD.
+// every wave issues kS32Ops copies per stage in the C-pass (RS + 1 in the
+// A-pass).  256 VGPRs, two waves per SIMD.
 // ---------------------------------------------------------------------------
 constexpr int kS32Stages = 6;
 constexpr int kS32Stage = 12 * 1024;
@@ -484,27 +485,34 @@ __device__ __forceinline__ void lds_dma16f(gmem<const float> *src, char *dst) {
 
 __device__ __forceinline__ v4f lds_v4f(const char *p) { return *(const lmem<v4f> *)p; }
 
-// A-pass: a wave owns 32 rows; the M columns and the rows of Wt (W
-// transposed, stride rpad) reach LDS by DMA, kS32Stages stages of 16 columns
-// (4 K-steps) deep.  Per stage a wave copies its 32 rows x 16 columns as two
-// 1 KB tiles (lane l: column 8h + l/8, rows 4(l%8) .. +3; LDS column-major,
-// 32 rows per column), and 1 KB w % rpad/16 of the stage's 16 x rpad block of
-// Wt (the 4 slots hold the block contiguously).  Lane (li, lk) then reads
-// rows 2li, 2li + 1 of column 4q + lk (K-step q) and W entries 16t + li of
-// that column (adjacent in a row of Wt, wt_pos) and feeds two MFMAs, so MFMA s maps its row index li to row
-// row0 + 2li + s; its accumulator v of lane (li', lk') holds
-// A[row0 + 8lk' + 2v + s][16t + li'].  Once per stage (16 products per chain)
-// the accumulators are added into FP64 sums.  Copies past n or m read a
-// clamped column or row; the W operand of columns past n is zeroed (only the
-// last kS32Stages - 1 stages can hold them) and rows past m are not stored.
-// The V update (FP64, as in the regular kernels) runs one s at a time: the
-// wave's 16 rows of that s go to a wave-private LDS slot and the quad of
-// lanes 4q .. 4q+3 updates row row0 + 2q + s (quad_row_update).  The Gram and
-// the row slots reuse the stage memory.
+// A-pass: a wave owns RW = 16 RS rows (RS = 2, 128-row blocks, from
+// m = 65536; RS = 1, 64-row blocks, on smaller levels so that the grid still
+// fills the chip); the M columns and the rows of Wt (W transposed, stride
+// rpad) reach LDS by DMA, kS32Stages stages of 16 columns (4 K-steps) deep.
+// Per stage a wave copies its RW rows x 16 columns as RS 1 KB tiles (lane l:
+// column CPD h + l/LPC, rows 4(l%LPC) .. +3; LDS column-major, RW rows per
+// column), and 1 KB w % rpad/16 of the stage's 16 x rpad block of Wt (the 4
+// slots hold the block contiguously): RS + 1 copies.  Lane (li, lk) then
+// reads rows RS li .. RS li + RS - 1 of column 4q + lk (K-step q) and W
+// entries 16t + li of that column (adjacent in a row of Wt, wt_pos) and feeds
+// RS MFMAs, so MFMA s maps its row index li to row row0 + RS li + s; its
+// accumulator v of lane (li', lk') holds A[row0 + RS(4lk' + v) + s][16t + li'].
+// Once per stage (16 products per chain) the accumulators are added into FP64
+// sums.  Copies past n or m read a clamped column or row; the W operand of
+// columns past n is zeroed (only the last kS32Stages - 1 stages can hold
+// them) and rows past m are not stored.  The V update (FP64, as in the
+// regular kernels) runs one s at a time: the wave's 16 rows of that s go to a
+// wave-private LDS slot and the quad of lanes 4q .. 4q+3 updates row
+// row0 + RS q + s (quad_row_update).  The Gram and the row slots reuse the
+// stage memory.
 // ---------------------------------------------------------------------------
-template <int RT, int MODE>
+template <int RT, int MODE, int RS>
 __device__ __forceinline__ void apass_s32_tile(const Job &J, int tile, double *smem) {
-    constexpr int RPAD = RT * 16, GS = RPAD, AS = RPAD + 1, RS = 2, NST = kS32Stages;
+    constexpr int RPAD = RT * 16, GS = RPAD, AS = RPAD + 1, NST = kS32Stages;
+    constexpr int RW = 16 * RS;      // rows per wave
+    constexpr int LPC = RW / 4;      // copy lanes per column (4 rows each)
+    constexpr int CPD = 64 / LPC;    // columns per 1 KB copy
+    constexpr int WOFF = 4096 * RS;  // Wt slots after the M tiles
     typedef float v2f __attribute__((ext_vector_type(2)));
     char *pipe = reinterpret_cast<char *>(smem);
     const int tid = threadIdx.x, lane = tid & 63;
@@ -512,25 +520,26 @@ __device__ __forceinline__ void apass_s32_tile(const Job &J, int tile, double *s
     const int li = lane & 15, lk = lane >> 4;
     const int64_t m = J.m, n = J.n, ldm = J.ldm;
     const int r = J.r;
-    const int64_t row0 = (int64_t)tile * 128 + wave * 32;
+    const int64_t row0 = (int64_t)tile * 4 * RW + wave * RW;
     const int ksteps = (int)((n + 15) / 16);
-    // copy sources: lane l takes column 8h + l/8 of the stage, rows 4(l%8) .. +3
-    int64_t rc = row0 + 4 * (lane & 7);
+    // copy sources: lane l takes column CPD h + l/LPC of the stage, rows
+    // 4(l%LPC) .. +3
+    int64_t rc = row0 + 4 * (lane % LPC);
     rc = rc < m ? rc : m - 4;   // m % 4 == 0
     const auto Mr = to_global(J.M) + rc;
-    const int cl = lane >> 3;
+    const int cl = lane / LPC;
     const auto Wt = to_global(J.Wt);
     const int64_t wlast = n * RPAD - 4;   // last 16 bytes of Wt
     const int64_t woff = 256 * (wave % RT) + 4 * lane;
     auto issue = [&](int kk) {
         char *st = pipe + (kk % NST) * kS32Stage;
 #pragma unroll
-        for (int h = 0; h < 2; ++h) {
-            const int64_t j = 16 * (int64_t)kk + 8 * h + cl;
-            lds_dma16f(Mr + (j < n ? j : n - 1) * ldm, st + wave * 2048 + h * 1024);
+        for (int h = 0; h < RS; ++h) {
+            const int64_t j = 16 * (int64_t)kk + CPD * h + cl;
+            lds_dma16f(Mr + (j < n ? j : n - 1) * ldm, st + wave * 1024 * RS + h * 1024);
         }
         const int64_t e = 16 * (int64_t)kk * RPAD + woff;
-        lds_dma16f(Wt + (e < wlast ? e : wlast), st + 8192 + wave * 1024);
+        lds_dma16f(Wt + (e < wlast ? e : wlast), st + WOFF + wave * 1024);
     };
     v4f acc[RS][RT];
     double hs[RS][RT][4];
@@ -547,10 +556,18 @@ __device__ __forceinline__ void apass_s32_tile(const Job &J, int tile, double *s
 #pragma unroll
         for (int q = 0; q < 4; ++q) {
             const int c = 4 * q + lk;
-            const v2f a = *(const lmem<v2f> *)(st + wave * 2048 + c * 128 + 8 * li);
+            // rows RS li .. RS li + RS - 1 of column c (LDS: RW rows per column)
+            const char *ap = st + wave * 1024 * RS + c * 4 * RW + 4 * RS * li;
+            float a[RS];
+            if constexpr (RS == 2) {
+                const v2f x = *(const lmem<v2f> *)ap;
+                a[0] = x[0]; a[1] = x[1];
+            } else {
+                a[0] = *(const lmem<float> *)ap;
+            }
             const bool dead = tail && 16 * (int64_t)kk + c >= n;
             // W entries 16t + li of column c: contiguous in the interleaved Wt row
-            const char *wp = st + 8192 + (c * RPAD + li * RT) * 4;
+            const char *wp = st + WOFF + (c * RPAD + li * RT) * 4;
             float b[RT];
             if constexpr (RT == 4) {
                 const v4f x = *(const lmem<v4f> *)wp;
@@ -584,13 +601,13 @@ __device__ __forceinline__ void apass_s32_tile(const Job &J, int tile, double *s
     int kk = 0;
     // stages kk <= ksteps - NST end at or before column 16 (ksteps - 1) < n
     for (; kk < ksteps - (NST - 1); ++kk) {
-        vm_wait_barrier<kS32Ops * (NST - 2)>();   // stage kk landed, stage kk - 1 read
+        vm_wait_barrier<(RS + 1) * (NST - 2)>();   // stage kk landed, stage kk - 1 read
         issue(kk + NST - 1);
         mma(kk, false);
     }
     static_for<NST - 1>([&](auto j_c) {   // drain (stages past ksteps are wholly masked)
         constexpr int j = decltype(j_c)::value;
-        vm_wait_barrier<kS32Ops * (NST - 2 - j)>();
+        vm_wait_barrier<(RS + 1) * (NST - 2 - j)>();
         mma(kk + j, true);
     });
     __syncthreads();   // every wave done with the stages
@@ -603,7 +620,7 @@ __device__ __forceinline__ void apass_s32_tile(const Job &J, int tile, double *s
     static_for<RS>([&](auto s_c) {
         constexpr int s2 = decltype(s_c)::value;
         __builtin_amdgcn_wave_barrier();
-        // hs[s2][t][v] = A[row0 + 2 q + s2][16t + li] with q = 4 lk + v
+        // hs[s2][t][v] = A[row0 + RS q + s2][16t + li] with q = 4 lk + v
 #pragma unroll
         for (int t = 0; t < RT; ++t)
 #pragma unroll
@@ -611,10 +628,10 @@ __device__ __forceinline__ void apass_s32_tile(const Job &J, int tile, double *s
         __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
         __builtin_amdgcn_wave_barrier();
         __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-        // lane 4q + p: entries EP p .. EP p + EP - 1 of row row0 + 2q + s2
+        // lane 4q + p: entries EP p .. EP p + EP - 1 of row row0 + RS q + s2
         constexpr int EP = RPAD / 4;
         const int q = lane >> 2, p = lane & 3;
-        const int64_t row = row0 + 2 * q + s2;
+        const int64_t row = row0 + RS * q + s2;
         const bool live = row < m;
         const double *arow = Aw + q * AS;
         if constexpr (MODE == MODE_STORE) {
@@ -657,7 +674,10 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k
     const int2 jt = block_job(bmap);
     const Job &J = jobs[jt.x];
     if (jt.y >= J.nA || J.st->stop) return;
-    apass_s32_tile<RT, MODE>(J, jt.y, smem);
+    if (J.tm == 64)
+        apass_s32_tile<RT, MODE, 1>(J, jt.y, smem);
+    else
+        apass_s32_tile<RT, MODE, 2>(J, jt.y, smem);
 }
 
 // (ta, tb) of upper 16x16 tile idx of an RT x RT tile grid, row by row.

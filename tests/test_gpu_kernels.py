@@ -115,10 +115,14 @@ def test_single_level_iterations_match_oracle(algo, h, w, n, r):
 @pytest.mark.parametrize("algo", ["hals", "mu"])
 @pytest.mark.parametrize("h,w,n,r", [(184, 184, 70, 10), (184, 184, 66, 20), (182, 184, 61, 40),
                                      (184, 184, 64, 50), (182, 186, 300, 50),
-                                     (184, 184, 1300, 50)])
+                                     (184, 184, 1300, 50), (128, 130, 90, 30),
+                                     (258, 262, 90, 50)])
 def test_streaming_fp32_iterations_match_oracle(algo, h, w, n, r):
-    """Levels with m >= 32768 use the FP32 streaming A- and C-pass kernels
+    """Levels with m >= 16384 use the FP32 streaming A- and C-pass kernels
     (every rank class here); same parity bar as the regular kernels.  The
+    A-pass takes 64-row blocks below m = 65536 (m = 16640 and 33852 .. 33856
+    here) and 128-row blocks from there (m = 67596, ending in a partial
+    block).  The
     C-pass's D tiles ride on column blocks 0 .. nCx-1 and the rest take passes
     over V alone: n <= 128 (one column block, all extra), n = 300 (three
     blocks, mixed, with m = 33852 ending in a partial 16-row step) and
