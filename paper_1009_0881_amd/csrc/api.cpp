@@ -69,8 +69,9 @@ void prof_collect(nmf_plan_t plan) {
 void set_fp32_stream(Job &J, const LevelInfo &li, const Plan &p) {
     if (!li.fstream || (J.ldm & 3) != 0 || (reinterpret_cast<uintptr_t>(J.M) & 15) != 0) return;
     J.stream = 1;
-    J.tm = li.m >= 65536 ? 128 : 64;   // A-pass rows per block (RS = 2 or 1)
+    J.tm = li.ftm;   // A-pass rows per block (RS = 2 or 1)
     J.nA = (int32_t)((li.m + J.tm - 1) / J.tm);
+    J.aks = li.aks;
     J.nCx = (int32_t)((p.d.n + 127) / 128);
     J.chunks = li.fcp_chunks;
     J.chunk = li.fcp_chunk;
@@ -157,6 +158,7 @@ Ctx make_ctx(nmf_plan_t plan, const float *dM, float *dV, float *dW, void *dws, 
         J.tol = p.d.tol;
         J.prec = 0;
         J.stream = 0;
+        J.aks = 1;
         if (p.d.prec == NMF_FP32 && allow_stream) set_fp32_stream(J, li, p);
         if (p.d.prec == NMF_BF16) {
             J.prec = 1;
@@ -294,8 +296,11 @@ nmf_status sweep(Ctx &c, int d, bool fp32 = false) {
     const int mode = p.d.algo == NMF_HALS ? 0 : (p.d.algo == NMF_MU ? 1 : 2);
     if (J.stream && bf)
         NMF_LAUNCH(K_APASS, launch_apass_stream(mode, J.rpad, dj, nullptr, J.nA, c.s));
-    else if (J.stream)
-        NMF_LAUNCH(K_APASS, launch_apass_s32(mode, J.rpad, dj, nullptr, J.nA, c.s));
+    else if (J.stream) {
+        NMF_LAUNCH(K_APASS, launch_apass_s32(mode, J.rpad, dj, nullptr, J.nA * J.aks, c.s));
+        if (J.aks > 1)
+            NMF_LAUNCH(K_APASS, launch_afinal_s32(mode, J.rpad, dj, nullptr, J.nA, c.s));
+    }
     else
         NMF_LAUNCH(K_APASS, launch_apass_jobs(mode, J.rpad, J.tm, dj, nullptr,
                                               apass_grid_single(J.nA),

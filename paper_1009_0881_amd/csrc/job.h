@@ -58,6 +58,9 @@ struct Job {
     int32_t prec;
     int32_t stream;      // 1: streaming A/C-pass kernels (large BF16 levels): A-pass
                          // tiles of kStreamARows rows, C-pass tiles of 256 columns
+    int32_t aks;         // FP32 streaming A-pass: the n-reduction split over aks blocks
+                         // per row tile (1: none); the partial rows of A (FP64, aks x
+                         // nA tm x rpad) occupy Cp until the second half has used them
 };
 
 }  // namespace nmf

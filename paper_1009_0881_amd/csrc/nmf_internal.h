@@ -54,7 +54,9 @@ struct LevelInfo {
     bool stream;         // BF16 mode, large level: streaming A/C-pass kernels
     int32_t scp_chunks;  // split of the m-reduction for the streaming C-pass
     int64_t scp_chunk;
-    bool fstream;        // large level: FP32 streaming kernels possible (m % 4 == 0)
+    bool fstream;        // large or wide level: FP32 streaming kernels possible (m % 4 == 0)
+    int32_t ftm;         // FP32 streaming A-pass rows per block (64 or 128)
+    int32_t aks;         // FP32 streaming A-pass: split of the n-reduction (1: none)
     int32_t fcp_chunks;  // split of the m-reduction for the FP32 streaming C-pass
     int64_t fcp_chunk;
     int32_t gram_parts;  // split of the length-m reduction of V^T V
@@ -198,8 +200,12 @@ int cpass_grid_single(int nCx, int chunks);
 // Streaming BF16 passes (job.stream): A-pass tiles of kStreamARows rows (nA blocks),
 // C-pass tiles of 256 columns x one row chunk (XCD-ordered grid).
 constexpr int64_t kStreamMinRows = 32768;
-// FP32 streaming passes (job.stream with prec = 0): levels with m >= 16384.
+// FP32 streaming passes (job.stream with prec = 0): levels with m >= 16384,
+// and, in plans whose finest level has m >= 16384, the coarser levels with
+// m >= 1024 and n >= 1024 (there the regular A-pass, one block over all of n
+// per row tile, is bound by its serial K loop).
 constexpr int64_t kFStreamMinRows = 16384;
+constexpr int64_t kFStreamWideRows = 1024, kFStreamWideCols = 1024;
 constexpr int kStreamARows = 256;   // rows per block of the streaming BF16 A-pass
 hipError_t launch_apass_stream(int mode, int rpad, const Job *jobs, const int2 *bmap, int blocks,
                                hipStream_t s);
@@ -213,6 +219,9 @@ hipError_t launch_apass_s32(int mode, int rpad, const Job *jobs, const int2 *bma
 hipError_t launch_cpass_s32(int rpad, const Job *jobs, const int2 *bmap, int blocks,
                             hipStream_t s);
 size_t apass_s32_lds_bytes(int rpad);
+// Second half of a split FP32 streaming A-pass (job.aks > 1): nA blocks.
+hipError_t launch_afinal_s32(int mode, int rpad, const Job *jobs, const int2 *bmap, int blocks,
+                             hipStream_t s);
 size_t apass_stream_lds_bytes(int rpad);
 hipError_t launch_make_wt(const float *W, int64_t n, int r, int rpad, float *Wt, hipStream_t s);
 // Residual from separately computed Grams (ANLS path): rel_err of

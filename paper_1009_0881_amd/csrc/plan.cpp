@@ -158,7 +158,7 @@ nmf_status build_plan(const nmf_desc &d0, Plan &p, std::string &err) {
     // Split of the length-m reductions.  Target about one block per CU for
     // V^T M (deterministic split-m partials) and at most 256 Gram partials.
     const int64_t ntiles = (d.n + 63) / 64;
-    size_t max_cp = 0, max_gp = 0;
+    size_t max_cp = 0, max_gp = 0, max_ap = 0;
     for (auto &li : p.lv) {
         int64_t chunks = std::max<int64_t>(1, p.num_cu / std::max<int64_t>(1, ntiles));
         chunks = std::min<int64_t>(chunks, std::max<int64_t>(1, (li.m + 63) / 64));
@@ -171,8 +171,25 @@ nmf_status build_plan(const nmf_desc &d0, Plan &p, std::string &err) {
         li.cp_chunks = (int32_t)((li.m + chunk - 1) / chunk);
         max_cp = std::max<size_t>(max_cp, (size_t)li.cp_chunks);
         // FP32 streaming C-pass (large levels): about two blocks per CU
-        li.fstream = d.algo != NMF_ANLS && li.m >= kFStreamMinRows && li.m % 4 == 0;
+        // wide coarse levels stream only in plans whose finest level does
+        // (plans that never stream give the same bits alone and in a batch)
+        li.fstream = d.algo != NMF_ANLS && li.m % 4 == 0 &&
+                     (li.m >= kFStreamMinRows ||
+                      (p.lv[0].m >= kFStreamMinRows && li.m >= kFStreamWideRows &&
+                       d.n >= kFStreamWideCols));
+        li.ftm = li.m >= 65536 ? 128 : 64;
+        li.aks = 1;
         if (li.fstream) {
+            // A-pass: split the n-reduction until there are about as many
+            // blocks as CUs, into at most 8 parts of at least 4 stages of 16
+            // columns
+            const int64_t tiles = (li.m + li.ftm - 1) / li.ftm;
+            const int64_t stages = (d.n + 15) / 16;
+            int64_t ks = (p.num_cu + tiles - 1) / tiles;
+            ks = std::min<int64_t>({ks, std::max<int64_t>(1, stages / 4), 8});
+            li.aks = li.ftm == 64 ? (int32_t)std::max<int64_t>(1, ks) : 1;   // k_afinal_s32: 64-row tiles
+            if (li.aks > 1)
+                max_ap = std::max<size_t>(max_ap, (size_t)li.aks * tiles * li.ftm * p.rpad);
             const int64_t ncx = (d.n + 127) / 128;
             int64_t sc = std::max<int64_t>(1, 2 * p.num_cu / ncx);
             sc = std::min<int64_t>(sc, std::max<int64_t>(1, li.m / 64));
@@ -229,7 +246,9 @@ nmf_status build_plan(const nmf_desc &d0, Plan &p, std::string &err) {
     ws.off_Df = take(sizeof(float) * rr);
     ws.gparts_cap = max_gp * rp2;
     ws.off_gparts = take(sizeof(double) * ws.gparts_cap);
-    ws.off_cparts = take(sizeof(double) * max_cp * r * n);
+    // C-pass partials; also the split A-pass's partial rows of A (FP32
+    // streaming levels with aks > 1), which are used up before the C-pass runs
+    ws.off_cparts = take(sizeof(double) * std::max<size_t>(max_cp * r * n, max_ap));
     ws.rparts_cap = std::max<size_t>({(size_t)cpass_final_blocks(d.n),
                                       (size_t)nnls_cols_blocks(d.n), (size_t)1024});
     ws.off_rparts = take(sizeof(double) * ws.rparts_cap);

@@ -464,6 +464,54 @@ __device__ __forceinline__ void quad_row_update(double (&x)[RPAD / 4], const dou
     }
 }
 
+// The V update of 16 rows first, first + step, ... of one wave from their rows
+// of A in LDS (Aw, stride rpad + 1, FP64): the quad of lanes 4q .. 4q+3 takes
+// row first + step q (quad_row_update); MODE_STORE stores A instead.  V (or
+// A) is read and written only for rows < m.
+template <int RPAD, int MODE>
+__device__ __forceinline__ void update_rows(const Job &J, const double *Aw, const double *Gs,
+                                            const double *Gi, int64_t first, int step) {
+    constexpr int AS = RPAD + 1, EP = RPAD / 4;
+    const int lane = threadIdx.x & 63, q = lane >> 2, p = lane & 3;
+    const int64_t m = J.m;
+    const int r = J.r;
+    const auto V = to_global(J.V);
+    // lane 4q + p: entries EP p .. EP p + EP - 1 of row first + step q
+    const int64_t row = first + (int64_t)step * q;
+    const bool live = row < m;
+    const double *arow = Aw + q * AS;
+    if constexpr (MODE == MODE_STORE) {
+        if (live) {
+#pragma unroll
+            for (int i = 0; i < EP; ++i) {
+                const int k = EP * p + i;
+                if (k < r) to_global(J.A)[row + (int64_t)k * m] = (float)arow[k];
+            }
+        }
+    } else {
+        // all loads unconditional (clamped row and column), then masked, so
+        // that they are in flight together
+        const int64_t rc = live ? row : m - 1;
+        float xv[EP];
+#pragma unroll
+        for (int i = 0; i < EP; ++i) {
+            const int k = EP * p + i;
+            xv[i] = V[rc + (int64_t)(k < r ? k : 0) * m];
+        }
+        double x[EP];
+#pragma unroll
+        for (int i = 0; i < EP; ++i) x[i] = (live && EP * p + i < r) ? (double)xv[i] : 0.0;
+        quad_row_update<RPAD, MODE>(x, arow, Gs, Gi, p, r);
+        if (live) {
+#pragma unroll
+            for (int i = 0; i < EP; ++i) {
+                const int k = EP * p + i;
+                if (k < r) V[row + (int64_t)k * m] = (float)x[i];
+            }
+        }
+    }
+}
+
 // ---------------------------------------------------------------------------
 // Streaming passes for large levels in FP32 mode (job.stream = 1, prec = 0):
 // m >= kFStreamMinRows, m and the column stride of M multiples of 4, M 16-byte
@@ -507,7 +555,7 @@ __device__ __forceinline__ v4f lds_v4f(const char *p) { return *(const lmem<v4f>
 // stage memory.
 // ---------------------------------------------------------------------------
 template <int RT, int MODE, int RS>
-__device__ __forceinline__ void apass_s32_tile(const Job &J, int tile, double *smem) {
+__device__ __forceinline__ void apass_s32_tile(const Job &J, int tile, int part, double *smem) {
     constexpr int RPAD = RT * 16, GS = RPAD, AS = RPAD + 1, NST = kS32Stages;
     constexpr int RW = 16 * RS;      // rows per wave
     constexpr int LPC = RW / 4;      // copy lanes per column (4 rows each)
@@ -521,7 +569,13 @@ __device__ __forceinline__ void apass_s32_tile(const Job &J, int tile, double *s
     const int64_t m = J.m, n = J.n, ldm = J.ldm;
     const int r = J.r;
     const int64_t row0 = (int64_t)tile * 4 * RW + wave * RW;
-    const int ksteps = (int)((n + 15) / 16);
+    // this block's stages kb .. ke-1 (all of n unless the reduction is split)
+    const int nstage = (int)((n + 15) / 16);
+    const int per = (nstage + J.aks - 1) / J.aks;
+    const int kb = part * per;
+    const int ke = kb + per < nstage ? kb + per : nstage;
+    const int ksteps = ke > kb ? ke - kb : 0;
+    const int64_t cend = 16 * (int64_t)ke < n ? 16 * (int64_t)ke : n;   // columns < cend
     // copy sources: lane l takes column CPD h + l/LPC of the stage, rows
     // 4(l%LPC) .. +3
     int64_t rc = row0 + 4 * (lane % LPC);
@@ -535,10 +589,10 @@ __device__ __forceinline__ void apass_s32_tile(const Job &J, int tile, double *s
         char *st = pipe + (kk % NST) * kS32Stage;
 #pragma unroll
         for (int h = 0; h < RS; ++h) {
-            const int64_t j = 16 * (int64_t)kk + CPD * h + cl;
+            const int64_t j = 16 * (int64_t)(kb + kk) + CPD * h + cl;
             lds_dma16f(Mr + (j < n ? j : n - 1) * ldm, st + wave * 1024 * RS + h * 1024);
         }
-        const int64_t e = 16 * (int64_t)kk * RPAD + woff;
+        const int64_t e = 16 * (int64_t)(kb + kk) * RPAD + woff;
         lds_dma16f(Wt + (e < wlast ? e : wlast), st + WOFF + wave * 1024);
     };
     v4f acc[RS][RT];
@@ -565,7 +619,7 @@ __device__ __forceinline__ void apass_s32_tile(const Job &J, int tile, double *s
             } else {
                 a[0] = *(const lmem<float> *)ap;
             }
-            const bool dead = tail && 16 * (int64_t)kk + c >= n;
+            const bool dead = tail && 16 * (int64_t)(kb + kk) + c >= cend;
             // W entries 16t + li of column c: contiguous in the interleaved Wt row
             const char *wp = st + WOFF + (c * RPAD + li * RT) * 4;
             float b[RT];
@@ -599,7 +653,7 @@ __device__ __forceinline__ void apass_s32_tile(const Job &J, int tile, double *s
 #pragma unroll
     for (int kk = 0; kk < NST - 1; ++kk) issue(kk);
     int kk = 0;
-    // stages kk <= ksteps - NST end at or before column 16 (ksteps - 1) < n
+    // stages kk <= ksteps - NST end at or before column 16 (ke - 1) < cend
     for (; kk < ksteps - (NST - 1); ++kk) {
         vm_wait_barrier<(RS + 1) * (NST - 2)>();   // stage kk landed, stage kk - 1 read
         issue(kk + NST - 1);
@@ -610,13 +664,25 @@ __device__ __forceinline__ void apass_s32_tile(const Job &J, int tile, double *s
         vm_wait_barrier<(RS + 1) * (NST - 2 - j)>();
         mma(kk + j, true);
     });
+    if (J.aks > 1) {
+        // split reduction: this part's FP64 rows of A, row i at Cp + (part *
+        // nA tm + i) rpad (rows past m too: never stored by the update)
+        const auto ap = to_global(J.Cp) + ((int64_t)part * J.nA * J.tm) * RPAD;
+#pragma unroll
+        for (int s2 = 0; s2 < RS; ++s2)
+#pragma unroll
+            for (int t = 0; t < RT; ++t)
+#pragma unroll
+                for (int v = 0; v < 4; ++v)
+                    ap[(row0 + RS * (4 * lk + v) + s2) * RPAD + 16 * t + li] = hs[s2][t][v];
+        return;
+    }
     __syncthreads();   // every wave done with the stages
     double *Gs = smem;
     double *Gi = Gs + RPAD * GS;
     if constexpr (MODE != MODE_STORE) load_gram<RPAD>(J.Bd, r, Gs, GS, Gi);
     double *Aw = Gi + RPAD + wave * 16 * AS;   // 16 rows of this wave (one s)
     __syncthreads();                            // Gram in LDS
-    const auto V = to_global(J.V);
     static_for<RS>([&](auto s_c) {
         constexpr int s2 = decltype(s_c)::value;
         __builtin_amdgcn_wave_barrier();
@@ -628,42 +694,7 @@ __device__ __forceinline__ void apass_s32_tile(const Job &J, int tile, double *s
         __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
         __builtin_amdgcn_wave_barrier();
         __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-        // lane 4q + p: entries EP p .. EP p + EP - 1 of row row0 + RS q + s2
-        constexpr int EP = RPAD / 4;
-        const int q = lane >> 2, p = lane & 3;
-        const int64_t row = row0 + RS * q + s2;
-        const bool live = row < m;
-        const double *arow = Aw + q * AS;
-        if constexpr (MODE == MODE_STORE) {
-            if (live) {
-#pragma unroll
-                for (int i = 0; i < EP; ++i) {
-                    const int k = EP * p + i;
-                    if (k < r) to_global(J.A)[row + (int64_t)k * m] = (float)arow[k];
-                }
-            }
-        } else {
-            // all loads unconditional (clamped row and column), then masked,
-            // so that they are in flight together
-            const int64_t rc = live ? row : m - 1;
-            float xv[EP];
-#pragma unroll
-            for (int i = 0; i < EP; ++i) {
-                const int k = EP * p + i;
-                xv[i] = V[rc + (int64_t)(k < r ? k : 0) * m];
-            }
-            double x[EP];
-#pragma unroll
-            for (int i = 0; i < EP; ++i) x[i] = (live && EP * p + i < r) ? (double)xv[i] : 0.0;
-            quad_row_update<RPAD, MODE>(x, arow, Gs, Gi, p, r);
-            if (live) {
-#pragma unroll
-                for (int i = 0; i < EP; ++i) {
-                    const int k = EP * p + i;
-                    if (k < r) V[row + (int64_t)k * m] = (float)x[i];
-                }
-            }
-        }
+        update_rows<RPAD, MODE>(J, Aw, Gs, Gi, row0 + s2, RS);
     });
 }
 
@@ -673,11 +704,63 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k
     extern __shared__ double smem[];
     const int2 jt = block_job(bmap);
     const Job &J = jobs[jt.x];
-    if (jt.y >= J.nA || J.st->stop) return;
+    if (jt.y >= J.nA * J.aks || J.st->stop) return;
+    const int tile = jt.y % J.nA, part = jt.y / J.nA;
     if (J.tm == 64)
-        apass_s32_tile<RT, MODE, 1>(J, jt.y, smem);
+        apass_s32_tile<RT, MODE, 1>(J, tile, part, smem);
     else
-        apass_s32_tile<RT, MODE, 2>(J, jt.y, smem);
+        apass_s32_tile<RT, MODE, 2>(J, tile, part, smem);
+}
+
+// Split A-pass, second half (job.aks > 1, 64-row tiles): the aks partial rows
+// of A of a tile are added in part order (FP64) into LDS, then each wave
+// updates its 16 rows of V as the unsplit A-pass does.
+template <int RT, int MODE>
+__global__ __launch_bounds__(256) void k_afinal_s32(const Job *__restrict__ jobs,
+                                                    const int2 *__restrict__ bmap) {
+    constexpr int RPAD = RT * 16, GS = RPAD, AS = RPAD + 1, PER = RPAD / 4;
+    extern __shared__ double smem[];
+    const int2 jt = block_job(bmap);
+    const Job &J = jobs[jt.x];
+    if (jt.y >= J.nA || J.st->stop) return;
+    const int tid = threadIdx.x, lane = tid & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+    const int64_t rw0 = (int64_t)jt.y * 64 + 16 * wave;   // this wave's 16 rows
+    double *Gs = smem;
+    double *Gi = Gs + RPAD * GS;
+    double *Aw = Gi + RPAD + wave * 16 * AS;
+    if constexpr (MODE != MODE_STORE) load_gram<RPAD>(J.Bd, J.r, Gs, GS, Gi);
+    // entries e = lane + 64 i of the wave's 16 x RPAD block (row e / RPAD)
+    const auto ap = to_global(J.Cp) + rw0 * RPAD;
+    const int64_t pstride = (int64_t)J.nA * J.tm * RPAD;
+    // parts taken four at a time, (p0 + p1) + (p2 + p3) added to the running
+    // sum (fixed order); the four loads of an entry are in flight together,
+    // and a part past aks reads part 0 with weight zero
+    double a[PER];
+#pragma unroll
+    for (int i = 0; i < PER; ++i) a[i] = 0.0;
+    for (int p0 = 0; p0 < J.aks; p0 += 4) {
+        double wgt[4];
+        int64_t off[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            wgt[u] = p0 + u < J.aks ? 1.0 : 0.0;
+            off[u] = (p0 + u < J.aks ? p0 + u : 0) * pstride + lane;
+        }
+#pragma unroll
+        for (int i = 0; i < PER; ++i) {
+            const double b0 = ap[off[0] + 64 * i], b1 = ap[off[1] + 64 * i];
+            const double b2 = ap[off[2] + 64 * i], b3 = ap[off[3] + 64 * i];
+            a[i] += (b0 * wgt[0] + b1 * wgt[1]) + (b2 * wgt[2] + b3 * wgt[3]);
+        }
+    }
+#pragma unroll
+    for (int i = 0; i < PER; ++i) {
+        const int e = lane + 64 * i;
+        Aw[(e / RPAD) * AS + e % RPAD] = a[i];
+    }
+    __syncthreads();   // Gram and rows of A in LDS
+    update_rows<RPAD, MODE>(J, Aw, Gs, Gi, rw0, 1);
 }
 
 // (ta, tb) of upper 16x16 tile idx of an RT x RT tile grid, row by row.
@@ -915,6 +998,30 @@ hipError_t launch_apass_s32(int mode, int rpad, const Job *jobs, const int2 *bma
     return hipGetLastError();
 }
 
+size_t afinal_s32_lds_bytes(int rpad) {
+    return sizeof(double) * ((size_t)rpad * rpad + rpad + 4 * 16 * (size_t)(rpad + 1));
+}
+
+hipError_t launch_afinal_s32(int mode, int rpad, const Job *jobs, const int2 *bmap, int blocks,
+                             hipStream_t s) {
+    if (blocks <= 0) return hipSuccess;
+    if (mode != MODE_HALS && mode != MODE_MU) return hipErrorInvalidValue;
+    const size_t lds = afinal_s32_lds_bytes(rpad);
+    const bool h = mode == MODE_HALS;
+    switch (rpad) {
+        case 16: h ? k_afinal_s32<1, MODE_HALS><<<blocks, 256, lds, s>>>(jobs, bmap)
+                   : k_afinal_s32<1, MODE_MU><<<blocks, 256, lds, s>>>(jobs, bmap); break;
+        case 32: h ? k_afinal_s32<2, MODE_HALS><<<blocks, 256, lds, s>>>(jobs, bmap)
+                   : k_afinal_s32<2, MODE_MU><<<blocks, 256, lds, s>>>(jobs, bmap); break;
+        case 48: h ? k_afinal_s32<3, MODE_HALS><<<blocks, 256, lds, s>>>(jobs, bmap)
+                   : k_afinal_s32<3, MODE_MU><<<blocks, 256, lds, s>>>(jobs, bmap); break;
+        case 64: h ? k_afinal_s32<4, MODE_HALS><<<blocks, 256, lds, s>>>(jobs, bmap)
+                   : k_afinal_s32<4, MODE_MU><<<blocks, 256, lds, s>>>(jobs, bmap); break;
+        default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
 hipError_t launch_cpass_s32(int rpad, const Job *jobs, const int2 *bmap, int blocks,
                             hipStream_t s) {
     if (blocks <= 0) return hipSuccess;
@@ -980,6 +1087,8 @@ static void stream_lds_attr(hipError_t &e) {
                           (const void *)k_cpass_stream<RT>,
                           (const void *)k_apass_s32<RT, MODE_HALS>,
                           (const void *)k_apass_s32<RT, MODE_MU>,
+                          (const void *)k_afinal_s32<RT, MODE_HALS>,
+                          (const void *)k_afinal_s32<RT, MODE_MU>,
                           (const void *)k_cpass_s32<RT>}) {
         const hipError_t x = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize,
                                                  160 * 1024);

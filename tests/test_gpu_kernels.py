@@ -6,7 +6,7 @@ import pytest
 import oracle as O
 import paper_1009_0881_amd as P
 import synth
-from gpu_util import TOL_FACTOR, TOL_REL_ERR, frob_rel, say
+from gpu_util import TOL_FACTOR, TOL_REL_ERR, frob_rel, gpu_solve, oracle_solve, say
 
 pytestmark = pytest.mark.gpu
 
@@ -143,6 +143,31 @@ def test_streaming_fp32_iterations_match_oracle(algo, h, w, n, r):
     assert res["log_len"] == iters
     d = np.max(np.abs(rel[:iters] - orel))
     say("  max |d rel_err|", d, "V", frob_rel(V, ores.V), "W", frob_rel(W, ores.W))
+    assert d <= TOL_REL_ERR
+    assert frob_rel(V, ores.V) <= TOL_FACTOR
+    assert frob_rel(W, ores.W) <= TOL_FACTOR
+
+
+@pytest.mark.parametrize("algo", ["hals", "mu"])
+@pytest.mark.parametrize("h,w,n,r", [(128, 128, 1100, 20), (128, 130, 1030, 50)])
+def test_streaming_fp32_multilevel_matches_oracle(algo, h, w, n, r):
+    """A plan whose finest level streams (m >= 16384) also streams its wide
+    coarse levels (m >= 1024, n >= 1024), splitting the A-pass's n-reduction
+    over several blocks per 64-row tile and adding the parts in a second
+    kernel: m = 4096 (4 parts) and 1024 (8 parts of 9 stages of 16 columns,
+    the last one short) here, m = 4160 and 1056 in the second case.  Three
+    levels, V-cycle, full weighting; same parity bar as the other solves."""
+    say("streaming fp32 multilevel", algo, h, w, n, r)
+    spec = synth.BlobSpec(h=h, w=w, n=n, r=r, k_lo=1, k_hi=max(1, min(5, r)),
+                          sig_lo=2.0, sig_hi=max(2.5, h / 4))
+    inst = synth.make_instance(spec, seed=6)
+    T = 8
+    res, rel, dep, V, W = gpu_solve(inst.M, inst.V0, inst.W0, h, w, r, 3, algo, "vc", "fw", T)
+    ores, orel, odep = oracle_solve(inst.M, inst.V0, inst.W0, h, w, r, 3, algo, "vc", "fw", T)
+    k = min(len(rel), 50)
+    d = float(np.max(np.abs(rel[:k] - orel[:k])))
+    say("  max |d rel_err|", d, "V", frob_rel(V, ores.V), "W", frob_rel(W, ores.W))
+    assert len(rel) == len(orel) and np.array_equal(dep, odep)
     assert d <= TOL_REL_ERR
     assert frob_rel(V, ores.V) <= TOL_FACTOR
     assert frob_rel(W, ores.W) <= TOL_FACTOR
