@@ -48,13 +48,13 @@ SWEEP_SOURCES = ("sweep.hip", "sweep_device.h", "device_common.h", "job.h")
 STREAM_SOURCES = SWEEP_SOURCES + ("stream.hip",)
 TRAFFIC = {
     ("orl", "fp32"): {
-        "sha": "3accac8295ae162d",
+        "sha": "1b98f6e27670d87d",
         "files": SWEEP_SOURCES,
-        "apass": {10304: 20016962, 2576: 6178816, 644: 2470272},
+        "apass": {10304: 20016963, 2576: 6178816, 644: 2470272},
         "cpass_partial": {10304: 21960635, 2576: 8363008, 644: 3509504},
-        "cpass_final": {10304: 5200969, 2576: 3923072, 644: 2643072},
-        "gram_v": {10304: 463262, 2576: 349952, 644: 237312},
-        "gram_w": {10304: 297676, 2576: 310624, 644: 310624},
+        "cpass_final": {10304: 5200969, 2576: 3923072, 644: 2642048},
+        "gram_v": {10304: 463262, 2576: 350720, 644: 236544},
+        "gram_w": {10304: 297676, 2576: 309984, 644: 309856},
     },
 }
 

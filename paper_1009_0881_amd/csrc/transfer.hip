@@ -95,20 +95,33 @@ __device__ __forceinline__ float stencil(const float *imgp, int rowlen, const Ta
     return (float)acc;
 }
 
+constexpr int kRestrictCols = 4;   // columns per thread of k_restrict
+
 __global__ __launch_bounds__(256) void k_restrict(const float *__restrict__ X, int64_t ldx,
                                                   float *__restrict__ Y, int h, int w, int hc,
                                                   int wc, int64_t ncols, int xfer,
                                                   const int32_t *stop) {
     if (stopped(stop)) return;
-    // grid: x over coarse pixels, y over columns (strided); 32-bit pixel math
+    // grid: x over coarse pixels, y over groups of kRestrictCols columns
+    // (strided); 32-bit pixel math.  A thread's columns are loaded together
+    // (9 taps each), then stored.
     const int mc = hc * wc;
     const int p = blockIdx.x * blockDim.x + threadIdx.x;
     if (p >= mc) return;
     const int cy = p / wc, cx = p - cy * wc;
-    for (int64_t col = blockIdx.y; col < ncols; col += gridDim.y) {
-        const Taps ty = restrict_taps(cy, h, xfer);
-        const Taps tx = restrict_taps(cx, w, xfer);
-        Y[col * mc + p] = stencil(X + col * ldx, w, ty, tx);
+    const Taps ty = restrict_taps(cy, h, xfer);
+    const Taps tx = restrict_taps(cx, w, xfer);
+    for (int64_t c0 = (int64_t)blockIdx.y * kRestrictCols; c0 < ncols;
+         c0 += (int64_t)gridDim.y * kRestrictCols) {
+        float out[kRestrictCols];
+#pragma unroll
+        for (int u = 0; u < kRestrictCols; ++u) {
+            const int64_t col = c0 + u < ncols ? c0 + u : ncols - 1;
+            out[u] = stencil(X + col * ldx, w, ty, tx);
+        }
+#pragma unroll
+        for (int u = 0; u < kRestrictCols; ++u)
+            if (c0 + u < ncols) Y[(c0 + u) * mc + p] = out[u];
     }
 }
 
@@ -377,7 +390,8 @@ hipError_t launch_restrict(int xfer, int h, int w, int64_t ncols, const float *X
     const int hc = (h + 1) / 2, wc = (w + 1) / 2;
     const int mc = hc * wc;
     if (mc == 0 || ncols == 0) return hipSuccess;
-    const dim3 grid((mc + 255) / 256, (unsigned)std::min<int64_t>(ncols, 65535));
+    const int64_t groups = (ncols + kRestrictCols - 1) / kRestrictCols;
+    const dim3 grid((mc + 255) / 256, (unsigned)std::min<int64_t>(groups, 65535));
     k_restrict<<<grid, 256, 0, s>>>(X, ldx, Y, h, w, hc, wc, ncols, xfer, stop);
     return hipGetLastError();
 }
