@@ -427,23 +427,30 @@ __device__ __forceinline__ void quad_row_update(double (&x)[RPAD / 4], const dou
     double prev[2] = {0.0, 0.0};
     auto dot = [&](int k, double dep) {
         const double *g = G + ordered_after(k * RPAD + EP * p, dep);
-        double s0 = 0.0, s1 = 0.0;
+        double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
 #pragma unroll
-        for (int i = 0; i < EP; i += 2) {
-            const v2d gv = *(const lmem<v2d> *)(g + i);
-            s0 = fma_t(x[i], gv[0], s0);
-            s1 = fma_t(x[i + 1], gv[1], s1);
+        for (int i = 0; i < EP; i += 4) {
+            const v2d ga = *(const lmem<v2d> *)(g + i);
+            const v2d gb = *(const lmem<v2d> *)(g + i + 2);
+            s0 = fma_t(x[i], ga[0], s0);
+            s1 = fma_t(x[i + 1], ga[1], s1);
+            s2 = fma_t(x[i + 2], gb[0], s2);
+            s3 = fma_t(x[i + 3], gb[1], s3);
         }
-        return quad_sum(s0 + s1);
+        return quad_sum((s0 + s1) + (s2 + s3));
     };
     if constexpr (MODE == MODE_HALS) {
         static_for<RPAD>([&](auto k_c) {
             constexpr int k = decltype(k_c)::value, ik = k % EP;
-            const double d = dot(k, prev[k & 1]);
+            const double dep = prev[k & 1];
+            // a_k and 1/G_kk read with Gram row k (not hoisted, not behind a branch)
+            const int ko = ordered_after(k, dep);
+            const double ak = arow[ko], gk = gi[ko];
+            const double d = dot(k, dep);
             prev[k & 1] = d;
-            const double gk = gi[k];
-            const double c = x[ik] + (arow[k] - d) * gk;
-            const double nx = gk > 0.0 ? (c > 0.0 ? c : 0.0) : x[ik];
+            const double c = x[ik] + (ak - d) * gk;
+            const double cp = c > 0.0 ? c : 0.0;
+            const double nx = gk > 0.0 ? cp : x[ik];
             x[ik] = p == k / EP ? nx : x[ik];
         });
     } else {
