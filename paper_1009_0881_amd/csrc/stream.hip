@@ -417,7 +417,8 @@ __device__ __forceinline__ double quad_sum(double v) {
 // summed by DPP.  HALS takes k = 0 .. RPAD-1 in turn, x_k <- max(0, x_k +
 // (a_k - sum_l x_l G_kl) / G_kk), formed by the lane that owns k; MU forms all
 // the sums from the old x, then x_k <- x_k a_k / sum_l x_l G_kl.  Steps with
-// 1/G_kk = 0 (k >= r, or G_kk = 0) leave x_k as it is.  The loads of Gram row
+// 1/G_kk = 0 (k >= r, or G_kk = 0) leave x_k as it is; steps k >= r are
+// skipped.  The loads of Gram row
 // k wait for the sum of step k - 2, so that at most two rows are in flight.
 template <int RPAD, int MODE>
 __device__ __forceinline__ void quad_row_update(double (&x)[RPAD / 4], const double *arow,
@@ -442,6 +443,7 @@ __device__ __forceinline__ void quad_row_update(double (&x)[RPAD / 4], const dou
     if constexpr (MODE == MODE_HALS) {
         static_for<RPAD>([&](auto k_c) {
             constexpr int k = decltype(k_c)::value, ik = k % EP;
+            if (k >= r) return;   // uniform: steps k >= r change nothing (1/G_kk = 0)
             const double dep = prev[k & 1];
             // a_k and 1/G_kk read with Gram row k (not hoisted, not behind a branch)
             const int ko = ordered_after(k, dep);
@@ -459,6 +461,7 @@ __device__ __forceinline__ void quad_row_update(double (&x)[RPAD / 4], const dou
         for (int i = 0; i < EP; ++i) den[i] = 0.0;
         static_for<RPAD>([&](auto k_c) {
             constexpr int k = decltype(k_c)::value, ik = k % EP;
+            if (k >= r) return;   // uniform: den_k is used only for k < r
             const double d = dot(k, prev[k & 1]);
             prev[k & 1] = d;
             den[ik] = p == k / EP ? d : den[ik];
