@@ -28,8 +28,10 @@ struct Job {
     float *W;            // r x n row-major
     float *Wt;           // n x rpad, transposed and zero-padded copy of W; entry k of row
                          // j at j * rpad + wt_pos(k, rpad / 16) (device_common.h)
-    float *A;            // ANLS: M W^T (m x r)
-    float *C;            // ANLS: V^T M (r x n)
+    float *A;            // products kept in FP32 (nmf_products): M W^T (m x r, column-major)
+    float *C;            //   and V^T M (r x n, row-major)
+    double *Ad, *Cd;     // ANLS: the same products in FP64 (taken instead of A / C when set),
+                         // the right-hand sides of the NNLS problems
     double *Bd, *Dd;     // W W^T and V^T V (r x r, FP64)
     double *Cp;          // V^T M partials: chunks x (n x r, entry (k, j) at j * r + k),
                          // FP64 (prec 0) or FP32 (prec 1, a float view of the buffer)

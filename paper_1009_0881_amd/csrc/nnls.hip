@@ -175,7 +175,7 @@ __device__ bool wave_nnls(const double *__restrict__ Gs, double *__restrict__ S,
 //               also emits the FP64 partial <C, W_new> per block.
 template <int RPAD, int WAVES, bool COLS>
 __global__ __launch_bounds__(WAVES * 64) void k_nnls(const double *__restrict__ Gd,
-                                                     const float *__restrict__ Rhs, int64_t count,
+                                                     const double *__restrict__ Rhs, int64_t count,
                                                      int r, float *__restrict__ X,
                                                      float *__restrict__ Xt,
                                                      double *__restrict__ rparts,
@@ -199,7 +199,7 @@ __global__ __launch_bounds__(WAVES * 64) void k_nnls(const double *__restrict__ 
          prob += (int64_t)gridDim.x * WAVES) {
         const bool ok = lane < r;
         const int64_t idx = COLS ? (int64_t)lane * count + prob : prob + (int64_t)lane * count;
-        const double b = ok ? (double)Rhs[idx] : 0.0;
+        const double b = ok ? Rhs[idx] : 0.0;
         double x = ok ? (double)X[idx] : 0.0;
         if (!wave_nnls<RPAD>(Gs, S, b, x, r, lane)) failed = true;
         if (ok) {
@@ -224,7 +224,7 @@ __global__ __launch_bounds__(WAVES * 64) void k_nnls(const double *__restrict__ 
 }
 
 template <int RPAD, bool COLS>
-hipError_t launch_nnls_t(const double *Gd, const float *Rhs, int64_t count, int r, float *X,
+hipError_t launch_nnls_t(const double *Gd, const double *Rhs, int64_t count, int r, float *X,
                          float *Xt, double *rparts, int32_t *flags, const int32_t *stop,
                          int blocks, hipStream_t s) {
     constexpr int WAVES = (RPAD >= 64) ? 2 : 4;
@@ -239,7 +239,7 @@ int nnls_cols_blocks(int64_t n) {
     return (int)(b > 1024 ? 1024 : (b < 1 ? 1 : b));
 }
 
-static hipError_t nnls_dispatch(int rpad, bool cols, const double *Gd, const float *Rhs,
+static hipError_t nnls_dispatch(int rpad, bool cols, const double *Gd, const double *Rhs,
                                 int64_t count, int r, float *X, float *Xt, double *rparts,
                                 int32_t *flags, const int32_t *stop, int blocks, hipStream_t s) {
     switch (rpad) {
@@ -255,14 +255,14 @@ static hipError_t nnls_dispatch(int rpad, bool cols, const double *Gd, const flo
     }
 }
 
-hipError_t launch_nnls_rows(int rpad, const double *Gd, const float *A, int64_t m, int r,
+hipError_t launch_nnls_rows(int rpad, const double *Gd, const double *A, int64_t m, int r,
                             float *V, int32_t *flags, const int32_t *stop, hipStream_t s) {
     int64_t b = (m + 3) / 4;
     const int blocks = (int)(b > 4096 ? 4096 : (b < 1 ? 1 : b));
     return nnls_dispatch(rpad, false, Gd, A, m, r, V, nullptr, nullptr, flags, stop, blocks, s);
 }
 
-hipError_t launch_nnls_cols(int rpad, const double *Gd, const float *C, int64_t n, int r,
+hipError_t launch_nnls_cols(int rpad, const double *Gd, const double *C, int64_t n, int r,
                             float *W, float *Wt, double *rparts, int32_t *flags,
                             const int32_t *stop, hipStream_t s) {
     return nnls_dispatch(rpad, true, Gd, C, n, r, W, Wt, rparts, flags, stop, nnls_cols_blocks(n),

@@ -253,8 +253,8 @@ nmf_status build_plan(const nmf_desc &d0, Plan &p, std::string &err) {
                                       (size_t)nnls_cols_blocks(d.n), (size_t)1024});
     ws.off_rparts = take(sizeof(double) * ws.rparts_cap);
     if (d.algo == NMF_ANLS) {
-        ws.off_A = take(sizeof(float) * (size_t)d.m * r);
-        ws.off_C = take(sizeof(float) * r * n);
+        ws.off_A = take(sizeof(double) * (size_t)d.m * r);   // FP64 right-hand sides
+        ws.off_C = take(sizeof(double) * r * n);
     } else {
         ws.off_A = ws.off_C = 0;
     }

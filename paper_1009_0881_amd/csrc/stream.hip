@@ -495,7 +495,9 @@ __device__ __forceinline__ void update_rows(const Job &J, const double *Aw, cons
 #pragma unroll
             for (int i = 0; i < EP; ++i) {
                 const int k = EP * p + i;
-                if (k < r) to_global(J.A)[row + (int64_t)k * m] = (float)arow[k];
+                if (k >= r) continue;
+                if (J.Ad) to_global(J.Ad)[row + (int64_t)k * m] = arow[k];
+                else to_global(J.A)[row + (int64_t)k * m] = (float)arow[k];
             }
         }
     } else {

@@ -249,7 +249,9 @@ __device__ void apass_tile(const Job &J, int tile, double *smem) {
         for (int e = tid; e < TM * r; e += 256) {
             const int rr = e % TM, k = e / TM;
             const int64_t row = brow + rr;
-            if (row < m) to_global(J.A)[row + (int64_t)k * m] = (float)arow(rr)[k];
+            if (row >= m) continue;
+            if (J.Ad) to_global(J.Ad)[row + (int64_t)k * m] = arow(rr)[k];
+            else to_global(J.A)[row + (int64_t)k * m] = (float)arow(rr)[k];
         }
     } else {
 #pragma unroll
@@ -916,7 +918,9 @@ __device__ __forceinline__ void cfinal_tile(const Job &J, int tile, double *smem
         for (int e = tid; e < CF * r; e += 256) {
             const int jj = e % CF, k = e / CF;
             const int64_t j = j0 + jj;
-            if (j < n) to_global(J.C)[(int64_t)k * n + j] = (float)Cs[jj * CS + k];
+            if (j >= n) continue;
+            if (J.Cd) to_global(J.Cd)[(int64_t)k * n + j] = Cs[jj * CS + k];
+            else to_global(J.C)[(int64_t)k * n + j] = (float)Cs[jj * CS + k];
         }
     } else {
         double part = 0.0;

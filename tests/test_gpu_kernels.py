@@ -176,11 +176,12 @@ def test_streaming_fp32_multilevel_matches_oracle(algo, h, w, n, r):
 @pytest.mark.parametrize("h,w,n,r", [(16, 16, 500, 10), (5, 7, 37, 3), (9, 9, 130, 17),
                                      (8, 8, 20, 1), (16, 16, 80, 64), (28, 23, 120, 40)])
 def test_anls_iterations_match_oracle(h, w, n, r):
-    """ANLS parity.  Each half-step is an exact NNLS solve whose solution moves
-    by about cond(V^T V) times the FP32 error of the product V^T M, so the
-    1e-4 factor bar is asserted where cond(V^T V) <= 1e5; for worse-conditioned
-    instances the rel_err trajectory must still match, and the GPU's W must be
-    the exact W-step minimiser for the GPU's V (objective gap <= 1e-7 ||M||^2)."""
+    """ANLS parity at the full bar (rel_err within 1e-5, factors within 1e-4).
+    Each half-step is an exact NNLS solve on FP64 right-hand sides that carry
+    only the rounding of the FP32 matrix-core products, so the unique solution
+    moves by about cond(V^T V) times that error: the three cases with cond above
+    1e5 (1.7e5, 3.8e8 and 7.8e5 here) drift by up to 9.7e-5 in W (the 64-rank
+    one), inside the bar.  cond is printed for every case."""
     say("anls", h, w, n, r)
     spec = synth.BlobSpec(h=h, w=w, n=n, r=r, k_lo=1, k_hi=max(1, min(5, r)),
                           sig_lo=1.0, sig_hi=max(1.5, h / 4))
@@ -198,12 +199,5 @@ def test_anls_iterations_match_oracle(h, w, n, r):
         "cond(V^T V) %.2e" % cond)
     assert d <= TOL_REL_ERR
     assert (V >= 0).all() and (W >= 0).all()
-    if cond <= 1e5:
-        assert frob_rel(V, ores.V) <= TOL_FACTOR
-        assert frob_rel(W, ores.W) <= TOL_FACTOR
-    else:
-        M64 = inst.M.astype(np.float64)
-        Wstar = O.anls_update_W(M64, V, W)
-        gap = O.objective(M64, V, W) - O.objective(M64, V, Wstar)
-        say("  W-step optimality gap / ||M||^2 = %.2e" % (gap / np.sum(M64 ** 2)))
-        assert gap <= 1e-7 * np.sum(M64 ** 2)
+    assert frob_rel(V, ores.V) <= TOL_FACTOR
+    assert frob_rel(W, ores.W) <= TOL_FACTOR

@@ -166,3 +166,21 @@ def test_one_step_from_oracle_states(algo):
         worst = max(worst, dv, dw)
         assert de <= 1e-6
     assert worst <= 1e-5
+
+
+@pytest.mark.timeout(600)
+def test_orl_shape_anls_three_levels():
+    """ANLS on the ORL-shaped workload (112x92, n = 400, r = 40, 3 levels, full
+    weighting, NI, T = 8: 8 iterations at 28x23, 6 at 56x46, 6 at 112x92).
+    The oracle's Python active-set loop makes this the slowest parity test
+    (about a minute of CPU).  Same bar as HALS and MU: per-iteration rel_err
+    within 1e-5, factors within 1e-4."""
+    inst = synth.make_instance(synth.CFG_ORL, 0)
+    args = (inst.M, inst.V0, inst.W0, 112, 92, 40, 3, "anls", "ni", "fw", 8)
+    g = gpu_solve(*args)
+    o = oracle_solve(*args)
+    _, ores = check("orl anls ni", g, o)
+    say("  cond(V^T V) %.3e  cond(W W^T) %.3e" % (np.linalg.cond(ores.V.T @ ores.V),
+                                                  np.linalg.cond(ores.W @ ores.W.T)))
+    assert frob_rel(g[3], ores.V) <= TOL_FACTOR
+    assert frob_rel(g[4], ores.W) <= TOL_FACTOR
