@@ -59,7 +59,8 @@ __all__ = [
     "hals_update_V", "hals_update_W", "hals_iteration",
     "mu_update_V", "mu_update_W", "mu_iteration",
     "nnls_gram", "anls_update_V", "anls_update_W", "anls_iteration",
-    "iteration", "rel_err", "objective", "gram_form_residual2",
+    "iteration", "bf16_round", "hals_update_V_bf16", "hals_update_W_bf16",
+    "mu_iteration_bf16", "iteration_bf16", "rel_err", "objective", "gram_form_residual2",
     "eckart_young_floor", "prolongation_bound", "solve", "SolveResult",
 ]
 
@@ -406,6 +407,82 @@ def iteration(algo: int, M, V, W):
 
 
 # ---------------------------------------------------------------------------
+# Reduced-precision products (the library's BF16 mode; the paper fixes no
+# precision, so this is the definition that mode follows, not a paper passage)
+# ---------------------------------------------------------------------------
+
+def bf16_round(x) -> np.ndarray:
+    """Round to the nearest bfloat16 value (8 significant bits, ties to even),
+    for normal-range inputs: with x = f 2^e, 0.5 <= |f| < 1, keep round(f 2^8)."""
+    x = np.asarray(x, dtype=np.float64)
+    f, e = np.frexp(x)
+    return np.ldexp(np.round(f * 256.0) / 256.0, e)
+
+
+def hals_update_V_bf16(M, V, W, Mb=None):
+    """Alg. 3's V half with the product A = M W^T formed from bfloat16-rounded
+    M and W (exact products, FP64 sums); B = W W^T and the update unchanged.
+    Mb: bf16_round(M) when the caller has it already."""
+    V = np.array(V, dtype=np.float64, copy=True)
+    A = (bf16_round(M) if Mb is None else Mb) @ bf16_round(W).T
+    B = W @ W.T
+    r = V.shape[1]
+    for k in range(r):
+        if B[k, k] > 0:
+            others = [l for l in range(r) if l != k]
+            V[:, k] = np.maximum(0.0, (A[:, k] - V[:, others] @ B[others, k]) / B[k, k])
+    return V
+
+
+def hals_update_W_bf16(M, V, W, Mb=None):
+    """Alg. 3's W half with C = V^T M and D = V^T V formed from bfloat16-rounded
+    V and M (exact products, FP64 sums)."""
+    W = np.array(W, dtype=np.float64, copy=True)
+    Vb = bf16_round(V)
+    C = Vb.T @ (bf16_round(M) if Mb is None else Mb)
+    D = Vb.T @ Vb
+    r = W.shape[0]
+    for k in range(r):
+        if D[k, k] > 0:
+            others = [l for l in range(r) if l != k]
+            W[k, :] = np.maximum(0.0, (C[k, :] - D[k, others] @ W[others, :]) / D[k, k])
+    return W
+
+
+def mu_iteration_bf16(M, V, W, Mb=None):
+    """Alg. 2 with the two M products formed from bfloat16-rounded operands:
+    V <- V o [bf(M) bf(W)^T] / [V (W W^T)], then
+    W <- W o [bf(V)^T bf(M)] / [(bf(V)^T bf(V)) W]; zero denominators keep the entry."""
+    if Mb is None:
+        Mb = bf16_round(M)
+    num = Mb @ bf16_round(W).T
+    den = V @ (W @ W.T)
+    Vn = np.array(V, dtype=np.float64, copy=True)
+    ok = den > 0
+    Vn[ok] = V[ok] * num[ok] / den[ok]
+    Vb = bf16_round(Vn)
+    num = Vb.T @ Mb
+    den = (Vb.T @ Vb) @ W
+    Wn = np.array(W, dtype=np.float64, copy=True)
+    ok = den > 0
+    Wn[ok] = W[ok] * num[ok] / den[ok]
+    return Vn, Wn
+
+
+def iteration_bf16(algo: int, M, V, W, Mb=None):
+    """One iteration of HALS or MU with bfloat16 operands in the two M products
+    (Mb: bf16_round(M), if already formed)."""
+    if Mb is None:
+        Mb = bf16_round(M)
+    if algo == HALS:
+        V = hals_update_V_bf16(M, V, W, Mb)
+        return V, hals_update_W_bf16(M, V, W, Mb)
+    if algo == MU:
+        return mu_iteration_bf16(M, V, W, Mb)
+    raise ValueError("bfloat16 products: HALS and MU only")
+
+
+# ---------------------------------------------------------------------------
 # Objective and diagnostics (eq. NMF, eq. subNNLS, Section 4.1 bound)
 # ---------------------------------------------------------------------------
 
@@ -467,13 +544,18 @@ class SolveResult:
 
 def solve(M, h: int, w: int, r: int, levels: int, algo: int, cycle: int, xfer: int,
           T, V0, W0, tol: float = 0.0, max_fine_iters: int = 0,
-          check_bound: bool = False, callback=None) -> SolveResult:
+          check_bound: bool = False, callback=None, bf16_products: bool = False,
+          refine_iters: int = 0) -> SolveResult:
     """Multilevel NMF (Section 4.1 steps 1-5 applied recursively by Alg. 4/5/6).
 
     The restrictions of M are computed once per level and kept (Alg. 6 note).
     W is passed between levels unchanged (only m is coarsened).  For ANLS the
     V iterate is not an input of the algorithm (Alg. 1, Remark 1), so its
     transfers do not influence the result.
+
+    bf16_products: the scheduled iterations use iteration_bf16 (the library's
+    BF16 mode), then `refine_iters` full-precision finest-level iterations
+    follow; the tolerance applies to those only, as in that mode.
     """
     M = np.asarray(M, dtype=np.float64)
     sides = level_sides(h, w, levels)
@@ -486,9 +568,11 @@ def solve(M, h: int, w: int, r: int, levels: int, algo: int, cycle: int, xfer: i
     res = SolveResult()
     depth = 0
 
-    def one(d):
+    Mbs = [bf16_round(Ml) for Ml in Ms] if bf16_products else None
+
+    def one(d, low=False):
         nonlocal V, W
-        V, W = iteration(algo, Ms[d], V, W)
+        V, W = iteration_bf16(algo, Ms[d], V, W, Mbs[d]) if low else iteration(algo, Ms[d], V, W)
         e = rel_err(Ms[d], V, W)
         res.log.append((d, e))
         res.total_iters += 1
@@ -515,13 +599,17 @@ def solve(M, h: int, w: int, r: int, levels: int, algo: int, cycle: int, xfer: i
         else:
             assert depth == d
             for _ in range(count):
-                e = one(d)
-                if tol > 0 and d == 0 and e <= tol:
+                e = one(d, bf16_products)
+                if tol > 0 and d == 0 and e <= tol and not bf16_products:
                     res.stopped = True
                     break
         if res.stopped:
             break
     assert res.stopped or depth == 0
+    for _ in range(refine_iters if bf16_products and not res.stopped else 0):
+        if one(0) <= tol and tol > 0:
+            res.stopped = True
+            break
     if tol > 0 and not res.stopped:
         for _ in range(max_fine_iters):
             if one(0) <= tol:

@@ -216,3 +216,55 @@ def test_rel_err_definition():
     V = np.array([[1.0], [0.0]])
     W = np.array([[3.0, 0.0]])
     assert O.rel_err(M, V, W) == pytest.approx(4.0 / 5.0, abs=1e-15)
+
+
+# ----------------------------------------------- bfloat16 product operands
+
+def test_bf16_round_closed_forms():
+    # 8 significant bits, ties to even (255 has exactly 8, 257 = 256 + 1 needs 9
+    # and ties down to the even 256): 1 + 2^-8 lies half-way between 1 and
+    # 1 + 2^-7 (mantissa 0 is even), 1 + 3*2^-8 half-way between 1 + 2^-7 and
+    # 1 + 2^-6 (mantissa 2 is even); anything above a tie rounds up
+    x = np.array([1.0, 1 + 2 ** -8, 1 + 3 * 2 ** -8, 1 + 2 ** -8 + 2 ** -20, -3.0, 0.0,
+                  255.0, 257.0, 2.0 ** -100, 0.1])
+    want = np.array([1.0, 1.0, 1 + 2 ** -6, 1 + 2 ** -7, -3.0, 0.0, 255.0, 256.0, 2.0 ** -100,
+                     0.10009765625])
+    np.testing.assert_array_equal(O.bf16_round(x), want)
+
+
+def test_bf16_round_equals_bit_rounding_of_float32():
+    # independent route on FP32 inputs: keep the top 16 bits of the IEEE single
+    # pattern after adding 0x7FFF plus the lowest kept bit (round to nearest even)
+    rng = np.random.default_rng(3)
+    x = (rng.standard_normal(20000) * np.exp(rng.uniform(-20, 20, 20000))).astype(np.float32)
+    u = x.view(np.uint32).astype(np.uint64)
+    u = (u + 0x7FFF + ((u >> 16) & 1)) >> 16
+    ref = (u.astype(np.uint32) << 16).view(np.float32).astype(np.float64)
+    np.testing.assert_array_equal(O.bf16_round(x.astype(np.float64)), ref)
+
+
+@pytest.mark.parametrize("algo", [O.HALS, O.MU])
+def test_bf16_iteration_reduces_to_the_plain_iteration(algo):
+    # With M, V and W already bfloat16 values, the V half-step equals Alg. 3 /
+    # Alg. 2 exactly; the W half-step equals the plain one applied to the
+    # bfloat16-rounded new V.  A rounded Gram W W^T, a rounded update or a
+    # product formed from the wrong operand breaks one of the two equalities.
+    M, V, W = (O.bf16_round(a) for a in rand_problem(7, 6, 3, 11))
+    V1, W1 = O.iteration_bf16(algo, M, V, W)
+    Vp = (O.hals_update_V if algo == O.HALS else O.mu_update_V)(M, V, W)
+    np.testing.assert_array_equal(V1, Vp)
+    assert not np.array_equal(O.bf16_round(V1), V1)
+    Wp = (O.hals_update_W if algo == O.HALS else O.mu_update_W)(M, O.bf16_round(V1), W)
+    np.testing.assert_array_equal(W1, Wp)
+
+
+def test_bf16_solve_refines_in_full_precision():
+    # the scheduled iterations use the rounded products, the refinement the
+    # plain ones; the log has both, and the tolerance only ends refinement steps
+    M, V, W = rand_problem(64, 20, 3, 5)
+    a = O.solve(M.astype(np.float32), 8, 8, 3, 2, O.HALS, O.NI, O.XFER_FW, 4, V, W,
+                bf16_products=True, refine_iters=2)
+    b = O.solve(M.astype(np.float32), 8, 8, 3, 2, O.HALS, O.NI, O.XFER_FW, 4, V, W)
+    assert len(a.log) == len(b.log) + 2
+    assert [d for d, _ in a.log[-2:]] == [0, 0]
+    assert a.log[0][1] != b.log[0][1]
