@@ -20,9 +20,9 @@
  *    image row-major: pixel (y, x) at y*w + x).  V is m x r column-major
  *    (basis image k = V + k*m).  W is r x n row-major (W + k*n).
  *  - Every call returns an nmf_status; no exception or abort crosses the ABI.
- *    On error nmf_last_error(plan) (or nmf_last_error(NULL) for errors that
- *    precede a plan) returns a human-readable message (thread-local storage,
- *    valid until the next call on the same thread).
+ *    On error nmf_last_error() returns a human-readable message of the last
+ *    failed call on the calling thread (thread-local storage, valid until the
+ *    next call on the same thread; the plan argument is not used).
  */
 #ifndef NMF_H
 #define NMF_H

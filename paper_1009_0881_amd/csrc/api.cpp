@@ -11,8 +11,7 @@ namespace {
 thread_local std::string g_err;
 }  // namespace
 
-nmf_status fail(nmf_plan_t plan, nmf_status st, const std::string &msg) {
-    if (plan) plan->p.err = msg;
+nmf_status fail(nmf_plan_t, nmf_status st, const std::string &msg) {
     g_err = msg;
     return st;
 }
@@ -25,43 +24,59 @@ T *at(char *base, size_t off) {
 }
 
 // ---- optional HIP-event timing of selected kernel kinds -------------------
-int prof_begin(nmf_plan_t plan, hipStream_t s, int kind) {
-    Profiler &pf = plan->p.prof;
-    if (!(pf.mask & (1u << kind))) return -1;
-    const size_t i = pf.pending_kind.size();
-    while (pf.pool.size() < 2 * (i + 1)) {
-        hipEvent_t e;
-        if (hipEventCreate(&e) != hipSuccess) return -1;
-        pf.pool.push_back(e);
+int prof_begin(Ctx &c, int kind) {
+    Profiler &pf = c.plan->p.prof;
+    if (!c.prof || !(pf.mask & (1u << kind))) return -1;
+    hipEvent_t e[2];
+    {
+        std::lock_guard<std::mutex> lk(pf.mu);
+        for (int i = 0; i < 2; ++i) {
+            if (!pf.pool.empty()) {
+                e[i] = pf.pool.back();
+                pf.pool.pop_back();
+            } else if (hipEventCreate(&e[i]) != hipSuccess) {
+                if (i) pf.pool.push_back(e[0]);
+                return -1;
+            }
+        }
     }
-    if (hipEventRecord(pf.pool[2 * i], s) != hipSuccess) return -1;
-    pf.pending_kind.push_back(kind);
-    return (int)i;
+    if (hipEventRecord(e[0], c.s) != hipSuccess) {
+        std::lock_guard<std::mutex> lk(pf.mu);
+        pf.pool.push_back(e[0]);
+        pf.pool.push_back(e[1]);
+        return -1;
+    }
+    c.prof_pending.push_back(Ctx::ProfEvent{kind, e[0], e[1]});
+    return (int)c.prof_pending.size() - 1;
 }
 
-void prof_end(nmf_plan_t plan, hipStream_t s, int idx) {
-    if (idx >= 0) (void)hipEventRecord(plan->p.prof.pool[2 * idx + 1], s);
+void prof_end(Ctx &c, int idx) {
+    if (idx >= 0) (void)hipEventRecord(c.prof_pending[idx].end, c.s);
 }
 
 // Call only after the stream has been synchronised.
-void prof_collect(nmf_plan_t plan) {
-    Profiler &pf = plan->p.prof;
-    for (size_t i = 0; i < pf.pending_kind.size(); ++i) {
+void prof_collect(Ctx &c) {
+    if (c.prof_pending.empty()) return;
+    Profiler &pf = c.plan->p.prof;
+    std::lock_guard<std::mutex> lk(pf.mu);
+    for (const Ctx::ProfEvent &e : c.prof_pending) {
         float ms = 0.0f;
-        if (hipEventElapsedTime(&ms, pf.pool[2 * i], pf.pool[2 * i + 1]) == hipSuccess) {
-            pf.counts[pf.pending_kind[i]]++;
-            pf.ms[pf.pending_kind[i]] += ms;
+        if (hipEventElapsedTime(&ms, e.begin, e.end) == hipSuccess) {
+            pf.counts[e.kind]++;
+            pf.ms[e.kind] += ms;
         }
+        pf.pool.push_back(e.begin);
+        pf.pool.push_back(e.end);
     }
-    pf.pending_kind.clear();
+    c.prof_pending.clear();
     (void)hipGetLastError();
 }
 
 #define NMF_LAUNCH(kind, call)                              \
     do {                                                    \
-        const int pi_ = prof_begin(c.plan, c.s, (kind));    \
+        const int pi_ = prof_begin(c, (kind));              \
         NMF_HIP(call);                                      \
-        prof_end(c.plan, c.s, pi_);                         \
+        prof_end(c, pi_);                                   \
     } while (0)
 
 // FP32 streaming tiling of a job when its level qualifies (large, m and the
@@ -83,7 +98,6 @@ void set_fp32_stream(Job &J, const LevelInfo &li, const Plan &p) {
 Ctx make_ctx(nmf_plan_t plan, const float *dM, float *dV, float *dW, void *dws, hipStream_t s,
              bool allow_stream) {
     const Plan &p = plan->p;
-    plan->p.prof.pending_kind.clear();
     Ctx c;
     c.plan = plan;
     c.p = &p;
@@ -104,8 +118,8 @@ Ctx make_ctx(nmf_plan_t plan, const float *dM, float *dV, float *dW, void *dws, 
     c.Cp = at<double>(c.ws, p.ws.off_cparts);
     c.Dp = at<double>(c.ws, p.ws.off_Dp);
     c.Wt = at<float>(c.ws, p.ws.off_Wt);
-    c.A = p.ws.off_A ? at<float>(c.ws, p.ws.off_A) : nullptr;
-    c.C = p.ws.off_C ? at<float>(c.ws, p.ws.off_C) : nullptr;
+    c.A = p.ws.off_A ? at<double>(c.ws, p.ws.off_A) : nullptr;
+    c.C = p.ws.off_C ? at<double>(c.ws, p.ws.off_C) : nullptr;
     for (size_t l = 0; l < p.lv.size(); ++l) {
         if (l == 0) {
             c.M.push_back(dM);
@@ -144,8 +158,10 @@ Ctx make_ctx(nmf_plan_t plan, const float *dM, float *dV, float *dW, void *dws, 
         J.V = c.V[l];
         J.W = dW;
         J.Wt = c.Wt;
-        J.A = c.A;
-        J.C = c.C;
+        J.A = nullptr;
+        J.C = nullptr;
+        J.Ad = c.A;
+        J.Cd = c.C;
         J.Bd = c.Bd;
         J.Dd = c.Dd;
         J.Cp = c.Cp;
@@ -376,7 +392,7 @@ nmf_status finish(Ctx &c, nmf_result *out) {
     DevState hs;
     nmf_status st = read_state(c, hs);
     if (st != NMF_OK) return st;
-    prof_collect(plan);
+    prof_collect(c);
     return result_from_state(plan, hs, c.depths, out);
 }
 
@@ -401,9 +417,7 @@ const char *nmf_status_string(nmf_status s) {
     }
 }
 
-const char *nmf_last_error(nmf_plan_t plan) {
-    return plan ? plan->p.err.c_str() : g_err.c_str();
-}
+const char *nmf_last_error(nmf_plan_t) { return g_err.c_str(); }
 
 nmf_status nmf_plan(const nmf_desc *desc, nmf_plan_t *out, size_t *workspace_bytes) {
     if (!desc || !out) return fail(nullptr, NMF_E_ARG, "null desc or out");
@@ -429,8 +443,11 @@ nmf_status nmf_plan(const nmf_desc *desc, nmf_plan_t *out, size_t *workspace_byt
 }
 
 nmf_status nmf_destroy(nmf_plan_t plan) {
-    if (plan)
+    if (plan) {
+        std::lock_guard<std::mutex> lk(plan->p.prof.mu);
         for (hipEvent_t e : plan->p.prof.pool) (void)hipEventDestroy(e);
+        plan->p.prof.pool.clear();
+    }
     delete plan;
     return NMF_OK;
 }
@@ -465,9 +482,19 @@ nmf_status nmf_solve(nmf_plan_t plan, const float *dM, float *dV, float *dW, int
     if (iters < 0) return fail(plan, NMF_E_ARG, "iters must be >= 0");
     if (reinterpret_cast<uintptr_t>(dWorkspace) & 255)
         return fail(plan, NMF_E_ARG, "workspace must be 256-byte aligned");
+    return solve_on(plan, dM, dV, dW, iters, dWorkspace, static_cast<hipStream_t>(stream), hOut,
+                    true);
+}
+
+}  // extern "C"
+
+namespace nmf {
+
+nmf_status solve_on(nmf_plan_t plan, const float *dM, float *dV, float *dW, int32_t iters,
+                    void *dWorkspace, hipStream_t s, nmf_result *hOut, bool profile) {
     const Plan &p = plan->p;
-    hipStream_t s = static_cast<hipStream_t>(stream);
     Ctx c = make_ctx(plan, dM, dV, dW, dWorkspace, s);
+    c.prof = profile;
     NMF_HIP(launch_state_reset(c.st, s));
     nmf_status st;
     if (p.d.check_input && (st = check_input(c)) != NMF_OK) return st;
@@ -528,6 +555,10 @@ nmf_status nmf_solve(nmf_plan_t plan, const float *dM, float *dV, float *dW, int
     return finish(c, hOut);
 }
 
+}  // namespace nmf
+
+extern "C" {
+
 nmf_status nmf_query_log(nmf_plan_t plan, const void *dWorkspace, void *stream, double *rel_err,
                          int32_t *depth, int32_t cap) {
     if (!plan || !dWorkspace) return fail(plan, NMF_E_ARG, "null argument");
@@ -579,6 +610,7 @@ nmf_status nmf_profile_read(nmf_plan_t plan, int64_t *counts, double *total_ms, 
                             int32_t reset) {
     if (!plan) return fail(plan, NMF_E_ARG, "null plan");
     Profiler &pf = plan->p.prof;
+    std::lock_guard<std::mutex> lk(pf.mu);
     for (int k = 0; k < K_NUM_KINDS && k < cap; ++k) {
         if (counts) counts[k] = pf.counts[k];
         if (total_ms) total_ms[k] = pf.ms[k];
@@ -602,6 +634,7 @@ nmf_status nmf_products(nmf_plan_t plan, const float *dM, const float *dV, const
     Job &J = c.jobs[0];
     J.A = dA;
     J.C = dC;
+    J.Ad = J.Cd = nullptr;
     NMF_HIP(launch_state_reset(c.st, s));
     NMF_HIP(launch_make_wt(dW, p.d.n, p.d.r, p.rpad, c.Wt, s));
     nmf_status st = upload_jobs(c);

@@ -36,7 +36,8 @@ struct Ctx {
     double *norm;
     double *nparts;               // norm partials, kNormParts per level
     double *Bd, *Dd, *gparts, *rparts;
-    float *Bf, *Df, *A, *C, *Wt;
+    float *Bf, *Df, *Wt;
+    double *A, *C;                // ANLS: FP64 products M W^T and V^T M
     double *Cp, *Dp;
     std::vector<const float *> M;
     std::vector<int64_t> ldm;
@@ -45,6 +46,12 @@ struct Ctx {
     Job *djobs;                   // device copy of `jobs` (workspace)
     std::vector<Job> jobs;        // one job per level, then the FP32 finest-level job
     std::vector<int8_t> depths;   // depth of every executed iteration (host mirror)
+    bool prof = true;             // time launches of the kinds in the plan's profile mask
+    struct ProfEvent {
+        int kind;
+        hipEvent_t begin, end;
+    };
+    std::vector<ProfEvent> prof_pending;   // event pairs recorded by this solve
 };
 
 // allow_stream: jobs of large levels may use the streaming kernels (single
@@ -54,6 +61,11 @@ Ctx make_ctx(nmf_plan_t plan, const float *dM, float *dV, float *dW, void *dws, 
 // BF16 mode: the BF16 operand copies of every level (and padding of the V
 // and W copies); nothing in FP32 mode.
 nmf_status prepare_bf16(Ctx &c);
+// The whole multilevel solve of nmf_solve on a workspace at dWorkspace (256-byte
+// aligned, plan->p.ws.total bytes); arguments already validated.  profile:
+// honour the plan's profile mask (HIP events); false records no event.
+nmf_status solve_on(nmf_plan_t plan, const float *dM, float *dV, float *dW, int32_t iters,
+                    void *dWorkspace, hipStream_t s, nmf_result *hOut, bool profile);
 // Fill an nmf_result from the final device state and the host depth log.
 nmf_status result_from_state(nmf_plan_t plan, const DevState &hs,
                              const std::vector<int8_t> &depths, nmf_result *out);

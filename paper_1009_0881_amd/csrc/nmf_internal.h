@@ -4,6 +4,7 @@
 
 #include <cstddef>
 #include <cstdint>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -84,11 +85,14 @@ enum KernelKind {
     K_RESTRICT, K_PROLONG, K_SUMSQ, K_NUM_KINDS
 };
 
-// Optional HIP-event timing of selected kernel kinds.
+// Optional HIP-event timing of selected kernel kinds.  A solve takes event
+// pairs from the pool, keeps its pending pairs in its own context and returns
+// them (with its times added to the totals) when it has synchronised; the
+// mutex makes concurrent solves on one plan safe.
 struct Profiler {
     uint32_t mask = 0;
-    std::vector<hipEvent_t> pool;            // created lazily, reused
-    std::vector<int> pending_kind;           // kind of event pair i (pool[2i], pool[2i+1])
+    std::mutex mu;                           // guards pool, counts, ms
+    std::vector<hipEvent_t> pool;            // idle events, created lazily, reused
     int64_t counts[K_NUM_KINDS] = {};
     double ms[K_NUM_KINDS] = {};
 };
@@ -103,7 +107,6 @@ struct Plan {
     int num_cu;
     int32_t gram_w_parts;
     int64_t gram_w_chunk;
-    std::string err;
 };
 
 std::vector<Step> make_schedule(int cycle, int levels, int64_t iters);
@@ -237,9 +240,9 @@ hipError_t enable_stream_lds();   // streaming A-passes (called by enable_large_
 // of W (G = V^T V, rhs = C columns); warm-started from the current factor.
 // A non-positive pivot sets bit 2 of *flags (the affected problem keeps its
 // last feasible iterate).
-hipError_t launch_nnls_rows(int rpad, const double *Gd, const float *A, int64_t m, int r,
+hipError_t launch_nnls_rows(int rpad, const double *Gd, const double *A, int64_t m, int r,
                             float *V, int32_t *flags, const int32_t *stop, hipStream_t s);
-hipError_t launch_nnls_cols(int rpad, const double *Gd, const float *C, int64_t n, int r,
+hipError_t launch_nnls_cols(int rpad, const double *Gd, const double *C, int64_t n, int r,
                             float *W, float *Wt, double *rparts, int32_t *flags,
                             const int32_t *stop, hipStream_t s);
 int nnls_cols_blocks(int64_t n);

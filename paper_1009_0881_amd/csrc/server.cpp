@@ -211,7 +211,10 @@ void worker_loop(nmf_server_s *S) {
         if ((st = admit(S)) != NMF_OK) break;
         if (S->ex->empty()) continue;
         if ((st = S->ex->tick()) != NMF_OK) break;
-        S->stats[5] = S->ex->ticks();
+        {
+            std::lock_guard<std::mutex> lk(S->mu);
+            S->stats[5] = S->ex->ticks();
+        }
         if (S->ex->any_done() && (st = collect(S)) != NMF_OK) break;
     }
     if (st != NMF_OK) {
