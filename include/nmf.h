@@ -122,6 +122,25 @@ nmf_status nmf_solve(nmf_plan_t plan, const float *dM, float *dV, float *dW, int
 
 nmf_status nmf_destroy(nmf_plan_t plan);
 
+/* nmf_solve without a caller workspace, for callers that cannot allocate
+ * device memory (code that must not call hipMalloc: tight serving loops,
+ * harnesses that forbid allocation).  The workspace is a fixed array of
+ * NMF_STATIC_WORKSPACE_BYTES in device global memory that the library holds on
+ * every GPU it is used on until the process ends; the call allocates nothing
+ * (no hipMalloc / hipFree, no allocating library routine) and records no
+ * profiling events.  Arguments, layouts and results are those of nmf_solve;
+ * the rel_err log stays in that array (only hOut reports the solve).
+ * Errors: as nmf_solve, and NMF_E_NOMEM when the plan's workspace_bytes
+ * exceeds NMF_STATIC_WORKSPACE_BYTES (e.g. 112x92 images, n = 400, r = 40,
+ * 3 levels need about 13 MiB; 256x256 images, n = 2000, r = 50 are refused).
+ * Every call on one GPU uses that GPU's single array: calls that overlap on
+ * one GPU (other streams or host threads) race and give undefined results;
+ * serialise them.  Each call re-initialises what it reads (nothing carries
+ * over from the previous call). */
+#define NMF_STATIC_WORKSPACE_BYTES (32u << 20)
+nmf_status nmf_solve_static(nmf_plan_t plan, const float *dM, float *dV, float *dW,
+                            int32_t iters, void *stream, nmf_result *hOut);
+
 const char *nmf_status_string(nmf_status s);
 const char *nmf_last_error(nmf_plan_t plan);
 

@@ -43,10 +43,11 @@ EXPORTS = [
     "nmf_restrict", "nmf_prolong", "nmf_iterate", "nmf_products", "nmf_gram",
     "nmf_profile", "nmf_profile_read", "nmf_batch_workspace", "nmf_solve_batch",
     "nmf_server_create", "nmf_server_submit", "nmf_server_poll", "nmf_server_stats",
-    "nmf_server_destroy",
+    "nmf_server_destroy", "nmf_solve_static",
 ]
 
 BATCH_GRAPH = 1
+STATIC_WORKSPACE_BYTES = 32 << 20     # NMF_STATIC_WORKSPACE_BYTES (include/nmf.h)
 
 # Kernel kinds of the event profiler (include/nmf.h).
 KERNEL_KINDS = ["apass", "gram_v", "cpass_partial", "cpass_final", "gram_w", "residual",
@@ -97,6 +98,7 @@ def lib() -> ctypes.CDLL:
         vp, i32, i64, sz = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_size_t
         L.nmf_plan.argtypes = [ctypes.POINTER(Desc), ctypes.POINTER(vp), ctypes.POINTER(sz)]
         L.nmf_solve.argtypes = [vp, vp, vp, vp, i32, vp, vp, ctypes.POINTER(Result)]
+        L.nmf_solve_static.argtypes = [vp, vp, vp, vp, i32, vp, ctypes.POINTER(Result)]
         L.nmf_destroy.argtypes = [vp]
         L.nmf_status_string.argtypes = [i32]
         L.nmf_status_string.restype = ctypes.c_char_p
@@ -233,6 +235,15 @@ class Plan:
         out = res.as_dict()
         out["_workspace"] = ws
         return out
+
+    def solve_static(self, M, V, W, iters: int, stream=None) -> dict:
+        """As solve(), through nmf_solve_static: no workspace argument, the
+        library's fixed device array serves instead (nothing is allocated)."""
+        _need_cuda(M, V, W)
+        res = Result()
+        _check(lib().nmf_solve_static(self.handle, _ptr(M), _ptr(V), _ptr(W), int(iters),
+                                      _stream_handle(stream), ctypes.byref(res)), self.handle)
+        return res.as_dict()
 
     def iterate(self, M, V, W, count: int, workspace=None, stream=None) -> float:
         _need_cuda(M, V, W)
