@@ -91,22 +91,23 @@ __device__ void apass_tile(const Job &J, int tile, double *smem) {
         for (int t = 0; t < RT; ++t) hi[q][t] = lo[q][t] = v4f{0.0f, 0.0f, 0.0f, 0.0f};
 
     float a0[S][RW], b0[S][RT], a1[S][RW], b1[S][RT];
+    // Loads are unconditional from clamped, in-bounds addresses (column j of
+    // a step past the wave's range or past n reads column n - 1; a row past m
+    // reads row 0) and the operands are masked where they are used: a select
+    // right after a load would make the compiler wait for it there, which
+    // defeats the double buffering.  Rows past m only feed rows of A that are
+    // never stored or used; columns outside the range get M = 0.
     auto load = [&](int64_t s, float (&a)[S][RW], float (&b)[S][RT]) {
 #pragma unroll
         for (int u = 0; u < S; ++u) {
             const int64_t j = 4 * (s + u) + lk;
-            const bool ok = (s + u) < s_end && j < n;
+            const int64_t jc = j < n ? j : n - 1;
 #pragma unroll
-            for (int q = 0; q < RW; ++q) a[u][q] = (ok && rok[q]) ? Mr[q][j * ldm] : 0.0f;
-            {
-                float w[RT];
-                load_wt<RT>(Wt + (ok ? j : 0) * RPAD, li, w);
-#pragma unroll
-                for (int t = 0; t < RT; ++t) b[u][t] = ok ? w[t] : 0.0f;
-            }
+            for (int q = 0; q < RW; ++q) a[u][q] = Mr[q][jc * ldm];
+            load_wt<RT>(Wt + jc * RPAD, li, b[u]);
         }
     };
-    auto compute = [&](const float (&a)[S][RW], const float (&b)[S][RT]) {
+    auto compute = [&](int64_t s, const float (&a)[S][RW], const float (&b)[S][RT]) {
 #pragma unroll
         for (int u0 = 0; u0 < S; u0 += 4) {      // 4 steps = 16 products per chain
             v4f acc[RW][RT];
@@ -115,22 +116,30 @@ __device__ void apass_tile(const Job &J, int tile, double *smem) {
 #pragma unroll
                 for (int t = 0; t < RT; ++t) acc[q][t] = v4f{0.0f, 0.0f, 0.0f, 0.0f};
 #pragma unroll
-            for (int u = u0; u < u0 + 4; ++u)
+            for (int u = u0; u < u0 + 4; ++u) {
+                const bool ok = (s + u) < s_end && 4 * (s + u) + lk < n;
 #pragma unroll
-                for (int q = 0; q < RW; ++q)
+                for (int q = 0; q < RW; ++q) {
+                    const float av = ok ? a[u][q] : 0.0f;
 #pragma unroll
                     for (int t = 0; t < RT; ++t)
-                        acc[q][t] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[u][q], b[u][t],
-                                                                         acc[q][t], 0, 0, 0);
+                        acc[q][t] = __builtin_amdgcn_mfma_f32_16x16x4f32(av, b[u][t], acc[q][t],
+                                                                         0, 0, 0);
+                }
+            }
 #pragma unroll
             for (int q = 0; q < RW; ++q)
 #pragma unroll
                 for (int t = 0; t < RT; ++t) two_sum_acc(hi[q][t], lo[q][t], acc[q][t]);
         }
     };
-    // factor rows of the epilogue: 16 lanes per row, rows tid/16 + 16i
+    // factor rows of the epilogue (16 lanes per row, rows tid/16 + 16i) and
+    // the Gram B: loads issued now from clamped addresses, values masked and
+    // stored after the main loop, so their latency overlaps it
     constexpr int EPR = TM / 16;
     double xv[UPD ? EPR : 1][RT];
+    float xf[UPD ? EPR : 1][RT];
+    GramRegs<RPAD> gregs;
     if constexpr (UPD) {
 #pragma unroll
         for (int i = 0; i < EPR; ++i) {
@@ -138,22 +147,41 @@ __device__ void apass_tile(const Job &J, int tile, double *smem) {
 #pragma unroll
             for (int t = 0; t < RT; ++t) {
                 const int k = 16 * t + (tid & 15);
-                xv[i][t] = (vrow < m && k < r) ? (double)Vg[vrow + (int64_t)k * m] : 0.0;
+                xf[i][t] = Vg[(vrow < m ? vrow : m - 1) + (int64_t)(k < r ? k : 0) * m];
             }
         }
+        gram_fetch<RPAD>(J.Bd, r, gregs);
     }
+    auto epilogue_inputs = [&]() {
+        if constexpr (UPD) {
+            gram_put<RPAD>(gregs, r, Gs, GS, Gi);
+#pragma unroll
+            for (int i = 0; i < EPR; ++i) {
+                const int64_t vrow = brow + (tid >> 4) + 16 * i;
+#pragma unroll
+                for (int t = 0; t < RT; ++t) {
+                    const int k = 16 * t + (tid & 15);
+                    xv[i][t] = (vrow < m && k < r) ? (double)xf[i][t] : 0.0;
+                }
+            }
+        }
+    };
     double *Aw = As + wave * TMW * AS;
     if constexpr (!BF) {
-        if (s_begin < s_end) load(s_begin, a0, b0);
-        // the Gram goes to LDS while the first operand batch is in flight
-        if constexpr (UPD) load_gram<RPAD>(J.Bd, r, Gs, GS, Gi);
+        load(s_begin, a0, b0);
+        // unconditional prefetch of the next batch (clamped addresses; see
+        // load); the scheduling barriers keep its loads ahead of the compute
+        // of the current batch instead of next to their use
         for (int64_t s = s_begin; s < s_end; s += 2 * S) {
-            if (s + S < s_end) load(s + S, a1, b1);
-            compute(a0, b0);
+            load(s + S, a1, b1);
+            __builtin_amdgcn_sched_barrier(0);
+            compute(s, a0, b0);
             if (s + S >= s_end) break;
-            if (s + 2 * S < s_end) load(s + 2 * S, a0, b0);
-            compute(a1, b1);
+            load(s + 2 * S, a0, b0);
+            __builtin_amdgcn_sched_barrier(0);
+            compute(s + S, a1, b1);
         }
+        epilogue_inputs();
         // hi[q][t][v] + lo[q][t][v] = A[row0 + 16q + 4*lk + v][16t + li]
 #pragma unroll
         for (int q = 0; q < RW; ++q)
@@ -214,7 +242,6 @@ __device__ void apass_tile(const Job &J, int tile, double *smem) {
                                                                             acc[q][t], 0, 0, 0);
         };
         if (k_begin < k_end) loadb(k_begin, ma0, wb0);
-        if constexpr (UPD) load_gram<RPAD>(J.Bd, r, Gs, GS, Gi);
         for (int64_t k0 = k_begin; k0 < k_end; k0 += 2 * SB) {
             if (k0 + SB < k_end) loadb(k0 + SB, ma1, wb1);
             computeb(ma0, wb0);
@@ -222,6 +249,7 @@ __device__ void apass_tile(const Job &J, int tile, double *smem) {
             if (k0 + 2 * SB < k_end) loadb(k0 + 2 * SB, ma0, wb0);
             computeb(ma1, wb1);
         }
+        epilogue_inputs();
         // acc[q][t][v] = A[row0 + 16q + 4*lk + v][16t + li]
 #pragma unroll
         for (int q = 0; q < RW; ++q)
@@ -377,42 +405,48 @@ __device__ __forceinline__ void cpass_tile(const Job &J, int tx, int ty, int ntx
 #pragma unroll
     for (int d = 0; d < DMAX; ++d) dacc[d] = v4d{0.0, 0.0, 0.0, 0.0};
 
-    // FP32: rows ib..ib+3 (ib = i0 + 4 lg) of the wave's M columns and of V
-    auto load_v = [&](int64_t ib, v4f (&vv)[RT]) {
-        if (vec && ib + 3 < rb) {
+    // FP32: rows ib..ib+3 (ib = i0 + 4 lg) of the wave's M columns and of V.
+    // Loads are unconditional from clamped, in-bounds addresses (rows past m
+    // read the last rows, columns k >= r of V read column 0) and V is masked
+    // where it is used (rows outside [ra, rb), k >= r): a select right after
+    // a load would make the compiler wait for it there and defeat the double
+    // buffering.  M columns past n were clamped to column 0: they only feed
+    // entries of C that are not stored.  VEC: float4 loads (m, ldm multiples
+    // of 4 and 16-byte aligned bases), else four scalar loads.
+    auto load1 = [&](auto vec_c, int64_t i0, v4f (&mv)[WC], v4f (&vv)[RT]) {
+        constexpr bool VEC = decltype(vec_c)::value;
+        const int64_t ib = i0 + 4 * lg;
+        if constexpr (VEC) {
+            const int64_t ibc = ib < m ? ib : m - 4;
+#pragma unroll
+            for (int c = 0; c < WC; ++c) mv[c] = *(gmem<const v4f> *)(Mc[c] + ibc);
 #pragma unroll
             for (int t = 0; t < RT; ++t) {
                 const int k = 16 * t + lj;
-                vv[t] = (k < r) ? *(gmem<const v4f> *)(V + ib + (int64_t)k * m)
-                                : v4f{0.0f, 0.0f, 0.0f, 0.0f};
+                vv[t] = *(gmem<const v4f> *)(V + ibc + (int64_t)(k < r ? k : 0) * m);
             }
         } else {
 #pragma unroll
             for (int s2 = 0; s2 < 4; ++s2) {
-                const int64_t i = ib + s2;
+                const int64_t ic = ib + s2 < m ? ib + s2 : m - 1;
+#pragma unroll
+                for (int c = 0; c < WC; ++c) mv[c][s2] = Mc[c][ic];
 #pragma unroll
                 for (int t = 0; t < RT; ++t) {
                     const int k = 16 * t + lj;
-                    vv[t][s2] = (k < r && i < rb) ? V[i + (int64_t)k * m] : 0.0f;
+                    vv[t][s2] = V[ic + (int64_t)(k < r ? k : 0) * m];
                 }
             }
         }
     };
-    auto load1 = [&](int64_t i0, v4f (&mv)[WC], v4f (&vv)[RT]) {
-        const int64_t ib = i0 + 4 * lg;
-        if (vec && ib + 3 < rb) {
+    // V operands of rows ib..ib+3 with rows outside [ra, rb) and k >= r zeroed
+    auto mask_v = [&](int64_t ib, const v4f (&vv)[RT], v4f (&vm)[RT]) {
 #pragma unroll
-            for (int c = 0; c < WC; ++c)
-                mv[c] = jok[c] ? *(gmem<const v4f> *)(Mc[c] + ib) : v4f{0.0f, 0.0f, 0.0f, 0.0f};
-        } else {
+        for (int t = 0; t < RT; ++t) {
+            const bool kok = 16 * t + lj < r;
 #pragma unroll
-            for (int s2 = 0; s2 < 4; ++s2) {
-                const int64_t i = ib + s2;
-#pragma unroll
-                for (int c = 0; c < WC; ++c) mv[c][s2] = (jok[c] && i < rb) ? Mc[c][i] : 0.0f;
-            }
+            for (int s2 = 0; s2 < 4; ++s2) vm[t][s2] = (kok && ib + s2 < rb) ? vv[t][s2] : 0.0f;
         }
-        load_v(ib, vv);
     };
     auto dtile_f64 = [&](const v4f (&vv)[RT], const int (&ta)[DMAX], const int (&tb)[DMAX],
                          const bool (&ok)[DMAX]) {
@@ -458,44 +492,54 @@ __device__ __forceinline__ void cpass_tile(const Job &J, int tx, int ty, int ntx
     };
 
     if constexpr (!BF) {
-        auto load = [&](int64_t i0, v4f (&mv)[SB][WC], v4f (&vv)[SB][RT]) {
+        auto main_loop = [&](auto vec_c) {
+            auto load = [&](int64_t i0, v4f (&mv)[SB][WC], v4f (&vv)[SB][RT]) {
 #pragma unroll
-            for (int u = 0; u < SB; ++u) load1(i0 + 16 * u, mv[u], vv[u]);
-        };
-        auto compute = [&](const v4f (&mvs)[SB][WC], const v4f (&vvs)[SB][RT]) {
+                for (int u = 0; u < SB; ++u) load1(vec_c, i0 + 16 * u, mv[u], vv[u]);
+            };
+            auto compute = [&](int64_t i0, const v4f (&mvs)[SB][WC], const v4f (&vvs)[SB][RT]) {
 #pragma unroll
-            for (int u = 0; u < SB; ++u) {
-                v4f acc[WC][RT];
-#pragma unroll
-                for (int c = 0; c < WC; ++c)
-#pragma unroll
-                    for (int t = 0; t < RT; ++t) acc[c][t] = v4f{0.0f, 0.0f, 0.0f, 0.0f};
-#pragma unroll
-                for (int s2 = 0; s2 < 4; ++s2)
+                for (int u = 0; u < SB; ++u) {
+                    v4f vm[RT];
+                    mask_v(i0 + 16 * u + 4 * lg, vvs[u], vm);
+                    v4f acc[WC][RT];
 #pragma unroll
                     for (int c = 0; c < WC; ++c)
 #pragma unroll
-                        for (int t = 0; t < RT; ++t)
-                            acc[c][t] = __builtin_amdgcn_mfma_f32_16x16x4f32(mvs[u][c][s2], vvs[u][t][s2],
-                                                                             acc[c][t], 0, 0, 0);
+                        for (int t = 0; t < RT; ++t) acc[c][t] = v4f{0.0f, 0.0f, 0.0f, 0.0f};
 #pragma unroll
-                for (int c = 0; c < WC; ++c)
+                    for (int s2 = 0; s2 < 4; ++s2)
 #pragma unroll
-                    for (int t = 0; t < RT; ++t) two_sum_acc(hi[c][t], lo[c][t], acc[c][t]);
-                dtile_f64(vvs[u], dta, dtb, dok);
-            }
-        };
-        if (ra < rb) {
+                        for (int c = 0; c < WC; ++c)
+#pragma unroll
+                            for (int t = 0; t < RT; ++t)
+                                acc[c][t] = __builtin_amdgcn_mfma_f32_16x16x4f32(
+                                    mvs[u][c][s2], vm[t][s2], acc[c][t], 0, 0, 0);
+#pragma unroll
+                    for (int c = 0; c < WC; ++c)
+#pragma unroll
+                        for (int t = 0; t < RT; ++t) two_sum_acc(hi[c][t], lo[c][t], acc[c][t]);
+                    dtile_f64(vm, dta, dtb, dok);
+                }
+            };
+            // the next batch is loaded unconditionally (clamped addresses): a
+            // conditional prefetch makes the compiler wait for every load at
+            // the join; the last one or two batches are loaded for nothing
             v4f m0[SB][WC], m1[SB][WC], v0[SB][RT], v1[SB][RT];
             load(ra, m0, v0);
             for (int64_t i0 = ra; i0 < rb; i0 += 32 * SB) {
-                const bool more = i0 + 16 * SB < rb;
-                if (more) load(i0 + 16 * SB, m1, v1);
-                compute(m0, v0);
-                if (!more) break;
-                if (i0 + 32 * SB < rb) load(i0 + 32 * SB, m0, v0);
-                compute(m1, v1);
+                load(i0 + 16 * SB, m1, v1);
+                __builtin_amdgcn_sched_barrier(0);
+                compute(i0, m0, v0);
+                if (i0 + 16 * SB >= rb) break;
+                load(i0 + 32 * SB, m0, v0);
+                __builtin_amdgcn_sched_barrier(0);
+                compute(i0 + 16 * SB, m1, v1);
             }
+        };
+        if (ra < rb) {
+            if (vec) main_loop(std::true_type{});
+            else main_loop(std::false_type{});
         }
     } else {
         // rows m..mpad of the copies are zero: K-steps may run past m
@@ -642,9 +686,11 @@ __device__ __forceinline__ void cpass_tile(const Job &J, int tx, int ty, int ntx
         }
         if constexpr (!BF) {
             for (int64_t i0 = ra; i0 < rb; i0 += 16) {
-                v4f vv[RT];
-                load_v(i0 + 4 * lg, vv);
-                dtile_f64(vv, eta, etb, eok);
+                v4f mv[WC], vv[RT], vm[RT];
+                if (vec) load1(std::true_type{}, i0, mv, vv);
+                else load1(std::false_type{}, i0, mv, vv);
+                mask_v(i0 + 4 * lg, vv, vm);
+                dtile_f64(vm, eta, etb, eok);
             }
         } else {
             for (int64_t ik = ra; ik < rb; ik += 32) {
@@ -874,15 +920,22 @@ __device__ __forceinline__ void cfinal_tile(const Job &J, int tile, double *smem
     // factor columns of the update: 16 lanes per column, column j0 + tid/16
     // (all waves for CF = 16, wave 0 for CF = 4)
     const bool colt = tid < 16 * CF;
+    // The column entries of W and the Gram D are loaded first (clamped
+    // addresses) and masked / stored only once the C sums below are done, so
+    // all of these loads are in flight together.
     double xw[RT];
+    float xwf[RT];
+    GramRegs<RPAD> gregs;
     if constexpr (MODE != MODE_STORE) {
         const int64_t j = j0 + (tid >> 4);
+        const int64_t jc = j < n ? j : n - 1;
 #pragma unroll
         for (int t = 0; t < RT; ++t) {
             const int k = 16 * t + (tid & 15);
-            xw[t] = (colt && j < n && k < r) ? (double)to_global(J.W)[(int64_t)k * n + j] : 0.0;
+            xwf[t] = to_global(J.W)[(int64_t)(k < r ? k : 0) * n + jc];
         }
     }
+    if constexpr (UPD) gram_fetch<RPAD>(J.Dd, r, gregs);
     if constexpr (!INIT) {
         constexpr int B = CF == 4 ? 64 : 16;
         const int64_t str = (int64_t)r * n;
@@ -894,17 +947,20 @@ __device__ __forceinline__ void cfinal_tile(const Job &J, int tile, double *smem
             const int64_t j = j0 + jj;
             off[i] = (jj < CF && k < r && j < n) ? j * r + k : -1;
         }
+        bool cok[PER];
+#pragma unroll
+        for (int i = 0; i < PER; ++i) cok[i] = off[i] >= 0;
         if (J.prec) {
             const float *src[PER];
 #pragma unroll
             for (int i = 0; i < PER; ++i)
-                src[i] = off[i] >= 0 ? reinterpret_cast<const float *>(J.Cp) + off[i] : nullptr;
-            sum_strided_n<PER, B>(src, str, J.chunks, cs);
+                src[i] = reinterpret_cast<const float *>(J.Cp) + (cok[i] ? off[i] : 0);
+            sum_strided_n<PER, B>(src, cok, str, J.chunks, cs);
         } else {
             const double *src[PER];
 #pragma unroll
-            for (int i = 0; i < PER; ++i) src[i] = off[i] >= 0 ? J.Cp + off[i] : nullptr;
-            sum_strided_n<PER, B>(src, str, J.chunks, cs);
+            for (int i = 0; i < PER; ++i) src[i] = J.Cp + (cok[i] ? off[i] : 0);
+            sum_strided_n<PER, B>(src, cok, str, J.chunks, cs);
         }
 #pragma unroll
         for (int i = 0; i < PER; ++i) {
@@ -912,7 +968,15 @@ __device__ __forceinline__ void cfinal_tile(const Job &J, int tile, double *smem
             if (jj < CF) Cs[jj * CS + k] = cs[i];
         }
     }
-    if constexpr (UPD) load_gram<RPAD>(J.Dd, r, Gs, GS, Gi);
+    if constexpr (UPD) gram_put<RPAD>(gregs, r, Gs, GS, Gi);
+    if constexpr (MODE != MODE_STORE) {
+        const int64_t j = j0 + (tid >> 4);
+#pragma unroll
+        for (int t = 0; t < RT; ++t) {
+            const int k = 16 * t + (tid & 15);
+            xw[t] = (colt && j < n && k < r) ? (double)xwf[t] : 0.0;
+        }
+    }
     if constexpr (!INIT) __syncthreads();
     if constexpr (MODE == MODE_STORE) {
         for (int e = tid; e < CF * r; e += 256) {

@@ -58,6 +58,8 @@ __device__ __forceinline__ float row_bcast(float v) {
 
 __device__ __forceinline__ double fma_t(double a, double b, double c) { return __builtin_fma(a, b, c); }
 __device__ __forceinline__ float fma_t(float a, float b, float c) { return __builtin_fmaf(a, b, c); }
+__device__ __forceinline__ double max_t(double a, double b) { return __builtin_fmax(a, b); }
+__device__ __forceinline__ float max_t(float a, float b) { return __builtin_fmaxf(a, b); }
 
 // Returns v unchanged, but only once dep has been computed: an empty asm that
 // takes dep as an input orders the instructions that use the result after
@@ -72,23 +74,39 @@ __device__ __forceinline__ int ordered_after(int v, T dep) {
 // (lane p holding entries 16t + p) and the r x r Gram G in LDS (row stride
 // gs, zero-padded).  Padded entries (l >= r) are zero and skipped in whole
 // groups of 4.
+//
+// The Gram rows are read in batches of GB rows, each batch issued one batch
+// ahead of the FMAs that use it (scheduling barriers keep the reads there;
+// left alone, the compiler waits on every read next to its use).  Rows
+// l >= r are zero in LDS: their batches are read but not used.
 template <int RT, class T>
 __device__ __forceinline__ void gram_matvec(const T (&x)[RT], const T *G, int gs, int r, int p,
                                             T (&acc)[RT]) {
-    constexpr int RPAD = 16 * RT;
+    constexpr int RPAD = 16 * RT, GB = 8, NB = RPAD / GB;
 #pragma unroll
     for (int t = 0; t < RT; ++t) acc[t] = T(0);
-    static_for<RPAD / 4>([&](auto lg_c) {
-        constexpr int lg = decltype(lg_c)::value;
-        if (4 * lg < r) {
-            static_for<4>([&](auto lq_c) {
-                constexpr int l = 4 * lg + decltype(lq_c)::value;
-                const T xl = row_bcast<l % 16>(x[l / 16]);
-                const T *gr = G + l * gs + p;
+    T buf[2][GB][RT];
+    auto fetch = [&](auto b_c) {
+        constexpr int b = decltype(b_c)::value;
 #pragma unroll
-                for (int t = 0; t < RT; ++t) acc[t] = fma_t(xl, gr[16 * t], acc[t]);
+        for (int i = 0; i < GB; ++i)
+#pragma unroll
+            for (int t = 0; t < RT; ++t) buf[b & 1][i][t] = G[(GB * b + i) * gs + p + 16 * t];
+    };
+    fetch(std::integral_constant<int, 0>{});
+    static_for<NB>([&](auto b_c) {
+        constexpr int b = decltype(b_c)::value;
+        if constexpr (b + 1 < NB) fetch(std::integral_constant<int, b + 1>{});
+        __builtin_amdgcn_sched_barrier(0);
+        if (GB * b < r) {
+            static_for<GB>([&](auto i_c) {
+                constexpr int i = decltype(i_c)::value, l = GB * b + i;
+                const T xl = row_bcast<l % 16>(x[l / 16]);
+#pragma unroll
+                for (int t = 0; t < RT; ++t) acc[t] = fma_t(xl, buf[b & 1][i][t], acc[t]);
             });
         }
+        __builtin_amdgcn_sched_barrier(0);
     });
 }
 
@@ -140,15 +158,22 @@ __device__ __forceinline__ void row_update(T (&x)[RT], const T *G, int gs, const
                 const T *gr = G + ordered_after((k + PD) * gs + p, dprev);
 #pragma unroll
                 for (int t = (k + PD) / 16; t < RT; ++t) rnew[t] = gr[16 * t];
+                // keep the loads here: the scheduler would otherwise sink them to
+                // their use PD steps later and wait for LDS there
+                __builtin_amdgcn_sched_barrier(0);
             }
-            const bool own = p == pk && ginv[kt] > T(0);
+            // Only the owner lane's d is broadcast.  With 1/G_kk = 0 (G_kk = 0)
+            // c0 = x_k and the floor is x_k itself, so d = 0 and x_k keeps its
+            // value; the floor is chosen off the dependency chain.  Lanes
+            // p <= pk update a g entry they no longer read.
+            const T lo = ginv[kt] > T(0) ? T(0) : x[kt];
             const T c0 = fma_t(g[kt], ginv[kt], x[kt]);
-            const T cand = c0 > T(0) ? c0 : T(0);
-            T d = own ? cand - x[kt] : T(0);
-            x[kt] = own ? cand : x[kt];
+            const T cand = max_t(c0, lo);
+            T d = cand - x[kt];
+            x[kt] = p == pk ? cand : x[kt];
             d = row_bcast<pk>(d);
             dprev = d;
-            g[kt] = p > pk ? fma_t(-d, rows[0][kt], g[kt]) : g[kt];
+            g[kt] = fma_t(-d, rows[0][kt], g[kt]);
 #pragma unroll
             for (int t = kt + 1; t < RT; ++t) g[t] = fma_t(-d, rows[0][t], g[t]);
 #pragma unroll
@@ -171,29 +196,52 @@ __device__ __forceinline__ void row_update(T (&x)[RT], const T *G, int gs, const
     }
 }
 
-// Load an r x r FP64 Gram (row-major, stride r) into LDS zero-padded to
-// RPAD x RPAD (stride gs), and its inverse diagonal.  Blocks of 256 threads:
-// every thread issues all of its loads before its first store, so the block
-// waits for one memory latency.
+// An r x r FP64 Gram (row-major, stride r) staged through registers: thread
+// tid holds entries tid + 256 i of the RPAD x RPAD zero-padded matrix and
+// diagonal entry tid.  gram_fetch issues the loads (clamped addresses, no
+// value depends on them yet); gram_put masks and stores them into LDS (stride
+// gs) with the inverse diagonal, so the loads can be in flight while other
+// work runs in between.  Blocks of 256 threads.
+template <int RPAD>
+struct GramRegs {
+    static constexpr int PER = (RPAD * RPAD + 255) / 256;
+    double v[PER];
+    double g;
+};
+
+template <int RPAD>
+__device__ __forceinline__ void gram_fetch(const double *__restrict__ Gd, int r,
+                                           GramRegs<RPAD> &R) {
+    const auto G = to_global(Gd);
+    const int tid = threadIdx.x;
+#pragma unroll
+    for (int i = 0; i < GramRegs<RPAD>::PER; ++i) {
+        const int e = tid + 256 * i, a = e / RPAD, b = e % RPAD;
+        R.v[i] = G[(e < RPAD * RPAD && a < r && b < r) ? a * r + b : 0];
+    }
+    R.g = G[tid < r ? tid * r + tid : 0];
+}
+
+template <int RPAD, class T = double>
+__device__ __forceinline__ void gram_put(const GramRegs<RPAD> &R, int r, T *Gs, int gs, T *gi) {
+    const int tid = threadIdx.x;
+#pragma unroll
+    for (int i = 0; i < GramRegs<RPAD>::PER; ++i) {
+        const int e = tid + 256 * i, a = e / RPAD, b = e % RPAD;
+        if (e < RPAD * RPAD) Gs[a * gs + b] = (a < r && b < r) ? (T)R.v[i] : T(0);
+    }
+    if (tid < RPAD) gi[tid] = (tid < r && R.g > 0.0) ? (T)(1.0 / R.g) : T(0);
+}
+
+// Load an r x r FP64 Gram into LDS zero-padded to RPAD x RPAD (stride gs),
+// and its inverse diagonal: every thread issues all of its loads before its
+// first store, so the block waits for one memory latency.
 template <int RPAD, class T = double>
 __device__ __forceinline__ void load_gram(const double *__restrict__ Gd, int r, T *Gs, int gs,
                                           T *gi) {
-    constexpr int PER = (RPAD * RPAD + 255) / 256;
-    const auto G = to_global(Gd);
-    const int tid = threadIdx.x;
-    double v[PER];
-#pragma unroll
-    for (int i = 0; i < PER; ++i) {
-        const int e = tid + 256 * i, a = e / RPAD, b = e % RPAD;
-        v[i] = (e < RPAD * RPAD && a < r && b < r) ? G[a * r + b] : 0.0;
-    }
-    const double g = (tid < r) ? G[tid * r + tid] : 0.0;
-#pragma unroll
-    for (int i = 0; i < PER; ++i) {
-        const int e = tid + 256 * i, a = e / RPAD, b = e % RPAD;
-        if (e < RPAD * RPAD) Gs[a * gs + b] = (T)v[i];
-    }
-    if (tid < RPAD) gi[tid] = g > 0.0 ? (T)(1.0 / g) : T(0);
+    GramRegs<RPAD> R;
+    gram_fetch<RPAD>(Gd, r, R);
+    gram_put<RPAD, T>(R, r, Gs, gs, gi);
 }
 
 // Sum of `count` values p0[0], p0[stride], ... (FP64 or FP32) in FP64, in
@@ -223,11 +271,13 @@ __device__ __forceinline__ double sum_strided(const T *__restrict__ pg, int64_t 
 }
 
 // Sums of `count` values (FP64 or FP32) for N outputs at once, in FP64:
-// out[e] = sum over p = 0..count-1 of pg[e][p * stride] in index order (pg[e]
-// null: 0).  The loads of all N outputs go out together in batches of B.
+// out[e] = sum over p = 0..count-1 of pg[e][p * stride] in index order, for
+// the outputs with ok[e] (the others are 0; pg[e] must still point at `count`
+// readable values).  The loads of all N outputs go out together in batches of
+// B, from clamped indices as in sum_strided.
 template <int N, int B = 16, class T = double>
-__device__ __forceinline__ void sum_strided_n(const T *const (&pg)[N], int64_t stride, int count,
-                                              double (&out)[N]) {
+__device__ __forceinline__ void sum_strided_n(const T *const (&pg)[N], const bool (&ok)[N],
+                                              int64_t stride, int count, double (&out)[N]) {
 #pragma unroll
     for (int e = 0; e < N; ++e) out[e] = 0.0;
     for (int p = 0; p < count; p += B) {
@@ -236,14 +286,12 @@ __device__ __forceinline__ void sum_strided_n(const T *const (&pg)[N], int64_t s
         for (int e = 0; e < N; ++e)
 #pragma unroll
             for (int u = 0; u < B; ++u)
-                t[e][u] = (pg[e] && p + u < count)
-                              ? (double)to_global(pg[e])[(int64_t)(p + u) * stride]
-                              : 0.0;
+                t[e][u] = (double)to_global(pg[e])[(int64_t)(p + u < count ? p + u : count - 1) * stride];
 #pragma unroll
         for (int e = 0; e < N; ++e)
 #pragma unroll
             for (int u = 0; u < B; ++u)
-                if (p + u < count) out[e] += t[e][u];
+                if (ok[e] && p + u < count) out[e] += t[e][u];
     }
 }
 
