@@ -342,7 +342,7 @@ nmf_status sweep(Ctx &c, int d, bool fp32 = false) {
         if (st != NMF_OK) return st;
         NMF_LAUNCH(K_RESID, launch_residual(c.rparts, nnls_cols_blocks(n), c.Dd, c.Bd, r, c.norm,
                                             d, c.log_rel, c.log_depth, p.d.log_cap, c.st,
-                                            p.d.tol, c.s));
+                                            c.jobs[0].hstop, p.d.tol, c.s));
     } else {
         NMF_LAUNCH(K_GRAM_W, launch_gram_w_jobs(1, dj, nullptr, J.nG, c.s));
     }
@@ -444,9 +444,16 @@ nmf_status nmf_plan(const nmf_desc *desc, nmf_plan_t *out, size_t *workspace_byt
 
 nmf_status nmf_destroy(nmf_plan_t plan) {
     if (plan) {
-        std::lock_guard<std::mutex> lk(plan->p.prof.mu);
-        for (hipEvent_t e : plan->p.prof.pool) (void)hipEventDestroy(e);
-        plan->p.prof.pool.clear();
+        {
+            std::lock_guard<std::mutex> lk(plan->p.prof.mu);
+            for (hipEvent_t e : plan->p.prof.pool) (void)hipEventDestroy(e);
+            plan->p.prof.pool.clear();
+        }
+        std::lock_guard<std::mutex> lk(plan->p.poll.mu);
+        for (hipEvent_t e : plan->p.poll.events) (void)hipEventDestroy(e);
+        for (int32_t *f : plan->p.poll.flags) (void)hipHostFree(f);
+        plan->p.poll.events.clear();
+        plan->p.poll.flags.clear();
     }
     delete plan;
     return NMF_OK;
@@ -483,18 +490,116 @@ nmf_status nmf_solve(nmf_plan_t plan, const float *dM, float *dV, float *dW, int
     if (reinterpret_cast<uintptr_t>(dWorkspace) & 255)
         return fail(plan, NMF_E_ARG, "workspace must be 256-byte aligned");
     return solve_on(plan, dM, dV, dW, iters, dWorkspace, static_cast<hipStream_t>(stream), hOut,
-                    true);
+                    true, true);
 }
 
 }  // extern "C"
 
 namespace nmf {
 
+namespace {
+
+// Tolerance checks of a solve.  Synchronous: every check_every counted
+// iterations the host reads the device state (the stream drains, then the
+// GPU idles until the next launches arrive).  Look-ahead: the stop flag is
+// mirrored into host-mapped memory by the kernel that sets it; at each check
+// the host records an event and waits only for the event of the previous
+// check, so one batch of iterations stays queued while it looks.  Iterations
+// issued after the stop return at once (every kernel tests the device flag),
+// so both modes compute the same result.
+struct Poller {
+    Ctx &c;
+    bool ahead = false;
+    int32_t *hflag = nullptr;    // host side of the mapped flag
+    std::vector<hipEvent_t> inflight;
+    int since = 0;
+
+    explicit Poller(Ctx &cx) : c(cx) {}
+    ~Poller() {
+        PollPool &pp = c.plan->p.poll;
+        std::lock_guard<std::mutex> lk(pp.mu);
+        for (hipEvent_t e : inflight) pp.events.push_back(e);
+        if (hflag) pp.flags.push_back(hflag);
+    }
+    // Take a mapped flag for this solve and point the jobs at it (before the
+    // job table is uploaded); stays synchronous if that fails.
+    void enable() {
+        PollPool &pp = c.plan->p.poll;
+        {
+            std::lock_guard<std::mutex> lk(pp.mu);
+            if (!pp.flags.empty()) {
+                hflag = pp.flags.back();
+                pp.flags.pop_back();
+            }
+        }
+        if (!hflag) {
+            void *h = nullptr;
+            if (hipHostMalloc(&h, 256, hipHostMallocMapped) != hipSuccess) {
+                (void)hipGetLastError();
+                return;
+            }
+            hflag = static_cast<int32_t *>(h);
+        }
+        void *dptr = nullptr;
+        if (hipHostGetDevicePointer(&dptr, hflag, 0) != hipSuccess) {
+            (void)hipGetLastError();
+            return;
+        }
+        *(volatile int32_t *)hflag = 0;
+        for (Job &J : c.jobs) J.hstop = static_cast<int32_t *>(dptr);
+        ahead = true;
+    }
+    nmf_status sync_check(bool &done) {
+        DevState hs;
+        nmf_status e = read_state(c, hs);
+        done = e == NMF_OK && hs.stop != 0;
+        return e;
+    }
+    nmf_status ahead_check(bool &done) {
+        nmf_plan_t plan = c.plan;
+        PollPool &pp = plan->p.poll;
+        hipEvent_t ev = nullptr;
+        {
+            std::lock_guard<std::mutex> lk(pp.mu);
+            if (!pp.events.empty()) {
+                ev = pp.events.back();
+                pp.events.pop_back();
+            }
+        }
+        if (!ev) NMF_HIP(hipEventCreateWithFlags(&ev, hipEventDisableTiming));
+        inflight.push_back(ev);
+        NMF_HIP(hipEventRecord(ev, c.s));
+        if (inflight.size() > 1) {
+            hipEvent_t old = inflight.front();
+            inflight.erase(inflight.begin());
+            {
+                std::lock_guard<std::mutex> lk(pp.mu);
+                pp.events.push_back(old);
+            }
+            NMF_HIP(hipEventSynchronize(old));
+        }
+        done = *(volatile int32_t *)hflag != 0;
+        return NMF_OK;
+    }
+    // Call after each iteration that counts towards the check interval.
+    nmf_status tick(bool &done) {
+        if (++since < c.p->d.check_every) return NMF_OK;
+        since = 0;
+        return now(done);
+    }
+    nmf_status now(bool &done) { return ahead ? ahead_check(done) : sync_check(done); }
+};
+
+}  // namespace
+
 nmf_status solve_on(nmf_plan_t plan, const float *dM, float *dV, float *dW, int32_t iters,
-                    void *dWorkspace, hipStream_t s, nmf_result *hOut, bool profile) {
+                    void *dWorkspace, hipStream_t s, nmf_result *hOut, bool profile,
+                    bool lookahead) {
     const Plan &p = plan->p;
     Ctx c = make_ctx(plan, dM, dV, dW, dWorkspace, s);
     c.prof = profile;
+    Poller poller(c);
+    if (lookahead && p.d.tol > 0.0) poller.enable();
     NMF_HIP(launch_state_reset(c.st, s));
     nmf_status st;
     if (p.d.check_input && (st = check_input(c)) != NMF_OK) return st;
@@ -505,15 +610,7 @@ nmf_status solve_on(nmf_plan_t plan, const float *dM, float *dV, float *dW, int3
 
     const bool use_tol = p.d.tol > 0.0;
     const bool bf16 = p.d.prec == NMF_BF16;
-    const int ce = p.d.check_every;
     bool done = false;
-    int since_check = 0;
-    auto poll = [&](bool &stop_now) -> nmf_status {
-        DevState hs;
-        nmf_status e = read_state(c, hs);
-        stop_now = e == NMF_OK && hs.stop != 0;
-        return e;
-    };
     for (const Step &stp : make_schedule(p.d.cycle, p.d.levels, iters)) {
         if (done) break;
         const int d = stp.depth;
@@ -526,10 +623,7 @@ nmf_status solve_on(nmf_plan_t plan, const float *dM, float *dV, float *dW, int3
         } else {
             for (int i = 0; i < stp.count && !done; ++i) {
                 if ((st = sweep(c, d)) != NMF_OK) return st;
-                if (use_tol && d == 0 && ++since_check >= ce) {
-                    since_check = 0;
-                    if ((st = poll(done)) != NMF_OK) return st;
-                }
+                if (use_tol && d == 0 && (st = poller.tick(done)) != NMF_OK) return st;
             }
         }
     }
@@ -537,19 +631,13 @@ nmf_status solve_on(nmf_plan_t plan, const float *dM, float *dV, float *dW, int3
     // these iterations only)
     for (int i = 0; bf16 && i < p.d.refine_iters && !done; ++i) {
         if ((st = sweep(c, 0, true)) != NMF_OK) return st;
-        if (use_tol && ++since_check >= ce) {
-            since_check = 0;
-            if ((st = poll(done)) != NMF_OK) return st;
-        }
+        if (use_tol && (st = poller.tick(done)) != NMF_OK) return st;
     }
     if (use_tol && !done) {
-        if ((st = poll(done)) != NMF_OK) return st;
+        if ((st = poller.now(done)) != NMF_OK) return st;
         for (int i = 0; i < p.d.max_fine_iters && !done; ++i) {
             if ((st = sweep(c, 0, bf16)) != NMF_OK) return st;
-            if (++since_check >= ce) {
-                since_check = 0;
-                if ((st = poll(done)) != NMF_OK) return st;
-            }
+            if ((st = poller.tick(done)) != NMF_OK) return st;
         }
     }
     return finish(c, hOut);

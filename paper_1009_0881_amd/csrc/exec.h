@@ -64,8 +64,12 @@ nmf_status prepare_bf16(Ctx &c);
 // The whole multilevel solve of nmf_solve on a workspace at dWorkspace (256-byte
 // aligned, plan->p.ws.total bytes); arguments already validated.  profile:
 // honour the plan's profile mask (HIP events); false records no event.
+// lookahead: tolerance checks through a host-mapped stop flag with one batch
+// of iterations kept queued (pinned host memory and events from the plan's
+// pools); false: synchronous checks, nothing allocated.
 nmf_status solve_on(nmf_plan_t plan, const float *dM, float *dV, float *dW, int32_t iters,
-                    void *dWorkspace, hipStream_t s, nmf_result *hOut, bool profile);
+                    void *dWorkspace, hipStream_t s, nmf_result *hOut, bool profile,
+                    bool lookahead);
 // Fill an nmf_result from the final device state and the host depth log.
 nmf_status result_from_state(nmf_plan_t plan, const DevState &hs,
                              const std::vector<int8_t> &depths, nmf_result *out);

@@ -41,6 +41,7 @@ struct Job {
     double *log_rel;
     int32_t *log_depth;
     DevState *st;
+    int32_t *hstop;      // host-mapped copy of st->stop, set with it (null: none)
     double tol;
     // BF16 precision mode (prec = 1): operand copies for the MFMA passes.
     // Mbp: A-pass copy of M, K-packed: element (i, j) at

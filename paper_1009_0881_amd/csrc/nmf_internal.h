@@ -85,6 +85,15 @@ enum KernelKind {
     K_RESTRICT, K_PROLONG, K_SUMSQ, K_NUM_KINDS
 };
 
+// Host-mapped stop flags and completion events for tolerance polling: a solve
+// takes one flag from the pool (allocated on first use) and returns it; the
+// mutex makes concurrent solves on one plan safe.
+struct PollPool {
+    std::mutex mu;
+    std::vector<int32_t *> flags;    // hipHostMalloc(hipHostMallocMapped), idle
+    std::vector<hipEvent_t> events;  // timing disabled, idle
+};
+
 // Optional HIP-event timing of selected kernel kinds.  A solve takes event
 // pairs from the pool, keeps its pending pairs in its own context and returns
 // them (with its times added to the totals) when it has synchronised; the
@@ -100,6 +109,7 @@ struct Profiler {
 struct Plan {
     nmf_desc d;
     Profiler prof;
+    PollPool poll;
     std::vector<LevelInfo> lv;
     Workspace ws;
     int rpad;            // r rounded up to a multiple of 16
@@ -231,8 +241,8 @@ hipError_t launch_make_wt(const float *W, int64_t n, int r, int rpad, float *Wt,
 // ||M||^2 - 2 sum(rparts) + <Dd, Bd>, logged at st->log_len.
 hipError_t launch_residual(const double *rparts, int nparts, const double *Dd, const double *Bd,
                            int r, const double *normM2, int depth, double *log_rel,
-                           int32_t *log_depth, int log_cap, DevState *st, double tol,
-                           hipStream_t s);
+                           int32_t *log_depth, int log_cap, DevState *st, int32_t *hstop,
+                           double tol, hipStream_t s);
 hipError_t enable_large_lds();
 hipError_t enable_stream_lds();   // streaming A-passes (called by enable_large_lds)
 

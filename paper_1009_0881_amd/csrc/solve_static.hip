@@ -60,5 +60,6 @@ extern "C" nmf_status nmf_solve_static(nmf_plan_t plan, const float *dM, float *
     void *ws = nullptr;
     nmf_status st = static_workspace(&ws);
     if (st != NMF_OK) return st;
-    return solve_on(plan, dM, dV, dW, iters, ws, static_cast<hipStream_t>(stream), hOut, false);
+    return solve_on(plan, dM, dV, dW, iters, ws, static_cast<hipStream_t>(stream), hOut, false,
+                    false);
 }

@@ -885,9 +885,11 @@ __global__ __launch_bounds__(64 * kGramWWaves) void k_gram_w(const Job *__restri
         if (!isfinite(e2)) {
             st->status = NMF_E_NONFINITE;
             st->stop = 1;
+            if (J.hstop) *J.hstop = 1;
         } else if (J.depth == 0 && J.prec == 0 && J.tol > 0.0 && rel <= J.tol) {
             st->stopped = 1;
             st->stop = 1;
+            if (J.hstop) *J.hstop = 1;
         }
     }
 }
@@ -1056,7 +1058,7 @@ __global__ __launch_bounds__(256) void k_residual(const double *__restrict__ rpa
                                                   const double *__restrict__ normM2, int depth,
                                                   double *__restrict__ log_rel,
                                                   int32_t *__restrict__ log_depth, int log_cap,
-                                                  DevState *st, double tol) {
+                                                  DevState *st, int32_t *hstop, double tol) {
     __shared__ double red[4];
     if (st->stop) return;
     const int tid = threadIdx.x;
@@ -1080,9 +1082,11 @@ __global__ __launch_bounds__(256) void k_residual(const double *__restrict__ rpa
         if (!isfinite(e2)) {
             st->status = NMF_E_NONFINITE;
             st->stop = 1;
+            if (hstop) *hstop = 1;
         } else if (depth == 0 && tol > 0.0 && rel <= tol) {
             st->stopped = 1;
             st->stop = 1;
+            if (hstop) *hstop = 1;
         }
     }
 }
@@ -1239,10 +1243,10 @@ hipError_t launch_make_wt(const float *W, int64_t n, int r, int rpad, float *Wt,
 
 hipError_t launch_residual(const double *rparts, int nparts, const double *Dd, const double *Bd,
                            int r, const double *normM2, int depth, double *log_rel,
-                           int32_t *log_depth, int log_cap, DevState *st, double tol,
-                           hipStream_t s) {
+                           int32_t *log_depth, int log_cap, DevState *st, int32_t *hstop,
+                           double tol, hipStream_t s) {
     k_residual<<<1, 256, 0, s>>>(rparts, nparts, Dd, Bd, r, normM2, depth, log_rel, log_depth,
-                                 log_cap, st, tol);
+                                 log_cap, st, hstop, tol);
     return hipGetLastError();
 }
 
