@@ -58,7 +58,7 @@ __all__ = [
     "schedule", "level_iteration_totals",
     "hals_update_V", "hals_update_W", "hals_iteration",
     "mu_update_V", "mu_update_W", "mu_iteration",
-    "nnls_gram", "anls_update_V", "anls_update_W", "anls_iteration",
+    "nnls_gram", "nnls_bpp", "anls_update_V", "anls_update_W", "anls_iteration",
     "iteration", "bf16_round", "hals_update_V_bf16", "hals_update_W_bf16",
     "mu_iteration_bf16", "iteration_bf16", "rel_err", "objective", "gram_form_residual2",
     "eckart_young_floor", "prolongation_bound", "solve", "SolveResult",
@@ -372,6 +372,53 @@ def nnls_gram(G: np.ndarray, b: np.ndarray, x_keep: Optional[np.ndarray] = None,
             if not passive.any():
                 break
     return x
+
+
+def nnls_bpp(G: np.ndarray, b: np.ndarray, x_start: Optional[np.ndarray] = None,
+             tol_scale: float = 1e-12, max_rounds: Optional[int] = None) -> np.ndarray:
+    """min_{x >= 0} 0.5 x^T G x - b^T x by block principal pivoting, the
+    exchange method that Section 2.1's footnote points to for the ANLS
+    subproblems (Judice and Pires; Kim and Park for NMF).
+
+    Keep a passive set F (free variables) and its complement (variables at
+    zero).  Each round solves G[F,F] z = b[F], sets z = 0 outside F, and
+    marks as infeasible every passive variable with z < 0 and every other one
+    whose gradient (G z - b) is below -tol.  While the number of infeasible
+    variables keeps falling, all of them change sides; once it stops falling,
+    three more rounds exchange all of them, and after that only the infeasible
+    variable with the highest index changes sides until the count falls again.
+    No infeasible variable: z is the minimiser.  F starts as the support of
+    x_start (all zero: empty).  Variables with G[k,k] == 0 keep x_start[k]
+    and take no part (R8).  The minimiser is unique for a positive definite
+    G, so the result equals nnls_gram's up to rounding.
+    """
+    r = b.shape[0]
+    live = np.array([G[k, k] > 0 for k in range(r)], dtype=bool)
+    x0 = np.zeros(r) if x_start is None else np.asarray(x_start, dtype=np.float64)
+    tol = tol_scale * max(1.0, float(np.max(np.abs(b[live]))) if live.any() else 1.0)
+    passive = live & (x0 > 0)
+    ninf, backup = r + 1, 3
+    for _ in range(max_rounds if max_rounds is not None else 8 * r + 16):
+        z = np.zeros(r)
+        idx = np.flatnonzero(passive)
+        if idx.size:
+            z[idx] = np.linalg.solve(G[np.ix_(idx, idx)], b[idx])
+        grad = G[:, idx] @ z[idx] - b
+        bad = live & np.where(passive, z < 0, grad < -tol)
+        if not bad.any():
+            out = np.where(live, z, x0)
+            return out
+        nv = int(bad.sum())
+        if nv < ninf:
+            ninf, backup = nv, 3
+            passive ^= bad
+        elif backup > 0:
+            backup -= 1
+            passive ^= bad
+        else:
+            j = int(np.flatnonzero(bad)[-1])
+            passive[j] = ~passive[j]
+    raise RuntimeError("block principal pivoting did not terminate")
 
 
 def anls_update_V(M: np.ndarray, V: np.ndarray, W: np.ndarray) -> np.ndarray:

@@ -236,7 +236,8 @@ nmf_status result_from_state(nmf_plan_t plan, const DevState &hs,
         return fail(plan, (nmf_status)hs.status, "non-finite residual during the solve");
     if (hs.flags & 4)
         return fail(plan, NMF_E_NONFINITE,
-                    "NNLS met a non-positive pivot (collinear or singular Gram)");
+                    "NNLS met a non-positive pivot (collinear or singular Gram) or its "
+                    "exchange did not end");
     return NMF_OK;
 }
 

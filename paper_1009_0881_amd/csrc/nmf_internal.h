@@ -247,9 +247,10 @@ hipError_t enable_large_lds();
 hipError_t enable_stream_lds();   // streaming A-passes (called by enable_large_lds)
 
 // ANLS: exact FP64 NNLS per row of V (G = W W^T, rhs = A rows) or per column
-// of W (G = V^T V, rhs = C columns); warm-started from the current factor.
-// A non-positive pivot sets bit 2 of *flags (the affected problem keeps its
-// last feasible iterate).
+// of W (G = V^T V, rhs = C columns) by block principal pivoting, the passive
+// set started from the current factor's support.  A non-positive pivot or an
+// exchange that does not end sets bit 2 of *flags (the affected problem keeps
+// its previous values).
 hipError_t launch_nnls_rows(int rpad, const double *Gd, const double *A, int64_t m, int r,
                             float *V, int32_t *flags, const int32_t *stop, hipStream_t s);
 hipError_t launch_nnls_cols(int rpad, const double *Gd, const double *C, int64_t n, int r,

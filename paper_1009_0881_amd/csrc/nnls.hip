@@ -3,14 +3,21 @@
 // The V half-step is m independent problems  min_{x>=0} 0.5 x^T B x - a_i^T x
 // (B = W W^T, a_i = row i of M W^T), the W half-step n problems with
 // (D = V^T V, c_j = column j of V^T M).  With a positive definite Gram the
-// minimiser is unique, so any exact method gives the same point; here each
-// problem is solved by the Lawson-Hanson active-set method on the Gram form:
-// passive-set systems G[P,P] z = b[P] by Cholesky, entering variable = largest
-// positive negative-gradient (lowest index on ties), step back to the
-// boundary when a passive variable would turn nonpositive.
+// minimiser is unique, so any exact method gives the same point.  Each
+// problem is solved by block principal pivoting (the exchange method the
+// paper's Section 2.1 footnote points to for ANLS): with the passive set F,
+// solve G[F,F] z = b[F] (Cholesky), take the gradient g = G z - b on the
+// variables outside F, and call infeasible every passive variable with z < 0
+// and every active one with g < -tol; all infeasible variables change sides
+// at once while their number keeps falling, for three more rounds after it
+// stops falling, and then only the highest-indexed one (the backup rule that
+// makes the exchange finite).  No infeasible variable: z is the solution.
+// Unlike an active-set method that adds one variable per solve, a whole
+// support change costs one solve per round, which keeps the first sweeps
+// (random start, all variables passive) short.
 //
 // One 64-wide wave per problem, lane k owning variable k (r <= 64).  The
-// search is warm-started from the support of the current factor row (the
+// passive set starts from the support of the current factor row (the
 // previous ANLS solution), which changes the path but not the result.
 // Variables with G_kk = 0 (a zero factor column) take no part and keep their
 // value.  Cholesky: lane at passive position p owns row p of the factor in
@@ -101,73 +108,52 @@ __device__ bool solve_passive(const double *__restrict__ Gs, double *__restrict_
     return true;
 }
 
-// Lawson-Hanson for one problem; x is the warm start on entry and the
-// solution on exit (lane k holds variable k).  Returns false on a
-// non-positive pivot (x is then left at the last feasible iterate).
+// Block principal pivoting for one problem; x is the warm start on entry and
+// the solution on exit (lane k holds variable k).  Returns false on a
+// non-positive pivot, or if the exchange has not ended after 8 RPAD + 16
+// rounds (x is then left unchanged).
 template <int RPAD>
 __device__ bool wave_nnls(const double *__restrict__ Gs, double *__restrict__ S, double b,
                           double &x, int r, int lane) {
     constexpr int GS = RPAD + 1;
     const bool valid = lane < r;
     const bool live = valid && Gs[lane * GS + lane] > 0.0;
-    if (live && !(x > 0.0 && x < INFINITY)) x = 0.0;
     const double tol = 1e-12 * fmax(1.0, wave_max_f64(live ? fabs(b) : 0.0));
-    uint64_t P = __ballot(live && x > 0.0);
-    uint64_t blocked = 0;
-    bool need_inner = P != 0ull;
-    bool first = false;
-    int jent = 0;
-    for (int outer = 0; outer < 4 * RPAD + 16; ++outer) {
-        if (need_inner) {
-            for (int inner = 0; inner < RPAD + 2; ++inner) {
-                double z = 0.0;
-                if (!solve_passive<RPAD>(Gs, S, P, b, z, lane)) return false;
-                const bool inP = (P >> lane) & 1ull;
-                const uint64_t nonpos = __ballot(inP && !(z > 0.0));
-                if (nonpos == 0ull) {
-                    if (inP) x = z;
-                    else if (live) x = 0.0;
-                    blocked = 0;
-                    break;
-                }
-                if (first && ((nonpos >> jent) & 1ull)) {   // entering variable rejected
-                    P &= ~(1ull << jent);
-                    blocked |= 1ull << jent;
-                    break;
-                }
-                first = false;
-                const double ratio = (inP && !(z > 0.0)) ? x / (x - z) : INFINITY;
-                const double amin = wave_min_f64(ratio);
-                const int qidx = __ffsll((unsigned long long)__ballot(ratio == amin)) - 1;
-                if (inP) x = x + amin * (z - x);
-                const uint64_t leave = __ballot(inP && !(x > 0.0)) | (1ull << qidx);
-                if ((leave >> lane) & 1ull) x = 0.0;
-                P &= ~leave;
-                blocked = 0;
-                if (P == 0ull) break;
-            }
-            need_inner = false;
-            first = false;
-        }
-        double gx = 0.0;
-        uint64_t rem = P;
+    uint64_t F = __ballot(live && x > 0.0 && x < INFINITY);
+    int ninf = RPAD + 1, backup = 3;
+    for (int round = 0; round < 8 * RPAD + 16; ++round) {
+        double z = 0.0;
+        if (F != 0ull && !solve_passive<RPAD>(Gs, S, F, b, z, lane)) return false;
+        const bool inF = (F >> lane) & 1ull;
+        // gradient (G z - b)_k of the variables outside F (z is 0 there)
+        double gz = 0.0;
+        uint64_t rem = F;
         while (rem) {
             const int l = __ffsll((unsigned long long)rem) - 1;
             rem &= rem - 1ull;
-            const double xl = __shfl(x, l, kWave);
-            if (valid) gx += Gs[lane * GS + l] * xl;
+            const double zl = __shfl(z, l, kWave);
+            if (valid) gz += Gs[lane * GS + l] * zl;
         }
-        const double gneg = b - gx;
-        const bool cand = live && !((P >> lane) & 1ull) && !((blocked >> lane) & 1ull) && gneg > tol;
-        const uint64_t cm = __ballot(cand);
-        if (cm == 0ull) break;
-        const double gmax = wave_max_f64(cand ? gneg : -INFINITY);
-        jent = __ffsll((unsigned long long)__ballot(cand && gneg == gmax)) - 1;
-        P |= 1ull << jent;
-        first = true;
-        need_inner = true;
+        const bool bad = live && (inF ? !(z >= 0.0) : (gz - b) < -tol);
+        const uint64_t V = __ballot(bad);
+        if (V == 0ull) {
+            if (inF) x = z;
+            else if (live) x = 0.0;
+            return true;
+        }
+        const int nv = __popcll(V);
+        if (nv < ninf) {
+            ninf = nv;
+            backup = 3;
+            F ^= V;
+        } else if (backup > 0) {
+            --backup;
+            F ^= V;
+        } else {
+            F ^= 1ull << (63 - __clzll((unsigned long long)V));
+        }
     }
-    return true;
+    return false;
 }
 
 // COLS = false: problems are rows i of V (x = V[i + k m], rhs = A[i + k m]).

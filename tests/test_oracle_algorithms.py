@@ -140,6 +140,71 @@ def test_nnls_equals_scipy_nnls(r):
         np.testing.assert_allclose(got, ref, atol=1e-8 * max(1, np.abs(ref).max()))
 
 
+@pytest.mark.parametrize("r", [1, 2, 3, 4])
+@pytest.mark.parametrize("seed", range(10))
+def test_bpp_equals_exhaustive_enumeration(r, seed):
+    # block principal pivoting (Section 2.1 footnote) reaches the unique
+    # minimiser from an empty, a full and a random starting support
+    rng = np.random.default_rng(500 + 100 * r + seed)
+    X = rng.normal(size=(r + 3, r))
+    y = rng.normal(size=r + 3)
+    G, b = X.T @ X, X.T @ y
+    want = enumerate_nnls(G, b)
+    for start in (None, np.ones(r), rng.uniform(size=r) * (rng.uniform(size=r) > 0.5)):
+        np.testing.assert_allclose(O.nnls_bpp(G, b, start), want, atol=1e-9)
+
+
+@pytest.mark.parametrize("r", [5, 10, 20, 40, 64])
+def test_bpp_equals_active_set_and_scipy(r):
+    rng = np.random.default_rng(70 + r)
+    for _ in range(5):
+        X = np.abs(rng.normal(size=(3 * r, r)))
+        y = rng.normal(size=3 * r) + 0.3
+        ref, _ = so.nnls(X, y)
+        G, b = X.T @ X, X.T @ y
+        for start in (None, np.ones(r)):
+            got = O.nnls_bpp(G, b, start)
+            np.testing.assert_allclose(got, ref, atol=1e-8 * max(1, np.abs(ref).max()))
+            np.testing.assert_allclose(got, O.nnls_gram(G, b), atol=1e-9 * max(1, np.abs(ref).max()))
+
+
+def test_bpp_backup_rule_ends_a_cycling_exchange():
+    # From the empty passive set, exchanging every infeasible variable at each
+    # round cycles on this positive definite instance ({} -> {0,2} -> {1,2} ->
+    # {} ...; found by a random search); the backup rule (single exchanges
+    # once the count stops falling) ends it at the minimiser (0, 0, 0.2418).
+    G = np.array([[2.8233, -1.9276, 4.3994], [-1.9276, 2.6995, -4.3377],
+                  [4.3994, -4.3377, 8.3432]])
+    b = np.array([0.2136, -1.6076, 2.0171])
+
+    def full_exchange_round(passive):
+        idx = np.flatnonzero(passive)
+        z = np.zeros(3)
+        z[idx] = np.linalg.solve(G[np.ix_(idx, idx)], b[idx]) if idx.size else 0.0
+        bad = np.where(passive, z < 0, G[:, idx] @ z[idx] - b < -1e-12)
+        return passive ^ bad
+
+    p = np.zeros(3, dtype=bool)
+    seen = [tuple(p)]
+    for _ in range(3):
+        p = full_exchange_round(p)
+        seen.append(tuple(p))
+    assert seen[3] == seen[0] and len(set(seen[:3])) == 3      # a 3-cycle
+    want = enumerate_nnls(G, b)
+    np.testing.assert_allclose(want, [0.0, 0.0, 2.0171 / 8.3432], atol=1e-12)
+    np.testing.assert_allclose(O.nnls_bpp(G, b), want, atol=1e-12)
+
+
+def test_bpp_zero_diagonal_variable_keeps_value():
+    X = np.random.default_rng(0).uniform(size=(6, 3))
+    X[:, 1] = 0.0
+    y = np.random.default_rng(1).uniform(size=6)
+    x = O.nnls_bpp(X.T @ X, X.T @ y, np.array([9.0, 7.0, 9.0]))
+    assert x[1] == 7.0
+    ref, _ = so.nnls(X[:, [0, 2]], y)
+    np.testing.assert_allclose(x[[0, 2]], ref, atol=1e-10)
+
+
 def test_anls_half_steps_are_exact_minimisers():
     M, V, W = rand_problem(20, 15, 5, 11)
     Vn = O.anls_update_V(M, V, W)
