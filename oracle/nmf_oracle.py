@@ -54,7 +54,8 @@ CYCLE_NAMES = {NI: "ni", VC: "vc", FMG: "fmg"}
 __all__ = [
     "HALS", "MU", "ANLS", "NI", "VC", "FMG", "XFER_FW", "XFER_BLOCK2",
     "level_sides", "transfer_1d", "restrict_matrix", "prolong_matrix",
-    "restrict_images", "prolong_images", "smoothness",
+    "restrict_images", "prolong_images", "smoothness", "level_ns", "restrict_cols",
+    "prolong_cols", "prolongation_bound_two_sided",
     "schedule", "level_iteration_totals",
     "hals_update_V", "hals_update_W", "hals_iteration",
     "mu_update_V", "mu_update_W", "mu_iteration",
@@ -168,6 +169,32 @@ def prolong_images(Y: np.ndarray, h: int, w: int, xfer: int) -> np.ndarray:
     return out.reshape(ncol, -1).T.copy()
 
 
+def level_ns(n: int, levels: int) -> List[int]:
+    """Column counts per level of a two-sided hierarchy, finest first:
+    n_{l+1} = ceil(n_l / 2) (reading R1 applied to the column index)."""
+    ns = [n]
+    for _ in range(levels - 1):
+        if ns[-1] < 2:
+            raise ValueError("cannot restrict fewer than 2 columns")
+        ns.append((ns[-1] + 1) // 2)
+    return ns
+
+
+def restrict_cols(X: np.ndarray, xfer: int) -> np.ndarray:
+    """X R_n^T: the 1-D operator of eq. restr applied along the column index
+    (Section 6.1's generalisation to n, for columns ordered along a smooth
+    axis: wavelength, time).  X is k x n; the result k x ceil(n/2)."""
+    R, _ = transfer_1d(X.shape[1], xfer)
+    return np.asarray(X, dtype=np.float64) @ R.T
+
+
+def prolong_cols(Y: np.ndarray, n: int, xfer: int) -> np.ndarray:
+    """Y P_n^T: the 1-D prolongation of eq. prol along the column index, back
+    to n columns."""
+    _, P = transfer_1d(n, xfer)
+    return np.asarray(Y, dtype=np.float64) @ P.T
+
+
 def smoothness(M: np.ndarray, h: int, w: int, xfer: int) -> float:
     """s_M = ||M - P(R(M))||_F / ||M||_F (Section 4.1)."""
     M = np.asarray(M, dtype=np.float64)
@@ -179,7 +206,7 @@ def smoothness(M: np.ndarray, h: int, w: int, xfer: int) -> float:
 # Multigrid cycles (Alg. 4 NI, Alg. 5 VC, Alg. 6 FMG; Table 1 budget)
 # ---------------------------------------------------------------------------
 
-def schedule(cycle: int, levels: int, T) -> List[Tuple[str, int, int]]:
+def schedule(cycle: int, levels: int, T, ratio: int = 4) -> List[Tuple[str, int, int]]:
     """Flat list of steps ("restrict", d, 0), ("prolong", d, 0) or
     ("run", d, count) for a budget of T fine-iteration equivalents.
 
@@ -188,14 +215,16 @@ def schedule(cycle: int, levels: int, T) -> List[Tuple[str, int, int]]:
     run d count  : ``count`` iterations of the NMF algorithm at depth d
 
     Depth 0 is the finest level.  Budgets are exact rationals; Run(d, t)
-    performs floor(t * 4^d) iterations (reading R5), and zero-iteration runs
-    are dropped.
+    performs floor(t * ratio^d) iterations (reading R5): ratio = 4 is the
+    paper's m' ~ m/4 cost model; a two-sided hierarchy also halves n, so a
+    coarse iteration costs about 1/8 (ratio = 8).  Zero-iteration runs are
+    dropped.
     """
     steps: List[Tuple[str, int, int]] = []
     T = Fraction(T)
 
     def run(d: int, t: Fraction) -> None:
-        count = math.floor(t * 4 ** d)
+        count = math.floor(t * ratio ** d)
         if count > 0:
             steps.append(("run", d, int(count)))
 
@@ -569,6 +598,24 @@ def prolongation_bound(M, h, w, xfer, Vc, W) -> Tuple[float, float]:
     return lhs, rhs
 
 
+def prolongation_bound_two_sided(M, h, w, xfer, Vc, Wc) -> Tuple[float, float]:
+    """Section 4.1's step-4 bound with both sides coarsened: writing
+    M' = R_m M R_n^T, M - P_m V' W' P_n^T = (M - P_m M' P_n^T)
+    + P_m (M' - V' W') P_n^T, so
+    ||M - P_m V' W' P_n^T|| <= ||M - P_m M' P_n^T|| + ||P_m||_F ||M' - V'W'|| ||P_n||_F.
+    Returns (lhs, rhs)."""
+    M = np.asarray(M, dtype=np.float64)
+    n = M.shape[1]
+    _, Pn = transfer_1d(n, xfer)
+    Pm = prolong_matrix(h, w, xfer)
+    Mc = restrict_cols(restrict_images(M, h, w, xfer), xfer)
+    back = prolong_cols(prolong_images(Mc, h, w, xfer), n, xfer)
+    lhs = float(np.linalg.norm(M - prolong_cols(prolong_images(Vc, h, w, xfer) @ Wc, n, xfer)))
+    rhs = (float(np.linalg.norm(M - back))
+           + float(np.linalg.norm(Pm)) * float(np.linalg.norm(Mc - Vc @ Wc)) * float(np.linalg.norm(Pn)))
+    return lhs, rhs
+
+
 # ---------------------------------------------------------------------------
 # Whole multilevel solve
 # ---------------------------------------------------------------------------
@@ -592,7 +639,7 @@ class SolveResult:
 def solve(M, h: int, w: int, r: int, levels: int, algo: int, cycle: int, xfer: int,
           T, V0, W0, tol: float = 0.0, max_fine_iters: int = 0,
           check_bound: bool = False, callback=None, bf16_products: bool = False,
-          refine_iters: int = 0) -> SolveResult:
+          refine_iters: int = 0, two_sided: bool = False) -> SolveResult:
     """Multilevel NMF (Section 4.1 steps 1-5 applied recursively by Alg. 4/5/6).
 
     The restrictions of M are computed once per level and kept (Alg. 6 note).
@@ -603,13 +650,20 @@ def solve(M, h: int, w: int, r: int, levels: int, algo: int, cycle: int, xfer: i
     bf16_products: the scheduled iterations use iteration_bf16 (the library's
     BF16 mode), then `refine_iters` full-precision finest-level iterations
     follow; the tolerance applies to those only, as in that mode.
+
+    two_sided: the hierarchy also coarsens the column index (Section 6.1's
+    generalisation for columns ordered along a smooth axis): M_{l+1} =
+    R_m M_l R_n^T, W moves between levels as V does but along its rows
+    (W' = W R_n^T, W = W' P_n^T), and the budget uses ratio 8 (schedule).
     """
     M = np.asarray(M, dtype=np.float64)
     sides = level_sides(h, w, levels)
+    ns = level_ns(M.shape[1], levels) if two_sided else [M.shape[1]] * levels
     Ms = [M]
     for d in range(levels - 1):
         hd, wd = sides[d]
-        Ms.append(restrict_images(Ms[-1], hd, wd, xfer))
+        Mc = restrict_images(Ms[-1], hd, wd, xfer)
+        Ms.append(restrict_cols(Mc, xfer) if two_sided else Mc)
     V = np.asarray(V0, dtype=np.float64).copy()
     W = np.asarray(W0, dtype=np.float64).copy()
     res = SolveResult()
@@ -630,18 +684,24 @@ def solve(M, h: int, w: int, r: int, levels: int, algo: int, cycle: int, xfer: i
             callback(d, V, W, e)
         return e
 
-    for kind, d, count in schedule(cycle, levels, T):
+    for kind, d, count in schedule(cycle, levels, T, 8 if two_sided else 4):
         if kind == "restrict":
             assert depth == d
             hd, wd = sides[d]
             V = restrict_images(V, hd, wd, xfer)
+            if two_sided:
+                W = restrict_cols(W, xfer)
             depth = d + 1
         elif kind == "prolong":
             assert depth == d + 1
             hd, wd = sides[d]
             if check_bound:
-                res.bound_checks.append(prolongation_bound(Ms[d], hd, wd, xfer, V, W))
+                res.bound_checks.append(
+                    prolongation_bound_two_sided(Ms[d], hd, wd, xfer, V, W) if two_sided
+                    else prolongation_bound(Ms[d], hd, wd, xfer, V, W))
             V = prolong_images(V, hd, wd, xfer)
+            if two_sided:
+                W = prolong_cols(W, ns[d], xfer)
             depth = d
         else:
             assert depth == d
