@@ -90,6 +90,16 @@ typedef struct {
                               wc).  Chosen by paper_1009_0881_amd.tune for a workload. */
     double tol;            /* > 0: stop after the first finest-level iteration with
                               rel_err <= tol (absolute threshold on rel_err)        */
+    int32_t two_sided;     /* 1: the hierarchy also halves the column count (Section
+                              6.1, for columns ordered along a smooth axis such as
+                              wavelength or time): M_{l+1} = R_m M_l R_n^T with the
+                              1-D operator of `xfer` along the columns, W moves
+                              between levels along its rows (W' = W R_n^T,
+                              W = W' P_n^T), and a depth-d run converts its budget at
+                              8^d iterations per finest-iteration equivalent.  FP32
+                              single solves only (not with NMF_BF16, not batched or
+                              served); every restricted column count must be >= 2. */
+    int32_t reserved;      /* 0                                                     */
 } nmf_desc;
 
 typedef struct {
@@ -98,7 +108,8 @@ typedef struct {
     int32_t fine_iters;      /* iterations executed on the finest level             */
     int32_t stopped;         /* 1 if tol was reached                                */
     double rel_err;          /* rel_err of the last iteration executed              */
-    double fine_equiv;       /* work in finest-iteration equivalents: sum 4^-depth  */
+    double fine_equiv;       /* work in finest-iteration equivalents: sum 4^-depth
+                                (8^-depth for two-sided hierarchies)                 */
     double queue_ms;         /* server: submit -> admission (0 elsewhere)           */
     double latency_ms;       /* server: submit -> factors in host memory            */
 } nmf_result;

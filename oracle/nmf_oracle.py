@@ -677,7 +677,7 @@ def solve(M, h: int, w: int, r: int, levels: int, algo: int, cycle: int, xfer: i
         e = rel_err(Ms[d], V, W)
         res.log.append((d, e))
         res.total_iters += 1
-        res.fine_equiv += 4.0 ** (-d)
+        res.fine_equiv += (8.0 if two_sided else 4.0) ** (-d)
         if d == 0:
             res.fine_iters += 1
         if callback is not None:

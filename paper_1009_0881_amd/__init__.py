@@ -69,6 +69,7 @@ class Desc(ctypes.Structure):
         ("max_fine_iters", ctypes.c_int32), ("check_every", ctypes.c_int32),
         ("log_cap", ctypes.c_int32), ("check_input", ctypes.c_int32),
         ("tile_cfg", ctypes.c_int32), ("tol", ctypes.c_double),
+        ("two_sided", ctypes.c_int32), ("reserved", ctypes.c_int32),
     ]
 
 
@@ -169,7 +170,7 @@ def tile(wc: int, cf: int) -> int:
 
 def make_desc(m, n, h, w, r, levels=1, algo="hals", cycle="ni", xfer="fw", prec="fp32",
               tol=0.0, max_fine_iters=0, check_every=8, log_cap=4096, check_input=False,
-              refine_iters=0, ldm=0, tile_cfg=0) -> Desc:
+              refine_iters=0, ldm=0, tile_cfg=0, two_sided=False) -> Desc:
     """nmf_desc from Python values (names as in include/nmf.h); tile_cfg is 0,
     an NMF_TILE value or a (wc, cf) pair."""
     d = Desc()
@@ -181,6 +182,7 @@ def make_desc(m, n, h, w, r, levels=1, algo="hals", cycle="ni", xfer="fw", prec=
     d.tol, d.max_fine_iters, d.check_every = tol, max_fine_iters, check_every
     d.log_cap, d.check_input, d.refine_iters = log_cap, int(check_input), refine_iters
     d.tile_cfg = tile(*tile_cfg) if isinstance(tile_cfg, (tuple, list)) else int(tile_cfg)
+    d.two_sided = int(bool(two_sided))
     return d
 
 
@@ -190,9 +192,10 @@ class Plan:
     def __init__(self, m: int, n: int, h: int, w: int, r: int, levels: int = 1,
                  algo="hals", cycle="ni", xfer="fw", prec="fp32", tol: float = 0.0,
                  max_fine_iters: int = 0, check_every: int = 8, log_cap: int = 4096,
-                 check_input: bool = False, refine_iters: int = 0, ldm: int = 0, tile_cfg=0):
+                 check_input: bool = False, refine_iters: int = 0, ldm: int = 0, tile_cfg=0,
+                 two_sided: bool = False):
         d = make_desc(m, n, h, w, r, levels, algo, cycle, xfer, prec, tol, max_fine_iters,
-                      check_every, log_cap, check_input, refine_iters, ldm, tile_cfg)
+                      check_every, log_cap, check_input, refine_iters, ldm, tile_cfg, two_sided)
         self.desc = d
         self.handle = ctypes.c_void_p()
         wsb = ctypes.c_size_t()

@@ -87,7 +87,7 @@ void set_fp32_stream(Job &J, const LevelInfo &li, const Plan &p) {
     J.tm = li.ftm;   // A-pass rows per block (RS = 2 or 1)
     J.nA = (int32_t)((li.m + J.tm - 1) / J.tm);
     J.aks = li.aks;
-    J.nCx = (int32_t)((p.d.n + 127) / 128);
+    J.nCx = (int32_t)((li.n + 127) / 128);
     J.chunks = li.fcp_chunks;
     J.chunk = li.fcp_chunk;
     J.nC = J.nCx * J.chunks;
@@ -125,10 +125,13 @@ Ctx make_ctx(nmf_plan_t plan, const float *dM, float *dV, float *dW, void *dws, 
             c.M.push_back(dM);
             c.ldm.push_back(p.d.ldm);
             c.V.push_back(dV);
+            c.Wl.push_back(dW);
         } else {
             c.M.push_back(at<float>(c.ws, p.lv[l].off_M));
             c.ldm.push_back(p.lv[l].m);
             c.V.push_back(at<float>(c.ws, p.lv[l].off_V));
+            // W moves between levels only in two-sided hierarchies
+            c.Wl.push_back(p.d.two_sided ? at<float>(c.ws, p.lv[l].off_W) : dW);
         }
     }
     c.W = dW;
@@ -139,24 +142,24 @@ Ctx make_ctx(nmf_plan_t plan, const float *dM, float *dV, float *dW, void *dws, 
         J.M = c.M[l];
         J.ldm = c.ldm[l];
         J.m = li.m;
-        J.n = p.d.n;
+        J.n = li.n;
         J.r = p.d.r;
         J.rpad = p.rpad;
         J.tm = apass_rows_per_block(li.m);
         J.chunks = li.cp_chunks;
         J.chunk = li.cp_chunk;
         J.nA = (int32_t)((li.m + J.tm - 1) / J.tm);
-        J.nCx = (int32_t)((p.d.n + 63) / 64);
+        J.nCx = (int32_t)((li.n + 63) / 64);
         J.nC = J.nCx * li.cp_chunks;
-        J.nF = cpass_final_blocks(p.d.n);
+        J.nF = cpass_final_blocks(li.n);
         J.wc = p.wc;
         J.cf = p.cf;
-        J.nFb = cfinal_tile_blocks(p.d.n, p.cf);
+        J.nFb = cfinal_tile_blocks(li.n, p.cf);
         J.nG = gram_tiles(p.rpad);
         J.depth = (int32_t)l;
         J.log_cap = p.d.log_cap;
         J.V = c.V[l];
-        J.W = dW;
+        J.W = c.Wl[l];
         J.Wt = c.Wt;
         J.A = nullptr;
         J.C = nullptr;
@@ -182,7 +185,7 @@ Ctx make_ctx(nmf_plan_t plan, const float *dM, float *dV, float *dW, void *dws, 
                 J.stream = 1;
                 J.tm = kStreamARows;
                 J.nA = (int32_t)((li.m + kStreamARows - 1) / kStreamARows);
-                J.nCx = (int32_t)((p.d.n + 255) / 256);
+                J.nCx = (int32_t)((li.n + 255) / 256);
                 J.chunks = li.scp_chunks;
                 J.chunk = li.scp_chunk;
                 J.nC = J.nCx * J.chunks;
@@ -225,10 +228,11 @@ nmf_status result_from_state(nmf_plan_t plan, const DevState &hs,
         out->total_iters = n;
         out->stopped = hs.stopped;
         out->rel_err = hs.last_rel;
+        const double per_depth = plan->p.d.two_sided ? 0.125 : 0.25;
         for (int i = 0; i < n && i < (int)depths.size(); ++i) {
             if (depths[i] == 0) out->fine_iters++;
             double f = 1.0;
-            for (int k = 0; k < depths[i]; ++k) f *= 0.25;
+            for (int k = 0; k < depths[i]; ++k) f *= per_depth;
             out->fine_equiv += f;
         }
     }
@@ -277,25 +281,43 @@ nmf_status upload_jobs(Ctx &c) {
     return NMF_OK;
 }
 
-// B = W W^T with the standalone Gram kernels (start of a solve, ANLS).
-nmf_status gram_W(Ctx &c) {
+// B = W W^T of level d's W with the standalone Gram kernels (ANLS).
+nmf_status gram_W(Ctx &c, int d) {
     nmf_plan_t plan = c.plan;
     const Plan &p = *c.p;
-    NMF_LAUNCH(K_GRAM_W, launch_gram(p.rpad, p.d.r, p.d.n, c.W, p.d.n, p.gram_w_parts,
-                                     p.gram_w_chunk, c.gparts, c.Bd, c.Bf, c.stop, c.s));
+    const LevelInfo &li = p.lv[d];
+    NMF_LAUNCH(K_GRAM_W, launch_gram(p.rpad, p.d.r, li.n, c.Wl[d], li.n, li.gram_w_parts,
+                                     li.gram_w_chunk, c.gparts, c.Bd, c.Bf, c.stop, c.s));
     return NMF_OK;
 }
 
 // Start of a solve: Wt (transposed, zero-padded W) from the W tile kernel and
 // B = W W^T from the B tile kernel.  The batch executor runs the same two
 // kernels, so single and batched solves agree bitwise.
-nmf_status init_w(Ctx &c) {
+// Also after a W transfer of a two-sided hierarchy, for the level it reached.
+nmf_status init_w(Ctx &c, int d = 0) {
     nmf_plan_t plan = c.plan;
-    const Job &J = c.jobs[0];
-    NMF_LAUNCH(K_GRAM_W, launch_cfinal_jobs(3, J.rpad, J.cf, c.djobs, nullptr, J.nFb,
+    const Job &J = c.jobs[d];
+    NMF_LAUNCH(K_GRAM_W, launch_cfinal_jobs(3, J.rpad, J.cf, c.djobs + d, nullptr, J.nFb,
                                             cfinal_lds_bytes(J.rpad, 3, J.cf), c.s));
-    NMF_LAUNCH(K_GRAM_W, launch_gram_w_jobs(0, c.djobs, nullptr, J.nG, c.s));
+    NMF_LAUNCH(K_GRAM_W, launch_gram_w_jobs(0, c.djobs + d, nullptr, J.nG, c.s));
     return NMF_OK;
+}
+
+// Two-sided hierarchies: W (r x n_d, row-major) restricted along its rows to
+// level d+1 (restrict_op) or prolonged from level d+1 to level d, then the
+// reached level's Wt and W W^T.
+nmf_status transfer_w(Ctx &c, int d, bool restrict_op) {
+    nmf_plan_t plan = c.plan;
+    const Plan &p = *c.p;
+    const int64_t nf = p.lv[d].n, nc = p.lv[d + 1].n;
+    if (restrict_op)
+        NMF_LAUNCH(K_RESTRICT, launch_xfer_cols(1, p.d.xfer, p.d.r, nf, c.Wl[d], nf, 1,
+                                                c.Wl[d + 1], nc, 1, c.stop, c.s));
+    else
+        NMF_LAUNCH(K_PROLONG, launch_xfer_cols(0, p.d.xfer, p.d.r, nf, c.Wl[d + 1], nc, 1,
+                                               c.Wl[d], nf, 1, c.stop, c.s));
+    return init_w(c, restrict_op ? d + 1 : d);
 }
 
 // One iteration of the inner algorithm at depth d, then the residual.
@@ -308,7 +330,7 @@ nmf_status sweep(Ctx &c, int d, bool fp32 = false) {
     const Job *dj = c.djobs + ji;
     const bool bf = J.prec == 1;
     const int r = p.d.r;
-    const int64_t n = p.d.n;
+    const int64_t n = J.n;
     int32_t *flags = &c.st->flags;
     const int mode = p.d.algo == NMF_HALS ? 0 : (p.d.algo == NMF_MU ? 1 : 2);
     if (J.stream && bf)
@@ -337,9 +359,9 @@ nmf_status sweep(Ctx &c, int d, bool fp32 = false) {
     NMF_LAUNCH(K_CFINAL, launch_cfinal_jobs(mode, J.rpad, J.cf, dj, nullptr, J.nFb,
                                             cfinal_lds_bytes(J.rpad, mode, J.cf), c.s));
     if (mode == 2) {
-        NMF_LAUNCH(K_NNLS_COLS, launch_nnls_cols(p.rpad, c.Dd, c.C, n, r, c.W, c.Wt, c.rparts,
+        NMF_LAUNCH(K_NNLS_COLS, launch_nnls_cols(p.rpad, c.Dd, c.C, n, r, J.W, c.Wt, c.rparts,
                                                  flags, c.stop, c.s));
-        nmf_status st = gram_W(c);
+        nmf_status st = gram_W(c, d);
         if (st != NMF_OK) return st;
         NMF_LAUNCH(K_RESID, launch_residual(c.rparts, nnls_cols_blocks(n), c.Dd, c.Bd, r, c.norm,
                                             d, c.log_rel, c.log_depth, p.d.log_cap, c.st,
@@ -357,14 +379,24 @@ nmf_status prepare_levels(Ctx &c) {
     nmf_plan_t plan = c.plan;
     const Plan &p = *c.p;
     for (size_t l = 1; l < p.lv.size(); ++l) {
-        NMF_LAUNCH(K_RESTRICT, launch_restrict(p.d.xfer, p.lv[l - 1].h, p.lv[l - 1].w, p.d.n,
-                                               c.M[l - 1], c.ldm[l - 1],
-                                               const_cast<float *>(c.M[l]), nullptr, c.s));
+        const LevelInfo &lf = p.lv[l - 1], &lc = p.lv[l];
+        float *Ml = const_cast<float *>(c.M[l]);
+        if (!p.d.two_sided) {
+            NMF_LAUNCH(K_RESTRICT, launch_restrict(p.d.xfer, lf.h, lf.w, lf.n, c.M[l - 1],
+                                                   c.ldm[l - 1], Ml, nullptr, c.s));
+        } else {
+            // R_m M_{l-1} (m_l x n_{l-1}), then along the columns to n_l
+            float *tmp = at<float>(c.ws, p.ws.off_tmpM);
+            NMF_LAUNCH(K_RESTRICT, launch_restrict(p.d.xfer, lf.h, lf.w, lf.n, c.M[l - 1],
+                                                   c.ldm[l - 1], tmp, nullptr, c.s));
+            NMF_LAUNCH(K_RESTRICT, launch_xfer_cols(1, p.d.xfer, lc.m, lf.n, tmp, 1, lc.m, Ml,
+                                                    1, lc.m, nullptr, c.s));
+        }
     }
     for (size_t l = 0; l < p.lv.size(); ++l) {
-        NMF_LAUNCH(K_SUMSQ, launch_sumsq(c.M[l], c.ldm[l], p.lv[l].m, p.d.n,
-                                         c.nparts + l * kNormParts, norm_parts(p.lv[l].m, p.d.n),
-                                         c.norm + l, c.s));
+        NMF_LAUNCH(K_SUMSQ, launch_sumsq(c.M[l], c.ldm[l], p.lv[l].m, p.lv[l].n,
+                                         c.nparts + l * kNormParts,
+                                         norm_parts(p.lv[l].m, p.lv[l].n), c.norm + l, c.s));
     }
     return NMF_OK;
 }
@@ -473,7 +505,7 @@ nmf_status nmf_query_levels(nmf_plan_t plan, int32_t *hw, int32_t cap_levels) {
 nmf_status nmf_query_schedule(nmf_plan_t plan, int32_t iters, int32_t *steps, int32_t cap,
                               int32_t *nsteps) {
     if (!plan || !nsteps || iters < 0) return fail(plan, NMF_E_ARG, "bad argument");
-    auto s = make_schedule(plan->p.d.cycle, plan->p.d.levels, iters);
+    auto s = make_schedule(plan->p.d.cycle, plan->p.d.levels, iters, plan->p.d.two_sided ? 8 : 4);
     *nsteps = (int32_t)s.size();
     for (size_t i = 0; i < s.size() && (int32_t)i < cap && steps; ++i) {
         steps[3 * i] = s[i].kind;
@@ -612,15 +644,17 @@ nmf_status solve_on(nmf_plan_t plan, const float *dM, float *dV, float *dW, int3
     const bool use_tol = p.d.tol > 0.0;
     const bool bf16 = p.d.prec == NMF_BF16;
     bool done = false;
-    for (const Step &stp : make_schedule(p.d.cycle, p.d.levels, iters)) {
+    for (const Step &stp : make_schedule(p.d.cycle, p.d.levels, iters, p.d.two_sided ? 8 : 4)) {
         if (done) break;
         const int d = stp.depth;
         if (stp.kind == 1) {
             NMF_LAUNCH(K_RESTRICT, launch_restrict(p.d.xfer, p.lv[d].h, p.lv[d].w, p.d.r, c.V[d],
                                                    p.lv[d].m, c.V[d + 1], c.stop, s));
+            if (p.d.two_sided && (st = transfer_w(c, d, true)) != NMF_OK) return st;
         } else if (stp.kind == 2) {
             NMF_LAUNCH(K_PROLONG, launch_prolong(p.d.xfer, p.lv[d].h, p.lv[d].w, p.d.r, c.V[d + 1],
                                                  c.V[d], c.stop, s));
+            if (p.d.two_sided && (st = transfer_w(c, d, false)) != NMF_OK) return st;
         } else {
             for (int i = 0; i < stp.count && !done; ++i) {
                 if ((st = sweep(c, d)) != NMF_OK) return st;

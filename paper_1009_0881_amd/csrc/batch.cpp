@@ -120,6 +120,8 @@ nmf_status Executor::add(nmf_plan_t plan, const float *dM, float *dV, float *dW,
     const Plan &p = plan->p;
     if (p.d.algo == NMF_ANLS)
         return fail(plan, NMF_E_ARG, "batched solves support HALS and MU (ANLS: use nmf_solve)");
+    if (p.d.two_sided)
+        return fail(plan, NMF_E_ARG, "two-sided hierarchies run as single solves (nmf_solve)");
     if ((int)insts_.size() >= capacity_) return fail(plan, NMF_E_BUSY, "batch capacity reached");
     Inst I;
     I.id = id;

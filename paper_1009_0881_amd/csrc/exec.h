@@ -42,6 +42,7 @@ struct Ctx {
     std::vector<const float *> M;
     std::vector<int64_t> ldm;
     std::vector<float *> V;
+    std::vector<float *> Wl;      // W of every level (all dW unless two-sided)
     float *W;
     Job *djobs;                   // device copy of `jobs` (workspace)
     std::vector<Job> jobs;        // one job per level, then the FP32 finest-level job

@@ -46,6 +46,10 @@ static_assert(sizeof(DevState) <= 256, "state block");
 struct LevelInfo {
     int32_t h, w;
     int64_t m;
+    int64_t n;           // columns at this level (the finest n unless two-sided)
+    size_t off_W;        // two-sided: workspace offset of W_l (levels >= 1)
+    int32_t gram_w_parts;   // split of the length-n reduction of W W^T (ANLS Gram)
+    int64_t gram_w_chunk;
     size_t off_M;        // workspace offset of M_l (levels >= 1)
     size_t off_V;        // workspace offset of V_l (levels >= 1)
     size_t off_Mbp, off_Mbc, off_Vb;   // BF16 mode: copies of M_l (A-pass, C-pass layouts), V_l
@@ -75,6 +79,7 @@ struct Workspace {
     size_t off_Bd, off_Bf, off_Dd, off_Df;
     size_t off_gparts, off_cparts, off_rparts, off_A, off_C, off_Wb;
     size_t off_Wt, off_Dp, off_jobs;
+    size_t off_tmpM;     // two-sided: R_m M_l before the column restriction
     size_t gparts_cap;   // doubles
     size_t rparts_cap;   // doubles
     size_t total;
@@ -119,7 +124,9 @@ struct Plan {
     int64_t gram_w_chunk;
 };
 
-std::vector<Step> make_schedule(int cycle, int levels, int64_t iters);
+// ratio: iterations per finest-iteration equivalent grow by this factor per
+// depth (4: m halved per axis; 8: two-sided).
+std::vector<Step> make_schedule(int cycle, int levels, int64_t iters, int ratio = 4);
 nmf_status build_plan(const nmf_desc &d, Plan &p, std::string &err);
 
 // ---- launchers (kernels.hip etc.) ------------------------------------------
@@ -128,6 +135,13 @@ hipError_t launch_restrict(int xfer, int h, int w, int64_t ncols, const float *X
                            float *Y, const int32_t *stop, hipStream_t s);
 hipError_t launch_prolong(int xfer, int h, int w, int64_t ncols, const float *Y, float *X,
                           const int32_t *stop, hipStream_t s);
+// 1-D transfer (eq. restr / eq. prol of `xfer`) along the second index j of
+// a rows x N array X, element (i, j) at X[i * xi + j * xj], into Y (rows x N',
+// element (i, c) at Y[i * yi + c * yj]); restrict: N' = ceil(N/2), else N is
+// the fine length and Y has N' = N entries per row from N_c = ceil(N/2).
+hipError_t launch_xfer_cols(int restrict_op, int xfer, int64_t rows, int64_t N, const float *X,
+                            int64_t xi, int64_t xj, float *Y, int64_t yi, int64_t yj,
+                            const int32_t *stop, hipStream_t s);
 hipError_t launch_sumsq(const float *X, int64_t ld, int64_t rows, int64_t ncols, double *parts,
                         int nparts, double *out, hipStream_t s);
 hipError_t launch_check_input(const float *M, int64_t ld, int64_t m, int64_t n, int32_t *flags,

@@ -37,11 +37,11 @@ size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
 // split, the budget counted in finest-iteration equivalents: Run(d, t)
 // performs floor(t * 4^d) iterations at depth d (depth 0 = finest) and
 // zero-iteration runs are dropped.
-std::vector<Step> make_schedule(int cycle, int levels, int64_t iters) {
+std::vector<Step> make_schedule(int cycle, int levels, int64_t iters, int ratio) {
     std::vector<Step> out;
     auto run = [&](int d, Rat t) {
         int64_t scale = 1;
-        for (int i = 0; i < d; ++i) scale *= 4;
+        for (int i = 0; i < d; ++i) scale *= ratio;
         const int64_t c = (t.num * scale) / t.den;
         if (c > 0) out.push_back(Step{0, d, (int32_t)c});
     };
@@ -94,6 +94,14 @@ nmf_status build_plan(const nmf_desc &d0, Plan &p, std::string &err) {
         err = "BF16 precision is available for HALS and MU";
         return NMF_E_ARG;
     }
+    if (d.two_sided != 0 && d.two_sided != 1) {
+        err = "two_sided must be 0 or 1";
+        return NMF_E_ARG;
+    }
+    if (d.two_sided && d.prec != NMF_FP32) {
+        err = "two-sided hierarchies run in FP32";
+        return NMF_E_ARG;
+    }
     if (d.h < 1 || d.w < 1 || d.m != (int64_t)d.h * d.w) {
         snprintf(buf, sizeof buf, "m (%lld) must equal h*w (%d*%d)", (long long)d.m, d.h, d.w);
         err = buf;
@@ -130,6 +138,7 @@ nmf_status build_plan(const nmf_desc &d0, Plan &p, std::string &err) {
     }
     p.lv.clear();
     int h = d.h, w = d.w;
+    int64_t nl = d.n;
     for (int l = 0; l < d.levels; ++l) {
         if (l > 0) {
             if (h < 2 || w < 2) {
@@ -137,13 +146,21 @@ nmf_status build_plan(const nmf_desc &d0, Plan &p, std::string &err) {
                 err = buf;
                 return NMF_E_SHAPE;
             }
+            if (d.two_sided && nl < 2) {
+                snprintf(buf, sizeof buf, "level %d: cannot restrict %lld columns", l,
+                         (long long)nl);
+                err = buf;
+                return NMF_E_SHAPE;
+            }
             h = (h + 1) / 2;
             w = (w + 1) / 2;
+            if (d.two_sided) nl = (nl + 1) / 2;
         }
         LevelInfo li{};
         li.h = h;
         li.w = w;
         li.m = (int64_t)h * w;
+        li.n = nl;
         if (d.algo == NMF_ANLS && li.m < d.r) {
             snprintf(buf, sizeof buf,
                      "ANLS: level %d has %lld pixels < r = %d (singular V^T V)", l,
@@ -157,9 +174,9 @@ nmf_status build_plan(const nmf_desc &d0, Plan &p, std::string &err) {
 
     // Split of the length-m reductions.  Target about one block per CU for
     // V^T M (deterministic split-m partials) and at most 256 Gram partials.
-    const int64_t ntiles = (d.n + 63) / 64;
     size_t max_cp = 0, max_gp = 0, max_ap = 0;
     for (auto &li : p.lv) {
+        const int64_t ntiles = (li.n + 63) / 64;
         int64_t chunks = std::max<int64_t>(1, p.num_cu / std::max<int64_t>(1, ntiles));
         chunks = std::min<int64_t>(chunks, std::max<int64_t>(1, (li.m + 63) / 64));
         int64_t chunk = (li.m + chunks - 1) / chunks;
@@ -176,7 +193,7 @@ nmf_status build_plan(const nmf_desc &d0, Plan &p, std::string &err) {
         li.fstream = d.algo != NMF_ANLS && li.m % 4 == 0 &&
                      (li.m >= kFStreamMinRows ||
                       (p.lv[0].m >= kFStreamMinRows && li.m >= kFStreamWideRows &&
-                       d.n >= kFStreamWideCols));
+                       li.n >= kFStreamWideCols));
         li.ftm = li.m >= 65536 ? 128 : 64;
         li.aks = 1;
         if (li.fstream) {
@@ -184,13 +201,13 @@ nmf_status build_plan(const nmf_desc &d0, Plan &p, std::string &err) {
             // blocks as CUs, into at most 8 parts of at least 4 stages of 16
             // columns
             const int64_t tiles = (li.m + li.ftm - 1) / li.ftm;
-            const int64_t stages = (d.n + 15) / 16;
+            const int64_t stages = (li.n + 15) / 16;
             int64_t ks = (p.num_cu + tiles - 1) / tiles;
             ks = std::min<int64_t>({ks, std::max<int64_t>(1, stages / 4), 8});
             li.aks = li.ftm == 64 ? (int32_t)std::max<int64_t>(1, ks) : 1;   // k_afinal_s32: 64-row tiles
             if (li.aks > 1)
                 max_ap = std::max<size_t>(max_ap, (size_t)li.aks * tiles * li.ftm * p.rpad);
-            const int64_t ncx = (d.n + 127) / 128;
+            const int64_t ncx = (li.n + 127) / 128;
             int64_t sc = std::max<int64_t>(1, 2 * p.num_cu / ncx);
             sc = std::min<int64_t>(sc, std::max<int64_t>(1, li.m / 64));
             int64_t sch = (li.m + sc - 1) / sc;
@@ -202,7 +219,7 @@ nmf_status build_plan(const nmf_desc &d0, Plan &p, std::string &err) {
         // streaming C-pass (large BF16 levels): about two blocks per CU
         li.stream = d.prec == NMF_BF16 && li.m >= kStreamMinRows;
         if (li.stream) {
-            const int64_t ncx = (d.n + 255) / 256;
+            const int64_t ncx = (li.n + 255) / 256;
             int64_t sc = std::max<int64_t>(1, 2 * p.num_cu / ncx);
             sc = std::min<int64_t>(sc, std::max<int64_t>(1, (li.m + 255) / 256));
             int64_t sch = (li.m + sc - 1) / sc;
@@ -217,15 +234,15 @@ nmf_status build_plan(const nmf_desc &d0, Plan &p, std::string &err) {
         li.gram_chunk = gc;
         li.gram_parts = (int32_t)((li.m + gc - 1) / gc);
         max_gp = std::max<size_t>(max_gp, (size_t)li.gram_parts);
-    }
-    {
-        int64_t gp = std::min<int64_t>(256, (d.n + 63) / 64);
-        int64_t gc = (d.n + gp - 1) / gp;
+        gp = std::min<int64_t>(256, (li.n + 63) / 64);
+        gc = (li.n + gp - 1) / gp;
         gc = (gc + 63) / 64 * 64;
-        p.gram_w_chunk = gc;
-        p.gram_w_parts = (int32_t)((d.n + gc - 1) / gc);
-        max_gp = std::max<size_t>(max_gp, (size_t)p.gram_w_parts);
+        li.gram_w_chunk = gc;
+        li.gram_w_parts = (int32_t)((li.n + gc - 1) / gc);
+        max_gp = std::max<size_t>(max_gp, (size_t)li.gram_w_parts);
     }
+    p.gram_w_chunk = p.lv[0].gram_w_chunk;
+    p.gram_w_parts = p.lv[0].gram_w_parts;
 
     Workspace &ws = p.ws;
     size_t off = 0;
@@ -258,10 +275,16 @@ nmf_status build_plan(const nmf_desc &d0, Plan &p, std::string &err) {
     } else {
         ws.off_A = ws.off_C = 0;
     }
+    size_t tmp_elems = 0;
     for (size_t l = 1; l < p.lv.size(); ++l) {
-        p.lv[l].off_M = take(sizeof(float) * (size_t)p.lv[l].m * n);
+        p.lv[l].off_M = take(sizeof(float) * (size_t)p.lv[l].m * p.lv[l].n);
         p.lv[l].off_V = take(sizeof(float) * (size_t)p.lv[l].m * r);
+        if (d.two_sided) {
+            p.lv[l].off_W = take(sizeof(float) * r * (size_t)p.lv[l].n);
+            tmp_elems = std::max<size_t>(tmp_elems, (size_t)p.lv[l].m * p.lv[l - 1].n);
+        }
     }
+    ws.off_tmpM = tmp_elems ? take(sizeof(float) * tmp_elems) : 0;
     ws.off_Wt = take(sizeof(float) * n * p.rpad);
     ws.off_Dp = take(sizeof(double) * max_cp * rp2);
     ws.off_jobs = take(sizeof(Job) * (p.lv.size() + 1));   // + FP32 refinement job

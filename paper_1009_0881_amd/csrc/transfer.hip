@@ -142,6 +142,31 @@ __global__ __launch_bounds__(256) void k_prolong(const float *__restrict__ Y,
     }
 }
 
+// 1-D transfer along the second index of a rows x N array (two-sided
+// hierarchies: the column index of M, the rows of W).  One output element per
+// thread: its up to three taps from the closed form, accumulated in FP64 in
+// tap order and rounded once.  The flat index runs over the output with the
+// unit-stride index fastest (i_fast: i, else c) so the loads coalesce.
+__global__ __launch_bounds__(256) void k_xfer_cols(int restrict_op, int xfer, int64_t rows,
+                                                   int64_t N, int64_t Nout,
+                                                   const float *__restrict__ X, int64_t xi,
+                                                   int64_t xj, float *__restrict__ Y,
+                                                   int64_t yi, int64_t yj, int i_fast,
+                                                   const int32_t *stop) {
+    if (stopped(stop)) return;
+    const int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (e >= rows * Nout) return;
+    const int64_t i = i_fast ? e % rows : e / Nout;
+    const int64_t c = i_fast ? e / rows : e % Nout;
+    const Taps t = restrict_op ? restrict_taps((int)c, (int)N, xfer)
+                               : prolong_taps((int)c, (int)((N + 1) / 2), xfer);
+    const auto x = to_global(X);
+    double acc = 0.0;
+#pragma unroll
+    for (int a = 0; a < 3; ++a) acc += t.wt[a] * (double)x[i * xi + (int64_t)t.idx[a] * xj];
+    Y[i * yi + c * yj] = (float)acc;
+}
+
 // Sum of squares of a column-major matrix in FP64: per-block partials, then a
 // single block adds them in index order (deterministic).
 // Partial part (of nparts) of ||X||_F^2: work items (column, 2048-row chunk),
@@ -403,6 +428,19 @@ hipError_t launch_prolong(int xfer, int h, int w, int64_t ncols, const float *Y,
     if (mf == 0 || ncols == 0) return hipSuccess;
     const dim3 grid((mf + 255) / 256, (unsigned)std::min<int64_t>(ncols, 65535));
     k_prolong<<<grid, 256, 0, s>>>(Y, X, h, w, hc, wc, ncols, xfer, stop);
+    return hipGetLastError();
+}
+
+hipError_t launch_xfer_cols(int restrict_op, int xfer, int64_t rows, int64_t N, const float *X,
+                            int64_t xi, int64_t xj, float *Y, int64_t yi, int64_t yj,
+                            const int32_t *stop, hipStream_t s) {
+    const int64_t Nout = restrict_op ? (N + 1) / 2 : N;
+    const int64_t total = rows * Nout;
+    if (total <= 0) return hipSuccess;
+    const int i_fast = xi == 1 ? 1 : 0;
+    k_xfer_cols<<<(unsigned)((total + 255) / 256), 256, 0, s>>>(restrict_op, xfer, rows, N, Nout,
+                                                                X, xi, xj, Y, yi, yj, i_fast,
+                                                                stop);
     return hipGetLastError();
 }
 

@@ -111,6 +111,57 @@ def make_instance(spec: BlobSpec, seed: int) -> Instance:
     return Instance(spec=spec, seed=seed, M=M32, V0=V0, W0=W0, eps_E=eps, Vstar=Vs, Wstar=Ws)
 
 
+@dataclasses.dataclass(frozen=True)
+class SpectralSpec:
+    """Hyperspectral-like data: r abundance maps (Gaussian blobs on an h x w
+    grid, as in BlobSpec) times r smooth spectra over n ordered bands (each a
+    sum of 1-3 Gaussian bumps of width bw_lo..bw_hi bands), so columns vary
+    smoothly with the band index (the case Section 6.1 names for coarsening
+    n as well)."""
+    h: int
+    w: int
+    n: int
+    r: int
+    sig_lo: float
+    sig_hi: float
+    bw_lo: float
+    bw_hi: float
+    noise_std: float = 0.01
+
+    @property
+    def m(self) -> int:
+        return self.h * self.w
+
+
+# 64x64 pixels, 256 bands, 12 materials
+CFG_SPECTRAL = SpectralSpec(h=64, w=64, n=256, r=12, sig_lo=3.0, sig_hi=12.0, bw_lo=6.0,
+                            bw_hi=30.0)
+
+
+def make_spectral_instance(spec: SpectralSpec, seed: int) -> Instance:
+    """Draw one planted spectral instance (draw order: maps, spectra, noise,
+    V0, W0); deterministic for (spec, seed)."""
+    rng = np.random.default_rng(seed)
+    blob = BlobSpec(h=spec.h, w=spec.w, n=spec.n, r=spec.r, k_lo=1, k_hi=1,
+                    sig_lo=spec.sig_lo, sig_hi=spec.sig_hi, noise_std=spec.noise_std)
+    Vs = _atoms(rng, blob)
+    t = np.arange(spec.n, dtype=np.float64)
+    Ws = np.zeros((spec.r, spec.n), dtype=np.float64)
+    for k in range(spec.r):
+        for _ in range(int(rng.integers(1, 4))):
+            c = rng.uniform(0.0, spec.n)
+            bw = rng.uniform(spec.bw_lo, spec.bw_hi)
+            Ws[k] += rng.uniform(0.2, 1.0) * np.exp(-((t - c) ** 2) / (2.0 * bw ** 2))
+    clean = Vs @ Ws
+    noise = np.abs(rng.normal(0.0, spec.noise_std, size=clean.shape))
+    M32 = np.asfortranarray((clean + noise).astype(np.float32))
+    V0 = np.asfortranarray(rng.uniform(0.0, 1.0, size=(spec.m, spec.r)).astype(np.float32))
+    W0 = np.ascontiguousarray(rng.uniform(0.0, 1.0, size=(spec.r, spec.n)).astype(np.float32))
+    M64 = M32.astype(np.float64)
+    eps = float(np.linalg.norm(M64 - clean) / np.linalg.norm(M64))
+    return Instance(spec=blob, seed=seed, M=M32, V0=V0, W0=W0, eps_E=eps, Vstar=Vs, Wstar=Ws)
+
+
 def uniform_pair(m: int, n: int, r: int, seed: int) -> Tuple[np.ndarray, np.ndarray, np.ndarray]:
     """Plain U[0,1] FP32 (M, V0, W0) of arbitrary shape: unstructured test data."""
     rng = np.random.default_rng(seed)

@@ -52,6 +52,8 @@ def test_status_strings():
     (dict(m=100, n=4, h=10, w=10, r=3, tile_cfg=(3, 4)), -1),    # wc not in {1, 2, 4}
     (dict(m=100, n=4, h=10, w=10, r=3, tile_cfg=(2, 8)), -1),    # cf not in {4, 16}
     (dict(m=100, n=4, h=10, w=10, r=3, tile_cfg=(1 | 16 << 8 | 1 << 16)), -1),
+    (dict(m=256, n=40, h=16, w=16, r=3, levels=2, two_sided=True, prec="bf16"), -1),
+    (dict(m=256, n=2, h=16, w=16, r=1, levels=3, two_sided=True), -2),   # 2 -> 1 column, then 1
 ])
 def test_plan_rejects_bad_descriptions(kw, status):
     with pytest.raises(P.NmfError) as e:
@@ -78,6 +80,14 @@ def test_level_sides_match_oracle(hw, levels):
 def test_schedule_matches_oracle(cycle, levels, T):
     pl = P.Plan(m=256 * 256, n=10, h=256, w=256, r=3, levels=levels, cycle=cycle)
     assert pl.schedule(T) == O.schedule(P.CYCLES[cycle], levels, T)
+
+
+@pytest.mark.parametrize("cycle", ["ni", "vc", "fmg"])
+@pytest.mark.parametrize("levels", [1, 2, 3, 4])
+@pytest.mark.parametrize("T", [0, 1, 5, 16, 123])
+def test_two_sided_schedule_matches_oracle(cycle, levels, T):
+    pl = P.Plan(m=256 * 256, n=64, h=256, w=256, r=3, levels=levels, cycle=cycle, two_sided=True)
+    assert pl.schedule(T) == O.schedule(P.CYCLES[cycle], levels, T, 8)
 
 
 def test_workspace_grows_with_levels_and_algo():
