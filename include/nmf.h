@@ -52,7 +52,11 @@ enum {
 };
 
 enum { NMF_HALS = 0, NMF_MU = 1, NMF_ANLS = 2 };          /* Alg. 3, Alg. 2, Alg. 1 */
-enum { NMF_NI = 0, NMF_VC = 1, NMF_FMG = 2 };             /* Alg. 4, Alg. 5, Alg. 6 */
+/* Alg. 4, Alg. 5, Alg. 6; NMF_WC: W-cycle (Section 7.1 lists other cycles as
+ * future work): the V-cycle's split of the budget t (t/4 before descending,
+ * t/2 after) with the coarse quarter spent in two consecutive W-cycles of t/8
+ * on the next level. */
+enum { NMF_NI = 0, NMF_VC = 1, NMF_FMG = 2, NMF_WC = 3 };
 /* Transfer operators.  FW: full weighting (eq. restr, boundary weights of the
  * fine neighbours that exist renormalised to sum 1) with the rd() mean
  * prolongation (eq. prol).  BLOCK2: 2x2 pixel-block mean / replication. */

@@ -35,6 +35,9 @@ design notes):
   R10 stopping: with tol > 0 the solve ends after the first finest-level
       iteration whose rel_err <= tol; after the schedule, finest-level
       iterations continue until then or until max_fine_iters more iterations.
+  R13 W-cycle (Section 7.1 names other cycles as future work): the V-cycle's
+      time split with the coarse quarter spent in two consecutive W-cycles
+      of one eighth each at the next level.
 """
 from __future__ import annotations
 
@@ -45,14 +48,14 @@ from typing import Dict, List, Optional, Sequence, Tuple
 import numpy as np
 
 HALS, MU, ANLS = 0, 1, 2
-NI, VC, FMG = 0, 1, 2
+NI, VC, FMG, WC = 0, 1, 2, 3
 XFER_FW, XFER_BLOCK2 = 0, 1
 
 ALGO_NAMES = {HALS: "hals", MU: "mu", ANLS: "anls"}
-CYCLE_NAMES = {NI: "ni", VC: "vc", FMG: "fmg"}
+CYCLE_NAMES = {NI: "ni", VC: "vc", FMG: "fmg", WC: "wc"}
 
 __all__ = [
-    "HALS", "MU", "ANLS", "NI", "VC", "FMG", "XFER_FW", "XFER_BLOCK2",
+    "HALS", "MU", "ANLS", "NI", "VC", "FMG", "WC", "XFER_FW", "XFER_BLOCK2",
     "level_sides", "transfer_1d", "restrict_matrix", "prolong_matrix",
     "restrict_images", "prolong_images", "smoothness", "level_ns", "restrict_cols",
     "prolong_cols", "prolongation_bound_two_sided",
@@ -256,7 +259,22 @@ def schedule(cycle: int, levels: int, T, ratio: int = 4) -> List[Tuple[str, int,
         steps.append(("prolong", d, 0))
         vc(L, 3 * t / 4, d)
 
-    {NI: ni, VC: vc, FMG: fmg}[cycle](levels, T, 0)
+    def wc(L: int, t: Fraction, d: int) -> None:
+        # W-cycle (Section 7.1 lists other cycles as future work; reading R13):
+        # the V-cycle's split of t (1/4 before, 1/2 after, 1/4 to the coarser
+        # levels) with the coarse share spent in two consecutive W-cycles of
+        # t/8 each at the next level
+        if L == 1:
+            run(d, t)
+            return
+        run(d, t / 4)
+        steps.append(("restrict", d, 0))
+        wc(L - 1, t / 8, d + 1)
+        wc(L - 1, t / 8, d + 1)
+        steps.append(("prolong", d, 0))
+        run(d, t / 2)
+
+    {NI: ni, VC: vc, FMG: fmg, WC: wc}[cycle](levels, T, 0)
     return steps
 
 

@@ -22,12 +22,12 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libnmf.so")
 
 HALS, MU, ANLS = 0, 1, 2
-NI, VC, FMG = 0, 1, 2
+NI, VC, FMG, WC = 0, 1, 2, 3
 XFER_FW, XFER_BLOCK2 = 0, 1
 FP32, BF16 = 0, 1
 
 ALGOS = {"hals": HALS, "mu": MU, "anls": ANLS}
-CYCLES = {"ni": NI, "vc": VC, "fmg": FMG}
+CYCLES = {"ni": NI, "vc": VC, "fmg": FMG, "wc": WC}
 XFERS = {"fw": XFER_FW, "block2": XFER_BLOCK2}
 PRECS = {"fp32": FP32, "bf16": BF16}
 

@@ -33,10 +33,43 @@ size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
 
 }  // namespace
 
-// Schedule of Alg. 4 (NI), Alg. 5 (VC), Alg. 6 (FMG) with the Table 1 time
-// split, the budget counted in finest-iteration equivalents: Run(d, t)
-// performs floor(t * 4^d) iterations at depth d (depth 0 = finest) and
-// zero-iteration runs are dropped.
+// Schedules of the cycles, the budget counted in finest-iteration equivalents:
+// Run(d, t) performs floor(t * ratio^d) iterations at depth d (depth 0 =
+// finest; ratio 4, or 8 for two-sided hierarchies) and zero-iteration runs
+// are dropped.  Every cycle over L > 1 levels with budget t has the same
+// shape: a share of t run at the current level, a restriction, one or more
+// visits of the next level with shares of t, a prolongation, and a closing
+// share, which is a run or (full multigrid) a V-cycle over the same levels.
+// The table holds each cycle's shares: nested iteration (Alg. 4) and the
+// V-cycle (Alg. 5) give the coarser levels 1/4 of t (Table 1), full
+// multigrid (Alg. 6) descends first and closes with a V-cycle of 3t/4, the
+// W-cycle spends the coarse quarter in two visits of t/8.
+namespace {
+
+struct CycleRule {
+    Rat pre;              // run at the current level before descending
+    int coarse_cycle;     // cycle used on the next level
+    int visits;           // consecutive visits of the next level
+    Rat coarse;           // share of t per visit
+    bool close_vcycle;    // closing share: V-cycle over the same levels (else a run)
+    Rat close;            // closing share of t
+};
+
+const CycleRule &cycle_rule(int cycle) {
+    static const CycleRule kNI{{0, 1}, NMF_NI, 1, {1, 4}, false, {3, 4}};
+    static const CycleRule kVC{{1, 4}, NMF_VC, 1, {1, 4}, false, {1, 2}};
+    static const CycleRule kFMG{{0, 1}, NMF_FMG, 1, {1, 4}, true, {3, 4}};
+    static const CycleRule kWC{{1, 4}, NMF_WC, 2, {1, 8}, false, {1, 2}};
+    switch (cycle) {
+        case NMF_VC: return kVC;
+        case NMF_FMG: return kFMG;
+        case NMF_WC: return kWC;
+        default: return kNI;
+    }
+}
+
+}  // namespace
+
 std::vector<Step> make_schedule(int cycle, int levels, int64_t iters, int ratio) {
     std::vector<Step> out;
     auto run = [&](int d, Rat t) {
@@ -45,40 +78,25 @@ std::vector<Step> make_schedule(int cycle, int levels, int64_t iters, int ratio)
         const int64_t c = (t.num * scale) / t.den;
         if (c > 0) out.push_back(Step{0, d, (int32_t)c});
     };
-    std::function<void(int, Rat, int)> ni, vc, fmg;
-    ni = [&](int L, Rat t, int d) {
+    auto share = [](Rat t, Rat f) { return mul(t, f.num, f.den); };
+    std::function<void(int, int, Rat, int)> cyc = [&](int cy, int L, Rat t, int d) {
         if (L == 1) return run(d, t);
+        const CycleRule &R = cycle_rule(cy);
+        if (R.pre.num > 0) run(d, share(t, R.pre));
         out.push_back(Step{1, d, 0});
-        ni(L - 1, mul(t, 1, 4), d + 1);
+        for (int v = 0; v < R.visits; ++v) cyc(R.coarse_cycle, L - 1, share(t, R.coarse), d + 1);
         out.push_back(Step{2, d, 0});
-        run(d, mul(t, 3, 4));
+        if (R.close_vcycle) cyc(NMF_VC, L, share(t, R.close), d);
+        else run(d, share(t, R.close));
     };
-    vc = [&](int L, Rat t, int d) {
-        if (L == 1) return run(d, t);
-        run(d, mul(t, 1, 4));
-        out.push_back(Step{1, d, 0});
-        vc(L - 1, mul(t, 1, 4), d + 1);
-        out.push_back(Step{2, d, 0});
-        run(d, mul(t, 1, 2));
-    };
-    fmg = [&](int L, Rat t, int d) {
-        if (L == 1) return run(d, t);
-        out.push_back(Step{1, d, 0});
-        fmg(L - 1, mul(t, 1, 4), d + 1);
-        out.push_back(Step{2, d, 0});
-        vc(L, mul(t, 3, 4), d);
-    };
-    const Rat T{iters, 1};
-    if (cycle == NMF_VC) vc(levels, T, 0);
-    else if (cycle == NMF_FMG) fmg(levels, T, 0);
-    else ni(levels, T, 0);
+    cyc(cycle, levels, Rat{iters, 1}, 0);
     return out;
 }
 
 nmf_status build_plan(const nmf_desc &d0, Plan &p, std::string &err) {
     nmf_desc d = d0;
     char buf[256];
-    if (d.algo < NMF_HALS || d.algo > NMF_ANLS || d.cycle < NMF_NI || d.cycle > NMF_FMG ||
+    if (d.algo < NMF_HALS || d.algo > NMF_ANLS || d.cycle < NMF_NI || d.cycle > NMF_WC ||
         d.xfer < NMF_XFER_FW || d.xfer > NMF_XFER_BLOCK2 || d.prec < NMF_FP32 || d.prec > NMF_BF16) {
         err = "unknown algo / cycle / xfer / prec value";
         return NMF_E_ARG;

@@ -74,7 +74,7 @@ def test_level_sides_match_oracle(hw, levels):
     assert pl.level_sides() == O.level_sides(h, w, levels)
 
 
-@pytest.mark.parametrize("cycle", ["ni", "vc", "fmg"])
+@pytest.mark.parametrize("cycle", ["ni", "vc", "fmg", "wc"])
 @pytest.mark.parametrize("levels", [1, 2, 3, 4])
 @pytest.mark.parametrize("T", [0, 1, 5, 16, 40, 123, 200, 1000])
 def test_schedule_matches_oracle(cycle, levels, T):
@@ -82,7 +82,7 @@ def test_schedule_matches_oracle(cycle, levels, T):
     assert pl.schedule(T) == O.schedule(P.CYCLES[cycle], levels, T)
 
 
-@pytest.mark.parametrize("cycle", ["ni", "vc", "fmg"])
+@pytest.mark.parametrize("cycle", ["ni", "vc", "fmg", "wc"])
 @pytest.mark.parametrize("levels", [1, 2, 3, 4])
 @pytest.mark.parametrize("T", [0, 1, 5, 16, 123])
 def test_two_sided_schedule_matches_oracle(cycle, levels, T):

@@ -38,7 +38,7 @@ def test_small_config_first_50_iterations():
 
 
 @pytest.mark.parametrize("algo", ["hals", "mu", "anls"])
-@pytest.mark.parametrize("cycle", ["ni", "vc", "fmg"])
+@pytest.mark.parametrize("cycle", ["ni", "vc", "fmg", "wc"])
 def test_small_config_full_schedule(algo, cycle):
     inst = synth.make_instance(synth.CFG_SMALL, 0)
     T = 16 if algo != "anls" else 8
@@ -51,7 +51,7 @@ def test_small_config_full_schedule(algo, cycle):
 
 
 @pytest.mark.parametrize("algo", ["hals", "mu"])
-@pytest.mark.parametrize("cycle", ["ni", "vc", "fmg"])
+@pytest.mark.parametrize("cycle", ["ni", "vc", "fmg", "wc"])
 def test_orl_shape_three_levels(algo, cycle):
     inst = synth.make_instance(synth.CFG_ORL, 0)
     args = (inst.M, inst.V0, inst.W0, 112, 92, 40, 3, algo, cycle, "fw", 16)

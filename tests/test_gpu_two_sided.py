@@ -46,7 +46,7 @@ def _check(tag, out):
 
 
 @pytest.mark.parametrize("algo", ["hals", "mu", "anls"])
-@pytest.mark.parametrize("cycle", ["ni", "vc", "fmg"])
+@pytest.mark.parametrize("cycle", ["ni", "vc", "fmg", "wc"])
 def test_spectral_two_sided_matches_oracle(algo, cycle):
     """32x32 abundance maps, 96 smooth bands, r = 8, 3 levels (96 -> 48 -> 24
     columns), full weighting on both sides."""

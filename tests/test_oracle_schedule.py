@@ -87,3 +87,48 @@ def test_schedule_is_well_formed(cycle, L, T):
 def test_single_level_is_plain_run():
     for cyc in (O.NI, O.VC, O.FMG):
         assert O.schedule(cyc, 1, 37) == [("run", 0, 37)]
+
+
+# ------------------------------------------------------------------ W-cycle
+
+@pytest.mark.parametrize("levels", [2, 3, 4, 5])
+@pytest.mark.parametrize("T", [64, 256, 4096])
+def test_w_cycle_keeps_the_table1_totals(levels, T):
+    # reading R13: the V-cycle's split, so every level gets the Table 1 totals
+    # (3T/4 iterations at each non-coarsest level, T at the coarsest) when
+    # every run's budget is a whole number of iterations (T a multiple of
+    # 2^(levels+1); smaller budgets lose iterations to the floor of each run)
+    st = O.schedule(O.WC, levels, T)
+    tot = O.level_iteration_totals(st, levels)
+    assert tot == O.level_iteration_totals(O.schedule(O.VC, levels, T), levels)
+    want = [3 * T // 4] * (levels - 1) + [T]
+    assert tot == want
+
+
+@pytest.mark.parametrize("levels", [2, 3, 4, 5])
+def test_w_cycle_visits_each_coarser_level_twice_per_visit_above(levels):
+    st = O.schedule(O.WC, levels, 4096)
+    # each visit of depth d restricts once and visits depth d+1 twice: depth d
+    # is visited 2^d times
+    visits = [2 ** d for d in range(levels)]
+    for d in range(levels - 1):
+        assert sum(1 for k, dd, _ in st if k == "restrict" and dd == d) == visits[d]
+        assert sum(1 for k, dd, c in st if k == "run" and dd == d + 1) >= visits[d + 1]
+    # transfers balance and the walk starts and ends on the finest level
+    depth = 0
+    for kind, d, _ in st:
+        if kind == "restrict":
+            assert depth == d
+            depth += 1
+        elif kind == "prolong":
+            assert depth == d + 1
+            depth -= 1
+        else:
+            assert depth == d
+    assert depth == 0
+
+
+def test_w_cycle_two_levels_written_out():
+    T = 16
+    assert O.schedule(O.WC, 2, T) == [("run", 0, 4), ("restrict", 0, 0), ("run", 1, 8),
+                                      ("run", 1, 8), ("prolong", 0, 0), ("run", 0, 8)]
