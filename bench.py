@@ -11,6 +11,8 @@ Prints ONE JSON line.  Workloads (seeded, synthetic):
   orl   (default) 112x92 images, n=400, r=40, 3 levels of full weighting
   small           16x16 images, n=500, r=10, 2 levels of 2x2 block restriction
   large           256x256 images, n=2000, r=50, 4 levels of full weighting
+  spectral        64x64 maps x 256 smooth bands, r=12, 3 two-sided levels (the band
+                  count halves with the grid); also times the one-sided hierarchy
   batch           512 uneven problems (sides 16-64, n 100-2000, r 5-40), 3 levels,
                   HALS, one batched solve (grouped launches) per step
   serve           Poisson arrivals (default 200 req/s) of problems drawn like
@@ -48,13 +50,10 @@ SWEEP_SOURCES = ("sweep.hip", "sweep_device.h", "device_common.h", "job.h")
 STREAM_SOURCES = SWEEP_SOURCES + ("stream.hip",)
 TRAFFIC = {
     ("orl", "fp32"): {
-        "sha": "1b98f6e27670d87d",
+        "sha": "d41ff4590f797f1c",
         "files": SWEEP_SOURCES,
-        "apass": {10304: 20016963, 2576: 6178816, 644: 2470272},
-        "cpass_partial": {10304: 21960635, 2576: 8363008, 644: 3509504},
-        "cpass_final": {10304: 5200969, 2576: 3923072, 644: 2642048},
-        "gram_v": {10304: 463262, 2576: 350720, 644: 236544},
-        "gram_w": {10304: 297676, 2576: 309984, 644: 309856},
+        "apass": {10304: 16467037, 2576: 6153595, 644: 2453112},
+        "cpass_partial": {10304: 19473603, 2576: 8886629, 644: 3730826},
     },
 }
 
@@ -71,6 +70,9 @@ WORKLOADS = {
     "orl": dict(spec="CFG_ORL", h=112, w=92, levels=3, xfer="fw"),
     "small": dict(spec="CFG_SMALL", h=16, w=16, levels=2, xfer="block2"),
     "large": dict(spec="CFG_LARGE", h=256, w=256, levels=4, xfer="fw"),
+    # hyperspectral-like: 64x64 abundance maps x 256 smooth bands, r = 12; the
+    # hierarchy halves the band count too (two-sided, Section 6.1)
+    "spectral": dict(spec="CFG_SPECTRAL", h=64, w=64, levels=3, xfer="fw", two_sided=True),
 }
 
 
@@ -300,7 +302,7 @@ def main() -> int:
                     help="only run 3 device-to-device copies of BYTES bytes (reference for "
                          "the FETCH_SIZE / WRITE_SIZE counters) and exit")
     ap.add_argument("--algo", default="hals", choices=["hals", "mu", "anls"])
-    ap.add_argument("--cycle", default="vc", choices=["ni", "vc", "fmg"])
+    ap.add_argument("--cycle", default="vc", choices=["ni", "vc", "fmg", "wc"])
     ap.add_argument("--levels", type=int, default=None)
     ap.add_argument("--budget", type=int, default=16,
                     help="schedule budget T in finest-iteration equivalents")
@@ -312,6 +314,8 @@ def main() -> int:
                          "refinement on the finest level)")
     ap.add_argument("--refine", type=int, default=4, help="bf16: FP32 refinement iterations")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-other-algos", action="store_true",
+                    help="orl: skip the time-to-target of the other two algorithms")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     args = ap.parse_args()
 
@@ -346,7 +350,8 @@ def main() -> int:
     wl = WORKLOADS[args.workload]
     spec = getattr(synth, wl["spec"])
     levels = args.levels or wl["levels"]
-    inst = synth.make_instance(spec, args.seed)
+    two_sided = bool(wl.get("two_sided"))
+    inst = (synth.make_spectral_instance if two_sided else synth.make_instance)(spec, args.seed)
     m, n, r = spec.m, spec.n, spec.r
     target = inst.eps_E + args.tau
 
@@ -356,14 +361,14 @@ def main() -> int:
     Vs = [V0d.clone() for _ in range(nbuf)]
     Ws = [W0d.clone() for _ in range(nbuf)]
 
-    def make_plan(L, prec="fp32"):
+    def make_plan(L, prec="fp32", two=False):
         return P.Plan(m=m, n=n, h=wl["h"], w=wl["w"], r=r, levels=L, algo=args.algo,
                       cycle=args.cycle, xfer=wl["xfer"], tol=target,
                       max_fine_iters=args.max_fine_iters, check_every=4, prec=prec,
                       refine_iters=args.refine if prec == "bf16" else 0,
-                      tile_cfg=parse_tile(args.tile))
+                      tile_cfg=parse_tile(args.tile), two_sided=two)
 
-    ml = make_plan(levels, args.prec)
+    ml = make_plan(levels, args.prec, two_sided)
     sl = make_plan(1)
     n_sched = sum(c for k, _, c in ml.schedule(args.budget) if k == "run")
     ws_ml, ws_sl = ml.workspace(), sl.workspace()
@@ -412,15 +417,58 @@ def main() -> int:
         dt, sl_res = run(sl, ws_sl, 0, i)
         sl_times.append(dt)
 
+    # the other two algorithms of the workload (ORL-shaped: all three), fewer solves
+    others = {}
+    if args.workload == "orl" and not args.no_other_algos and args.prec == "fp32":
+        for alg, cyc, bud in (("hals", "vc", 16), ("mu", "vc", 16), ("anls", "ni", 8)):
+            if alg == args.algo:
+                continue
+            def plan_for(L):
+                return P.Plan(m=m, n=n, h=wl["h"], w=wl["w"], r=r, levels=L, algo=alg, cycle=cyc,
+                              xfer=wl["xfer"], tol=target, max_fine_iters=args.max_fine_iters,
+                              check_every=4)
+            pm, ps = plan_for(levels), plan_for(1)
+            wm, wsl = pm.workspace(), ps.workspace()
+            tm, tsl = [], []
+            for i in range(2 + 5):
+                dt, rm = run(pm, wm, bud, i)
+                if i >= 2:
+                    tm.append(dt)
+                dt, rs = run(ps, wsl, 0, i)
+                if i >= 2:
+                    tsl.append(dt)
+            mm, ms_ = float(np.median(tm) * 1e3), float(np.median(tsl) * 1e3)
+            others[alg] = {"cycle": cyc, "budget": bud, "multilevel_ms": round(mm, 4),
+                           "single_level_ms": round(ms_, 4), "speedup": round(ms_ / mm, 3),
+                           "iterations": rm["total_iters"], "fine": rm["fine_iters"],
+                           "single_level_iterations": rs["total_iters"],
+                           "reached_target": bool(rm["stopped"] and rs["stopped"])}
+
+    # two-sided workload: the one-sided hierarchy on the same data, for comparison
+    one_ms = None
+    if two_sided:
+        ol = make_plan(levels, args.prec, False)
+        ws_ol = ol.workspace()
+        ot = []
+        for i in range(K):
+            dt, o_res = run(ol, ws_ol, args.budget, i)
+            ot.append(dt)
+        one_ms = {"p50": round(float(np.percentile(np.array(ot) * 1e3, 50)), 4),
+                  "iterations": o_res["total_iters"], "fine": o_res["fine_iters"],
+                  "reached_target": bool(o_res["stopped"])}
+
     ok = all(res["stopped"] == 1 for res in results) and sl_res["stopped"] == 1
     times_ms = np.array(times) * 1e3
     sl_ms = np.array(sl_times) * 1e3
 
     # --- roofline of the dominant kernel --------------------------------------
     sides = level_sides(wl["h"], wl["w"], levels)
+    ncols = [n]
+    for _ in range(levels - 1):
+        ncols.append((ncols[-1] + 1) // 2 if two_sided else ncols[-1])
     tot_bytes = tot_flops = 0
     for it, d in enumerate(dep_log):
-        b, f = kernel_bytes_flops(dominant, sides[d][0] * sides[d][1], n, r,
+        b, f = kernel_bytes_flops(dominant, sides[d][0] * sides[d][1], ncols[d], r,
                                   bf=args.prec == "bf16" and it < n_sched)
         tot_bytes += b
         tot_flops += f
@@ -432,13 +480,17 @@ def main() -> int:
         ms_ = [sides[d][0] * sides[d][1] for d in dep_log]
         if all(m_ in tab for m_ in ms_):
             traffic = int(sum(tab[m_] for m_ in ms_) / max(1, len(ms_)))
+    # achieved = the kernel's algorithmic bytes per solve over its measured time per
+    # solve: the same ratio as per launch, and it stays right when a level issues two
+    # launches of the kind (split A-pass) and for the launches issued past the stop
+    # (they return at once; their time is counted, their bytes are not)
     cnt, ms_tot = prof_dom.get(dominant, (0, 0.0))
     solves = len(results)
     launches_per_solve = cnt / max(1, solves)
     per_launch_bytes = tot_bytes / max(1, len(dep_log))
-    per_launch_flops = tot_flops / max(1, len(dep_log))
+    t_solve = (ms_tot / max(1, solves)) * 1e-3
     avg_s = (ms_tot / max(1, cnt)) * 1e-3
-    achieved = per_launch_bytes / avg_s / 1e9 if avg_s > 0 else 0.0
+    achieved = tot_bytes / t_solve / 1e9 if t_solve > 0 else 0.0
     roofline = {
         "kernel": dominant,
         "bound": "hbm",
@@ -450,11 +502,12 @@ def main() -> int:
         "traffic_unit": "bytes per launch (HBM, rocprofv3 FETCH_SIZE + WRITE_SIZE, copy-scaled)",
         "avg_launch_us": round(avg_s * 1e6, 3),
         "launches_per_solve": launches_per_solve,
-        "algorithmic_bytes_per_launch": int(per_launch_bytes),
-        "mfma_tflops": round(per_launch_flops / avg_s / 1e12, 3) if avg_s > 0 else 0.0,
-        "mfma_frac": round(per_launch_flops / avg_s / 1e12 / (PEAK_BF16_MFMA_TFLOPS if args.prec == "bf16"
-                                                              else PEAK_FP32_MFMA_TFLOPS), 4)
-        if avg_s > 0 else 0.0,
+        "algorithmic_bytes_per_iteration": int(per_launch_bytes),
+        "iterations_per_solve": len(dep_log),
+        "mfma_tflops": round(tot_flops / t_solve / 1e12, 3) if t_solve > 0 else 0.0,
+        "mfma_frac": round(tot_flops / t_solve / 1e12 / (PEAK_BF16_MFMA_TFLOPS if args.prec == "bf16"
+                                                         else PEAK_FP32_MFMA_TFLOPS), 4)
+        if t_solve > 0 else 0.0,
     }
     kernels = {k: {"launches_per_solve": v[0], "avg_us": round(v[1] / max(1, v[0]) * 1e3, 3),
                    "ms_per_solve": round(v[1], 4)} for k, v in prof_all.items()}
@@ -468,7 +521,7 @@ def main() -> int:
             cores = max([i.get("num_threads", 1) for i in threadpool_info()] or [1])
         except Exception:   # threadpoolctl missing: report the affinity mask
             cores = len(os.sched_getaffinity(0))
-        cyc = {"ni": O.NI, "vc": O.VC, "fmg": O.FMG}[args.cycle]
+        cyc = {"ni": O.NI, "vc": O.VC, "fmg": O.FMG, "wc": O.WC}[args.cycle]
         alg = {"hals": O.HALS, "mu": O.MU, "anls": O.ANLS}[args.algo]
         xf = O.XFER_FW if wl["xfer"] == "fw" else O.XFER_BLOCK2
         t0 = time.perf_counter()
@@ -476,7 +529,8 @@ def main() -> int:
         fine_it = 0
         while True:
             ores = O.solve(inst.M, wl["h"], wl["w"], r, levels, alg, cyc, xf, args.budget,
-                           inst.V0, inst.W0, tol=target, max_fine_iters=args.max_fine_iters)
+                           inst.V0, inst.W0, tol=target, max_fine_iters=args.max_fine_iters,
+                           two_sided=two_sided)
             nsol += 1
             fine_it = ores.fine_iters
             if time.perf_counter() - t0 >= args.cpu_seconds or nsol >= 50:
@@ -503,8 +557,10 @@ def main() -> int:
         "dtype": "bf16+f32" if args.prec == "bf16" else "f32",
         "data": "synthetic",
         "config": {
-            "workload": f"{args.workload}: {wl['h']}x{wl['w']} planted-blob images, n={n}, r={r}, "
-                        f"{levels} levels ({wl['xfer']}), {args.cycle.upper()} {args.algo.upper()} "
+            "workload": f"{args.workload}: {wl['h']}x{wl['w']} planted-blob "
+                        f"{'maps x smooth spectra' if two_sided else 'images'}, n={n}, r={r}, "
+                        f"{levels} {'two-sided ' if two_sided else ''}levels ({wl['xfer']}), "
+                        f"{args.cycle.upper()} {args.algo.upper()} "
                         + ("BF16 GEMMs, FP32 accumulation, " + str(args.refine) + " FP32 refinement "
                            "iterations on the finest level" if args.prec == "bf16" else "FP32")
                         + f", budget T={args.budget}, target rel_err <= eps_E+{args.tau:g}",
@@ -523,6 +579,8 @@ def main() -> int:
                        "multilevel_fine_equiv": round(last["fine_equiv"], 3),
                        "single_level": sl_res["total_iters"]},
         "all_reached_target": bool(ok),
+        "one_sided_multilevel_ms": one_ms,
+        "other_algorithms": others or None,
         "tile_cfg": tile_desc(parse_tile(args.tile)),
         "roofline": roofline,
         "kernels": kernels,
