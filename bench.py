@@ -37,6 +37,7 @@ sys.path.insert(0, ROOT)
 PEAK_HBM_GBS = 8000.0          # MI355X HBM3E
 PEAK_FP32_MFMA_TFLOPS = 157.3  # MI355X dense FP32 matrix
 PEAK_BF16_MFMA_TFLOPS = 2500.0  # MI355X dense BF16 matrix
+PEAK_FP64_VALU_TFLOPS = 78.6   # MI355X FP64 vector
 
 EXTRA_WORKLOADS = ("batch", "serve")
 
@@ -113,6 +114,12 @@ def kernel_bytes_flops(kind, m, n, r, bf=False):
                 2 * m * n * r + 2 * m * r * r)
     if kind == "cpass_final":     # W update and W W^T: read C, read/write W
         return 4 * r * n + 8 * r * n + 8 * r * r, 6 * n * r * r
+    if kind in ("nnls_rows", "nnls_cols"):
+        # one exact solve per problem: a Cholesky of the r x r Gram (r^3 / 3
+        # multiply-adds), the two substitutions and the gradient (r^2 each);
+        # FP64 right-hand sides in, FP32 factor read and written
+        cnt = m if kind == "nnls_rows" else n
+        return 8 * cnt * r + 8 * cnt * r + 8 * r * r, cnt * (2 * r ** 3 // 3 + 6 * r * r)
     return 0, 0
 
 
@@ -499,24 +506,30 @@ def main() -> int:
     per_launch_bytes = tot_bytes / max(1, len(dep_log))
     t_solve = (ms_tot / max(1, solves)) * 1e-3
     avg_s = (ms_tot / max(1, cnt)) * 1e-3
-    achieved = tot_bytes / t_solve / 1e9 if t_solve > 0 else 0.0
+    alu = dominant in ("nnls_rows", "nnls_cols")
+    if alu:     # FP64 vector arithmetic, no matrix cores: one exact solve per problem
+        achieved = tot_flops / t_solve / 1e12 if t_solve > 0 else 0.0
+        peak, unit = PEAK_FP64_VALU_TFLOPS, "TFLOP/s"
+    else:
+        achieved = tot_bytes / t_solve / 1e9 if t_solve > 0 else 0.0
+        peak, unit = PEAK_HBM_GBS, "GB/s"
     roofline = {
         "kernel": dominant,
-        "bound": "hbm",
-        "achieved": round(achieved, 1),
-        "peak": PEAK_HBM_GBS,
-        "unit": "GB/s",
-        "frac": round(achieved / PEAK_HBM_GBS, 4),
+        "bound": "alu" if alu else "hbm",
+        "achieved": round(achieved, 3 if alu else 1),
+        "peak": peak,
+        "unit": unit,
+        "frac": round(achieved / peak, 4),
         "traffic": traffic,
         "traffic_unit": "bytes per launch (HBM, rocprofv3 FETCH_SIZE + WRITE_SIZE, copy-scaled)",
         "avg_launch_us": round(avg_s * 1e6, 3),
         "launches_per_solve": launches_per_solve,
         "algorithmic_bytes_per_iteration": int(per_launch_bytes),
         "iterations_per_solve": len(dep_log),
-        "mfma_tflops": round(tot_flops / t_solve / 1e12, 3) if t_solve > 0 else 0.0,
+        "mfma_tflops": 0.0 if alu else (round(tot_flops / t_solve / 1e12, 3) if t_solve > 0 else 0.0),
         "mfma_frac": round(tot_flops / t_solve / 1e12 / (PEAK_BF16_MFMA_TFLOPS if args.prec == "bf16"
                                                          else PEAK_FP32_MFMA_TFLOPS), 4)
-        if t_solve > 0 else 0.0,
+        if t_solve > 0 and not alu else 0.0,
     }
     kernels = {k: {"launches_per_solve": v[0], "avg_us": round(v[1] / max(1, v[0]) * 1e3, 3),
                    "ms_per_solve": round(v[1], 4)} for k, v in prof_all.items()}

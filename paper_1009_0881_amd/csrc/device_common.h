@@ -3,12 +3,22 @@
 
 #include <hip/hip_runtime.h>
 #include <cstdint>
+#include <type_traits>
 
 namespace nmf {
 
 typedef float v4f __attribute__((ext_vector_type(4)));
 
 constexpr int kWave = 64;
+
+// f(integral_constant<int, I>) for I = 0..N-1, unrolled at compile time.
+template <int N, int I = 0, class F>
+__device__ __forceinline__ void static_for(F &&f) {
+    if constexpr (I < N) {
+        f(std::integral_constant<int, I>{});
+        static_for<N, I + 1>(f);
+    }
+}
 
 // Global-memory view of a pointer.  Pointers read from a job table are generic
 // to the compiler, which then issues FLAT loads: they count against both the

@@ -28,14 +28,6 @@ constexpr int MODE_HALS = 0, MODE_MU = 1, MODE_STORE = 2, MODE_INIT = 3;
 // Prefetch distance (in HALS steps) of the Gram rows in row_update.
 constexpr int kGramAhead = 2;
 
-template <int N, int I = 0, class F>
-__device__ __forceinline__ void static_for(F &&f) {
-    if constexpr (I < N) {
-        f(std::integral_constant<int, I>{});
-        static_for<N, I + 1>(f);
-    }
-}
-
 // (job, tile) of this block: entry blockIdx.x of the launch's block map, or
 // (0, blockIdx.x) for a launch over a single job (null map).
 __device__ __forceinline__ int2 block_job(const int2 *bmap) {
