@@ -74,7 +74,7 @@ typedef struct {
     int32_t r;             /* rank, 1..64                                           */
     int32_t levels;        /* >= 1 (1 = plain single-level NMF)                     */
     int32_t algo;          /* NMF_HALS / NMF_MU / NMF_ANLS                          */
-    int32_t cycle;         /* NMF_NI / NMF_VC / NMF_FMG                             */
+    int32_t cycle;         /* NMF_NI / NMF_VC / NMF_FMG / NMF_WC                    */
     int32_t xfer;          /* NMF_XFER_FW / NMF_XFER_BLOCK2                         */
     int32_t prec;          /* NMF_FP32 / NMF_BF16                                   */
     int32_t refine_iters;  /* BF16 only: finest-level FP32 iterations appended      */
