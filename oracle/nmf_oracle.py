@@ -38,6 +38,14 @@ design notes):
   R13 W-cycle (Section 7.1 names other cycles as future work): the V-cycle's
       time split with the coarse quarter spent in two consecutive W-cycles
       of one eighth each at the next level.
+  R17 KL objective (Section 7.1 names other objective functions): the
+      generalized Kullback-Leibler divergence D(M | VW) = sum M log(M/(VW))
+      - M + VW (0 log 0 = 0), minimised by the multiplicative updates of Lee
+      and Seung: V <- V o [(M / VW) W^T] / [1 W^T], then W <- W o [V^T (M /
+      VW)] / [V^T 1].  The hierarchy, transfers and schedule are unchanged;
+      the logged error of an iteration is D(M_l | VW) / sum(M_l).  Where
+      (VW)_ij = 0 the ratio M_ij / (VW)_ij is taken as 0; a zero denominator
+      (a zero row of W or column of V) leaves the entry unchanged, as R7.
 """
 from __future__ import annotations
 
@@ -47,15 +55,15 @@ from typing import Dict, List, Optional, Sequence, Tuple
 
 import numpy as np
 
-HALS, MU, ANLS = 0, 1, 2
+HALS, MU, ANLS, KL = 0, 1, 2, 3
 NI, VC, FMG, WC = 0, 1, 2, 3
 XFER_FW, XFER_BLOCK2 = 0, 1
 
-ALGO_NAMES = {HALS: "hals", MU: "mu", ANLS: "anls"}
+ALGO_NAMES = {HALS: "hals", MU: "mu", ANLS: "anls", KL: "kl"}
 CYCLE_NAMES = {NI: "ni", VC: "vc", FMG: "fmg", WC: "wc"}
 
 __all__ = [
-    "HALS", "MU", "ANLS", "NI", "VC", "FMG", "WC", "XFER_FW", "XFER_BLOCK2",
+    "HALS", "MU", "ANLS", "KL", "NI", "VC", "FMG", "WC", "XFER_FW", "XFER_BLOCK2",
     "level_sides", "transfer_1d", "restrict_matrix", "prolong_matrix",
     "restrict_images", "prolong_images", "smoothness", "level_ns", "restrict_cols",
     "prolong_cols", "prolongation_bound_two_sided",
@@ -63,6 +71,7 @@ __all__ = [
     "hals_update_V", "hals_update_W", "hals_iteration",
     "mu_update_V", "mu_update_W", "mu_iteration",
     "nnls_gram", "nnls_bpp", "anls_update_V", "anls_update_W", "anls_iteration",
+    "kl_ratio", "kl_divergence", "rel_kl", "kl_update_V", "kl_update_W", "kl_iteration",
     "iteration", "bf16_round", "hals_update_V_bf16", "hals_update_W_bf16",
     "mu_iteration_bf16", "iteration_bf16", "rel_err", "objective", "gram_form_residual2",
     "eckart_young_floor", "prolongation_bound", "solve", "SolveResult",
@@ -496,8 +505,68 @@ def anls_iteration(M, V, W):
     return V, W
 
 
+# ---------------------------------------------------------------------------
+# Kullback-Leibler objective (Section 7.1's other objective functions; R17)
+# ---------------------------------------------------------------------------
+
+def kl_ratio(M: np.ndarray, P: np.ndarray) -> np.ndarray:
+    """M / P entrywise, 0 where P = 0 (R17)."""
+    Q = np.zeros_like(P)
+    ok = P > 0
+    Q[ok] = M[ok] / P[ok]
+    return Q
+
+
+def kl_divergence(M, V, W) -> float:
+    """D(M | V W) = sum_ij M_ij log(M_ij / (VW)_ij) - M_ij + (VW)_ij, with
+    0 log 0 = 0 (R17); +inf where M_ij > 0 = (VW)_ij."""
+    M = np.asarray(M, dtype=np.float64)
+    P = V @ W
+    t = P - M
+    pos = M > 0
+    with np.errstate(divide="ignore"):
+        t[pos] += M[pos] * np.log(M[pos] / P[pos])
+    return float(np.sum(t))
+
+
+def rel_kl(M, V, W) -> float:
+    """The logged error of the KL objective: D(M | V W) / sum(M) (R17)."""
+    return kl_divergence(M, V, W) / float(np.sum(np.asarray(M, dtype=np.float64)))
+
+
+def kl_update_V(M: np.ndarray, V: np.ndarray, W: np.ndarray) -> np.ndarray:
+    """V <- V o [(M / VW) W^T] / [1 W^T]: the denominator of column k is
+    sum_j W_kj; zero denominators keep the entry (R17)."""
+    Q = kl_ratio(M, V @ W)
+    num = Q @ W.T
+    den = W.sum(axis=1)
+    out = np.array(V, dtype=np.float64, copy=True)
+    ok = den > 0
+    out[:, ok] = V[:, ok] * num[:, ok] / den[ok]
+    return out
+
+
+def kl_update_W(M: np.ndarray, V: np.ndarray, W: np.ndarray) -> np.ndarray:
+    """W <- W o [V^T (M / VW)] / [V^T 1]: the denominator of row k is
+    sum_i V_ik; zero denominators keep the entry (R17)."""
+    Q = kl_ratio(M, V @ W)
+    num = V.T @ Q
+    den = V.sum(axis=0)
+    out = np.array(W, dtype=np.float64, copy=True)
+    ok = den > 0
+    out[ok, :] = W[ok, :] * num[ok, :] / den[ok, None]
+    return out
+
+
+def kl_iteration(M, V, W):
+    V = kl_update_V(M, V, W)
+    W = kl_update_W(M, V, W)
+    return V, W
+
+
 def iteration(algo: int, M, V, W):
-    return {HALS: hals_iteration, MU: mu_iteration, ANLS: anls_iteration}[algo](M, V, W)
+    return {HALS: hals_iteration, MU: mu_iteration, ANLS: anls_iteration,
+            KL: kl_iteration}[algo](M, V, W)
 
 
 # ---------------------------------------------------------------------------
@@ -692,7 +761,7 @@ def solve(M, h: int, w: int, r: int, levels: int, algo: int, cycle: int, xfer: i
     def one(d, low=False):
         nonlocal V, W
         V, W = iteration_bf16(algo, Ms[d], V, W, Mbs[d]) if low else iteration(algo, Ms[d], V, W)
-        e = rel_err(Ms[d], V, W)
+        e = rel_kl(Ms[d], V, W) if algo == KL else rel_err(Ms[d], V, W)
         res.log.append((d, e))
         res.total_iters += 1
         res.fine_equiv += (8.0 if two_sided else 4.0) ** (-d)
