@@ -51,7 +51,14 @@ enum {
                               error)                                                 */
 };
 
-enum { NMF_HALS = 0, NMF_MU = 1, NMF_ANLS = 2 };          /* Alg. 3, Alg. 2, Alg. 1 */
+/* Alg. 3, Alg. 2, Alg. 1; NMF_KL: the generalized Kullback-Leibler divergence
+ * D(M | VW) = sum M log(M/(VW)) - M + VW (Section 7.1 lists other objective
+ * functions as an extension) minimised by the Lee-Seung multiplicative
+ * updates V <- V o [(M/VW) W^T] / [1 W^T], W <- W o [V^T (M/VW)] / [V^T 1]
+ * on the same hierarchy and schedule; (VW)_ij = 0 gives the ratio 0, a zero
+ * denominator keeps the entry.  Its logged error (and the tolerance) is
+ * D(M_l | VW) / sum(M_l).  FP32, one-sided, single solves. */
+enum { NMF_HALS = 0, NMF_MU = 1, NMF_ANLS = 2, NMF_KL = 3 };
 /* Alg. 4, Alg. 5, Alg. 6; NMF_WC: W-cycle (Section 7.1 lists other cycles as
  * future work): the V-cycle's split of the budget t (t/4 before descending,
  * t/2 after) with the coarse quarter spent in two consecutive W-cycles of t/8
@@ -73,7 +80,7 @@ typedef struct {
     int32_t h, w;          /* finest image grid                                     */
     int32_t r;             /* rank, 1..64                                           */
     int32_t levels;        /* >= 1 (1 = plain single-level NMF)                     */
-    int32_t algo;          /* NMF_HALS / NMF_MU / NMF_ANLS                          */
+    int32_t algo;          /* NMF_HALS / NMF_MU / NMF_ANLS / NMF_KL                 */
     int32_t cycle;         /* NMF_NI / NMF_VC / NMF_FMG / NMF_WC                    */
     int32_t xfer;          /* NMF_XFER_FW / NMF_XFER_BLOCK2                         */
     int32_t prec;          /* NMF_FP32 / NMF_BF16                                   */
@@ -210,13 +217,15 @@ nmf_status nmf_gram(int32_t r, int64_t L, const float *dX, int64_t ldx, double *
 /* ---- kernel timing (HIP events on the solve's stream) ---------------------
  * Kernel kinds: 0 A-pass (M W^T + V update), 1 Gram V^T V, 2 C-pass partials
  * (V^T M), 3 C-pass reduction + W update, 4 Gram W W^T, 5 residual, 6 NNLS
- * rows of V, 7 NNLS columns of W, 8 restriction, 9 prolongation, 10 ||M||^2.
+ * rows of V, 7 NNLS columns of W, 8 restriction, 9 prolongation, 10 ||M||^2
+ * (and sum(M) for NMF_KL), 11 KL divergence partials.  For NMF_KL kind 0 is
+ * the V pass, 2 the W pass, 3 the W update and 5 the logged divergence.
  * With bit k of `mask` set, every launch of kind k by later nmf_solve /
  * nmf_iterate calls on this plan is bracketed by two hipEventRecord calls on
  * the call's stream; the elapsed times are summed when the call synchronises
  * at its end.  nmf_profile_read copies the per-kind launch counts and total
  * milliseconds (cap entries) and, if reset != 0, clears them. */
-#define NMF_NUM_KERNEL_KINDS 11
+#define NMF_NUM_KERNEL_KINDS 12
 nmf_status nmf_profile(nmf_plan_t plan, uint32_t mask);
 nmf_status nmf_profile_read(nmf_plan_t plan, int64_t *counts, double *total_ms, int32_t cap,
                             int32_t reset);

@@ -21,12 +21,12 @@ import numpy as np
 HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libnmf.so")
 
-HALS, MU, ANLS = 0, 1, 2
+HALS, MU, ANLS, KL = 0, 1, 2, 3
 NI, VC, FMG, WC = 0, 1, 2, 3
 XFER_FW, XFER_BLOCK2 = 0, 1
 FP32, BF16 = 0, 1
 
-ALGOS = {"hals": HALS, "mu": MU, "anls": ANLS}
+ALGOS = {"hals": HALS, "mu": MU, "anls": ANLS, "kl": KL}
 CYCLES = {"ni": NI, "vc": VC, "fmg": FMG, "wc": WC}
 XFERS = {"fw": XFER_FW, "block2": XFER_BLOCK2}
 PRECS = {"fp32": FP32, "bf16": BF16}
@@ -51,7 +51,7 @@ STATIC_WORKSPACE_BYTES = 32 << 20     # NMF_STATIC_WORKSPACE_BYTES (include/nmf.
 
 # Kernel kinds of the event profiler (include/nmf.h).
 KERNEL_KINDS = ["apass", "gram_v", "cpass_partial", "cpass_final", "gram_w", "residual",
-                "nnls_rows", "nnls_cols", "restrict", "prolong", "sumsq"]
+                "nnls_rows", "nnls_cols", "restrict", "prolong", "sumsq", "kl_div"]
 
 
 class NmfError(RuntimeError):

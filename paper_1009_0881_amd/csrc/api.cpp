@@ -120,6 +120,13 @@ Ctx make_ctx(nmf_plan_t plan, const float *dM, float *dV, float *dW, void *dws, 
     c.Wt = at<float>(c.ws, p.ws.off_Wt);
     c.A = p.ws.off_A ? at<double>(c.ws, p.ws.off_A) : nullptr;
     c.C = p.ws.off_C ? at<double>(c.ws, p.ws.off_C) : nullptr;
+    if (p.d.algo == NMF_KL) {
+        c.klw = at<double>(c.ws, p.ws.off_klw);
+        c.klwp = at<double>(c.ws, p.ws.off_klwp);
+        c.klvp = at<double>(c.ws, p.ws.off_klvp);
+        c.kld = at<double>(c.ws, p.ws.off_kld);
+        c.klm = at<double>(c.ws, p.ws.off_klm);
+    }
     for (size_t l = 0; l < p.lv.size(); ++l) {
         if (l == 0) {
             c.M.push_back(dM);
@@ -298,6 +305,12 @@ nmf_status gram_W(Ctx &c, int d) {
 nmf_status init_w(Ctx &c, int d = 0) {
     nmf_plan_t plan = c.plan;
     const Job &J = c.jobs[d];
+    if (c.p->d.algo == NMF_KL) {   // Wt and the row sums of W
+        NMF_LAUNCH(K_CFINAL, launch_kl_wfinal(J.rpad, J.n, J.r, 0, nullptr, nullptr, c.Wl[d],
+                                              c.Wt, c.klwp, true, c.stop, c.s));
+        NMF_LAUNCH(K_CFINAL, launch_kl_wsum(J.rpad, J.n, c.klwp, c.klw, c.stop, c.s));
+        return NMF_OK;
+    }
     NMF_LAUNCH(K_GRAM_W, launch_cfinal_jobs(3, J.rpad, J.cf, c.djobs + d, nullptr, J.nFb,
                                             cfinal_lds_bytes(J.rpad, 3, J.cf), c.s));
     NMF_LAUNCH(K_GRAM_W, launch_gram_w_jobs(0, c.djobs + d, nullptr, J.nG, c.s));
@@ -328,6 +341,23 @@ nmf_status sweep(Ctx &c, int d, bool fp32 = false) {
     const int ji = fp32 ? (int)p.lv.size() : d;
     const Job &J = c.jobs[ji];
     const Job *dj = c.djobs + ji;
+    if (p.d.algo == NMF_KL) {   // KL divergence: V pass, W pass, W update, divergence, log
+        const LevelInfo &li = p.lv[d];
+        NMF_LAUNCH(K_APASS, launch_kl_vpass(J.rpad, J.M, J.ldm, J.m, J.n, J.r, J.V, J.W, c.Wt,
+                                            c.klw, c.stop, c.s));
+        NMF_LAUNCH(K_CPART, launch_kl_wpass(J.rpad, J.M, J.ldm, J.m, J.n, J.r, J.V, J.W,
+                                            li.cp_chunks, li.cp_chunk, c.Cp, c.klvp, c.stop,
+                                            c.s));
+        NMF_LAUNCH(K_CFINAL, launch_kl_wfinal(J.rpad, J.n, J.r, li.cp_chunks, c.Cp, c.klvp, J.W,
+                                              c.Wt, c.klwp, false, c.stop, c.s));
+        NMF_LAUNCH(K_KL_DIV, launch_kl_div(J.rpad, J.M, J.ldm, J.m, J.n, J.r, J.V, J.W, c.kld,
+                                           c.stop, c.s));
+        NMF_LAUNCH(K_RESID, launch_kl_log(J.m, J.n, J.rpad, c.kld, c.klwp, c.klw, c.klm, d,
+                                          c.log_rel, c.log_depth, p.d.log_cap, c.st,
+                                          c.jobs[0].hstop, p.d.tol, c.s));
+        c.depths.push_back((int8_t)d);
+        return NMF_OK;
+    }
     const bool bf = J.prec == 1;
     const int r = p.d.r;
     const int64_t n = J.n;
@@ -397,6 +427,10 @@ nmf_status prepare_levels(Ctx &c) {
         NMF_LAUNCH(K_SUMSQ, launch_sumsq(c.M[l], c.ldm[l], p.lv[l].m, p.lv[l].n,
                                          c.nparts + l * kNormParts,
                                          norm_parts(p.lv[l].m, p.lv[l].n), c.norm + l, c.s));
+        if (p.d.algo == NMF_KL)   // sum(M_l), the scale of the logged divergence
+            NMF_LAUNCH(K_SUMSQ, launch_msum(c.M[l], c.ldm[l], p.lv[l].m, p.lv[l].n,
+                                            c.nparts + l * kNormParts,
+                                            norm_parts(p.lv[l].m, p.lv[l].n), c.klm + l, c.s));
     }
     return NMF_OK;
 }

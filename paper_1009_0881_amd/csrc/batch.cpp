@@ -118,8 +118,9 @@ int Executor::slot_of(int id) const {
 nmf_status Executor::add(nmf_plan_t plan, const float *dM, float *dV, float *dW, int32_t iters,
                          void *dws, int id) {
     const Plan &p = plan->p;
-    if (p.d.algo == NMF_ANLS)
-        return fail(plan, NMF_E_ARG, "batched solves support HALS and MU (ANLS: use nmf_solve)");
+    if (p.d.algo == NMF_ANLS || p.d.algo == NMF_KL)
+        return fail(plan, NMF_E_ARG,
+                    "batched solves support HALS and MU (ANLS, KL: use nmf_solve)");
     if (p.d.two_sided)
         return fail(plan, NMF_E_ARG, "two-sided hierarchies run as single solves (nmf_solve)");
     if ((int)insts_.size() >= capacity_) return fail(plan, NMF_E_BUSY, "batch capacity reached");

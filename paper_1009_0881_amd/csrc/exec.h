@@ -39,6 +39,9 @@ struct Ctx {
     float *Bf, *Df, *Wt;
     double *A, *C;                // ANLS: FP64 products M W^T and V^T M
     double *Cp, *Dp;
+    // NMF_KL: row sums of W and their block partials, column sums of V per
+    // chunk, divergence partials, sum(M_l) per level (null otherwise)
+    double *klw = nullptr, *klwp = nullptr, *klvp = nullptr, *kld = nullptr, *klm = nullptr;
     std::vector<const float *> M;
     std::vector<int64_t> ldm;
     std::vector<float *> V;

@@ -80,6 +80,10 @@ struct Workspace {
     size_t off_gparts, off_cparts, off_rparts, off_A, off_C, off_Wb;
     size_t off_Wt, off_Dp, off_jobs;
     size_t off_tmpM;     // two-sided: R_m M_l before the column restriction
+    // NMF_KL: row sums of W (rpad), their block partials, the column sums of V
+    // per chunk, the divergence partials (16-row blocks of the finest level)
+    // and sum(M_l) per level
+    size_t off_klw, off_klwp, off_klvp, off_kld, off_klm;
     size_t gparts_cap;   // doubles
     size_t rparts_cap;   // doubles
     size_t total;
@@ -87,7 +91,7 @@ struct Workspace {
 
 enum KernelKind {
     K_APASS = 0, K_GRAM_V, K_CPART, K_CFINAL, K_GRAM_W, K_RESID, K_NNLS_ROWS, K_NNLS_COLS,
-    K_RESTRICT, K_PROLONG, K_SUMSQ, K_NUM_KINDS
+    K_RESTRICT, K_PROLONG, K_SUMSQ, K_KL_DIV, K_NUM_KINDS
 };
 
 // Host-mapped stop flags and completion events for tolerance polling: a solve
@@ -271,5 +275,29 @@ hipError_t launch_nnls_cols(int rpad, const double *Gd, const double *C, int64_t
                             float *W, float *Wt, double *rparts, int32_t *flags,
                             const int32_t *stop, hipStream_t s);
 int nnls_cols_blocks(int64_t n);
+
+// KL divergence (kl.hip): the kernels of one iteration and the set-up ones.
+int kl_row_blocks(int64_t m);
+int kl_col_blocks(int64_t n);
+hipError_t launch_kl_vpass(int rpad, const float *M, int64_t ldm, int64_t m, int64_t n, int r,
+                           float *V, const float *W, const float *Wt, const double *wsum,
+                           const int32_t *stop, hipStream_t s);
+hipError_t launch_kl_wpass(int rpad, const float *M, int64_t ldm, int64_t m, int64_t n, int r,
+                           const float *V, const float *W, int chunks, int64_t chunk, double *Cp,
+                           double *vparts, const int32_t *stop, hipStream_t s);
+hipError_t launch_kl_wfinal(int rpad, int64_t n, int r, int chunks, const double *Cp,
+                            const double *vparts, float *W, float *Wt, double *wparts, bool init,
+                            const int32_t *stop, hipStream_t s);
+hipError_t launch_kl_wsum(int rpad, int64_t n, const double *wparts, double *wsum,
+                          const int32_t *stop, hipStream_t s);
+hipError_t launch_kl_div(int rpad, const float *M, int64_t ldm, int64_t m, int64_t n, int r,
+                         const float *V, const float *W, double *dparts, const int32_t *stop,
+                         hipStream_t s);
+hipError_t launch_kl_log(int64_t m, int64_t n, int rpad, const double *dparts,
+                         const double *wparts, double *wsum, const double *msum, int depth,
+                         double *log_rel, int32_t *log_depth, int log_cap, DevState *st,
+                         int32_t *hstop, double tol, hipStream_t s);
+hipError_t launch_msum(const float *M, int64_t ldm, int64_t m, int64_t n, double *parts,
+                       int nparts, double *out, hipStream_t s);
 
 }  // namespace nmf

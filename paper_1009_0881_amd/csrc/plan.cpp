@@ -96,7 +96,7 @@ std::vector<Step> make_schedule(int cycle, int levels, int64_t iters, int ratio)
 nmf_status build_plan(const nmf_desc &d0, Plan &p, std::string &err) {
     nmf_desc d = d0;
     char buf[256];
-    if (d.algo < NMF_HALS || d.algo > NMF_ANLS || d.cycle < NMF_NI || d.cycle > NMF_WC ||
+    if (d.algo < NMF_HALS || d.algo > NMF_KL || d.cycle < NMF_NI || d.cycle > NMF_WC ||
         d.xfer < NMF_XFER_FW || d.xfer > NMF_XFER_BLOCK2 || d.prec < NMF_FP32 || d.prec > NMF_BF16) {
         err = "unknown algo / cycle / xfer / prec value";
         return NMF_E_ARG;
@@ -110,6 +110,10 @@ nmf_status build_plan(const nmf_desc &d0, Plan &p, std::string &err) {
     }
     if (d.prec == NMF_BF16 && d.algo == NMF_ANLS) {
         err = "BF16 precision is available for HALS and MU";
+        return NMF_E_ARG;
+    }
+    if (d.algo == NMF_KL && (d.prec != NMF_FP32 || d.two_sided != 0)) {
+        err = "the KL objective runs in FP32 on one-sided hierarchies";
         return NMF_E_ARG;
     }
     if (d.two_sided != 0 && d.two_sided != 1) {
@@ -208,7 +212,7 @@ nmf_status build_plan(const nmf_desc &d0, Plan &p, std::string &err) {
         // FP32 streaming C-pass (large levels): about two blocks per CU
         // wide coarse levels stream only in plans whose finest level does
         // (plans that never stream give the same bits alone and in a batch)
-        li.fstream = d.algo != NMF_ANLS && li.m % 4 == 0 &&
+        li.fstream = (d.algo == NMF_HALS || d.algo == NMF_MU) && li.m % 4 == 0 &&
                      (li.m >= kFStreamMinRows ||
                       (p.lv[0].m >= kFStreamMinRows && li.m >= kFStreamWideRows &&
                        li.n >= kFStreamWideCols));
@@ -279,6 +283,15 @@ nmf_status build_plan(const nmf_desc &d0, Plan &p, std::string &err) {
     ws.off_Dd = take(sizeof(double) * rr);
     ws.off_Bf = take(sizeof(float) * rr);
     ws.off_Df = take(sizeof(float) * rr);
+    if (d.algo == NMF_KL) {
+        ws.off_klw = take(sizeof(double) * p.rpad);
+        ws.off_klwp = take(sizeof(double) * p.rpad * (size_t)kl_col_blocks(d.n));
+        ws.off_klvp = take(sizeof(double) * p.rpad * max_cp);
+        ws.off_kld = take(sizeof(double) * (size_t)kl_row_blocks(d.m));
+        ws.off_klm = take(sizeof(double) * d.levels);
+    } else {
+        ws.off_klw = ws.off_klwp = ws.off_klvp = ws.off_kld = ws.off_klm = 0;
+    }
     ws.gparts_cap = max_gp * rp2;
     ws.off_gparts = take(sizeof(double) * ws.gparts_cap);
     // C-pass partials; also the split A-pass's partial rows of A (FP32

@@ -54,6 +54,9 @@ def test_status_strings():
     (dict(m=100, n=4, h=10, w=10, r=3, tile_cfg=(1 | 16 << 8 | 1 << 16)), -1),
     (dict(m=256, n=40, h=16, w=16, r=3, levels=2, two_sided=True, prec="bf16"), -1),
     (dict(m=256, n=2, h=16, w=16, r=1, levels=3, two_sided=True), -2),   # 2 -> 1 column, then 1
+    (dict(m=256, n=40, h=16, w=16, r=3, levels=2, algo="kl", prec="bf16"), -1),   # KL: FP32
+    (dict(m=256, n=40, h=16, w=16, r=3, levels=2, algo="kl", two_sided=True), -1),  # one-sided
+    (dict(m=100, n=4, h=10, w=10, r=3, algo=4), -1),     # past NMF_KL
 ])
 def test_plan_rejects_bad_descriptions(kw, status):
     with pytest.raises(P.NmfError) as e:
