@@ -16,9 +16,11 @@
 
 namespace nmf {
 // Launch-size helpers the planner sizes partial buffers with; the real ones
-// live beside the kernels.  The same formulas: one block per 4 columns, and
-// the NNLS column launch capped at 1024 blocks.
+// live beside the kernels.  The same formulas: one block per 4 columns, the
+// NNLS column launch capped at 1024 blocks, KL blocks of 16 rows / 64 columns.
 int cpass_final_blocks(int64_t n) { return (int)((n + 3) / 4); }
+int kl_row_blocks(int64_t m) { return (int)((m + 15) / 16); }
+int kl_col_blocks(int64_t n) { return (int)((n + 63) / 64); }
 int nnls_cols_blocks(int64_t n) {
     int64_t b = (n + 3) / 4;
     return (int)(b > 1024 ? 1024 : (b < 1 ? 1 : b));
@@ -59,11 +61,12 @@ int main() {
         int deep = 1;   // levels the grid allows: every restricted side >= 2
         for (int s = d.h < d.w ? d.h : d.w; s >= 2 && deep < 12; s = (s + 1) / 2) ++deep;
         d.levels = (int32_t)pick(1, deep - 1 > 1 ? deep - 1 : 1);
-        d.algo = (int32_t)pick(0, 2);
+        d.algo = (int32_t)pick(0, 3);
         d.cycle = (int32_t)pick(0, 3);
         d.xfer = (int32_t)pick(0, 1);
         d.two_sided = (int32_t)(next() % 4 == 0);
-        d.prec = (int32_t)(d.algo != NMF_ANLS && !d.two_sided && next() % 3 == 0);
+        if (d.algo == NMF_KL) d.two_sided = 0;
+        d.prec = (int32_t)(d.algo < NMF_ANLS && !d.two_sided && next() % 3 == 0);
         d.tol = (next() & 1) ? 1e-2 : 0.0;
         d.refine_iters = d.prec ? (int32_t)pick(0, 4) : 0;
         d.tile_cfg = (next() % 4 == 0) ? NMF_TILE(1 << pick(0, 2), pick(0, 1) ? 16 : 4) : 0;
@@ -92,7 +95,8 @@ int main() {
         const size_t offs[] = {w.off_state, w.off_log, w.off_logdepth, w.off_norm, w.off_nparts,
                                w.off_Bd, w.off_Bf, w.off_Dd, w.off_Df, w.off_gparts,
                                w.off_cparts, w.off_rparts, w.off_A, w.off_C, w.off_Wb,
-                               w.off_Wt, w.off_Dp, w.off_jobs, w.off_tmpM};
+                               w.off_Wt, w.off_Dp, w.off_jobs, w.off_tmpM, w.off_klw,
+                               w.off_klwp, w.off_klvp, w.off_kld, w.off_klm};
         for (size_t o : offs) check(o <= w.total, "workspace region past the end", d);
         check((int)p.lv.size() == d.levels, "level count", d);
         for (size_t l = 0; l < p.lv.size(); ++l) {
