@@ -15,8 +15,8 @@
 //                the next V pass
 //
 // Products P, Q W^T and V^T Q run on v_mfma_f32_16x16x4f32 in FP32; the
-// update factors, the cross-wave and cross-chunk sums and the divergence are
-// FP64.  A zero denominator keeps the entry.  Every sum has a fixed order.
+// update factors and the cross-wave and cross-chunk sums are FP64; each
+// divergence term is evaluated in FP32 (kl_term) and the terms added in FP64.  A zero denominator keeps the entry.  Every sum has a fixed order.
 //
 // MFMA layouts (16x16x4, lane l = 16 lk + li): the A operand is A[li][lk], the
 // B operand B[lk][li], the result D[4 lk + v][li].  The V pass forms the
@@ -34,6 +34,31 @@ namespace {
 constexpr int kKlWaves = 4;
 
 __device__ __forceinline__ float kl_q(float mv, float p) { return p > 0.0f ? mv / p : 0.0f; }
+
+// One divergence term M log(M / P) - M + P = P phi(M / P) with
+// phi(x) = x log x - x + 1 >= 0, in FP32.  Near x = 1 the direct form cancels
+// (phi ~ (x - 1)^2 / 2), so for |u| < 1/4, u = (M - P) / P, phi is summed as
+// its series sum_{k >= 2} (-1)^k u^k / (k (k - 1)) up to k = 12 (truncation
+// below 3e-9 relative); elsewhere phi >= 0.028 and the direct form loses at
+// most a few units in the last place.  P = 0: +inf where M > 0, 0 where M = 0.
+__device__ __forceinline__ float kl_term(float mv, float p) {
+    if (!(p > 0.0f)) return mv > 0.0f ? INFINITY : 0.0f;
+    const float u = (mv - p) / p;
+    float phi;
+    if (fabsf(u) < 0.25f) {
+        constexpr float c[11] = {1.0f / 2,   -1.0f / 6,   1.0f / 12,  -1.0f / 20,
+                                 1.0f / 30,  -1.0f / 42,  1.0f / 56,  -1.0f / 72,
+                                 1.0f / 90,  -1.0f / 110, 1.0f / 132};
+        float t = c[10];
+#pragma unroll
+        for (int i = 9; i >= 0; --i) t = fmaf(t, u, c[i]);
+        phi = t * u * u;
+    } else {
+        const float x = mv / p;
+        phi = x > 0.0f ? (x * logf(x) - x) + 1.0f : 1.0f;
+    }
+    return p * phi;
+}
 
 // ---------------------------------------------------------------------------
 // V pass: block b owns rows 16 b .. 16 b + 15; its four waves split the
@@ -78,6 +103,16 @@ __global__ __launch_bounds__(256) void k_kl_vpass(const float *__restrict__ M, i
         const int64_t ja = j0 + li;
         const bool jaok = ja < c1;
         const int64_t jac = jaok ? ja : c1 - 1;
+        // the M entries of this step first: they do not depend on P
+        float mv[4];
+        gmem<const float> *wtr[4];
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+            const int64_t col = j0 + 4 * lk + v;
+            const int64_t cc = col < c1 ? col : c1 - 1;
+            mv[v] = Mg[rowc + cc * ldm];
+            wtr[v] = to_global(Wt) + cc * RPAD;
+        }
         v4f p = {0.0f, 0.0f, 0.0f, 0.0f};
 #pragma unroll
         for (int s = 0; s < NS; ++s) {
@@ -89,14 +124,8 @@ __global__ __launch_bounds__(256) void k_kl_vpass(const float *__restrict__ M, i
         // p[v] = P[row li][col j0 + 4 lk + v]; columns past the range and rows
         // past m have P = 0, hence Q = 0
         float q[4];
-        gmem<const float> *wtr[4];
 #pragma unroll
-        for (int v = 0; v < 4; ++v) {
-            const int64_t col = j0 + 4 * lk + v;
-            const int64_t cc = col < c1 ? col : c1 - 1;
-            q[v] = kl_q(Mg[rowc + cc * ldm], p[v]);
-            wtr[v] = to_global(Wt) + cc * RPAD;
-        }
+        for (int v = 0; v < 4; ++v) q[v] = kl_q(mv[v], p[v]);
         // A += Q W^T: K-step v takes Q[row li][col j0 + 4 lk + v] and
         // W[16 t + li][the same column] (its row of Wt)
 #pragma unroll
@@ -221,54 +250,64 @@ __global__ __launch_bounds__(256) void k_kl_wpass(const float *__restrict__ M, i
 }
 
 // ---------------------------------------------------------------------------
-// W update over 64 columns per block: C = sum of the chunk partials and the
-// column sums of V = sum of their partials (chunk order), W <- W o C / vsum
-// (kept where vsum = 0), Wt, and the block's partial row sums of the stored
-// new W.  init: no update (start of a solve), only Wt and the row sums.
+// W update: block (cb, kg) owns columns 64 cb .. 64 cb + 63 of the four rows
+// k = 4 kg .. 4 kg + 3 (thread: row 4 kg + tid / 64, column tid % 64).
+// C = sum of the chunk partials and the column sums of V = sum of their
+// partials, both in chunk order with the loads issued in batches of 8;
+// W <- W o C / vsum (kept where vsum = 0), Wt, and the block's partial row
+// sums of the stored new W (column order).  init: no update (start of a
+// solve), only Wt and the row sums.
 // ---------------------------------------------------------------------------
 __global__ __launch_bounds__(256) void k_kl_wfinal(int64_t n, int r, int rpad, int chunks,
                                                    const double *__restrict__ Cp,
                                                    const double *__restrict__ vparts,
                                                    float *__restrict__ W, float *__restrict__ Wt,
-                                                   double *__restrict__ wparts, int init,
+                                                   double *__restrict__ wparts, int init, int ncb,
                                                    const int32_t *stop) {
-    __shared__ double vsum[kMaxRank];
-    __shared__ double Wn[kMaxRank][65];
+    constexpr int B = 8;
+    __shared__ double vsum[4];
+    __shared__ double Wn[4][64];
     if (stopped(stop)) return;
     const int tid = threadIdx.x;
-    const int64_t j0 = (int64_t)blockIdx.x * 64;
-    if (!init && tid < rpad) {
+    const int cb = (int)(blockIdx.x % ncb), kg = (int)(blockIdx.x / ncb);
+    const int kk = tid >> 6, jj = tid & 63;
+    const int k = 4 * kg + kk;
+    const int64_t j = (int64_t)cb * 64 + jj;
+    const bool live = k < r && j < n;
+    // batched, ordered sum of `chunks` values at p, p + stride, ...
+    auto ordered_sum = [&](const double *p, int64_t stride) {
         double s = 0.0;
-        for (int c = 0; c < chunks; ++c) s += vparts[(int64_t)c * rpad + tid];
-        vsum[tid] = s;
-    }
-    __syncthreads();
-    const int jj = tid & 63;
-    const int64_t j = j0 + jj;
-    const auto Wg = to_global(W);
-    for (int k = tid >> 6; k < rpad; k += 4) {
-        double wn = 0.0;
-        if (j < n) {
-            float wf = 0.0f;
-            if (k < r) {
-                wf = Wg[(int64_t)k * n + j];
-                if (!init && vsum[k] > 0.0) {
-                    double c = 0.0;
-                    for (int cc = 0; cc < chunks; ++cc) c += Cp[((int64_t)cc * r + k) * n + j];
-                    wf = (float)((double)wf * c / vsum[k]);
-                    Wg[(int64_t)k * n + j] = wf;
-                }
-            }
-            to_global(Wt)[j * rpad + wt_pos(k, rpad / 16)] = wf;
-            wn = (double)wf;
+        for (int c0 = 0; c0 < chunks; c0 += B) {
+            double v[B];
+#pragma unroll
+            for (int u = 0; u < B; ++u)
+                v[u] = (c0 + u < chunks) ? p[(int64_t)(c0 + u) * stride] : 0.0;
+#pragma unroll
+            for (int u = 0; u < B; ++u)
+                if (c0 + u < chunks) s += v[u];
         }
-        Wn[k][jj] = wn;
-    }
+        return s;
+    };
+    if (!init && jj == 0) vsum[kk] = k < r ? ordered_sum(vparts + k, rpad) : 0.0;
+    double c = 0.0;
+    if (!init && live) c = ordered_sum(Cp + (int64_t)k * n + j, (int64_t)r * n);
     __syncthreads();
-    if (tid < rpad) {
+    const auto Wg = to_global(W);
+    float wf = 0.0f;
+    if (live) {
+        wf = Wg[(int64_t)k * n + j];
+        if (!init && vsum[kk] > 0.0) {
+            wf = (float)((double)wf * c / vsum[kk]);
+            Wg[(int64_t)k * n + j] = wf;
+        }
+    }
+    if (j < n && k < rpad) to_global(Wt)[j * rpad + wt_pos(k, rpad / 16)] = wf;
+    Wn[kk][jj] = (double)wf;
+    __syncthreads();
+    if (jj == 0 && k < rpad) {
         double s = 0.0;
-        for (int c = 0; c < 64; ++c) s += Wn[tid][c];
-        to_global(wparts)[(int64_t)blockIdx.x * rpad + tid] = s;
+        for (int c2 = 0; c2 < 64; ++c2) s += Wn[kk][c2];
+        to_global(wparts)[(int64_t)cb * rpad + k] = s;
     }
 }
 
@@ -286,8 +325,8 @@ __global__ __launch_bounds__(64) void k_kl_wsum(const double *__restrict__ wpart
 
 // ---------------------------------------------------------------------------
 // Divergence partials: the tiles of the V pass (16 rows per block, columns
-// split over the waves), sum over the block's entries of
-// M log(M / P) - M + P in FP64 (+inf where M > 0 = P).
+// split over the waves), sum over the block's entries of the terms of
+// kl_term, added in FP64.
 // ---------------------------------------------------------------------------
 template <int RT>
 __global__ __launch_bounds__(256) void k_kl_div(const float *__restrict__ M, int64_t ldm,
@@ -320,6 +359,12 @@ __global__ __launch_bounds__(256) void k_kl_div(const float *__restrict__ M, int
         const int64_t ja = j0 + li;
         const bool jaok = ja < c1;
         const int64_t jac = jaok ? ja : c1 - 1;
+        float mf[4];
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+            const int64_t col = j0 + 4 * lk + v;
+            mf[v] = Mg[rowc + (col < c1 ? col : c1 - 1) * ldm];
+        }
         v4f p = {0.0f, 0.0f, 0.0f, 0.0f};
 #pragma unroll
         for (int s = 0; s < NS; ++s) {
@@ -331,10 +376,7 @@ __global__ __launch_bounds__(256) void k_kl_div(const float *__restrict__ M, int
 #pragma unroll
         for (int v = 0; v < 4; ++v) {
             const int64_t col = j0 + 4 * lk + v;
-            const int64_t cc = col < c1 ? col : c1 - 1;
-            const double mv = (double)Mg[rowc + cc * ldm];
-            const double pv = (double)p[v];
-            if (rok && col < c1) tsum += (pv - mv) + (mv > 0.0 ? mv * log(mv / pv) : 0.0);
+            if (rok && col < c1) tsum += (double)kl_term(mf[v], p[v]);
         }
     }
     tsum = block_sum_f64<256>(tsum, red);
@@ -446,8 +488,9 @@ hipError_t launch_kl_wpass(int rpad, const float *M, int64_t ldm, int64_t m, int
 hipError_t launch_kl_wfinal(int rpad, int64_t n, int r, int chunks, const double *Cp,
                             const double *vparts, float *W, float *Wt, double *wparts, bool init,
                             const int32_t *stop, hipStream_t s) {
-    k_kl_wfinal<<<kl_col_blocks(n), 256, 0, s>>>(n, r, rpad, chunks, Cp, vparts, W, Wt, wparts,
-                                                 init ? 1 : 0, stop);
+    const int ncb = kl_col_blocks(n);
+    k_kl_wfinal<<<ncb * (rpad / 4), 256, 0, s>>>(n, r, rpad, chunks, Cp, vparts, W, Wt, wparts,
+                                                 init ? 1 : 0, ncb, stop);
     return hipGetLastError();
 }
 
