@@ -46,6 +46,16 @@ design notes):
       the logged error of an iteration is D(M_l | VW) / sum(M_l).  Where
       (VW)_ij = 0 the ratio M_ij / (VW)_ij is taken as 0; a zero denominator
       (a zero row of W or column of V) leaves the entry unchanged, as R7.
+  R18 NTF (Section 7.1: multilevel techniques for nonnegative tensor
+      factorisation): a 3-way tensor X (I x J x K) whose mode 1 is the pixel
+      index of an h x w grid, approximated by sum_r a_r o b_r o c_r with
+      A (I x R), B (J x R), C (K x R) >= 0.  One iteration updates A, then B,
+      then C, each by the HALS steps of Alg. 3 on that mode's unfolding
+      (X_(1) = A (C kr B)^T, X_(2) = B (C kr A)^T, X_(3) = C (B kr A)^T, kr
+      the Khatri-Rao product, column (j, k) of X_(1) at j + J k).  Mode 1 is
+      coarsened as the images are (X_(1) restricted by rows, A transferred as
+      V); B and C stay on every level.  The error is ||X - [[A, B, C]]||_F /
+      ||X||_F after each iteration; schedule, budget and stopping as R5, R10.
 """
 from __future__ import annotations
 
@@ -72,6 +82,8 @@ __all__ = [
     "mu_update_V", "mu_update_W", "mu_iteration",
     "nnls_gram", "nnls_bpp", "anls_update_V", "anls_update_W", "anls_iteration",
     "kl_ratio", "kl_divergence", "rel_kl", "kl_update_V", "kl_update_W", "kl_iteration",
+    "khatri_rao", "unfold", "fold1", "cp_tensor", "ntf_iteration", "ntf_rel_err", "solve_ntf",
+    "NtfResult",
     "iteration", "bf16_round", "hals_update_V_bf16", "hals_update_W_bf16",
     "mu_iteration_bf16", "iteration_bf16", "rel_err", "objective", "gram_form_residual2",
     "eckart_young_floor", "prolongation_bound", "solve", "SolveResult",
@@ -567,6 +579,125 @@ def kl_iteration(M, V, W):
 def iteration(algo: int, M, V, W):
     return {HALS: hals_iteration, MU: mu_iteration, ANLS: anls_iteration,
             KL: kl_iteration}[algo](M, V, W)
+
+
+# ---------------------------------------------------------------------------
+# Nonnegative tensor factorisation (Section 7.1; reading R18)
+# ---------------------------------------------------------------------------
+
+def khatri_rao(C: np.ndarray, B: np.ndarray) -> np.ndarray:
+    """Column-wise Kronecker product C kr B: row j + J k, column r holds
+    C[k, r] B[j, r] (the row order of the mode-1 unfolding's columns)."""
+    K, R = C.shape
+    J = B.shape[0]
+    return (C[:, None, :] * B[None, :, :]).reshape(K * J, R)
+
+
+def unfold(X: np.ndarray, mode: int) -> np.ndarray:
+    """Mode-n unfolding of a 3-way tensor: X_(1)[i, j + J k], X_(2)[j, i + I k],
+    X_(3)[k, i + I j] (the first remaining index fastest)."""
+    I, J, K = X.shape
+    if mode == 1:
+        return X.transpose(0, 2, 1).reshape(I, K * J)
+    if mode == 2:
+        return X.transpose(1, 2, 0).reshape(J, K * I)
+    return X.transpose(2, 1, 0).reshape(K, J * I)
+
+
+def fold1(X1: np.ndarray, J: int, K: int) -> np.ndarray:
+    """Inverse of unfold(., 1): the tensor from its mode-1 unfolding."""
+    I = X1.shape[0]
+    return X1.reshape(I, K, J).transpose(0, 2, 1)
+
+
+def cp_tensor(A: np.ndarray, B: np.ndarray, C: np.ndarray) -> np.ndarray:
+    """[[A, B, C]] = sum_r a_r o b_r o c_r."""
+    return np.einsum("ir,jr,kr->ijk", A, B, C)
+
+
+def ntf_iteration(X: np.ndarray, A, B, C):
+    """One HALS-NTF iteration (R18): each factor in turn takes the HALS steps
+    of Alg. 3 on its unfolding, with the Khatri-Rao product of the other two
+    (already updated ones included) as the fixed factor."""
+    A = hals_update_V(unfold(X, 1), A, khatri_rao(C, B).T)
+    B = hals_update_V(unfold(X, 2), B, khatri_rao(C, A).T)
+    C = hals_update_V(unfold(X, 3), C, khatri_rao(B, A).T)
+    return A, B, C
+
+
+def ntf_rel_err(X: np.ndarray, A, B, C) -> float:
+    """||X - [[A, B, C]]||_F / ||X||_F, evaluated directly."""
+    X = np.asarray(X, dtype=np.float64)
+    return float(np.linalg.norm(X - cp_tensor(A, B, C)) / np.linalg.norm(X))
+
+
+class NtfResult:
+    def __init__(self):
+        self.A = self.B = self.C = None
+        self.log: List[Tuple[int, float]] = []
+        self.stopped = False
+        self.fine_iters = 0
+        self.total_iters = 0
+        self.fine_equiv = 0.0
+
+
+def solve_ntf(X, h: int, w: int, r: int, levels: int, cycle: int, xfer: int, T, A0, B0, C0,
+              tol: float = 0.0, max_fine_iters: int = 0, callback=None) -> NtfResult:
+    """Multilevel HALS-NTF (R18): the hierarchy, schedule and stopping of
+    solve() with the tensor's mode 1 (the h x w grid) coarsened; A moves
+    between levels as V does, B and C are shared by all levels."""
+    X = np.asarray(X, dtype=np.float64)
+    I, J, K = X.shape
+    assert I == h * w
+    sides = level_sides(h, w, levels)
+    Xs = [X]
+    for d in range(levels - 1):
+        hd, wd = sides[d]
+        Xs.append(fold1(restrict_images(unfold(Xs[-1], 1), hd, wd, xfer), J, K))
+    A = np.asarray(A0, dtype=np.float64).copy()
+    B = np.asarray(B0, dtype=np.float64).copy()
+    C = np.asarray(C0, dtype=np.float64).copy()
+    res = NtfResult()
+    depth = 0
+
+    def one(d):
+        nonlocal A, B, C
+        A, B, C = ntf_iteration(Xs[d], A, B, C)
+        e = ntf_rel_err(Xs[d], A, B, C)
+        res.log.append((d, e))
+        res.total_iters += 1
+        res.fine_equiv += 4.0 ** (-d)
+        if d == 0:
+            res.fine_iters += 1
+        if callback is not None:
+            callback(d, A, B, C, e)
+        return e
+
+    for kind, d, count in schedule(cycle, levels, T):
+        if kind == "restrict":
+            assert depth == d
+            A = restrict_images(A, *sides[d], xfer)
+            depth = d + 1
+        elif kind == "prolong":
+            assert depth == d + 1
+            A = prolong_images(A, *sides[d], xfer)
+            depth = d
+        else:
+            assert depth == d
+            for _ in range(count):
+                if one(d) <= tol and tol > 0 and d == 0:
+                    res.stopped = True
+                    break
+        if res.stopped:
+            break
+    assert res.stopped or depth == 0
+    if tol > 0 and not res.stopped:
+        for _ in range(max_fine_iters):
+            if one(0) <= tol:
+                res.stopped = True
+                break
+    res.A, res.B, res.C = A, B, C
+    return res
 
 
 # ---------------------------------------------------------------------------
