@@ -110,7 +110,16 @@ typedef struct {
                               8^d iterations per finest-iteration equivalent.  FP32
                               single solves only (not with NMF_BF16, not batched or
                               served); every restricted column count must be >= 2. */
-    int32_t reserved;      /* 0                                                     */
+    int32_t ntf_k;         /* 0: matrix NMF.  K > 0: nonnegative tensor factorisation
+                              (Section 7.1 proposes the multilevel technique for NTF):
+                              M is the mode-1 unfolding of an I x J x K tensor X, I = m
+                              = h*w pixels, n = J*K, column j + J k holding X[:, j, k];
+                              X ~ sum_r a_r o b_r o c_r is fitted by the HALS steps of
+                              Alg. 3 on each mode's unfolding in turn (A, then B, then
+                              C); mode 1 is coarsened as the images are and A moves
+                              between levels as V does.  Solved by nmf_ntf_solve.
+                              HALS, FP32, one-sided; n must be a multiple of K and
+                              K <= 16384.                                          */
 } nmf_desc;
 
 typedef struct {
@@ -162,6 +171,18 @@ nmf_status nmf_destroy(nmf_plan_t plan);
 #define NMF_STATIC_WORKSPACE_BYTES (32u << 20)
 nmf_status nmf_solve_static(nmf_plan_t plan, const float *dM, float *dV, float *dW,
                             int32_t iters, void *stream, nmf_result *hOut);
+
+/* Multilevel NTF (plan with ntf_k = K > 0; Section 7.1).  dX: the mode-1
+ * unfolding (m x J*K column-major, column stride ldm, column j + J k holding
+ * X[:, j, k]); dA: m x r column-major (the V of a matrix solve); dBt: B^T,
+ * r x J row-major; dCt: C^T, r x K row-major; all three updated in place.
+ * Schedule, budget, tolerance (on ||X - [[A, B, C]]||_F / ||X||_F, logged per
+ * iteration) and the result are those of nmf_solve.  The workspace holds,
+ * besides the matrix solve's buffers, the Khatri-Rao product (C kr B)^T and
+ * A^T X_(1).  Errors as nmf_solve; NMF_E_ARG for a plan without ntf_k.
+ * nmf_solve, nmf_solve_static and nmf_iterate reject NTF plans. */
+nmf_status nmf_ntf_solve(nmf_plan_t plan, const float *dX, float *dA, float *dBt, float *dCt,
+                         int32_t iters, void *dWorkspace, void *stream, nmf_result *hOut);
 
 const char *nmf_status_string(nmf_status s);
 const char *nmf_last_error(nmf_plan_t plan);
@@ -218,14 +239,15 @@ nmf_status nmf_gram(int32_t r, int64_t L, const float *dX, int64_t ldx, double *
  * Kernel kinds: 0 A-pass (M W^T + V update), 1 Gram V^T V, 2 C-pass partials
  * (V^T M), 3 C-pass reduction + W update, 4 Gram W W^T, 5 residual, 6 NNLS
  * rows of V, 7 NNLS columns of W, 8 restriction, 9 prolongation, 10 ||M||^2
- * (and sum(M) for NMF_KL), 11 KL divergence partials.  For NMF_KL kind 0 is
+ * (and sum(M) for NMF_KL), 11 KL divergence partials, 12 NTF mode updates,
+ * factor Grams and Khatri-Rao products.  For NMF_KL kind 0 is
  * the V pass, 2 the W pass, 3 the W update and 5 the logged divergence.
  * With bit k of `mask` set, every launch of kind k by later nmf_solve /
  * nmf_iterate calls on this plan is bracketed by two hipEventRecord calls on
  * the call's stream; the elapsed times are summed when the call synchronises
  * at its end.  nmf_profile_read copies the per-kind launch counts and total
  * milliseconds (cap entries) and, if reset != 0, clears them. */
-#define NMF_NUM_KERNEL_KINDS 12
+#define NMF_NUM_KERNEL_KINDS 13
 nmf_status nmf_profile(nmf_plan_t plan, uint32_t mask);
 nmf_status nmf_profile_read(nmf_plan_t plan, int64_t *counts, double *total_ms, int32_t cap,
                             int32_t reset);

@@ -43,7 +43,7 @@ EXPORTS = [
     "nmf_restrict", "nmf_prolong", "nmf_iterate", "nmf_products", "nmf_gram",
     "nmf_profile", "nmf_profile_read", "nmf_batch_workspace", "nmf_solve_batch",
     "nmf_server_create", "nmf_server_submit", "nmf_server_poll", "nmf_server_stats",
-    "nmf_server_destroy", "nmf_solve_static",
+    "nmf_server_destroy", "nmf_solve_static", "nmf_ntf_solve",
 ]
 
 BATCH_GRAPH = 1
@@ -51,7 +51,7 @@ STATIC_WORKSPACE_BYTES = 32 << 20     # NMF_STATIC_WORKSPACE_BYTES (include/nmf.
 
 # Kernel kinds of the event profiler (include/nmf.h).
 KERNEL_KINDS = ["apass", "gram_v", "cpass_partial", "cpass_final", "gram_w", "residual",
-                "nnls_rows", "nnls_cols", "restrict", "prolong", "sumsq", "kl_div"]
+                "nnls_rows", "nnls_cols", "restrict", "prolong", "sumsq", "kl_div", "ntf"]
 
 
 class NmfError(RuntimeError):
@@ -69,7 +69,7 @@ class Desc(ctypes.Structure):
         ("max_fine_iters", ctypes.c_int32), ("check_every", ctypes.c_int32),
         ("log_cap", ctypes.c_int32), ("check_input", ctypes.c_int32),
         ("tile_cfg", ctypes.c_int32), ("tol", ctypes.c_double),
-        ("two_sided", ctypes.c_int32), ("reserved", ctypes.c_int32),
+        ("two_sided", ctypes.c_int32), ("ntf_k", ctypes.c_int32),
     ]
 
 
@@ -100,6 +100,7 @@ def lib() -> ctypes.CDLL:
         L.nmf_plan.argtypes = [ctypes.POINTER(Desc), ctypes.POINTER(vp), ctypes.POINTER(sz)]
         L.nmf_solve.argtypes = [vp, vp, vp, vp, i32, vp, vp, ctypes.POINTER(Result)]
         L.nmf_solve_static.argtypes = [vp, vp, vp, vp, i32, vp, ctypes.POINTER(Result)]
+        L.nmf_ntf_solve.argtypes = [vp, vp, vp, vp, vp, i32, vp, vp, ctypes.POINTER(Result)]
         L.nmf_destroy.argtypes = [vp]
         L.nmf_status_string.argtypes = [i32]
         L.nmf_status_string.restype = ctypes.c_char_p
@@ -170,7 +171,7 @@ def tile(wc: int, cf: int) -> int:
 
 def make_desc(m, n, h, w, r, levels=1, algo="hals", cycle="ni", xfer="fw", prec="fp32",
               tol=0.0, max_fine_iters=0, check_every=8, log_cap=4096, check_input=False,
-              refine_iters=0, ldm=0, tile_cfg=0, two_sided=False) -> Desc:
+              refine_iters=0, ldm=0, tile_cfg=0, two_sided=False, ntf_k=0) -> Desc:
     """nmf_desc from Python values (names as in include/nmf.h); tile_cfg is 0,
     an NMF_TILE value or a (wc, cf) pair."""
     d = Desc()
@@ -183,6 +184,7 @@ def make_desc(m, n, h, w, r, levels=1, algo="hals", cycle="ni", xfer="fw", prec=
     d.log_cap, d.check_input, d.refine_iters = log_cap, int(check_input), refine_iters
     d.tile_cfg = tile(*tile_cfg) if isinstance(tile_cfg, (tuple, list)) else int(tile_cfg)
     d.two_sided = int(bool(two_sided))
+    d.ntf_k = int(ntf_k)
     return d
 
 
@@ -193,9 +195,10 @@ class Plan:
                  algo="hals", cycle="ni", xfer="fw", prec="fp32", tol: float = 0.0,
                  max_fine_iters: int = 0, check_every: int = 8, log_cap: int = 4096,
                  check_input: bool = False, refine_iters: int = 0, ldm: int = 0, tile_cfg=0,
-                 two_sided: bool = False):
+                 two_sided: bool = False, ntf_k: int = 0):
         d = make_desc(m, n, h, w, r, levels, algo, cycle, xfer, prec, tol, max_fine_iters,
-                      check_every, log_cap, check_input, refine_iters, ldm, tile_cfg, two_sided)
+                      check_every, log_cap, check_input, refine_iters, ldm, tile_cfg, two_sided,
+                      ntf_k)
         self.desc = d
         self.handle = ctypes.c_void_p()
         wsb = ctypes.c_size_t()
@@ -235,6 +238,20 @@ class Plan:
         res = Result()
         _check(lib().nmf_solve(self.handle, _ptr(M), _ptr(V), _ptr(W), int(iters), _ptr(ws),
                                _stream_handle(stream), ctypes.byref(res)), self.handle)
+        out = res.as_dict()
+        out["_workspace"] = ws
+        return out
+
+    def solve_ntf(self, X, A, Bt, Ct, iters: int, workspace=None, stream=None) -> dict:
+        """NTF plan (ntf_k = K): X the mode-1 unfolding as an (n, m) float32 CUDA
+        tensor (n = J K, row j + J k holding X[:, j, k]); A (r, m); Bt (r, J);
+        Ct (r, K).  A, Bt and Ct are updated in place."""
+        _need_cuda(X, A, Bt, Ct)
+        ws = workspace if workspace is not None else self.workspace()
+        res = Result()
+        _check(lib().nmf_ntf_solve(self.handle, _ptr(X), _ptr(A), _ptr(Bt), _ptr(Ct), int(iters),
+                                   _ptr(ws), _stream_handle(stream), ctypes.byref(res)),
+               self.handle)
         out = res.as_dict()
         out["_workspace"] = ws
         return out

@@ -120,6 +120,10 @@ Ctx make_ctx(nmf_plan_t plan, const float *dM, float *dV, float *dW, void *dws, 
     c.Wt = at<float>(c.ws, p.ws.off_Wt);
     c.A = p.ws.off_A ? at<double>(c.ws, p.ws.off_A) : nullptr;
     c.C = p.ws.off_C ? at<double>(c.ws, p.ws.off_C) : nullptr;
+    if (p.d.ntf_k > 0) {
+        c.ntfGB = at<double>(c.ws, p.ws.off_ntfG);
+        c.ntfGC = c.ntfGB + (size_t)p.d.r * p.d.r;
+    }
     if (p.d.algo == NMF_KL) {
         c.klw = at<double>(c.ws, p.ws.off_klw);
         c.klwp = at<double>(c.ws, p.ws.off_klwp);
@@ -305,6 +309,14 @@ nmf_status gram_W(Ctx &c, int d) {
 nmf_status init_w(Ctx &c, int d = 0) {
     nmf_plan_t plan = c.plan;
     const Job &J = c.jobs[d];
+    if (c.p->d.ntf_k > 0) {   // B^T B, C^T C, the mode-1 Gram, the Khatri-Rao product
+        const int64_t K = c.p->d.ntf_k, Jd = J.n / K;
+        NMF_LAUNCH(K_NTF, launch_ntf_gram(c.ntfB, Jd, J.r, c.ntfGB, nullptr, nullptr, c.stop, c.s));
+        NMF_LAUNCH(K_NTF, launch_ntf_gram(c.ntfC, K, J.r, c.ntfGC, c.ntfGB, c.Bd, c.stop, c.s));
+        NMF_LAUNCH(K_NTF, launch_ntf_kr(c.ntfB, c.ntfC, Jd, K, J.r, J.rpad, c.Wl[d], c.Wt, c.stop,
+                                        c.s));
+        return NMF_OK;
+    }
     if (c.p->d.algo == NMF_KL) {   // Wt and the row sums of W
         NMF_LAUNCH(K_CFINAL, launch_kl_wfinal(J.rpad, J.n, J.r, 0, nullptr, nullptr, c.Wl[d],
                                               c.Wt, c.klwp, true, c.stop, c.s));
@@ -341,6 +353,38 @@ nmf_status sweep(Ctx &c, int d, bool fp32 = false) {
     const int ji = fp32 ? (int)p.lv.size() : d;
     const Job &J = c.jobs[ji];
     const Job *dj = c.djobs + ji;
+    if (p.d.ntf_k > 0) {   // NTF: mode 1 on the matrix kernels, then modes 2 and 3
+        const int r = p.d.r;
+        const int64_t n = J.n, K = p.d.ntf_k, Jd = n / K;
+        NMF_LAUNCH(K_APASS, launch_apass_jobs(0, J.rpad, J.tm, dj, nullptr,
+                                              apass_grid_single(J.nA),
+                                              apass_lds_bytes(J.rpad, J.tm, 0), c.s, false));
+        NMF_LAUNCH(K_CPART, launch_cpass_jobs(J.rpad, J.wc, dj, nullptr,
+                                              cpass_grid_single(J.nCx, J.chunks), c.s, false));
+        NMF_LAUNCH(K_GRAM_V, launch_reduce_jobs(dj, nullptr, J.nG, c.s));
+        // Y = A^T X_(1) (FP64, J.Cd) by the product-store mode of the W-update kernel
+        NMF_LAUNCH(K_CFINAL, launch_cfinal_jobs(2, J.rpad, J.cf, dj, nullptr, J.nFb,
+                                                cfinal_lds_bytes(J.rpad, 2, J.cf), c.s));
+        // B: rows j, a_j[s] = sum_k Y[s, j + J k] C[k, s], Gram D o C^T C
+        NMF_LAUNCH(K_NTF, launch_ntf_mode(J.rpad, c.C, n, c.Dd, c.ntfGC, c.ntfB, Jd, c.ntfC, K,
+                                          1, Jd, r, nullptr, c.stop, c.s));
+        NMF_LAUNCH(K_NTF, launch_ntf_gram(c.ntfB, Jd, r, c.ntfGB, nullptr, nullptr, c.stop, c.s));
+        // C: rows k, a_k[s] = sum_j Y[s, j + J k] B[j, s], Gram D o B^T B; residual partials
+        NMF_LAUNCH(K_NTF, launch_ntf_mode(J.rpad, c.C, n, c.Dd, c.ntfGB, c.ntfC, K, c.ntfB, Jd,
+                                          Jd, 1, r, c.rparts, c.stop, c.s));
+        // C^T C and the mode-1 Gram (B^T B) o (C^T C) of the new B and C (the Gram of
+        // their exact Khatri-Rao product, FP64) into Bd: the residual's last term
+        // (with D) and the Gram of the next A-pass
+        NMF_LAUNCH(K_NTF, launch_ntf_gram(c.ntfC, K, r, c.ntfGC, c.ntfGB, c.Bd, c.stop, c.s));
+        NMF_LAUNCH(K_RESID, launch_residual(c.rparts, ntf_mode_blocks(K), c.Dd, c.Bd, r, c.norm,
+                                            d, c.log_rel, c.log_depth, p.d.log_cap, c.st,
+                                            c.jobs[0].hstop, p.d.tol, c.s));
+        // the Khatri-Rao product of the new B and C for the next A-pass
+        NMF_LAUNCH(K_NTF, launch_ntf_kr(c.ntfB, c.ntfC, Jd, K, r, J.rpad, J.W, c.Wt, c.stop,
+                                        c.s));
+        c.depths.push_back((int8_t)d);
+        return NMF_OK;
+    }
     if (p.d.algo == NMF_KL) {   // KL divergence: V pass, W pass, W update, divergence, log
         const LevelInfo &li = p.lv[d];
         NMF_LAUNCH(K_APASS, launch_kl_vpass(J.rpad, J.M, J.ldm, J.m, J.n, J.r, J.V, J.W, c.Wt,
@@ -560,6 +604,18 @@ nmf_status nmf_solve(nmf_plan_t plan, const float *dM, float *dV, float *dW, int
                     true, true);
 }
 
+nmf_status nmf_ntf_solve(nmf_plan_t plan, const float *dX, float *dA, float *dBt, float *dCt,
+                         int32_t iters, void *dWorkspace, void *stream, nmf_result *hOut) {
+    if (!plan || !dX || !dA || !dBt || !dCt || !dWorkspace)
+        return fail(plan, NMF_E_ARG, "null plan or buffer");
+    if (iters < 0) return fail(plan, NMF_E_ARG, "iters must be >= 0");
+    if (reinterpret_cast<uintptr_t>(dWorkspace) & 255)
+        return fail(plan, NMF_E_ARG, "workspace must be 256-byte aligned");
+    if (plan->p.d.ntf_k <= 0) return fail(plan, NMF_E_ARG, "nmf_ntf_solve needs ntf_k > 0");
+    return solve_on(plan, dX, dA, nullptr, iters, dWorkspace, static_cast<hipStream_t>(stream),
+                    hOut, true, true, dBt, dCt);
+}
+
 }  // extern "C"
 
 namespace nmf {
@@ -661,9 +717,16 @@ struct Poller {
 
 nmf_status solve_on(nmf_plan_t plan, const float *dM, float *dV, float *dW, int32_t iters,
                     void *dWorkspace, hipStream_t s, nmf_result *hOut, bool profile,
-                    bool lookahead) {
+                    bool lookahead, float *dB, float *dC) {
     const Plan &p = plan->p;
+    const bool ntf = p.d.ntf_k > 0;
+    if (ntf != (dB != nullptr && dC != nullptr))
+        return fail(plan, NMF_E_ARG, ntf ? "an NTF plan (ntf_k > 0) is solved by nmf_ntf_solve"
+                                         : "nmf_ntf_solve needs a plan with ntf_k > 0");
+    if (ntf) dW = at<float>(static_cast<char *>(dWorkspace), p.ws.off_ntfW);
     Ctx c = make_ctx(plan, dM, dV, dW, dWorkspace, s);
+    c.ntfB = dB;
+    c.ntfC = dC;
     c.prof = profile;
     Poller poller(c);
     if (lookahead && p.d.tol > 0.0) poller.enable();
@@ -741,6 +804,8 @@ nmf_status nmf_iterate(nmf_plan_t plan, const float *dM, float *dV, float *dW, i
                        void *dWorkspace, void *stream, double *hRelErr) {
     if (!plan || !dM || !dV || !dW || !dWorkspace || count < 0)
         return fail(plan, NMF_E_ARG, "bad argument");
+    if (plan->p.d.ntf_k > 0)
+        return fail(plan, NMF_E_ARG, "an NTF plan (ntf_k > 0) is solved by nmf_ntf_solve");
     hipStream_t s = static_cast<hipStream_t>(stream);
     Ctx c = make_ctx(plan, dM, dV, dW, dWorkspace, s);
     NMF_HIP(launch_state_reset(c.st, s));

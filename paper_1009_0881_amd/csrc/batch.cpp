@@ -123,6 +123,8 @@ nmf_status Executor::add(nmf_plan_t plan, const float *dM, float *dV, float *dW,
                     "batched solves support HALS and MU (ANLS, KL: use nmf_solve)");
     if (p.d.two_sided)
         return fail(plan, NMF_E_ARG, "two-sided hierarchies run as single solves (nmf_solve)");
+    if (p.d.ntf_k > 0)
+        return fail(plan, NMF_E_ARG, "NTF plans run as single solves (nmf_ntf_solve)");
     if ((int)insts_.size() >= capacity_) return fail(plan, NMF_E_BUSY, "batch capacity reached");
     Inst I;
     I.id = id;

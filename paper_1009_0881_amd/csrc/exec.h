@@ -42,6 +42,10 @@ struct Ctx {
     // NMF_KL: row sums of W and their block partials, column sums of V per
     // chunk, divergence partials, sum(M_l) per level (null otherwise)
     double *klw = nullptr, *klwp = nullptr, *klvp = nullptr, *kld = nullptr, *klm = nullptr;
+    // NTF: B^T (r x J) and C^T (r x K) of the caller and the Grams B^T B,
+    // C^T C (their Hadamard product, the mode-1 Gram, lives in Bd; null otherwise)
+    float *ntfB = nullptr, *ntfC = nullptr;
+    double *ntfGB = nullptr, *ntfGC = nullptr;
     std::vector<const float *> M;
     std::vector<int64_t> ldm;
     std::vector<float *> V;
@@ -71,9 +75,11 @@ nmf_status prepare_bf16(Ctx &c);
 // lookahead: tolerance checks through a host-mapped stop flag with one batch
 // of iterations kept queued (pinned host memory and events from the plan's
 // pools); false: synchronous checks, nothing allocated.
+// NTF plans: dW is ignored (the Khatri-Rao product in the workspace serves as
+// W) and dB, dC are B^T and C^T; nullptr for matrix plans.
 nmf_status solve_on(nmf_plan_t plan, const float *dM, float *dV, float *dW, int32_t iters,
                     void *dWorkspace, hipStream_t s, nmf_result *hOut, bool profile,
-                    bool lookahead);
+                    bool lookahead, float *dB = nullptr, float *dC = nullptr);
 // Fill an nmf_result from the final device state and the host depth log.
 nmf_status result_from_state(nmf_plan_t plan, const DevState &hs,
                              const std::vector<int8_t> &depths, nmf_result *out);

@@ -84,6 +84,9 @@ struct Workspace {
     // per chunk, the divergence partials (16-row blocks of the finest level)
     // and sum(M_l) per level
     size_t off_klw, off_klwp, off_klvp, off_kld, off_klm;
+    // NTF: (C kr B)^T (r x n FP32, the W of the jobs) and the Grams B^T B,
+    // C^T C (r x r FP64 each; their Hadamard product is Bd); A^T X_(1) is off_C
+    size_t off_ntfW, off_ntfG;
     size_t gparts_cap;   // doubles
     size_t rparts_cap;   // doubles
     size_t total;
@@ -91,7 +94,7 @@ struct Workspace {
 
 enum KernelKind {
     K_APASS = 0, K_GRAM_V, K_CPART, K_CFINAL, K_GRAM_W, K_RESID, K_NNLS_ROWS, K_NNLS_COLS,
-    K_RESTRICT, K_PROLONG, K_SUMSQ, K_KL_DIV, K_NUM_KINDS
+    K_RESTRICT, K_PROLONG, K_SUMSQ, K_KL_DIV, K_NTF, K_NUM_KINDS
 };
 
 // Host-mapped stop flags and completion events for tolerance polling: a solve
@@ -299,5 +302,16 @@ hipError_t launch_kl_log(int64_t m, int64_t n, int rpad, const double *dparts,
                          int32_t *hstop, double tol, hipStream_t s);
 hipError_t launch_msum(const float *M, int64_t ldm, int64_t m, int64_t n, double *parts,
                        int nparts, double *out, hipStream_t s);
+
+// NTF (ntf.hip): mode updates of B and C, factor Grams, the Khatri-Rao product.
+int ntf_mode_blocks(int64_t rows);
+hipError_t launch_ntf_mode(int rpad, const double *Y, int64_t n, const double *D,
+                           const double *Go, float *Ft, int64_t L, const float *Ot, int64_t Lo,
+                           int64_t sa, int64_t sb, int r, double *rparts, const int32_t *stop,
+                           hipStream_t s);
+hipError_t launch_ntf_gram(const float *Ft, int64_t L, int r, double *G, const double *Hm,
+                           double *H, const int32_t *stop, hipStream_t s);
+hipError_t launch_ntf_kr(const float *Bt, const float *Ct, int64_t J, int64_t K, int r, int rpad,
+                         float *W, float *Wt, const int32_t *stop, hipStream_t s);
 
 }  // namespace nmf

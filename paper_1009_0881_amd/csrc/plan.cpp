@@ -112,6 +112,15 @@ nmf_status build_plan(const nmf_desc &d0, Plan &p, std::string &err) {
         err = "BF16 precision is available for HALS and MU";
         return NMF_E_ARG;
     }
+    if (d.ntf_k < 0 || (d.ntf_k > 0 && (d.algo != NMF_HALS || d.prec != NMF_FP32 ||
+                                         d.two_sided != 0))) {
+        err = "NTF (ntf_k > 0) runs HALS in FP32 on one-sided hierarchies";
+        return NMF_E_ARG;
+    }
+    if (d.ntf_k > 0 && (d.n % d.ntf_k != 0 || d.ntf_k > 16384)) {
+        err = "NTF: n must be a multiple of ntf_k = K, and K <= 16384";
+        return NMF_E_SHAPE;
+    }
     if (d.algo == NMF_KL && (d.prec != NMF_FP32 || d.two_sided != 0)) {
         err = "the KL objective runs in FP32 on one-sided hierarchies";
         return NMF_E_ARG;
@@ -212,7 +221,7 @@ nmf_status build_plan(const nmf_desc &d0, Plan &p, std::string &err) {
         // FP32 streaming C-pass (large levels): about two blocks per CU
         // wide coarse levels stream only in plans whose finest level does
         // (plans that never stream give the same bits alone and in a batch)
-        li.fstream = (d.algo == NMF_HALS || d.algo == NMF_MU) && li.m % 4 == 0 &&
+        li.fstream = (d.algo == NMF_HALS || d.algo == NMF_MU) && d.ntf_k == 0 && li.m % 4 == 0 &&
                      (li.m >= kFStreamMinRows ||
                       (p.lv[0].m >= kFStreamMinRows && li.m >= kFStreamWideRows &&
                        li.n >= kFStreamWideCols));
@@ -303,8 +312,17 @@ nmf_status build_plan(const nmf_desc &d0, Plan &p, std::string &err) {
     if (d.algo == NMF_ANLS) {
         ws.off_A = take(sizeof(double) * (size_t)d.m * r);   // FP64 right-hand sides
         ws.off_C = take(sizeof(double) * r * n);
+    } else if (d.ntf_k > 0) {
+        ws.off_A = 0;
+        ws.off_C = take(sizeof(double) * r * n);             // A^T X_(1)
     } else {
         ws.off_A = ws.off_C = 0;
+    }
+    if (d.ntf_k > 0) {
+        ws.off_ntfW = take(sizeof(float) * r * n);
+        ws.off_ntfG = take(sizeof(double) * 3 * rr);
+    } else {
+        ws.off_ntfW = ws.off_ntfG = 0;
     }
     size_t tmp_elems = 0;
     for (size_t l = 1; l < p.lv.size(); ++l) {

@@ -274,8 +274,8 @@ nmf_status nmf_server_submit(nmf_server *S, const nmf_desc *desc, const float *h
                              uint64_t *ticket) {
     if (!S || !desc || !hM || !hV0 || !hW0 || !ticket || iters < 0)
         return fail(nullptr, NMF_E_ARG, "bad argument");
-    if (desc->algo == NMF_ANLS || desc->algo == NMF_KL)
-        return fail(nullptr, NMF_E_ARG, "the server runs HALS and MU");
+    if (desc->algo == NMF_ANLS || desc->algo == NMF_KL || desc->ntf_k != 0)
+        return fail(nullptr, NMF_E_ARG, "the server runs HALS and MU matrix solves");
     if (desc->ldm != 0 && desc->ldm != desc->m)
         return fail(nullptr, NMF_E_ARG, "server requests take contiguous columns (ldm = m)");
     nmf_plan_t plan = nullptr;

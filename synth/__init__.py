@@ -162,6 +162,62 @@ def make_spectral_instance(spec: SpectralSpec, seed: int) -> Instance:
     return Instance(spec=blob, seed=seed, M=M32, V0=V0, W0=W0, eps_E=eps, Vstar=Vs, Wstar=Ws)
 
 
+@dataclasses.dataclass(frozen=True)
+class TensorSpec:
+    """Video-like 3-way data for NTF: r blob images (as in BlobSpec, mode 1 the
+    h x w pixels) times r nonnegative profiles over J and over K (uniform in
+    [0, 1]), plus |N(0, noise_std^2)| noise."""
+    h: int
+    w: int
+    J: int
+    K: int
+    r: int
+    sig_lo: float
+    sig_hi: float
+    noise_std: float = 0.01
+
+    @property
+    def m(self) -> int:
+        return self.h * self.w
+
+
+# 56x46 pixels, 20 x 20 other modes, rank 12
+CFG_TENSOR = TensorSpec(h=56, w=46, J=20, K=20, r=12, sig_lo=2.0, sig_hi=8.0)
+
+
+@dataclasses.dataclass
+class TensorInstance:
+    spec: TensorSpec
+    seed: int
+    X1: np.ndarray        # (m, J K) float32 Fortran: the mode-1 unfolding, column j + J k
+    A0: np.ndarray        # (m, r) float32 Fortran
+    Bt0: np.ndarray       # (r, J) float32 C
+    Ct0: np.ndarray       # (r, K) float32 C
+    eps_E: float          # ||X - [[A*, B*, C*]]||_F / ||X||_F of the planted factors
+
+
+def make_tensor_instance(spec: TensorSpec, seed: int) -> TensorInstance:
+    """Draw one planted tensor (draw order: images, B*, C*, noise, A0, B0, C0);
+    deterministic for (spec, seed)."""
+    rng = np.random.default_rng(seed)
+    blob = BlobSpec(h=spec.h, w=spec.w, n=1, r=spec.r, k_lo=1, k_hi=3, sig_lo=spec.sig_lo,
+                    sig_hi=spec.sig_hi, noise_std=spec.noise_std)
+    As = _atoms(rng, blob)
+    Bs = rng.uniform(0.0, 1.0, size=(spec.J, spec.r))
+    Cs = rng.uniform(0.0, 1.0, size=(spec.K, spec.r))
+    # column j + J k of the unfolding: A* (C*[k] * B*[j])
+    kr = (Cs[:, None, :] * Bs[None, :, :]).reshape(spec.K * spec.J, spec.r)
+    clean = As @ kr.T
+    noise = np.abs(rng.normal(0.0, spec.noise_std, size=clean.shape))
+    X1 = np.asfortranarray((clean + noise).astype(np.float32))
+    A0 = np.asfortranarray(rng.uniform(0.0, 1.0, size=(spec.m, spec.r)).astype(np.float32))
+    Bt0 = np.ascontiguousarray(rng.uniform(0.0, 1.0, size=(spec.r, spec.J)).astype(np.float32))
+    Ct0 = np.ascontiguousarray(rng.uniform(0.0, 1.0, size=(spec.r, spec.K)).astype(np.float32))
+    X64 = X1.astype(np.float64)
+    eps = float(np.linalg.norm(X64 - clean) / np.linalg.norm(X64))
+    return TensorInstance(spec=spec, seed=seed, X1=X1, A0=A0, Bt0=Bt0, Ct0=Ct0, eps_E=eps)
+
+
 def uniform_pair(m: int, n: int, r: int, seed: int) -> Tuple[np.ndarray, np.ndarray, np.ndarray]:
     """Plain U[0,1] FP32 (M, V0, W0) of arbitrary shape: unstructured test data."""
     rng = np.random.default_rng(seed)

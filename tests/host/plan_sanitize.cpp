@@ -70,6 +70,13 @@ int main() {
         d.tol = (next() & 1) ? 1e-2 : 0.0;
         d.refine_iters = d.prec ? (int32_t)pick(0, 4) : 0;
         d.tile_cfg = (next() % 4 == 0) ? NMF_TILE(1 << pick(0, 2), pick(0, 1) ? 16 : 4) : 0;
+        if (next() % 8 == 0) {   // NTF: n = J K
+            d.algo = NMF_HALS;
+            d.prec = NMF_FP32;
+            d.two_sided = 0;
+            d.ntf_k = (int32_t)pick(1, 64);
+            d.n = d.ntf_k * pick(1, 80);
+        }
         // one field in eight goes out of range
         switch (next() % 16) {
             case 0: d.r = (int32_t)pick(65, 200); break;
@@ -96,7 +103,8 @@ int main() {
                                w.off_Bd, w.off_Bf, w.off_Dd, w.off_Df, w.off_gparts,
                                w.off_cparts, w.off_rparts, w.off_A, w.off_C, w.off_Wb,
                                w.off_Wt, w.off_Dp, w.off_jobs, w.off_tmpM, w.off_klw,
-                               w.off_klwp, w.off_klvp, w.off_kld, w.off_klm};
+                               w.off_klwp, w.off_klvp, w.off_kld, w.off_klm, w.off_ntfW,
+                               w.off_ntfG};
         for (size_t o : offs) check(o <= w.total, "workspace region past the end", d);
         check((int)p.lv.size() == d.levels, "level count", d);
         for (size_t l = 0; l < p.lv.size(); ++l) {

@@ -57,6 +57,10 @@ def test_status_strings():
     (dict(m=256, n=40, h=16, w=16, r=3, levels=2, algo="kl", prec="bf16"), -1),   # KL: FP32
     (dict(m=256, n=40, h=16, w=16, r=3, levels=2, algo="kl", two_sided=True), -1),  # one-sided
     (dict(m=100, n=4, h=10, w=10, r=3, algo=4), -1),     # past NMF_KL
+    (dict(m=100, n=12, h=10, w=10, r=3, ntf_k=5), -2),   # NTF: n not a multiple of K
+    (dict(m=100, n=12, h=10, w=10, r=3, ntf_k=3, algo="mu"), -1),        # NTF: HALS only
+    (dict(m=100, n=12, h=10, w=10, r=3, ntf_k=3, prec="bf16"), -1),      # NTF: FP32 only
+    (dict(m=100, n=12, h=10, w=10, r=3, ntf_k=-1), -1),
 ])
 def test_plan_rejects_bad_descriptions(kw, status):
     with pytest.raises(P.NmfError) as e:
