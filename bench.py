@@ -39,7 +39,7 @@ PEAK_FP32_MFMA_TFLOPS = 157.3  # MI355X dense FP32 matrix
 PEAK_BF16_MFMA_TFLOPS = 2500.0  # MI355X dense BF16 matrix
 PEAK_FP64_VALU_TFLOPS = 78.6   # MI355X FP64 vector
 
-EXTRA_WORKLOADS = ("batch", "serve")
+EXTRA_WORKLOADS = ("batch", "serve", "tensor")
 
 # HBM traffic per launch (bytes) of the sweep kernels, by (workload, precision),
 # kernel kind and level size m: rocprofv3 --pmc FETCH_SIZE and WRITE_SIZE
@@ -221,6 +221,82 @@ def bench_batch(args) -> int:
     return 0 if ok else 1
 
 
+def bench_tensor(args) -> int:
+    """Multilevel NTF (mode 1 coarsened) against single-level NTF, both to
+    ||X - [[A, B, C]]||_F / ||X||_F <= eps_E + tau, on the video-like planted
+    tensor (56x46 pixels x 20 x 20, rank 12)."""
+    import torch
+    import paper_1009_0881_amd as P
+    import synth
+    torch.cuda.set_device(0)
+    spec = synth.CFG_TENSOR
+    inst = synth.make_tensor_instance(spec, args.seed)
+    m, n, r, K = spec.m, spec.J * spec.K, spec.r, spec.K
+    levels = args.levels or 3
+    target = inst.eps_E + args.tau
+    Xd = torch.from_numpy(np.ascontiguousarray(inst.X1.T)).cuda()
+    A0 = torch.from_numpy(np.ascontiguousarray(inst.A0.T)).cuda()
+    B0 = torch.from_numpy(inst.Bt0.copy()).cuda()
+    C0 = torch.from_numpy(inst.Ct0.copy()).cuda()
+    A, B, C = A0.clone(), B0.clone(), C0.clone()
+
+    def plan(L):
+        return P.Plan(m=m, n=n, h=spec.h, w=spec.w, r=r, levels=L, cycle=args.cycle, xfer="fw",
+                      tol=target, max_fine_iters=args.max_fine_iters, check_every=4, ntf_k=K)
+
+    def run(pl, ws, budget):
+        A.copy_(A0)
+        B.copy_(B0)
+        C.copy_(C0)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        res = pl.solve_ntf(Xd, A, B, C, budget, workspace=ws)
+        return time.perf_counter() - t0, res
+
+    ml, sl = plan(levels), plan(1)
+    wm, wsl = ml.workspace(), sl.workspace()
+    for _ in range(args.warmup):
+        run(ml, wm, args.budget)
+        run(sl, wsl, 0)
+    tm, tsl = [], []
+    for _ in range(args.steps):
+        dt, rm = run(ml, wm, args.budget)
+        tm.append(dt)
+    for _ in range(args.steps):
+        dt, rs = run(sl, wsl, 0)
+        tsl.append(dt)
+    ml.profile(P.KERNEL_KINDS)
+    run(ml, wm, args.budget)
+    prof = ml.profile_read(reset=True)
+    ml.profile([])
+    mm, ms_ = np.array(tm) * 1e3, np.array(tsl) * 1e3
+    out = {
+        "metric": "time to rel. err 1e-2 vs plain FP32 single-level; solves/s + p50/p99 latency",
+        "value": round(1e3 / float(np.mean(mm)), 3), "unit": "solves/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(float(np.mean(mm)), 4),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": f"tensor: {spec.h}x{spec.w} planted-blob images x {spec.J} x "
+                               f"{spec.K}, rank {r}, NTF (HALS per mode), {levels} levels (fw) on "
+                               f"the image mode, {args.cycle.upper()}, budget T={args.budget}, "
+                               f"target rel_err <= eps_E+{args.tau:g}"},
+        "time_to_target_ms": {"multilevel_p50": round(float(np.percentile(mm, 50)), 4),
+                              "multilevel_p99": round(float(np.percentile(mm, 99)), 4),
+                              "single_level_p50": round(float(np.percentile(ms_, 50)), 4)},
+        "speedup_vs_single_level": round(float(np.percentile(ms_, 50) / np.percentile(mm, 50)), 3),
+        "eps_E": round(inst.eps_E, 6), "target_rel_err": round(target, 6),
+        "iterations": {"multilevel_total": rm["total_iters"], "multilevel_fine": rm["fine_iters"],
+                       "multilevel_fine_equiv": round(rm["fine_equiv"], 3),
+                       "single_level": rs["total_iters"]},
+        "all_reached_target": bool(rm["stopped"] and rs["stopped"]),
+        "roofline": None, "cpu_baseline": None,
+        "kernels": {k: {"launches_per_solve": v[0], "avg_us": round(v[1] / max(1, v[0]) * 1e3, 3),
+                        "ms_per_solve": round(v[1], 4)} for k, v in prof.items()},
+    }
+    print(json.dumps(out), flush=True)
+    return 0
+
+
 def bench_serve(args) -> int:
     """Poisson arrivals served with continuous batching; latency arrival -> host result."""
     pool = _pool_instances(128, 5000)
@@ -357,6 +433,8 @@ def main() -> int:
         return bench_batch(args)
     if args.workload == "serve":
         return bench_serve(args)
+    if args.workload == "tensor":
+        return bench_tensor(args)
     wl = WORKLOADS[args.workload]
     spec = getattr(synth, wl["spec"])
     levels = args.levels or wl["levels"]
