@@ -51,10 +51,10 @@ SWEEP_SOURCES = ("sweep.hip", "sweep_device.h", "device_common.h", "job.h")
 STREAM_SOURCES = SWEEP_SOURCES + ("stream.hip",)
 TRAFFIC = {
     ("orl", "fp32"): {
-        "sha": "d41ff4590f797f1c",
+        "sha": "281118bfd199c8d3",
         "files": SWEEP_SOURCES,
-        "apass": {10304: 16467037, 2576: 6153595, 644: 2453112},
-        "cpass_partial": {10304: 19473603, 2576: 8886629, 644: 3730826},
+        "apass": {10304: 14698707, 2576: 6153594, 644: 2453112},
+        "cpass_partial": {10304: 17383565, 2576: 8886627, 644: 3730826},
     },
 }
 
@@ -385,7 +385,10 @@ def main() -> int:
                     help="only run 3 device-to-device copies of BYTES bytes (reference for "
                          "the FETCH_SIZE / WRITE_SIZE counters) and exit")
     ap.add_argument("--algo", default="hals", choices=["hals", "mu", "anls", "kl"])
-    ap.add_argument("--cycle", default="vc", choices=["ni", "vc", "fmg", "wc"])
+    ap.add_argument("--cycle", default=None, choices=["ni", "vc", "fmg", "wc"],
+                    help="schedule; default: W-cycle on the 112x92 workload (the fastest to the "
+                         "target there among NI / VC / FMG / WC at T = 16, the others are "
+                         "reported beside it), V-cycle elsewhere")
     ap.add_argument("--levels", type=int, default=None)
     ap.add_argument("--budget", type=int, default=16,
                     help="schedule budget T in finest-iteration equivalents")
@@ -404,6 +407,8 @@ def main() -> int:
                     help="orl: skip the time-to-target of the other two algorithms")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     args = ap.parse_args()
+    if args.cycle is None:
+        args.cycle = "wc" if args.workload == "orl" else "vc"
 
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); "
@@ -517,6 +522,7 @@ def main() -> int:
     for i in range(K):
         dt, sl_res = run(sl, ws_sl, 0, i)
         sl_times.append(dt)
+    sl_ms_all = np.array(sl_times) * 1e3
 
     # the other two algorithms of the workload (ORL-shaped: all three), fewer solves
     others = {}
@@ -547,6 +553,27 @@ def main() -> int:
                            "iterations": rm["total_iters"], "fine": rm["fine_iters"],
                            "single_level_iterations": rs["total_iters"],
                            "reached_target": bool(rm["stopped"] and rs["stopped"])}
+
+    # the other cycles of the same algorithm and budget (ORL-shaped workload)
+    other_cycles = {}
+    if args.workload == "orl" and not args.no_other_algos and args.prec == "fp32":
+        for cyc in ("ni", "vc", "fmg", "wc"):
+            if cyc == args.cycle:
+                continue
+            pc = P.Plan(m=m, n=n, h=wl["h"], w=wl["w"], r=r, levels=levels, algo=args.algo,
+                        cycle=cyc, xfer=wl["xfer"], tol=target,
+                        max_fine_iters=args.max_fine_iters, check_every=4)
+            wc_ = pc.workspace()
+            tc = []
+            for i in range(2 + 7):
+                dt, rc_ = run(pc, wc_, args.budget, i)
+                if i >= 2:
+                    tc.append(dt)
+            mc = float(np.median(tc) * 1e3)
+            other_cycles[cyc] = {"ms": round(mc, 4),
+                                 "speedup": round(float(np.percentile(sl_ms_all, 50)) / mc, 3),
+                                 "iterations": rc_["total_iters"], "fine": rc_["fine_iters"],
+                                 "reached_target": bool(rc_["stopped"])}
 
     # two-sided workload: the one-sided hierarchy on the same data, for comparison
     one_ms = None
@@ -692,6 +719,7 @@ def main() -> int:
         "all_reached_target": bool(ok),
         "one_sided_multilevel_ms": one_ms,
         "other_algorithms": others or None,
+        "other_cycles": other_cycles or None,
         "tile_cfg": tile_desc(parse_tile(args.tile)),
         "roofline": roofline,
         "kernels": kernels,
