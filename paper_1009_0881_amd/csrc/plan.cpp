@@ -153,11 +153,13 @@ nmf_status build_plan(const nmf_desc &d0, Plan &p, std::string &err) {
     p.d = d;
     p.rpad = (d.r + 15) / 16 * 16;
     // Tile shapes: latency tiles (row-split C-pass, narrow W-update tiles) for
-    // problems large enough to run alone, throughput tiles below.
+    // problems large enough to run alone, throughput tiles below.  Wide
+    // problems keep 16-column W-update tiles (n = 2000: 125 blocks of 16
+    // columns beat 500 of 4; n = 400: 100 blocks of 4 beat 25 of 16).
     if (d.tile_cfg == 0) {
         const bool big = d.m >= 8192;
         p.wc = big ? (p.rpad <= 32 ? 4 : 2) : 1;
-        p.cf = big ? 4 : 16;
+        p.cf = big && d.n < 1536 ? 4 : 16;
     } else {
         p.wc = d.tile_cfg & 0xff;
         p.cf = (d.tile_cfg >> 8) & 0xff;
