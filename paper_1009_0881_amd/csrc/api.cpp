@@ -81,6 +81,10 @@ void prof_collect(Ctx &c) {
 
 // FP32 streaming tiling of a job when its level qualifies (large, m and the
 // column stride of M multiples of 4, M 16-byte aligned).
+// Blocks of the D-reduction launch: the upper Gram tiles, then (single
+// solves) the blocks that sum V^T M over the chunks.
+int reduce_blocks(const Job &J) { return J.nG + (J.Cr ? J.nCr : 0); }
+
 void set_fp32_stream(Job &J, const LevelInfo &li, const Plan &p) {
     if (!li.fstream || (J.ldm & 3) != 0 || (reinterpret_cast<uintptr_t>(J.M) & 15) != 0) return;
     J.stream = 1;
@@ -117,6 +121,7 @@ Ctx make_ctx(nmf_plan_t plan, const float *dM, float *dV, float *dW, void *dws, 
     c.rparts = at<double>(c.ws, p.ws.off_rparts);
     c.Cp = at<double>(c.ws, p.ws.off_cparts);
     c.Dp = at<double>(c.ws, p.ws.off_Dp);
+    c.Cr = p.ws.off_Cr ? at<double>(c.ws, p.ws.off_Cr) : nullptr;
     c.Wt = at<float>(c.ws, p.ws.off_Wt);
     c.A = p.ws.off_A ? at<double>(c.ws, p.ws.off_A) : nullptr;
     c.C = p.ws.off_C ? at<double>(c.ws, p.ws.off_C) : nullptr;
@@ -180,6 +185,10 @@ Ctx make_ctx(nmf_plan_t plan, const float *dM, float *dV, float *dW, void *dws, 
         J.Dd = c.Dd;
         J.Cp = c.Cp;
         J.Dp = c.Dp;
+        // single solves reduce V^T M in the D-reduction launch (more blocks
+        // than the W update has); grouped launches keep it in the W update
+        J.Cr = allow_stream ? c.Cr : nullptr;
+        J.nCr = (int32_t)((li.n * p.d.r + 255) / 256);
         J.rparts = c.rparts;
         J.normM2 = c.norm + l;
         J.log_rel = c.log_rel;
@@ -361,7 +370,7 @@ nmf_status sweep(Ctx &c, int d, bool fp32 = false) {
                                               apass_lds_bytes(J.rpad, J.tm, 0), c.s, false));
         NMF_LAUNCH(K_CPART, launch_cpass_jobs(J.rpad, J.wc, dj, nullptr,
                                               cpass_grid_single(J.nCx, J.chunks), c.s, false));
-        NMF_LAUNCH(K_GRAM_V, launch_reduce_jobs(dj, nullptr, J.nG, c.s));
+        NMF_LAUNCH(K_GRAM_V, launch_reduce_jobs(dj, nullptr, reduce_blocks(J), c.s));
         // Y = A^T X_(1) (FP64, J.Cd) by the product-store mode of the W-update kernel
         NMF_LAUNCH(K_CFINAL, launch_cfinal_jobs(2, J.rpad, J.cf, dj, nullptr, J.nFb,
                                                 cfinal_lds_bytes(J.rpad, 2, J.cf), c.s));
@@ -429,7 +438,7 @@ nmf_status sweep(Ctx &c, int d, bool fp32 = false) {
     else
         NMF_LAUNCH(K_CPART, launch_cpass_jobs(J.rpad, J.wc, dj, nullptr,
                                               cpass_grid_single(J.nCx, J.chunks), c.s, bf));
-    NMF_LAUNCH(K_GRAM_V, launch_reduce_jobs(dj, nullptr, J.nG, c.s));
+    NMF_LAUNCH(K_GRAM_V, launch_reduce_jobs(dj, nullptr, reduce_blocks(J), c.s));
     NMF_LAUNCH(K_CFINAL, launch_cfinal_jobs(mode, J.rpad, J.cf, dj, nullptr, J.nFb,
                                             cfinal_lds_bytes(J.rpad, mode, J.cf), c.s));
     if (mode == 2) {
@@ -857,6 +866,7 @@ nmf_status nmf_products(nmf_plan_t plan, const float *dM, const float *dV, const
     J.A = dA;
     J.C = dC;
     J.Ad = J.Cd = nullptr;
+    J.Cr = nullptr;   // no D-reduction launch here: the W update sums the partials
     NMF_HIP(launch_state_reset(c.st, s));
     NMF_HIP(launch_make_wt(dW, p.d.n, p.d.r, p.rpad, c.Wt, s));
     nmf_status st = upload_jobs(c);

@@ -36,6 +36,10 @@ struct Job {
     double *Cp;          // V^T M partials: chunks x (n x r, entry (k, j) at j * r + k),
                          // FP64 (prec 0) or FP32 (prec 1, a float view of the buffer)
     double *Dp;          // V^T V partials: chunks x rpad x rpad (upper 16x16 tiles)
+    double *Cr;          // V^T M summed over the chunks (n x r, FP64, layout of one chunk)
+                         // by the D-reduction kernel's extra blocks, read by the W
+                         // update instead of the partials; null: the W update sums them
+    int32_t nCr;         // those extra blocks (256 entries each)
     double *rparts;      // residual partials of the W-update tiles, nF
     const double *normM2;   // ||M_depth||^2
     double *log_rel;

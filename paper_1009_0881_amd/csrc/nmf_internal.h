@@ -77,7 +77,7 @@ struct Step {            // one schedule entry
 struct Workspace {
     size_t off_state, off_log, off_logdepth, off_norm, off_nparts;
     size_t off_Bd, off_Bf, off_Dd, off_Df;
-    size_t off_gparts, off_cparts, off_rparts, off_A, off_C, off_Wb;
+    size_t off_gparts, off_cparts, off_Cr, off_rparts, off_A, off_C, off_Wb;
     size_t off_Wt, off_Dp, off_jobs;
     size_t off_tmpM;     // two-sided: R_m M_l before the column restriction
     // NMF_KL: row sums of W (rpad), their block partials, the column sums of V

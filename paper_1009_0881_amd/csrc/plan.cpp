@@ -310,6 +310,8 @@ nmf_status build_plan(const nmf_desc &d0, Plan &p, std::string &err) {
     // C-pass partials; also the split A-pass's partial rows of A (FP32
     // streaming levels with aks > 1), which are used up before the C-pass runs
     ws.off_cparts = take(sizeof(double) * std::max<size_t>(max_cp * r * n, max_ap));
+    // V^T M summed over the chunks (single solves of the W-update paths)
+    ws.off_Cr = d.algo != NMF_KL ? take(sizeof(double) * r * n) : 0;
     ws.rparts_cap = std::max<size_t>({(size_t)cpass_final_blocks(d.n),
                                       (size_t)nnls_cols_blocks(d.n), (size_t)1024});
     ws.off_rparts = take(sizeof(double) * ws.rparts_cap);

@@ -765,6 +765,9 @@ __device__ __forceinline__ void gram_tile_pair(int idx, int rt, int &ta, int &tb
 // D = V^T V from the C-pass partials (upper-triangle 16x16 tiles, row stride
 // rpad): one block per upper tile; D[a][b] = sum_p parts[p][a'][b'] with
 // (a', b') = (min, max)(a, b), added in index order, written to both halves.
+// With J.Cr set, the blocks past the upper tiles sum V^T M over the chunks,
+// 256 entries each, in index order from 0 (the W update's own order, so its
+// C is the same either way).
 // ---------------------------------------------------------------------------
 __global__ __launch_bounds__(256) void k_reduce(const Job *__restrict__ jobs,
                                                 const int2 *__restrict__ bmap) {
@@ -772,6 +775,15 @@ __global__ __launch_bounds__(256) void k_reduce(const Job *__restrict__ jobs,
     const Job &J = jobs[jt.x];
     if (J.st->stop) return;
     const int r = J.r, rpad = J.rpad;
+    const int ntiles = (rpad / 16) * (rpad / 16 + 1) / 2;
+    if (jt.y >= ntiles) {
+        const int64_t rn = (int64_t)r * J.n;
+        const int64_t e = (int64_t)(jt.y - ntiles) * 256 + threadIdx.x;
+        if (!J.Cr || e >= rn) return;
+        J.Cr[e] = J.prec ? sum_strided<64>(reinterpret_cast<const float *>(J.Cp) + e, rn, J.chunks)
+                         : sum_strided<64>(J.Cp + e, rn, J.chunks);
+        return;
+    }
     int ta, tb;
     gram_tile_pair(jt.y, rpad / 16, ta, tb);
     const int ra = 16 * ta + (threadIdx.x >> 4), rb = 16 * tb + (threadIdx.x & 15);
@@ -897,7 +909,8 @@ __global__ __launch_bounds__(64 * kGramWWaves) void k_gram_w(const Job *__restri
 // ---------------------------------------------------------------------------
 // W-update tile: CF (4 or 16) columns of W.  The threads reduce the entries
 // of those columns of C from the C-pass partials (chunk-major, n x r per
-// chunk: the tile's entries are contiguous; fixed order, batched loads); then
+// chunk: the tile's entries are contiguous; fixed order, batched loads), or
+// read them from J.Cr where the D-reduction launch has summed them; then
 // 16 lanes per column update it (HALS / MU against D) and write W, its
 // transposed copy Wt (and the BF16 copy).  Also emits, per 4 columns (one
 // wave), the residual partial sum_j (w_j^T D w_j - 2 c_j^T w_j): the first
@@ -952,7 +965,12 @@ __device__ __forceinline__ void cfinal_tile(const Job &J, int tile, double *smem
         bool cok[PER];
 #pragma unroll
         for (int i = 0; i < PER; ++i) cok[i] = off[i] >= 0;
-        if (J.prec) {
+        if (J.Cr) {   // already summed over the chunks
+#pragma unroll
+            for (int i = 0; i < PER; ++i) cs[i] = to_global(J.Cr)[cok[i] ? off[i] : 0];
+#pragma unroll
+            for (int i = 0; i < PER; ++i) cs[i] = cok[i] ? cs[i] : 0.0;
+        } else if (J.prec) {
             const float *src[PER];
 #pragma unroll
             for (int i = 0; i < PER; ++i)
