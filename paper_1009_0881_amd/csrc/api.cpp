@@ -161,7 +161,7 @@ Ctx make_ctx(nmf_plan_t plan, const float *dM, float *dV, float *dW, void *dws, 
         J.n = li.n;
         J.r = p.d.r;
         J.rpad = p.rpad;
-        J.tm = apass_rows_per_block(li.m);
+        J.tm = li.atm;
         J.chunks = li.cp_chunks;
         J.chunk = li.cp_chunk;
         J.nA = (int32_t)((li.m + J.tm - 1) / J.tm);
@@ -224,7 +224,7 @@ Ctx make_ctx(nmf_plan_t plan, const float *dM, float *dV, float *dW, void *dws, 
     if (J0.stream) {     // the FP32 job uses the regular tiling of level 0
         const LevelInfo &l0 = p.lv[0];
         J0.stream = 0;
-        J0.tm = apass_rows_per_block(l0.m);
+        J0.tm = l0.atm;
         J0.nA = (int32_t)((l0.m + J0.tm - 1) / J0.tm);
         J0.nCx = (int32_t)((p.d.n + 63) / 64);
         J0.chunks = l0.cp_chunks;

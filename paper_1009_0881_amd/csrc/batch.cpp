@@ -32,7 +32,7 @@ size_t batch_table_bytes(const nmf_plan_t *plans, int count) {
         const Plan &p = plans[i]->p;
         const int64_t n = p.d.n, r = p.d.r;
         const LevelInfo &l0 = p.lv[0];
-        const int64_t tm = apass_rows_per_block(l0.m);
+        const int64_t tm = l0.atm;
         const int64_t nCx = cdiv(n, 64);
         blocks += cdiv(l0.m, tm) + nCx * l0.cp_chunks + 2 * gram_tiles(p.rpad) +
                   cpass_final_blocks(n);

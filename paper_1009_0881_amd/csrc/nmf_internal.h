@@ -54,6 +54,7 @@ struct LevelInfo {
     size_t off_V;        // workspace offset of V_l (levels >= 1)
     size_t off_Mbp, off_Mbc, off_Vb;   // BF16 mode: copies of M_l (A-pass, C-pass layouts), V_l
     int64_t mpad;        // m rounded up to 32 (column stride of the BF16 copies)
+    int32_t atm;         // rows per block of the regular A-pass (16 or 64)
     int32_t cp_chunks;   // split of the m-reduction in V^T M
     int64_t cp_chunk;    // rows per chunk (multiple of 16; 32 in BF16 mode)
     bool stream;         // BF16 mode, large level: streaming A/C-pass kernels
@@ -126,6 +127,8 @@ struct Plan {
     Workspace ws;
     int rpad;            // r rounded up to a multiple of 16
     int wc, cf;          // tiles: C-pass row groups per tile, W-update columns per tile
+    bool thru;           // throughput tiles (problems sized for batches): C-pass chunks
+                         // of at least 512 rows
     int num_cu;
     int32_t gram_w_parts;
     int64_t gram_w_chunk;
@@ -214,7 +217,6 @@ hipError_t launch_norms_many(const NormJob *jobs, const int2 *bmap, int blocks, 
 hipError_t launch_state_reset_many(DevState *const *states, int count, hipStream_t s);
 hipError_t launch_gather_states(DevState *const *states, int count, DevState *out,
                                 hipStream_t s);
-int apass_rows_per_block(int64_t m);
 size_t apass_lds_bytes(int rpad, int tm, int mode);
 size_t cfinal_lds_bytes(int rpad, int mode, int cf);
 int cpass_final_blocks(int64_t n);   // W-update residual partials (one per 4 columns)

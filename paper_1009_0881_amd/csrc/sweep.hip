@@ -1114,8 +1114,6 @@ __global__ __launch_bounds__(256) void k_residual(const double *__restrict__ rpa
 
 // ---- host side -------------------------------------------------------------
 
-int apass_rows_per_block(int64_t m) { return m >= 32768 ? 64 : 16; }
-
 size_t apass_lds_bytes(int rpad, int tm, int mode) {
     const bool upd = mode != MODE_STORE;
     const int rw = tm == 16 ? 1 : 2;
