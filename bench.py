@@ -51,10 +51,10 @@ SWEEP_SOURCES = ("sweep.hip", "sweep_device.h", "device_common.h", "job.h")
 STREAM_SOURCES = SWEEP_SOURCES + ("stream.hip",)
 TRAFFIC = {
     ("orl", "fp32"): {
-        "sha": "281118bfd199c8d3",
+        "sha": "2dd8ec1be100460f",
         "files": SWEEP_SOURCES,
-        "apass": {10304: 14698707, 2576: 6153594, 644: 2453112},
-        "cpass_partial": {10304: 17383565, 2576: 8886627, 644: 3730826},
+        "apass": {10304: 14697620, 2576: 6152577, 644: 2452091},
+        "cpass_partial": {10304: 17393499, 2576: 8894826, 644: 3740044},
     },
 }
 
