@@ -157,7 +157,7 @@ def bench_batch(args) -> int:
     def kwargs(spec, inst):
         return dict(m=spec.m, n=spec.n, h=spec.h, w=spec.w, r=spec.r, levels=3, algo="hals",
                     cycle=args.cycle, xfer="fw", tol=inst.eps_E + args.tau,
-                    max_fine_iters=args.max_fine_iters, check_every=4)
+                    max_fine_iters=args.max_fine_iters, check_every=4, grouped=True)
 
     tile_cfg, tuning = parse_tile(args.tile), None
     if args.tune:   # tile autotuner on every 8th problem of the batch

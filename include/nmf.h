@@ -73,6 +73,7 @@ enum { NMF_XFER_FW = 0, NMF_XFER_BLOCK2 = 1 };
  * FP32; Grams, updates and residuals stay FP32/FP64 as in FP32 mode. */
 enum { NMF_FP32 = 0, NMF_BF16 = 1 };
 #define NMF_TILE(wc, cf) ((int32_t)(wc) | ((int32_t)(cf) << 8))   /* nmf_desc.tile_cfg */
+#define NMF_TILE_GROUPED ((int32_t)1 << 16)                          /* nmf_desc.tile_cfg flag */
 
 typedef struct {
     int64_t m, n;          /* M is m x n; m must equal h*w                          */
@@ -98,7 +99,14 @@ typedef struct {
                               tile.  Single and batched solves of one plan run the same
                               tiles, hence the same arithmetic; plans with different
                               tiles agree to rounding (the C-pass sum order depends on
-                              wc).  Chosen by paper_1009_0881_amd.tune for a workload. */
+                              wc).  Chosen by paper_1009_0881_amd.tune for a workload.
+                              NMF_TILE_GROUPED may be or-ed in (alone or with
+                              NMF_TILE(wc, cf)): a plan for problems solved in grouped
+                              launches (nmf_solve_batch, the server), where the problems
+                              fill the chip together.  Its C-pass chunks keep at least
+                              512 rows (fewer FP64 partials of V^T M); a problem solved
+                              alone with such a plan is slower, with the same bits as in
+                              a batch.  Other bits above 15 are rejected (NMF_E_ARG). */
     double tol;            /* > 0: stop after the first finest-level iteration with
                               rel_err <= tol (absolute threshold on rel_err)        */
     int32_t two_sided;     /* 1: the hierarchy also halves the column count (Section

@@ -169,11 +169,15 @@ def tile(wc: int, cf: int) -> int:
     return int(wc) | (int(cf) << 8)
 
 
+TILE_GROUPED = 1 << 16   # NMF_TILE_GROUPED: plan sized for grouped (batch / server) launches
+
+
 def make_desc(m, n, h, w, r, levels=1, algo="hals", cycle="ni", xfer="fw", prec="fp32",
               tol=0.0, max_fine_iters=0, check_every=8, log_cap=4096, check_input=False,
-              refine_iters=0, ldm=0, tile_cfg=0, two_sided=False, ntf_k=0) -> Desc:
+              refine_iters=0, ldm=0, tile_cfg=0, two_sided=False, ntf_k=0,
+              grouped=False) -> Desc:
     """nmf_desc from Python values (names as in include/nmf.h); tile_cfg is 0,
-    an NMF_TILE value or a (wc, cf) pair."""
+    an NMF_TILE value or a (wc, cf) pair; grouped ors in NMF_TILE_GROUPED."""
     d = Desc()
     d.m, d.n, d.ldm, d.h, d.w, d.r, d.levels = m, n, ldm, h, w, r, levels
     d.algo = ALGOS.get(algo, algo) if isinstance(algo, str) else algo
@@ -183,6 +187,8 @@ def make_desc(m, n, h, w, r, levels=1, algo="hals", cycle="ni", xfer="fw", prec=
     d.tol, d.max_fine_iters, d.check_every = tol, max_fine_iters, check_every
     d.log_cap, d.check_input, d.refine_iters = log_cap, int(check_input), refine_iters
     d.tile_cfg = tile(*tile_cfg) if isinstance(tile_cfg, (tuple, list)) else int(tile_cfg)
+    if grouped:
+        d.tile_cfg |= TILE_GROUPED
     d.two_sided = int(bool(two_sided))
     d.ntf_k = int(ntf_k)
     return d
@@ -195,10 +201,10 @@ class Plan:
                  algo="hals", cycle="ni", xfer="fw", prec="fp32", tol: float = 0.0,
                  max_fine_iters: int = 0, check_every: int = 8, log_cap: int = 4096,
                  check_input: bool = False, refine_iters: int = 0, ldm: int = 0, tile_cfg=0,
-                 two_sided: bool = False, ntf_k: int = 0):
+                 two_sided: bool = False, ntf_k: int = 0, grouped: bool = False):
         d = make_desc(m, n, h, w, r, levels, algo, cycle, xfer, prec, tol, max_fine_iters,
                       check_every, log_cap, check_input, refine_iters, ldm, tile_cfg, two_sided,
-                      ntf_k)
+                      ntf_k, grouped)
         self.desc = d
         self.handle = ctypes.c_void_p()
         wsb = ctypes.c_size_t()

@@ -127,7 +127,7 @@ struct Plan {
     Workspace ws;
     int rpad;            // r rounded up to a multiple of 16
     int wc, cf;          // tiles: C-pass row groups per tile, W-update columns per tile
-    bool thru;           // throughput tiles (problems sized for batches): C-pass chunks
+    bool grouped;        // NMF_TILE_GROUPED: sized for grouped launches, C-pass chunks
                          // of at least 512 rows
     int num_cu;
     int32_t gram_w_parts;

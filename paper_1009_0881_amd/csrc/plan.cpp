@@ -156,20 +156,24 @@ nmf_status build_plan(const nmf_desc &d0, Plan &p, std::string &err) {
     // problems large enough to run alone, throughput tiles below.  Wide
     // problems keep 16-column W-update tiles (n = 2000: 125 blocks of 16
     // columns beat 500 of 4; n = 400: 100 blocks of 4 beat 25 of 16).
-    if (d.tile_cfg == 0) {
+    const int32_t tiles = d.tile_cfg & 0xffff;
+    if ((d.tile_cfg & ~(NMF_TILE_GROUPED | 0xffff)) != 0) {
+        err = "tile_cfg: unknown flag bits (only NMF_TILE_GROUPED is defined above bit 15)";
+        return NMF_E_ARG;
+    }
+    p.grouped = (d.tile_cfg & NMF_TILE_GROUPED) != 0;
+    if (tiles == 0) {
         const bool big = d.m >= 8192;
         p.wc = big ? (p.rpad <= 32 ? 4 : 2) : 1;
         p.cf = big && d.n < 1536 ? 4 : 16;
-        p.thru = !big;
     } else {
-        p.wc = d.tile_cfg & 0xff;
-        p.cf = (d.tile_cfg >> 8) & 0xff;
-        if ((p.wc != 1 && p.wc != 2 && p.wc != 4) || (p.cf != 4 && p.cf != 16) ||
-            (d.tile_cfg >> 16) != 0) {
-            err = "tile_cfg must be 0 or NMF_TILE(wc, cf) with wc in {1, 2, 4}, cf in {4, 16}";
+        p.wc = tiles & 0xff;
+        p.cf = (tiles >> 8) & 0xff;
+        if ((p.wc != 1 && p.wc != 2 && p.wc != 4) || (p.cf != 4 && p.cf != 16)) {
+            err = "tile_cfg must be 0 or NMF_TILE(wc, cf) with wc in {1, 2, 4}, cf in {4, 16} "
+                  "(optionally with NMF_TILE_GROUPED)";
             return NMF_E_ARG;
         }
-        p.thru = p.wc == 1;
     }
     p.lv.clear();
     int h = d.h, w = d.w;
@@ -209,19 +213,19 @@ nmf_status build_plan(const nmf_desc &d0, Plan &p, std::string &err) {
 
     // Split of the length-m reductions.  Target about one block per CU for
     // V^T M (deterministic split-m partials) and at most 256 Gram partials.
-    // Throughput tiles keep chunks of at least 512 rows: in a batch the
-    // problems fill the chip, and shorter chunks write FP64 partials that
-    // outweigh M (chunks * 8r bytes per column against 4m).  (512-problem
-    // batch: 114.9 ms with one block per CU per problem, 107.7 ms with 512-row
-    // chunks, 108.3 with 256, 111.7 with 1024; 64-row A-pass tiles from
-    // m = 1024 on top made it 127.3 ms.)
+    // Grouped plans keep chunks of at least 512 rows: in a batch the problems
+    // fill the chip, and shorter chunks write FP64 partials that outweigh M
+    // (chunks * 8r bytes per column against 4m).  (512-problem batch: 114.9 ms
+    // with one block per CU per problem, 107.7 ms with 512-row chunks, 108.3
+    // with 256, 111.7 with 1024; 64-row A-pass tiles from m = 1024 on top made
+    // it 127.3 ms.  Alone, the 64x64 two-sided solve went from 0.84 to 0.93 ms.)
     size_t max_cp = 0, max_gp = 0, max_ap = 0;
     for (auto &li : p.lv) {
         li.atm = li.m >= 32768 ? 64 : 16;
         const int64_t ntiles = (li.n + 63) / 64;
         int64_t chunks = std::max<int64_t>(1, p.num_cu / std::max<int64_t>(1, ntiles));
         chunks = std::min<int64_t>(chunks, std::max<int64_t>(1, (li.m + 63) / 64));
-        if (p.thru) chunks = std::min<int64_t>(chunks, std::max<int64_t>(1, li.m / 512));
+        if (p.grouped) chunks = std::min<int64_t>(chunks, std::max<int64_t>(1, li.m / 512));
         int64_t chunk = (li.m + chunks - 1) / chunks;
         // FP32: whole 16-row steps for each of up to 4 row groups of a C-pass
         // tile; BF16: see kBfPad

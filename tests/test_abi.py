@@ -51,7 +51,8 @@ def test_status_strings():
     (dict(m=100, n=0, h=10, w=10, r=3), -2),             # n < 1
     (dict(m=100, n=4, h=10, w=10, r=3, tile_cfg=(3, 4)), -1),    # wc not in {1, 2, 4}
     (dict(m=100, n=4, h=10, w=10, r=3, tile_cfg=(2, 8)), -1),    # cf not in {4, 16}
-    (dict(m=100, n=4, h=10, w=10, r=3, tile_cfg=(1 | 16 << 8 | 1 << 16)), -1),
+    (dict(m=100, n=4, h=10, w=10, r=3, tile_cfg=(1 | 16 << 8 | 1 << 17)), -1),
+    (dict(m=100, n=4, h=10, w=10, r=3, tile_cfg=(1 << 18)), -1),
     (dict(m=256, n=40, h=16, w=16, r=3, levels=2, two_sided=True, prec="bf16"), -1),
     (dict(m=256, n=2, h=16, w=16, r=1, levels=3, two_sided=True), -2),   # 2 -> 1 column, then 1
     (dict(m=256, n=40, h=16, w=16, r=3, levels=2, algo="kl", prec="bf16"), -1),   # KL: FP32
@@ -110,6 +111,17 @@ def test_plan_accepts_every_tile_candidate():
     for wc, cf in tune.CANDIDATES:
         pl = P.Plan(m=256, n=40, h=16, w=16, r=20, levels=2, tile_cfg=(wc, cf))
         assert pl.desc.tile_cfg == P.tile(wc, cf) == (wc | cf << 8)
+
+
+def test_grouped_flag():
+    base = dict(m=2304, n=300, h=48, w=48, r=20, levels=3)
+    a = P.Plan(**base)
+    g = P.Plan(**base, grouped=True)
+    t = P.Plan(**base, tile_cfg=(2, 4), grouped=True)
+    assert g.desc.tile_cfg == P.TILE_GROUPED == 1 << 16
+    assert t.desc.tile_cfg == P.tile(2, 4) | P.TILE_GROUPED
+    # fewer C-pass chunks: the partial buffers shrink
+    assert g.workspace_bytes < a.workspace_bytes
 
 
 def test_tune_cache_round_trip(tmp_path):

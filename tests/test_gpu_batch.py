@@ -48,7 +48,8 @@ def _plan(d):
     return P.Plan(m=d["h"] * d["w"], n=d["n"], h=d["h"], w=d["w"], r=d["r"], levels=d["L"],
                   algo=algo, cycle=d["cyc"], xfer=d["xf"], tol=d["tol"],
                   max_fine_iters=200 if d["tol"] > 0 else 0, check_every=4,
-                  prec=prec or "fp32", refine_iters=3 if prec else 0)
+                  prec=prec or "fp32", refine_iters=3 if prec else 0,
+                  grouped=d.get("grouped", False))
 
 
 def _run_single(d):
@@ -139,6 +140,35 @@ def test_batch_sampled_from_uneven_distribution():
         assert _same(sres, bres[i])
         assert torch.equal(sV, bV[i]) and torch.equal(sW, bW[i])
     say("  stopped", sum(r["stopped"] for r in bres), "of 32")
+
+
+def test_grouped_plans_batch_equals_single_and_oracle():
+    """Plans with NMF_TILE_GROUPED (C-pass chunks of at least 512 rows): the
+    batch still reproduces single solves of the same plans bitwise, and the
+    factors stay at the oracle parity bar."""
+    mix = [MIX[1], MIX[3], MIX[6], MIX[7],
+           (40, 36, 300, 20, 3, "hals", "vc", "fw", 16, 0.0),
+           (64, 48, 500, 33, 3, "mu", "ni", "fw", 12, 0.0)]
+    ds = _instances(mix, seed0=700)
+    for d in ds:
+        d["grouped"] = True
+    say("grouped plans: batch of", len(ds), "vs single solves and the oracle")
+    bres, bV, bW = _run_batch(ds)
+    for i, d in enumerate(ds):
+        sres, sV, sW = _run_single(d)
+        assert _same(sres, bres[i]), (sres, bres[i])
+        assert torch.equal(sV, bV[i]) and torch.equal(sW, bW[i])
+    for i in (0, 4, 5):   # FP32 problems without a tolerance
+        d = ds[i]
+        ores, orel, _ = oracle_solve(d["inst"].M, d["inst"].V0, d["inst"].W0, d["h"], d["w"],
+                                     d["r"], d["L"], d["algo"], d["cyc"], d["xf"], d["T"])
+        V, W = P.factors_to_host(bV[i], bW[i])
+        dV, dW = frob_rel(V, ores.V), frob_rel(W, ores.W)
+        drel = abs(bres[i]["rel_err"] - orel[-1])
+        say(f"  problem {i} vs oracle: |d rel_err| {drel:.3g} V {dV:.3g} W {dW:.3g}")
+        assert bres[i]["total_iters"] == len(orel)
+        assert drel <= TOL_REL_ERR
+        assert dV <= TOL_FACTOR and dW <= TOL_FACTOR
 
 
 def test_batch_rejects_anls():
