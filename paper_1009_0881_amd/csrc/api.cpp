@@ -122,6 +122,7 @@ Ctx make_ctx(nmf_plan_t plan, const float *dM, float *dV, float *dW, void *dws, 
     c.Cp = at<double>(c.ws, p.ws.off_cparts);
     c.Dp = at<double>(c.ws, p.ws.off_Dp);
     c.Cr = p.ws.off_Cr ? at<double>(c.ws, p.ws.off_Cr) : nullptr;
+    c.bparts = at<double>(c.ws, p.ws.off_bparts);
     c.Wt = at<float>(c.ws, p.ws.off_Wt);
     c.A = p.ws.off_A ? at<double>(c.ws, p.ws.off_A) : nullptr;
     c.C = p.ws.off_C ? at<double>(c.ws, p.ws.off_C) : nullptr;
@@ -189,6 +190,8 @@ Ctx make_ctx(nmf_plan_t plan, const float *dM, float *dV, float *dW, void *dws, 
         // than the W update has); grouped launches keep it in the W update
         J.Cr = allow_stream ? c.Cr : nullptr;
         J.nCr = (int32_t)((li.n * p.d.r + 255) / 256);
+        J.gseg = li.gseg;
+        J.bparts = c.bparts;
         J.rparts = c.rparts;
         J.normM2 = c.norm + l;
         J.log_rel = c.log_rel;
@@ -334,7 +337,9 @@ nmf_status init_w(Ctx &c, int d = 0) {
     }
     NMF_LAUNCH(K_GRAM_W, launch_cfinal_jobs(3, J.rpad, J.cf, c.djobs + d, nullptr, J.nFb,
                                             cfinal_lds_bytes(J.rpad, 3, J.cf), c.s));
-    NMF_LAUNCH(K_GRAM_W, launch_gram_w_jobs(0, c.djobs + d, nullptr, J.nG, c.s));
+    NMF_LAUNCH(K_GRAM_W, launch_gram_w_jobs(0, c.djobs + d, nullptr, J.nG * J.gseg, c.s));
+    if (J.gseg > 1)
+        NMF_LAUNCH(K_GRAM_W, launch_gram_sum_jobs(0, c.djobs + d, nullptr, J.nG, c.s));
     return NMF_OK;
 }
 
@@ -450,7 +455,9 @@ nmf_status sweep(Ctx &c, int d, bool fp32 = false) {
                                             d, c.log_rel, c.log_depth, p.d.log_cap, c.st,
                                             c.jobs[0].hstop, p.d.tol, c.s));
     } else {
-        NMF_LAUNCH(K_GRAM_W, launch_gram_w_jobs(1, dj, nullptr, J.nG, c.s));
+        NMF_LAUNCH(K_GRAM_W, launch_gram_w_jobs(1, dj, nullptr, J.nG * J.gseg, c.s));
+        if (J.gseg > 1)
+            NMF_LAUNCH(K_GRAM_W, launch_gram_sum_jobs(1, dj, nullptr, J.nG, c.s));
     }
     c.depths.push_back((int8_t)d);
     return NMF_OK;

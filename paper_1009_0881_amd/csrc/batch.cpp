@@ -34,7 +34,7 @@ size_t batch_table_bytes(const nmf_plan_t *plans, int count) {
         const LevelInfo &l0 = p.lv[0];
         const int64_t tm = l0.atm;
         const int64_t nCx = cdiv(n, 64);
-        blocks += cdiv(l0.m, tm) + nCx * l0.cp_chunks + 2 * gram_tiles(p.rpad) +
+        blocks += cdiv(l0.m, tm) + nCx * l0.cp_chunks + gram_tiles(p.rpad) * (1 + l0.gseg) +
                   cpass_final_blocks(n);
         int64_t xt = 0;
         for (size_t l = 1; l < p.lv.size(); ++l)
@@ -225,17 +225,24 @@ nmf_status Executor::setup_fresh() {
         for (Inst *I : kv.second) {
             const Job &J = I->c.jobs[0];
             for (int k = 0; k < J.nFb; ++k) bF.push_back(make_int2((int)jobs.size(), k));
-            for (int k = 0; k < J.nG; ++k) bG.push_back(make_int2((int)jobs.size(), k));
+            for (int k = 0; k < J.nG * J.gseg; ++k) bG.push_back(make_int2((int)jobs.size(), k));
             jobs.push_back(J);
         }
+        std::vector<int2> bT;   // one block per upper tile (k_gram_sum)
+        bool seg = false;
+        for (size_t j = 0; j < jobs.size(); ++j) {
+            for (int k = 0; k < jobs[j].nG; ++k) bT.push_back(make_int2((int)j, k));
+            seg = seg || jobs[j].gseg > 1;
+        }
         const Job *dj;
-        const int2 *dF, *dG;
+        const int2 *dF, *dG, *dT;
         if ((st = upload(jobs, &dj)) != NMF_OK || (st = upload(bF, &dF)) != NMF_OK ||
-            (st = upload(bG, &dG)) != NMF_OK)
+            (st = upload(bG, &dG)) != NMF_OK || (st = upload(bT, &dT)) != NMF_OK)
             return st;
         NMF_HIP(launch_cfinal_jobs(3, rpad, cf, dj, dF, (int)bF.size(),
                                    cfinal_lds_bytes(rpad, 3, cf), s_));
         NMF_HIP(launch_gram_w_jobs(0, dj, dG, (int)bG.size(), s_));
+        if (seg) NMF_HIP(launch_gram_sum_jobs(0, dj, dT, (int)bT.size(), s_));
     }
     return NMF_OK;
 }
@@ -363,24 +370,28 @@ nmf_status Executor::launch_sweeps(const std::vector<Inst *> &active, bool captu
             g = it->second;
         } else {
             std::vector<Job> jobs;
-            std::vector<int2> bA, bC, bG, bF;
+            std::vector<int2> bA, bC, bG, bF, bW;
             for (Inst *I : kv.second) {
                 const Job &J = job_of(I);
                 const int j = (int)jobs.size();
                 for (int k = 0; k < J.nA; ++k) bA.push_back(make_int2(j, k));
                 for (int k = 0; k < J.nC; ++k) bC.push_back(make_int2(j, k));
                 for (int k = 0; k < J.nG; ++k) bG.push_back(make_int2(j, k));
+                for (int k = 0; k < J.nG * J.gseg; ++k) bW.push_back(make_int2(j, k));
                 for (int k = 0; k < J.nFb; ++k) bF.push_back(make_int2(j, k));
                 jobs.push_back(J);
             }
             if ((st = upload(jobs, &g.dj)) != NMF_OK || (st = upload(bA, &g.bA)) != NMF_OK ||
                 (st = upload(bC, &g.bC)) != NMF_OK || (st = upload(bG, &g.bG)) != NMF_OK ||
-                (st = upload(bF, &g.bF)) != NMF_OK)
+                (st = upload(bF, &g.bF)) != NMF_OK || (st = upload(bW, &g.bW)) != NMF_OK)
                 return st;
             g.nA = (int)bA.size();
             g.nC = (int)bC.size();
             g.nG = (int)bG.size();
             g.nF = (int)bF.size();
+            g.nW = (int)bW.size();
+            g.seg = false;
+            for (const Job &J : jobs) g.seg = g.seg || J.gseg > 1;
             cache_[gkey] = g;
         }
         gl.push_back(g);
@@ -393,7 +404,8 @@ nmf_status Executor::launch_sweeps(const std::vector<Inst *> &active, bool captu
             NMF_HIP(launch_reduce_jobs(g.dj, g.bG, g.nG, s_));
             NMF_HIP(launch_cfinal_jobs(g.mode, g.rpad, g.cf, g.dj, g.bF, g.nF,
                                        cfinal_lds_bytes(g.rpad, g.mode, g.cf), s_));
-            NMF_HIP(launch_gram_w_jobs(1, g.dj, g.bG, g.nG, s_));
+            NMF_HIP(launch_gram_w_jobs(1, g.dj, g.bW, g.nW, s_));
+            if (g.seg) NMF_HIP(launch_gram_sum_jobs(1, g.dj, g.bG, g.nG, s_));
         }
         return NMF_OK;
     };

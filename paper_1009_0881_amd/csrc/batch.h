@@ -68,8 +68,9 @@ private:
         int rpad, tm, mode, wc, cf;
         bool bf;
         const Job *dj;
-        const int2 *bA, *bC, *bG, *bF;
-        int nA, nC, nG, nF;
+        const int2 *bA, *bC, *bG, *bF, *bW;   // bW: B = W W^T blocks (nG * gseg per job)
+        int nA, nC, nG, nF, nW;
+        bool seg;             // some job has gseg > 1: B partials summed by k_gram_sum
     };
 
     template <class T>

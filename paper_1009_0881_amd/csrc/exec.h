@@ -40,6 +40,7 @@ struct Ctx {
     double *A, *C;                // ANLS: FP64 products M W^T and V^T M
     double *Cp, *Dp;
     double *Cr;                   // V^T M summed over the chunks (null: KL plans)
+    double *bparts;               // partial tiles of B = W W^T (segmented launches)
     // NMF_KL: row sums of W and their block partials, column sums of V per
     // chunk, divergence partials, sum(M_l) per level (null otherwise)
     double *klw = nullptr, *klwp = nullptr, *klvp = nullptr, *kld = nullptr, *klm = nullptr;

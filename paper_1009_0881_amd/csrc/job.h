@@ -41,6 +41,8 @@ struct Job {
                          // update instead of the partials; null: the W update sums them
     int32_t nCr;         // those extra blocks (256 entries each)
     double *rparts;      // residual partials of the W-update tiles, nF
+    int32_t gseg;        // B = W W^T: column segments per upper tile (blocks nG * gseg)
+    double *bparts;      // their partial tiles: [tile][segment][256] (gseg > 1)
     const double *normM2;   // ||M_depth||^2
     double *log_rel;
     int32_t *log_depth;

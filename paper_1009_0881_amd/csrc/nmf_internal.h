@@ -2,6 +2,7 @@
 // the kernel launchers.  Host C++ only; the kernels live in *.hip files.
 #pragma once
 
+#include <algorithm>
 #include <cstddef>
 #include <cstdint>
 #include <mutex>
@@ -55,6 +56,7 @@ struct LevelInfo {
     size_t off_Mbp, off_Mbc, off_Vb;   // BF16 mode: copies of M_l (A-pass, C-pass layouts), V_l
     int64_t mpad;        // m rounded up to 32 (column stride of the BF16 copies)
     int32_t atm;         // rows per block of the regular A-pass (16 or 64)
+    int32_t gseg;        // B = W W^T: column segments per upper tile (1..kGramSegMax)
     int32_t cp_chunks;   // split of the m-reduction in V^T M
     int64_t cp_chunk;    // rows per chunk (multiple of 16; 32 in BF16 mode)
     bool stream;         // BF16 mode, large level: streaming A/C-pass kernels
@@ -78,7 +80,7 @@ struct Step {            // one schedule entry
 struct Workspace {
     size_t off_state, off_log, off_logdepth, off_norm, off_nparts;
     size_t off_Bd, off_Bf, off_Dd, off_Df;
-    size_t off_gparts, off_cparts, off_Cr, off_rparts, off_A, off_C, off_Wb;
+    size_t off_gparts, off_cparts, off_Cr, off_bparts, off_rparts, off_A, off_C, off_Wb;
     size_t off_Wt, off_Dp, off_jobs;
     size_t off_tmpM;     // two-sided: R_m M_l before the column restriction
     // NMF_KL: row sums of W (rpad), their block partials, the column sums of V
@@ -224,11 +226,22 @@ int cfinal_tile_blocks(int64_t n, int cf);   // W-update blocks of cf columns
 // Upper-triangle 16x16 tiles of an rpad x rpad Gram: blocks of the Gram
 // reduction (D) and of the B = W W^T kernel.
 inline int gram_tiles(int rpad) { return (rpad / 16) * (rpad / 16 + 1) / 2; }
+// Column segments of B = W W^T per upper tile: one below n = 1024 (the blocks
+// of one tile then cost less than the hand-over), else one per 256 columns, at
+// most kGramSegMax.
+constexpr int kGramSegMax = 8;
+inline int gram_w_segments(int64_t n) {
+    return n < 1024 ? 1 : (int)std::min<int64_t>(kGramSegMax, (n + 255) / 256);
+}
 // B = W W^T (FP64) from the current W, one block per upper tile.  with_resid:
 // block 0 also assembles the residual of the iteration from the W-update
 // partials, logs rel_err and sets the stop flag.
 hipError_t launch_gram_w_jobs(int with_resid, const Job *jobs, const int2 *bmap, int blocks,
                               hipStream_t s);
+// B from the segment partials of launch_gram_w_jobs for jobs with gseg > 1
+// (one block per upper tile, blocks = nG per job; jobs with gseg = 1 return).
+hipError_t launch_gram_sum_jobs(int with_resid, const Job *jobs, const int2 *bmap, int blocks,
+                                hipStream_t s);
 // Grids of single-problem (null block map) A-pass / C-pass launches, whose
 // blocks are mapped to tiles XCD by XCD.
 int apass_grid_single(int nA);

@@ -222,6 +222,7 @@ nmf_status build_plan(const nmf_desc &d0, Plan &p, std::string &err) {
     size_t max_cp = 0, max_gp = 0, max_ap = 0;
     for (auto &li : p.lv) {
         li.atm = li.m >= 32768 ? 64 : 16;
+        li.gseg = gram_w_segments(li.n);
         const int64_t ntiles = (li.n + 63) / 64;
         int64_t chunks = std::max<int64_t>(1, p.num_cu / std::max<int64_t>(1, ntiles));
         chunks = std::min<int64_t>(chunks, std::max<int64_t>(1, (li.m + 63) / 64));
@@ -326,6 +327,7 @@ nmf_status build_plan(const nmf_desc &d0, Plan &p, std::string &err) {
     ws.off_cparts = take(sizeof(double) * std::max<size_t>(max_cp * r * n, max_ap));
     // V^T M summed over the chunks (single solves of the W-update paths)
     ws.off_Cr = d.algo != NMF_KL ? take(sizeof(double) * r * n) : 0;
+    ws.off_bparts = take(sizeof(double) * kGramSegMax * gram_tiles(p.rpad) * 256);
     ws.rparts_cap = std::max<size_t>({(size_t)cpass_final_blocks(d.n),
                                       (size_t)nnls_cols_blocks(d.n), (size_t)1024});
     ws.off_rparts = take(sizeof(double) * ws.rparts_cap);

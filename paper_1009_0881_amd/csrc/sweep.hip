@@ -796,92 +796,14 @@ __global__ __launch_bounds__(256) void k_reduce(const Job *__restrict__ jobs,
 }
 
 // ---------------------------------------------------------------------------
-// B = W W^T in FP64 from the FP32 W (r x n, row-major): block = upper tile
-// (ta, tb); its 8 waves split n into contiguous ranges and run FP64 MFMAs
-// (products of FP32 values are exact), lane (li, lk) supplying columns
-// j0 + 4 lk + s of rows 16 ta + li and 16 tb + li to MFMA s; the loads of 8
-// 16-column steps go out together.  The wave partials are added in LDS in
-// wave order.  with_resid: block 0 also assembles the residual of the
-// iteration, e^2 = ||M_d||^2 + sum of the W-update partials (index order),
-// logs rel_err and sets the stop flag.
+// Residual of the iteration from the W-update partials (one block, index
+// order): e^2 = ||M_d||^2 + sum of the partials; logs rel_err and sets the
+// stop flag.  rs: this thread's share, partials tid, tid + NT, ...
 // ---------------------------------------------------------------------------
-constexpr int kGramWWaves = 8;
-
-__global__ __launch_bounds__(64 * kGramWWaves) void k_gram_w(const Job *__restrict__ jobs,
-                                                             const int2 *__restrict__ bmap,
-                                                             int with_resid) {
-    constexpr int NW = kGramWWaves, NT = 64 * NW, U = 8;
-    __shared__ double part[NW - 1][256];
-    __shared__ double red[NW];
-    const int2 jt = block_job(bmap);
-    const Job &J = jobs[jt.x];
-    if (J.st->stop) return;
-    const int r = J.r, rpad = J.rpad;
-    const int64_t n = J.n;
-    int ta, tb;
-    gram_tile_pair(jt.y, rpad / 16, ta, tb);
-    const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
-    const int li = lane & 15, lk = lane >> 4;
-    const int ka = 16 * ta + li, kb = 16 * tb + li;
-    const auto W = to_global(J.W);
-    const gmem<const float> *wa = W + (int64_t)(ka < r ? ka : 0) * n;
-    const gmem<const float> *wb = W + (int64_t)(kb < r ? kb : 0) * n;
-    const bool va = ka < r, vb = kb < r;
-    const bool vec = (n & 3) == 0 && ((uintptr_t)J.W & 15) == 0;
-    // residual (block 0): the W-update partials of the previous kernel
-    double rs = 0.0;
-    if (with_resid && jt.y == 0)
-        for (int i = tid; i < J.nF; i += NT) rs += to_global(J.rparts)[i];
-    // columns per wave, a multiple of 16
-    const int64_t per = (n + 16 * NW - 1) / (16 * NW) * 16;
-    const int64_t c0 = wave * per, c1 = (c0 + per < n) ? c0 + per : n;
-    v4d acc = {0.0, 0.0, 0.0, 0.0};
-    for (int64_t jg = c0; jg < c1; jg += 16 * U) {
-        v4f xa[U], xb[U];
-#pragma unroll
-        for (int u = 0; u < U; ++u) {
-            const int64_t jb = jg + 16 * u + 4 * lk;
-            if (vec && jb + 3 < c1) {
-                xa[u] = va ? *(gmem<const v4f> *)(wa + jb) : v4f{0.0f, 0.0f, 0.0f, 0.0f};
-                xb[u] = vb ? *(gmem<const v4f> *)(wb + jb) : v4f{0.0f, 0.0f, 0.0f, 0.0f};
-            } else {
-#pragma unroll
-                for (int s2 = 0; s2 < 4; ++s2) {
-                    const bool ok = jb + s2 < c1;
-                    xa[u][s2] = (va && ok) ? wa[jb + s2] : 0.0f;
-                    xb[u][s2] = (vb && ok) ? wb[jb + s2] : 0.0f;
-                }
-            }
-        }
-#pragma unroll
-        for (int u = 0; u < U; ++u)
-#pragma unroll
-            for (int s2 = 0; s2 < 4; ++s2)
-                acc = __builtin_amdgcn_mfma_f64_16x16x4f64((double)xa[u][s2], (double)xb[u][s2], acc,
-                                                           0, 0, 0);
-    }
-    // acc[v] = B[16 ta + 4 v + lk][16 tb + li]
-    if (wave > 0)
-#pragma unroll
-        for (int v = 0; v < 4; ++v) part[wave - 1][v * 64 + lane] = acc[v];
-    __syncthreads();
-    if (wave == 0) {
-#pragma unroll
-        for (int v = 0; v < 4; ++v) {
-            double b = acc[v];
-#pragma unroll
-            for (int w2 = 0; w2 < NW - 1; ++w2) b += part[w2][v * 64 + lane];
-            const int a1 = 16 * ta + 4 * v + lk, b1 = 16 * tb + li;
-            // a diagonal tile keeps exact symmetry: its lower half copies the upper
-            if (a1 < r && b1 < r && (ta != tb || a1 <= b1)) {
-                J.Bd[a1 * r + b1] = b;
-                J.Bd[b1 * r + a1] = b;
-            }
-        }
-    }
-    if (!with_resid || jt.y != 0) return;
+template <int NT>
+__device__ __forceinline__ void log_residual(const Job &J, double rs, double *red) {
     rs = block_sum_f64<NT>(rs, red);
-    if (tid == 0) {
+    if (threadIdx.x == 0) {
         DevState *st = J.st;
         const double nm = *J.normM2;
         const double e2 = nm + rs;
@@ -904,6 +826,140 @@ __global__ __launch_bounds__(64 * kGramWWaves) void k_gram_w(const Job *__restri
             if (J.hstop) *J.hstop = 1;
         }
     }
+}
+
+// ---------------------------------------------------------------------------
+// B = W W^T in FP64 from the FP32 W (r x n, row-major): block = (upper tile
+// (ta, tb), column segment); its 8 waves split the segment into contiguous
+// ranges and run FP64 MFMAs (products of FP32 values are exact), lane (li, lk)
+// supplying columns j0 + 4 lk + s of rows 16 ta + li and 16 tb + li to MFMA s;
+// the loads of 8 16-column steps go out together, and steps wholly past the
+// range are skipped (their operands would be zero).  The wave partials are
+// added in LDS in wave order.  One segment (J.gseg = 1): the block writes its
+// tile of B, and with with_resid block 0 also logs the iteration's residual.
+// Several: the block stores its partial tile and k_gram_sum adds them.
+// ---------------------------------------------------------------------------
+constexpr int kGramWWaves = 8;
+
+__global__ __launch_bounds__(64 * kGramWWaves) void k_gram_w(const Job *__restrict__ jobs,
+                                                             const int2 *__restrict__ bmap,
+                                                             int with_resid) {
+    constexpr int NW = kGramWWaves, NT = 64 * NW, U = 8;
+    __shared__ double part[NW - 1][256];
+    __shared__ double red[NW];
+    const int2 jt = block_job(bmap);
+    const Job &J = jobs[jt.x];
+    if (J.st->stop) return;
+    const int r = J.r, rpad = J.rpad;
+    const int64_t n = J.n;
+    const int gseg = J.gseg;
+    const int tile = jt.y / gseg, seg = jt.y % gseg;
+    int ta, tb;
+    gram_tile_pair(tile, rpad / 16, ta, tb);
+    const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+    const int li = lane & 15, lk = lane >> 4;
+    const int ka = 16 * ta + li, kb = 16 * tb + li;
+    const auto W = to_global(J.W);
+    const gmem<const float> *wa = W + (int64_t)(ka < r ? ka : 0) * n;
+    const gmem<const float> *wb = W + (int64_t)(kb < r ? kb : 0) * n;
+    const bool va = ka < r, vb = kb < r;
+    const bool vec = (n & 3) == 0 && ((uintptr_t)J.W & 15) == 0;
+    // residual (block 0, one segment): the W-update partials of the previous kernel
+    const bool resid = with_resid && gseg == 1 && jt.y == 0;
+    double rs = 0.0;
+    if (resid)
+        for (int i = tid; i < J.nF; i += NT) rs += to_global(J.rparts)[i];
+    // the segment's columns, then columns per wave, multiples of 16
+    const int64_t slen = (n + 16 * gseg - 1) / (16 * gseg) * 16;
+    const int64_t s0 = seg * slen, s1 = (s0 + slen < n) ? s0 + slen : n;
+    const int64_t per = (slen + 16 * NW - 1) / (16 * NW) * 16;
+    const int64_t c0 = s0 + wave * per, c1 = (c0 + per < s1) ? c0 + per : s1;
+    v4d acc = {0.0, 0.0, 0.0, 0.0};
+    for (int64_t jg = c0; jg < c1; jg += 16 * U) {
+        v4f xa[U], xb[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const int64_t jb = jg + 16 * u + 4 * lk;
+            if (vec && jb + 3 < c1) {
+                xa[u] = va ? *(gmem<const v4f> *)(wa + jb) : v4f{0.0f, 0.0f, 0.0f, 0.0f};
+                xb[u] = vb ? *(gmem<const v4f> *)(wb + jb) : v4f{0.0f, 0.0f, 0.0f, 0.0f};
+            } else {
+#pragma unroll
+                for (int s2 = 0; s2 < 4; ++s2) {
+                    const bool ok = jb + s2 < c1;
+                    xa[u][s2] = (va && ok) ? wa[jb + s2] : 0.0f;
+                    xb[u][s2] = (vb && ok) ? wb[jb + s2] : 0.0f;
+                }
+            }
+        }
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            if (jg + 16 * u >= c1) break;   // uniform: the rest of the batch is zero
+#pragma unroll
+            for (int s2 = 0; s2 < 4; ++s2)
+                acc = __builtin_amdgcn_mfma_f64_16x16x4f64((double)xa[u][s2], (double)xb[u][s2], acc,
+                                                           0, 0, 0);
+        }
+    }
+    // acc[v] = B[16 ta + 4 v + lk][16 tb + li]
+    if (wave > 0)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) part[wave - 1][v * 64 + lane] = acc[v];
+    __syncthreads();
+    if (wave == 0) {
+        double *pt = J.bparts + ((int64_t)tile * gseg + seg) * 256;
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+            double b = acc[v];
+#pragma unroll
+            for (int w2 = 0; w2 < NW - 1; ++w2) b += part[w2][v * 64 + lane];
+            if (gseg > 1) {
+                pt[v * 64 + lane] = b;
+                continue;
+            }
+            const int a1 = 16 * ta + 4 * v + lk, b1 = 16 * tb + li;
+            // a diagonal tile keeps exact symmetry: its lower half copies the upper
+            if (a1 < r && b1 < r && (ta != tb || a1 <= b1)) {
+                J.Bd[a1 * r + b1] = b;
+                J.Bd[b1 * r + a1] = b;
+            }
+        }
+    }
+    if (resid) log_residual<NT>(J, rs, red);
+}
+
+// B from the segment partials of k_gram_w (jobs with J.gseg > 1; others
+// return): block = upper tile, thread = tile entry, segments added in order;
+// with_resid: block 0 also logs the iteration's residual.
+__global__ __launch_bounds__(256) void k_gram_sum(const Job *__restrict__ jobs,
+                                                  const int2 *__restrict__ bmap, int with_resid) {
+    __shared__ double red[4];
+    const int2 jt = block_job(bmap);
+    const Job &J = jobs[jt.x];
+    if (J.gseg <= 1 || J.st->stop) return;
+    const int r = J.r, gseg = J.gseg, tid = threadIdx.x;
+    int ta, tb;
+    gram_tile_pair(jt.y, J.rpad / 16, ta, tb);
+    const bool resid = with_resid && jt.y == 0;
+    double rs = 0.0;
+    if (resid)
+        for (int i = tid; i < J.nF; i += 256) rs += to_global(J.rparts)[i];
+    const auto p0 = to_global(J.bparts) + (int64_t)jt.y * gseg * 256 + tid;
+    double t[kGramSegMax];
+#pragma unroll
+    for (int q = 0; q < kGramSegMax; ++q) t[q] = q < gseg ? p0[q * 256] : 0.0;
+    double b = 0.0;
+#pragma unroll
+    for (int q = 0; q < kGramSegMax; ++q)
+        if (q < gseg) b += t[q];
+    // entry tid = v * 64 + lane of the tile layout: B[16 ta + 4 v + lk][16 tb + li]
+    const int v = tid >> 6, lane = tid & 63;
+    const int a1 = 16 * ta + 4 * v + (lane >> 4), b1 = 16 * tb + (lane & 15);
+    if (a1 < r && b1 < r && (ta != tb || a1 <= b1)) {
+        J.Bd[a1 * r + b1] = b;
+        J.Bd[b1 * r + a1] = b;
+    }
+    if (resid) log_residual<256>(J, rs, red);
 }
 
 // ---------------------------------------------------------------------------
@@ -1217,6 +1273,13 @@ hipError_t launch_gram_w_jobs(int with_resid, const Job *jobs, const int2 *bmap,
                               hipStream_t s) {
     if (blocks <= 0) return hipSuccess;
     k_gram_w<<<blocks, 64 * kGramWWaves, 0, s>>>(jobs, bmap, with_resid);
+    return hipGetLastError();
+}
+
+hipError_t launch_gram_sum_jobs(int with_resid, const Job *jobs, const int2 *bmap, int blocks,
+                                hipStream_t s) {
+    if (blocks <= 0) return hipSuccess;
+    k_gram_sum<<<blocks, 256, 0, s>>>(jobs, bmap, with_resid);
     return hipGetLastError();
 }
 
