@@ -278,14 +278,16 @@ nmf_status prepare_bf16(Ctx &c) {
     const Job &J0 = c.jobs[0];
     for (size_t l = 0; l < p.lv.size(); ++l) {
         const Job &J = c.jobs[l];
-        NMF_HIP(launch_pack_bf16(c.M[l], c.ldm[l], J.m, J.n, const_cast<uint16_t *>(J.Mbp),
-                                 J.npad, c.s));
-        if (J.stream)
-            NMF_HIP(launch_pack_bf16_cpanel(c.M[l], c.ldm[l], J.m, J.n,
-                                            const_cast<uint16_t *>(J.Mbc), J.mpad, c.s));
-        else
+        if (J.stream) {   // both layouts in one pass over M_l
+            NMF_HIP(launch_pack_bf16_both(c.M[l], c.ldm[l], J.m, J.n,
+                                          const_cast<uint16_t *>(J.Mbp), J.npad,
+                                          const_cast<uint16_t *>(J.Mbc), J.mpad, c.s));
+        } else {
+            NMF_HIP(launch_pack_bf16(c.M[l], c.ldm[l], J.m, J.n, const_cast<uint16_t *>(J.Mbp),
+                                     J.npad, c.s));
             NMF_HIP(launch_to_bf16_cols(c.M[l], c.ldm[l], J.m, J.n,
                                         const_cast<uint16_t *>(J.Mbc), J.mpad, J.n, c.s));
+        }
         NMF_HIP(launch_to_bf16_cols(c.V[l], J.m, J.m, J.r, J.Vb, J.mpad, J.rpad, c.s));
     }
     // W (r x n row-major) read as n x r column-major: Wb is rpad x npad row-major

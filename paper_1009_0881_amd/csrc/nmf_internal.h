@@ -166,10 +166,12 @@ hipError_t launch_to_bf16_cols(const float *X, int64_t ldx, int64_t rows, int64_
                                uint16_t *Y, int64_t rows_pad, int64_t cols_pad, hipStream_t s);
 hipError_t launch_pack_bf16(const float *X, int64_t ldx, int64_t rows, int64_t cols, uint16_t *Y,
                             int64_t cols_pad, hipStream_t s);
-// pack_bf16_cpanel: the column-panelled C-pass layout of streaming levels
-// (rows_pad a multiple of 32, columns padded to 16).
-hipError_t launch_pack_bf16_cpanel(const float *X, int64_t ldx, int64_t rows, int64_t cols,
-                                   uint16_t *Y, int64_t rows_pad, hipStream_t s);
+// pack_bf16_both (streaming levels): the K-packed copy with cols_pad columns
+// and the column-panelled C-pass copy (rows_pad rows, columns padded to 16) in
+// one pass over X; rows_pad and cols_pad multiples of 32.
+hipError_t launch_pack_bf16_both(const float *X, int64_t ldx, int64_t rows, int64_t cols,
+                                 uint16_t *Ya, int64_t cols_pad, uint16_t *Yc, int64_t rows_pad,
+                                 hipStream_t s);
 
 hipError_t launch_gram(int rpad, int r, int64_t L, const float *X, int64_t ldx, int parts,
                        int64_t chunk, double *gparts, double *Gd, float *Gf, const int32_t *stop,

@@ -310,34 +310,73 @@ __global__ __launch_bounds__(256) void k_pack_bf16(const float *__restrict__ X, 
     *reinterpret_cast<uint4 *>(Y + e * 8) = w;
 }
 
-// Column-panelled copy for the streaming C-pass: element (i, j) of X at
-// ((j/16 * S + i/32) * 4 + i%32/8) * 128 + j%16 * 8 + i%8, S = rows_pad / 32,
-// zero outside.  One thread per 8-row group of one column; consecutive threads
-// take consecutive columns of a panel, so each writes 16 contiguous bytes next
-// to its neighbour's.
-__global__ __launch_bounds__(256) void k_pack_bf16_cpanel(const float *__restrict__ X, int64_t ldx,
-                                                          int64_t rows, int64_t cols,
-                                                          uint16_t *__restrict__ Y,
-                                                          int64_t rows_pad, int64_t total) {
-    const int64_t e = blockIdx.x * (int64_t)256 + threadIdx.x;   // (panel, step, group, col)
-    if (e >= total) return;
-    const int jj = (int)(e & 15);
-    const int64_t q = e >> 4;                 // (panel * S + step) * 4 + group
-    const int64_t S = rows_pad / 32;
-    const int64_t pst = q >> 2, panel = pst / S, step = pst - panel * S;
-    const int64_t j = panel * 16 + jj, i0 = step * 32 + (q & 3) * 8;
-    uint16_t v[8];
+// Both BF16 copies of a streaming level in one pass over X: the K-packed
+// copy of k_pack_bf16 (Ya: rows16 x cols_pad) and the column-panelled copy
+// for the streaming C-pass (Yc: element (i, j) at ((j/16 * S + i/32) * 4 +
+// i%32/8) * 128 + j%16 * 8 + i%8, S = rows_pad / 32, columns up to cols
+// rounded up to 16), zero outside X.
+// Block = 32 x 32 tile (rows_pad and cols_pad are multiples of 32 and cover
+// both copies): 8 lanes load a column's 32 rows (128 contiguous bytes, float4
+// where aligned), the tile goes through LDS as BF16, then 128 threads write
+// its two 1 KB panel-steps of Yc and 128 its eight 256-byte (row panel,
+// column group) runs of Ya, 16 bytes each.
+__global__ __launch_bounds__(256) void k_pack_bf16_both(const float *__restrict__ X, int64_t ldx,
+                                                        int64_t rows, int64_t cols,
+                                                        uint16_t *__restrict__ Ya,
+                                                        int64_t cols_pad,
+                                                        uint16_t *__restrict__ Yc,
+                                                        int64_t rows_pad) {
+    __shared__ uint16_t T[32 * 32];   // T[c * 32 + r]
+    const int64_t ntr = rows_pad / 32;
+    const int64_t rt = blockIdx.x % ntr, ct = blockIdx.x / ntr;
+    const int64_t i0 = rt * 32, j0 = ct * 32;
+    const int t = threadIdx.x;
+    {
+        const int c = t >> 3, r = (t & 7) * 4;
+        const int64_t j = j0 + c, i = i0 + r;
+        uint16_t v[4];
+        const float *xc = X + j * ldx + i;
+        if (j < cols && i + 3 < rows && (ldx & 3) == 0 && ((uintptr_t)xc & 15) == 0) {
+            const float4 f = *reinterpret_cast<const float4 *>(xc);
+            v[0] = bf16_rne(f.x); v[1] = bf16_rne(f.y); v[2] = bf16_rne(f.z); v[3] = bf16_rne(f.w);
+        } else {
 #pragma unroll
-    for (int u = 0; u < 8; ++u) {
-        const int64_t i = i0 + u;
-        v[u] = (i < rows && j < cols) ? bf16_rne(X[j * ldx + i]) : (uint16_t)0;
+            for (int u = 0; u < 4; ++u)
+                v[u] = (j < cols && i + u < rows) ? bf16_rne(xc[u]) : (uint16_t)0;
+        }
+#pragma unroll
+        for (int u = 0; u < 4; ++u) T[c * 32 + r + u] = v[u];
     }
-    uint4 w;
-    w.x = v[0] | ((uint32_t)v[1] << 16);
-    w.y = v[2] | ((uint32_t)v[3] << 16);
-    w.z = v[4] | ((uint32_t)v[5] << 16);
-    w.w = v[6] | ((uint32_t)v[7] << 16);
-    *reinterpret_cast<uint4 *>(Y + e * 8) = w;
+    __syncthreads();
+    uint16_t w[8];
+    if (t < 128) {   // Yc: panel pan of the tile, entry e of its 1 KB block
+        const int pan = t >> 6, e = t & 63, g = e >> 4, jj = e & 15;
+        const int64_t P = ct * 2 + pan;
+        if (P * 16 >= cols) return;   // past the panelled columns
+#pragma unroll
+        for (int u = 0; u < 8; ++u) w[u] = T[(pan * 16 + jj) * 32 + g * 8 + u];
+        const int64_t S = rows_pad / 32;
+        uint4 o;
+        o.x = w[0] | ((uint32_t)w[1] << 16);
+        o.y = w[2] | ((uint32_t)w[3] << 16);
+        o.z = w[4] | ((uint32_t)w[5] << 16);
+        o.w = w[6] | ((uint32_t)w[7] << 16);
+        *reinterpret_cast<uint4 *>(Yc + (P * S + rt) * 512 + e * 8) = o;
+    } else {         // Ya: run (row panel pp, column group gg) of the tile, row ii
+        const int tt = t - 128, ch = tt >> 4, pp = ch >> 2, gg = ch & 3, ii = tt & 15;
+        const int64_t prow = rt * 2 + pp;
+        const int64_t rows16 = (rows + 15) / 16 * 16;
+        if (prow * 16 >= rows16) return;
+#pragma unroll
+        for (int q = 0; q < 8; ++q) w[q] = T[(gg * 8 + q) * 32 + pp * 16 + ii];
+        const int64_t G = cols_pad / 8, g8 = ct * 4 + gg;
+        uint4 o;
+        o.x = w[0] | ((uint32_t)w[1] << 16);
+        o.y = w[2] | ((uint32_t)w[3] << 16);
+        o.z = w[4] | ((uint32_t)w[5] << 16);
+        o.w = w[6] | ((uint32_t)w[7] << 16);
+        *reinterpret_cast<uint4 *>(Ya + ((prow * G + g8) * 16 + ii) * 8) = o;
+    }
 }
 
 // ---- grouped setup kernels (one launch over many problems) ------------------
@@ -506,13 +545,15 @@ hipError_t launch_pack_bf16(const float *X, int64_t ldx, int64_t rows, int64_t c
     return hipGetLastError();
 }
 
-hipError_t launch_pack_bf16_cpanel(const float *X, int64_t ldx, int64_t rows, int64_t cols,
-                                   uint16_t *Y, int64_t rows_pad, hipStream_t s) {
-    const int64_t total = (cols + 15) / 16 * (rows_pad / 32) * 4 * 16;
-    if (total <= 0) return hipSuccess;
-    if (rows_pad % 32 != 0 || rows_pad < rows) return hipErrorInvalidValue;
-    k_pack_bf16_cpanel<<<(unsigned)((total + 255) / 256), 256, 0, s>>>(X, ldx, rows, cols, Y,
-                                                                       rows_pad, total);
+hipError_t launch_pack_bf16_both(const float *X, int64_t ldx, int64_t rows, int64_t cols,
+                                 uint16_t *Ya, int64_t cols_pad, uint16_t *Yc, int64_t rows_pad,
+                                 hipStream_t s) {
+    if (rows <= 0 || cols <= 0) return hipSuccess;
+    if (rows_pad % 32 != 0 || rows_pad < rows || cols_pad % 32 != 0 || cols_pad < cols)
+        return hipErrorInvalidValue;
+    const int64_t blocks = rows_pad / 32 * (cols_pad / 32);
+    k_pack_bf16_both<<<(unsigned)blocks, 256, 0, s>>>(X, ldx, rows, cols, Ya, cols_pad, Yc,
+                                                      rows_pad);
     return hipGetLastError();
 }
 
