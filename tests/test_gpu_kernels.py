@@ -49,6 +49,22 @@ def test_restrict_and_prolong_random_images(xfer, hw):
     np.testing.assert_allclose(got.cpu().numpy().T.astype(np.float64), want, rtol=2 ** -23, atol=0)
 
 
+@pytest.mark.parametrize("hw,ncols", [((64, 64), 37), ((31, 40), 5), ((256, 256), 9),
+                                      ((130, 132), 3)])
+def test_restrict_fw_four_pixel_path(hw, ncols):
+    """Full-weighting restriction with w and the strides multiples of 4 runs four coarse
+    pixels per thread (interior rows loaded as float4); border groups and an odd column
+    count take the per-pixel path.  Same bar as above against the oracle."""
+    h, w = hw
+    say("restrict fw4", hw, ncols)
+    rng = np.random.default_rng(h * 7 + w + ncols)
+    X = rng.uniform(size=(h * w, ncols)).astype(np.float32)
+    Xd = torch.from_numpy(np.ascontiguousarray(X.T)).cuda()
+    got = P.restrict(Xd, h, w, "fw").cpu().numpy().T.astype(np.float64)
+    want = O.restrict_images(X.astype(np.float64), h, w, P.XFERS["fw"])
+    np.testing.assert_allclose(got, want, rtol=2 ** -23, atol=0)
+
+
 @pytest.mark.parametrize("r,L", [(1, 5), (10, 500), (17, 1000), (40, 10304), (50, 2000),
                                  (64, 333), (33, 65536)])
 def test_gram_fp64(r, L):
