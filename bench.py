@@ -51,10 +51,10 @@ SWEEP_SOURCES = ("sweep.hip", "sweep_device.h", "device_common.h", "job.h")
 STREAM_SOURCES = SWEEP_SOURCES + ("stream.hip",)
 TRAFFIC = {
     ("orl", "fp32"): {
-        "sha": "2dd8ec1be100460f",
+        "sha": "39797302b0054ed5",
         "files": SWEEP_SOURCES,
-        "apass": {10304: 14697620, 2576: 6152577, 644: 2452091},
-        "cpass_partial": {10304: 17393499, 2576: 8894826, 644: 3740044},
+        "apass": {10304: 14704341, 2576: 6151554, 644: 2453115},
+        "cpass_partial": {10304: 17388031, 2576: 8887660, 644: 3732877},
     },
 }
 
