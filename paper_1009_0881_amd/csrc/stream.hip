@@ -418,21 +418,33 @@ __device__ __forceinline__ double quad_sum(double v) {
 // (a_k - sum_l x_l G_kl) / G_kk), formed by the lane that owns k; MU forms all
 // the sums from the old x, then x_k <- x_k a_k / sum_l x_l G_kl.  Steps with
 // 1/G_kk = 0 (k >= r, or G_kk = 0) leave x_k as it is; steps k >= r are
-// skipped.  The loads of Gram row
-// k wait for the sum of step k - 2, so that at most two rows are in flight.
+// skipped: each step runs the next one only while k + 1 < r (a nest of
+// uniform branches).  Step k reads the lane's part of Gram row k + 2 (with
+// a_{k+2} and 1/G_{k+2,k+2}) behind the previous step's sum and holds it two
+// steps in registers, so LDS latency stays off the chain of dependent sums;
+// without that, each step's reads waited behind its own branch.
 template <int RPAD, int MODE>
 __device__ __forceinline__ void quad_row_update(double (&x)[RPAD / 4], const double *arow,
                                                 const double *G, const double *gi, int p, int r) {
     typedef double v2d __attribute__((ext_vector_type(2)));
-    constexpr int EP = RPAD / 4;
-    double prev[2] = {0.0, 0.0};
-    auto dot = [&](int k, double dep) {
-        const double *g = G + ordered_after(k * RPAD + EP * p, dep);
+    constexpr int EP = RPAD / 4, NV = EP / 2, PD = 2;
+    struct Row {
+        v2d g[NV];
+        double a, gk;
+    };
+    auto load_row = [&](int k, double dep, Row &dst) {
+        const int ko = ordered_after(k, dep);
+        const double *g = G + ko * RPAD + EP * p;
+#pragma unroll
+        for (int v = 0; v < NV; ++v) dst.g[v] = *(const lmem<v2d> *)(g + 2 * v);
+        dst.a = arow[ko];
+        dst.gk = gi[ko];
+    };
+    auto dot = [&](const Row &row) {
         double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
 #pragma unroll
         for (int i = 0; i < EP; i += 4) {
-            const v2d ga = *(const lmem<v2d> *)(g + i);
-            const v2d gb = *(const lmem<v2d> *)(g + i + 2);
+            const v2d ga = row.g[i / 2], gb = row.g[i / 2 + 1];
             s0 = fma_t(x[i], ga[0], s0);
             s1 = fma_t(x[i + 1], ga[1], s1);
             s2 = fma_t(x[i + 2], gb[0], s2);
@@ -440,32 +452,42 @@ __device__ __forceinline__ void quad_row_update(double (&x)[RPAD / 4], const dou
         }
         return quad_sum((s0 + s1) + (s2 + s3));
     };
-    if constexpr (MODE == MODE_HALS) {
-        static_for<RPAD>([&](auto k_c) {
-            constexpr int k = decltype(k_c)::value, ik = k % EP;
-            if (k >= r) return;   // uniform: steps k >= r change nothing (1/G_kk = 0)
-            const double dep = prev[k & 1];
-            // a_k and 1/G_kk read with Gram row k (not hoisted, not behind a branch)
-            const int ko = ordered_after(k, dep);
-            const double ak = arow[ko], gk = gi[ko];
-            const double d = dot(k, dep);
-            prev[k & 1] = d;
+    if (r <= 0) return;
+    Row rows[PD];
+#pragma unroll
+    for (int i = 0; i < PD; ++i) load_row(i < RPAD ? i : 0, 0.0, rows[i]);
+    double dprev = 0.0;
+    double den[MODE == MODE_HALS ? 1 : EP];
+#pragma unroll
+    for (int i = 0; i < (MODE == MODE_HALS ? 1 : EP); ++i) den[i] = 0.0;
+    auto step = [&](auto self, auto k_c) -> void {
+        constexpr int k = decltype(k_c)::value, ik = k % EP;
+        Row rnew;
+        if constexpr (k + PD < RPAD) {
+            load_row(k + PD, dprev, rnew);
+            // keep the reads here, ahead of this step's sum
+            __builtin_amdgcn_sched_barrier(0);
+        }
+        const double d = dot(rows[0]);
+        dprev = d;
+        if constexpr (MODE == MODE_HALS) {
+            const double ak = rows[0].a, gk = rows[0].gk;
             const double c = x[ik] + (ak - d) * gk;
             const double cp = c > 0.0 ? c : 0.0;
             const double nx = gk > 0.0 ? cp : x[ik];
             x[ik] = p == k / EP ? nx : x[ik];
-        });
-    } else {
-        double den[EP];
-#pragma unroll
-        for (int i = 0; i < EP; ++i) den[i] = 0.0;
-        static_for<RPAD>([&](auto k_c) {
-            constexpr int k = decltype(k_c)::value, ik = k % EP;
-            if (k >= r) return;   // uniform: den_k is used only for k < r
-            const double d = dot(k, prev[k & 1]);
-            prev[k & 1] = d;
+        } else {
             den[ik] = p == k / EP ? d : den[ik];
-        });
+        }
+#pragma unroll
+        for (int i = 0; i + 1 < PD; ++i) rows[i] = rows[i + 1];
+        if constexpr (k + PD < RPAD) rows[PD - 1] = rnew;
+        if constexpr (k + 1 < RPAD) {
+            if (k + 1 < r) self(self, std::integral_constant<int, k + 1>{});
+        }
+    };
+    step(step, std::integral_constant<int, 0>{});
+    if constexpr (MODE != MODE_HALS) {
 #pragma unroll
         for (int i = 0; i < EP; ++i) {
             const int k = EP * p + i;

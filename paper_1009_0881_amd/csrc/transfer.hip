@@ -125,92 +125,6 @@ __global__ __launch_bounds__(256) void k_restrict(const float *__restrict__ X, i
     }
 }
 
-constexpr int kRestrict4Cols = 2;   // columns per thread of k_restrict_fw4
-
-// FW restriction, four adjacent coarse pixels of a coarse row per thread (w
-// and the column strides multiples of 4, X and Y 16-byte aligned).  Groups
-// inside the image load each of their 3 fine rows as one float and two float4
-// (fine x = 2 cx0 - 1 .. 2 cx0 + 7) instead of nine scattered floats per pixel,
-// and store the four results as one float4; the taps, the FP64 sums and their
-// order are those of k_restrict, so the result is the same bits.  Groups on
-// the border take k_restrict's per-pixel path.
-__global__ __launch_bounds__(256) void k_restrict_fw4(const float *__restrict__ X, int64_t ldx,
-                                                      float *__restrict__ Y, int h, int w, int hc,
-                                                      int wc, int64_t ncols,
-                                                      const int32_t *stop) {
-    if (stopped(stop)) return;
-    constexpr int RC = kRestrict4Cols;
-    const int wc4 = (wc + 3) / 4;
-    const int q = blockIdx.x * blockDim.x + threadIdx.x;
-    if (q >= hc * wc4) return;
-    const int cy = q / wc4, cx0 = (q - cy * wc4) * 4;
-    const int mc = hc * wc;
-    const Taps ty = restrict_taps(cy, h, NMF_XFER_FW);
-    // every tap of the four pixels inside the image (then also cx0 + 3 < wc)
-    const bool inner = cy >= 1 && 2 * cy + 1 < h && cx0 >= 1 && 2 * (cx0 + 3) + 1 < w;
-    const bool vst = (wc & 3) == 0 && cx0 + 3 < wc;
-    for (int64_t c0 = (int64_t)blockIdx.y * RC; c0 < ncols; c0 += (int64_t)gridDim.y * RC) {
-        float out[RC][4];
-        if (inner) {
-            float win[RC][3][9];
-#pragma unroll
-            for (int c = 0; c < RC; ++c) {
-                const int64_t col = c0 + c < ncols ? c0 + c : ncols - 1;
-                const auto img = to_global(X + col * ldx);
-#pragma unroll
-                for (int a = 0; a < 3; ++a) {
-                    const int64_t b0 = (int64_t)ty.idx[a] * w + 2 * cx0 - 1;
-                    const float4 f = *(gmem<const float4> *)(img + b0 + 1);
-                    const float4 g = *(gmem<const float4> *)(img + b0 + 5);
-                    win[c][a][0] = img[b0];
-                    win[c][a][1] = f.x; win[c][a][2] = f.y; win[c][a][3] = f.z; win[c][a][4] = f.w;
-                    win[c][a][5] = g.x; win[c][a][6] = g.y; win[c][a][7] = g.z; win[c][a][8] = g.w;
-                }
-            }
-#pragma unroll
-            for (int u = 0; u < 4; ++u) {
-                // interior taps: fine x = 2cx - 1, 2cx, 2cx + 1 = window 2u, 2u + 1, 2u + 2
-                const Taps tx = restrict_taps(cx0 + u, w, NMF_XFER_FW);
-#pragma unroll
-                for (int c = 0; c < RC; ++c) {
-                    double acc = 0.0;
-#pragma unroll
-                    for (int a = 0; a < 3; ++a) {
-                        double row = 0.0;
-#pragma unroll
-                        for (int b = 0; b < 3; ++b) row += tx.wt[b] * (double)win[c][a][2 * u + b];
-                        acc += ty.wt[a] * row;
-                    }
-                    out[c][u] = (float)acc;
-                }
-            }
-        } else {
-#pragma unroll
-            for (int u = 0; u < 4; ++u) {
-                const int cx = cx0 + u < wc ? cx0 + u : wc - 1;
-                const Taps tx = restrict_taps(cx, w, NMF_XFER_FW);
-#pragma unroll
-                for (int c = 0; c < RC; ++c) {
-                    const int64_t col = c0 + c < ncols ? c0 + c : ncols - 1;
-                    out[c][u] = stencil(X + col * ldx, w, ty, tx);
-                }
-            }
-        }
-#pragma unroll
-        for (int c = 0; c < RC; ++c) {
-            if (c0 + c >= ncols) break;
-            float *yo = Y + (c0 + c) * mc + (int64_t)cy * wc + cx0;
-            if (vst) {
-                *(gmem<float4> *)to_global(yo) = make_float4(out[c][0], out[c][1], out[c][2], out[c][3]);
-            } else {
-#pragma unroll
-                for (int u = 0; u < 4; ++u)
-                    if (cx0 + u < wc) yo[u] = out[c][u];
-            }
-        }
-    }
-}
-
 __global__ __launch_bounds__(256) void k_prolong(const float *__restrict__ Y,
                                                  float *__restrict__ X, int h, int w, int hc,
                                                  int wc, int64_t ncols, int xfer,
@@ -540,14 +454,6 @@ hipError_t launch_restrict(int xfer, int h, int w, int64_t ncols, const float *X
     const int hc = (h + 1) / 2, wc = (w + 1) / 2;
     const int mc = hc * wc;
     if (mc == 0 || ncols == 0) return hipSuccess;
-    if (xfer == NMF_XFER_FW && (w & 3) == 0 && (ldx & 3) == 0 && (mc & 3) == 0 &&
-        ((uintptr_t)X & 15) == 0 && ((uintptr_t)Y & 15) == 0) {
-        const int64_t groups = (ncols + kRestrict4Cols - 1) / kRestrict4Cols;
-        const int q = hc * ((wc + 3) / 4);
-        const dim3 grid((q + 255) / 256, (unsigned)std::min<int64_t>(groups, 65535));
-        k_restrict_fw4<<<grid, 256, 0, s>>>(X, ldx, Y, h, w, hc, wc, ncols, stop);
-        return hipGetLastError();
-    }
     const int64_t groups = (ncols + kRestrictCols - 1) / kRestrictCols;
     const dim3 grid((mc + 255) / 256, (unsigned)std::min<int64_t>(groups, 65535));
     k_restrict<<<grid, 256, 0, s>>>(X, ldx, Y, h, w, hc, wc, ncols, xfer, stop);

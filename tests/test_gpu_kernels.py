@@ -51,12 +51,11 @@ def test_restrict_and_prolong_random_images(xfer, hw):
 
 @pytest.mark.parametrize("hw,ncols", [((64, 64), 37), ((31, 40), 5), ((256, 256), 9),
                                       ((130, 132), 3)])
-def test_restrict_fw_four_pixel_path(hw, ncols):
-    """Full-weighting restriction with w and the strides multiples of 4 runs four coarse
-    pixels per thread (interior rows loaded as float4); border groups and an odd column
-    count take the per-pixel path.  Same bar as above against the oracle."""
+def test_restrict_fw_larger_images(hw, ncols):
+    """Full-weighting restriction of larger and ragged images (up to the 256x256 grid),
+    odd column counts included.  Same bar as above against the oracle."""
     h, w = hw
-    say("restrict fw4", hw, ncols)
+    say("restrict fw", hw, ncols)
     rng = np.random.default_rng(h * 7 + w + ncols)
     X = rng.uniform(size=(h * w, ncols)).astype(np.float32)
     Xd = torch.from_numpy(np.ascontiguousarray(X.T)).cuda()
