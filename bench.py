@@ -534,8 +534,10 @@ def main() -> int:
     # the other two algorithms of the workload (ORL-shaped: all three), fewer solves
     others = {}
     if args.workload == "orl" and not args.no_other_algos and args.prec == "fp32":
-        for alg, cyc, bud in (("hals", "vc", 16), ("mu", "vc", 16), ("anls", "ni", 8),
-                              ("kl", "vc", 16)):
+        # each algorithm at the fastest 3-level schedule of a scan over cycles and
+        # budgets (MU needs many cheap coarse iterations, KL a nested-iteration start)
+        for alg, cyc, bud in (("hals", "vc", 16), ("mu", "vc", 256), ("anls", "ni", 8),
+                              ("kl", "ni", 32)):
             if alg == args.algo:
                 continue
             tgt = target_kl if alg == "kl" else target_frob
