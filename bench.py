@@ -70,9 +70,10 @@ def kernel_sources_sha(files) -> str:
 WORKLOADS = {
     "orl": dict(spec="CFG_ORL", h=112, w=92, levels=3, xfer="fw"),
     "small": dict(spec="CFG_SMALL", h=16, w=16, levels=2, xfer="block2"),
-    # budget: the FP32 V-cycle over 4 levels reaches the target fastest at T = 24
-    # here (T = 16 leaves too few coarse iterations, T >= 32 too many)
-    "large": dict(spec="CFG_LARGE", h=256, w=256, levels=4, xfer="fw", budget=24),
+    # budgets: the fastest V-cycle budgets over 4 levels in a scan of T (FP32:
+    # T = 16 leaves too few coarse iterations, T >= 32 too many; BF16 likewise)
+    "large": dict(spec="CFG_LARGE", h=256, w=256, levels=4, xfer="fw", budget=22,
+                  budget_bf16=20),
     # hyperspectral-like: 64x64 abundance maps x 256 smooth bands, r = 12; the
     # hierarchy halves the band count too (two-sided, Section 6.1)
     "spectral": dict(spec="CFG_SPECTRAL", h=64, w=64, levels=3, xfer="fw", two_sided=True),
@@ -394,7 +395,7 @@ def main() -> int:
     ap.add_argument("--levels", type=int, default=None)
     ap.add_argument("--budget", type=int, default=None,
                     help="schedule budget T in finest-iteration equivalents; default 16, "
-                         "24 for the FP32 256x256 workload")
+                         "22 (FP32) or 20 (BF16) for the 256x256 workload")
     ap.add_argument("--tau", type=float, default=1e-2)
     ap.add_argument("--seed", type=int, default=0)
     ap.add_argument("--max-fine-iters", type=int, default=20000)
@@ -414,8 +415,9 @@ def main() -> int:
         args.cycle = "wc" if args.workload == "orl" else "vc"
     if args.budget is None:
         args.budget = 16
-        if args.prec == "fp32" and args.workload in WORKLOADS:
-            args.budget = WORKLOADS[args.workload].get("budget", 16)
+        if args.workload in WORKLOADS:
+            key = "budget" if args.prec == "fp32" else "budget_bf16"
+            args.budget = WORKLOADS[args.workload].get(key, 16)
 
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); "
