@@ -391,7 +391,8 @@ def main() -> int:
     ap.add_argument("--cycle", default=None, choices=["ni", "vc", "fmg", "wc"],
                     help="schedule; default: W-cycle on the 112x92 workload (the fastest to the "
                          "target there among NI / VC / FMG / WC at T = 16, the others are "
-                         "reported beside it), V-cycle elsewhere")
+                         "reported beside it), nested iteration at T = 8 on the tensor "
+                         "workload, V-cycle elsewhere (each the fastest of a scan)")
     ap.add_argument("--levels", type=int, default=None)
     ap.add_argument("--budget", type=int, default=None,
                     help="schedule budget T in finest-iteration equivalents; default 16, "
@@ -412,9 +413,9 @@ def main() -> int:
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     args = ap.parse_args()
     if args.cycle is None:
-        args.cycle = "wc" if args.workload == "orl" else "vc"
+        args.cycle = {"orl": "wc", "tensor": "ni"}.get(args.workload, "vc")
     if args.budget is None:
-        args.budget = 16
+        args.budget = 8 if args.workload == "tensor" else 16
         if args.workload in WORKLOADS:
             key = "budget" if args.prec == "fp32" else "budget_bf16"
             args.budget = WORKLOADS[args.workload].get(key, 16)
