@@ -76,7 +76,9 @@ WORKLOADS = {
                   budget_bf16=20),
     # hyperspectral-like: 64x64 abundance maps x 256 smooth bands, r = 12; the
     # hierarchy halves the band count too (two-sided, Section 6.1)
-    "spectral": dict(spec="CFG_SPECTRAL", h=64, w=64, levels=3, xfer="fw", two_sided=True),
+    # budget: the fastest 3-level two-sided schedule of a scan (VC, T = 1)
+    "spectral": dict(spec="CFG_SPECTRAL", h=64, w=64, levels=3, xfer="fw", two_sided=True,
+                     budget=1),
 }
 
 
