@@ -66,8 +66,13 @@ Executor::Executor(char *base, const BatchArea &area, int capacity, hipStream_t 
 }
 
 Executor::~Executor() {
-    if (gexec_) (void)hipStreamSynchronize(s_);   // the captured tick may still run
+    // the captured tick or a look-ahead gather may still run
+    if (gexec_ || polls_[0].live || polls_[1].live) (void)hipStreamSynchronize(s_);
     drop_graph();
+    for (PendingPoll &pp : polls_) {
+        if (pp.ev) (void)hipEventDestroy(pp.ev);
+        if (pp.h) (void)hipHostFree(pp.h);
+    }
 }
 
 void Executor::drop_graph() {
@@ -494,14 +499,56 @@ nmf_status Executor::gather(std::vector<DevState> &hs) {
     return NMF_OK;
 }
 
-// Read every problem's device state; problems whose stop flag is set are done.
-nmf_status Executor::poll() {
-    std::vector<DevState> hs;
-    nmf_status st = gather(hs);
-    if (st != NMF_OK) return st;
-    for (size_t i = 0; i < insts_.size(); ++i)
-        if (hs[i].stop && insts_[i].stage != 2) insts_[i].stage = 2;
+// Queue a gather of the live problems' states into pp (pinned host memory).
+nmf_status Executor::poll_issue(PendingPoll &pp) {
+    nmf_plan_t plan = nullptr;
+    if (!pp.h) {
+        void *h = nullptr;
+        NMF_HIP(hipHostMalloc(&h, sizeof(DevState) * (size_t)std::max(capacity_, 1),
+                              hipHostMallocDefault));
+        pp.h = static_cast<DevState *>(h);
+        NMF_HIP(hipEventCreateWithFlags(&pp.ev, hipEventDisableTiming));
+    }
+    pp.ids.clear();
+    pp.sts.clear();
+    for (Inst &I : insts_) {
+        if (I.stage == 2) continue;
+        pp.ids.push_back(I.id);
+        pp.sts.push_back(I.c.st);
+    }
+    if (pp.sts.empty()) return NMF_OK;
+    NMF_HIP(hipMemcpyAsync(dstptr_, pp.sts.data(), sizeof(DevState *) * pp.sts.size(),
+                           hipMemcpyHostToDevice, s_));
+    NMF_HIP(launch_gather_states(dstptr_, (int)pp.sts.size(), dgather_, s_));
+    NMF_HIP(hipMemcpyAsync(pp.h, dgather_, sizeof(DevState) * pp.sts.size(),
+                           hipMemcpyDeviceToHost, s_));
+    NMF_HIP(hipEventRecord(pp.ev, s_));
+    pp.live = true;
     return NMF_OK;
+}
+
+// Wait for a queued gather; problems whose stop flag it shows are done.
+nmf_status Executor::poll_finish(PendingPoll &pp) {
+    nmf_plan_t plan = nullptr;
+    if (!pp.live) return NMF_OK;
+    NMF_HIP(hipEventSynchronize(pp.ev));
+    pp.live = false;
+    for (size_t k = 0; k < pp.ids.size(); ++k) {
+        const int i = slot_of(pp.ids[k]);
+        if (i >= 0 && pp.h[k].stop && insts_[i].stage != 2) insts_[i].stage = 2;
+    }
+    return NMF_OK;
+}
+
+// A tolerance check: queue this check's gather, then act on the previous one.
+nmf_status Executor::poll() {
+    PendingPoll &now = polls_[poll_next_];
+    PendingPoll &prev = polls_[poll_next_ ^ 1];
+    nmf_status st = poll_finish(now);   // (only if two checks ago was never read)
+    if (st != NMF_OK) return st;
+    if ((st = poll_issue(now)) != NMF_OK) return st;
+    poll_next_ ^= 1;
+    return poll_finish(prev);
 }
 
 bool Executor::all_done() const {

@@ -83,6 +83,20 @@ private:
     nmf_status gather(std::vector<DevState> &hs);
     int slot_of(int id) const;
     void drop_graph();
+    // Look-ahead tolerance checks: at a check the executor queues a gather of
+    // the live problems' states into pinned host memory and then waits only
+    // for the previous check's gather (issued check_every ticks earlier), so
+    // the stream never drains; problems learn of their stop one check late,
+    // and the ticks issued meanwhile return at once on the device stop flag.
+    struct PendingPoll {
+        DevState *h = nullptr;        // pinned host copy of the gathered states
+        hipEvent_t ev = nullptr;
+        std::vector<int> ids;         // problem ids, in gather order
+        std::vector<DevState *> sts;  // their state pointers (the upload source)
+        bool live = false;
+    };
+    nmf_status poll_issue(PendingPoll &pp);
+    nmf_status poll_finish(PendingPoll &pp);
 
     char *base_;
     BatchArea area_;
@@ -102,6 +116,8 @@ private:
     std::vector<int64_t> last_key_, graph_key_;
     hipGraphExec_t gexec_ = nullptr;
     int stable_ticks_ = 0;
+    PendingPoll polls_[2];
+    int poll_next_ = 0;
 };
 
 }  // namespace nmf
