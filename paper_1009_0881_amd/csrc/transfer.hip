@@ -95,32 +95,33 @@ __device__ __forceinline__ float stencil(const float *imgp, int rowlen, const Ta
     return (float)acc;
 }
 
-constexpr int kRestrictCols = 4;   // columns per thread of k_restrict
-
+// Columns per thread of k_restrict: 4 for wide matrices (M: fewer threads,
+// their loads batched), 1 for the r columns of a factor (more blocks for a
+// latency-bound launch).  The per-pixel arithmetic is the same either way.
+template <int RC>
 __global__ __launch_bounds__(256) void k_restrict(const float *__restrict__ X, int64_t ldx,
                                                   float *__restrict__ Y, int h, int w, int hc,
                                                   int wc, int64_t ncols, int xfer,
                                                   const int32_t *stop) {
     if (stopped(stop)) return;
-    // grid: x over coarse pixels, y over groups of kRestrictCols columns
-    // (strided); 32-bit pixel math.  A thread's columns are loaded together
-    // (9 taps each), then stored.
+    // grid: x over coarse pixels, y over groups of RC columns (strided);
+    // 32-bit pixel math.  A thread's columns are loaded together (9 taps
+    // each), then stored.
     const int mc = hc * wc;
     const int p = blockIdx.x * blockDim.x + threadIdx.x;
     if (p >= mc) return;
     const int cy = p / wc, cx = p - cy * wc;
     const Taps ty = restrict_taps(cy, h, xfer);
     const Taps tx = restrict_taps(cx, w, xfer);
-    for (int64_t c0 = (int64_t)blockIdx.y * kRestrictCols; c0 < ncols;
-         c0 += (int64_t)gridDim.y * kRestrictCols) {
-        float out[kRestrictCols];
+    for (int64_t c0 = (int64_t)blockIdx.y * RC; c0 < ncols; c0 += (int64_t)gridDim.y * RC) {
+        float out[RC];
 #pragma unroll
-        for (int u = 0; u < kRestrictCols; ++u) {
+        for (int u = 0; u < RC; ++u) {
             const int64_t col = c0 + u < ncols ? c0 + u : ncols - 1;
             out[u] = stencil(X + col * ldx, w, ty, tx);
         }
 #pragma unroll
-        for (int u = 0; u < kRestrictCols; ++u)
+        for (int u = 0; u < RC; ++u)
             if (c0 + u < ncols) Y[(c0 + u) * mc + p] = out[u];
     }
 }
@@ -454,9 +455,14 @@ hipError_t launch_restrict(int xfer, int h, int w, int64_t ncols, const float *X
     const int hc = (h + 1) / 2, wc = (w + 1) / 2;
     const int mc = hc * wc;
     if (mc == 0 || ncols == 0) return hipSuccess;
-    const int64_t groups = (ncols + kRestrictCols - 1) / kRestrictCols;
-    const dim3 grid((mc + 255) / 256, (unsigned)std::min<int64_t>(groups, 65535));
-    k_restrict<<<grid, 256, 0, s>>>(X, ldx, Y, h, w, hc, wc, ncols, xfer, stop);
+    if (ncols <= 64) {
+        const dim3 grid((mc + 255) / 256, (unsigned)ncols);
+        k_restrict<1><<<grid, 256, 0, s>>>(X, ldx, Y, h, w, hc, wc, ncols, xfer, stop);
+    } else {
+        const int64_t groups = (ncols + 3) / 4;
+        const dim3 grid((mc + 255) / 256, (unsigned)std::min<int64_t>(groups, 65535));
+        k_restrict<4><<<grid, 256, 0, s>>>(X, ldx, Y, h, w, hc, wc, ncols, xfer, stop);
+    }
     return hipGetLastError();
 }
 
