@@ -247,7 +247,7 @@ def bench_tensor(args) -> int:
 
     def plan(L):
         return P.Plan(m=m, n=n, h=spec.h, w=spec.w, r=r, levels=L, cycle=args.cycle, xfer="fw",
-                      tol=target, max_fine_iters=args.max_fine_iters, check_every=4, ntf_k=K)
+                      tol=target, max_fine_iters=args.max_fine_iters, check_every=args.check_every, ntf_k=K)
 
     def run(pl, ws, budget):
         A.copy_(A0)
@@ -400,6 +400,9 @@ def main() -> int:
                     help="schedule budget T in finest-iteration equivalents; default 16, "
                          "22 (FP32) or 20 (BF16) for the 256x256 workload")
     ap.add_argument("--tau", type=float, default=1e-2)
+    ap.add_argument("--check-every", type=int, default=2,
+                    help="single solves: finest-level iterations between host checks of the "
+                         "stop flag (look-ahead; fewer iterations queued past the stop than 4)")
     ap.add_argument("--seed", type=int, default=0)
     ap.add_argument("--max-fine-iters", type=int, default=20000)
     ap.add_argument("--prec", default="fp32", choices=["fp32", "bf16"],
@@ -473,7 +476,7 @@ def main() -> int:
     def make_plan(L, prec="fp32", two=False):
         return P.Plan(m=m, n=n, h=wl["h"], w=wl["w"], r=r, levels=L, algo=args.algo,
                       cycle=args.cycle, xfer=wl["xfer"], tol=target,
-                      max_fine_iters=args.max_fine_iters, check_every=4, prec=prec,
+                      max_fine_iters=args.max_fine_iters, check_every=args.check_every, prec=prec,
                       refine_iters=args.refine if prec == "bf16" else 0,
                       tile_cfg=parse_tile(args.tile), two_sided=two)
 
@@ -549,7 +552,7 @@ def main() -> int:
             def plan_for(L):
                 return P.Plan(m=m, n=n, h=wl["h"], w=wl["w"], r=r, levels=L, algo=alg, cycle=cyc,
                               xfer=wl["xfer"], tol=tgt, max_fine_iters=args.max_fine_iters,
-                              check_every=4)
+                              check_every=args.check_every)
             pm, ps = plan_for(levels), plan_for(1)
             wm, wsl = pm.workspace(), ps.workspace()
             tm, tsl = [], []
@@ -576,7 +579,7 @@ def main() -> int:
                 continue
             pc = P.Plan(m=m, n=n, h=wl["h"], w=wl["w"], r=r, levels=levels, algo=args.algo,
                         cycle=cyc, xfer=wl["xfer"], tol=target,
-                        max_fine_iters=args.max_fine_iters, check_every=4)
+                        max_fine_iters=args.max_fine_iters, check_every=args.check_every)
             wc_ = pc.workspace()
             tc = []
             for i in range(2 + 7):
