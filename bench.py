@@ -43,8 +43,10 @@ EXTRA_WORKLOADS = ("batch", "serve", "tensor")
 
 # HBM traffic per launch (bytes) of the sweep kernels, by (workload, precision),
 # kernel kind and level size m: rocprofv3 --pmc FETCH_SIZE and WRITE_SIZE
-# passes (KiB per dispatch), scaled by what the same counters read for a
-# 256 MiB device-to-device copy (FETCH_SIZE x2.0, WRITE_SIZE x1.0).  An entry
+# passes (KiB per dispatch, averaged over the dispatches that ran: launches
+# issued past a stop return at once and are left out), scaled by what the
+# same counters read for a 256 MiB device-to-device copy (FETCH_SIZE x2.0,
+# WRITE_SIZE x1.0).  An entry
 # holds while the SHA-256 prefix of the kernel sources its kernels come from
 # is `sha`; traffic is null otherwise.
 SWEEP_SOURCES = ("sweep.hip", "sweep_device.h", "device_common.h", "job.h")
@@ -53,8 +55,8 @@ TRAFFIC = {
     ("orl", "fp32"): {
         "sha": "39797302b0054ed5",
         "files": SWEEP_SOURCES,
-        "apass": {10304: 14704341, 2576: 6151554, 644: 2453115},
-        "cpass_partial": {10304: 17388031, 2576: 8887660, 644: 3732877},
+        "apass": {10304: 20996893, 2576: 6151550, 644: 2453114},
+        "cpass_partial": {10304: 24822840, 2576: 8887655, 644: 3732875},
     },
 }
 
