@@ -53,10 +53,10 @@ SWEEP_SOURCES = ("sweep.hip", "sweep_device.h", "device_common.h", "job.h")
 STREAM_SOURCES = SWEEP_SOURCES + ("stream.hip",)
 TRAFFIC = {
     ("orl", "fp32"): {
-        "sha": "39797302b0054ed5",
+        "sha": "1f7edef398eecb5a",
         "files": SWEEP_SOURCES,
-        "apass": {10304: 20996893, 2576: 6151550, 644: 2453114},
-        "cpass_partial": {10304: 24822840, 2576: 8887655, 644: 3732875},
+        "apass": {10304: 20994764, 2576: 6151281, 644: 2453004},
+        "cpass_partial": {10304: 24911220, 2576: 9514477, 644: 4031221},
     },
 }
 

@@ -1227,10 +1227,11 @@ hipError_t launch_apass_jobs(int mode, int rpad, int tm, const Job *jobs, const 
 // C-pass configurations: WC column tiles (and row groups) per wave, from the
 // plan (1: one wave per column tile over the whole chunk, for throughput; 2
 // or 4: shorter per-wave chains, for latency), and SB 16-row steps per FP32
-// load batch by rank class.
+// load batch by rank class (two up to r = 48: two steps of loads in flight
+// per wave; one above, where the wider operand tiles hold more registers).
 template <int RT>
 struct CpassCfg {
-    static constexpr int SB = RT <= 2 ? 2 : 1;
+    static constexpr int SB = RT <= 3 ? 2 : 1;
 };
 
 template <int RT, int WC>
