@@ -53,7 +53,7 @@ SWEEP_SOURCES = ("sweep.hip", "sweep_device.h", "device_common.h", "job.h")
 STREAM_SOURCES = SWEEP_SOURCES + ("stream.hip",)
 TRAFFIC = {
     ("orl", "fp32"): {
-        "sha": "1f7edef398eecb5a",
+        "sha": "c9e5231b5947697d",
         "files": SWEEP_SOURCES,
         "apass": {10304: 20994764, 2576: 6151281, 644: 2453004},
         "cpass_partial": {10304: 24911220, 2576: 9514477, 644: 4031221},

@@ -1227,16 +1227,17 @@ hipError_t launch_apass_jobs(int mode, int rpad, int tm, const Job *jobs, const 
 // C-pass configurations: WC column tiles (and row groups) per wave, from the
 // plan (1: one wave per column tile over the whole chunk, for throughput; 2
 // or 4: shorter per-wave chains, for latency), and SB 16-row steps per FP32
-// load batch by rank class (two up to r = 48: two steps of loads in flight
-// per wave; one above, where the wider operand tiles hold more registers).
-template <int RT>
+// load batch by rank class and WC (two up to r = 32, and up to r = 48 with at
+// most two column tiles per wave: two steps of loads in flight per wave; one
+// where the wider operand tiles would not fit the registers).
+template <int RT, int WC>
 struct CpassCfg {
-    static constexpr int SB = RT <= 3 ? 2 : 1;
+    static constexpr int SB = RT <= 2 || (RT == 3 && WC <= 2) ? 2 : 1;
 };
 
 template <int RT, int WC>
 static void cpass_launch(bool bf, const Job *jobs, const int2 *bmap, int blocks, hipStream_t s) {
-    constexpr int SB = CpassCfg<RT>::SB;
+    constexpr int SB = CpassCfg<RT, WC>::SB;
     const size_t lds = sizeof(double) * cpass_lds_doubles<RT, WC>();
     if (bf) k_cpass<RT, WC, SB, true><<<blocks, 256, lds, s>>>(jobs, bmap);
     else k_cpass<RT, WC, SB, false><<<blocks, 256, lds, s>>>(jobs, bmap);
@@ -1358,10 +1359,10 @@ static void lds_attr(hipError_t &e) {
     }
     set((const void *)k_cfinal<RT, MODE, 4>);
     set((const void *)k_cfinal<RT, MODE, 16>);
-    constexpr int SB = CpassCfg<RT>::SB;
-    for (const void *f : {(const void *)k_cpass<RT, 1, SB, false>, (const void *)k_cpass<RT, 1, SB, true>,
-                          (const void *)k_cpass<RT, 2, SB, false>, (const void *)k_cpass<RT, 2, SB, true>,
-                          (const void *)k_cpass<RT, 4, SB, false>, (const void *)k_cpass<RT, 4, SB, true>})
+    constexpr int S1 = CpassCfg<RT, 1>::SB, S2 = CpassCfg<RT, 2>::SB, S4 = CpassCfg<RT, 4>::SB;
+    for (const void *f : {(const void *)k_cpass<RT, 1, S1, false>, (const void *)k_cpass<RT, 1, S1, true>,
+                          (const void *)k_cpass<RT, 2, S2, false>, (const void *)k_cpass<RT, 2, S2, true>,
+                          (const void *)k_cpass<RT, 4, S4, false>, (const void *)k_cpass<RT, 4, S4, true>})
         set(f);
 }
 
