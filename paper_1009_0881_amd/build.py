@@ -1,4 +1,4 @@
-"""Build libnmf.so (HIP for gfx950) in-tree with hipcc.
+"""Build libnmf.so (HIP for gfx950) in-tree with hipcc, and the probes/ programs.
 
     python -m paper_1009_0881_amd.build [--jobs N] [--debug]
 
@@ -18,6 +18,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 OUT_DIR = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libnmf.so")
+PROBES = os.path.join(HERE, "probes")
 ARCH = os.environ.get("NMF_OFFLOAD_ARCH", "gfx950")
 
 # Packed FP32 instructions are disabled for all device code: the compiler may
@@ -58,9 +59,26 @@ def build(jobs: int = 8, debug: bool = False, verbose: bool = False) -> str:
     if res.returncode != 0:
         raise RuntimeError(f"link failed: {' '.join(cmd)}\n{res.stdout}\n{res.stderr}")
     os.replace(tmp, LIB)
+    probes = build_probes(jobs, extra)
     if verbose:
-        print(f"built {LIB} from {len(srcs)} sources")
+        print(f"built {LIB} from {len(srcs)} sources" + (f" and {len(probes)} probe(s)" if probes else ""))
     return LIB
+
+
+def build_probes(jobs: int = 8, extra=()) -> list:
+    """Standalone measurement programs (probes/*.hip -> probes/<name>), not part of the library."""
+    srcs = sorted(glob.glob(os.path.join(PROBES, "*.hip")))
+
+    def one(src):
+        exe = os.path.splitext(src)[0]
+        cmd = [hipcc(), "-x", "hip", *COMMON, *extra, src, "-o", exe]
+        res = subprocess.run(cmd, capture_output=True, text=True)
+        if res.returncode != 0:
+            raise RuntimeError(f"compile failed: {' '.join(cmd)}\n{res.stdout}\n{res.stderr}")
+        return exe
+
+    with cf.ThreadPoolExecutor(max_workers=max(1, jobs)) as ex:
+        return list(ex.map(one, srcs))
 
 
 def main(argv=None) -> int:
