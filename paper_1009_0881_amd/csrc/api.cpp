@@ -79,12 +79,12 @@ void prof_collect(Ctx &c) {
         prof_end(c, pi_);                                   \
     } while (0)
 
-// FP32 streaming tiling of a job when its level qualifies (large, m and the
-// column stride of M multiples of 4, M 16-byte aligned).
 // Blocks of the D-reduction launch: the upper Gram tiles, then (single
 // solves) the blocks that sum V^T M over the chunks.
 int reduce_blocks(const Job &J) { return J.nG + (J.Cr ? J.nCr : 0); }
 
+// FP32 streaming tiling of a job when its level qualifies (large, m and the
+// column stride of M multiples of 4, M 16-byte aligned).
 void set_fp32_stream(Job &J, const LevelInfo &li, const Plan &p) {
     if (!li.fstream || (J.ldm & 3) != 0 || (reinterpret_cast<uintptr_t>(J.M) & 15) != 0) return;
     J.stream = 1;
